@@ -1,0 +1,150 @@
+/*
+ * tumordb.h — C ABI of the MI355X tumour-database retrieval library.
+ *
+ * The retrieval method of "A for-loop is all you need" (arXiv 2205.04550):
+ * a patient's two binary segmentations in atlas space (FLAIR and T1Gd,
+ * Sec. 2.2 step 2-3 and Sec. 2.3) are compared with every pre-simulated
+ * tumour of a database (Sec. 2.2 step 3). Each simulation, a density in
+ * [0, 1], is thresholded into a FLAIR mask (lower threshold) and a T1Gd mask
+ * (higher threshold) (Sec. 2.3); similarity is Dice_T1Gd + Dice_FLAIR and the
+ * highest sum is the best match (Sec. 2.3); the exhaustive loop over the
+ * database is the ground truth (Sec. 2.3, "Baseline for-loop search").
+ *
+ * Conventions for every call:
+ *  - Grid: nx * ny * nz voxels, x fastest ([nz][ny][nx]); nx % 32 == 0.
+ *  - Mask m = 0 is FLAIR (voxel c >= t_lo), m = 1 is T1Gd (c >= t_hi).
+ *  - Query labels are uint8 per voxel: bit 0 FLAIR, bit 1 T1Gd; other bits
+ *    are ignored.
+ *  - Dice_m = 2 I_m / (A_m + B_m) in IEEE double, and 1 when A_m + B_m == 0;
+ *    score = Dice_T1Gd + Dice_FLAIR (double). I, A, B are exact uint32 counts.
+ *  - Ranking is a total order: score descending, then database index
+ *    ascending. Indices are 0-based in insertion order.
+ *  - "device" pointers are HIP device memory of the current device; the
+ *    caller owns every buffer (storage, inputs, outputs, workspace). The
+ *    library never allocates device memory.
+ *  - stream is a hipStream_t passed as void* (NULL = the null stream). Calls
+ *    enqueue asynchronously; results are valid once the stream is synced.
+ *  - Every call validates all arguments before enqueuing anything; on error
+ *    it writes nothing, returns a negative code and db_last_error() explains.
+ *    No C++ exception crosses this ABI. Faults of enqueued work surface at
+ *    db_sync() (or the caller's own synchronisation) as DB_EHIP.
+ *  - A handle is not thread-safe while db_append runs; queries on one handle
+ *    may run concurrently only with distinct workspaces.
+ */
+#ifndef TUMORDB_H
+#define TUMORDB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct db_t db_t; /* opaque handle over caller-owned device storage */
+
+/* Half-open voxel box [x0, x1) x [y0, y1) x [z0, z1). */
+typedef struct {
+    int32_t x0, y0, z0, x1, y1, z1;
+} db_roi_t;
+
+/* Counts behind one score; index [0] = FLAIR, [1] = T1Gd.
+ * inter = |A n B (n R)|, a = |A (n R)| (query), b = |B (n R)| (database). */
+typedef struct {
+    uint32_t inter[2], a[2], b[2];
+} db_counts_t;
+
+enum {
+    DB_OK = 0,
+    DB_EINVAL = -1, /* bad argument (null pointer, bad size, k out of range, bad ROI) */
+    DB_ENOMEM = -2, /* host-side allocation failed */
+    DB_EHIP = -3,   /* a HIP runtime call failed; db_last_error has its string */
+    DB_ESTATE = -4, /* handle is not a live handle of this library */
+    DB_ENOSPC = -5  /* storage capacity or workspace too small */
+};
+
+#define DB_KMAX 1024 /* largest k a query may request */
+
+/* ---------------------------------------------------------------- build --- */
+
+/* Bytes of device storage for `capacity` entries of an nx*ny*nz grid.
+ * Layout (offsets from the storage base, all 256-byte aligned):
+ *   planes: uint32 [capacity][2][Wp], Wp = round_up(nx*ny*nz/32, 4); word w of
+ *           mask m holds voxels 32w..32w+31 of that mask, LSB first; words
+ *           past nx*ny*nz/32 are zero;
+ *   popcount: uint32 [capacity][2] = |B_FLAIR|, |B_T1Gd| per entry.
+ * Returns 0 if the dimensions are invalid. */
+size_t db_storage_bytes(int nx, int ny, int nz, int64_t capacity);
+
+/* Create an empty database handle over `storage` (device, >= db_storage_bytes,
+ * 256-byte aligned). Thresholds t_lo < t_hi select the FLAIR and T1Gd masks
+ * (Sec. 2.3: FLAIR at the lower density level, T1Gd at the higher). Nothing
+ * is enqueued. The storage must outlive the handle. */
+int db_build(db_t **out, int nx, int ny, int nz, float t_lo, float t_hi, int64_t capacity,
+             void *storage, size_t storage_bytes);
+
+/* Threshold and bit-pack n simulated densities (device float32 [n][nz][ny][nx],
+ * 16-byte aligned) into entries db_size() .. db_size()+n-1 (Sec. 2.3: the
+ * masks are extracted from the raw simulations once, before any query).
+ * DB_ENOSPC if capacity would be exceeded. The input may be released once the
+ * stream has passed this call. */
+int db_append(db_t *db, const float *conc, int64_t n, void *stream);
+
+/* Number of entries appended so far (-1 for an invalid handle). */
+int64_t db_size(const db_t *db);
+
+/* ---------------------------------------------------------------- query --- */
+
+/* Workspace bytes a query call needs for nq queries and top-k (0 if invalid). */
+size_t db_query_workspace_bytes(const db_t *db, int nq, int k);
+
+/* The overlap stage of one query against every entry (Sec. 2.3, baseline
+ * loop): inter[n][m] = |A_m n B_m(n)| for n < db_size(), and, if qcount is
+ * not NULL, qcount[m] = |A_m|. q_labels: device uint8 [nz][ny][nx];
+ * inter: device uint32 [db_size()][2]; qcount: device uint32 [2] or NULL. */
+int db_scan(const db_t *db, const uint8_t *q_labels, uint32_t *inter, uint32_t *qcount, void *ws,
+            size_t ws_bytes, void *stream);
+
+/* One query (Sec. 2.2 step 3 with the Sec. 2.3 score): the k best entries by
+ * Dice_T1Gd + Dice_FLAIR. idx: device int32 [k]; score: device double [k];
+ * counts: device db_counts_t [k] or NULL. 1 <= k <= min(db_size(), DB_KMAX). */
+int db_query(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx, double *score,
+             db_counts_t *counts, void *ws, size_t ws_bytes, void *stream);
+
+/* nq queries in one launch sequence, each optionally restricted to its own
+ * box: both masks are cut to the box before Dice (an extension; the paper
+ * compares whole volumes). q_labels: device uint8 [nq][nz][ny][nx];
+ * rois: HOST array [nq] (validated before enqueue: inside the grid, non-empty)
+ * or NULL for whole grids; outputs idx [nq][k], score [nq][k], counts
+ * [nq][k] or NULL (device). The kernel sequence is recorded once into a HIP
+ * graph per (handle, shape, pointers) and replayed. */
+int db_query_batch(const db_t *db, int nq, const uint8_t *q_labels, const db_roi_t *rois, int k,
+                   int32_t *idx, double *score, db_counts_t *counts, void *ws, size_t ws_bytes,
+                   void *stream);
+
+/* ----------------------------------------------------------------- misc --- */
+
+/* Wait for `stream` and report any asynchronous device error as DB_EHIP. */
+int db_sync(const db_t *db, void *stream);
+
+/* Timing of the dominant kernel: while enabled, every db_scan / db_query
+ * records a HIP event pair on its stream around the overlap-scan kernel and
+ * every db_query_batch one around its graph launch. db_profile_read waits
+ * for the recorded events, returns their summed elapsed milliseconds and the
+ * number of pairs, and clears them. For measurement, not for production. */
+int db_profile(db_t *db, int enable);
+int db_profile_read(db_t *db, double *ms, int64_t *launches);
+
+/* Release the handle (host memory only; the storage belongs to the caller).
+ * Waits for no stream: the caller must not free storage still in use. */
+void db_free(db_t *db);
+
+/* Message of the last failing call on this thread ("" if none). Valid until
+ * the next library call on the same thread. */
+const char *db_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TUMORDB_H */

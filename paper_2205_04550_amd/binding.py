@@ -1,0 +1,216 @@
+"""ctypes binding of libtumordb (include/tumordb.h) with torch for device memory and streams.
+
+Argument marshalling only: every step of the retrieval runs in the HIP
+kernels of libtumordb.so. There is no fallback: if the library is missing
+the import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtumordb.so")
+
+DB_OK, DB_EINVAL, DB_ENOMEM, DB_EHIP, DB_ESTATE, DB_ENOSPC = 0, -1, -2, -3, -4, -5
+DB_KMAX = 1024
+SYMBOLS = ("db_storage_bytes", "db_build", "db_append", "db_size", "db_query_workspace_bytes",
+           "db_scan", "db_query", "db_query_batch", "db_sync", "db_free", "db_last_error",
+           "db_profile", "db_profile_read")
+
+
+class DbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class RoiT(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("x0", "y0", "z0", "x1", "y1", "z1")]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(python -m paper_2205_04550_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t
+    sig = {
+        "db_storage_bytes": (sz, [i32, i32, i32, i64]),
+        "db_build": (i32, [ctypes.POINTER(vp), i32, i32, i32, ctypes.c_float, ctypes.c_float,
+                           i64, vp, sz]),
+        "db_append": (i32, [vp, vp, i64, vp]),
+        "db_size": (i64, [vp]),
+        "db_query_workspace_bytes": (sz, [vp, i32, i32]),
+        "db_scan": (i32, [vp, vp, vp, vp, vp, sz, vp]),
+        "db_query": (i32, [vp, vp, i32, vp, vp, vp, vp, sz, vp]),
+        "db_query_batch": (i32, [vp, i32, vp, vp, i32, vp, vp, vp, vp, sz, vp]),
+        "db_sync": (i32, [vp, vp]),
+        "db_free": (None, [vp]),
+        "db_last_error": (ctypes.c_char_p, []),
+        "db_profile": (i32, [vp, i32]),
+        "db_profile_read": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+def _check(rc: int) -> None:
+    if rc != DB_OK:
+        raise DbError(rc, LIB.db_last_error().decode())
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def storage_bytes(nx: int, ny: int, nz: int, capacity: int) -> int:
+    return LIB.db_storage_bytes(nx, ny, nz, capacity)
+
+
+class TumorDB:
+    """A database of bit-packed FLAIR/T1Gd masks resident in device memory."""
+
+    def __init__(self, nx: int, ny: int, nz: int, capacity: int, t_lo: float, t_hi: float,
+                 device: str | torch.device = "cuda"):
+        nbytes = storage_bytes(nx, ny, nz, capacity)
+        if nbytes == 0:
+            raise DbError(DB_EINVAL, f"bad grid {nx}x{ny}x{nz} or capacity {capacity}")
+        self.dims = (nx, ny, nz)
+        self.capacity = capacity
+        self.t_lo, self.t_hi = t_lo, t_hi
+        self.storage = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        _check(LIB.db_build(ctypes.byref(h), nx, ny, nz, t_lo, t_hi, capacity,
+                            self.storage.data_ptr(), nbytes))
+        self._h = h
+        self.W = nx * ny * nz // 32
+        self.Wp = (self.W + 3) // 4 * 4
+        self._ws = {}
+
+    # ---- build --------------------------------------------------------------------------
+    def append(self, conc: torch.Tensor, stream=None) -> None:
+        """Threshold + pack float32 densities [n][nz][ny][nx] (device)."""
+        nx, ny, nz = self.dims
+        assert conc.dtype == torch.float32 and conc.is_cuda and conc.is_contiguous()
+        assert conc.numel() % (nx * ny * nz) == 0
+        n = conc.numel() // (nx * ny * nz)
+        _check(LIB.db_append(self._h, conc.data_ptr(), n, _stream(stream)))
+
+    def __len__(self) -> int:
+        return LIB.db_size(self._h)
+
+    @property
+    def planes(self) -> torch.Tensor:
+        """int32 view [capacity][2][Wp] of the packed masks (bits are uint32 words)."""
+        nb = self.capacity * 2 * self.Wp * 4
+        return self.storage[:nb].view(torch.int32).view(self.capacity, 2, self.Wp)
+
+    @property
+    def popcounts(self) -> torch.Tensor:
+        """int32 view [capacity][2] of |B_FLAIR|, |B_T1Gd|."""
+        off = (self.capacity * 2 * self.Wp * 4 + 255) // 256 * 256
+        return self.storage[off:off + self.capacity * 8].view(torch.int32).view(self.capacity, 2)
+
+    # ---- query --------------------------------------------------------------------------
+    def workspace_bytes(self, nq: int, k: int) -> int:
+        return LIB.db_query_workspace_bytes(self._h, nq, k)
+
+    def workspace(self, nq: int, k: int) -> torch.Tensor:
+        nb = self.workspace_bytes(nq, k)
+        if nb == 0:
+            raise DbError(DB_EINVAL, f"bad workspace request nq={nq} k={k}")
+        ws = self._ws.get((nq, k))
+        if ws is None or ws.numel() < nb:
+            ws = torch.empty(nb, dtype=torch.uint8, device=self.storage.device)
+            self._ws[(nq, k)] = ws
+        return ws
+
+    def scan(self, q_labels: torch.Tensor, inter: torch.Tensor | None = None,
+             qcount: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None):
+        """Intersections [N][2] (int32 holding uint32) and query counts [2]."""
+        n = len(self)
+        dev = self.storage.device
+        inter = torch.empty((n, 2), dtype=torch.int32, device=dev) if inter is None else inter
+        qcount = torch.empty(2, dtype=torch.int32, device=dev) if qcount is None else qcount
+        ws = self.workspace(1, 1) if ws is None else ws
+        _check(LIB.db_scan(self._h, q_labels.data_ptr(), inter.data_ptr(), qcount.data_ptr(),
+                           ws.data_ptr(), ws.numel(), _stream(stream)))
+        return inter, qcount
+
+    def query(self, q_labels: torch.Tensor, k: int, with_counts: bool = True, out=None,
+              ws: torch.Tensor | None = None, stream=None):
+        """Top-k (idx int32 [k], score float64 [k], counts int32 [k][6] or None)."""
+        dev = self.storage.device
+        if out is None:
+            idx = torch.empty(k, dtype=torch.int32, device=dev)
+            score = torch.empty(k, dtype=torch.float64, device=dev)
+            counts = torch.empty((k, 6), dtype=torch.int32, device=dev) if with_counts else None
+        else:
+            idx, score, counts = out
+        ws = self.workspace(1, k) if ws is None else ws
+        _check(LIB.db_query(self._h, q_labels.data_ptr(), k, idx.data_ptr(), score.data_ptr(),
+                            _ptr(counts), ws.data_ptr(), ws.numel(), _stream(stream)))
+        return idx, score, counts
+
+    def query_batch(self, q_labels: torch.Tensor, rois, k: int, with_counts: bool = True,
+                    out=None, ws: torch.Tensor | None = None, stream=None):
+        """nq queries [nq][nz][ny][nx] with boxes int [nq][6] (x0,y0,z0,x1,y1,z1) or None."""
+        nq = q_labels.shape[0]
+        dev = self.storage.device
+        if out is None:
+            idx = torch.empty((nq, k), dtype=torch.int32, device=dev)
+            score = torch.empty((nq, k), dtype=torch.float64, device=dev)
+            counts = torch.empty((nq, k, 6), dtype=torch.int32, device=dev) if with_counts else None
+        else:
+            idx, score, counts = out
+        roi_arr = None
+        rp = None
+        if rois is not None:
+            roi_arr = np.ascontiguousarray(np.asarray(rois, dtype=np.int32).reshape(nq, 6))
+            rp = roi_arr.ctypes.data
+        ws = self.workspace(nq, k) if ws is None else ws
+        _check(LIB.db_query_batch(self._h, nq, q_labels.data_ptr(), rp, k, idx.data_ptr(),
+                                  score.data_ptr(), _ptr(counts), ws.data_ptr(), ws.numel(),
+                                  _stream(stream)))
+        return idx, score, counts
+
+    def profile(self, enable: bool) -> None:
+        """Record HIP events around the dominant kernel of every later query call."""
+        _check(LIB.db_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(summed milliseconds, launches) of the dominant kernel since the last read."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(LIB.db_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def sync(self, stream=None) -> None:
+        _check(LIB.db_sync(self._h, _stream(stream)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            LIB.db_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

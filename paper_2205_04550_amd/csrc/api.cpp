@@ -1,0 +1,520 @@
+// api.cpp — the C ABI of libtumordb (argument checks, workspace layout, launch order).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(DB_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool live(const db_t *db) { return db && db->magic == tdb::kMagic; }
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+}  // namespace
+
+namespace tdb {
+
+bool make_geometry(int nx, int ny, int nz, Geometry *g)
+{
+    if (nx <= 0 || ny <= 0 || nz <= 0 || nx % 32 != 0)
+        return false;
+    const int64_t V = (int64_t)nx * ny * nz;
+    // Word indices are int32 and the batched kernel divides row numbers by
+    // ny with a 32-bit reciprocal: keep ny * ny * nz below 2^32.
+    if (V / 32 >= (int64_t)1 << 27 || (int64_t)ny * ny * nz >= ((int64_t)1 << 32))
+        return false;
+    g->nx = nx;
+    g->ny = ny;
+    g->nz = nz;
+    g->V = V;
+    g->W = (int)(V / 32);
+    g->Wp = (int)align_up((size_t)g->W, 4);
+    g->nxw = nx / 32;
+    return true;
+}
+
+WsLayout ws_layout(const db_t *db, int nq, int k, bool batched)
+{
+    WsLayout L{};
+    const int64_t cap = db->capacity;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, kAlign);
+        return o;
+    };
+    L.qpack = take((size_t)nq * 2 * db->g.Wp * 4);
+    L.qpart = take((size_t)nq * kQueryParts * 2 * 4);
+    L.acnt = take((size_t)nq * 2 * 4);
+    L.rois = take((size_t)nq * 6 * 4);
+    L.inter = take((size_t)nq * cap * 2 * 4);
+    L.bcnt = batched ? take((size_t)nq * cap * 2 * 4) : off;
+    // plan: query order [nq] + 8 queue counters
+    L.plan = take(((size_t)nq + 8) * 4);
+    const size_t cand = (size_t)nq * topk_blocks(cap) * k;
+    L.topk_a = take(cand * 12);
+    L.topk_b = take(cand * 12);
+    L.total = off;
+    return L;
+}
+
+// Host state of a cached batched-query graph.
+struct BatchGraph {
+    int nq = 0, k = 0;
+    int64_t n = 0;
+    const void *labels = nullptr, *ws = nullptr, *idx = nullptr, *score = nullptr,
+               *counts = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int32_t *staging = nullptr;  // pinned upload buffer: rois [nq][6] + order [nq]
+    size_t staging_elems = 0;
+    hipEvent_t uploaded = nullptr;
+    bool upload_pending = false;
+
+    void drop_exec()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+    }
+    ~BatchGraph()
+    {
+        drop_exec();
+        if (uploaded) {
+            if (upload_pending) (void)hipEventSynchronize(uploaded);
+            (void)hipEventDestroy(uploaded);
+        }
+        if (staging) (void)hipHostFree(staging);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+// Event pairs recorded around each launch of the dominant kernel (the scan,
+// or the whole batched graph) while profiling is on.
+struct Profiler {
+    bool on = false;
+    std::vector<hipEvent_t> ev;  // start, stop, start, stop, ...
+    size_t used = 0;             // events recorded since the last read
+
+    hipError_t mark(hipStream_t s)
+    {
+        if (used == ev.size()) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            ev.push_back(e);
+        }
+        return hipEventRecord(ev[used++], s);
+    }
+    ~Profiler()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace tdb
+
+using namespace tdb;
+
+// Start/stop marks around the dominant kernel when profiling is on.
+static hipError_t prof_mark(const db_t *db, hipStream_t s)
+{
+    if (!db->prof || !db->prof->on) return hipSuccess;
+    return db->prof->mark(s);
+}
+
+
+static int check_query_common(const char *fn, const db_t *db, const uint8_t *q_labels, void *ws)
+{
+    if (!live(db)) return fail(DB_ESTATE, "%s: invalid handle", fn);
+    if (db->count <= 0) return fail(DB_EINVAL, "%s: database is empty", fn);
+    if (!q_labels || !aligned(q_labels, 16))
+        return fail(DB_EINVAL, "%s: q_labels must be non-NULL and 16-byte aligned", fn);
+    if (!ws || !aligned(ws, kAlign))
+        return fail(DB_EINVAL, "%s: workspace must be non-NULL and 256-byte aligned", fn);
+    return DB_OK;
+}
+
+template <class T>
+static T *at(void *ws, size_t off)
+{
+    return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+// Enqueue the kernel sequence of a batched query on stream s.
+static hipError_t enqueue_batch(const db_t *db, int nq, const uint8_t *q_labels, int k,
+                                int32_t *idx, double *score, db_counts_t *counts, void *ws,
+                                const WsLayout &L, hipStream_t s)
+{
+    uint32_t *qpack = at<uint32_t>(ws, L.qpack);
+    uint32_t *acnt = at<uint32_t>(ws, L.acnt);
+    uint32_t *inter = at<uint32_t>(ws, L.inter);
+    uint32_t *bcnt = at<uint32_t>(ws, L.bcnt);
+    int32_t *rois = at<int32_t>(ws, L.rois);
+    int32_t *order = at<int32_t>(ws, L.plan);
+    int32_t *counters = order + nq;
+    hipError_t e = launch_pack_queries(db, q_labels, nq, rois, qpack, at<uint32_t>(ws, L.qpart), s);
+    if (e == hipSuccess) e = launch_sum_parts(at<uint32_t>(ws, L.qpart), nq, acnt, s);
+    if (e == hipSuccess) e = launch_fill_u32(counters, 8, 0, s);
+    if (e == hipSuccess)
+        e = launch_batch_scan(db, db->count, nq, qpack, rois, order, 0, counters, inter, bcnt, s);
+    if (e == hipSuccess) {
+        TopkArgs a{};
+        a.n = db->count;
+        a.nq = nq;
+        a.k = k;
+        a.inter = inter;
+        a.inter_qstride = 2 * db->capacity;
+        a.bcnt = bcnt;
+        a.bcnt_qstride = 2 * db->capacity;
+        a.acnt = acnt;
+        const size_t cand = (size_t)nq * topk_blocks(db->capacity) * k;
+        a.buf_s[0] = at<uint64_t>(ws, L.topk_a);
+        a.buf_s[1] = at<uint64_t>(ws, L.topk_b);
+        a.buf_i[0] = reinterpret_cast<int32_t *>(a.buf_s[0] + cand);
+        a.buf_i[1] = reinterpret_cast<int32_t *>(a.buf_s[1] + cand);
+        a.out_idx = idx;
+        a.out_score = score;
+        a.out_counts = counts;
+        e = launch_topk(a, s);
+    }
+    return e;
+}
+
+extern "C" {
+
+size_t db_storage_bytes(int nx, int ny, int nz, int64_t capacity)
+{
+    Geometry g;
+    if (!make_geometry(nx, ny, nz, &g) || capacity <= 0 || capacity > INT32_MAX)
+        return 0;
+    return align_up((size_t)capacity * 2 * g.Wp * 4, kAlign) +
+           align_up((size_t)capacity * 2 * 4, kAlign);
+}
+
+int db_build(db_t **out, int nx, int ny, int nz, float t_lo, float t_hi, int64_t capacity,
+             void *storage, size_t storage_bytes)
+{
+    if (!out) return fail(DB_EINVAL, "db_build: out is NULL");
+    Geometry g;
+    if (!make_geometry(nx, ny, nz, &g))
+        return fail(DB_EINVAL, "db_build: bad grid %dx%dx%d (need positive dims, nx %% 32 == 0)",
+                    nx, ny, nz);
+    if (capacity <= 0 || capacity > INT32_MAX)
+        return fail(DB_EINVAL, "db_build: capacity %lld out of range", (long long)capacity);
+    if (!(t_lo == t_lo) || !(t_hi == t_hi) || !(t_lo < t_hi))
+        return fail(DB_EINVAL, "db_build: need t_lo < t_hi (got %g, %g)", t_lo, t_hi);
+    if (!storage || !aligned(storage, kAlign))
+        return fail(DB_EINVAL, "db_build: storage must be non-NULL and 256-byte aligned");
+    const size_t need = db_storage_bytes(nx, ny, nz, capacity);
+    if (storage_bytes < need)
+        return fail(DB_ENOSPC, "db_build: storage %zu bytes < %zu needed", storage_bytes, need);
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "db_build: device query");
+    db_t *db = new (std::nothrow) db_t{};
+    if (!db) return fail(DB_ENOMEM, "db_build: out of host memory");
+    db->magic = kMagic;
+    db->g = g;
+    db->t_lo = t_lo;
+    db->t_hi = t_hi;
+    db->capacity = capacity;
+    db->count = 0;
+    db->planes = static_cast<uint32_t *>(storage);
+    db->popcnt = reinterpret_cast<uint32_t *>(static_cast<char *>(storage) +
+                                              align_up((size_t)capacity * 2 * g.Wp * 4, kAlign));
+    db->storage_bytes = storage_bytes;
+    db->cus = cus;
+    db->device = dev;
+    db->graph = nullptr;
+    db->prof = nullptr;
+    *out = db;
+    g_err[0] = 0;
+    return DB_OK;
+}
+
+int db_append(db_t *db, const float *conc, int64_t n, void *stream)
+{
+    if (!live(db)) return fail(DB_ESTATE, "db_append: invalid handle");
+    if (n < 0) return fail(DB_EINVAL, "db_append: n < 0");
+    if (n == 0) return DB_OK;
+    if (!conc || !aligned(conc, 16))
+        return fail(DB_EINVAL, "db_append: conc must be non-NULL and 16-byte aligned");
+    if (db->count + n > db->capacity)
+        return fail(DB_ENOSPC, "db_append: %lld + %lld entries exceed capacity %lld",
+                    (long long)db->count, (long long)n, (long long)db->capacity);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint32_t *planes = db->planes + db->count * 2 * (int64_t)db->g.Wp;
+    uint32_t *pc = db->popcnt + db->count * 2;
+    hipError_t e = launch_pack_db(db, conc, n, planes, pc, s);
+    if (e != hipSuccess) return hip_fail(e, "db_append: launch");
+    db->count += n;
+    return DB_OK;
+}
+
+int64_t db_size(const db_t *db) { return live(db) ? db->count : -1; }
+
+size_t db_query_workspace_bytes(const db_t *db, int nq, int k)
+{
+    if (!live(db) || nq <= 0 || k <= 0 || k > DB_KMAX) return 0;
+    return ws_layout(db, nq, k, true).total;
+}
+
+int db_scan(const db_t *db, const uint8_t *q_labels, uint32_t *inter, uint32_t *qcount, void *ws,
+            size_t ws_bytes, void *stream)
+{
+    int rc = check_query_common("db_scan", db, q_labels, ws);
+    if (rc) return rc;
+    if (!inter) return fail(DB_EINVAL, "db_scan: inter is NULL");
+    const WsLayout L = ws_layout(db, 1, 1, true);
+    if (ws_bytes < L.total)
+        return fail(DB_ENOSPC, "db_scan: workspace %zu bytes < %zu needed", ws_bytes, L.total);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_pack_queries(db, q_labels, 1, nullptr, at<uint32_t>(ws, L.qpack),
+                                       at<uint32_t>(ws, L.qpart), s);
+    if (e == hipSuccess)
+        e = launch_sum_parts(at<uint32_t>(ws, L.qpart), 1,
+                             qcount ? qcount : at<uint32_t>(ws, L.acnt), s);
+    if (e == hipSuccess) e = prof_mark(db, s);
+    if (e == hipSuccess) e = launch_scan(db, db->count, at<uint32_t>(ws, L.qpack), inter, s);
+    if (e == hipSuccess) e = prof_mark(db, s);
+    if (e != hipSuccess) return hip_fail(e, "db_scan: launch");
+    return DB_OK;
+}
+
+int db_query(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx, double *score,
+             db_counts_t *counts, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_query_common("db_query", db, q_labels, ws);
+    if (rc) return rc;
+    if (k < 1 || k > DB_KMAX || k > db->count)
+        return fail(DB_EINVAL, "db_query: k = %d outside [1, min(%lld, %d)]", k,
+                    (long long)db->count, DB_KMAX);
+    if (!idx || !score) return fail(DB_EINVAL, "db_query: idx and score must be non-NULL");
+    const WsLayout L = ws_layout(db, 1, k, true);
+    if (ws_bytes < L.total)
+        return fail(DB_ENOSPC, "db_query: workspace %zu bytes < %zu needed", ws_bytes, L.total);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint32_t *inter = at<uint32_t>(ws, L.inter);
+    uint32_t *acnt = at<uint32_t>(ws, L.acnt);
+    hipError_t e = launch_pack_queries(db, q_labels, 1, nullptr, at<uint32_t>(ws, L.qpack),
+                                       at<uint32_t>(ws, L.qpart), s);
+    if (e == hipSuccess) e = launch_sum_parts(at<uint32_t>(ws, L.qpart), 1, acnt, s);
+    if (e == hipSuccess) e = prof_mark(db, s);
+    if (e == hipSuccess) e = launch_scan(db, db->count, at<uint32_t>(ws, L.qpack), inter, s);
+    if (e == hipSuccess) e = prof_mark(db, s);
+    if (e == hipSuccess) {
+        TopkArgs a{};
+        a.n = db->count;
+        a.nq = 1;
+        a.k = k;
+        a.inter = inter;
+        a.inter_qstride = 0;
+        a.bcnt = db->popcnt;
+        a.bcnt_qstride = 0;
+        a.acnt = acnt;
+        a.buf_s[0] = at<uint64_t>(ws, L.topk_a);
+        a.buf_s[1] = at<uint64_t>(ws, L.topk_b);
+        const size_t cand = topk_blocks(db->capacity) * (size_t)k;
+        a.buf_i[0] = reinterpret_cast<int32_t *>(a.buf_s[0] + cand);
+        a.buf_i[1] = reinterpret_cast<int32_t *>(a.buf_s[1] + cand);
+        a.out_idx = idx;
+        a.out_score = score;
+        a.out_counts = counts;
+        e = launch_topk(a, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "db_query: launch");
+    return DB_OK;
+}
+
+int db_query_batch(const db_t *db_c, int nq, const uint8_t *q_labels, const db_roi_t *rois, int k,
+                   int32_t *idx, double *score, db_counts_t *counts, void *ws, size_t ws_bytes,
+                   void *stream)
+{
+    int rc = check_query_common("db_query_batch", db_c, q_labels, ws);
+    if (rc) return rc;
+    db_t *db = const_cast<db_t *>(db_c);  // only the graph cache is mutated
+    const Geometry &g = db->g;
+    if (nq < 1) return fail(DB_EINVAL, "db_query_batch: nq = %d < 1", nq);
+    if (k < 1 || k > DB_KMAX || k > db->count)
+        return fail(DB_EINVAL, "db_query_batch: k = %d outside [1, min(%lld, %d)]", k,
+                    (long long)db->count, DB_KMAX);
+    if (!idx || !score) return fail(DB_EINVAL, "db_query_batch: idx and score must be non-NULL");
+    const WsLayout L = ws_layout(db, nq, k, true);
+    if (ws_bytes < L.total)
+        return fail(DB_ENOSPC, "db_query_batch: workspace %zu bytes < %zu needed", ws_bytes,
+                    L.total);
+    // Boxes (host) -> validated copy + cost order of the queries.
+    std::vector<int32_t> box((size_t)nq * 6);
+    std::vector<int64_t> cost(nq);
+    for (int q = 0; q < nq; ++q) {
+        db_roi_t r = rois ? rois[q] : db_roi_t{0, 0, 0, g.nx, g.ny, g.nz};
+        if (r.x0 < 0 || r.y0 < 0 || r.z0 < 0 || r.x1 > g.nx || r.y1 > g.ny || r.z1 > g.nz ||
+            r.x0 >= r.x1 || r.y0 >= r.y1 || r.z0 >= r.z1)
+            return fail(DB_EINVAL, "db_query_batch: ROI %d (%d,%d,%d)-(%d,%d,%d) is empty or "
+                        "outside the %dx%dx%d grid", q, r.x0, r.y0, r.z0, r.x1, r.y1, r.z1,
+                        g.nx, g.ny, g.nz);
+        int32_t *b = &box[(size_t)q * 6];
+        b[0] = r.x0; b[1] = r.y0; b[2] = r.z0; b[3] = r.x1; b[4] = r.y1; b[5] = r.z1;
+        const int64_t nw = ((r.x1 - 1) >> 5) - (r.x0 >> 5) + 1;
+        cost[q] = nw * (int64_t)(r.y1 - r.y0) * (r.z1 - r.z0);
+    }
+    std::vector<int32_t> order(nq);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+
+    if (!db->graph) {
+        db->graph = new (std::nothrow) BatchGraph();
+        if (!db->graph) return fail(DB_ENOMEM, "db_query_batch: out of host memory");
+    }
+    BatchGraph &G = *db->graph;
+    hipError_t e = hipSuccess;
+    if (!G.cap) {
+        e = hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&G.uploaded, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "db_query_batch: stream/event create");
+    }
+    // Pinned staging buffer; wait for the previous upload before reusing it.
+    const size_t elems = (size_t)nq * 7;
+    if (G.upload_pending) {
+        e = hipEventSynchronize(G.uploaded);
+        if (e != hipSuccess) return hip_fail(e, "db_query_batch: wait for previous upload");
+        G.upload_pending = false;
+    }
+    if (G.staging_elems < elems) {
+        if (G.staging) (void)hipHostFree(G.staging);
+        G.staging = nullptr;
+        G.staging_elems = 0;
+        e = hipHostMalloc((void **)&G.staging, elems * 4, hipHostMallocDefault);
+        if (e != hipSuccess) return hip_fail(e, "db_query_batch: pinned staging");
+        G.staging_elems = elems;
+    }
+    std::memcpy(G.staging, box.data(), (size_t)nq * 6 * 4);
+    std::memcpy(G.staging + (size_t)nq * 6, order.data(), (size_t)nq * 4);
+
+    // (Re)record the graph when the shape or any pointer changed.
+    const bool same = G.exec && G.nq == nq && G.k == k && G.n == db->count &&
+                      G.labels == q_labels && G.ws == ws && G.idx == idx && G.score == score &&
+                      G.counts == counts;
+    if (!same) {
+        G.drop_exec();
+        hipGraph_t graph = nullptr;
+        e = hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "db_query_batch: begin capture");
+        hipError_t le = enqueue_batch(db, nq, q_labels, k, idx, score, counts, ws, L, G.cap);
+        e = hipStreamEndCapture(G.cap, &graph);
+        if (le != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(le, "db_query_batch: record");
+        }
+        if (e != hipSuccess) return hip_fail(e, "db_query_batch: end capture");
+        e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            G.exec = nullptr;
+            return hip_fail(e, "db_query_batch: instantiate");
+        }
+        G.nq = nq;
+        G.k = k;
+        G.n = db->count;
+        G.labels = q_labels;
+        G.ws = ws;
+        G.idx = idx;
+        G.score = score;
+        G.counts = counts;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    e = hipMemcpyAsync(at<int32_t>(ws, L.rois), G.staging, (size_t)nq * 6 * 4,
+                       hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(at<int32_t>(ws, L.plan), G.staging + (size_t)nq * 6, (size_t)nq * 4,
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(G.uploaded, s);
+    if (e != hipSuccess) return hip_fail(e, "db_query_batch: upload");
+    G.upload_pending = true;
+    e = prof_mark(db, s);
+    if (e == hipSuccess) e = hipGraphLaunch(G.exec, s);
+    if (e == hipSuccess) e = prof_mark(db, s);
+    if (e != hipSuccess) return hip_fail(e, "db_query_batch: graph launch");
+    return DB_OK;
+}
+
+int db_sync(const db_t *db, void *stream)
+{
+    if (!live(db)) return fail(DB_ESTATE, "db_sync: invalid handle");
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "db_sync");
+    return DB_OK;
+}
+
+int db_profile(db_t *db, int enable)
+{
+    if (!live(db)) return fail(DB_ESTATE, "db_profile: invalid handle");
+    if (!db->prof) {
+        db->prof = new (std::nothrow) Profiler();
+        if (!db->prof) return fail(DB_ENOMEM, "db_profile: out of host memory");
+    }
+    db->prof->on = enable != 0;
+    return DB_OK;
+}
+
+int db_profile_read(db_t *db, double *ms, int64_t *launches)
+{
+    if (!live(db)) return fail(DB_ESTATE, "db_profile_read: invalid handle");
+    if (!ms || !launches) return fail(DB_EINVAL, "db_profile_read: NULL output");
+    double total = 0.0;
+    int64_t n = 0;
+    if (db->prof) {
+        Profiler &P = *db->prof;
+        for (size_t i = 0; i + 1 < P.used; i += 2) {
+            hipError_t e = hipEventSynchronize(P.ev[i + 1]);
+            float t = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, P.ev[i], P.ev[i + 1]);
+            if (e != hipSuccess) return hip_fail(e, "db_profile_read");
+            total += t;
+            ++n;
+        }
+        P.used = 0;
+    }
+    *ms = total;
+    *launches = n;
+    return DB_OK;
+}
+
+void db_free(db_t *db)
+{
+    if (!live(db)) return;
+    delete db->graph;
+    delete db->prof;
+    db->magic = 0;
+    delete db;
+}
+
+const char *db_last_error(void) { return g_err; }
+
+}  // extern "C"

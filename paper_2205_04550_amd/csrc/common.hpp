@@ -1,0 +1,83 @@
+// common.hpp — device helpers shared by the retrieval kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tdb {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+
+// Streaming 16-byte load that should not displace reused data (query words)
+// from the caches: each database word is read exactly once per query.
+__device__ __forceinline__ u32x4 load_stream(const u32x4 *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
+__device__ __forceinline__ uint32_t popc(uint32_t x) { return (uint32_t)__builtin_popcount(x); }
+
+__device__ __forceinline__ uint32_t popc_and4(u32x4 a, u32x4 b)
+{
+    return popc(a.x & b.x) + popc(a.y & b.y) + popc(a.z & b.z) + popc(a.w & b.w);
+}
+
+__device__ __forceinline__ uint32_t popc4(u32x4 a)
+{
+    return popc(a.x) + popc(a.y) + popc(a.z) + popc(a.w);
+}
+
+// Sum over the 64 lanes of a wave; every lane receives the total.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Block-wide sum of two counters; the result is valid in thread 0.
+// lds must hold 2 * (blockDim.x / 64) words.
+__device__ __forceinline__ void block_sum2(uint32_t &a, uint32_t &b, uint32_t *lds)
+{
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    if (lane == 0) {
+        lds[2 * wid] = a;
+        lds[2 * wid + 1] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + kWave - 1) / kWave;
+        uint32_t sa = 0, sb = 0;
+        for (int w = 0; w < nw; ++w) {
+            sa += lds[2 * w];
+            sb += lds[2 * w + 1];
+        }
+        a = sa;
+        b = sb;
+    }
+}
+
+// Dice of one mask in IEEE double; 1 when both masks are empty.
+__device__ __forceinline__ double dice(uint32_t inter, uint32_t a, uint32_t b)
+{
+    uint64_t den = (uint64_t)a + (uint64_t)b;
+    if (den == 0)
+        return 1.0;
+    return (double)(2 * (uint64_t)inter) / (double)den;
+}
+
+// Ranking order: higher score first, then lower index. Scores are
+// non-negative doubles, so their bit patterns order like the values.
+__device__ __forceinline__ bool ranks_before(uint64_t sa, int32_t ia, uint64_t sb, int32_t ib)
+{
+    return sa > sb || (sa == sb && ia < ib);
+}
+
+}  // namespace tdb

@@ -1,0 +1,98 @@
+// internal.hpp — handle layout, workspace layout and kernel launchers of libtumordb.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/tumordb.h"
+
+namespace tdb {
+
+constexpr uint64_t kMagic = 0x7475'6d6f'7264'6231ULL;  // "tumordb1"
+constexpr size_t kAlign = 256;
+constexpr int kQueryParts = 64;     // blocks of the query-pack kernel
+constexpr int kTopkChunk = 2048;    // entries one top-k block ranks at a time
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Geometry {
+    int nx, ny, nz;
+    int64_t V;   // voxels
+    int W;       // words per mask plane (V / 32)
+    int Wp;      // padded to a multiple of 4 words (16 bytes)
+    int nxw;     // words per x-row (nx / 32)
+};
+
+bool make_geometry(int nx, int ny, int nz, Geometry *g);
+
+struct BatchGraph;  // cached HIP graph of a batched query (api.cpp)
+struct Profiler;    // HIP events around the dominant kernel (api.cpp)
+
+}  // namespace tdb
+
+struct db_t {
+    uint64_t magic;
+    tdb::Geometry g;
+    float t_lo, t_hi;
+    int64_t capacity, count;
+    uint32_t *planes;   // [capacity][2][Wp]
+    uint32_t *popcnt;   // [capacity][2]
+    size_t storage_bytes;
+    int cus;                 // compute units of the device the handle was built on
+    int device;
+    tdb::BatchGraph *graph;
+    tdb::Profiler *prof;
+};
+
+namespace tdb {
+
+// Offsets of the pieces of a query workspace (bytes from its base).
+struct WsLayout {
+    size_t qpack;    // uint32 [nq][2][Wp] packed (and ROI-masked) queries
+    size_t qpart;    // uint32 [nq][kQueryParts][2] per-block query counts
+    size_t acnt;     // uint32 [nq][2] query counts |A_m (n R)|
+    size_t rois;     // int32 [nq][6] ROI boxes (batched calls)
+    size_t inter;    // uint32 [nq][capacity][2] intersections
+    size_t bcnt;     // uint32 [nq][capacity][2] database counts inside the ROI (batched)
+    size_t plan;     // int32 work list of the batched kernel + queue counters
+    size_t topk_a;   // ping-pong top-k candidate buffers: uint64 score bits + int32 index
+    size_t topk_b;
+    size_t total;
+};
+
+WsLayout ws_layout(const db_t *db, int nq, int k, bool batched);
+int64_t topk_blocks(int64_t n);
+
+// ---- launchers (each returns hipGetLastError of its launch) ----
+hipError_t launch_pack_db(const db_t *db, const float *conc, int64_t n, uint32_t *planes,
+                          uint32_t *popcnt, hipStream_t s);
+hipError_t launch_pack_queries(const db_t *db, const uint8_t *labels, int nq, const int32_t *rois,
+                               uint32_t *qpack, uint32_t *qpart, hipStream_t s);
+hipError_t launch_sum_parts(const uint32_t *qpart, int nq, uint32_t *acnt, hipStream_t s);
+hipError_t launch_scan(const db_t *db, int64_t n, const uint32_t *qpack, uint32_t *inter,
+                       hipStream_t s);
+hipError_t launch_batch_scan(const db_t *db, int64_t n, int nq, const uint32_t *qpack,
+                             const int32_t *rois, const int32_t *plan, int64_t n_items,
+                             int32_t *counters, uint32_t *inter, uint32_t *bcnt, hipStream_t s);
+hipError_t launch_fill_u32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+
+// Top-k over n entries per query. inter: [nq][n..][2] with row stride
+// inter_qstride; bcnt likewise (stride 0 = the database popcounts, shared).
+struct TopkArgs {
+    int64_t n;
+    int nq, k;
+    const uint32_t *inter;
+    int64_t inter_qstride;   // uint32 elements between queries
+    const uint32_t *bcnt;
+    int64_t bcnt_qstride;
+    const uint32_t *acnt;    // [nq][2]
+    uint64_t *buf_s[2];
+    int32_t *buf_i[2];
+    int32_t *out_idx;        // [nq][k]
+    double *out_score;       // [nq][k]
+    db_counts_t *out_counts; // [nq][k] or null
+};
+hipError_t launch_topk(const TopkArgs &a, hipStream_t s);
+
+}  // namespace tdb

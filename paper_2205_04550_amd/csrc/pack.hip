@@ -1,0 +1,181 @@
+// pack.hip — threshold + bit-pack of simulated densities, and packing of query labels.
+//
+// Paper Sec. 2.3 ("Query to a database of synthetic tumors"): the raw
+// simulations are densities in [0, 1]; FLAIR and T1Gd segmentations are
+// extracted by thresholding at a lower and a higher level. Here each mask is
+// stored as one bit per voxel (LSB-first in uint32 words, x fastest), which
+// is all a Dice overlap needs and is 32x smaller than float32.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace tdb {
+
+// One block per simulation: 32 voxels -> one word per mask, plus the mask
+// populations |B_FLAIR|, |B_T1Gd| used by every later Dice.
+__global__ void __launch_bounds__(256) pack_db_kernel(const float *__restrict__ conc, int64_t V,
+                                                      int W, int Wp, float t_lo, float t_hi,
+                                                      uint32_t *__restrict__ planes,
+                                                      uint32_t *__restrict__ popcnt)
+{
+    __shared__ uint32_t red[2 * 4];
+    const int64_t s = blockIdx.x;
+    const f32x4 *c = reinterpret_cast<const f32x4 *>(conc + s * V);
+    uint32_t *o = planes + s * 2 * (int64_t)Wp;
+    uint32_t n0 = 0, n1 = 0;
+    for (int w = threadIdx.x; w < Wp; w += blockDim.x) {
+        uint32_t b0 = 0, b1 = 0;
+        if (w < W) {
+            f32x4 v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                v[j] = __builtin_nontemporal_load(c + (int64_t)w * 8 + j);
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    b0 |= (uint32_t)(v[j][e] >= t_lo) << (4 * j + e);
+                    b1 |= (uint32_t)(v[j][e] >= t_hi) << (4 * j + e);
+                }
+        }
+        o[w] = b0;
+        o[Wp + w] = b1;
+        n0 += popc(b0);
+        n1 += popc(b1);
+    }
+    block_sum2(n0, n1, red);
+    if (threadIdx.x == 0) {
+        popcnt[2 * s] = n0;
+        popcnt[2 * s + 1] = n1;
+    }
+}
+
+hipError_t launch_pack_db(const db_t *db, const float *conc, int64_t n, uint32_t *planes,
+                          uint32_t *popcnt, hipStream_t s)
+{
+    const Geometry &g = db->g;
+    // One launch per at most 2^31-1 simulations is far beyond any capacity.
+    hipLaunchKernelGGL(pack_db_kernel, dim3((unsigned)n), dim3(256), 0, s, conc, g.V, g.W, g.Wp,
+                       db->t_lo, db->t_hi, planes, popcnt);
+    return hipGetLastError();
+}
+
+// Bits of word w of one mask that lie inside the ROI (all ones without ROI).
+__device__ __forceinline__ uint32_t roi_word_mask(const int32_t *r, int w, int nxw, int ny)
+{
+    const int wx = w % nxw;
+    const int row = w / nxw;
+    const int y = row % ny;
+    const int z = row / ny;
+    if (z < r[2] || z >= r[5] || y < r[1] || y >= r[4])
+        return 0u;
+    const int lo = r[0] - 32 * wx;  // first voxel of the box relative to the word
+    const int hi = r[3] - 32 * wx;  // one past the last
+    if (hi <= 0 || lo >= 32)
+        return 0u;
+    uint32_t m = 0xffffffffu;
+    if (lo > 0) m &= 0xffffffffu << lo;
+    if (hi < 32) m &= (1u << hi) - 1u;
+    return m;
+}
+
+// grid (kQueryParts, nq): labels uint8 [nq][V] -> packed [nq][2][Wp] and
+// per-block counts [nq][kQueryParts][2]. With rois, bits outside the box
+// are cleared, so later overlaps need no masking of the query side.
+__global__ void __launch_bounds__(256) pack_query_kernel(const uint8_t *__restrict__ labels,
+                                                         int64_t V, int W, int Wp, int nxw, int ny,
+                                                         const int32_t *__restrict__ rois,
+                                                         uint32_t *__restrict__ qpack,
+                                                         uint32_t *__restrict__ qpart)
+{
+    __shared__ uint32_t red[2 * 4];
+    const int q = blockIdx.y;
+    const u32x4 *lab = reinterpret_cast<const u32x4 *>(labels + (int64_t)q * V);
+    uint32_t *o = qpack + (int64_t)q * 2 * Wp;
+    const int32_t *r = rois ? rois + 6 * q : nullptr;
+    uint32_t n0 = 0, n1 = 0;
+    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < Wp; w += gridDim.x * blockDim.x) {
+        uint32_t b0 = 0, b1 = 0;
+        if (w < W) {
+            u32x4 v[2];
+            v[0] = lab[2 * (int64_t)w];
+            v[1] = lab[2 * (int64_t)w + 1];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t x = v[h][e];
+#pragma unroll
+                    for (int by = 0; by < 4; ++by) {
+                        const int bit = 16 * h + 4 * e + by;
+                        b0 |= ((x >> (8 * by)) & 1u) << bit;
+                        b1 |= ((x >> (8 * by + 1)) & 1u) << bit;
+                    }
+                }
+            if (r) {
+                const uint32_t m = roi_word_mask(r, w, nxw, ny);
+                b0 &= m;
+                b1 &= m;
+            }
+        }
+        o[w] = b0;
+        o[Wp + w] = b1;
+        n0 += popc(b0);
+        n1 += popc(b1);
+    }
+    block_sum2(n0, n1, red);
+    if (threadIdx.x == 0) {
+        uint32_t *p = qpart + ((int64_t)q * kQueryParts + blockIdx.x) * 2;
+        p[0] = n0;
+        p[1] = n1;
+    }
+}
+
+hipError_t launch_pack_queries(const db_t *db, const uint8_t *labels, int nq, const int32_t *rois,
+                               uint32_t *qpack, uint32_t *qpart, hipStream_t s)
+{
+    const Geometry &g = db->g;
+    hipLaunchKernelGGL(pack_query_kernel, dim3(kQueryParts, nq), dim3(256), 0, s, labels, g.V,
+                       g.W, g.Wp, g.nxw, g.ny, rois, qpack, qpart);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(64) sum_parts_kernel(const uint32_t *__restrict__ qpart,
+                                                      uint32_t *__restrict__ acnt)
+{
+    const int q = blockIdx.x;
+    uint32_t a = 0, b = 0;
+    for (int i = threadIdx.x; i < kQueryParts; i += 64) {
+        a += qpart[((int64_t)q * kQueryParts + i) * 2];
+        b += qpart[((int64_t)q * kQueryParts + i) * 2 + 1];
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if (threadIdx.x == 0) {
+        acnt[2 * q] = a;
+        acnt[2 * q + 1] = b;
+    }
+}
+
+hipError_t launch_sum_parts(const uint32_t *qpart, int nq, uint32_t *acnt, hipStream_t s)
+{
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(nq), dim3(64), 0, s, qpart, acnt);
+    return hipGetLastError();
+}
+
+__global__ void fill_kernel(int32_t *p, int64_t n, int32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_u32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
+{
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace tdb

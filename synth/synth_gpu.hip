@@ -12,22 +12,19 @@
 
 #include "synth_formula.h"
 
-__global__ void __launch_bounds__(256) synth_fill_kernel(const synth_params_t *__restrict__ params,
+// grid (ny * nz rows, simulations): one block fills one x-row of one volume.
+__global__ void __launch_bounds__(128) synth_fill_kernel(const synth_params_t *__restrict__ params,
                                                          synth_brain_t b, int nx, int ny, int nz,
-                                                         int64_t total, float *__restrict__ out)
+                                                         float *__restrict__ out)
 {
-    int64_t V = (int64_t)nx * ny * nz;
-    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
-         g += (int64_t)gridDim.x * blockDim.x) {
-        int64_t t = g / V;
-        int64_t v = g - t * V;
-        int i = (int)(v % nx);
-        int64_t r = v / nx;
-        int j = (int)(r % ny);
-        int k = (int)(r / ny);
-        synth_params_t p = params[t];
-        out[g] = synth_conc(&p, &b, i, j, k);
-    }
+    const int r = blockIdx.x;
+    const int t = blockIdx.y;
+    const int j = r % ny;
+    const int k = r / ny;
+    const synth_params_t p = params[t];
+    float *o = out + ((int64_t)t * nz * ny + r) * nx;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x)
+        o[i] = synth_conc(&p, &b, i, j, k);
 }
 
 extern "C" int synth_fill_gpu(const void *params_dev, int64_t count, int nx, int ny, int nz,
@@ -42,11 +39,14 @@ extern "C" int synth_fill_gpu(const void *params_dev, int64_t count, int nx, int
     b.iAx = 1.0 / (0.40 * nx);
     b.iAy = 1.0 / (0.46 * ny);
     b.iAz = 1.0 / (0.36 * nz);
-    int64_t total = count * (int64_t)nx * ny * nz;
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(synth_fill_kernel, dim3((unsigned)blocks), dim3(256), 0,
-                       (hipStream_t)stream, (const synth_params_t *)params_dev, b, nx, ny, nz,
-                       total, out_dev);
-    return hipGetLastError() == hipSuccess ? 0 : -2;
+    if ((int64_t)ny * nz > 0x7fffffff) return -1;
+    const int64_t V = (int64_t)nx * ny * nz;
+    for (int64_t t0 = 0; t0 < count; t0 += 65535) {
+        const int64_t c = (count - t0 < 65535) ? count - t0 : 65535;
+        hipLaunchKernelGGL(synth_fill_kernel, dim3((unsigned)(ny * nz), (unsigned)c), dim3(128), 0,
+                           (hipStream_t)stream, (const synth_params_t *)params_dev + t0, b, nx, ny,
+                           nz, out_dev + t0 * V);
+        if (hipGetLastError() != hipSuccess) return -2;
+    }
+    return 0;
 }

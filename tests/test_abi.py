@@ -1,0 +1,70 @@
+"""The C ABI library loads, exports what include/tumordb.h declares, and rejects bad
+arguments before touching the GPU (CPU-only checks)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tumordb.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(db_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("db_build", "db_append", "db_query", "db_query_batch", "db_scan", "db_sync",
+              "db_free", "db_last_error", "db_storage_bytes", "db_query_workspace_bytes"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2205_04550_amd import binding
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert set(declared_functions()) == set(binding.SYMBOLS)
+
+
+def test_storage_bytes():
+    from paper_2205_04550_amd import binding
+    # 128^3: 65,536 words per mask plane, 2 planes, 4 bytes; popcounts 8 bytes per entry.
+    planes = 50000 * 2 * 65536 * 4
+    pcs = (50000 * 8 + 255) // 256 * 256
+    assert binding.storage_bytes(128, 128, 128, 50000) == planes + pcs
+    # Ragged plane: 32x3x1 = 3 words, padded to 4.
+    assert binding.storage_bytes(32, 3, 1, 10) == 512 + 256  # 10*2*4*4=320 -> 512; 80 -> 256
+    assert binding.storage_bytes(33, 4, 4, 10) == 0      # nx not a multiple of 32
+    assert binding.storage_bytes(32, 0, 4, 10) == 0
+    assert binding.storage_bytes(32, 4, 4, 0) == 0
+
+
+def test_build_rejects_bad_arguments_before_any_gpu_call():
+    from paper_2205_04550_amd import binding as b
+    h = ctypes.c_void_p()
+    assert b.LIB.db_build(None, 64, 64, 64, 0.25, 0.675, 10, 256, 1 << 30) == b.DB_EINVAL
+    assert b"NULL" in b.LIB.db_last_error()
+    assert b.LIB.db_build(ctypes.byref(h), 63, 64, 64, 0.25, 0.675, 10, 256, 1 << 30) == b.DB_EINVAL
+    assert b.LIB.db_build(ctypes.byref(h), 64, 64, 64, 0.7, 0.25, 10, 256, 1 << 30) == b.DB_EINVAL
+    assert b.LIB.db_build(ctypes.byref(h), 64, 64, 64, 0.25, 0.675, 10, None, 1 << 30) == b.DB_EINVAL
+    assert b.LIB.db_build(ctypes.byref(h), 64, 64, 64, 0.25, 0.675, 10, 257, 1 << 30) == b.DB_EINVAL
+    assert b.LIB.db_build(ctypes.byref(h), 64, 64, 64, 0.25, 0.675, 10, 256, 100) == b.DB_ENOSPC
+    assert b"needed" in b.LIB.db_last_error()
+    assert h.value is None
+
+
+def test_calls_on_invalid_handle():
+    from paper_2205_04550_amd import binding as b
+    assert b.LIB.db_size(None) == -1
+    assert b.LIB.db_query(None, 256, 1, 256, 256, None, 256, 1 << 20, None) == b.DB_ESTATE
+    assert b.LIB.db_query_batch(None, 1, 256, None, 1, 256, 256, None, 256, 1 << 20, None) == b.DB_ESTATE
+    assert b.LIB.db_scan(None, 256, 256, None, 256, 1 << 20, None) == b.DB_ESTATE
+    assert b.LIB.db_append(None, 256, 1, None) == b.DB_ESTATE
+    assert b.LIB.db_sync(None, None) == b.DB_ESTATE
+    assert b.LIB.db_query_workspace_bytes(None, 1, 10) == 0
+    b.LIB.db_free(None)  # no-op
