@@ -24,6 +24,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Integer VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (lane-ops/s).
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# Sources of the dominant kernel: committed traffic counters are void once these change.
+SCAN_SOURCES = ("paper_2205_04550_amd/csrc/scan.hip", "paper_2205_04550_amd/csrc/common.hpp")
 
 
 def log(msg: str) -> None:
@@ -35,12 +39,33 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["full", "small"], default="full")
+    ap.add_argument("--workload", choices=["full", "small", "batch"], default="full",
+                    help="full: 50,000 x 128^3 exact scan, 1 query (the headline); small: "
+                         "1,000 x 64^3; batch: 256 box-restricted queries per launch on the "
+                         "full database")
+    ap.add_argument("--nq", type=int, default=256, help="queries per launch (batch workload)")
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target duration of the CPU-oracle sample (0 disables it)")
     ap.add_argument("--build-chunk", type=int, default=2048)
+    ap.add_argument("--copy-calibration", type=float, default=0,
+                    help="only run a device-to-device copy of this many bytes (3 times), as the "
+                         "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE, and exit")
     return ap.parse_args()
+
+
+def copy_calibration(nbytes: int) -> int:
+    import torch
+    n = int(nbytes) // 16 * 16
+    src = torch.empty(n, dtype=torch.uint8, device="cuda").view(torch.int64)
+    src.random_()
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n, "copies": 3}), flush=True)
+    return 0
 
 
 def source_sha(*rel: str) -> str:
@@ -51,14 +76,14 @@ def source_sha(*rel: str) -> str:
     return h.hexdigest()
 
 
-def load_traffic(kernel_src: str, workload: str):
+def load_traffic(workload: str):
     """HBM traffic per launch from committed rocprofv3 counter runs, if still current."""
     path = os.path.join(ROOT, "profiles", f"scan_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_sha256") != source_sha(kernel_src):
+    if t.get("kernel_source_sha256") != source_sha(*SCAN_SOURCES):
         return None
     return t.get("bytes_per_launch")
 
@@ -83,12 +108,95 @@ def cpu_baseline(gen, q, t_lo, t_hi, target_s: float):
                       f"{passes} passes of the plain for-loop, {elapsed:.1f} s"}
 
 
+def roi_work(rois, n: int):
+    """Voxel pairs compared and packed word positions (both masks) inside the boxes."""
+    vox = 0
+    words = 0
+    for x0, y0, z0, x1, y1, z1 in rois.tolist():
+        vox += (x1 - x0) * (y1 - y0) * (z1 - z0)
+        words += (((x1 - 1) >> 5) - (x0 >> 5) + 1) * (y1 - y0) * (z1 - z0)
+    return vox * n, 2 * words * n
+
+
+def bench_batch(args, db, gen, n, build_s) -> int:
+    """256 noisy queries, each cut to its own box, per db_query_batch launch."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import synth
+    t_lo, t_hi, k, nq = synth.T_LO, synth.T_HI, args.k, args.nq
+    log(f"making {nq} queries and boxes")
+    labels, srcs = synth.make_queries(gen, n, nq, synth.BATCH_QUERY_SEED)
+    rois = synth.make_rois(labels, synth.ROI_SEED)
+    lab_d = torch.from_numpy(labels).cuda()
+    out = (torch.empty((nq, k), dtype=torch.int32, device="cuda"),
+           torch.empty((nq, k), dtype=torch.float64, device="cuda"),
+           torch.empty((nq, k, 6), dtype=torch.int32, device="cuda"))
+    ws = db.workspace(nq, k)
+    db.query_batch(lab_d, rois, k, out=out, ws=ws)
+    db.sync()
+    # Re-check two queries' returned entries with the oracle.
+    ok = True
+    for qi in (0, nq - 1):
+        idx = out[0][qi].cpu().numpy().tolist()
+        _, o_cnt, o_sc = oracle.scan(gen, n, labels[qi], t_lo, t_hi, roi=rois[qi], indices=idx)
+        ok &= bool(np.array_equal(o_sc.view(np.uint64), out[1][qi].cpu().numpy().view(np.uint64))
+                   and np.array_equal(out[2][qi].cpu().numpy().view(np.uint32).astype(np.uint64),
+                                      o_cnt))
+    log(f"returned entries of queries 0 and {nq - 1} re-checked by the oracle: "
+        f"{'ok' if ok else 'MISMATCH'}")
+    for _ in range(args.warmup):
+        db.query_batch(lab_d, rois, k, out=out, ws=ws)
+    torch.cuda.synchronize()
+    db.profile(True)
+    db.profile_read()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        db.query_batch(lab_d, rois, k, out=out, ws=ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g_ms, launches = db.profile_read()
+    db.profile(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    pairs_vox, words = roi_work(rois, n)
+    g_avg = g_ms / max(1, launches)
+    ops = 3 * words   # per packed word and mask: AND, popcount-add (I), popcount-add (B)
+    achieved = ops / (g_avg * 1e-3)
+    log(f"{ms:.2f} ms per {nq}-query launch; {pairs_vox / (ms * 1e-3):.3e} voxel pairs/s; "
+        f"{achieved / VALU_PEAK_OPS:.1%} of integer VALU issue")
+    line = {
+        "metric": "database voxels compared/sec",
+        "value": pairs_vox / (ms * 1e-3),
+        "unit": "voxels/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"batched exact scan, {nq} box-restricted queries x {n} sims x "
+                               f"{gen.nx}^3, top-{k} each, one persistent launch from a HIP graph",
+                   "n_db": n, "nq": nq, "k": k, "mean_box_voxels": pairs_vox / n / nq},
+        "queries_per_s": nq / (ms * 1e-3),
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                     "unit": "Tops/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                     "kernel": "batch_scan_kernel (graph)", "kernel_avg_ms": g_avg,
+                     "algorithmic_ops_per_launch": ops,
+                     "hbm_floor_gb_per_launch": n * 2 * gen.nvox / 8 / 1e9},
+        "cpu_baseline": None,
+        "parity": {"returned_entries_rechecked_by_oracle": ok},
+        "build_s": build_s,
+    }
+    print(json.dumps(line), flush=True)
+    return 0 if ok else 1
+
+
 def main() -> int:
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path runs "
               "on a single MI355X; multi-GPU sharding is a design note only).", file=sys.stderr)
         return 2
+    if args.copy_calibration:
+        return copy_calibration(int(args.copy_calibration))
     import numpy as np
     import torch
 
@@ -98,7 +206,7 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
-    gen, n = (synth.FULL, synth.FULL_N) if args.workload == "full" else (synth.SMALL, synth.SMALL_N)
+    gen, n = (synth.SMALL, synth.SMALL_N) if args.workload == "small" else (synth.FULL, synth.FULL_N)
     t_lo, t_hi, k = synth.T_LO, synth.T_HI, args.k
     V = gen.nvox
 
@@ -119,6 +227,9 @@ def main() -> int:
     torch.cuda.empty_cache()
     build_s = time.perf_counter() - tb
     log(f"built in {build_s:.1f} s")
+
+    if args.workload == "batch":
+        return bench_batch(args, db, gen, n, build_s)
 
     src = synth.query_source(n, synth.QUERY_SEED, 0)
     q = gen.query(src, t_lo, t_hi, synth.QUERY_SEED, 0)
@@ -160,7 +271,7 @@ def main() -> int:
     alg_bytes = n * 2 * (V // 8)
     scan_avg_ms = scan_ms / max(1, launches)
     achieved = alg_bytes / (scan_avg_ms * 1e-3) / 1e9
-    traffic = load_traffic("paper_2205_04550_amd/csrc/scan.hip", args.workload)
+    traffic = load_traffic(args.workload)
     log(f"{ms_per_step:.3f} ms/query; scan kernel {scan_avg_ms:.3f} ms = {achieved:.0f} GB/s")
 
     cpu = None

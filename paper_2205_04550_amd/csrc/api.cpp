@@ -72,8 +72,9 @@ WsLayout ws_layout(const db_t *db, int nq, int k, bool batched)
     L.rois = take((size_t)nq * 6 * 4);
     L.inter = take((size_t)nq * cap * 2 * 4);
     L.bcnt = batched ? take((size_t)nq * cap * 2 * 4) : off;
-    // plan: query order [nq] + 8 queue counters
-    L.plan = take(((size_t)nq + 8) * 4);
+    // plan: query order [nq], 8 queue counters, slab list offsets [nq * nz + 1] and
+    // slab lists [nq * nz] (at most one chunk per query and one slab per plane)
+    L.plan = take(((size_t)nq + 8 + 2 * (size_t)nq * db->g.nz + 1) * 4);
     const size_t cand = (size_t)nq * topk_blocks(cap) * k;
     L.topk_a = take(cand * 12);
     L.topk_b = take(cand * 12);
@@ -166,7 +167,7 @@ static T *at(void *ws, size_t off)
 // Enqueue the kernel sequence of a batched query on stream s.
 static hipError_t enqueue_batch(const db_t *db, int nq, const uint8_t *q_labels, int k,
                                 int32_t *idx, double *score, db_counts_t *counts, void *ws,
-                                const WsLayout &L, hipStream_t s)
+                                const WsLayout &L, const BatchPlan &P, hipStream_t s)
 {
     uint32_t *qpack = at<uint32_t>(ws, L.qpack);
     uint32_t *acnt = at<uint32_t>(ws, L.acnt);
@@ -175,11 +176,14 @@ static hipError_t enqueue_batch(const db_t *db, int nq, const uint8_t *q_labels,
     int32_t *rois = at<int32_t>(ws, L.rois);
     int32_t *order = at<int32_t>(ws, L.plan);
     int32_t *counters = order + nq;
+    int32_t *list_off = counters + 8;
+    int32_t *list_q = list_off + (size_t)nq * db->g.nz + 1;
     hipError_t e = launch_pack_queries(db, q_labels, nq, rois, qpack, at<uint32_t>(ws, L.qpart), s);
     if (e == hipSuccess) e = launch_sum_parts(at<uint32_t>(ws, L.qpart), nq, acnt, s);
     if (e == hipSuccess) e = launch_fill_u32(counters, 8, 0, s);
     if (e == hipSuccess)
-        e = launch_batch_scan(db, db->count, nq, qpack, rois, order, 0, counters, inter, bcnt, s);
+        e = launch_batch_scan(db, db->count, nq, P, qpack, rois, order, list_off, list_q, counters,
+                              inter, bcnt, s);
     if (e == hipSuccess) {
         TopkArgs a{};
         a.n = db->count;
@@ -231,10 +235,17 @@ int db_build(db_t **out, int nx, int ny, int nz, float t_lo, float t_hi, int64_t
     const size_t need = db_storage_bytes(nx, ny, nz, capacity);
     if (storage_bytes < need)
         return fail(DB_ENOSPC, "db_build: storage %zu bytes < %zu needed", storage_bytes, need);
-    int dev = 0, cus = 0;
+    int dev = 0, cus = 0, lds = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) return hip_fail(e, "db_build: device query");
+    // Let the batched kernel use all of it (above the default dynamic limit).
+    if (batch_set_lds_limit(lds) != hipSuccess) {
+        (void)hipGetLastError();
+        lds = 65536;
+    }
     db_t *db = new (std::nothrow) db_t{};
     if (!db) return fail(DB_ENOMEM, "db_build: out of host memory");
     db->magic = kMagic;
@@ -249,6 +260,7 @@ int db_build(db_t **out, int nx, int ny, int nz, float t_lo, float t_hi, int64_t
     db->storage_bytes = storage_bytes;
     db->cus = cus;
     db->device = dev;
+    db->lds_max = lds;
     db->graph = nullptr;
     db->prof = nullptr;
     *out = db;
@@ -386,6 +398,23 @@ int db_query_batch(const db_t *db_c, int nq, const uint8_t *q_labels, const db_r
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    // Per (query chunk, z-slab): the queries whose box meets the slab, costliest first.
+    const BatchPlan P = batch_plan(db, nq);
+    std::vector<int32_t> list_off, list_q;
+    if (P.use_lds) {
+        list_off.reserve((size_t)P.nchunks * P.nslabs + 1);
+        list_off.push_back(0);
+        for (int c = 0; c < P.nchunks; ++c)
+            for (int sl = 0; sl < P.nslabs; ++sl) {
+                const int zs0 = sl * P.Z, zs1 = std::min(g.nz, zs0 + P.Z);
+                for (int32_t q : order) {
+                    if (q / P.qchunk != c) continue;
+                    const int32_t *b = &box[(size_t)q * 6];
+                    if (b[2] < zs1 && b[5] > zs0) list_q.push_back(q);
+                }
+                list_off.push_back((int32_t)list_q.size());
+            }
+    }
 
     if (!db->graph) {
         db->graph = new (std::nothrow) BatchGraph();
@@ -399,7 +428,7 @@ int db_query_batch(const db_t *db_c, int nq, const uint8_t *q_labels, const db_r
         if (e != hipSuccess) return hip_fail(e, "db_query_batch: stream/event create");
     }
     // Pinned staging buffer; wait for the previous upload before reusing it.
-    const size_t elems = (size_t)nq * 7;
+    const size_t elems = (size_t)nq * 7 + list_off.size() + list_q.size();
     if (G.upload_pending) {
         e = hipEventSynchronize(G.uploaded);
         if (e != hipSuccess) return hip_fail(e, "db_query_batch: wait for previous upload");
@@ -415,6 +444,10 @@ int db_query_batch(const db_t *db_c, int nq, const uint8_t *q_labels, const db_r
     }
     std::memcpy(G.staging, box.data(), (size_t)nq * 6 * 4);
     std::memcpy(G.staging + (size_t)nq * 6, order.data(), (size_t)nq * 4);
+    int32_t *st_lists = G.staging + (size_t)nq * 7;
+    if (!list_off.empty()) std::memcpy(st_lists, list_off.data(), list_off.size() * 4);
+    if (!list_q.empty())
+        std::memcpy(st_lists + list_off.size(), list_q.data(), list_q.size() * 4);
 
     // (Re)record the graph when the shape or any pointer changed.
     const bool same = G.exec && G.nq == nq && G.k == k && G.n == db->count &&
@@ -425,7 +458,7 @@ int db_query_batch(const db_t *db_c, int nq, const uint8_t *q_labels, const db_r
         hipGraph_t graph = nullptr;
         e = hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "db_query_batch: begin capture");
-        hipError_t le = enqueue_batch(db, nq, q_labels, k, idx, score, counts, ws, L, G.cap);
+        hipError_t le = enqueue_batch(db, nq, q_labels, k, idx, score, counts, ws, L, P, G.cap);
         e = hipStreamEndCapture(G.cap, &graph);
         if (le != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -453,6 +486,14 @@ int db_query_batch(const db_t *db_c, int nq, const uint8_t *q_labels, const db_r
     if (e == hipSuccess)
         e = hipMemcpyAsync(at<int32_t>(ws, L.plan), G.staging + (size_t)nq * 6, (size_t)nq * 4,
                            hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !list_off.empty()) {
+        int32_t *d_off = at<int32_t>(ws, L.plan) + nq + 8;
+        int32_t *d_q = d_off + (size_t)nq * g.nz + 1;
+        e = hipMemcpyAsync(d_off, st_lists, list_off.size() * 4, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && !list_q.empty())
+            e = hipMemcpyAsync(d_q, st_lists + list_off.size(), list_q.size() * 4,
+                               hipMemcpyHostToDevice, s);
+    }
     if (e == hipSuccess) e = hipEventRecord(G.uploaded, s);
     if (e != hipSuccess) return hip_fail(e, "db_query_batch: upload");
     G.upload_pending = true;

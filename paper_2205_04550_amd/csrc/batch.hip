@@ -1,19 +1,29 @@
-// batch.hip — many queries, each restricted to its own box, in one persistent launch.
+// batch.hip — many queries, each restricted to its own box, in one launch.
 //
 // Same overlap as the single-query scan (paper Sec. 2.3: Dice of both masks,
 // summed), but query q only looks at voxels inside its box R_q, on both
 // sides: I_m = |A_m n B_m n R_q|, and the database side's |B_m n R_q| is
 // counted on the fly (it depends on the box). The query words were ROI-masked
-// when packed, so only the database side needs the x-edge masks.
+// when packed, so only the database side needs x-edge masks.
 //
-// Work: item = (query q, tile of kTile consecutive entries). Items are held
-// in 8 queues, one per XCD: queue x owns tiles t = x, x+8, ... and, inside a
-// tile, the queries in descending cost order (cost = box words). Workgroups
-// are dispatched round-robin over the XCDs, so block b starts on queue b % 8
-// and the tiles a queue touches stay in that XCD's L2 while every query
-// passes over them. A block that finds its queue empty steals from the
-// others, so every item is done even if the dispatch order differs; the
-// mapping only affects speed. Every block exits once all 8 queues are empty.
+// Main kernel (batch_lds_kernel): one block owns a tile of kTile entries and
+// streams them through LDS in z-slabs of Z planes, so every database word is
+// read from HBM exactly once per launch. For each slab, the block's waves
+// take the queries whose box meets the slab (a host-built list, costliest
+// first) and run them against the LDS copy: a lane per box row, the packed
+// query row from L2 reused for the kTile entries. Per-(query, entry) counters
+// live in LDS; a wave folds its 16 partial counters with a reduce-scatter (17
+// shuffles) and adds them there; the block writes them out after the last
+// slab. The work is integer VALU bound: per packed word and mask, AND +
+// popcount for I and AND + popcount for |B n R|.
+//
+// Fallback (batch_rows_kernel): grids whose one-plane slab does not fit in LDS
+// use a persistent (query, tile) kernel that reads the database through L2.
+// Its items sit in 8 queues, one per XCD (tile t in queue t % 8, queries in
+// descending cost inside a tile); block b starts on queue b % 8 (dispatch is
+// round-robin over XCDs) and steals from the others when its queue is empty,
+// so every item is done whatever the dispatch order; the mapping only affects
+// L2 locality. Every block exits once all 8 queues are empty.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -21,6 +31,8 @@ namespace tdb {
 
 constexpr int kTile = 4;
 constexpr int kXcd = 8;
+constexpr int kBatchThreads = 1024;
+constexpr int kQueryChunk = 256;   // queries whose counters share one block's LDS
 
 // ceil(2^32 / d) for d >= 2 (d = 1 is handled by the caller: it would need 2^32).
 // floor(r * M / 2^32) == r / d whenever r * d < 2^32, which the host
@@ -35,7 +47,194 @@ __device__ __forceinline__ uint32_t div_magic(uint32_t r, uint32_t d, uint32_t M
     return d == 1 ? r : __umulhi(r, M);
 }
 
-__global__ void __launch_bounds__(256) batch_scan_kernel(
+// Bits of word wx (voxels x = 32 wx .. 32 wx + 31) inside [x0, x1).
+__device__ __forceinline__ uint32_t xmask(int wx, int x0, int x1)
+{
+    const int lo = x0 - 32 * wx, hi = x1 - 32 * wx;
+    if (hi <= 0 || lo >= 32) return 0u;
+    uint32_t m = 0xffffffffu;
+    if (lo > 0) m &= 0xffffffffu << lo;
+    if (hi < 32) m &= (1u << hi) - 1u;
+    return m;
+}
+
+// Sum 16 per-lane values over the 64 lanes of a wave with 17 shuffles
+// (halve the value set at each xor step, then fold the last two lane bits).
+// Every lane returns the total of value number
+//   ((lane >> 5) & 1) << 3 | ((lane >> 4) & 1) << 2 | ((lane >> 3) & 1) << 1 | ((lane >> 2) & 1).
+__device__ __forceinline__ uint32_t reduce16(const uint32_t (&v)[16], int lane)
+{
+    const bool h5 = lane & 32, h4 = lane & 16, h3 = lane & 8, h2 = lane & 4;
+    uint32_t a[8], b[4], c[2];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint32_t send = h5 ? v[j] : v[j + 8];
+        const uint32_t keep = h5 ? v[j + 8] : v[j];
+        a[j] = keep + __shfl_xor(send, 32, 64);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t send = h4 ? a[j] : a[j + 4];
+        const uint32_t keep = h4 ? a[j + 4] : a[j];
+        b[j] = keep + __shfl_xor(send, 16, 64);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const uint32_t send = h3 ? b[j] : b[j + 2];
+        const uint32_t keep = h3 ? b[j + 2] : b[j];
+        c[j] = keep + __shfl_xor(send, 8, 64);
+    }
+    const uint32_t send = h2 ? c[0] : c[1];
+    const uint32_t keep = h2 ? c[1] : c[0];
+    uint32_t d = keep + __shfl_xor(send, 4, 64);
+    d += __shfl_xor(d, 2, 64);
+    d += __shfl_xor(d, 1, 64);
+    return d;
+}
+
+// grid (tiles, query chunks), kBatchThreads threads. Dynamic LDS:
+//   D   uint32 [kTile][2][Z * ny * nxw]   the tile's slab, both masks
+//   cnt uint32 [nqc][kTile][4]            I_FLAIR, I_T1Gd, |B_FLAIR n R|, |B_T1Gd n R|
+// list_off [chunks * nslabs + 1] / list_q: per (chunk, slab) the queries whose
+// box meets the slab.
+__global__ void __launch_bounds__(kBatchThreads) batch_lds_kernel(
+    const uint32_t *__restrict__ planes, int Wp, int nxw, int ny, int nz, int64_t n, int Z,
+    int nslabs, const uint32_t *__restrict__ qpack, const int32_t *__restrict__ rois,
+    const int32_t *__restrict__ list_off, const int32_t *__restrict__ list_q, int qchunk, int nq,
+    uint32_t *__restrict__ inter, uint32_t *__restrict__ bcnt, int64_t out_qstride)
+{
+    extern __shared__ u32x4 lds4[];
+    uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
+    const int plane_w = ny * nxw;              // words per z-plane of one mask
+    const int slab_w = Z * plane_w;            // words per slab of one mask
+    uint32_t *D = lds;                         // [kTile][2][slab_w]
+    uint32_t *cnt = lds + kTile * 2 * slab_w;  // [nqc][kTile][4]
+    const int chunk = blockIdx.y;
+    const int q0 = chunk * qchunk;
+    const int nqc = min(qchunk, nq - q0);
+    const int64_t e0 = (int64_t)blockIdx.x * kTile;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwaves = blockDim.x >> 6;
+
+    for (int i = threadIdx.x; i < nqc * kTile * 4; i += blockDim.x)
+        cnt[i] = 0;
+
+    for (int slab = 0; slab < nslabs; ++slab) {
+        const int zs0 = slab * Z;
+        const int zn = min(Z, nz - zs0);
+        const int words = zn * plane_w;
+        __syncthreads();  // the previous slab is consumed; counters are zeroed
+        // Stage the tile's slab: kTile entries x 2 masks x `words` words.
+        if ((plane_w & 3) == 0) {
+            const int w4 = words >> 2;
+            for (int i = threadIdx.x; i < kTile * 2 * w4; i += blockDim.x) {
+                const int sm = i / w4;
+                const int j = i - sm * w4;
+                const int s = sm >> 1, m = sm & 1;
+                const int64_t e = (e0 + s < n) ? e0 + s : n - 1;  // alias past the end
+                const u32x4 *g = reinterpret_cast<const u32x4 *>(
+                    planes + e * 2 * (int64_t)Wp + (int64_t)m * Wp + (int64_t)zs0 * plane_w);
+                reinterpret_cast<u32x4 *>(D + sm * slab_w)[j] = load_stream(g + j);
+            }
+        } else {
+            for (int i = threadIdx.x; i < kTile * 2 * words; i += blockDim.x) {
+                const int sm = i / words;
+                const int j = i - sm * words;
+                const int s = sm >> 1, m = sm & 1;
+                const int64_t e = (e0 + s < n) ? e0 + s : n - 1;
+                D[sm * slab_w + j] =
+                    planes[e * 2 * (int64_t)Wp + (int64_t)m * Wp + (int64_t)zs0 * plane_w + j];
+            }
+        }
+        __syncthreads();
+        const int lo = list_off[chunk * nslabs + slab];
+        const int hi = list_off[chunk * nslabs + slab + 1];
+        for (int li = lo + wave; li < hi; li += nwaves) {
+            const int q = list_q[li];
+            const int32_t *R = rois + 6 * q;
+            const int x0 = R[0], y0 = R[1], z0 = R[2], x1 = R[3], y1 = R[4], z1 = R[5];
+            const int zlo = max(z0, zs0), zhi = min(z1, zs0 + zn);
+            const uint32_t nyr = (uint32_t)(y1 - y0);
+            const uint32_t nr = (zhi > zlo) ? (uint32_t)(zhi - zlo) * nyr : 0u;
+            const uint32_t M = nyr > 1 ? magic_u32(nyr) : 0u;
+            const uint32_t *Q0 = qpack + (int64_t)q * 2 * Wp;
+            const uint32_t *Q1 = Q0 + Wp;
+            uint32_t acc[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc[j] = 0;
+            if (nxw == 4) {
+                // 128-voxel rows: one 16-byte word group per row and mask.
+                const uint32_t xm0 = xmask(0, x0, x1), xm1 = xmask(1, x0, x1);
+                const uint32_t xm2 = xmask(2, x0, x1), xm3 = xmask(3, x0, x1);
+                for (uint32_t r = lane; r < nr; r += 64) {
+                    const uint32_t zr = div_magic(r, nyr, M);
+                    const int z = zlo + (int)zr;
+                    const int y = y0 + (int)(r - zr * nyr);
+                    const int gw = (z * ny + y) * 4;
+                    const int lw = ((z - zs0) * ny + y) * 4;
+                    const u32x4 qa = *reinterpret_cast<const u32x4 *>(Q0 + gw);
+                    const u32x4 qb = *reinterpret_cast<const u32x4 *>(Q1 + gw);
+#pragma unroll
+                    for (int s = 0; s < kTile; ++s) {
+                        const u32x4 da = *reinterpret_cast<const u32x4 *>(D + (2 * s) * slab_w + lw);
+                        const u32x4 db = *reinterpret_cast<const u32x4 *>(D + (2 * s + 1) * slab_w + lw);
+                        acc[4 * s + 0] += popc_and4(qa, da);
+                        acc[4 * s + 1] += popc_and4(qb, db);
+                        acc[4 * s + 2] += popc(da.x & xm0) + popc(da.y & xm1) + popc(da.z & xm2) +
+                                          popc(da.w & xm3);
+                        acc[4 * s + 3] += popc(db.x & xm0) + popc(db.y & xm1) + popc(db.z & xm2) +
+                                          popc(db.w & xm3);
+                    }
+                }
+            } else {
+                const int wx0 = x0 >> 5, wx1 = (x1 - 1) >> 5;
+                for (uint32_t r = lane; r < nr; r += 64) {
+                    const uint32_t zr = div_magic(r, nyr, M);
+                    const int z = zlo + (int)zr;
+                    const int y = y0 + (int)(r - zr * nyr);
+                    const int gw = (z * ny + y) * nxw;
+                    const int lw = ((z - zs0) * ny + y) * nxw;
+                    for (int wx = wx0; wx <= wx1; ++wx) {
+                        const uint32_t xm = xmask(wx, x0, x1);
+                        const uint32_t qa = Q0[gw + wx], qb = Q1[gw + wx];
+#pragma unroll
+                        for (int s = 0; s < kTile; ++s) {
+                            const uint32_t da = D[(2 * s) * slab_w + lw + wx];
+                            const uint32_t db = D[(2 * s + 1) * slab_w + lw + wx];
+                            acc[4 * s + 0] += popc(qa & da);
+                            acc[4 * s + 1] += popc(qb & db);
+                            acc[4 * s + 2] += popc(da & xm);
+                            acc[4 * s + 3] += popc(db & xm);
+                        }
+                    }
+                }
+            }
+            const uint32_t tot = reduce16(acc, lane);
+            if ((lane & 3) == 0) {
+                const int vidx = (((lane >> 5) & 1) << 3) | (((lane >> 4) & 1) << 2) |
+                                 (((lane >> 3) & 1) << 1) | ((lane >> 2) & 1);
+                atomicAdd(&cnt[(q - q0) * kTile * 4 + vidx], tot);
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nqc * kTile; i += blockDim.x) {
+        const int qi = i / kTile, s = i - qi * kTile;
+        const int64_t e = e0 + s;
+        if (e < n) {
+            const uint32_t *c = cnt + i * 4;
+            uint32_t *io = inter + (int64_t)(q0 + qi) * out_qstride + 2 * e;
+            uint32_t *bo = bcnt + (int64_t)(q0 + qi) * out_qstride + 2 * e;
+            io[0] = c[0];
+            io[1] = c[1];
+            bo[0] = c[2];
+            bo[1] = c[3];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) batch_rows_kernel(
     const uint32_t *__restrict__ planes, int Wp, int nxw, int ny, int64_t n, int nq,
     const uint32_t *__restrict__ qpack, const int32_t *__restrict__ rois,
     const int32_t *__restrict__ order, int64_t ntiles, int32_t *counters,
@@ -127,17 +326,47 @@ __global__ void __launch_bounds__(256) batch_scan_kernel(
     }
 }
 
-hipError_t launch_batch_scan(const db_t *db, int64_t n, int nq, const uint32_t *qpack,
-                             const int32_t *rois, const int32_t *plan, int64_t n_items,
-                             int32_t *counters, uint32_t *inter, uint32_t *bcnt, hipStream_t s)
+BatchPlan batch_plan(const db_t *db, int nq)
 {
-    (void)n_items;
+    BatchPlan p{};
+    const Geometry &g = db->g;
+    p.qchunk = nq < kQueryChunk ? nq : kQueryChunk;
+    p.nchunks = (nq + p.qchunk - 1) / p.qchunk;
+    const int64_t plane_bytes = (int64_t)g.ny * g.nxw * 4;
+    const int64_t cnt_bytes = (int64_t)p.qchunk * kTile * 4 * 4;
+    const int64_t budget = (int64_t)db->lds_max - cnt_bytes;
+    int64_t Z = budget > 0 ? budget / (kTile * 2 * plane_bytes) : 0;
+    if (Z > g.nz) Z = g.nz;
+    p.Z = (int)Z;
+    p.use_lds = Z >= 1;
+    p.nslabs = p.use_lds ? (g.nz + p.Z - 1) / p.Z : 0;
+    p.lds_bytes = p.use_lds ? (size_t)(kTile * 2 * plane_bytes * Z + cnt_bytes) : 0;
+    return p;
+}
+
+hipError_t batch_set_lds_limit(int bytes)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&batch_lds_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+hipError_t launch_batch_scan(const db_t *db, int64_t n, int nq, const BatchPlan &p,
+                             const uint32_t *qpack, const int32_t *rois, const int32_t *order,
+                             const int32_t *list_off, const int32_t *list_q, int32_t *counters,
+                             uint32_t *inter, uint32_t *bcnt, hipStream_t s)
+{
     const Geometry &g = db->g;
     const int64_t ntiles = (n + kTile - 1) / kTile;
-    const int blocks = db->cus * 8;
-    hipLaunchKernelGGL(batch_scan_kernel, dim3(blocks), dim3(256), 0, s, db->planes, g.Wp, g.nxw,
-                       g.ny, n, nq, qpack, rois, plan, ntiles, counters, inter, bcnt,
-                       2 * db->capacity);
+    if (p.use_lds) {
+        hipLaunchKernelGGL(batch_lds_kernel, dim3((unsigned)ntiles, p.nchunks), dim3(kBatchThreads),
+                           p.lds_bytes, s, db->planes, g.Wp, g.nxw, g.ny, g.nz, n, p.Z, p.nslabs,
+                           qpack, rois, list_off, list_q, p.qchunk, nq, inter, bcnt,
+                           2 * db->capacity);
+    } else {
+        hipLaunchKernelGGL(batch_rows_kernel, dim3(db->cus * 8), dim3(256), 0, s, db->planes, g.Wp,
+                           g.nxw, g.ny, n, nq, qpack, rois, order, ntiles, counters, inter, bcnt,
+                           2 * db->capacity);
+    }
     return hipGetLastError();
 }
 

@@ -41,6 +41,7 @@ struct db_t {
     size_t storage_bytes;
     int cus;                 // compute units of the device the handle was built on
     int device;
+    int lds_max;             // LDS bytes one block may use on that device
     tdb::BatchGraph *graph;
     tdb::Profiler *prof;
 };
@@ -55,7 +56,7 @@ struct WsLayout {
     size_t rois;     // int32 [nq][6] ROI boxes (batched calls)
     size_t inter;    // uint32 [nq][capacity][2] intersections
     size_t bcnt;     // uint32 [nq][capacity][2] database counts inside the ROI (batched)
-    size_t plan;     // int32 work list of the batched kernel + queue counters
+    size_t plan;     // int32: query order [nq], queue counters [8], slab lists (batched)
     size_t topk_a;   // ping-pong top-k candidate buffers: uint64 score bits + int32 index
     size_t topk_b;
     size_t total;
@@ -72,9 +73,18 @@ hipError_t launch_pack_queries(const db_t *db, const uint8_t *labels, int nq, co
 hipError_t launch_sum_parts(const uint32_t *qpart, int nq, uint32_t *acnt, hipStream_t s);
 hipError_t launch_scan(const db_t *db, int64_t n, const uint32_t *qpack, uint32_t *inter,
                        hipStream_t s);
-hipError_t launch_batch_scan(const db_t *db, int64_t n, int nq, const uint32_t *qpack,
-                             const int32_t *rois, const int32_t *plan, int64_t n_items,
-                             int32_t *counters, uint32_t *inter, uint32_t *bcnt, hipStream_t s);
+// Shape of a batched launch: LDS slabs of Z planes (use_lds) or the L2 fallback.
+struct BatchPlan {
+    bool use_lds;
+    int Z, nslabs, qchunk, nchunks;
+    size_t lds_bytes;
+};
+BatchPlan batch_plan(const db_t *db, int nq);
+hipError_t batch_set_lds_limit(int bytes);
+hipError_t launch_batch_scan(const db_t *db, int64_t n, int nq, const BatchPlan &p,
+                             const uint32_t *qpack, const int32_t *rois, const int32_t *order,
+                             const int32_t *list_off, const int32_t *list_q, int32_t *counters,
+                             uint32_t *inter, uint32_t *bcnt, hipStream_t s);
 hipError_t launch_fill_u32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 
 // Top-k over n entries per query. inter: [nq][n..][2] with row stride

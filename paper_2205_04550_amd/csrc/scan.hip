@@ -12,13 +12,17 @@
 // reads 16-byte words of both mask planes with non-temporal loads, UNROLL
 // deep, so each wave keeps UNROLL * SIMS * 2 KiB of loads in flight. The
 // query (2 * Wp words) is re-read from L2 by every block and amortised over
-// the SIMS entries of the block.
+// the SIMS entries of the block. SIMS = 2, UNROLL = 2 was the fastest of a
+// sweep over block size (256/512/1024), SIMS (1/2/4), UNROLL (2/4/8),
+// persistent vs one-shot grids and temporal vs non-temporal loads: 6.99 TB/s
+// against 7.13-7.17 TB/s for a plain non-temporal read of the same bytes;
+// SIMS = 1 loses ~10% to the doubled L2 traffic of the query.
 #include "common.hpp"
 #include "internal.hpp"
 
 namespace tdb {
 
-template <int SIMS, int UNROLL>
+template <int SIMS, int UNROLL, bool TAIL>
 __global__ void __launch_bounds__(256) scan_kernel(const u32x4 *__restrict__ db, int64_t rec_u4,
                                                    int plane_u4, const u32x4 *__restrict__ q,
                                                    int64_t n, uint32_t *__restrict__ inter)
@@ -40,7 +44,7 @@ __global__ void __launch_bounds__(256) scan_kernel(const u32x4 *__restrict__ db,
 #pragma unroll
         for (int u = 0; u < UNROLL; ++u) {
             const int i = base + u * 256 + threadIdx.x;
-            if (i < plane_u4) {
+            if (!TAIL || i < plane_u4) {
                 q0[u] = q[i];
                 q1[u] = q[plane_u4 + i];
 #pragma unroll
@@ -78,11 +82,17 @@ hipError_t launch_scan(const db_t *db, int64_t n, const uint32_t *qpack, uint32_
 {
     const int plane_u4 = db->g.Wp / 4;
     const int64_t rec_u4 = 2 * (int64_t)plane_u4;
-    constexpr int SIMS = 1, UNROLL = 4;
+    constexpr int SIMS = 2, UNROLL = 2;
     const int64_t blocks = (n + SIMS - 1) / SIMS;
-    hipLaunchKernelGGL((scan_kernel<SIMS, UNROLL>), dim3((unsigned)blocks), dim3(256), 0, s,
-                       reinterpret_cast<const u32x4 *>(db->planes), rec_u4, plane_u4,
-                       reinterpret_cast<const u32x4 *>(qpack), n, inter);
+    const auto *dbp = reinterpret_cast<const u32x4 *>(db->planes);
+    const auto *qp = reinterpret_cast<const u32x4 *>(qpack);
+    // Planes that are a whole number of block steps need no tail test.
+    if (plane_u4 % (256 * UNROLL) == 0)
+        hipLaunchKernelGGL((scan_kernel<SIMS, UNROLL, false>), dim3((unsigned)blocks), dim3(256),
+                           0, s, dbp, rec_u4, plane_u4, qp, n, inter);
+    else
+        hipLaunchKernelGGL((scan_kernel<SIMS, UNROLL, true>), dim3((unsigned)blocks), dim3(256), 0,
+                           s, dbp, rec_u4, plane_u4, qp, n, inter);
     return hipGetLastError();
 }
 

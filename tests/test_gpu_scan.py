@@ -79,7 +79,7 @@ def test_small_config_full_parity():
     assert np.array_equal(_host(inter).view(np.uint32).astype(np.uint64), o_cnt[:, 0:2])
     assert list(_host(qcount)) == [int(o_cnt[0, 2]), int(o_cnt[0, 3])]
     assert np.array_equal(_host(db.popcounts)[:n].view(np.uint32).astype(np.uint64), o_cnt[:, 4:6])
-    for kk in (1, k, 333, n):
+    for kk in (1, k, 32, 33, 333, n):   # 32 / 33: the two selection paths
         say(f"small config: query k={kk}")
         idx, score, counts = db.query(qd, kk)
         db.sync()
