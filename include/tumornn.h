@@ -1,0 +1,114 @@
+/*
+ * tumornn.h — C ABI of the encoder kernels used for embedding search.
+ *
+ * The paper compresses each tumour with a convolutional autoencoder: strided
+ * 3-D convolutions (stride 2, kernel 3) down to a small grid, a linear layer
+ * to the latent, and a decoder of strided transposed convolutions mirroring
+ * it (Sec. 2.4 "Implementation"; Sec. 2.3 "Autoencoders"); database and
+ * query are compared by L2 distance of their latents (Sec. 2.3). The inputs
+ * here are the two masks mean-pooled by 2 in every axis (the paper's
+ * downsampling idea, Sec. 2.3 "Baseline for-loop search", DS64).
+ *
+ * Conventions:
+ *  - Tensors are dense, row-major, device memory: activations [B][C][D][H][W]
+ *    (W fastest), convolution weights [Co][Ci][3][3][3], linear weights
+ *    [Out][In], biases [Co]. Transposed-convolution weights are [Ci][Co][3][3][3]
+ *    (input channels first); see the duality notes below.
+ *  - dtype codes: NN_F32, NN_F64 for activations / gradients; weights may be
+ *    NN_BF16 (uint16 storage, bfloat16 bits) or NN_F32 with NN_F32
+ *    activations, and must be NN_F64 with NN_F64 activations (the FP64
+ *    build exists for finite-difference checks). Accumulation is in the
+ *    activation type.
+ *  - Return 0 on success, a negative DB_* code (tumordb.h) on bad arguments;
+ *    the message is in db_last_error(). Nothing is written on error.
+ *  - Calls are asynchronous on `stream` (hipStream_t as void*).
+ *
+ * Convolution, kernel 3, stride 2, padding 1, on even extents D, H, W:
+ *   Y[b,co,o] = bias[co] + sum_{ci,k} Wt[co,ci,k] X[b,ci,2o+k-1]   (o < D/2 per axis)
+ * Transposed convolution with output padding 1 (output 2x the input) is the
+ * adjoint of that map: its forward is nn_conv3d_s2_bwd_data (plus a bias),
+ * its input gradient is nn_conv3d_s2_fwd, and its weight gradient is
+ * nn_conv3d_s2_bwd_weight with the roles of X and dY exchanged.
+ */
+#ifndef TUMORNN_H
+#define TUMORNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "tumordb.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { NN_F32 = 0, NN_F64 = 1, NN_BF16 = 2 };
+
+/* 2x2x2 mean of the packed masks of database entries idx[0..B) (device
+ * int32): out [B][2][nz/2][ny/2][nx/2] (dtype), channel 0 FLAIR, 1 T1Gd;
+ * values are k/8 exactly. Needs even dims. */
+int nn_meanpool_db(const db_t *db, const int32_t *idx, int B, void *out, int dtype, void *stream);
+
+/* Same from query labels uint8 [B][nz][ny][nx] (bit 0 FLAIR, bit 1 T1Gd). */
+int nn_meanpool_labels(const uint8_t *labels, int B, int nx, int ny, int nz, void *out, int dtype,
+                       void *stream);
+
+/* Y = act(conv(X)) with X [B][Ci][D][H][W], Y [B][Co][D/2][H/2][W/2];
+ * bias [Co] or NULL; relu != 0 applies max(0, .). */
+int nn_conv3d_s2_fwd(int dtype, int B, int Ci, int Co, int D, int H, int W, const void *X,
+                     const void *Wt, int wdtype, const void *bias, int relu, void *Y,
+                     void *stream);
+
+/* dX = conv^T(dY) (the adjoint map; also the transposed-convolution forward):
+ * dY [B][Co][D/2][H/2][W/2] -> dX [B][Ci][D][H][W]; bias [Ci] or NULL is added
+ * and relu != 0 applied (used only as a transposed-convolution forward). */
+int nn_conv3d_s2_bwd_data(int dtype, int B, int Ci, int Co, int D, int H, int W, const void *dY,
+                          const void *Wt, int wdtype, const void *bias, int relu, void *dX,
+                          void *stream);
+
+/* dWt[co,ci,k] = sum_{b,o} dY[b,co,o] X[b,ci,2o+k-1] and dbias[co] = sum dY
+ * (dbias may be NULL). Deterministic two-stage reduction through ws. */
+size_t nn_conv3d_s2_bwd_weight_ws_bytes(int dtype, int B, int Ci, int Co, int D, int H, int W);
+int nn_conv3d_s2_bwd_weight(int dtype, int B, int Ci, int Co, int D, int H, int W, const void *X,
+                            const void *dY, void *dWt, void *dbias, void *ws, size_t ws_bytes,
+                            void *stream);
+
+/* Y[b,j] = act(bias[j] + sum_i Wt[j,i] X[b,i]); X [B][In], Wt [Out][In]. */
+int nn_linear_fwd(int dtype, int B, int In, int Out, const void *X, const void *Wt, int wdtype,
+                  const void *bias, int relu, void *Y, void *stream);
+/* dX[b,i] = sum_j Wt[j,i] dY[b,j]. */
+int nn_linear_bwd_data(int dtype, int B, int In, int Out, const void *dY, const void *Wt,
+                       int wdtype, void *dX, void *stream);
+/* dWt[j,i] = sum_b dY[b,j] X[b,i]; dbias[j] = sum_b dY[b,j] (or NULL). */
+int nn_linear_bwd_weight(int dtype, int B, int In, int Out, const void *X, const void *dY,
+                         void *dWt, void *dbias, void *stream);
+
+/* out[c] = sum_{b,s} X[b][c][s] for X [B][C][S] (a bias gradient; fixed order). */
+int nn_channel_sum(int dtype, int B, int C, int64_t S, const void *X, void *out, void *stream);
+
+/* dX = dY where Y > 0 else 0 (n elements). */
+int nn_relu_bwd(int dtype, int64_t n, const void *Y, const void *dY, void *dX, void *stream);
+
+/* loss[0] = mean((A - B)^2) over n elements (deterministic; ws of
+ * nn_mse_ws_bytes(n) bytes). */
+size_t nn_mse_ws_bytes(int dtype, int64_t n);
+int nn_mse_fwd(int dtype, int64_t n, const void *A, const void *B, void *loss, void *ws,
+               size_t ws_bytes, void *stream);
+/* dA = g[0] * 2 (A - B) / n, with g a device scalar (the upstream gradient). */
+int nn_mse_bwd(int dtype, int64_t n, const void *A, const void *B, const void *g, void *dA,
+               void *stream);
+
+/* Adam (Kingma & Ba) on FP32 master weights, then the BF16 copy (round to
+ * nearest even): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * w -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps); w_bf16 may be NULL. */
+int nn_adam_step(int64_t n, float *w, float *m, float *v, const float *g, uint16_t *w_bf16,
+                 float lr, float b1, float b2, float eps, int t, void *stream);
+
+/* FP32 -> BF16 bits, round to nearest even (NaN stays NaN). */
+int nn_to_bf16(int64_t n, const float *x, uint16_t *y, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TUMORNN_H */

@@ -11,7 +11,9 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtumordb.so")
 
-SOURCES = ["api.cpp", "pack.hip", "scan.hip", "select.hip", "batch.hip"]
+SOURCES = ["api.cpp", "pack.hip", "scan.hip", "select.hip", "batch.hip", "nn.hip"]
+# Sources with floating-point arithmetic that may be contracted into FMAs.
+CONTRACT_OK = {"nn.hip"}
 
 HIPCC = os.environ.get("HIPCC", "hipcc")
 COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall",
@@ -23,7 +25,8 @@ EXACT = ["-ffp-contract=off", "-fno-fast-math"]
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC, *COMMON, *EXACT, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    fp = ["-ffp-contract=fast"] if src in CONTRACT_OK else EXACT
+    cmd = [HIPCC, *COMMON, *fp, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

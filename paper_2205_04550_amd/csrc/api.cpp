@@ -37,6 +37,17 @@ bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 namespace tdb {
 
+int tdb_set_error(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+bool tdb_live(const db_t *db) { return live(db); }
+
 bool make_geometry(int nx, int ny, int nz, Geometry *g)
 {
     if (nx <= 0 || ny <= 0 || nz <= 0 || nx % 32 != 0)

@@ -26,6 +26,10 @@ struct Geometry {
 
 bool make_geometry(int nx, int ny, int nz, Geometry *g);
 
+// Error reporting shared by every C entry point (message read by db_last_error).
+int tdb_set_error(int code, const char *fmt, ...);
+bool tdb_live(const db_t *db);
+
 struct BatchGraph;  // cached HIP graph of a batched query (api.cpp)
 struct Profiler;    // HIP events around the dominant kernel (api.cpp)
 

@@ -1,0 +1,738 @@
+// nn.hip — encoder / decoder kernels for the embedding search (C ABI in include/tumornn.h).
+//
+// The paper's autoencoder (Sec. 2.4 "Implementation"): strided 3-D
+// convolutions (stride 2, kernel 3), a linear layer to the latent, and a
+// mirrored decoder of strided transposed convolutions; trained to reconstruct
+// its input. Channel counts here are tiny (2..64), so the layers are direct
+// convolutions on the vector ALUs: one thread per output (or input, for the
+// adjoint) voxel with block-uniform channel and batch indices, so weights
+// are read as scalars. Weight gradients reduce in two deterministic stages.
+// Every kernel is a template over the activation type T (float, or double
+// for finite-difference checks) and the weight storage type (bfloat16 bits,
+// float or double); accumulation is in T.
+#include <hip/hip_runtime.h>
+
+#include "../../include/tumornn.h"
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace tdb {
+
+__device__ __forceinline__ float ld_w(const uint16_t *p, int64_t i)
+{
+    return __uint_as_float((uint32_t)p[i] << 16);
+}
+__device__ __forceinline__ float ld_w(const float *p, int64_t i) { return p[i]; }
+__device__ __forceinline__ double ld_w(const double *p, int64_t i) { return p[i]; }
+
+template <class T>
+__device__ __forceinline__ T wsum(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---- convolution, kernel 3, stride 2, padding 1 ------------------------------------------
+
+// grid (ceil(OD*OH*OW / 256), Co, B)
+template <class T, class WT>
+__global__ void __launch_bounds__(256) conv_fwd_kernel(int Ci, int Co, int D, int H, int W,
+                                                       const T *__restrict__ X,
+                                                       const WT *__restrict__ Wt,
+                                                       const T *__restrict__ bias, int relu,
+                                                       T *__restrict__ Y)
+{
+    const int OD = D / 2, OH = H / 2, OW = W / 2;
+    const int osp = OD * OH * OW;
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    const int co = blockIdx.y, b = blockIdx.z;
+    if (o >= osp) return;
+    const int ow = o % OW, oh = (o / OW) % OH, od = o / (OW * OH);
+    const int64_t isp = (int64_t)D * H * W;
+    T acc = bias ? bias[co] : T(0);
+    for (int ci = 0; ci < Ci; ++ci) {
+        const T *x = X + ((int64_t)b * Ci + ci) * isp;
+        const WT *w = Wt + ((int64_t)co * Ci + ci) * 27;
+#pragma unroll
+        for (int kd = 0; kd < 3; ++kd) {
+            const int id = 2 * od + kd - 1;
+            if (id < 0 || id >= D) continue;
+#pragma unroll
+            for (int kh = 0; kh < 3; ++kh) {
+                const int ih = 2 * oh + kh - 1;
+                if (ih < 0 || ih >= H) continue;
+#pragma unroll
+                for (int kw = 0; kw < 3; ++kw) {
+                    const int iw = 2 * ow + kw - 1;
+                    if (iw < 0 || iw >= W) continue;
+                    acc += (T)ld_w(w, kd * 9 + kh * 3 + kw) * x[((int64_t)id * H + ih) * W + iw];
+                }
+            }
+        }
+    }
+    if (relu && acc < T(0)) acc = T(0);
+    Y[((int64_t)b * Co + co) * osp + o] = acc;
+}
+
+// Adjoint map: grid (ceil(D*H*W / 256), Ci, B); one thread per input voxel.
+template <class T, class WT>
+__global__ void __launch_bounds__(256) conv_bwd_data_kernel(int Ci, int Co, int D, int H, int W,
+                                                            const T *__restrict__ dY,
+                                                            const WT *__restrict__ Wt,
+                                                            const T *__restrict__ bias, int relu,
+                                                            T *__restrict__ dX)
+{
+    const int OD = D / 2, OH = H / 2, OW = W / 2;
+    const int osp = OD * OH * OW;
+    const int isp = D * H * W;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ci = blockIdx.y, b = blockIdx.z;
+    if (i >= isp) return;
+    const int iw = i % W, ih = (i / W) % H, id = i / (W * H);
+    T acc = bias ? bias[ci] : T(0);
+    for (int co = 0; co < Co; ++co) {
+        const T *dy = dY + ((int64_t)b * Co + co) * osp;
+        const WT *w = Wt + ((int64_t)co * Ci + ci) * 27;
+#pragma unroll
+        for (int kd = 0; kd < 3; ++kd) {
+            const int td = id + 1 - kd;
+            if (td < 0 || (td & 1) || (td >> 1) >= OD) continue;
+#pragma unroll
+            for (int kh = 0; kh < 3; ++kh) {
+                const int th = ih + 1 - kh;
+                if (th < 0 || (th & 1) || (th >> 1) >= OH) continue;
+#pragma unroll
+                for (int kw = 0; kw < 3; ++kw) {
+                    const int tw = iw + 1 - kw;
+                    if (tw < 0 || (tw & 1) || (tw >> 1) >= OW) continue;
+                    acc += (T)ld_w(w, kd * 9 + kh * 3 + kw) *
+                           dy[((td >> 1) * OH + (th >> 1)) * OW + (tw >> 1)];
+                }
+            }
+        }
+    }
+    if (relu && acc < T(0)) acc = T(0);
+    dX[((int64_t)b * Ci + ci) * isp + i] = acc;
+}
+
+constexpr int kWgChunk = 4096;  // (batch, output voxel) positions per weight-gradient block
+
+// Stage 1: grid (chunks, Ci, Co). partial [chunks][Co][Ci][28]: 27 taps + sum of dY.
+template <class T>
+__global__ void __launch_bounds__(256) conv_bwd_weight_partial(int B, int Ci, int Co, int D, int H,
+                                                               int W, const T *__restrict__ X,
+                                                               const T *__restrict__ dY,
+                                                               T *__restrict__ partial)
+{
+    __shared__ T red[4][28];
+    const int OD = D / 2, OH = H / 2, OW = W / 2;
+    const int osp = OD * OH * OW;
+    const int64_t isp = (int64_t)D * H * W;
+    const int co = blockIdx.z, ci = blockIdx.y;
+    const int64_t P = (int64_t)B * osp;
+    const int64_t p0 = (int64_t)blockIdx.x * kWgChunk;
+    const int64_t p1 = p0 + kWgChunk < P ? p0 + kWgChunk : P;
+    T acc[28];
+#pragma unroll
+    for (int k = 0; k < 28; ++k) acc[k] = T(0);
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const int b = (int)(p / osp);
+        const int o = (int)(p - (int64_t)b * osp);
+        const int ow = o % OW, oh = (o / OW) % OH, od = o / (OW * OH);
+        const T g = dY[((int64_t)b * Co + co) * osp + o];
+        const T *x = X + ((int64_t)b * Ci + ci) * isp;
+#pragma unroll
+        for (int kd = 0; kd < 3; ++kd) {
+            const int id = 2 * od + kd - 1;
+#pragma unroll
+            for (int kh = 0; kh < 3; ++kh) {
+                const int ih = 2 * oh + kh - 1;
+#pragma unroll
+                for (int kw = 0; kw < 3; ++kw) {
+                    const int iw = 2 * ow + kw - 1;
+                    const bool in = id >= 0 && id < D && ih >= 0 && ih < H && iw >= 0 && iw < W;
+                    // Out-of-range taps read element 0 (always valid) and count as zero.
+                    const int64_t off = in ? ((int64_t)id * H + ih) * W + iw : 0;
+                    const T xv = in ? x[off] : T(0);
+                    acc[kd * 9 + kh * 3 + kw] += g * xv;
+                }
+            }
+        }
+        acc[27] += g;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 28; ++k) {
+        const T s = wsum(acc[k]);
+        if (lane == 0) red[wave][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < 28) {
+        const int k = threadIdx.x;
+        const T s = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+        partial[(((int64_t)blockIdx.x * Co + co) * Ci + ci) * 28 + k] = s;
+    }
+}
+
+// Stage 2: one thread per (co, ci, tap) sums the chunks in order.
+template <class T>
+__global__ void conv_bwd_weight_final(int nchunks, int Ci, int Co, const T *__restrict__ partial,
+                                      T *__restrict__ dW, T *__restrict__ dbias)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Co * Ci * 28) return;
+    const int k = t % 28;
+    const int cc = t / 28;  // co * Ci + ci
+    T s = T(0);
+    for (int c = 0; c < nchunks; ++c)
+        s += partial[((int64_t)c * Co * Ci + cc) * 28 + k];
+    if (k < 27)
+        dW[(int64_t)cc * 27 + k] = s;
+    else if (dbias && (cc % Ci) == 0)
+        dbias[cc / Ci] = s;
+}
+
+// ---- linear ---------------------------------------------------------------------------------
+
+template <class T, class WT>
+__global__ void __launch_bounds__(256) linear_fwd_kernel(int B, int In, int Out,
+                                                         const T *__restrict__ X,
+                                                         const WT *__restrict__ Wt,
+                                                         const T *__restrict__ bias, int relu,
+                                                         T *__restrict__ Y)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (j >= Out) return;
+    const T *x = X + (int64_t)b * In;
+    const WT *w = Wt + (int64_t)j * In;
+    T acc = bias ? bias[j] : T(0);
+    for (int i = 0; i < In; ++i) acc += (T)ld_w(w, i) * x[i];
+    if (relu && acc < T(0)) acc = T(0);
+    Y[(int64_t)b * Out + j] = acc;
+}
+
+template <class T, class WT>
+__global__ void __launch_bounds__(256) linear_bwd_data_kernel(int B, int In, int Out,
+                                                              const T *__restrict__ dY,
+                                                              const WT *__restrict__ Wt,
+                                                              T *__restrict__ dX)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = blockIdx.y;
+    if (i >= In) return;
+    const T *dy = dY + (int64_t)b * Out;
+    T acc = T(0);
+    for (int j = 0; j < Out; ++j) acc += (T)ld_w(Wt, (int64_t)j * In + i) * dy[j];
+    dX[(int64_t)b * In + i] = acc;
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) linear_bwd_weight_kernel(int B, int In, int Out,
+                                                                const T *__restrict__ X,
+                                                                const T *__restrict__ dY,
+                                                                T *__restrict__ dW,
+                                                                T *__restrict__ dbias)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= In) return;
+    T acc = T(0);
+    for (int b = 0; b < B; ++b) acc += dY[(int64_t)b * Out + j] * X[(int64_t)b * In + i];
+    dW[(int64_t)j * In + i] = acc;
+    if (dbias && i == 0) {
+        T s = T(0);
+        for (int b = 0; b < B; ++b) s += dY[(int64_t)b * Out + j];
+        dbias[j] = s;
+    }
+}
+
+// out[c] = sum over (b, s) of X[b][c][s]: one block per channel, fixed reduction order.
+template <class T>
+__global__ void __launch_bounds__(256) channel_sum_kernel(int B, int C, int64_t S,
+                                                          const T *__restrict__ X,
+                                                          T *__restrict__ out)
+{
+    __shared__ T red[4];
+    const int c = blockIdx.x;
+    T acc = T(0);
+    for (int b = 0; b < B; ++b) {
+        const T *x = X + ((int64_t)b * C + c) * S;
+        for (int64_t i = threadIdx.x; i < S; i += blockDim.x) acc += x[i];
+    }
+    acc = wsum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[c] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// ---- elementwise, loss, optimiser ---------------------------------------------------------
+
+template <class T>
+__global__ void relu_bwd_kernel(int64_t n, const T *__restrict__ Y, const T *__restrict__ dY,
+                                T *__restrict__ dX)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dX[i] = Y[i] > T(0) ? dY[i] : T(0);
+}
+
+constexpr int kMseBlocks = 512;
+
+template <class T>
+__global__ void __launch_bounds__(256) mse_partial_kernel(int64_t n, const T *__restrict__ A,
+                                                          const T *__restrict__ B,
+                                                          T *__restrict__ partial)
+{
+    __shared__ T red[4];
+    T acc = T(0);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const T d = A[i] - B[i];
+        acc += d * d;
+    }
+    acc = wsum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+template <class T>
+__global__ void mse_final_kernel(int nb, int64_t n, const T *__restrict__ partial,
+                                 T *__restrict__ loss)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        T s = T(0);
+        for (int i = 0; i < nb; ++i) s += partial[i];
+        loss[0] = s / (T)n;
+    }
+}
+
+template <class T>
+__global__ void mse_bwd_kernel(int64_t n, const T *__restrict__ A, const T *__restrict__ B,
+                               const T *__restrict__ g, T *__restrict__ dA)
+{
+    const T scale = g[0] * T(2) / (T)n;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dA[i] = scale * (A[i] - B[i]);
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
+        return (uint16_t)((u >> 16) | 0x0040u);  // quiet NaN
+    const uint32_t bias = 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)((u + bias) >> 16);
+}
+
+__global__ void adam_kernel(int64_t n, float *__restrict__ w, float *__restrict__ m,
+                            float *__restrict__ v, const float *__restrict__ g,
+                            uint16_t *__restrict__ wb, float lr, float b1, float b2, float eps,
+                            float c1, float c2)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        w[i] = wi;
+        if (wb) wb[i] = f32_to_bf16_rne(wi);
+    }
+}
+
+__global__ void to_bf16_kernel(int64_t n, const float *__restrict__ x, uint16_t *__restrict__ y)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = f32_to_bf16_rne(x[i]);
+}
+
+// ---- mean-pooling of the masks ------------------------------------------------------------
+
+// out [B][2][nz/2][ny/2][nx/2] = (number of set voxels in the 2x2x2 block) / 8.
+template <class T>
+__global__ void meanpool_db_kernel(const uint32_t *__restrict__ planes, int Wp, int nxw, int ny,
+                                   int nz, int nx, const int32_t *__restrict__ idx, int B,
+                                   T *__restrict__ out)
+{
+    const int X = nx / 2, Y = ny / 2, Z = nz / 2;
+    const int64_t per = (int64_t)2 * Z * Y * X;
+    const int64_t total = per * B;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(t / per);
+        int64_t r = t - (int64_t)b * per;
+        const int x = (int)(r % X);
+        r /= X;
+        const int y = (int)(r % Y);
+        r /= Y;
+        const int z = (int)(r % Z);
+        const int m = (int)(r / Z);
+        const uint32_t *pl = planes + (int64_t)idx[b] * 2 * Wp + (int64_t)m * Wp;
+        const int wx = (2 * x) >> 5, bit = (2 * x) & 31;
+        int c = 0;
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy) {
+                const uint32_t wv = pl[((int64_t)(2 * z + dz) * ny + (2 * y + dy)) * nxw + wx];
+                c += __builtin_popcount((wv >> bit) & 3u);
+            }
+        out[t] = (T)c * T(0.125);
+    }
+}
+
+template <class T>
+__global__ void meanpool_labels_kernel(const uint8_t *__restrict__ lab, int B, int nx, int ny,
+                                       int nz, T *__restrict__ out)
+{
+    const int X = nx / 2, Y = ny / 2, Z = nz / 2;
+    const int64_t per = (int64_t)2 * Z * Y * X;
+    const int64_t total = per * B;
+    const int64_t V = (int64_t)nx * ny * nz;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(t / per);
+        int64_t r = t - (int64_t)b * per;
+        const int x = (int)(r % X);
+        r /= X;
+        const int y = (int)(r % Y);
+        r /= Y;
+        const int z = (int)(r % Z);
+        const int m = (int)(r / Z);
+        const uint8_t *l = lab + (int64_t)b * V;
+        int c = 0;
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 2; ++dx)
+                    c += (l[((int64_t)(2 * z + dz) * ny + (2 * y + dy)) * nx + 2 * x + dx] >> m) & 1;
+        out[t] = (T)c * T(0.125);
+    }
+}
+
+}  // namespace tdb
+
+// ---- C ABI ----------------------------------------------------------------------------------
+
+using namespace tdb;
+
+namespace {
+
+unsigned grid1(int64_t n, int64_t cap = 4096)
+{
+    int64_t g = (n + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+bool conv_dims_ok(int B, int Ci, int Co, int D, int H, int W)
+{
+    return B > 0 && Ci > 0 && Co > 0 && D >= 2 && H >= 2 && W >= 2 && !(D & 1) && !(H & 1) &&
+           !(W & 1) && B <= 65535 && Ci <= 65535 && Co <= 65535 &&
+           (int64_t)D * H * W < ((int64_t)1 << 31);
+}
+
+int dtype_pair(int dtype, int wdtype)
+{
+    if (dtype == NN_F32 && wdtype == NN_BF16) return 0;
+    if (dtype == NN_F32 && wdtype == NN_F32) return 1;
+    if (dtype == NN_F64 && wdtype == NN_F64) return 2;
+    return -1;
+}
+
+int launched(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return tdb_set_error(DB_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return DB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nn_meanpool_db(const db_t *db, const int32_t *idx, int B, void *out, int dtype, void *stream)
+{
+    if (!tdb_live(db)) return tdb_set_error(DB_ESTATE, "nn_meanpool_db: invalid handle");
+    const Geometry &g = db->g;
+    if (!idx || !out || B <= 0 || (g.nx & 1) || (g.ny & 1) || (g.nz & 1) ||
+        (dtype != NN_F32 && dtype != NN_F64))
+        return tdb_set_error(DB_EINVAL, "nn_meanpool_db: bad arguments");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t total = (int64_t)B * 2 * (g.nz / 2) * (g.ny / 2) * (g.nx / 2);
+    if (dtype == NN_F32)
+        hipLaunchKernelGGL(meanpool_db_kernel<float>, dim3(grid1(total)), dim3(256), 0, s,
+                           db->planes, g.Wp, g.nxw, g.ny, g.nz, g.nx, idx, B, (float *)out);
+    else
+        hipLaunchKernelGGL(meanpool_db_kernel<double>, dim3(grid1(total)), dim3(256), 0, s,
+                           db->planes, g.Wp, g.nxw, g.ny, g.nz, g.nx, idx, B, (double *)out);
+    return launched("nn_meanpool_db");
+}
+
+int nn_meanpool_labels(const uint8_t *labels, int B, int nx, int ny, int nz, void *out, int dtype,
+                       void *stream)
+{
+    if (!labels || !out || B <= 0 || nx <= 0 || ny <= 0 || nz <= 0 || (nx & 1) || (ny & 1) ||
+        (nz & 1) || (dtype != NN_F32 && dtype != NN_F64))
+        return tdb_set_error(DB_EINVAL, "nn_meanpool_labels: bad arguments");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t total = (int64_t)B * 2 * (nz / 2) * (ny / 2) * (nx / 2);
+    if (dtype == NN_F32)
+        hipLaunchKernelGGL(meanpool_labels_kernel<float>, dim3(grid1(total)), dim3(256), 0, s,
+                           labels, B, nx, ny, nz, (float *)out);
+    else
+        hipLaunchKernelGGL(meanpool_labels_kernel<double>, dim3(grid1(total)), dim3(256), 0, s,
+                           labels, B, nx, ny, nz, (double *)out);
+    return launched("nn_meanpool_labels");
+}
+
+int nn_conv3d_s2_fwd(int dtype, int B, int Ci, int Co, int D, int H, int W, const void *X,
+                     const void *Wt, int wdtype, const void *bias, int relu, void *Y, void *stream)
+{
+    const int pair = dtype_pair(dtype, wdtype);
+    if (pair < 0 || !conv_dims_ok(B, Ci, Co, D, H, W) || !X || !Wt || !Y)
+        return tdb_set_error(DB_EINVAL, "nn_conv3d_s2_fwd: bad arguments");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int osp = (D / 2) * (H / 2) * (W / 2);
+    const dim3 grid((osp + 255) / 256, Co, B);
+    if (pair == 0)
+        hipLaunchKernelGGL((conv_fwd_kernel<float, uint16_t>), grid, dim3(256), 0, s, Ci, Co, D, H,
+                           W, (const float *)X, (const uint16_t *)Wt, (const float *)bias, relu,
+                           (float *)Y);
+    else if (pair == 1)
+        hipLaunchKernelGGL((conv_fwd_kernel<float, float>), grid, dim3(256), 0, s, Ci, Co, D, H, W,
+                           (const float *)X, (const float *)Wt, (const float *)bias, relu,
+                           (float *)Y);
+    else
+        hipLaunchKernelGGL((conv_fwd_kernel<double, double>), grid, dim3(256), 0, s, Ci, Co, D, H,
+                           W, (const double *)X, (const double *)Wt, (const double *)bias, relu,
+                           (double *)Y);
+    return launched("nn_conv3d_s2_fwd");
+}
+
+int nn_conv3d_s2_bwd_data(int dtype, int B, int Ci, int Co, int D, int H, int W, const void *dY,
+                          const void *Wt, int wdtype, const void *bias, int relu, void *dX,
+                          void *stream)
+{
+    const int pair = dtype_pair(dtype, wdtype);
+    if (pair < 0 || !conv_dims_ok(B, Ci, Co, D, H, W) || !dY || !Wt || !dX)
+        return tdb_set_error(DB_EINVAL, "nn_conv3d_s2_bwd_data: bad arguments");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int isp = D * H * W;
+    const dim3 grid((isp + 255) / 256, Ci, B);
+    if (pair == 0)
+        hipLaunchKernelGGL((conv_bwd_data_kernel<float, uint16_t>), grid, dim3(256), 0, s, Ci, Co,
+                           D, H, W, (const float *)dY, (const uint16_t *)Wt, (const float *)bias,
+                           relu, (float *)dX);
+    else if (pair == 1)
+        hipLaunchKernelGGL((conv_bwd_data_kernel<float, float>), grid, dim3(256), 0, s, Ci, Co, D,
+                           H, W, (const float *)dY, (const float *)Wt, (const float *)bias, relu,
+                           (float *)dX);
+    else
+        hipLaunchKernelGGL((conv_bwd_data_kernel<double, double>), grid, dim3(256), 0, s, Ci, Co,
+                           D, H, W, (const double *)dY, (const double *)Wt, (const double *)bias,
+                           relu, (double *)dX);
+    return launched("nn_conv3d_s2_bwd_data");
+}
+
+size_t nn_conv3d_s2_bwd_weight_ws_bytes(int dtype, int B, int Ci, int Co, int D, int H, int W)
+{
+    if ((dtype != NN_F32 && dtype != NN_F64) || !conv_dims_ok(B, Ci, Co, D, H, W)) return 0;
+    const int64_t P = (int64_t)B * (D / 2) * (H / 2) * (W / 2);
+    const int64_t chunks = (P + kWgChunk - 1) / kWgChunk;
+    return (size_t)chunks * Co * Ci * 28 * (dtype == NN_F32 ? 4 : 8);
+}
+
+int nn_conv3d_s2_bwd_weight(int dtype, int B, int Ci, int Co, int D, int H, int W, const void *X,
+                            const void *dY, void *dWt, void *dbias, void *ws, size_t ws_bytes,
+                            void *stream)
+{
+    const size_t need = nn_conv3d_s2_bwd_weight_ws_bytes(dtype, B, Ci, Co, D, H, W);
+    if (need == 0 || !X || !dY || !dWt || !ws)
+        return tdb_set_error(DB_EINVAL, "nn_conv3d_s2_bwd_weight: bad arguments");
+    if (ws_bytes < need)
+        return tdb_set_error(DB_ENOSPC, "nn_conv3d_s2_bwd_weight: workspace %zu < %zu", ws_bytes,
+                             need);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t P = (int64_t)B * (D / 2) * (H / 2) * (W / 2);
+    const int chunks = (int)((P + kWgChunk - 1) / kWgChunk);
+    const dim3 g1(chunks, Ci, Co);
+    const unsigned g2 = (unsigned)((Co * Ci * 28 + 255) / 256);
+    if (dtype == NN_F32) {
+        hipLaunchKernelGGL(conv_bwd_weight_partial<float>, g1, dim3(256), 0, s, B, Ci, Co, D, H, W,
+                           (const float *)X, (const float *)dY, (float *)ws);
+        hipLaunchKernelGGL(conv_bwd_weight_final<float>, dim3(g2), dim3(256), 0, s, chunks, Ci, Co,
+                           (const float *)ws, (float *)dWt, (float *)dbias);
+    } else {
+        hipLaunchKernelGGL(conv_bwd_weight_partial<double>, g1, dim3(256), 0, s, B, Ci, Co, D, H,
+                           W, (const double *)X, (const double *)dY, (double *)ws);
+        hipLaunchKernelGGL(conv_bwd_weight_final<double>, dim3(g2), dim3(256), 0, s, chunks, Ci,
+                           Co, (const double *)ws, (double *)dWt, (double *)dbias);
+    }
+    return launched("nn_conv3d_s2_bwd_weight");
+}
+
+int nn_linear_fwd(int dtype, int B, int In, int Out, const void *X, const void *Wt, int wdtype,
+                  const void *bias, int relu, void *Y, void *stream)
+{
+    const int pair = dtype_pair(dtype, wdtype);
+    if (pair < 0 || B <= 0 || In <= 0 || Out <= 0 || B > 65535 || !X || !Wt || !Y)
+        return tdb_set_error(DB_EINVAL, "nn_linear_fwd: bad arguments");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const dim3 grid((Out + 255) / 256, B);
+    if (pair == 0)
+        hipLaunchKernelGGL((linear_fwd_kernel<float, uint16_t>), grid, dim3(256), 0, s, B, In, Out,
+                           (const float *)X, (const uint16_t *)Wt, (const float *)bias, relu,
+                           (float *)Y);
+    else if (pair == 1)
+        hipLaunchKernelGGL((linear_fwd_kernel<float, float>), grid, dim3(256), 0, s, B, In, Out,
+                           (const float *)X, (const float *)Wt, (const float *)bias, relu,
+                           (float *)Y);
+    else
+        hipLaunchKernelGGL((linear_fwd_kernel<double, double>), grid, dim3(256), 0, s, B, In, Out,
+                           (const double *)X, (const double *)Wt, (const double *)bias, relu,
+                           (double *)Y);
+    return launched("nn_linear_fwd");
+}
+
+int nn_linear_bwd_data(int dtype, int B, int In, int Out, const void *dY, const void *Wt,
+                       int wdtype, void *dX, void *stream)
+{
+    const int pair = dtype_pair(dtype, wdtype);
+    if (pair < 0 || B <= 0 || In <= 0 || Out <= 0 || B > 65535 || !dY || !Wt || !dX)
+        return tdb_set_error(DB_EINVAL, "nn_linear_bwd_data: bad arguments");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const dim3 grid((In + 255) / 256, B);
+    if (pair == 0)
+        hipLaunchKernelGGL((linear_bwd_data_kernel<float, uint16_t>), grid, dim3(256), 0, s, B, In,
+                           Out, (const float *)dY, (const uint16_t *)Wt, (float *)dX);
+    else if (pair == 1)
+        hipLaunchKernelGGL((linear_bwd_data_kernel<float, float>), grid, dim3(256), 0, s, B, In,
+                           Out, (const float *)dY, (const float *)Wt, (float *)dX);
+    else
+        hipLaunchKernelGGL((linear_bwd_data_kernel<double, double>), grid, dim3(256), 0, s, B, In,
+                           Out, (const double *)dY, (const double *)Wt, (double *)dX);
+    return launched("nn_linear_bwd_data");
+}
+
+int nn_linear_bwd_weight(int dtype, int B, int In, int Out, const void *X, const void *dY,
+                         void *dWt, void *dbias, void *stream)
+{
+    if ((dtype != NN_F32 && dtype != NN_F64) || B <= 0 || In <= 0 || Out <= 0 || Out > 65535 ||
+        !X || !dY || !dWt)
+        return tdb_set_error(DB_EINVAL, "nn_linear_bwd_weight: bad arguments");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const dim3 grid((In + 255) / 256, Out);
+    if (dtype == NN_F32)
+        hipLaunchKernelGGL(linear_bwd_weight_kernel<float>, grid, dim3(256), 0, s, B, In, Out,
+                           (const float *)X, (const float *)dY, (float *)dWt, (float *)dbias);
+    else
+        hipLaunchKernelGGL(linear_bwd_weight_kernel<double>, grid, dim3(256), 0, s, B, In, Out,
+                           (const double *)X, (const double *)dY, (double *)dWt, (double *)dbias);
+    return launched("nn_linear_bwd_weight");
+}
+
+int nn_channel_sum(int dtype, int B, int C, int64_t S, const void *X, void *out, void *stream)
+{
+    if ((dtype != NN_F32 && dtype != NN_F64) || B <= 0 || C <= 0 || S <= 0 || !X || !out)
+        return tdb_set_error(DB_EINVAL, "nn_channel_sum: bad arguments");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype == NN_F32)
+        hipLaunchKernelGGL(channel_sum_kernel<float>, dim3(C), dim3(256), 0, s, B, C, S,
+                           (const float *)X, (float *)out);
+    else
+        hipLaunchKernelGGL(channel_sum_kernel<double>, dim3(C), dim3(256), 0, s, B, C, S,
+                           (const double *)X, (double *)out);
+    return launched("nn_channel_sum");
+}
+
+int nn_relu_bwd(int dtype, int64_t n, const void *Y, const void *dY, void *dX, void *stream)
+{
+    if ((dtype != NN_F32 && dtype != NN_F64) || n <= 0 || !Y || !dY || !dX)
+        return tdb_set_error(DB_EINVAL, "nn_relu_bwd: bad arguments");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype == NN_F32)
+        hipLaunchKernelGGL(relu_bwd_kernel<float>, dim3(grid1(n)), dim3(256), 0, s, n,
+                           (const float *)Y, (const float *)dY, (float *)dX);
+    else
+        hipLaunchKernelGGL(relu_bwd_kernel<double>, dim3(grid1(n)), dim3(256), 0, s, n,
+                           (const double *)Y, (const double *)dY, (double *)dX);
+    return launched("nn_relu_bwd");
+}
+
+size_t nn_mse_ws_bytes(int dtype, int64_t n)
+{
+    if ((dtype != NN_F32 && dtype != NN_F64) || n <= 0) return 0;
+    return (size_t)kMseBlocks * (dtype == NN_F32 ? 4 : 8);
+}
+
+int nn_mse_fwd(int dtype, int64_t n, const void *A, const void *B, void *loss, void *ws,
+               size_t ws_bytes, void *stream)
+{
+    const size_t need = nn_mse_ws_bytes(dtype, n);
+    if (need == 0 || !A || !B || !loss || !ws)
+        return tdb_set_error(DB_EINVAL, "nn_mse_fwd: bad arguments");
+    if (ws_bytes < need) return tdb_set_error(DB_ENOSPC, "nn_mse_fwd: workspace too small");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype == NN_F32) {
+        hipLaunchKernelGGL(mse_partial_kernel<float>, dim3(kMseBlocks), dim3(256), 0, s, n,
+                           (const float *)A, (const float *)B, (float *)ws);
+        hipLaunchKernelGGL(mse_final_kernel<float>, dim3(1), dim3(64), 0, s, kMseBlocks, n,
+                           (const float *)ws, (float *)loss);
+    } else {
+        hipLaunchKernelGGL(mse_partial_kernel<double>, dim3(kMseBlocks), dim3(256), 0, s, n,
+                           (const double *)A, (const double *)B, (double *)ws);
+        hipLaunchKernelGGL(mse_final_kernel<double>, dim3(1), dim3(64), 0, s, kMseBlocks, n,
+                           (const double *)ws, (double *)loss);
+    }
+    return launched("nn_mse_fwd");
+}
+
+int nn_mse_bwd(int dtype, int64_t n, const void *A, const void *B, const void *g, void *dA,
+               void *stream)
+{
+    if ((dtype != NN_F32 && dtype != NN_F64) || n <= 0 || !A || !B || !g || !dA)
+        return tdb_set_error(DB_EINVAL, "nn_mse_bwd: bad arguments");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (dtype == NN_F32)
+        hipLaunchKernelGGL(mse_bwd_kernel<float>, dim3(grid1(n)), dim3(256), 0, s, n,
+                           (const float *)A, (const float *)B, (const float *)g, (float *)dA);
+    else
+        hipLaunchKernelGGL(mse_bwd_kernel<double>, dim3(grid1(n)), dim3(256), 0, s, n,
+                           (const double *)A, (const double *)B, (const double *)g, (double *)dA);
+    return launched("nn_mse_bwd");
+}
+
+int nn_adam_step(int64_t n, float *w, float *m, float *v, const float *g, uint16_t *w_bf16,
+                 float lr, float b1, float b2, float eps, int t, void *stream)
+{
+    if (n <= 0 || !w || !m || !v || !g || t < 1 || !(b1 >= 0.f && b1 < 1.f) ||
+        !(b2 >= 0.f && b2 < 1.f))
+        return tdb_set_error(DB_EINVAL, "nn_adam_step: bad arguments");
+    const float c1 = 1.0f - powf(b1, (float)t);
+    const float c2 = 1.0f - powf(b2, (float)t);
+    hipLaunchKernelGGL(adam_kernel, dim3(grid1(n)), dim3(256), 0, static_cast<hipStream_t>(stream),
+                       n, w, m, v, g, w_bf16, lr, b1, b2, eps, c1, c2);
+    return launched("nn_adam_step");
+}
+
+int nn_to_bf16(int64_t n, const float *x, uint16_t *y, void *stream)
+{
+    if (n <= 0 || !x || !y) return tdb_set_error(DB_EINVAL, "nn_to_bf16: bad arguments");
+    hipLaunchKernelGGL(to_bf16_kernel, dim3(grid1(n)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), n, x, y);
+    return launched("nn_to_bf16");
+}
+
+}  // extern "C"

@@ -1,0 +1,374 @@
+"""Convolutional autoencoder on the hand-written HIP kernels of include/tumornn.h.
+
+The paper compresses each tumour with an autoencoder (Sec. 2.3
+"Autoencoders", Sec. 2.4 "Implementation"): strided 3-D convolutions
+(stride 2, kernel 3) down to a small grid, flatten, a linear layer to the
+latent; the decoder mirrors it with strided transposed convolutions; trained
+on reconstruction. Here the input is the two masks mean-pooled to half
+resolution, the encoder has four stride-2 convolutions (2 -> 8 -> 16 -> 32 ->
+64 channels, ReLU) and a linear layer to a 512-d latent; the decoder is a
+linear layer (ReLU) and four stride-2 transposed convolutions (ReLU except the
+last). Loss: mean squared reconstruction error; optimiser: Adam on FP32
+master weights with BF16 working copies of the weights.
+
+Every forward and backward step runs in libtumordb.so; torch only provides
+memory, streams and the autograd bookkeeping (torch.autograd.Function).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import torch
+
+from .binding import LIB, _check
+
+NN_F32, NN_F64, NN_BF16 = 0, 1, 2
+
+_vp, _i32, _i64, _sz, _f32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_size_t, ctypes.c_float
+_SIGS = {
+    "nn_meanpool_db": (_i32, [_vp, _vp, _i32, _vp, _i32, _vp]),
+    "nn_meanpool_labels": (_i32, [_vp, _i32, _i32, _i32, _i32, _vp, _i32, _vp]),
+    "nn_conv3d_s2_fwd": (_i32, [_i32] + [_i32] * 6 + [_vp, _vp, _i32, _vp, _i32, _vp, _vp]),
+    "nn_conv3d_s2_bwd_data": (_i32, [_i32] + [_i32] * 6 + [_vp, _vp, _i32, _vp, _i32, _vp, _vp]),
+    "nn_conv3d_s2_bwd_weight_ws_bytes": (_sz, [_i32] * 7),
+    "nn_conv3d_s2_bwd_weight": (_i32, [_i32] * 7 + [_vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "nn_linear_fwd": (_i32, [_i32] * 4 + [_vp, _vp, _i32, _vp, _i32, _vp, _vp]),
+    "nn_linear_bwd_data": (_i32, [_i32] * 4 + [_vp, _vp, _i32, _vp, _vp]),
+    "nn_linear_bwd_weight": (_i32, [_i32] * 4 + [_vp, _vp, _vp, _vp, _vp]),
+    "nn_channel_sum": (_i32, [_i32, _i32, _i32, _i64, _vp, _vp, _vp]),
+    "nn_relu_bwd": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp]),
+    "nn_mse_ws_bytes": (_sz, [_i32, _i64]),
+    "nn_mse_fwd": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "nn_mse_bwd": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp, _vp]),
+    "nn_adam_step": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _f32, _f32, _f32, _f32, _i32, _vp]),
+    "nn_to_bf16": (_i32, [_i64, _vp, _vp, _vp]),
+}
+for _n, (_r, _a) in _SIGS.items():
+    _f = getattr(LIB, _n)
+    _f.restype = _r
+    _f.argtypes = _a
+NN_SYMBOLS = tuple(_SIGS)
+
+
+def _s() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dt(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return NN_F32
+    if t.dtype == torch.float64:
+        return NN_F64
+    raise TypeError(f"activations must be float32 or float64, got {t.dtype}")
+
+
+def _wdt(w: torch.Tensor) -> int:
+    return {torch.bfloat16: NN_BF16, torch.float32: NN_F32, torch.float64: NN_F64}[w.dtype]
+
+
+def _p(t):
+    return None if t is None else t.data_ptr()
+
+
+def _c(t):
+    return t if t.is_contiguous() else t.contiguous()
+
+
+# ---- pooling ------------------------------------------------------------------------------
+
+def meanpool_db(db, idx: torch.Tensor, dtype=torch.float32) -> torch.Tensor:
+    """2x2x2 mean of the masks of database entries idx (int32, device): [B][2][nz/2][ny/2][nx/2]."""
+    nx, ny, nz = db.dims
+    idx = _c(idx.to(torch.int32))
+    B = idx.numel()
+    out = torch.empty((B, 2, nz // 2, ny // 2, nx // 2), dtype=dtype, device=idx.device)
+    _check(LIB.nn_meanpool_db(db._h, idx.data_ptr(), B, out.data_ptr(), _dt(out), _s()))
+    return out
+
+
+def meanpool_labels(labels: torch.Tensor, dtype=torch.float32) -> torch.Tensor:
+    """2x2x2 mean of query labels uint8 [B][nz][ny][nx] (bit0 FLAIR, bit1 T1Gd)."""
+    labels = _c(labels)
+    if labels.dim() == 3:
+        labels = labels[None]
+    B, nz, ny, nx = labels.shape
+    out = torch.empty((B, 2, nz // 2, ny // 2, nx // 2), dtype=dtype, device=labels.device)
+    _check(LIB.nn_meanpool_labels(labels.data_ptr(), B, nx, ny, nz, out.data_ptr(), _dt(out), _s()))
+    return out
+
+
+# ---- autograd functions ---------------------------------------------------------------------
+
+class Conv3dS2(torch.autograd.Function):
+    """y = act(conv3d(x, w, b, stride 2, padding 1)); w_compute is the weight copy used."""
+
+    @staticmethod
+    def forward(ctx, x, w, b, w_compute, relu: bool):
+        x = _c(x)
+        B, Ci, D, H, W = x.shape
+        Co = w.shape[0]
+        y = torch.empty((B, Co, D // 2, H // 2, W // 2), dtype=x.dtype, device=x.device)
+        _check(LIB.nn_conv3d_s2_fwd(_dt(x), B, Ci, Co, D, H, W, x.data_ptr(), w_compute.data_ptr(),
+                                    _wdt(w_compute), _p(b), int(relu), y.data_ptr(), _s()))
+        ctx.save_for_backward(x, w_compute, y)
+        ctx.relu = relu
+        ctx.has_bias = b is not None
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, wc, y = ctx.saved_tensors
+        B, Ci, D, H, W = x.shape
+        Co = wc.shape[0]
+        gy = _c(gy)
+        if ctx.relu:
+            g = torch.empty_like(gy)
+            _check(LIB.nn_relu_bwd(_dt(gy), gy.numel(), y.data_ptr(), gy.data_ptr(), g.data_ptr(), _s()))
+        else:
+            g = gy
+        dx = None
+        if ctx.needs_input_grad[0]:
+            dx = torch.empty_like(x)
+            _check(LIB.nn_conv3d_s2_bwd_data(_dt(x), B, Ci, Co, D, H, W, g.data_ptr(), wc.data_ptr(),
+                                             _wdt(wc), None, 0, dx.data_ptr(), _s()))
+        dw = torch.empty((Co, Ci, 3, 3, 3), dtype=x.dtype, device=x.device)
+        db_ = torch.empty(Co, dtype=x.dtype, device=x.device) if ctx.has_bias else None
+        nb = LIB.nn_conv3d_s2_bwd_weight_ws_bytes(_dt(x), B, Ci, Co, D, H, W)
+        ws = torch.empty(nb, dtype=torch.uint8, device=x.device)
+        _check(LIB.nn_conv3d_s2_bwd_weight(_dt(x), B, Ci, Co, D, H, W, x.data_ptr(), g.data_ptr(),
+                                           dw.data_ptr(), _p(db_), ws.data_ptr(), nb, _s()))
+        return dx, dw, db_, None, None
+
+
+class ConvT3dS2(torch.autograd.Function):
+    """y = act(conv_transpose3d(x, w, b, stride 2, padding 1, output_padding 1)).
+
+    w has the transposed-convolution layout [Cin][Cout][3][3][3]; the map is
+    the adjoint of the stride-2 convolution with weight w viewed as
+    [Co = Cin][Ci = Cout].
+    """
+
+    @staticmethod
+    def forward(ctx, x, w, b, w_compute, relu: bool):
+        x = _c(x)
+        B, Cin, d, h, wd = x.shape
+        Cout = w.shape[1]
+        D, H, W = 2 * d, 2 * h, 2 * wd
+        y = torch.empty((B, Cout, D, H, W), dtype=x.dtype, device=x.device)
+        _check(LIB.nn_conv3d_s2_bwd_data(_dt(x), B, Cout, Cin, D, H, W, x.data_ptr(),
+                                         w_compute.data_ptr(), _wdt(w_compute), _p(b), int(relu),
+                                         y.data_ptr(), _s()))
+        ctx.save_for_backward(x, w_compute, y)
+        ctx.relu = relu
+        ctx.has_bias = b is not None
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, wc, y = ctx.saved_tensors
+        B, Cin, d, h, wd = x.shape
+        Cout = wc.shape[1]
+        D, H, W = 2 * d, 2 * h, 2 * wd
+        gy = _c(gy)
+        if ctx.relu:
+            g = torch.empty_like(gy)
+            _check(LIB.nn_relu_bwd(_dt(gy), gy.numel(), y.data_ptr(), gy.data_ptr(), g.data_ptr(), _s()))
+        else:
+            g = gy
+        dx = None
+        if ctx.needs_input_grad[0]:
+            dx = torch.empty_like(x)
+            _check(LIB.nn_conv3d_s2_fwd(_dt(x), B, Cout, Cin, D, H, W, g.data_ptr(), wc.data_ptr(),
+                                        _wdt(wc), None, 0, dx.data_ptr(), _s()))
+        dw = torch.empty((Cin, Cout, 3, 3, 3), dtype=x.dtype, device=x.device)
+        nb = LIB.nn_conv3d_s2_bwd_weight_ws_bytes(_dt(x), B, Cout, Cin, D, H, W)
+        ws = torch.empty(nb, dtype=torch.uint8, device=x.device)
+        _check(LIB.nn_conv3d_s2_bwd_weight(_dt(x), B, Cout, Cin, D, H, W, g.data_ptr(), x.data_ptr(),
+                                           dw.data_ptr(), None, ws.data_ptr(), nb, _s()))
+        db_ = None
+        if ctx.has_bias:
+            db_ = torch.empty(Cout, dtype=x.dtype, device=x.device)
+            _check(LIB.nn_channel_sum(_dt(x), B, Cout, D * H * W, g.data_ptr(), db_.data_ptr(), _s()))
+        return dx, dw, db_, None, None
+
+
+class Linear(torch.autograd.Function):
+    """y = act(x w^T + b), x [B][In], w [Out][In]."""
+
+    @staticmethod
+    def forward(ctx, x, w, b, w_compute, relu: bool):
+        x = _c(x)
+        B, In = x.shape
+        Out = w.shape[0]
+        y = torch.empty((B, Out), dtype=x.dtype, device=x.device)
+        _check(LIB.nn_linear_fwd(_dt(x), B, In, Out, x.data_ptr(), w_compute.data_ptr(),
+                                 _wdt(w_compute), _p(b), int(relu), y.data_ptr(), _s()))
+        ctx.save_for_backward(x, w_compute, y)
+        ctx.relu = relu
+        ctx.has_bias = b is not None
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, wc, y = ctx.saved_tensors
+        B, In = x.shape
+        Out = wc.shape[0]
+        gy = _c(gy)
+        if ctx.relu:
+            g = torch.empty_like(gy)
+            _check(LIB.nn_relu_bwd(_dt(gy), gy.numel(), y.data_ptr(), gy.data_ptr(), g.data_ptr(), _s()))
+        else:
+            g = gy
+        dx = None
+        if ctx.needs_input_grad[0]:
+            dx = torch.empty_like(x)
+            _check(LIB.nn_linear_bwd_data(_dt(x), B, In, Out, g.data_ptr(), wc.data_ptr(), _wdt(wc),
+                                          dx.data_ptr(), _s()))
+        dw = torch.empty((Out, In), dtype=x.dtype, device=x.device)
+        db_ = torch.empty(Out, dtype=x.dtype, device=x.device) if ctx.has_bias else None
+        _check(LIB.nn_linear_bwd_weight(_dt(x), B, In, Out, x.data_ptr(), g.data_ptr(), dw.data_ptr(),
+                                        _p(db_), _s()))
+        return dx, dw, db_, None, None
+
+
+class MSE(torch.autograd.Function):
+    """mean((a - b)^2); b is the target (no gradient)."""
+
+    @staticmethod
+    def forward(ctx, a, b):
+        a, b = _c(a), _c(b)
+        n = a.numel()
+        loss = torch.empty((), dtype=a.dtype, device=a.device)
+        nb = LIB.nn_mse_ws_bytes(_dt(a), n)
+        ws = torch.empty(nb, dtype=torch.uint8, device=a.device)
+        _check(LIB.nn_mse_fwd(_dt(a), n, a.data_ptr(), b.data_ptr(), loss.data_ptr(), ws.data_ptr(),
+                              nb, _s()))
+        ctx.save_for_backward(a, b)
+        return loss
+
+    @staticmethod
+    def backward(ctx, gl):
+        a, b = ctx.saved_tensors
+        gl = _c(gl.to(a.dtype))
+        da = torch.empty_like(a)
+        _check(LIB.nn_mse_bwd(_dt(a), a.numel(), a.data_ptr(), b.data_ptr(), gl.data_ptr(),
+                              da.data_ptr(), _s()))
+        return da, None
+
+
+# ---- model ----------------------------------------------------------------------------------
+
+class AutoEncoder:
+    """Encoder 2->8->16->32->64 stride-2 convolutions + linear to `latent`, mirrored decoder.
+
+    dtype float32: BF16 working weights, FP32 master weights, activations and
+    biases. dtype float64: every weight in double (for gradient checks).
+    """
+
+    def __init__(self, grid: int = 64, channels=(2, 8, 16, 32, 64), latent: int = 512,
+                 dtype=torch.float32, device="cuda", seed: int = 0):
+        assert grid % 16 == 0
+        self.grid, self.channels, self.latent = grid, tuple(channels), latent
+        self.dtype = dtype
+        self.bf16 = dtype == torch.float32
+        g = torch.Generator().manual_seed(seed)
+        s = grid // 16
+        self.flat = channels[-1] * s ** 3
+        self.params = {}
+
+        def uni(shape, fan_in):
+            bound = math.sqrt(6.0 / fan_in)   # He-uniform for ReLU layers
+            return ((torch.rand(shape, generator=g, dtype=torch.float64) * 2 - 1) * bound)
+
+        for i in range(4):
+            ci, co = channels[i], channels[i + 1]
+            self.params[f"enc{i}.w"] = uni((co, ci, 3, 3, 3), ci * 27)
+            self.params[f"enc{i}.b"] = torch.zeros(co, dtype=torch.float64)
+        self.params["enc_fc.w"] = uni((latent, self.flat), self.flat)
+        self.params["enc_fc.b"] = torch.zeros(latent, dtype=torch.float64)
+        self.params["dec_fc.w"] = uni((self.flat, latent), latent)
+        self.params["dec_fc.b"] = torch.zeros(self.flat, dtype=torch.float64)
+        for i in reversed(range(4)):
+            ci, co = channels[i + 1], channels[i]       # transposed conv: Cin -> Cout
+            self.params[f"dec{i}.w"] = uni((ci, co, 3, 3, 3), ci * 27)
+            self.params[f"dec{i}.b"] = torch.zeros(co, dtype=torch.float64)
+        for k in self.params:
+            self.params[k] = self.params[k].to(device=device, dtype=dtype).requires_grad_(True)
+        self.work = {}
+        self.refresh_working_weights()
+
+    def refresh_working_weights(self) -> None:
+        """BF16 copies (round to nearest even) of the weight tensors, or the weights themselves."""
+        for k, p in self.params.items():
+            if not k.endswith(".w"):
+                continue
+            if self.bf16:
+                wb = self.work.get(k)
+                if wb is None:
+                    wb = torch.empty(p.shape, dtype=torch.bfloat16, device=p.device)
+                    self.work[k] = wb
+                _check(LIB.nn_to_bf16(p.numel(), p.data_ptr(), wb.data_ptr(), _s()))
+            else:
+                self.work[k] = p.detach()
+
+    def _w(self, name):
+        return self.params[name + ".w"], self.params[name + ".b"], self.work[name + ".w"]
+
+    def encode(self, x: torch.Tensor) -> torch.Tensor:
+        h = x
+        for i in range(4):
+            w, b, wc = self._w(f"enc{i}")
+            h = Conv3dS2.apply(h, w, b, wc, True)
+        h = h.reshape(h.shape[0], -1)
+        w, b, wc = self._w("enc_fc")
+        return Linear.apply(h, w, b, wc, False)
+
+    def decode(self, z: torch.Tensor) -> torch.Tensor:
+        w, b, wc = self._w("dec_fc")
+        h = Linear.apply(z, w, b, wc, True)
+        s = self.grid // 16
+        h = h.reshape(h.shape[0], self.channels[-1], s, s, s)
+        for i in reversed(range(4)):
+            w, b, wc = self._w(f"dec{i}")
+            h = ConvT3dS2.apply(h, w, b, wc, i != 0)
+        return h
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        return self.decode(self.encode(x))
+
+    def loss(self, x: torch.Tensor) -> torch.Tensor:
+        return MSE.apply(self.forward(x), x)
+
+    def n_params(self) -> int:
+        return sum(p.numel() for p in self.params.values())
+
+
+class Adam:
+    """Adam on the FP32 master weights; refreshes the BF16 working copies in the same kernel."""
+
+    def __init__(self, model: AutoEncoder, lr=1e-3, betas=(0.9, 0.999), eps=1e-8):
+        assert model.dtype == torch.float32
+        self.model, self.lr, self.b1, self.b2, self.eps = model, lr, betas[0], betas[1], eps
+        self.m = {k: torch.zeros_like(p, requires_grad=False) for k, p in model.params.items()}
+        self.v = {k: torch.zeros_like(p, requires_grad=False) for k, p in model.params.items()}
+        self.t = 0
+
+    def step(self) -> None:
+        self.t += 1
+        for k, p in self.model.params.items():
+            if p.grad is None:
+                continue
+            wb = self.model.work.get(k) if (self.model.bf16 and k.endswith(".w")) else None
+            _check(LIB.nn_adam_step(p.numel(), p.data_ptr(), self.m[k].data_ptr(), self.v[k].data_ptr(),
+                                    p.grad.data_ptr(), _p(wb), self.lr, self.b1, self.b2, self.eps,
+                                    self.t, _s()))
+            p.grad = None
+
+
+def train_step(model: AutoEncoder, opt: Adam, x: torch.Tensor) -> torch.Tensor:
+    """One step: forward, MSE against the input, backward, Adam. Returns the loss (device)."""
+    loss = model.loss(x)
+    loss.backward()
+    opt.step()
+    return loss.detach()

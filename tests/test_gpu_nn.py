@@ -1,0 +1,255 @@
+"""GPU checks of the encoder kernels: layer parity with the float64 CPU oracle, gradients
+against the oracle's autograd and against finite differences, mean-pooling, Adam and BF16."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import build_db_from_host, need_gpu, say
+from oracle import encoder as E
+
+pytestmark = pytest.mark.gpu
+
+
+def _cpu64(t):
+    return t.detach().to("cpu", torch.float64)
+
+
+def _rel(a, b):
+    return float((a - b).abs().max() / max(b.abs().max(), 1e-30))
+
+
+def test_meanpool_db_and_labels_exact():
+    need_gpu()
+    from paper_2205_04550_amd import nn
+    gen = synth.GenConfig(64, 32, 16, 2.0, 10.0, 0.5, 3.0, 12)
+    n = 9
+    db, conc = build_db_from_host(gen, n, synth.T_LO, synth.T_HI)
+    import oracle
+    labs = np.stack([oracle.threshold(c, synth.T_LO, synth.T_HI) for c in conc])
+    idx = torch.tensor([3, 0, 8, 3], dtype=torch.int32, device="cuda")
+    for dt in (torch.float32, torch.float64):
+        got = nn.meanpool_db(db, idx, dt).cpu().numpy()
+        want = E.meanpool(labs[[3, 0, 8, 3]])
+        assert np.array_equal(got.astype(np.float64), want)
+        got2 = nn.meanpool_labels(torch.from_numpy(labs).cuda(), dt).cpu().numpy()
+        assert np.array_equal(got2.astype(np.float64), E.meanpool(labs))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_layers_match_oracle_forward_and_backward(dtype):
+    need_gpu()
+    from paper_2205_04550_amd import nn
+    torch.manual_seed(0)
+    B, Ci, Co, D, H, W = 3, 5, 7, 10, 8, 6
+    x64 = torch.randn(B, Ci, D, H, W, dtype=torch.float64)
+    w64 = torch.randn(Co, Ci, 3, 3, 3, dtype=torch.float64) * 0.2
+    b64 = torch.randn(Co, dtype=torch.float64)
+    if dtype == torch.float32:
+        wc = w64.to(torch.bfloat16)                  # the kernels' BF16 working weights
+        w_ref = wc.to(torch.float64)
+        tol = 2e-5
+    else:
+        wc = None
+        w_ref = w64
+        tol = 1e-12
+    xs = x64.to("cuda", dtype).requires_grad_(True)
+    ws = w64.to("cuda", dtype).requires_grad_(True)
+    bs = b64.to("cuda", dtype).requires_grad_(True)
+    wcs = wc.cuda() if wc is not None else ws.detach()
+    # conv forward / backward
+    for relu in (False, True):
+        say(f"conv {dtype} relu={relu}")
+        y = nn.Conv3dS2.apply(xs, ws, bs, wcs, relu)
+        xr = x64.clone().requires_grad_(True)
+        wr = w_ref.clone().requires_grad_(True)
+        br = b64.clone().requires_grad_(True)
+        yr = E.conv(xr, wr, br, relu)
+        assert _rel(_cpu64(y), yr.detach()) < tol
+        gy = torch.randn_like(yr)
+        (yr * gy).sum().backward()
+        gx, gw, gb = torch.autograd.grad(y, (xs, ws, bs), gy.to("cuda", dtype))
+        assert _rel(_cpu64(gx), xr.grad) < tol
+        assert _rel(_cpu64(gw), wr.grad) < tol
+        assert _rel(_cpu64(gb), br.grad) < tol
+    # transposed conv: weight [Cin][Cout] with Cin = Co here (maps Co -> Ci channels)
+    xt64 = torch.randn(B, Co, D // 2, H // 2, W // 2, dtype=torch.float64)
+    bt64 = torch.randn(Ci, dtype=torch.float64)
+    xts = xt64.to("cuda", dtype).requires_grad_(True)
+    bts = bt64.to("cuda", dtype).requires_grad_(True)
+    for relu in (False, True):
+        say(f"convT {dtype} relu={relu}")
+        y = nn.ConvT3dS2.apply(xts, ws, bts, wcs, relu)
+        xr = xt64.clone().requires_grad_(True)
+        wr = w_ref.clone().requires_grad_(True)
+        br = bt64.clone().requires_grad_(True)
+        yr = E.conv_t(xr, wr, br, relu)
+        assert y.shape == yr.shape
+        assert _rel(_cpu64(y), yr.detach()) < tol
+        gy = torch.randn_like(yr)
+        (yr * gy).sum().backward()
+        gx, gw, gb = torch.autograd.grad(y, (xts, ws, bts), gy.to("cuda", dtype))
+        assert _rel(_cpu64(gx), xr.grad) < tol
+        assert _rel(_cpu64(gw), wr.grad) < tol
+        assert _rel(_cpu64(gb), br.grad) < tol
+    # linear
+    In, Out = 37, 19
+    xl64 = torch.randn(B, In, dtype=torch.float64)
+    wl64 = torch.randn(Out, In, dtype=torch.float64) * 0.3
+    bl64 = torch.randn(Out, dtype=torch.float64)
+    wlc = wl64.to(torch.bfloat16).cuda() if dtype == torch.float32 else None
+    wl_ref = wl64.to(torch.bfloat16).to(torch.float64) if dtype == torch.float32 else wl64
+    xls = xl64.to("cuda", dtype).requires_grad_(True)
+    wls = wl64.to("cuda", dtype).requires_grad_(True)
+    bls = bl64.to("cuda", dtype).requires_grad_(True)
+    for relu in (False, True):
+        say(f"linear {dtype} relu={relu}")
+        y = nn.Linear.apply(xls, wls, bls, wlc if wlc is not None else wls.detach(), relu)
+        xr = xl64.clone().requires_grad_(True)
+        wr = wl_ref.clone().requires_grad_(True)
+        br = bl64.clone().requires_grad_(True)
+        yr = torch.nn.functional.linear(xr, wr, br)
+        yr = torch.relu(yr) if relu else yr
+        assert _rel(_cpu64(y), yr.detach()) < tol
+        gy = torch.randn_like(yr)
+        (yr * gy).sum().backward()
+        gx, gw, gb = torch.autograd.grad(y, (xls, wls, bls), gy.to("cuda", dtype))
+        assert _rel(_cpu64(gx), xr.grad) < tol
+        assert _rel(_cpu64(gw), wr.grad) < tol
+        assert _rel(_cpu64(gb), br.grad) < tol
+
+
+def test_gradcheck_float64_functions():
+    need_gpu()
+    from paper_2205_04550_amd import nn
+    torch.manual_seed(1)
+    d = dict(dtype=torch.float64, device="cuda")
+    x = torch.randn(2, 2, 4, 4, 4, **d, requires_grad=True)
+    w = torch.randn(3, 2, 3, 3, 3, **d, requires_grad=True)
+    b = torch.randn(3, **d, requires_grad=True)
+    assert torch.autograd.gradcheck(lambda x, w, b: nn.Conv3dS2.apply(x, w, b, w, False),
+                                    (x, w, b), eps=1e-6, atol=1e-8, rtol=1e-6)
+    xt = torch.randn(2, 3, 2, 2, 2, **d, requires_grad=True)
+    bt = torch.randn(2, **d, requires_grad=True)
+    assert torch.autograd.gradcheck(lambda x, w, b: nn.ConvT3dS2.apply(x, w, b, w, False),
+                                    (xt, w, bt), eps=1e-6, atol=1e-8, rtol=1e-6)
+    xl = torch.randn(3, 6, **d, requires_grad=True)
+    wl = torch.randn(4, 6, **d, requires_grad=True)
+    bl = torch.randn(4, **d, requires_grad=True)
+    assert torch.autograd.gradcheck(lambda x, w, b: nn.Linear.apply(x, w, b, w, False),
+                                    (xl, wl, bl), eps=1e-6, atol=1e-8, rtol=1e-6)
+    a = torch.randn(5, 3, **d, requires_grad=True)
+    t = torch.randn(5, 3, **d)
+    assert torch.autograd.gradcheck(lambda a: nn.MSE.apply(a, t), (a,), eps=1e-6, atol=1e-8)
+
+
+def test_autoencoder_finite_differences_16cube():
+    """Whole autoencoder in float64 on a 16^3 instance (16 -> 8 -> 4 -> 2 -> 1, 64 channels,
+    latent 512, mirrored decoder), batch 2: analytic gradients of the MSE loss against
+    central differences (h = 1e-6) for every bias and 200 random entries of every weight
+    and of the input."""
+    need_gpu()
+    from paper_2205_04550_amd import nn
+    model = nn.AutoEncoder(grid=16, latent=512, dtype=torch.float64, seed=3)
+    torch.manual_seed(4)
+    # Random biases: with zero biases, units whose inputs are all zero sit exactly on the
+    # ReLU kink, where the derivative is one-sided and central differences see half of it.
+    with torch.no_grad():
+        for k, p in model.params.items():
+            if k.endswith(".b"):
+                p.copy_(torch.randn(p.shape, dtype=torch.float64) * 0.1)
+    x = torch.rand(2, 2, 16, 16, 16, dtype=torch.float64, device="cuda").requires_grad_(True)
+    target = x.detach().clone()   # the reconstruction target stays fixed when x is perturbed
+
+    def loss_of(inp):
+        return nn.MSE.apply(model.forward(inp), target)
+
+    loss = loss_of(x)
+    loss.backward()
+    # forward agrees with the oracle
+    params_cpu = {k: _cpu64(p) for k, p in model.params.items()}
+    ref = E.mse(E.decode(params_cpu, E.encode(params_cpu, _cpu64(x)), 64, 1), _cpu64(x))
+    assert abs(float(loss.detach()) - float(ref)) <= 1e-12 * abs(float(ref))
+    h = 1e-6
+    l0 = float(loss.detach())
+    rng = np.random.default_rng(5)
+    tensors = [(k, p) for k, p in model.params.items()] + [("input", x)]
+    checked = skipped = 0
+    for name, p in tensors:
+        g = p.grad.detach().cpu().numpy().ravel()
+        flat = p.data.view(-1)
+        if name.endswith(".b"):
+            coords = range(flat.numel())
+        else:
+            coords = rng.choice(flat.numel(), size=min(200, flat.numel()), replace=False)
+        gmax = float(np.abs(g).max())
+        for c in coords:
+            c = int(c)
+            old = float(flat[c])
+            flat[c] = old + h
+            lp = float(loss_of(x.detach()))
+            flat[c] = old - h
+            lm = float(loss_of(x.detach()))
+            flat[c] = old
+            fd = (lp - lm) / (2 * h)
+            # A ReLU switching inside [-h, h] makes the one-sided slopes disagree: skip it.
+            if abs((lp - l0) / h - (l0 - lm) / h) > 1e-3 * abs(fd) + 1e-6:
+                skipped += 1
+                continue
+            assert abs(fd - g[c]) <= 1e-5 * abs(g[c]) + 1e-7 * gmax + 1e-9, (name, c, fd, g[c])
+            checked += 1
+    assert skipped <= 0.01 * (checked + skipped)
+    say(f"finite differences: {checked} coordinates agree, {skipped} skipped at ReLU kinks")
+
+
+def test_bf16_rounding_and_adam_step():
+    need_gpu()
+    from paper_2205_04550_amd import nn
+    from paper_2205_04550_amd.binding import LIB, _check
+    rng = np.random.default_rng(9)
+    x = (rng.standard_normal(10000) * 10.0 ** rng.integers(-5, 5, 10000)).astype(np.float32)
+    x[:4] = np.array([1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -1.0 - 2 ** -8, 0.0], np.float32)  # ties
+    u = x.view(np.uint32).astype(np.uint64)
+    want = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)    # round to nearest even
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.empty(x.size, dtype=torch.bfloat16, device="cuda")
+    _check(LIB.nn_to_bf16(x.size, xd.data_ptr(), yd.data_ptr(), torch.cuda.current_stream().cuda_stream))
+    got = yd.view(torch.int16).cpu().numpy().view(np.uint16)
+    assert np.array_equal(got, want)
+    # one Adam step against the textbook formula in float32 (numpy)
+    w = rng.standard_normal(513).astype(np.float32)
+    g = rng.standard_normal(513).astype(np.float32)
+    m = rng.standard_normal(513).astype(np.float32) * 0.1
+    v = np.abs(rng.standard_normal(513).astype(np.float32)) * 0.1
+    lr, b1, b2, eps, t = 1e-3, 0.9, 0.999, 1e-8, 3
+    W, M, Vv, G = (torch.from_numpy(a.copy()).cuda() for a in (w, m, v, g))
+    wb = torch.empty(513, dtype=torch.bfloat16, device="cuda")
+    _check(LIB.nn_adam_step(513, W.data_ptr(), M.data_ptr(), Vv.data_ptr(), G.data_ptr(),
+                            wb.data_ptr(), lr, b1, b2, eps, t, torch.cuda.current_stream().cuda_stream))
+    m2 = np.float32(b1) * m + np.float32(1 - b1) * g
+    v2 = np.float32(b2) * v + np.float32(1 - b2) * g * g
+    w2 = w - np.float32(lr) * (m2 / np.float32(1 - b1 ** t)) / (np.sqrt(v2 / np.float32(1 - b2 ** t)) + np.float32(eps))
+    assert np.allclose(M.cpu().numpy(), m2, rtol=1e-6, atol=1e-7)
+    assert np.allclose(Vv.cpu().numpy(), v2, rtol=1e-6, atol=1e-7)
+    assert np.allclose(W.cpu().numpy(), w2, rtol=1e-6, atol=1e-6)
+    assert torch.equal(wb, W.to(torch.bfloat16))
+
+
+def test_training_overfits_one_batch():
+    """Forward, backward and Adam together: repeated steps on one batch must drive its
+    reconstruction loss well down."""
+    need_gpu()
+    from paper_2205_04550_amd import nn
+    gen = synth.SMALL
+    n = 64
+    db, _ = build_db_from_host(gen, n, synth.T_LO, synth.T_HI)
+    model = nn.AutoEncoder(grid=32, latent=64, seed=0)
+    opt = nn.Adam(model, lr=2e-3)
+    idx = torch.arange(0, 64, 8, dtype=torch.int32, device="cuda")
+    x = nn.meanpool_db(db, idx)
+    losses = [float(nn.train_step(model, opt, x)) for _ in range(150)]
+    say(f"loss {losses[0]:.5f} -> {min(losses):.5f} (last {losses[-1]:.5f})")
+    assert all(math.isfinite(l) for l in losses)
+    assert np.mean(losses[-10:]) < 0.5 * losses[0]

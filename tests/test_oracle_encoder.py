@@ -1,0 +1,83 @@
+"""Pins of the embedding-path oracle (CPU, float64) against closed forms and identities."""
+import numpy as np
+import torch
+
+from oracle import encoder as E
+
+
+def test_meanpool_closed_forms():
+    lab = np.zeros((1, 4, 4, 8), dtype=np.uint8)
+    lab[0, 1, 2, 5] = 1          # one FLAIR voxel -> 1/8 in block (0, 1, 2)
+    lab[0, 2:4, 0:2, 0:2] = 3    # a full 2x2x2 block of both masks -> 1
+    out = E.meanpool(lab)
+    assert out.shape == (1, 2, 2, 2, 4)
+    assert out[0, 0, 0, 1, 2] == 0.125
+    assert out[0, 0, 1, 0, 0] == 1.0 and out[0, 1, 1, 0, 0] == 1.0
+    assert out[0, 1, 0, 1, 2] == 0.0
+    rng = np.random.default_rng(0)
+    lab = rng.integers(0, 4, size=(2, 6, 8, 32), dtype=np.uint8)
+    out = E.meanpool(lab)
+    for m in range(2):
+        assert out[:, m].sum() * 8 == ((lab >> m) & 1).sum()
+    assert set(np.unique(out * 8)) <= set(range(9))
+
+
+def test_conv_with_centre_delta_is_strided_copy():
+    torch.manual_seed(0)
+    x = torch.randn(2, 3, 8, 6, 4, dtype=torch.float64)
+    w = torch.zeros(3, 3, 3, 3, 3, dtype=torch.float64)
+    for c in range(3):
+        w[c, c, 1, 1, 1] = 1.0                     # centre tap -> input voxel 2o
+    y = E.conv(x, w, None, False)
+    assert torch.equal(y, x[:, :, ::2, ::2, ::2])
+    w2 = torch.zeros_like(w)
+    for c in range(3):
+        w2[c, c, 2, 2, 2] = 1.0                    # last tap -> input voxel 2o + 1
+    y2 = E.conv(x, w2, None, False)
+    assert torch.equal(y2, x[:, :, 1::2, 1::2, 1::2])
+
+
+def test_transposed_conv_is_the_adjoint():
+    torch.manual_seed(1)
+    x = torch.randn(2, 4, 8, 8, 6, dtype=torch.float64)
+    w = torch.randn(5, 4, 3, 3, 3, dtype=torch.float64)      # conv: 4 -> 5 channels
+    y = torch.randn(2, 5, 4, 4, 3, dtype=torch.float64)
+    lhs = (E.conv(x, w, None, False) * y).sum()
+    rhs = (x * E.conv_t(y, w, None, False)).sum()               # same tensor as [Cin][Cout]
+    assert abs(float(lhs - rhs)) <= 1e-10 * abs(float(lhs))
+    assert E.conv_t(y, w, None, False).shape == x.shape
+
+
+def test_linear_identity_and_relu():
+    z = torch.randn(3, 7, dtype=torch.float64)
+    assert torch.equal(torch.nn.functional.linear(z, torch.eye(7, dtype=torch.float64)), z)
+    w = torch.zeros(2, 2, 3, 3, 3, dtype=torch.float64)
+    w[0, 0, 1, 1, 1] = 1.0
+    w[1, 1, 1, 1, 1] = 1.0
+    # A 2x2x2 grid: the centre tap of output voxel 0 reads input voxel 0.
+    x = torch.zeros(1, 2, 2, 2, 2, dtype=torch.float64)
+    x[0, 0, 0, 0, 0], x[0, 1, 0, 0, 0] = -1.0, 2.0
+    y = E.conv(x, w, None, True)
+    assert y.shape == (1, 2, 1, 1, 1)
+    assert float(y[0, 0]) == 0.0 and float(y[0, 1]) == 2.0
+
+
+def test_distance_forms():
+    rng = np.random.default_rng(3)
+    Q = rng.standard_normal((4, 16))
+    X = np.concatenate([Q[:2], rng.standard_normal((5, 16))])
+    d = E.sqdist_direct(Q, X)
+    assert d[0, 0] == 0.0 and d[1, 1] == 0.0
+    e = np.eye(16)
+    assert E.sqdist_direct(e[:1], e[1:2])[0, 0] == 2.0
+    expanded = (Q ** 2).sum(1)[:, None] + (X ** 2).sum(1)[None, :] - 2 * Q @ X.T
+    assert np.allclose(expanded, d, atol=1e-12)
+    top = E.topk_by_distance(np.array([[3.0, 1.0, 1.0, 0.5]]), 3)
+    assert top.tolist() == [[3, 1, 2]]
+
+
+def test_mse_gradient_closed_form():
+    a = torch.randn(3, 5, dtype=torch.float64, requires_grad=True)
+    b = torch.randn(3, 5, dtype=torch.float64)
+    E.mse(a, b).backward()
+    assert torch.allclose(a.grad, 2 * (a.detach() - b) / a.numel(), rtol=0, atol=1e-15)
