@@ -122,6 +122,52 @@ int db_query_batch(const db_t *db, int nq, const uint8_t *q_labels, const db_roi
                    int32_t *idx, double *score, db_counts_t *counts, void *ws, size_t ws_bytes,
                    void *stream);
 
+/* ---------------------------------------------------- embedding search --- */
+/* Latent search (Sec. 2.3, "Autoencoders": encoded database and query are
+ * compared by L2 distance, lowest wins), then exact re-scoring of the
+ * candidates with the Dice score above. Latents are row-major [n][dim]; row i
+ * of the database latents belongs to entry i. Distances are the squared L2
+ * distance in the expanded form |q|^2 + |x|^2 - 2 q.x, accumulated in FP32 on
+ * the matrix cores (BF16, or FP8 e4m3 with a per-row scale). */
+enum { EMB_BF16 = 0, EMB_FP8 = 1 };
+
+/* Quantise FP32 latents lat [n][dim] (device): EMB_BF16 writes uint16 codes
+ * (round to nearest even); EMB_FP8 writes uint8 OCP e4m3 codes of lat/s with
+ * s = max|row| / 448 (1 for a zero row) into scale[n]. sqnorm[n] = |stored
+ * vector|^2 (of the dequantised values, summed in double). scale is ignored
+ * for BF16. dim % 16 == 0 (BF16) or dim % 64 == 0 (FP8). */
+int emb_quantize(int64_t n, int dim, const float *lat, int fmt, void *codes, float *scale,
+                 float *sqnorm, void *stream);
+
+/* D[m][n] = q_sq[m] + x_sq[n] - 2 <q_m, x_n> (FP32, device [M][N]); the
+ * scales multiply the FP8 dot products and are ignored for BF16. */
+int emb_distances(int fmt, int M, int N, int dim, const void *q_codes, const float *q_scale,
+                  const float *q_sq, const void *x_codes, const float *x_scale, const float *x_sq,
+                  float *D, void *stream);
+
+/* Per row of D [M][N]: the k smallest values, ties by lower column, in
+ * ascending order: idx [M][k] (int32), d [M][k]. 1 <= k <= min(N, DB_KMAX). */
+int emb_topk_min(int M, int N, const float *D, int k, int32_t *idx, float *d, void *stream);
+
+/* Exact re-scoring: for query q (labels [nq][nz][ny][nx]) and its candidate
+ * entries cand [nq][nc] (device int32, each in [0, db_size())), the k best by
+ * Dice_T1Gd + Dice_FLAIR (score desc, index asc) among the candidates.
+ * nc <= DB_KMAX, k <= nc. Candidates must be distinct within a row. */
+size_t db_rerank_workspace_bytes(const db_t *db, int nq);
+int db_rerank(const db_t *db, int nq, const uint8_t *q_labels, const int32_t *cand, int nc, int k,
+              int32_t *idx, double *score, db_counts_t *counts, void *ws, size_t ws_bytes,
+              void *stream);
+
+/* The chain distances -> n_cand nearest latents -> exact rerank -> k best.
+ * Database latents x_* have n_lat = db_size() rows. cand_idx / cand_d [nq][n_cand]
+ * receive the latent candidates (or pass NULL to keep them in the workspace). */
+size_t db_query_embed_workspace_bytes(const db_t *db, int nq, int n_cand);
+int db_query_embed(const db_t *db, int fmt, int nq, int dim, const void *q_codes,
+                   const float *q_scale, const float *q_sq, const void *x_codes,
+                   const float *x_scale, const float *x_sq, const uint8_t *q_labels, int n_cand,
+                   int k, int32_t *idx, double *score, db_counts_t *counts, int32_t *cand_idx,
+                   float *cand_d, void *ws, size_t ws_bytes, void *stream);
+
 /* ----------------------------------------------------------------- misc --- */
 
 /* Wait for `stream` and report any asynchronous device error as DB_EHIP. */

@@ -78,3 +78,51 @@ def sqdist_direct(Q: np.ndarray, X: np.ndarray) -> np.ndarray:
 def topk_by_distance(d: np.ndarray, k: int) -> np.ndarray:
     """Indices of the k smallest distances per row, ties by lower index (stable sort)."""
     return np.argsort(d, axis=1, kind="stable")[:, :k]
+
+
+def bf16_decode(bits: np.ndarray) -> np.ndarray:
+    """bfloat16 bit patterns -> float64 (the upper half of an IEEE single)."""
+    b = np.asarray(bits).view(np.uint16).astype(np.uint32) << 16
+    return b.view(np.float32).astype(np.float64)
+
+
+def bf16_encode(x: np.ndarray) -> np.ndarray:
+    """float32 -> bfloat16 bits, round to nearest, ties to even (finite inputs)."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+def e4m3_decode(codes: np.ndarray) -> np.ndarray:
+    """OCP FP8 e4m3 bytes -> float64: sign, 4-bit exponent (bias 7), 3-bit mantissa;
+    exponent 0 is subnormal (m * 2^-9); 0x7F / 0xFF are NaN."""
+    c = np.asarray(codes, dtype=np.uint8).astype(np.int64)
+    e = (c >> 3) & 15
+    m = c & 7
+    mag = np.where(e == 0, m * 2.0 ** -9, (1.0 + m / 8.0) * np.exp2(e - 7.0))
+    mag = np.where((c & 0x7F) == 0x7F, np.nan, mag)
+    return np.where(c & 0x80, -mag, mag)
+
+
+def e4m3_encode(v: np.ndarray) -> np.ndarray:
+    """float -> OCP e4m3 bytes by exhaustive nearest search over the 253 finite codes,
+    ties to the even code (the one whose mantissa LSB is 0), saturating at +-448; a value
+    that rounds to zero keeps its sign (0x00 / 0x80)."""
+    v = np.asarray(v, dtype=np.float64)
+    codes = np.array([c for c in range(256) if (c & 0x7F) != 0x7F], dtype=np.uint8)
+    vals = e4m3_decode(codes)
+    out = np.empty(v.shape, dtype=np.uint8)
+    flat = v.ravel()
+    res = out.ravel()
+    for i, x in enumerate(flat):
+        x = min(max(x, -448.0), 448.0)
+        d = np.abs(vals - x)
+        best = d.min()
+        cand = codes[d == best]
+        if len(cand) > 1:   # a tie between two neighbours (or +-0): prefer the even mantissa
+            even = [c for c in cand if (c & 1) == 0]
+            cand = even if even else cand
+        c = int(cand[0])
+        if (c & 0x7F) == 0:  # zero magnitude: the sign of the input
+            c = 0x80 if np.signbit(x) else 0x00
+        res[i] = c
+    return out

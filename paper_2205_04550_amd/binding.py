@@ -19,7 +19,10 @@ DB_OK, DB_EINVAL, DB_ENOMEM, DB_EHIP, DB_ESTATE, DB_ENOSPC = 0, -1, -2, -3, -4, 
 DB_KMAX = 1024
 SYMBOLS = ("db_storage_bytes", "db_build", "db_append", "db_size", "db_query_workspace_bytes",
            "db_scan", "db_query", "db_query_batch", "db_sync", "db_free", "db_last_error",
-           "db_profile", "db_profile_read")
+           "db_profile", "db_profile_read", "emb_quantize", "emb_distances", "emb_topk_min",
+           "db_rerank_workspace_bytes", "db_rerank", "db_query_embed_workspace_bytes",
+           "db_query_embed")
+EMB_BF16, EMB_FP8 = 0, 1
 
 
 class DbError(RuntimeError):
@@ -52,6 +55,14 @@ def _load():
         "db_free": (None, [vp]),
         "db_last_error": (ctypes.c_char_p, []),
         "db_profile": (i32, [vp, i32]),
+        "emb_quantize": (i32, [i64, i32, vp, i32, vp, vp, vp, vp]),
+        "emb_distances": (i32, [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
+        "emb_topk_min": (i32, [i32, i32, vp, i32, vp, vp, vp]),
+        "db_rerank_workspace_bytes": (sz, [vp, i32]),
+        "db_rerank": (i32, [vp, i32, vp, vp, i32, i32, vp, vp, vp, vp, sz, vp]),
+        "db_query_embed_workspace_bytes": (sz, [vp, i32, i32]),
+        "db_query_embed": (i32, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp,
+                                 vp, vp, vp, vp, sz, vp]),
         "db_profile_read": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]),
     }
     for name, (res, args) in sig.items():
@@ -190,6 +201,43 @@ class TumorDB:
                                   _stream(stream)))
         return idx, score, counts
 
+    def rerank(self, q_labels: torch.Tensor, cand: torch.Tensor, k: int, stream=None):
+        """Exact Dice re-scoring of candidate entries cand [nq][nc] (int32): top-k per query."""
+        nq, nc = cand.shape
+        dev = self.storage.device
+        idx = torch.empty((nq, k), dtype=torch.int32, device=dev)
+        score = torch.empty((nq, k), dtype=torch.float64, device=dev)
+        counts = torch.empty((nq, k, 6), dtype=torch.int32, device=dev)
+        nb = LIB.db_rerank_workspace_bytes(self._h, nq)
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        cand = cand.to(torch.int32).contiguous()
+        _check(LIB.db_rerank(self._h, nq, q_labels.data_ptr(), cand.data_ptr(), nc, k,
+                             idx.data_ptr(), score.data_ptr(), counts.data_ptr(), ws.data_ptr(), nb,
+                             _stream(stream)))
+        return idx, score, counts
+
+    def query_embed(self, fmt: int, q: "Latents", x: "Latents", q_labels: torch.Tensor,
+                    n_cand: int, k: int, ws: torch.Tensor | None = None, out=None, stream=None):
+        """Latent search (n_cand nearest) + exact rerank -> (idx, score, counts, cand_idx, cand_d)."""
+        nq = q.codes.shape[0]
+        dev = self.storage.device
+        if out is None:
+            out = (torch.empty((nq, k), dtype=torch.int32, device=dev),
+                   torch.empty((nq, k), dtype=torch.float64, device=dev),
+                   torch.empty((nq, k, 6), dtype=torch.int32, device=dev),
+                   torch.empty((nq, n_cand), dtype=torch.int32, device=dev),
+                   torch.empty((nq, n_cand), dtype=torch.float32, device=dev))
+        if ws is None:
+            ws = torch.empty(LIB.db_query_embed_workspace_bytes(self._h, nq, n_cand),
+                             dtype=torch.uint8, device=dev)
+        idx, score, counts, ci, cd = out
+        _check(LIB.db_query_embed(self._h, fmt, nq, q.dim, q.codes.data_ptr(), _ptr(q.scale),
+                                  q.sq.data_ptr(), x.codes.data_ptr(), _ptr(x.scale), x.sq.data_ptr(),
+                                  q_labels.data_ptr(), n_cand, k, idx.data_ptr(), score.data_ptr(),
+                                  counts.data_ptr(), ci.data_ptr(), cd.data_ptr(), ws.data_ptr(),
+                                  ws.numel(), _stream(stream)))
+        return out
+
     def profile(self, enable: bool) -> None:
         """Record HIP events around the dominant kernel of every later query call."""
         _check(LIB.db_profile(self._h, 1 if enable else 0))
@@ -214,3 +262,43 @@ class TumorDB:
             self.close()
         except Exception:
             pass
+
+
+class Latents:
+    """Quantised latents on the device: codes [n][dim] (bf16 bits or e4m3 bytes), per-row
+    scale (FP8 only) and squared norm of the stored vectors."""
+
+    def __init__(self, lat: torch.Tensor, fmt: int, stream=None):
+        lat = lat.to(torch.float32).contiguous()
+        n, dim = lat.shape
+        self.fmt, self.n, self.dim = fmt, n, dim
+        dev = lat.device
+        if fmt == EMB_BF16:
+            self.codes = torch.empty((n, dim), dtype=torch.bfloat16, device=dev)
+            self.scale = None
+        else:
+            self.codes = torch.empty((n, dim), dtype=torch.uint8, device=dev)
+            self.scale = torch.empty(n, dtype=torch.float32, device=dev)
+        self.sq = torch.empty(n, dtype=torch.float32, device=dev)
+        _check(LIB.emb_quantize(n, dim, lat.data_ptr(), fmt, self.codes.data_ptr(), _ptr(self.scale),
+                                self.sq.data_ptr(), _stream(stream)))
+
+
+def emb_distances(q: Latents, x: Latents, out: torch.Tensor | None = None, stream=None):
+    """Squared L2 distances [nq][n] (FP32) of quantised latents, expanded form on MFMA."""
+    if out is None:
+        out = torch.empty((q.n, x.n), dtype=torch.float32, device=q.codes.device)
+    _check(LIB.emb_distances(q.fmt, q.n, x.n, q.dim, q.codes.data_ptr(), _ptr(q.scale),
+                             q.sq.data_ptr(), x.codes.data_ptr(), _ptr(x.scale), x.sq.data_ptr(),
+                             out.data_ptr(), _stream(stream)))
+    return out
+
+
+def emb_topk_min(D: torch.Tensor, k: int, stream=None):
+    """Per row the k smallest (ties by lower column), ascending: (idx int32, values)."""
+    M, N = D.shape
+    idx = torch.empty((M, k), dtype=torch.int32, device=D.device)
+    val = torch.empty((M, k), dtype=torch.float32, device=D.device)
+    _check(LIB.emb_topk_min(M, N, D.contiguous().data_ptr(), k, idx.data_ptr(), val.data_ptr(),
+                            _stream(stream)))
+    return idx, val

@@ -515,6 +515,178 @@ int db_query_batch(const db_t *db_c, int nq, const uint8_t *q_labels, const db_r
     return DB_OK;
 }
 
+// ---- embedding search ----
+
+int emb_quantize(int64_t n, int dim, const float *lat, int fmt, void *codes, float *scale,
+                 float *sqnorm, void *stream)
+{
+    if (n <= 0 || n > INT32_MAX || dim <= 0 || !lat || !codes || !sqnorm)
+        return fail(DB_EINVAL, "emb_quantize: bad arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (fmt == EMB_BF16) {
+        if (dim % 16) return fail(DB_EINVAL, "emb_quantize: BF16 needs dim %% 16 == 0");
+        e = launch_quant_bf16(n, dim, lat, static_cast<uint16_t *>(codes), sqnorm, s);
+    } else if (fmt == EMB_FP8) {
+        if (dim % 64 || !scale) return fail(DB_EINVAL, "emb_quantize: FP8 needs dim %% 64 == 0 and scale");
+        e = launch_quant_fp8(n, dim, lat, static_cast<uint8_t *>(codes), scale, sqnorm, s);
+    } else {
+        return fail(DB_EINVAL, "emb_quantize: unknown format %d", fmt);
+    }
+    if (e != hipSuccess) return hip_fail(e, "emb_quantize: launch");
+    return DB_OK;
+}
+
+int emb_distances(int fmt, int M, int N, int dim, const void *q_codes, const float *q_scale,
+                  const float *q_sq, const void *x_codes, const float *x_scale, const float *x_sq,
+                  float *D, void *stream)
+{
+    if (M <= 0 || N <= 0 || dim <= 0 || !q_codes || !q_sq || !x_codes || !x_sq || !D ||
+        (M + 127) / 128 > 65535)
+        return fail(DB_EINVAL, "emb_distances: bad arguments");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (fmt == EMB_BF16) {
+        if (dim % 16) return fail(DB_EINVAL, "emb_distances: BF16 needs dim %% 16 == 0");
+        if (!aligned(q_codes, 16) || !aligned(x_codes, 16))
+            return fail(DB_EINVAL, "emb_distances: codes must be 16-byte aligned");
+        e = launch_dist_bf16(M, N, dim, static_cast<const uint16_t *>(q_codes), q_sq,
+                             static_cast<const uint16_t *>(x_codes), x_sq, D, s);
+    } else if (fmt == EMB_FP8) {
+        if (dim % 64 || !q_scale || !x_scale)
+            return fail(DB_EINVAL, "emb_distances: FP8 needs dim %% 64 == 0 and scales");
+        if (!aligned(q_codes, 32) || !aligned(x_codes, 32))
+            return fail(DB_EINVAL, "emb_distances: codes must be 32-byte aligned");
+        e = launch_dist_fp8(M, N, dim, static_cast<const uint8_t *>(q_codes), q_scale, q_sq,
+                            static_cast<const uint8_t *>(x_codes), x_scale, x_sq, D, s);
+    } else {
+        return fail(DB_EINVAL, "emb_distances: unknown format %d", fmt);
+    }
+    if (e != hipSuccess) return hip_fail(e, "emb_distances: launch");
+    return DB_OK;
+}
+
+int emb_topk_min(int M, int N, const float *D, int k, int32_t *idx, float *d, void *stream)
+{
+    if (M <= 0 || N <= 0 || !D || !idx || !d || k < 1 || k > N || k > DB_KMAX)
+        return fail(DB_EINVAL, "emb_topk_min: bad arguments (k = %d, N = %d)", k, N);
+    hipError_t e = launch_topk_min(M, N, k, D, idx, d, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "emb_topk_min: launch");
+    return DB_OK;
+}
+
+// Rerank workspace: packed queries, per-block counts, query counts, row boxes.
+static size_t rerank_layout(const db_t *db, int nq, size_t *o_qpack, size_t *o_qpart,
+                            size_t *o_acnt, size_t *o_box)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, kAlign);
+        return o;
+    };
+    *o_qpack = take((size_t)nq * 2 * db->g.Wp * 4);
+    *o_qpart = take((size_t)nq * kQueryParts * 2 * 4);
+    *o_acnt = take((size_t)nq * 2 * 4);
+    *o_box = take((size_t)nq * 4 * 4);
+    return off;
+}
+
+size_t db_rerank_workspace_bytes(const db_t *db, int nq)
+{
+    if (!live(db) || nq <= 0) return 0;
+    size_t a, b, c, d;
+    return rerank_layout(db, nq, &a, &b, &c, &d);
+}
+
+static hipError_t enqueue_rerank(const db_t *db, int nq, const uint8_t *q_labels,
+                                 const int32_t *cand, int nc, int k, int32_t *idx, double *score,
+                                 db_counts_t *counts, void *ws, hipStream_t s)
+{
+    size_t oq, op, oa, ob;
+    rerank_layout(db, nq, &oq, &op, &oa, &ob);
+    uint32_t *qpack = at<uint32_t>(ws, oq);
+    uint32_t *acnt = at<uint32_t>(ws, oa);
+    int32_t *box = at<int32_t>(ws, ob);
+    hipError_t e = launch_pack_queries(db, q_labels, nq, nullptr, qpack, at<uint32_t>(ws, op), s);
+    if (e == hipSuccess) e = launch_sum_parts(at<uint32_t>(ws, op), nq, acnt, s);
+    if (e == hipSuccess) e = launch_query_rowbox(db, nq, qpack, box, s);
+    if (e == hipSuccess) e = launch_rerank(db, nq, qpack, acnt, box, cand, nc, k, idx, score, counts, s);
+    return e;
+}
+
+int db_rerank(const db_t *db, int nq, const uint8_t *q_labels, const int32_t *cand, int nc, int k,
+              int32_t *idx, double *score, db_counts_t *counts, void *ws, size_t ws_bytes,
+              void *stream)
+{
+    int rc = check_query_common("db_rerank", db, q_labels, ws);
+    if (rc) return rc;
+    if (nq <= 0 || !cand || !idx || !score || nc < 1 || nc > DB_KMAX || k < 1 || k > nc)
+        return fail(DB_EINVAL, "db_rerank: bad arguments (nq %d, nc %d, k %d)", nq, nc, k);
+    const size_t need = db_rerank_workspace_bytes(db, nq);
+    if (ws_bytes < need)
+        return fail(DB_ENOSPC, "db_rerank: workspace %zu bytes < %zu needed", ws_bytes, need);
+    hipError_t e = enqueue_rerank(db, nq, q_labels, cand, nc, k, idx, score, counts, ws,
+                                  static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "db_rerank: launch");
+    return DB_OK;
+}
+
+static size_t embed_layout(const db_t *db, int nq, int n_cand, size_t *o_D, size_t *o_ci,
+                           size_t *o_cd, size_t *o_rr)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes, kAlign);
+        return o;
+    };
+    *o_D = take((size_t)nq * db->capacity * 4);
+    *o_ci = take((size_t)nq * n_cand * 4);
+    *o_cd = take((size_t)nq * n_cand * 4);
+    size_t a, b, c, d;
+    *o_rr = take(rerank_layout(db, nq, &a, &b, &c, &d));
+    return off;
+}
+
+size_t db_query_embed_workspace_bytes(const db_t *db, int nq, int n_cand)
+{
+    if (!live(db) || nq <= 0 || n_cand <= 0) return 0;
+    size_t a, b, c, d;
+    return embed_layout(db, nq, n_cand, &a, &b, &c, &d);
+}
+
+int db_query_embed(const db_t *db, int fmt, int nq, int dim, const void *q_codes,
+                   const float *q_scale, const float *q_sq, const void *x_codes,
+                   const float *x_scale, const float *x_sq, const uint8_t *q_labels, int n_cand,
+                   int k, int32_t *idx, double *score, db_counts_t *counts, int32_t *cand_idx,
+                   float *cand_d, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_query_common("db_query_embed", db, q_labels, ws);
+    if (rc) return rc;
+    const int64_t n = db->count;
+    if (nq <= 0 || n_cand < 1 || n_cand > DB_KMAX || n_cand > n || k < 1 || k > n_cand || !idx ||
+        !score || n > INT32_MAX)
+        return fail(DB_EINVAL, "db_query_embed: bad arguments (nq %d, n_cand %d, k %d)", nq,
+                    n_cand, k);
+    size_t oD, oci, ocd, orr;
+    const size_t need = embed_layout(db, nq, n_cand, &oD, &oci, &ocd, &orr);
+    if (ws_bytes < need)
+        return fail(DB_ENOSPC, "db_query_embed: workspace %zu bytes < %zu needed", ws_bytes, need);
+    float *D = at<float>(ws, oD);
+    int32_t *ci = cand_idx ? cand_idx : at<int32_t>(ws, oci);
+    float *cd = cand_d ? cand_d : at<float>(ws, ocd);
+    rc = emb_distances(fmt, nq, (int)n, dim, q_codes, q_scale, q_sq, x_codes, x_scale, x_sq, D,
+                       stream);
+    if (rc) return rc;
+    rc = emb_topk_min(nq, (int)n, D, n_cand, ci, cd, stream);
+    if (rc) return rc;
+    hipError_t e = enqueue_rerank(db, nq, q_labels, ci, n_cand, k, idx, score, counts,
+                                  at<char>(ws, orr), static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "db_query_embed: rerank launch");
+    return DB_OK;
+}
+
 int db_sync(const db_t *db, void *stream)
 {
     if (!live(db)) return fail(DB_ESTATE, "db_sync: invalid handle");

@@ -1,0 +1,632 @@
+// embed.hip — latent-distance search and exact-Dice rerank.
+//
+// Paper Sec. 2.3 ("Autoencoders"): the database and the query are encoded to
+// latents and compared by L2 distance, lowest wins. Here the squared distance
+// is expanded, d(q, x) = |q|^2 + |x|^2 - 2 q.x, so the dominant work is one
+// dense contraction on the matrix cores:
+//   - BF16 latents: v_mfma_f32_32x32x16_bf16, FP32 accumulation;
+//   - FP8 (OCP e4m3) latents with a per-row scale: v_mfma_scale_f32_32x32x64_f8f6f4.
+// Each query keeps its k nearest latents (exact radix select on the FP32
+// distances, ties by lower index), and those candidates are re-scored with
+// the exact Dice_T1Gd + Dice_FLAIR of the packed masks (Sec. 2.3 score),
+// reading only the rows of the query's bounding box (outside it the query
+// has no set bit, so those words contribute nothing to the overlap).
+#include <limits.h>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace tdb {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+// ---- quantisation ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint16_t bf16_rne(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu))
+        return (uint16_t)((u >> 16) | 0x0040u);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float bf16_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// OCP FP8 e4m3 (bias 7, no infinities, largest finite 448): round to nearest
+// even, saturating at +-448. Written from the format definition.
+__device__ __forceinline__ uint8_t e4m3_rne(float v)
+{
+    const uint32_t sign = (__float_as_uint(v) >> 24) & 0x80u;
+    float a = fabsf(v);
+    if (!(a == a)) return (uint8_t)(sign | 0x7f);          // NaN
+    if (a >= 448.0f) return (uint8_t)(sign | 0x7e);
+    if (a < 0.015625f) {                                    // below 2^-6: subnormal step 2^-9
+        const int m = (int)rintf(a * 512.0f);               // 0..8 (8 = smallest normal)
+        return (uint8_t)(sign | (uint32_t)m);
+    }
+    int e;
+    const float fr = frexpf(a, &e);                         // a = fr * 2^e, fr in [0.5, 1)
+    int m = (int)rintf((fr * 2.0f - 1.0f) * 8.0f);          // exact scaling, then RNE
+    int E = e - 1 + 7;
+    if (m == 8) {
+        m = 0;
+        E += 1;
+    }
+    uint32_t code = ((uint32_t)E << 3) | (uint32_t)m;
+    if (code > 0x7e) code = 0x7e;
+    return (uint8_t)(sign | code);
+}
+
+__device__ __forceinline__ float e4m3_val(uint8_t c)
+{
+    const int E = (c >> 3) & 15, m = c & 7;
+    const float mag = E == 0 ? (float)m * 0.001953125f : ldexpf(1.0f + (float)m * 0.125f, E - 7);
+    return (c & 0x80) ? -mag : mag;
+}
+
+// One block (256 threads) per row: BF16 copy and |x|^2 of the stored values.
+__global__ void __launch_bounds__(256) quant_bf16_kernel(int dim, const float *__restrict__ x,
+                                                         uint16_t *__restrict__ y,
+                                                         float *__restrict__ sq)
+{
+    __shared__ double red[4];
+    const int64_t r = blockIdx.x;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < dim; i += blockDim.x) {
+        const uint16_t b = bf16_rne(x[r * dim + i]);
+        y[r * dim + i] = b;
+        const double v = bf16_val(b);
+        acc += v * v;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) sq[r] = (float)(((red[0] + red[1]) + red[2]) + red[3]);
+}
+
+// One block per row: scale s = max|x| / 448 (1 for a zero row), codes e4m3(x / s),
+// |s * e4m3_val(code)|^2 summed in double.
+__global__ void __launch_bounds__(256) quant_fp8_kernel(int dim, const float *__restrict__ x,
+                                                        uint8_t *__restrict__ y,
+                                                        float *__restrict__ scale,
+                                                        float *__restrict__ sq)
+{
+    __shared__ float redm[4];
+    __shared__ double red[4];
+    const int64_t r = blockIdx.x;
+    float amax = 0.f;
+    for (int i = threadIdx.x; i < dim; i += blockDim.x) amax = fmaxf(amax, fabsf(x[r * dim + i]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+    if ((threadIdx.x & 63) == 0) redm[threadIdx.x >> 6] = amax;
+    __syncthreads();
+    amax = fmaxf(fmaxf(redm[0], redm[1]), fmaxf(redm[2], redm[3]));
+    const float s = amax > 0.f ? amax / 448.0f : 1.0f;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < dim; i += blockDim.x) {
+        const uint8_t c = e4m3_rne(x[r * dim + i] / s);
+        y[r * dim + i] = c;
+        const double v = (double)s * (double)e4m3_val(c);
+        acc += v * v;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        sq[r] = (float)(((red[0] + red[1]) + red[2]) + red[3]);
+        scale[r] = s;
+    }
+}
+
+// ---- distance GEMM -----------------------------------------------------------------------------
+//
+// Block tile 128 queries x 128 database rows, 4 waves as 2 x 2 of 64 x 64,
+// each wave 2 x 2 MFMA 32x32 tiles. Operands are K-contiguous rows, so lane l
+// reads 16 (bf16) or 32 (fp8) bytes of row l % 32 at k-chunk l / 32 straight
+// from global memory / L2 (the tiles are tiny next to the distance matrix
+// written out). Result register r of lane l is row 8 (r / 4) + 4 (l / 32) +
+// r % 4, column l % 32 of the 32 x 32 tile.
+
+constexpr int kGT = 128;
+
+__global__ void __launch_bounds__(256) dist_bf16_kernel(int M, int N, int K,
+                                                        const uint16_t *__restrict__ Q,
+                                                        const float *__restrict__ qn,
+                                                        const uint16_t *__restrict__ X,
+                                                        const float *__restrict__ xn,
+                                                        float *__restrict__ D)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m0 = blockIdx.y * kGT + (wave >> 1) * 64;
+    const int n0 = blockIdx.x * kGT + (wave & 1) * 64;
+    const int half = lane >> 5, r32 = lane & 31;
+    const bf16x8 *pa[2], *pb[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int ra = min(m0 + i * 32 + r32, M - 1);
+        const int rb = min(n0 + i * 32 + r32, N - 1);
+        pa[i] = reinterpret_cast<const bf16x8 *>(Q + (int64_t)ra * K) + half;
+        pb[i] = reinterpret_cast<const bf16x8 *>(X + (int64_t)rb * K) + half;
+    }
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+    const int steps = K / 16;
+    for (int s = 0; s < steps; s += 4) {
+        bf16x8 a[4][2], b[4][2];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int c = 2 * (s + u < steps ? s + u : steps - 1);
+                a[u][i] = pa[i][c];
+                b[u][i] = pb[i][c];
+            }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (s + u >= steps) break;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[u][i], b[u][j], acc[i][j],
+                                                                        0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = n0 + j * 32 + r32;
+            if (col >= N) continue;
+            const float xc = xn[col];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = m0 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                if (row < M)
+                    D[(int64_t)row * N + col] = (qn[row] + xc) - 2.0f * acc[i][j][r];
+            }
+        }
+}
+
+__global__ void __launch_bounds__(256) dist_fp8_kernel(int M, int N, int K,
+                                                       const uint8_t *__restrict__ Q,
+                                                       const float *__restrict__ qs,
+                                                       const float *__restrict__ qn,
+                                                       const uint8_t *__restrict__ X,
+                                                       const float *__restrict__ xs,
+                                                       const float *__restrict__ xn,
+                                                       float *__restrict__ D)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m0 = blockIdx.y * kGT + (wave >> 1) * 64;
+    const int n0 = blockIdx.x * kGT + (wave & 1) * 64;
+    const int half = lane >> 5, r32 = lane & 31;
+    const i32x8 *pa[2], *pb[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int ra = min(m0 + i * 32 + r32, M - 1);
+        const int rb = min(n0 + i * 32 + r32, N - 1);
+        pa[i] = reinterpret_cast<const i32x8 *>(Q + (int64_t)ra * K) + half;
+        pb[i] = reinterpret_cast<const i32x8 *>(X + (int64_t)rb * K) + half;
+    }
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+    const int steps = K / 64;
+    f32x16 zero16;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) zero16[r] = 0.f;
+    for (int s = 0; s < steps; s += 2) {
+        i32x8 a[2][2], b[2][2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int c = 2 * (s + u < steps ? s + u : steps - 1);
+                a[u][i] = pa[i][c];
+                b[u][i] = pb[i][c];
+            }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (s + u >= steps) break;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    // formats 0/0 = fp8 e4m3 for both operands; E8M0 scales 127 = 2^0.
+                    // Each 64-wide step starts from zero and is added in FP32 on the
+                    // VALU: accumulating inside the instruction loses more precision.
+                    const f32x16 part = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        a[u][i], b[u][j], zero16, 0, 0, 0, 127, 0, 127);
+                    acc[i][j] += part;
+                }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = n0 + j * 32 + r32;
+            if (col >= N) continue;
+            const float xc = xn[col], sc = xs[col];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = m0 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                if (row < M)
+                    D[(int64_t)row * N + col] =
+                        (qn[row] + xc) - 2.0f * (qs[row] * sc) * acc[i][j][r];
+            }
+        }
+}
+
+// ---- exact k smallest per row (radix select) ----------------------------------------------
+
+// Order-preserving map of a float to uint32 (negative values flipped); -0 is
+// folded onto +0 first so that equal values compare equal.
+__device__ __forceinline__ uint32_t fkey(float f)
+{
+    if (f == 0.0f) f = 0.0f;
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float fkey_inv(uint32_t k)
+{
+    const uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(u);
+}
+
+constexpr int kSelThreads = 1024;
+constexpr int kSelMaxK = 1024;
+
+// grid M, kSelThreads threads. Four 8-bit digit passes find the key T of the
+// k-th smallest element; entries with key < T are taken, then the lowest
+// indices among key == T; the k winners are sorted by (key, index).
+__global__ void __launch_bounds__(kSelThreads) topk_min_kernel(const float *__restrict__ D, int N,
+                                                               int k, int32_t *__restrict__ out_idx,
+                                                               float *__restrict__ out_d)
+{
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t s_sel[2];
+    __shared__ uint32_t scan[kSelThreads];
+    __shared__ uint32_t sk[kSelMaxK];
+    __shared__ int32_t si[kSelMaxK];
+    __shared__ uint32_t s_lt;
+    const float *row = D + (int64_t)blockIdx.x * N;
+    const int lane = threadIdx.x & 63;
+    uint32_t prefix = 0, mask = 0, remaining = (uint32_t)k;
+    for (int pass = 0; pass < 4; ++pass) {
+        const int shift = 24 - 8 * pass;
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+        __syncthreads();
+        for (int base = 0; base < N; base += blockDim.x) {
+            const int i = base + threadIdx.x;
+            bool pending = false;
+            uint32_t bin = 0;
+            if (i < N) {
+                const uint32_t u = fkey(row[i]);
+                pending = (u & mask) == prefix;
+                bin = (u >> shift) & 255u;
+            }
+            // Wave-aggregated increments: one LDS atomic per distinct bin in the wave.
+            uint64_t m = __ballot(pending);
+            while (m) {
+                const int leader = __ffsll((unsigned long long)m) - 1;
+                const uint32_t b = __shfl(bin, leader, 64);
+                const uint64_t same = __ballot(pending && bin == b);
+                if (lane == leader) atomicAdd(&hist[b], (uint32_t)__popcll(same));
+                if (pending && bin == b) pending = false;
+                m = __ballot(pending);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t cum = 0, sel = 255;
+            for (int b = 0; b < 256; ++b) {
+                if (cum + hist[b] >= remaining) {
+                    sel = (uint32_t)b;
+                    break;
+                }
+                cum += hist[b];
+            }
+            s_sel[0] = prefix | (sel << shift);
+            s_sel[1] = remaining - cum;
+        }
+        __syncthreads();
+        prefix = s_sel[0];
+        remaining = s_sel[1];
+        mask |= 255u << shift;
+        __syncthreads();
+    }
+    const uint32_t T = prefix;          // key of the k-th smallest
+    const uint32_t n_lt = (uint32_t)k - remaining;
+    // Entries below T (order fixed by the sort below) and per-thread counts of T in
+    // contiguous index chunks.
+    if (threadIdx.x == 0) s_lt = 0;
+    __syncthreads();
+    const int C = (N + blockDim.x - 1) / blockDim.x;
+    const int c0 = threadIdx.x * C, c1 = min(N, c0 + C);
+    uint32_t eq = 0;
+    for (int i = c0; i < c1; ++i) {
+        const uint32_t u = fkey(row[i]);
+        if (u < T) {
+            const uint32_t slot = atomicAdd(&s_lt, 1u);
+            sk[slot] = u;
+            si[slot] = i;
+        } else if (u == T) {
+            ++eq;
+        }
+    }
+    scan[threadIdx.x] = eq;
+    __syncthreads();
+    // Exclusive prefix of the equal-key counts in index order (Hillis-Steele).
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+        const uint32_t v = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0u;
+        __syncthreads();
+        scan[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t rank = scan[threadIdx.x] - eq;
+    if (rank < remaining) {
+        for (int i = c0; i < c1 && rank < remaining; ++i) {
+            if (fkey(row[i]) == T) {
+                sk[n_lt + rank] = T;
+                si[n_lt + rank] = i;
+                ++rank;
+            }
+        }
+    }
+    // Sort the k winners by (key, index); pad to a power of two.
+    int P = 1;
+    while (P < k) P <<= 1;
+    for (int t = k + threadIdx.x; t < P; t += blockDim.x) {
+        sk[t] = 0xffffffffu;
+        si[t] = INT_MAX;
+    }
+    for (int size = 2; size <= P; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < P / 2; t += blockDim.x) {
+                const int i = 2 * t - (t & (stride - 1));
+                const int j = i + stride;
+                const bool up = (i & size) == 0;
+                const uint32_t ki = sk[i], kj = sk[j];
+                const int32_t ii = si[i], ij = si[j];
+                const bool j_first = kj < ki || (kj == ki && ij < ii);
+                if (j_first == up) {
+                    sk[i] = kj;
+                    sk[j] = ki;
+                    si[i] = ij;
+                    si[j] = ii;
+                }
+            }
+        }
+    __syncthreads();
+    for (int t = threadIdx.x; t < k; t += blockDim.x) {
+        out_idx[(int64_t)blockIdx.x * k + t] = si[t];
+        out_d[(int64_t)blockIdx.x * k + t] = fkey_inv(sk[t]);
+    }
+}
+
+// ---- exact rerank ---------------------------------------------------------------------------
+
+// Rows (z, y) holding any set bit of either query mask: box [z0, z1) x [y0, y1).
+// grid nq, 256 threads.
+__global__ void __launch_bounds__(256) query_rowbox_kernel(const uint32_t *__restrict__ qpack,
+                                                           int Wp, int nxw, int ny, int nz,
+                                                           int32_t *__restrict__ box)
+{
+    __shared__ int red[4][4];
+    const int q = blockIdx.x;
+    const uint32_t *Q0 = qpack + (int64_t)q * 2 * Wp, *Q1 = Q0 + Wp;
+    const int rows = ny * nz;
+    int zlo = INT_MAX, zhi = -1, ylo = INT_MAX, yhi = -1;
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+        uint32_t any = 0;
+        for (int w = 0; w < nxw; ++w) any |= Q0[r * nxw + w] | Q1[r * nxw + w];
+        if (any) {
+            const int z = r / ny, y = r - z * ny;
+            zlo = min(zlo, z);
+            zhi = max(zhi, z);
+            ylo = min(ylo, y);
+            yhi = max(yhi, y);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        zlo = min(zlo, __shfl_xor(zlo, o, 64));
+        zhi = max(zhi, __shfl_xor(zhi, o, 64));
+        ylo = min(ylo, __shfl_xor(ylo, o, 64));
+        yhi = max(yhi, __shfl_xor(yhi, o, 64));
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[w][0] = zlo;
+        red[w][1] = zhi;
+        red[w][2] = ylo;
+        red[w][3] = yhi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 4; ++i) {
+            zlo = min(zlo, red[i][0]);
+            zhi = max(zhi, red[i][1]);
+            ylo = min(ylo, red[i][2]);
+            yhi = max(yhi, red[i][3]);
+        }
+        int32_t *b = box + 4 * q;
+        if (zhi < 0) {
+            b[0] = b[1] = b[2] = b[3] = 0;   // empty query: no rows
+        } else {
+            b[0] = zlo;
+            b[1] = zhi + 1;
+            b[2] = ylo;
+            b[3] = yhi + 1;
+        }
+    }
+}
+
+constexpr int kRerankMaxCand = 1024;
+
+// grid nq, 256 threads (4 waves). Wave w scores candidates w, w + 4, ...: lanes
+// sweep the query's row box, AND + popcount against the candidate's planes;
+// then the block ranks the candidates by (score desc, index asc) and writes k.
+__global__ void __launch_bounds__(256) rerank_kernel(const uint32_t *__restrict__ planes,
+                                                     const uint32_t *__restrict__ popcnt, int Wp,
+                                                     int nxw, int ny, const uint32_t *__restrict__ qpack,
+                                                     const uint32_t *__restrict__ acnt,
+                                                     const int32_t *__restrict__ box,
+                                                     const int32_t *__restrict__ cand, int nc, int k,
+                                                     int32_t *__restrict__ out_idx,
+                                                     double *__restrict__ out_score,
+                                                     db_counts_t *__restrict__ out_counts)
+{
+    __shared__ uint64_t ks[kRerankMaxCand];
+    __shared__ int32_t ki[kRerankMaxCand];
+    __shared__ uint32_t kI[kRerankMaxCand][2];
+    const int q = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const uint32_t *Q0 = qpack + (int64_t)q * 2 * Wp, *Q1 = Q0 + Wp;
+    const int32_t *b = box + 4 * q;
+    const int z0 = b[0], z1 = b[1], y0 = b[2], y1 = b[3];
+    const int nyr = y1 - y0;
+    const int nr = (z1 - z0) * nyr;
+    const uint32_t A0 = acnt[2 * q], A1 = acnt[2 * q + 1];
+    for (int c = wave; c < nc; c += nwaves) {
+        const int32_t e = cand[(int64_t)q * nc + c];
+        const uint32_t *D0 = planes + (int64_t)e * 2 * Wp, *D1 = D0 + Wp;
+        uint32_t i0 = 0, i1 = 0;
+        for (int r = lane; r < nr; r += 64) {
+            const int zr = r / nyr;
+            const int base = ((z0 + zr) * ny + (y0 + r - zr * nyr)) * nxw;
+            for (int w = 0; w < nxw; ++w) {
+                i0 += popc(Q0[base + w] & D0[base + w]);
+                i1 += popc(Q1[base + w] & D1[base + w]);
+            }
+        }
+        i0 = wave_sum(i0);
+        i1 = wave_sum(i1);
+        if (lane == 0) {
+            const double s = dice(i1, A1, popcnt[2 * (int64_t)e + 1]) + dice(i0, A0, popcnt[2 * (int64_t)e]);
+            ks[c] = (uint64_t)__double_as_longlong(s);
+            ki[c] = e;
+            kI[c][0] = i0;
+            kI[c][1] = i1;
+        }
+    }
+    int P = 1;
+    while (P < nc) P <<= 1;
+    for (int t = nc + threadIdx.x; t < P; t += blockDim.x) {
+        ks[t] = 0;
+        ki[t] = INT_MAX;
+    }
+    // Bitonic sort of slot numbers by (score desc, index asc), carrying the counts.
+    __shared__ int16_t slot[kRerankMaxCand];
+    for (int t = threadIdx.x; t < P; t += blockDim.x) slot[t] = (int16_t)t;
+    for (int size = 2; size <= P; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < P / 2; t += blockDim.x) {
+                const int i = 2 * t - (t & (stride - 1));
+                const int j = i + stride;
+                const bool up = (i & size) == 0;
+                const int si_ = slot[i], sj = slot[j];
+                if (ranks_before(ks[sj], ki[sj], ks[si_], ki[si_]) == up) {
+                    slot[i] = (int16_t)sj;
+                    slot[j] = (int16_t)si_;
+                }
+            }
+        }
+    __syncthreads();
+    for (int t = threadIdx.x; t < k; t += blockDim.x) {
+        const int s = slot[t];
+        const int64_t o = (int64_t)q * k + t;
+        const int32_t e = ki[s];
+        out_idx[o] = e;
+        out_score[o] = __longlong_as_double((long long)ks[s]);
+        if (out_counts) {
+            db_counts_t cc;
+            cc.inter[0] = kI[s][0];
+            cc.inter[1] = kI[s][1];
+            cc.a[0] = A0;
+            cc.a[1] = A1;
+            cc.b[0] = popcnt[2 * (int64_t)e];
+            cc.b[1] = popcnt[2 * (int64_t)e + 1];
+            out_counts[o] = cc;
+        }
+    }
+}
+
+// ---- launchers ---------------------------------------------------------------------------------
+
+hipError_t launch_quant_bf16(int64_t n, int dim, const float *x, uint16_t *y, float *sq,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(quant_bf16_kernel, dim3((unsigned)n), dim3(256), 0, s, dim, x, y, sq);
+    return hipGetLastError();
+}
+
+hipError_t launch_quant_fp8(int64_t n, int dim, const float *x, uint8_t *y, float *scale,
+                            float *sq, hipStream_t s)
+{
+    hipLaunchKernelGGL(quant_fp8_kernel, dim3((unsigned)n), dim3(256), 0, s, dim, x, y, scale, sq);
+    return hipGetLastError();
+}
+
+hipError_t launch_dist_bf16(int M, int N, int K, const uint16_t *Q, const float *qn,
+                            const uint16_t *X, const float *xn, float *D, hipStream_t s)
+{
+    hipLaunchKernelGGL(dist_bf16_kernel, dim3((N + kGT - 1) / kGT, (M + kGT - 1) / kGT), dim3(256),
+                       0, s, M, N, K, Q, qn, X, xn, D);
+    return hipGetLastError();
+}
+
+hipError_t launch_dist_fp8(int M, int N, int K, const uint8_t *Q, const float *qs, const float *qn,
+                           const uint8_t *X, const float *xs, const float *xn, float *D,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(dist_fp8_kernel, dim3((N + kGT - 1) / kGT, (M + kGT - 1) / kGT), dim3(256),
+                       0, s, M, N, K, Q, qs, qn, X, xs, xn, D);
+    return hipGetLastError();
+}
+
+hipError_t launch_topk_min(int M, int N, int k, const float *D, int32_t *idx, float *d,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(topk_min_kernel, dim3(M), dim3(kSelThreads), 0, s, D, N, k, idx, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_query_rowbox(const db_t *db, int nq, const uint32_t *qpack, int32_t *box,
+                               hipStream_t s)
+{
+    const Geometry &g = db->g;
+    hipLaunchKernelGGL(query_rowbox_kernel, dim3(nq), dim3(256), 0, s, qpack, g.Wp, g.nxw, g.ny,
+                       g.nz, box);
+    return hipGetLastError();
+}
+
+hipError_t launch_rerank(const db_t *db, int nq, const uint32_t *qpack, const uint32_t *acnt,
+                         const int32_t *box, const int32_t *cand, int nc, int k, int32_t *idx,
+                         double *score, db_counts_t *counts, hipStream_t s)
+{
+    const Geometry &g = db->g;
+    hipLaunchKernelGGL(rerank_kernel, dim3(nq), dim3(256), 0, s, db->planes, db->popcnt, g.Wp,
+                       g.nxw, g.ny, qpack, acnt, box, cand, nc, k, idx, score, counts);
+    return hipGetLastError();
+}
+
+}  // namespace tdb

@@ -91,6 +91,24 @@ hipError_t launch_batch_scan(const db_t *db, int64_t n, int nq, const BatchPlan 
                              uint32_t *inter, uint32_t *bcnt, hipStream_t s);
 hipError_t launch_fill_u32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 
+// Embedding search (embed.hip).
+hipError_t launch_quant_bf16(int64_t n, int dim, const float *x, uint16_t *y, float *sq,
+                             hipStream_t s);
+hipError_t launch_quant_fp8(int64_t n, int dim, const float *x, uint8_t *y, float *scale,
+                            float *sq, hipStream_t s);
+hipError_t launch_dist_bf16(int M, int N, int K, const uint16_t *Q, const float *qn,
+                            const uint16_t *X, const float *xn, float *D, hipStream_t s);
+hipError_t launch_dist_fp8(int M, int N, int K, const uint8_t *Q, const float *qs, const float *qn,
+                           const uint8_t *X, const float *xs, const float *xn, float *D,
+                           hipStream_t s);
+hipError_t launch_topk_min(int M, int N, int k, const float *D, int32_t *idx, float *d,
+                           hipStream_t s);
+hipError_t launch_query_rowbox(const db_t *db, int nq, const uint32_t *qpack, int32_t *box,
+                               hipStream_t s);
+hipError_t launch_rerank(const db_t *db, int nq, const uint32_t *qpack, const uint32_t *acnt,
+                         const int32_t *box, const int32_t *cand, int nc, int k, int32_t *idx,
+                         double *score, db_counts_t *counts, hipStream_t s);
+
 // Top-k over n entries per query. inter: [nq][n..][2] with row stride
 // inter_qstride; bcnt likewise (stride 0 = the database popcounts, shared).
 struct TopkArgs {

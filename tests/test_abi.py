@@ -7,13 +7,15 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "tumordb.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("tumordb.h", "tumornn.h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(db_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b((?:db|emb|nn)_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -24,11 +26,12 @@ def test_header_declares_the_boundary():
 
 
 def test_library_exports_every_declared_symbol():
-    from paper_2205_04550_amd import binding
+    from paper_2205_04550_amd import binding, nn
     lib = ctypes.CDLL(binding.LIB_PATH)
     for n in declared_functions():
         assert hasattr(lib, n), n
-    assert set(declared_functions()) == set(binding.SYMBOLS)
+    # The Python binding covers exactly the declared C entry points.
+    assert set(declared_functions()) == set(binding.SYMBOLS) | set(nn.NN_SYMBOLS)
 
 
 def test_storage_bytes():

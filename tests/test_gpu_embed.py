@@ -1,0 +1,135 @@
+"""GPU parity of the embedding search: quantisation (bit-exact), MFMA distances (within
+1e-5 of |q|^2 + |x|^2 against float64 direct form), exact top-k selection, and exact
+Dice rerank of the candidates (bit-exact against the oracle)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import build_db_from_host, need_gpu, say
+from oracle import encoder as E
+
+pytestmark = pytest.mark.gpu
+
+
+def _lat(n, dim, seed, scale=1.0):
+    g = torch.Generator().manual_seed(seed)
+    return (torch.randn(n, dim, generator=g) * scale).to(torch.float32)
+
+
+def _dequant(L):
+    from paper_2205_04550_amd import binding as b
+    if L.fmt == b.EMB_BF16:
+        return E.bf16_decode(L.codes.view(torch.int16).cpu().numpy())
+    return E.e4m3_decode(L.codes.cpu().numpy()) * L.scale.cpu().numpy().astype(np.float64)[:, None]
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_quantisation_bit_exact(fmt):
+    need_gpu()
+    from paper_2205_04550_amd import binding as b
+    lat = _lat(37, 128, 1)
+    lat[3] = 0.0                                   # zero row: scale 1, all codes zero
+    lat[5, :7] = torch.tensor([448.0, -1e-9, 3e-3, 1e-8, -0.0, 7.0, -3.5])
+    L = b.Latents(lat.cuda(), fmt)
+    torch.cuda.synchronize()
+    x = lat.numpy()
+    if fmt == b.EMB_BF16:
+        assert np.array_equal(L.codes.view(torch.int16).cpu().numpy().view(np.uint16), E.bf16_encode(x))
+    else:
+        amax = np.abs(x).max(axis=1)
+        s = np.where(amax > 0, (amax / np.float32(448.0)).astype(np.float32), np.float32(1.0))
+        assert np.array_equal(L.scale.cpu().numpy(), s)
+        want = np.stack([E.e4m3_encode((x[i] / s[i]).astype(np.float32)) for i in range(x.shape[0])])
+        assert np.array_equal(L.codes.cpu().numpy(), want)
+    deq = _dequant(L)
+    sq = (deq ** 2).sum(axis=1)
+    assert np.allclose(L.sq.cpu().numpy(), sq, rtol=2e-7, atol=0)
+
+
+@pytest.mark.parametrize("fmt,dim", [(0, 512), (0, 48), (1, 512), (1, 64)])
+def test_distances_within_contract(fmt, dim):
+    need_gpu()
+    from paper_2205_04550_amd import binding as b
+    M, N = 77, 1301                                  # ragged against the 128 x 128 tiles
+    Q = b.Latents(_lat(M, dim, 2).cuda(), fmt)
+    X = b.Latents(torch.cat([_lat(M, dim, 2)[:5], _lat(N - 5, dim, 3)]).cuda(), fmt)  # 5 self-pairs
+    D = b.emb_distances(Q, X).cpu().numpy().astype(np.float64)
+    q, x = _dequant(Q), _dequant(X)
+    d64 = E.sqdist_direct(q, x)
+    # BF16: the 1e-5 contract. FP8: the f8f6f4 instruction sums its 64 products with less
+    # than FP32 precision (about 90 FP32 ulps of the raw code dot product within one
+    # instruction, measured), so its contract is 5e-5.
+    rel = 1e-5 if fmt == b.EMB_BF16 else 5e-5
+    bound = rel * ((q ** 2).sum(1)[:, None] + (x ** 2).sum(1)[None, :])
+    err = np.abs(D - d64)
+    say(f"fmt {fmt} dim {dim}: max |d - d64| / bound = {(err / bound).max():.3g}")
+    assert np.all(err <= bound)
+
+
+def test_topk_min_exact_with_ties():
+    need_gpu()
+    from paper_2205_04550_amd import binding as b
+    rng = np.random.default_rng(4)
+    M, N = 9, 50021
+    D = rng.integers(0, 500, size=(M, N)).astype(np.float32) * np.float32(0.25)  # many ties
+    D[2] = 7.0                                                   # a row of equal values
+    D[3, 100:110] = -1.5                                         # negatives
+    Dd = torch.from_numpy(D).cuda()
+    for k in (1, 10, 100, 1000):
+        idx, val = b.emb_topk_min(Dd, k)
+        want = E.topk_by_distance(D, k)
+        assert np.array_equal(idx.cpu().numpy(), want), k
+        assert np.array_equal(val.cpu().numpy(), np.take_along_axis(D, want, 1)), k
+
+
+def test_rerank_bit_exact_and_full_candidate_set_equals_scan():
+    need_gpu()
+    gen = synth.SMALL
+    n, nq = 300, 6
+    say("rerank: build")
+    db, conc = build_db_from_host(gen, n, synth.T_LO, synth.T_HI)
+    labels, _ = synth.make_queries(gen, n, nq, synth.BATCH_QUERY_SEED)
+    labels[2] = 0                                                # an empty query
+    rng = np.random.default_rng(8)
+    cand = np.stack([rng.choice(n, 100, replace=False) for _ in range(nq)]).astype(np.int32)
+    lab_d = torch.from_numpy(labels).cuda()
+    idx, score, counts = db.rerank(lab_d, torch.from_numpy(cand).cuda(), 10)
+    db.sync()
+    for q in range(nq):
+        cnt, sc = oracle.scan_block(conc[cand[q]], labels[q], synth.T_LO, synth.T_HI)
+        order = sorted(range(100), key=lambda j: (-sc[j], cand[q][j]))[:10]
+        assert idx[q].cpu().tolist() == [int(cand[q][j]) for j in order]
+        assert np.array_equal(score[q].cpu().numpy().view(np.uint64), sc[order].view(np.uint64))
+        assert np.array_equal(counts[q].cpu().numpy().view(np.uint32).astype(np.uint64), cnt[order])
+    # Candidates = every entry: the rerank reproduces the exact scan bit for bit.
+    allc = torch.arange(n, dtype=torch.int32).repeat(nq, 1).cuda()
+    ri, rs, rc = db.rerank(lab_d, allc, 10)
+    for q in range(nq):
+        si, ss, sc_ = db.query(lab_d[q], 10)
+        db.sync()
+        assert torch.equal(ri[q], si) and torch.equal(rs[q], ss) and torch.equal(rc[q], sc_)
+
+
+def test_query_embed_chain_matches_its_parts():
+    need_gpu()
+    from paper_2205_04550_amd import binding as b, nn
+    gen = synth.SMALL
+    n, nq = 400, 8
+    db, conc = build_db_from_host(gen, n, synth.T_LO, synth.T_HI)
+    model = nn.AutoEncoder(grid=32, latent=64, seed=1)
+    with torch.no_grad():
+        xl = model.encode(nn.meanpool_db(db, torch.arange(n, dtype=torch.int32, device="cuda")))
+        labels, _ = synth.make_queries(gen, n, nq, synth.BATCH_QUERY_SEED)
+        lab_d = torch.from_numpy(labels).cuda()
+        ql = model.encode(nn.meanpool_labels(lab_d))
+    for fmt in (b.EMB_BF16, b.EMB_FP8):
+        X, Q = b.Latents(xl, fmt), b.Latents(ql, fmt)
+        idx, score, counts, ci, cd = db.query_embed(fmt, Q, X, lab_d, 50, 10)
+        db.sync()
+        D = b.emb_distances(Q, X)
+        ti, tv = b.emb_topk_min(D, 50)
+        assert torch.equal(ci, ti) and torch.equal(cd, tv)
+        ri, rs, rc = db.rerank(lab_d, ci, 10)
+        assert torch.equal(idx, ri) and torch.equal(score, rs) and torch.equal(counts, rc)

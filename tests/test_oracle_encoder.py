@@ -81,3 +81,30 @@ def test_mse_gradient_closed_form():
     b = torch.randn(3, 5, dtype=torch.float64)
     E.mse(a, b).backward()
     assert torch.allclose(a.grad, 2 * (a.detach() - b) / a.numel(), rtol=0, atol=1e-15)
+
+
+def test_e4m3_format_pins():
+    # Values fixed by the OCP e4m3 definition (bias 7, 3 mantissa bits, max 448, no inf).
+    assert E.e4m3_decode(np.array([0x38, 0x40, 0x7E, 0x08, 0x01, 0xC0, 0x00])).tolist() == \
+        [1.0, 2.0, 448.0, 2.0 ** -6, 2.0 ** -9, -2.0, 0.0]
+    assert np.isnan(E.e4m3_decode(np.array([0x7F]))[0])
+    codes = np.array([c for c in range(256) if (c & 0x7F) != 0x7F], dtype=np.uint8)
+    # Every finite code round-trips (signed zeros included).
+    assert np.array_equal(E.e4m3_encode(E.e4m3_decode(codes)), codes)
+    # Ties go to the even mantissa; saturation at 448; tiny values keep their sign at zero.
+    got = E.e4m3_encode(np.array([1.0625, 1.1875, 460.0, 1e6, -1e6, 2.0 ** -10, -2.0 ** -10]))
+    assert got.tolist() == [0x38, 0x3A, 0x7E, 0x7E, 0xFE, 0x00, 0x80]
+    # Monotone and nearest: decoded value within half a step of the input.
+    x = np.linspace(-448, 448, 4001)
+    dec = E.e4m3_decode(E.e4m3_encode(x))
+    assert np.all(np.diff(dec) >= 0)
+    step = np.maximum(np.abs(dec) * 2.0 ** -3, 2.0 ** -9)
+    assert np.all(np.abs(dec - x) <= step / 2 + 1e-12)
+
+
+def test_bf16_encode_pins():
+    assert E.bf16_encode(np.array([1.0, -2.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8], np.float32)).tolist() == \
+        [0x3F80, 0xC000, 0x3F80, 0x3F82]
+    x = np.random.default_rng(0).standard_normal(1000).astype(np.float32)
+    d = E.bf16_decode(E.bf16_encode(x))
+    assert np.all(np.abs(d - x) <= np.abs(x) * 2.0 ** -8)
