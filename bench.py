@@ -39,10 +39,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["full", "small", "batch"], default="full",
+    ap.add_argument("--workload", choices=["full", "small", "batch", "embed", "train"],
+                    default="full",
                     help="full: 50,000 x 128^3 exact scan, 1 query (the headline); small: "
-                         "1,000 x 64^3; batch: 256 box-restricted queries per launch on the "
-                         "full database")
+                         "1,000 x 64^3; batch: 256 box-restricted queries per launch; embed: "
+                         "1,024 held-out queries through encoder + BF16 MFMA distances + "
+                         "top-100 + exact rerank; train: encoder training steps (batch 32)")
+    ap.add_argument("--train-steps", type=int, default=300,
+                    help="encoder training steps before the embed workload")
+    ap.add_argument("--embed-nq", type=int, default=1024)
     ap.add_argument("--nq", type=int, default=256, help="queries per launch (batch workload)")
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -189,6 +194,191 @@ def bench_batch(args, db, gen, n, build_s) -> int:
     return 0 if ok else 1
 
 
+FP32_VECTOR_PEAK = 157.3e12      # MI355X vector FP32 (packed) FLOP/s
+BF16_MFMA_PEAK = 2.5e15          # MI355X dense BF16 matrix FLOP/s
+
+
+def model_macs(model) -> int:
+    """Multiply-accumulates of one forward pass of the autoencoder for one sample."""
+    g, c = model.grid, model.channels
+    macs = 0
+    for i in range(4):
+        out = (g >> (i + 1)) ** 3
+        macs += out * c[i + 1] * c[i] * 27          # encoder convolution i
+        macs += out * c[i + 1] * c[i] * 27          # its mirrored transposed convolution
+    macs += 2 * model.flat * model.latent           # encoder and decoder linear layers
+    return macs
+
+
+def train_encoder(model, db, n: int, steps: int, batch: int, seed: int = 7):
+    import torch
+    from paper_2205_04550_amd import nn
+    opt = nn.Adam(model, lr=1e-3)
+    g = torch.Generator().manual_seed(seed)
+    losses = []
+    for _ in range(steps):
+        idx = torch.randint(0, n, (batch,), generator=g).to(torch.int32).cuda()
+        losses.append(nn.train_step(model, opt, nn.meanpool_db(db, idx)))
+    return opt, [float(l) for l in losses]
+
+
+def bench_train(args, db, gen, n, build_s) -> int:
+    """Encoder training: batch 32 of mean-pooled 2 x 64^3 inputs; forward, backward, Adam."""
+    import torch
+    from paper_2205_04550_amd import nn
+    batch = 32
+    model = nn.AutoEncoder(grid=gen.nx // 2, latent=512, seed=0)
+    opt = nn.Adam(model, lr=1e-3)
+    g = torch.Generator().manual_seed(7)
+    idx_all = [torch.randint(0, n, (batch,), generator=g).to(torch.int32).cuda()
+               for _ in range(args.warmup + args.steps)]
+    losses = []
+    for i in range(args.warmup):
+        losses.append(nn.train_step(model, opt, nn.meanpool_db(db, idx_all[i])))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        losses.append(nn.train_step(model, opt, nn.meanpool_db(db, idx_all[args.warmup + i])))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    flop = 3 * 2 * model_macs(model) * batch    # forward + backward (about twice the forward)
+    losses = [float(l) for l in losses]
+    log(f"{ms:.2f} ms per training step of {batch}; loss {losses[0]:.5f} -> {losses[-1]:.5f}")
+    line = {
+        "metric": "encoder training samples/sec", "value": batch / (ms * 1e-3),
+        "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (bf16 weights)", "data": "synthetic",
+        "config": {"workload": f"autoencoder training, batch {batch} x 2 x {model.grid}^3, "
+                               f"latent 512, {model.n_params()} parameters, Adam",
+                   "n_db": n},
+        "roofline": {"bound": "alu", "achieved": flop / (ms * 1e-3) / 1e12,
+                     "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": flop / (ms * 1e-3) / FP32_VECTOR_PEAK, "traffic": None,
+                     "kernel": "whole step (direct convolutions on the vector ALUs)",
+                     "algorithmic_flop_per_step": flop},
+        "loss_first_last": [losses[0], losses[-1]],
+        "cpu_baseline": None, "build_s": build_s,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_embed(args, db, gen, n, build_s) -> int:
+    """Held-out queries through encoder, BF16 MFMA distances, top-100 and exact rerank."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2205_04550_amd import binding as B, nn
+    nq, n_cand, k = args.embed_nq, 100, 15
+    model = nn.AutoEncoder(grid=gen.nx // 2, latent=512, seed=0)
+    log(f"training the encoder for {args.train_steps} steps of 32")
+    t0 = time.perf_counter()
+    _, losses = train_encoder(model, db, n, args.train_steps, 32)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log(f"trained in {train_s:.1f} s, loss {losses[0]:.5f} -> {losses[-1]:.5f}")
+    t0 = time.perf_counter()
+    lat = torch.empty((n, model.latent), dtype=torch.float32, device="cuda")
+    with torch.no_grad():
+        for s in range(0, n, 500):
+            idx = torch.arange(s, min(n, s + 500), dtype=torch.int32, device="cuda")
+            lat[s:s + idx.numel()] = model.encode(nn.meanpool_db(db, idx))
+    X = B.Latents(lat, B.EMB_BF16)
+    torch.cuda.synchronize()
+    encode_db_s = time.perf_counter() - t0
+    log(f"encoded {n} entries in {encode_db_s:.1f} s; making {nq} held-out queries")
+    labels, _ = synth.make_queries(gen, n, nq, synth.HELDOUT_SEED, held_out_seed=synth.HELDOUT_SEED)
+    lab_d = torch.from_numpy(labels).cuda()
+    del labels
+    # Exact top-k of every query (the ground truth), one exact scan per query.
+    ws1 = db.workspace(1, k)
+    ex_idx = torch.empty((nq, k), dtype=torch.int32, device="cuda")
+    ex_out = (torch.empty(k, dtype=torch.int32, device="cuda"),
+              torch.empty(k, dtype=torch.float64, device="cuda"), None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q in range(nq):
+        db.query(lab_d[q], k, out=ex_out, ws=ws1)
+        ex_idx[q].copy_(ex_out[0])
+    torch.cuda.synchronize()
+    exact_ms_per_query = (time.perf_counter() - t0) * 1e3 / nq
+    log(f"exact scan: {exact_ms_per_query:.3f} ms per query")
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    stage = np.zeros(4)
+
+    def step(timed: bool):
+        if timed:
+            ev[0].record()
+        with torch.no_grad():
+            ql = model.encode(nn.meanpool_labels(lab_d))
+        Q = B.Latents(ql, B.EMB_BF16)
+        if timed:
+            ev[1].record()
+        D = B.emb_distances(Q, X, out=Dbuf)
+        if timed:
+            ev[2].record()
+        ci, cd = B.emb_topk_min(D, n_cand)
+        if timed:
+            ev[3].record()
+        out = db.rerank(lab_d, ci, k)
+        if timed:
+            ev[4].record()
+        return out, ci
+
+    Dbuf = torch.empty((nq, n), dtype=torch.float32, device="cuda")
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        (idx, score, counts), ci = step(True)
+        torch.cuda.synchronize()
+        stage += [ev[i].elapsed_time(ev[i + 1]) for i in range(4)]
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    stage /= args.steps
+    got = idx.cpu().numpy()
+    ex = ex_idx.cpu().numpy()
+    recall10 = float(np.mean([len(set(got[q, :10]) & set(ex[q, :10])) / 10 for q in range(nq)]))
+    top_n = {f"top{t}": float(np.mean([ex[q, 0] in got[q, :t] for q in range(nq)])) for t in (1, 5, 15)}
+    cand_recall = float(np.mean([len(set(ci[q].cpu().numpy()) & set(ex[q, :10])) / 10
+                                 for q in range(min(nq, 256))]))
+    gemm_flop = 2.0 * nq * n * model.latent
+    names = ["encode queries", "distance GEMM (BF16 MFMA)", "top-100 select", "exact rerank"]
+    dom = int(np.argmax(stage))
+    log(f"{ms:.2f} ms per {nq} queries ({nq / (ms * 1e-3):.0f} q/s); stages "
+        + ", ".join(f"{a} {b:.3f} ms" for a, b in zip(names, stage))
+        + f"; recall@10 {recall10:.3f}; {top_n}; speed-up vs exact "
+          f"{exact_ms_per_query * nq / ms:.0f}x")
+    line = {
+        "metric": "queries/sec at recall@10", "value": nq / (ms * 1e-3), "unit": "queries/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"embedding search, {nq} held-out queries x {n} latents (512-d "
+                               f"BF16), top-{n_cand} by MFMA distance, exact 128^3 Dice rerank, "
+                               f"top-{k}", "n_db": n, "nq": nq, "n_cand": n_cand,
+                   "train_steps": args.train_steps},
+        "recall_at_10": recall10, **top_n, "candidate_recall_at_10": cand_recall,
+        "speedup_vs_exact_scan": exact_ms_per_query * nq / ms,
+        "exact_ms_per_query": exact_ms_per_query,
+        "stages_ms": dict(zip(names, stage.tolist())),
+        "roofline": {"bound": "mfma", "achieved": gemm_flop / (stage[1] * 1e-3) / 1e12,
+                     "peak": BF16_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": gemm_flop / (stage[1] * 1e-3) / BF16_MFMA_PEAK, "traffic": None,
+                     "kernel": "dist_bf16_kernel", "kernel_avg_ms": stage[1],
+                     "dominant_stage": names[dom]},
+        "cpu_baseline": None, "build_s": build_s, "train_s": train_s,
+        "encode_db_s": encode_db_s, "train_loss_first_last": [losses[0], losses[-1]],
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main() -> int:
     args = parse()
     if args.gpus != 1:
@@ -230,6 +420,10 @@ def main() -> int:
 
     if args.workload == "batch":
         return bench_batch(args, db, gen, n, build_s)
+    if args.workload == "train":
+        return bench_train(args, db, gen, n, build_s)
+    if args.workload == "embed":
+        return bench_embed(args, db, gen, n, build_s)
 
     src = synth.query_source(n, synth.QUERY_SEED, 0)
     q = gen.query(src, t_lo, t_hi, synth.QUERY_SEED, 0)

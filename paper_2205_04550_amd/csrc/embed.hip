@@ -505,26 +505,55 @@ __global__ void __launch_bounds__(256) rerank_kernel(const uint32_t *__restrict_
     const int nyr = y1 - y0;
     const int nr = (z1 - z0) * nyr;
     const uint32_t A0 = acnt[2 * q], A1 = acnt[2 * q + 1];
-    for (int c = wave; c < nc; c += nwaves) {
-        const int32_t e = cand[(int64_t)q * nc + c];
-        const uint32_t *D0 = planes + (int64_t)e * 2 * Wp, *D1 = D0 + Wp;
-        uint32_t i0 = 0, i1 = 0;
+    // Candidates in groups of kRC per wave: each query row is loaded once per group.
+    constexpr int kRC = 4;
+    for (int c0 = wave * kRC; c0 < nc; c0 += nwaves * kRC) {
+        const uint32_t *D0[kRC], *D1[kRC];
+#pragma unroll
+        for (int j = 0; j < kRC; ++j) {
+            const int c = min(c0 + j, nc - 1);          // a repeated candidate is discarded
+            const int32_t e = cand[(int64_t)q * nc + c];
+            D0[j] = planes + (int64_t)e * 2 * Wp;
+            D1[j] = D0[j] + Wp;
+        }
+        uint32_t i0[kRC], i1[kRC];
+#pragma unroll
+        for (int j = 0; j < kRC; ++j) i0[j] = i1[j] = 0;
         for (int r = lane; r < nr; r += 64) {
             const int zr = r / nyr;
             const int base = ((z0 + zr) * ny + (y0 + r - zr * nyr)) * nxw;
-            for (int w = 0; w < nxw; ++w) {
-                i0 += popc(Q0[base + w] & D0[base + w]);
-                i1 += popc(Q1[base + w] & D1[base + w]);
+            if (nxw == 4) {
+                const u32x4 qa = *reinterpret_cast<const u32x4 *>(Q0 + base);
+                const u32x4 qb = *reinterpret_cast<const u32x4 *>(Q1 + base);
+#pragma unroll
+                for (int j = 0; j < kRC; ++j) {
+                    i0[j] += popc_and4(qa, *reinterpret_cast<const u32x4 *>(D0[j] + base));
+                    i1[j] += popc_and4(qb, *reinterpret_cast<const u32x4 *>(D1[j] + base));
+                }
+            } else {
+                for (int w = 0; w < nxw; ++w) {
+                    const uint32_t qa = Q0[base + w], qb = Q1[base + w];
+#pragma unroll
+                    for (int j = 0; j < kRC; ++j) {
+                        i0[j] += popc(qa & D0[j][base + w]);
+                        i1[j] += popc(qb & D1[j][base + w]);
+                    }
+                }
             }
         }
-        i0 = wave_sum(i0);
-        i1 = wave_sum(i1);
-        if (lane == 0) {
-            const double s = dice(i1, A1, popcnt[2 * (int64_t)e + 1]) + dice(i0, A0, popcnt[2 * (int64_t)e]);
-            ks[c] = (uint64_t)__double_as_longlong(s);
-            ki[c] = e;
-            kI[c][0] = i0;
-            kI[c][1] = i1;
+#pragma unroll
+        for (int j = 0; j < kRC; ++j) {
+            const uint32_t a0 = wave_sum(i0[j]), a1 = wave_sum(i1[j]);
+            const int c = c0 + j;
+            if (lane == 0 && c < nc) {
+                const int32_t e = cand[(int64_t)q * nc + c];
+                const double sc = dice(a1, A1, popcnt[2 * (int64_t)e + 1]) +
+                                  dice(a0, A0, popcnt[2 * (int64_t)e]);
+                ks[c] = (uint64_t)__double_as_longlong(sc);
+                ki[c] = e;
+                kI[c][0] = a0;
+                kI[c][1] = a1;
+            }
         }
     }
     int P = 1;

@@ -36,7 +36,31 @@ __device__ __forceinline__ T wsum(T v)
 
 // ---- convolution, kernel 3, stride 2, padding 1 ------------------------------------------
 
-// grid (ceil(OD*OH*OW / 256), Co, B)
+constexpr int kCB = 8;   // output channels per thread: each input tap is loaded once for all
+constexpr int kCC = 8;   // channels of the other side staged in LDS per step
+
+// Weights of kCB output channels x kCC input channels, laid out [cc][tap][c] so that
+// one tap's kCB weights are contiguous (vector reads, same address across the wave).
+// `other` = the summed-over channel index base, `own` = this block's channel base.
+template <class T, class WT>
+__device__ __forceinline__ void stage_weights(T *wsh, const WT *__restrict__ Wt, int Ci, int Co,
+                                              int own0, int nown, int other0, int nother,
+                                              bool own_is_co)
+{
+    for (int t = threadIdx.x; t < kCC * 27 * kCB; t += blockDim.x) {
+        const int c = t % kCB, tap = (t / kCB) % 27, cc = t / (kCB * 27);
+        T v = T(0);
+        if (c < nown && cc < nother) {
+            const int own = own0 + c, oth = other0 + cc;
+            const int co = own_is_co ? own : oth;
+            const int ci = own_is_co ? oth : own;
+            v = (T)ld_w(Wt, ((int64_t)co * Ci + ci) * 27 + tap);
+        }
+        wsh[t] = v;
+    }
+}
+
+// grid (ceil(OD*OH*OW / 256), ceil(Co / kCB), B)
 template <class T, class WT>
 __global__ void __launch_bounds__(256) conv_fwd_kernel(int Ci, int Co, int D, int H, int W,
                                                        const T *__restrict__ X,
@@ -44,39 +68,60 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(int Ci, int Co, int D, in
                                                        const T *__restrict__ bias, int relu,
                                                        T *__restrict__ Y)
 {
+    __shared__ T wsh[kCC * 27 * kCB];
     const int OD = D / 2, OH = H / 2, OW = W / 2;
     const int osp = OD * OH * OW;
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    const int co = blockIdx.y, b = blockIdx.z;
-    if (o >= osp) return;
-    const int ow = o % OW, oh = (o / OW) % OH, od = o / (OW * OH);
+    const bool active = o < osp;
+    const int oo = active ? o : 0;
+    const int co0 = blockIdx.y * kCB, b = blockIdx.z;
+    const int nco = min(kCB, Co - co0);
+    const int ow = oo % OW, oh = (oo / OW) % OH, od = oo / (OW * OH);
     const int64_t isp = (int64_t)D * H * W;
-    T acc = bias ? bias[co] : T(0);
-    for (int ci = 0; ci < Ci; ++ci) {
-        const T *x = X + ((int64_t)b * Ci + ci) * isp;
-        const WT *w = Wt + ((int64_t)co * Ci + ci) * 27;
+    T acc[kCB];
 #pragma unroll
-        for (int kd = 0; kd < 3; ++kd) {
-            const int id = 2 * od + kd - 1;
-            if (id < 0 || id >= D) continue;
+    for (int c = 0; c < kCB; ++c) acc[c] = bias ? bias[min(co0 + c, Co - 1)] : T(0);
+    for (int ci0 = 0; ci0 < Ci; ci0 += kCC) {
+        const int ncc = min(kCC, Ci - ci0);
+        __syncthreads();
+        stage_weights(wsh, Wt, Ci, Co, co0, nco, ci0, ncc, true);
+        __syncthreads();
+        for (int cc = 0; cc < ncc; ++cc) {
+            const T *x = X + ((int64_t)b * Ci + ci0 + cc) * isp;
+            const T *w = wsh + cc * 27 * kCB;
+            // Not unrolled over kd: keeps the live weights to one 3x3 plane (9 x kCB).
+#pragma unroll 1
+            for (int kd = 0; kd < 3; ++kd) {
+                const int id = 2 * od + kd - 1;
 #pragma unroll
-            for (int kh = 0; kh < 3; ++kh) {
-                const int ih = 2 * oh + kh - 1;
-                if (ih < 0 || ih >= H) continue;
+                for (int kh = 0; kh < 3; ++kh) {
+                    const int ih = 2 * oh + kh - 1;
 #pragma unroll
-                for (int kw = 0; kw < 3; ++kw) {
-                    const int iw = 2 * ow + kw - 1;
-                    if (iw < 0 || iw >= W) continue;
-                    acc += (T)ld_w(w, kd * 9 + kh * 3 + kw) * x[((int64_t)id * H + ih) * W + iw];
+                    for (int kw = 0; kw < 3; ++kw) {
+                        const int iw = 2 * ow + kw - 1;
+                        const bool in = id >= 0 && id < D && ih >= 0 && ih < H && iw >= 0 && iw < W;
+                        const int64_t off = in ? ((int64_t)id * H + ih) * W + iw : 0;
+                        const T xv = in ? x[off] : T(0);
+                        const T *wt = w + (kd * 9 + kh * 3 + kw) * kCB;
+#pragma unroll
+                        for (int c = 0; c < kCB; ++c) acc[c] += wt[c] * xv;
+                    }
                 }
             }
         }
     }
-    if (relu && acc < T(0)) acc = T(0);
-    Y[((int64_t)b * Co + co) * osp + o] = acc;
+    if (!active) return;
+#pragma unroll
+    for (int c = 0; c < kCB; ++c) {
+        if (c >= nco) break;
+        T v = acc[c];
+        if (relu && v < T(0)) v = T(0);
+        Y[((int64_t)b * Co + co0 + c) * osp + o] = v;
+    }
 }
 
-// Adjoint map: grid (ceil(D*H*W / 256), Ci, B); one thread per input voxel.
+// Adjoint map: grid (ceil(D*H*W / 256), ceil(Ci / kCB), B); one thread per input voxel
+// and kCB input channels (each dY tap is loaded once for all of them).
 template <class T, class WT>
 __global__ void __launch_bounds__(256) conv_bwd_data_kernel(int Ci, int Co, int D, int H, int W,
                                                             const T *__restrict__ dY,
@@ -84,37 +129,56 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(int Ci, int Co, int 
                                                             const T *__restrict__ bias, int relu,
                                                             T *__restrict__ dX)
 {
+    __shared__ T wsh[kCC * 27 * kCB];
     const int OD = D / 2, OH = H / 2, OW = W / 2;
     const int osp = OD * OH * OW;
     const int isp = D * H * W;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int ci = blockIdx.y, b = blockIdx.z;
-    if (i >= isp) return;
-    const int iw = i % W, ih = (i / W) % H, id = i / (W * H);
-    T acc = bias ? bias[ci] : T(0);
-    for (int co = 0; co < Co; ++co) {
-        const T *dy = dY + ((int64_t)b * Co + co) * osp;
-        const WT *w = Wt + ((int64_t)co * Ci + ci) * 27;
+    const bool active = i < isp;
+    const int ii = active ? i : 0;
+    const int ci0 = blockIdx.y * kCB, b = blockIdx.z;
+    const int nci = min(kCB, Ci - ci0);
+    const int iw = ii % W, ih = (ii / W) % H, id = ii / (W * H);
+    T acc[kCB];
 #pragma unroll
-        for (int kd = 0; kd < 3; ++kd) {
-            const int td = id + 1 - kd;
-            if (td < 0 || (td & 1) || (td >> 1) >= OD) continue;
+    for (int c = 0; c < kCB; ++c) acc[c] = bias ? bias[min(ci0 + c, Ci - 1)] : T(0);
+    for (int co0 = 0; co0 < Co; co0 += kCC) {
+        const int ncc = min(kCC, Co - co0);
+        __syncthreads();
+        stage_weights(wsh, Wt, Ci, Co, ci0, nci, co0, ncc, false);
+        __syncthreads();
+        for (int cc = 0; cc < ncc; ++cc) {
+            const T *dy = dY + ((int64_t)b * Co + co0 + cc) * osp;
+            const T *w = wsh + cc * 27 * kCB;
 #pragma unroll
-            for (int kh = 0; kh < 3; ++kh) {
-                const int th = ih + 1 - kh;
-                if (th < 0 || (th & 1) || (th >> 1) >= OH) continue;
+            for (int kd = 0; kd < 3; ++kd) {
+                const int td = id + 1 - kd;
+                if (td < 0 || (td & 1) || (td >> 1) >= OD) continue;
 #pragma unroll
-                for (int kw = 0; kw < 3; ++kw) {
-                    const int tw = iw + 1 - kw;
-                    if (tw < 0 || (tw & 1) || (tw >> 1) >= OW) continue;
-                    acc += (T)ld_w(w, kd * 9 + kh * 3 + kw) *
-                           dy[((td >> 1) * OH + (th >> 1)) * OW + (tw >> 1)];
+                for (int kh = 0; kh < 3; ++kh) {
+                    const int th = ih + 1 - kh;
+                    if (th < 0 || (th & 1) || (th >> 1) >= OH) continue;
+#pragma unroll
+                    for (int kw = 0; kw < 3; ++kw) {
+                        const int tw = iw + 1 - kw;
+                        if (tw < 0 || (tw & 1) || (tw >> 1) >= OW) continue;
+                        const T g = dy[((td >> 1) * OH + (th >> 1)) * OW + (tw >> 1)];
+                        const T *wt = w + (kd * 9 + kh * 3 + kw) * kCB;
+#pragma unroll
+                        for (int c = 0; c < kCB; ++c) acc[c] += wt[c] * g;
+                    }
                 }
             }
         }
     }
-    if (relu && acc < T(0)) acc = T(0);
-    dX[((int64_t)b * Ci + ci) * isp + i] = acc;
+    if (!active) return;
+#pragma unroll
+    for (int c = 0; c < kCB; ++c) {
+        if (c >= nci) break;
+        T v = acc[c];
+        if (relu && v < T(0)) v = T(0);
+        dX[((int64_t)b * Ci + ci0 + c) * isp + i] = v;
+    }
 }
 
 constexpr int kWgChunk = 4096;  // (batch, output voxel) positions per weight-gradient block
@@ -505,7 +569,7 @@ int nn_conv3d_s2_fwd(int dtype, int B, int Ci, int Co, int D, int H, int W, cons
         return tdb_set_error(DB_EINVAL, "nn_conv3d_s2_fwd: bad arguments");
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const int osp = (D / 2) * (H / 2) * (W / 2);
-    const dim3 grid((osp + 255) / 256, Co, B);
+    const dim3 grid((osp + 255) / 256, (Co + kCB - 1) / kCB, B);
     if (pair == 0)
         hipLaunchKernelGGL((conv_fwd_kernel<float, uint16_t>), grid, dim3(256), 0, s, Ci, Co, D, H,
                            W, (const float *)X, (const uint16_t *)Wt, (const float *)bias, relu,
@@ -530,7 +594,7 @@ int nn_conv3d_s2_bwd_data(int dtype, int B, int Ci, int Co, int D, int H, int W,
         return tdb_set_error(DB_EINVAL, "nn_conv3d_s2_bwd_data: bad arguments");
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const int isp = D * H * W;
-    const dim3 grid((isp + 255) / 256, Ci, B);
+    const dim3 grid((isp + 255) / 256, (Ci + kCB - 1) / kCB, B);
     if (pair == 0)
         hipLaunchKernelGGL((conv_bwd_data_kernel<float, uint16_t>), grid, dim3(256), 0, s, Ci, Co,
                            D, H, W, (const float *)dY, (const uint16_t *)Wt, (const float *)bias,

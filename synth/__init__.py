@@ -175,7 +175,8 @@ def make_queries(cfg: GenConfig, n_db: int, nq: int, query_seed: int, t_lo: floa
     """
     labs = np.empty((nq, cfg.nz, cfg.ny, cfg.nx), dtype=np.uint8)
     srcs = np.empty(nq, dtype=np.int64)
-    for q in range(nq):
+
+    def one(q):
         if held_out_seed is None:
             s = query_source(n_db, query_seed, q)
             labs[q] = cfg.query(s, t_lo, t_hi, query_seed, q, flip_frac)
@@ -183,6 +184,15 @@ def make_queries(cfg: GenConfig, n_db: int, nq: int, query_seed: int, t_lo: floa
             s = q
             labs[q] = cfg.query(s, t_lo, t_hi, query_seed, q, flip_frac, seed=held_out_seed)
         srcs[q] = s
+
+    # Each query is independent and the C generator releases the GIL.
+    if nq > 4:
+        import concurrent.futures as cf
+        with cf.ThreadPoolExecutor(max_workers=default_threads()) as ex:
+            list(ex.map(one, range(nq)))
+    else:
+        for q in range(nq):
+            one(q)
     return labs, srcs
 
 
