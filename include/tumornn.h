@@ -83,8 +83,11 @@ int nn_linear_bwd_data(int dtype, int B, int In, int Out, const void *dY, const 
 int nn_linear_bwd_weight(int dtype, int B, int In, int Out, const void *X, const void *dY,
                          void *dWt, void *dbias, void *stream);
 
-/* out[c] = sum_{b,s} X[b][c][s] for X [B][C][S] (a bias gradient; fixed order). */
-int nn_channel_sum(int dtype, int B, int C, int64_t S, const void *X, void *out, void *stream);
+/* out[c] = sum_{b,s} X[b][c][s] for X [B][C][S] (a bias gradient); two fixed-order
+ * stages through ws of nn_channel_sum_ws_bytes bytes. */
+size_t nn_channel_sum_ws_bytes(int dtype, int B, int C, int64_t S);
+int nn_channel_sum(int dtype, int B, int C, int64_t S, const void *X, void *out, void *ws,
+                   size_t ws_bytes, void *stream);
 
 /* dX = dY where Y > 0 else 0 (n elements). */
 int nn_relu_bwd(int dtype, int64_t n, const void *Y, const void *dY, void *dX, void *stream);

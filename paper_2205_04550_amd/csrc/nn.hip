@@ -260,39 +260,6 @@ __global__ void conv_bwd_weight_final(int nchunks, int Ci, int Co, const T *__re
 
 // ---- linear ---------------------------------------------------------------------------------
 
-template <class T, class WT>
-__global__ void __launch_bounds__(256) linear_fwd_kernel(int B, int In, int Out,
-                                                         const T *__restrict__ X,
-                                                         const WT *__restrict__ Wt,
-                                                         const T *__restrict__ bias, int relu,
-                                                         T *__restrict__ Y)
-{
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
-    if (j >= Out) return;
-    const T *x = X + (int64_t)b * In;
-    const WT *w = Wt + (int64_t)j * In;
-    T acc = bias ? bias[j] : T(0);
-    for (int i = 0; i < In; ++i) acc += (T)ld_w(w, i) * x[i];
-    if (relu && acc < T(0)) acc = T(0);
-    Y[(int64_t)b * Out + j] = acc;
-}
-
-template <class T, class WT>
-__global__ void __launch_bounds__(256) linear_bwd_data_kernel(int B, int In, int Out,
-                                                              const T *__restrict__ dY,
-                                                              const WT *__restrict__ Wt,
-                                                              T *__restrict__ dX)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
-    if (i >= In) return;
-    const T *dy = dY + (int64_t)b * Out;
-    T acc = T(0);
-    for (int j = 0; j < Out; ++j) acc += (T)ld_w(Wt, (int64_t)j * In + i) * dy[j];
-    dX[(int64_t)b * In + i] = acc;
-}
-
 template <class T>
 __global__ void __launch_bounds__(256) linear_bwd_weight_kernel(int B, int In, int Out,
                                                                 const T *__restrict__ X,
@@ -313,23 +280,114 @@ __global__ void __launch_bounds__(256) linear_bwd_weight_kernel(int B, int In, i
     }
 }
 
-// out[c] = sum over (b, s) of X[b][c][s]: one block per channel, fixed reduction order.
+// out[c] = sum over (b, s) of X[b][c][s], in two fixed-order stages:
+// grid (chunks, C) partial sums over kCsChunk consecutive (b, s) positions, then
+// one thread per channel adds the chunks in order.
+constexpr int kCsChunk = 16384;
+
 template <class T>
-__global__ void __launch_bounds__(256) channel_sum_kernel(int B, int C, int64_t S,
-                                                          const T *__restrict__ X,
-                                                          T *__restrict__ out)
+__global__ void __launch_bounds__(256) channel_sum_partial(int B, int C, int64_t S,
+                                                           const T *__restrict__ X,
+                                                           T *__restrict__ partial)
 {
     __shared__ T red[4];
-    const int c = blockIdx.x;
+    const int c = blockIdx.y;
+    const int64_t P = (int64_t)B * S;
+    const int64_t p0 = (int64_t)blockIdx.x * kCsChunk;
+    const int64_t p1 = p0 + kCsChunk < P ? p0 + kCsChunk : P;
     T acc = T(0);
-    for (int b = 0; b < B; ++b) {
-        const T *x = X + ((int64_t)b * C + c) * S;
-        for (int64_t i = threadIdx.x; i < S; i += blockDim.x) acc += x[i];
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const int64_t b = p / S, sidx = p - b * S;
+        acc += X[(b * C + c) * S + sidx];
     }
     acc = wsum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) out[c] = ((red[0] + red[1]) + red[2]) + red[3];
+    if (threadIdx.x == 0)
+        partial[(int64_t)c * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+template <class T>
+__global__ void channel_sum_final(int C, int nchunks, const T *__restrict__ partial,
+                                  T *__restrict__ out)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    T s = T(0);
+    for (int i = 0; i < nchunks; ++i) s += partial[(int64_t)c * nchunks + i];
+    out[c] = s;
+}
+
+// ---- tiled GEMM for the linear layers (vector ALUs) ------------------------------------------
+//
+// C[m][n] = act(bias[n] + sum_k A[m][k] * B(k, n)), A row-major [M][K]; B is either
+// [N][K] (K contiguous: forward, x W^T) or [K][N] (N contiguous: input gradient,
+// dY W). 256 threads, tile 32 x 64 x 32 staged in LDS; each thread 2 x 4 outputs.
+constexpr int kLM = 32, kLN = 64, kLK = 32;
+
+template <class T, class WT, bool B_KN>
+__global__ void __launch_bounds__(256) linear_gemm_kernel(int M, int N, int K,
+                                                          const T *__restrict__ A,
+                                                          const WT *__restrict__ Bm,
+                                                          const T *__restrict__ bias, int relu,
+                                                          T *__restrict__ C)
+{
+    __shared__ T As[kLK][kLM + 1];
+    __shared__ T Bs[kLK][kLN + 1];
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int m0 = blockIdx.y * kLM, n0 = blockIdx.x * kLN;
+    T acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+    for (int k0 = 0; k0 < K; k0 += kLK) {
+        for (int t = threadIdx.x; t < kLM * kLK; t += blockDim.x) {
+            const int mm = t / kLK, kk = t % kLK;
+            const int m = m0 + mm, k = k0 + kk;
+            As[kk][mm] = (m < M && k < K) ? A[(int64_t)(m < M ? m : 0) * K + (k < K ? k : 0)] : T(0);
+        }
+        for (int t = threadIdx.x; t < kLN * kLK; t += blockDim.x) {
+            int nn, kk;
+            if (B_KN) {          // N contiguous in memory
+                nn = t % kLN;
+                kk = t / kLN;
+            } else {             // K contiguous in memory
+                kk = t % kLK;
+                nn = t / kLK;
+            }
+            const int n = n0 + nn, k = k0 + kk;
+            const bool in = n < N && k < K;
+            const int nc = in ? n : 0, kc = in ? k : 0;
+            const T v = (T)ld_w(Bm, B_KN ? (int64_t)kc * N + nc : (int64_t)nc * K + kc);
+            Bs[kk][nn] = in ? v : T(0);
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < kLK; ++kk) {
+            const T a0 = As[kk][ty * 2], a1 = As[kk][ty * 2 + 1];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const T bv = Bs[kk][tx + 16 * j];
+                acc[0][j] += a0 * bv;
+                acc[1][j] += a1 * bv;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int m = m0 + ty * 2 + i;
+        if (m >= M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = n0 + tx + 16 * j;
+            if (n >= N) continue;
+            T v = acc[i][j] + (bias ? bias[n] : T(0));
+            if (relu && v < T(0)) v = T(0);
+            C[(int64_t)m * N + n] = v;
+        }
+    }
 }
 
 // ---- elementwise, loss, optimiser ---------------------------------------------------------
@@ -654,19 +712,19 @@ int nn_linear_fwd(int dtype, int B, int In, int Out, const void *X, const void *
     if (pair < 0 || B <= 0 || In <= 0 || Out <= 0 || B > 65535 || !X || !Wt || !Y)
         return tdb_set_error(DB_EINVAL, "nn_linear_fwd: bad arguments");
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    const dim3 grid((Out + 255) / 256, B);
+    const dim3 grid((Out + kLN - 1) / kLN, (B + kLM - 1) / kLM);
     if (pair == 0)
-        hipLaunchKernelGGL((linear_fwd_kernel<float, uint16_t>), grid, dim3(256), 0, s, B, In, Out,
-                           (const float *)X, (const uint16_t *)Wt, (const float *)bias, relu,
-                           (float *)Y);
+        hipLaunchKernelGGL((linear_gemm_kernel<float, uint16_t, false>), grid, dim3(256), 0, s, B,
+                           Out, In, (const float *)X, (const uint16_t *)Wt, (const float *)bias,
+                           relu, (float *)Y);
     else if (pair == 1)
-        hipLaunchKernelGGL((linear_fwd_kernel<float, float>), grid, dim3(256), 0, s, B, In, Out,
-                           (const float *)X, (const float *)Wt, (const float *)bias, relu,
+        hipLaunchKernelGGL((linear_gemm_kernel<float, float, false>), grid, dim3(256), 0, s, B, Out,
+                           In, (const float *)X, (const float *)Wt, (const float *)bias, relu,
                            (float *)Y);
     else
-        hipLaunchKernelGGL((linear_fwd_kernel<double, double>), grid, dim3(256), 0, s, B, In, Out,
-                           (const double *)X, (const double *)Wt, (const double *)bias, relu,
-                           (double *)Y);
+        hipLaunchKernelGGL((linear_gemm_kernel<double, double, false>), grid, dim3(256), 0, s, B,
+                           Out, In, (const double *)X, (const double *)Wt, (const double *)bias,
+                           relu, (double *)Y);
     return launched("nn_linear_fwd");
 }
 
@@ -677,16 +735,19 @@ int nn_linear_bwd_data(int dtype, int B, int In, int Out, const void *dY, const 
     if (pair < 0 || B <= 0 || In <= 0 || Out <= 0 || B > 65535 || !dY || !Wt || !dX)
         return tdb_set_error(DB_EINVAL, "nn_linear_bwd_data: bad arguments");
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    const dim3 grid((In + 255) / 256, B);
+    const dim3 grid((In + kLN - 1) / kLN, (B + kLM - 1) / kLM);
     if (pair == 0)
-        hipLaunchKernelGGL((linear_bwd_data_kernel<float, uint16_t>), grid, dim3(256), 0, s, B, In,
-                           Out, (const float *)dY, (const uint16_t *)Wt, (float *)dX);
+        hipLaunchKernelGGL((linear_gemm_kernel<float, uint16_t, true>), grid, dim3(256), 0, s, B, In,
+                           Out, (const float *)dY, (const uint16_t *)Wt, (const float *)nullptr, 0,
+                           (float *)dX);
     else if (pair == 1)
-        hipLaunchKernelGGL((linear_bwd_data_kernel<float, float>), grid, dim3(256), 0, s, B, In,
-                           Out, (const float *)dY, (const float *)Wt, (float *)dX);
+        hipLaunchKernelGGL((linear_gemm_kernel<float, float, true>), grid, dim3(256), 0, s, B, In,
+                           Out, (const float *)dY, (const float *)Wt, (const float *)nullptr, 0,
+                           (float *)dX);
     else
-        hipLaunchKernelGGL((linear_bwd_data_kernel<double, double>), grid, dim3(256), 0, s, B, In,
-                           Out, (const double *)dY, (const double *)Wt, (double *)dX);
+        hipLaunchKernelGGL((linear_gemm_kernel<double, double, true>), grid, dim3(256), 0, s, B, In,
+                           Out, (const double *)dY, (const double *)Wt, (const double *)nullptr, 0,
+                           (double *)dX);
     return launched("nn_linear_bwd_data");
 }
 
@@ -707,17 +768,33 @@ int nn_linear_bwd_weight(int dtype, int B, int In, int Out, const void *X, const
     return launched("nn_linear_bwd_weight");
 }
 
-int nn_channel_sum(int dtype, int B, int C, int64_t S, const void *X, void *out, void *stream)
+size_t nn_channel_sum_ws_bytes(int dtype, int B, int C, int64_t S)
 {
-    if ((dtype != NN_F32 && dtype != NN_F64) || B <= 0 || C <= 0 || S <= 0 || !X || !out)
+    if ((dtype != NN_F32 && dtype != NN_F64) || B <= 0 || C <= 0 || S <= 0) return 0;
+    const int64_t chunks = ((int64_t)B * S + kCsChunk - 1) / kCsChunk;
+    return (size_t)chunks * C * (dtype == NN_F32 ? 4 : 8);
+}
+
+int nn_channel_sum(int dtype, int B, int C, int64_t S, const void *X, void *out, void *ws,
+                   size_t ws_bytes, void *stream)
+{
+    const size_t need = nn_channel_sum_ws_bytes(dtype, B, C, S);
+    if (need == 0 || !X || !out || !ws || C > 65535)
         return tdb_set_error(DB_EINVAL, "nn_channel_sum: bad arguments");
+    if (ws_bytes < need) return tdb_set_error(DB_ENOSPC, "nn_channel_sum: workspace too small");
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    if (dtype == NN_F32)
-        hipLaunchKernelGGL(channel_sum_kernel<float>, dim3(C), dim3(256), 0, s, B, C, S,
-                           (const float *)X, (float *)out);
-    else
-        hipLaunchKernelGGL(channel_sum_kernel<double>, dim3(C), dim3(256), 0, s, B, C, S,
-                           (const double *)X, (double *)out);
+    const int chunks = (int)(((int64_t)B * S + kCsChunk - 1) / kCsChunk);
+    if (dtype == NN_F32) {
+        hipLaunchKernelGGL(channel_sum_partial<float>, dim3(chunks, C), dim3(256), 0, s, B, C, S,
+                           (const float *)X, (float *)ws);
+        hipLaunchKernelGGL(channel_sum_final<float>, dim3((C + 63) / 64), dim3(64), 0, s, C, chunks,
+                           (const float *)ws, (float *)out);
+    } else {
+        hipLaunchKernelGGL(channel_sum_partial<double>, dim3(chunks, C), dim3(256), 0, s, B, C, S,
+                           (const double *)X, (double *)ws);
+        hipLaunchKernelGGL(channel_sum_final<double>, dim3((C + 63) / 64), dim3(64), 0, s, C,
+                           chunks, (const double *)ws, (double *)out);
+    }
     return launched("nn_channel_sum");
 }
 

@@ -36,7 +36,8 @@ _SIGS = {
     "nn_linear_fwd": (_i32, [_i32] * 4 + [_vp, _vp, _i32, _vp, _i32, _vp, _vp]),
     "nn_linear_bwd_data": (_i32, [_i32] * 4 + [_vp, _vp, _i32, _vp, _vp]),
     "nn_linear_bwd_weight": (_i32, [_i32] * 4 + [_vp, _vp, _vp, _vp, _vp]),
-    "nn_channel_sum": (_i32, [_i32, _i32, _i32, _i64, _vp, _vp, _vp]),
+    "nn_channel_sum_ws_bytes": (_sz, [_i32, _i32, _i32, _i64]),
+    "nn_channel_sum": (_i32, [_i32, _i32, _i32, _i64, _vp, _vp, _vp, _sz, _vp]),
     "nn_relu_bwd": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp]),
     "nn_mse_ws_bytes": (_sz, [_i32, _i64]),
     "nn_mse_fwd": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -189,7 +190,10 @@ class ConvT3dS2(torch.autograd.Function):
         db_ = None
         if ctx.has_bias:
             db_ = torch.empty(Cout, dtype=x.dtype, device=x.device)
-            _check(LIB.nn_channel_sum(_dt(x), B, Cout, D * H * W, g.data_ptr(), db_.data_ptr(), _s()))
+            nbs = LIB.nn_channel_sum_ws_bytes(_dt(x), B, Cout, D * H * W)
+            wss = torch.empty(nbs, dtype=torch.uint8, device=x.device)
+            _check(LIB.nn_channel_sum(_dt(x), B, Cout, D * H * W, g.data_ptr(), db_.data_ptr(),
+                                      wss.data_ptr(), nbs, _s()))
         return dx, dw, db_, None, None
 
 
