@@ -113,6 +113,27 @@ def cpu_baseline(gen, q, t_lo, t_hi, target_s: float):
                       f"{passes} passes of the plain for-loop, {elapsed:.1f} s"}
 
 
+def cpu_baseline_batch(gen, labels, rois, t_lo, t_hi, target_s: float):
+    """The oracle's loop with boxes, on a bounded sample: 64 entries x the first queries."""
+    import numpy as np
+    import oracle
+    threads = oracle._threads()
+    conc = gen.conc_cpu(0, 64, threads)
+    pairs = 0
+    t0 = time.perf_counter()
+    q = 0
+    while time.perf_counter() - t0 < target_s or q == 0:
+        oracle.scan_block(conc, labels[q % len(labels)], t_lo, t_hi, roi=rois[q % len(labels)],
+                          threads=threads)
+        r = rois[q % len(labels)]
+        pairs += 64 * int((r[3] - r[0]) * (r[4] - r[1]) * (r[5] - r[2]))
+        q += 1
+    el = time.perf_counter() - t0
+    return {"value": pairs / el, "unit": "voxels/s", "cores": threads, "kind": "oracle",
+            "sample": f"64 of the {gen.nx}^3 database volumes (float32, host RAM) x {q} box-"
+                      f"restricted queries, plain for-loop, {el:.1f} s"}
+
+
 def roi_work(rois, n: int):
     """Voxel pairs compared and packed word positions (both masks) inside the boxes."""
     vox = 0
@@ -151,6 +172,10 @@ def bench_batch(args, db, gen, n, build_s) -> int:
                                       o_cnt))
     log(f"returned entries of queries 0 and {nq - 1} re-checked by the oracle: "
         f"{'ok' if ok else 'MISMATCH'}")
+    from paper_2205_04550_amd import autotune
+    log("autotuning the launch shape (z-planes per LDS slab x block size)")
+    best, table = autotune.tune_batch(db, lab_d, rois, k, reps=3, log=log)
+    log(f"picked {best[0] or 'max'} planes x {best[1]} threads ({best[2]:.2f} ms)")
     for _ in range(args.warmup):
         db.query_batch(lab_d, rois, k, out=out, ws=ws)
     torch.cuda.synchronize()
@@ -168,6 +193,10 @@ def bench_batch(args, db, gen, n, build_s) -> int:
     g_avg = g_ms / max(1, launches)
     ops = 3 * words   # per packed word and mask: AND, popcount-add (I), popcount-add (B)
     achieved = ops / (g_avg * 1e-3)
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = cpu_baseline_batch(gen, labels, rois, t_lo, t_hi, args.cpu_seconds)
+        log(f"cpu oracle {cpu['value']:.3e} voxel pairs/s on {cpu['cores']} threads")
     log(f"{ms:.2f} ms per {nq}-query launch; {pairs_vox / (ms * 1e-3):.3e} voxel pairs/s; "
         f"{achieved / VALU_PEAK_OPS:.1%} of integer VALU issue")
     line = {
@@ -186,7 +215,9 @@ def bench_batch(args, db, gen, n, build_s) -> int:
                      "kernel": "batch_scan_kernel (graph)", "kernel_avg_ms": g_avg,
                      "algorithmic_ops_per_launch": ops,
                      "hbm_floor_gb_per_launch": n * 2 * gen.nvox / 8 / 1e9},
-        "cpu_baseline": None,
+        "autotune": {"picked": {"slab_planes": best[0], "block_threads": best[1]},
+                     "table_ms": [list(t) for t in table]},
+        "cpu_baseline": cpu,
         "parity": {"returned_entries_rechecked_by_oracle": ok},
         "build_s": build_s,
     }

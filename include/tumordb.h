@@ -122,6 +122,12 @@ int db_query_batch(const db_t *db, int nq, const uint8_t *q_labels, const db_roi
                    int32_t *idx, double *score, db_counts_t *counts, void *ws, size_t ws_bytes,
                    void *stream);
 
+/* Launch shape of db_query_batch: z-planes per LDS slab (0 = as many as fit)
+ * and block size (0 = 1024; else 256, 512 or 1024). Results do not depend on
+ * it; the autotuner (paper_2205_04550_amd/autotune.py) picks it by timing. A
+ * change takes effect at the next recording of the batch graph. */
+int db_tune_batch(db_t *db, int slab_planes, int block_threads);
+
 /* ---------------------------------------------------- embedding search --- */
 /* Latent search (Sec. 2.3, "Autoencoders": encoded database and query are
  * compared by L2 distance, lowest wins), then exact re-scoring of the

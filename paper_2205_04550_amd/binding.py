@@ -21,7 +21,7 @@ SYMBOLS = ("db_storage_bytes", "db_build", "db_append", "db_size", "db_query_wor
            "db_scan", "db_query", "db_query_batch", "db_sync", "db_free", "db_last_error",
            "db_profile", "db_profile_read", "emb_quantize", "emb_distances", "emb_topk_min",
            "db_rerank_workspace_bytes", "db_rerank", "db_query_embed_workspace_bytes",
-           "db_query_embed")
+           "db_query_embed", "db_tune_batch")
 EMB_BF16, EMB_FP8 = 0, 1
 
 
@@ -55,6 +55,7 @@ def _load():
         "db_free": (None, [vp]),
         "db_last_error": (ctypes.c_char_p, []),
         "db_profile": (i32, [vp, i32]),
+        "db_tune_batch": (i32, [vp, i32, i32]),
         "emb_quantize": (i32, [i64, i32, vp, i32, vp, vp, vp, vp]),
         "emb_distances": (i32, [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
         "emb_topk_min": (i32, [i32, i32, vp, i32, vp, vp, vp]),
@@ -237,6 +238,10 @@ class TumorDB:
                                   counts.data_ptr(), ci.data_ptr(), cd.data_ptr(), ws.data_ptr(),
                                   ws.numel(), _stream(stream)))
         return out
+
+    def tune_batch(self, slab_planes: int = 0, block_threads: int = 0) -> None:
+        """Launch shape of query_batch (0 = defaults); results are the same for any shape."""
+        _check(LIB.db_tune_batch(self._h, slab_planes, block_threads))
 
     def profile(self, enable: bool) -> None:
         """Record HIP events around the dominant kernel of every later query call."""

@@ -95,7 +95,7 @@ WsLayout ws_layout(const db_t *db, int nq, int k, bool batched)
 
 // Host state of a cached batched-query graph.
 struct BatchGraph {
-    int nq = 0, k = 0;
+    int nq = 0, k = 0, Z = 0, threads = 0;
     int64_t n = 0;
     const void *labels = nullptr, *ws = nullptr, *idx = nullptr, *score = nullptr,
                *counts = nullptr;
@@ -272,6 +272,8 @@ int db_build(db_t **out, int nx, int ny, int nz, float t_lo, float t_hi, int64_t
     db->cus = cus;
     db->device = dev;
     db->lds_max = lds;
+    db->batch_planes = 0;
+    db->batch_threads = 0;
     db->graph = nullptr;
     db->prof = nullptr;
     *out = db;
@@ -461,7 +463,8 @@ int db_query_batch(const db_t *db_c, int nq, const uint8_t *q_labels, const db_r
         std::memcpy(st_lists + list_off.size(), list_q.data(), list_q.size() * 4);
 
     // (Re)record the graph when the shape or any pointer changed.
-    const bool same = G.exec && G.nq == nq && G.k == k && G.n == db->count &&
+    const bool same = G.exec && G.nq == nq && G.k == k && G.n == db->count && G.Z == P.Z &&
+                      G.threads == P.threads &&
                       G.labels == q_labels && G.ws == ws && G.idx == idx && G.score == score &&
                       G.counts == counts;
     if (!same) {
@@ -485,6 +488,8 @@ int db_query_batch(const db_t *db_c, int nq, const uint8_t *q_labels, const db_r
         G.nq = nq;
         G.k = k;
         G.n = db->count;
+        G.Z = P.Z;
+        G.threads = P.threads;
         G.labels = q_labels;
         G.ws = ws;
         G.idx = idx;
@@ -693,6 +698,20 @@ int db_sync(const db_t *db, void *stream)
     hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "db_sync");
+    return DB_OK;
+}
+
+int db_tune_batch(db_t *db, int slab_planes, int block_threads)
+{
+    if (!live(db)) return fail(DB_ESTATE, "db_tune_batch: invalid handle");
+    if (slab_planes < 0 || slab_planes > db->g.nz)
+        return fail(DB_EINVAL, "db_tune_batch: slab_planes %d outside [0, %d]", slab_planes,
+                    db->g.nz);
+    if (block_threads != 0 && block_threads != 256 && block_threads != 512 &&
+        block_threads != 1024)
+        return fail(DB_EINVAL, "db_tune_batch: block_threads must be 0, 256, 512 or 1024");
+    db->batch_planes = slab_planes;
+    db->batch_threads = block_threads;
     return DB_OK;
 }
 

@@ -92,6 +92,45 @@ __device__ __forceinline__ uint32_t reduce16(const uint32_t (&v)[16], int lane)
     return d;
 }
 
+// Rows of 128 voxels (4 words per mask) for a box whose x-range covers words
+// W0..W1: only those words are counted; the database side needs a mask only on
+// the two edge words (the query side was masked when packed).
+template <int W0, int W1>
+__device__ __forceinline__ void count_rows4(uint32_t (&acc)[16], const uint32_t *D, int slab_w,
+                                            const uint32_t *Q0, const uint32_t *Q1, uint32_t nr,
+                                            uint32_t nyr, uint32_t M, int zlo, int y0, int zs0,
+                                            int ny, uint32_t mlo, uint32_t mhi, int lane)
+{
+    for (uint32_t r = lane; r < nr; r += 64) {
+        const uint32_t zr = div_magic(r, nyr, M);
+        const int z = zlo + (int)zr;
+        const int y = y0 + (int)(r - zr * nyr);
+        const int gw = (z * ny + y) * 4;
+        const int lw = ((z - zs0) * ny + y) * 4;
+        const u32x4 qa = *reinterpret_cast<const u32x4 *>(Q0 + gw);
+        const u32x4 qb = *reinterpret_cast<const u32x4 *>(Q1 + gw);
+#pragma unroll
+        for (int s = 0; s < kTile; ++s) {
+            const u32x4 da = *reinterpret_cast<const u32x4 *>(D + (2 * s) * slab_w + lw);
+            const u32x4 db = *reinterpret_cast<const u32x4 *>(D + (2 * s + 1) * slab_w + lw);
+#pragma unroll
+            for (int w = W0; w <= W1; ++w) {
+                const uint32_t dwa = da[w], dwb = db[w];
+                acc[4 * s + 0] += popc(qa[w] & dwa);
+                acc[4 * s + 1] += popc(qb[w] & dwb);
+                if (w == W0 || w == W1) {
+                    const uint32_t m = (W0 == W1) ? (mlo & mhi) : (w == W0 ? mlo : mhi);
+                    acc[4 * s + 2] += popc(dwa & m);
+                    acc[4 * s + 3] += popc(dwb & m);
+                } else {
+                    acc[4 * s + 2] += popc(dwa);
+                    acc[4 * s + 3] += popc(dwb);
+                }
+            }
+        }
+    }
+}
+
 // grid (tiles, query chunks), kBatchThreads threads. Dynamic LDS:
 //   D   uint32 [kTile][2][Z * ny * nxw]   the tile's slab, both masks
 //   cnt uint32 [nqc][kTile][4]            I_FLAIR, I_T1Gd, |B_FLAIR n R|, |B_T1Gd n R|
@@ -164,29 +203,26 @@ __global__ void __launch_bounds__(kBatchThreads) batch_lds_kernel(
 #pragma unroll
             for (int j = 0; j < 16; ++j) acc[j] = 0;
             if (nxw == 4) {
-                // 128-voxel rows: one 16-byte word group per row and mask.
-                const uint32_t xm0 = xmask(0, x0, x1), xm1 = xmask(1, x0, x1);
-                const uint32_t xm2 = xmask(2, x0, x1), xm3 = xmask(3, x0, x1);
-                for (uint32_t r = lane; r < nr; r += 64) {
-                    const uint32_t zr = div_magic(r, nyr, M);
-                    const int z = zlo + (int)zr;
-                    const int y = y0 + (int)(r - zr * nyr);
-                    const int gw = (z * ny + y) * 4;
-                    const int lw = ((z - zs0) * ny + y) * 4;
-                    const u32x4 qa = *reinterpret_cast<const u32x4 *>(Q0 + gw);
-                    const u32x4 qb = *reinterpret_cast<const u32x4 *>(Q1 + gw);
-#pragma unroll
-                    for (int s = 0; s < kTile; ++s) {
-                        const u32x4 da = *reinterpret_cast<const u32x4 *>(D + (2 * s) * slab_w + lw);
-                        const u32x4 db = *reinterpret_cast<const u32x4 *>(D + (2 * s + 1) * slab_w + lw);
-                        acc[4 * s + 0] += popc_and4(qa, da);
-                        acc[4 * s + 1] += popc_and4(qb, db);
-                        acc[4 * s + 2] += popc(da.x & xm0) + popc(da.y & xm1) + popc(da.z & xm2) +
-                                          popc(da.w & xm3);
-                        acc[4 * s + 3] += popc(db.x & xm0) + popc(db.y & xm1) + popc(db.z & xm2) +
-                                          popc(db.w & xm3);
-                    }
+                // 128-voxel rows: one 16-byte word group per row and mask, counted
+                // over the box's words only (10 word ranges, each its own loop).
+                const int wx0 = x0 >> 5, wx1 = (x1 - 1) >> 5;
+                const uint32_t mlo = 0xffffffffu << (x0 & 31);
+                const uint32_t mhi = (x1 & 31) ? ((1u << (x1 & 31)) - 1u) : 0xffffffffu;
+#define TDB_ROWS(a, b)                                                                          \
+    count_rows4<a, b>(acc, D, slab_w, Q0, Q1, nr, nyr, M, zlo, y0, zs0, ny, mlo, mhi, lane)
+                switch (wx0 * 4 + wx1) {
+                case 0: TDB_ROWS(0, 0); break;
+                case 1: TDB_ROWS(0, 1); break;
+                case 2: TDB_ROWS(0, 2); break;
+                case 3: TDB_ROWS(0, 3); break;
+                case 5: TDB_ROWS(1, 1); break;
+                case 6: TDB_ROWS(1, 2); break;
+                case 7: TDB_ROWS(1, 3); break;
+                case 10: TDB_ROWS(2, 2); break;
+                case 11: TDB_ROWS(2, 3); break;
+                default: TDB_ROWS(3, 3); break;
                 }
+#undef TDB_ROWS
             } else {
                 const int wx0 = x0 >> 5, wx1 = (x1 - 1) >> 5;
                 for (uint32_t r = lane; r < nr; r += 64) {
@@ -336,7 +372,9 @@ BatchPlan batch_plan(const db_t *db, int nq)
     const int64_t cnt_bytes = (int64_t)p.qchunk * kTile * 4 * 4;
     const int64_t budget = (int64_t)db->lds_max - cnt_bytes;
     int64_t Z = budget > 0 ? budget / (kTile * 2 * plane_bytes) : 0;
+    if (db->batch_planes > 0 && db->batch_planes < Z) Z = db->batch_planes;  // tuned depth
     if (Z > g.nz) Z = g.nz;
+    p.threads = db->batch_threads > 0 ? db->batch_threads : kBatchThreads;
     p.Z = (int)Z;
     p.use_lds = Z >= 1;
     p.nslabs = p.use_lds ? (g.nz + p.Z - 1) / p.Z : 0;
@@ -358,7 +396,7 @@ hipError_t launch_batch_scan(const db_t *db, int64_t n, int nq, const BatchPlan 
     const Geometry &g = db->g;
     const int64_t ntiles = (n + kTile - 1) / kTile;
     if (p.use_lds) {
-        hipLaunchKernelGGL(batch_lds_kernel, dim3((unsigned)ntiles, p.nchunks), dim3(kBatchThreads),
+        hipLaunchKernelGGL(batch_lds_kernel, dim3((unsigned)ntiles, p.nchunks), dim3(p.threads),
                            p.lds_bytes, s, db->planes, g.Wp, g.nxw, g.ny, g.nz, n, p.Z, p.nslabs,
                            qpack, rois, list_off, list_q, p.qchunk, nq, inter, bcnt,
                            2 * db->capacity);

@@ -46,6 +46,8 @@ struct db_t {
     int cus;                 // compute units of the device the handle was built on
     int device;
     int lds_max;             // LDS bytes one block may use on that device
+    int batch_planes;        // tuned z-planes per LDS slab of the batched scan (0 = most that fit)
+    int batch_threads;       // tuned block size of the batched scan (0 = default)
     tdb::BatchGraph *graph;
     tdb::Profiler *prof;
 };
@@ -80,7 +82,7 @@ hipError_t launch_scan(const db_t *db, int64_t n, const uint32_t *qpack, uint32_
 // Shape of a batched launch: LDS slabs of Z planes (use_lds) or the L2 fallback.
 struct BatchPlan {
     bool use_lds;
-    int Z, nslabs, qchunk, nchunks;
+    int Z, nslabs, qchunk, nchunks, threads;
     size_t lds_bytes;
 };
 BatchPlan batch_plan(const db_t *db, int nq);

@@ -117,3 +117,21 @@ def test_batch_boxes_of_the_workload_generator():
     res = db.query_batch(torch.from_numpy(labels).cuda(), rois, k)
     db.sync()
     _compare(res, ref, k)
+
+
+def test_batch_results_do_not_depend_on_launch_shape():
+    """Every slab depth / block size the autotuner may pick gives the same bytes."""
+    need_gpu()
+    gen = synth.GenConfig(128, 24, 20, 2.0, 10.0, 0.5, 3.0, 31)
+    n, nq, k = 75, 9, 7
+    db, conc = build_db_from_host(gen, n, T_LO, T_HI)
+    labels, _ = synth.make_queries(gen, n, nq, synth.BATCH_QUERY_SEED)
+    rois = _edge_rois((gen.nx, gen.ny, gen.nz), nq, np.random.default_rng(3))
+    ref = _oracle_batch(conc, labels, rois, k)
+    lab_d = torch.from_numpy(labels).cuda()
+    for planes, threads in [(0, 0), (1, 256), (2, 512), (3, 1024), (7, 512), (20, 1024)]:
+        say(f"shape planes={planes} threads={threads}")
+        db.tune_batch(planes, threads)
+        res = db.query_batch(lab_d, rois, k)
+        db.sync()
+        _compare(res, ref, k)
