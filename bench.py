@@ -296,6 +296,40 @@ def bench_train(args, db, gen, n, build_s) -> int:
     return 0
 
 
+def cpu_baseline_embed(model, X, labels, gen, n, n_cand, k, target_s: float):
+    """The oracle's embedding query on host cores, one query at a time: float64 mean-pool
+    and encoder, float64 direct distances to the stored latents, top-n_cand, and the
+    for-loop Dice on the candidates (their volumes regenerated on the CPU)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from oracle import encoder as E
+    threads = oracle._threads()
+    params = {k2: p.detach().to("cpu", torch.float64) for k2, p in model.params.items()}
+    xlat = E.bf16_decode(X.codes.view(torch.int16).cpu().numpy())
+    t0 = time.perf_counter()
+    done = 0
+    while time.perf_counter() - t0 < target_s or done == 0:
+        lab = labels[done % len(labels)]
+        z = E.encode(params, torch.from_numpy(E.meanpool(lab[None]))).numpy()
+        d = E.sqdist_direct(z, xlat)[0]
+        cand = E.topk_by_distance(d[None], n_cand)[0]
+        _, cnt, sc = oracle.scan(gen, n, lab, synth_t()[0], synth_t()[1], indices=cand.tolist(),
+                                 threads=threads)
+        oracle.rank(sc, k)
+        done += 1
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} of the held-out queries, one at a time (encoder, float64 "
+                      f"distances to {n} latents, top-{n_cand}, for-loop Dice), {el:.1f} s"}
+
+
+def synth_t():
+    import synth
+    return synth.T_LO, synth.T_HI
+
+
 def bench_embed(args, db, gen, n, build_s) -> int:
     """Held-out queries through encoder, BF16 MFMA distances, top-100 and exact rerank."""
     import numpy as np
@@ -323,6 +357,7 @@ def bench_embed(args, db, gen, n, build_s) -> int:
     log(f"encoded {n} entries in {encode_db_s:.1f} s; making {nq} held-out queries")
     labels, _ = synth.make_queries(gen, n, nq, synth.HELDOUT_SEED, held_out_seed=synth.HELDOUT_SEED)
     lab_d = torch.from_numpy(labels).cuda()
+    lab_host_sample = labels[:32].copy()
     del labels
     # Exact top-k of every query (the ground truth), one exact scan per query.
     ws1 = db.workspace(1, k)
@@ -378,6 +413,11 @@ def bench_embed(args, db, gen, n, build_s) -> int:
     top_n = {f"top{t}": float(np.mean([ex[q, 0] in got[q, :t] for q in range(nq)])) for t in (1, 5, 15)}
     cand_recall = float(np.mean([len(set(ci[q].cpu().numpy()) & set(ex[q, :10])) / 10
                                  for q in range(min(nq, 256))]))
+    cpu = None
+    if args.cpu_seconds > 0:
+        log("timing the CPU oracle on a sample of the queries")
+        cpu = cpu_baseline_embed(model, X, lab_host_sample, gen, n, n_cand, k, args.cpu_seconds)
+        log(f"cpu oracle {cpu['value']:.3f} queries/s on {cpu['cores']} threads")
     gemm_flop = 2.0 * nq * n * model.latent
     names = ["encode queries", "distance GEMM (BF16 MFMA)", "top-100 select", "exact rerank"]
     dom = int(np.argmax(stage))
@@ -403,7 +443,7 @@ def bench_embed(args, db, gen, n, build_s) -> int:
                      "frac": gemm_flop / (stage[1] * 1e-3) / BF16_MFMA_PEAK, "traffic": None,
                      "kernel": "dist_bf16_kernel", "kernel_avg_ms": stage[1],
                      "dominant_stage": names[dom]},
-        "cpu_baseline": None, "build_s": build_s, "train_s": train_s,
+        "cpu_baseline": cpu, "build_s": build_s, "train_s": train_s,
         "encode_db_s": encode_db_s, "train_loss_first_last": [losses[0], losses[-1]],
     }
     print(json.dumps(line), flush=True)

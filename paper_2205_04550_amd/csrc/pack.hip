@@ -10,8 +10,10 @@
 
 namespace tdb {
 
-// One block per simulation: 32 voxels -> one word per mask, plus the mask
-// populations |B_FLAIR|, |B_T1Gd| used by every later Dice.
+// One block per simulation. Lanes read consecutive 16-byte groups (4 voxels),
+// so every load instruction is fully coalesced; the 4-bit nibbles of 8
+// neighbouring lanes are OR-ed into one 32-voxel word with three xor shuffles.
+// Also counts the mask populations |B_FLAIR|, |B_T1Gd| used by every later Dice.
 __global__ void __launch_bounds__(256) pack_db_kernel(const float *__restrict__ conc, int64_t V,
                                                       int W, int Wp, float t_lo, float t_hi,
                                                       uint32_t *__restrict__ planes,
@@ -21,26 +23,34 @@ __global__ void __launch_bounds__(256) pack_db_kernel(const float *__restrict__ 
     const int64_t s = blockIdx.x;
     const f32x4 *c = reinterpret_cast<const f32x4 *>(conc + s * V);
     uint32_t *o = planes + s * 2 * (int64_t)Wp;
+    const int nvec = 8 * W, nall = 8 * Wp;   // 16-byte groups with data / incl. padding words
+    const int j = threadIdx.x & 7;
     uint32_t n0 = 0, n1 = 0;
-    for (int w = threadIdx.x; w < Wp; w += blockDim.x) {
+    for (int base = 0; base < nall; base += blockDim.x) {   // uniform trip count
+        const int i = base + threadIdx.x;
         uint32_t b0 = 0, b1 = 0;
-        if (w < W) {
-            f32x4 v[8];
+        if (i < nvec) {
+            const f32x4 v = __builtin_nontemporal_load(c + i);
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
-                v[j] = __builtin_nontemporal_load(c + (int64_t)w * 8 + j);
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    b0 |= (uint32_t)(v[j][e] >= t_lo) << (4 * j + e);
-                    b1 |= (uint32_t)(v[j][e] >= t_hi) << (4 * j + e);
-                }
+            for (int e = 0; e < 4; ++e) {
+                b0 |= (uint32_t)(v[e] >= t_lo) << e;
+                b1 |= (uint32_t)(v[e] >= t_hi) << e;
+            }
         }
-        o[w] = b0;
-        o[Wp + w] = b1;
-        n0 += popc(b0);
-        n1 += popc(b1);
+        b0 <<= 4 * j;
+        b1 <<= 4 * j;
+#pragma unroll
+        for (int o2 = 1; o2 < 8; o2 <<= 1) {
+            b0 |= __shfl_xor(b0, o2, 64);
+            b1 |= __shfl_xor(b1, o2, 64);
+        }
+        if (j == 0 && i < nall) {
+            const int w = i >> 3;
+            o[w] = b0;
+            o[Wp + w] = b1;
+            n0 += popc(b0);
+            n1 += popc(b1);
+        }
     }
     block_sum2(n0, n1, red);
     if (threadIdx.x == 0) {
