@@ -174,6 +174,22 @@ int db_query_embed(const db_t *db, int fmt, int nq, int dim, const void *q_codes
                    int k, int32_t *idx, double *score, db_counts_t *counts, int32_t *cand_idx,
                    float *cand_d, void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------- downsampled queries --- */
+/* The paper's cheaper exact variant (Sec. 2.3, DS64 / DS32 in Tables 1-2):
+ * downsample database and query by order-0 (nearest-neighbour) spline
+ * interpolation and run the same Dice query at the lower resolution. Output
+ * voxel o of an axis reads source voxel round(o (n_in - 1) / (n_out - 1)).
+ * Output axes are 1..256 voxels (dst nx % 32 == 0 as for any database). */
+
+/* Append entries [first, first + n) of src to dst, resampled to dst's grid
+ * (thresholds must match). The masks are resampled directly: thresholding
+ * commutes with order-0 sampling. */
+int db_append_resampled(db_t *dst, const db_t *src, int64_t first, int64_t n, void *stream);
+
+/* Resample nq query label volumes uint8 [nq][nz][ny][nx] to [nq][mz][my][mx] (device). */
+int labels_resample(int nq, const uint8_t *in, int nx, int ny, int nz, uint8_t *out, int mx,
+                    int my, int mz, void *stream);
+
 /* ----------------------------------------------------------------- misc --- */
 
 /* Wait for `stream` and report any asynchronous device error as DB_EHIP. */

@@ -155,3 +155,16 @@ def query(gen, n_db: int, q: np.ndarray, k: int, t_lo: float, t_hi: float, roi=N
     _, cnt, sc = scan(gen, n_db, q, t_lo, t_hi, roi, chunk, threads)
     top = rank(sc, k)
     return np.array(top, dtype=np.int64), sc[top], cnt[top]
+
+
+def resample_nearest(labels: np.ndarray, shape) -> np.ndarray:
+    """Order-0 spline (nearest-neighbour) resampling of label volumes [..., nz, ny, nx] to
+    [..., *shape] with scipy.ndimage.zoom, the routine the paper used for DS64 / DS32
+    (Sec. 2.3); a library primitive used as one step."""
+    import scipy.ndimage as nd
+    lab = np.asarray(labels)
+    lead = lab.ndim - 3
+    factors = [1.0] * lead + [o / i for o, i in zip(shape, lab.shape[lead:])]
+    out = nd.zoom(lab, factors, order=0)
+    assert out.shape[lead:] == tuple(shape), (out.shape, shape)
+    return out

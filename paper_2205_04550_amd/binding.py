@@ -21,7 +21,7 @@ SYMBOLS = ("db_storage_bytes", "db_build", "db_append", "db_size", "db_query_wor
            "db_scan", "db_query", "db_query_batch", "db_sync", "db_free", "db_last_error",
            "db_profile", "db_profile_read", "emb_quantize", "emb_distances", "emb_topk_min",
            "db_rerank_workspace_bytes", "db_rerank", "db_query_embed_workspace_bytes",
-           "db_query_embed", "db_tune_batch")
+           "db_query_embed", "db_tune_batch", "db_append_resampled", "labels_resample")
 EMB_BF16, EMB_FP8 = 0, 1
 
 
@@ -56,6 +56,8 @@ def _load():
         "db_last_error": (ctypes.c_char_p, []),
         "db_profile": (i32, [vp, i32]),
         "db_tune_batch": (i32, [vp, i32, i32]),
+        "db_append_resampled": (i32, [vp, vp, i64, i64, vp]),
+        "labels_resample": (i32, [i32, vp, i32, i32, i32, vp, i32, i32, i32, vp]),
         "emb_quantize": (i32, [i64, i32, vp, i32, vp, vp, vp, vp]),
         "emb_distances": (i32, [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
         "emb_topk_min": (i32, [i32, i32, vp, i32, vp, vp, vp]),
@@ -239,6 +241,12 @@ class TumorDB:
                                   ws.numel(), _stream(stream)))
         return out
 
+    def append_resampled(self, src: "TumorDB", first: int = 0, n: int | None = None,
+                         stream=None) -> None:
+        """Append src's entries resampled (order 0) to this database's grid."""
+        n = len(src) - first if n is None else n
+        _check(LIB.db_append_resampled(self._h, src._h, first, n, _stream(stream)))
+
     def tune_batch(self, slab_planes: int = 0, block_threads: int = 0) -> None:
         """Launch shape of query_batch (0 = defaults); results are the same for any shape."""
         _check(LIB.db_tune_batch(self._h, slab_planes, block_threads))
@@ -307,3 +315,16 @@ def emb_topk_min(D: torch.Tensor, k: int, stream=None):
     _check(LIB.emb_topk_min(M, N, D.contiguous().data_ptr(), k, idx.data_ptr(), val.data_ptr(),
                             _stream(stream)))
     return idx, val
+
+
+def labels_resample(labels: torch.Tensor, shape, stream=None) -> torch.Tensor:
+    """Order-0 resampling of uint8 labels [nq][nz][ny][nx] to [nq][*shape] (shape = (mz, my, mx))."""
+    lab = labels.contiguous()
+    if lab.dim() == 3:
+        lab = lab[None]
+    nq, nz, ny, nx = lab.shape
+    mz, my, mx = shape
+    out = torch.empty((nq, mz, my, mx), dtype=torch.uint8, device=lab.device)
+    _check(LIB.labels_resample(nq, lab.data_ptr(), nx, ny, nz, out.data_ptr(), mx, my, mz,
+                               _stream(stream)))
+    return out

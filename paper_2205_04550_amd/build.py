@@ -11,7 +11,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtumordb.so")
 
-SOURCES = ["api.cpp", "pack.hip", "scan.hip", "select.hip", "batch.hip", "nn.hip", "embed.hip"]
+SOURCES = ["api.cpp", "pack.hip", "scan.hip", "select.hip", "batch.hip", "nn.hip", "embed.hip",
+           "resample.hip"]
 # Sources with floating-point arithmetic that may be contracted into FMAs.
 CONTRACT_OK = {"nn.hip"}
 

@@ -692,6 +692,57 @@ int db_query_embed(const db_t *db, int fmt, int nq, int dim, const void *q_codes
     return DB_OK;
 }
 
+// ---- order-0 resampling ----
+
+// Output voxel o of an axis of n_out samples reads source voxel
+// round(o * (n_in - 1) / (n_out - 1)), in exact integer arithmetic.
+static bool fill_map(uint16_t *map, int n_in, int n_out)
+{
+    if (n_out < 1 || n_out > kMaxResample || n_in < 1 || n_in > 65535) return false;
+    for (int o = 0; o < n_out; ++o) {
+        const int64_t num = 2 * (int64_t)o * (n_in - 1) + (n_out - 1);
+        map[o] = (uint16_t)(n_out == 1 ? 0 : num / (2 * (int64_t)(n_out - 1)));
+    }
+    return true;
+}
+
+int db_append_resampled(db_t *dst, const db_t *src, int64_t first, int64_t n, void *stream)
+{
+    if (!live(dst) || !live(src)) return fail(DB_ESTATE, "db_append_resampled: invalid handle");
+    if (first < 0 || n < 0 || first + n > src->count)
+        return fail(DB_EINVAL, "db_append_resampled: entries [%lld, %lld) outside the source",
+                    (long long)first, (long long)(first + n));
+    if (n == 0) return DB_OK;
+    if (dst->count + n > dst->capacity)
+        return fail(DB_ENOSPC, "db_append_resampled: capacity %lld exceeded",
+                    (long long)dst->capacity);
+    if (dst->t_lo != src->t_lo || dst->t_hi != src->t_hi)
+        return fail(DB_EINVAL, "db_append_resampled: thresholds of the two databases differ");
+    ResampleMaps maps;
+    if (!fill_map(maps.x, src->g.nx, dst->g.nx) || !fill_map(maps.y, src->g.ny, dst->g.ny) ||
+        !fill_map(maps.z, src->g.nz, dst->g.nz))
+        return fail(DB_EINVAL, "db_append_resampled: output axes must be 1..%d voxels",
+                    kMaxResample);
+    hipError_t e = launch_resample_db(src, first, n, dst, maps, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "db_append_resampled: launch");
+    dst->count += n;
+    return DB_OK;
+}
+
+int labels_resample(int nq, const uint8_t *in, int nx, int ny, int nz, uint8_t *out, int mx,
+                    int my, int mz, void *stream)
+{
+    if (nq <= 0 || !in || !out || nx <= 0 || ny <= 0 || nz <= 0)
+        return fail(DB_EINVAL, "labels_resample: bad arguments");
+    ResampleMaps maps;
+    if (!fill_map(maps.x, nx, mx) || !fill_map(maps.y, ny, my) || !fill_map(maps.z, nz, mz))
+        return fail(DB_EINVAL, "labels_resample: output axes must be 1..%d voxels", kMaxResample);
+    hipError_t e = launch_resample_labels(nq, in, nx, ny, nz, out, mx, my, mz, maps,
+                                          static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "labels_resample: launch");
+    return DB_OK;
+}
+
 int db_sync(const db_t *db, void *stream)
 {
     if (!live(db)) return fail(DB_ESTATE, "db_sync: invalid handle");

@@ -111,6 +111,16 @@ hipError_t launch_rerank(const db_t *db, int nq, const uint32_t *qpack, const ui
                          const int32_t *box, const int32_t *cand, int nc, int k, int32_t *idx,
                          double *score, db_counts_t *counts, hipStream_t s);
 
+// Order-0 resampling (resample.hip): source index of every output voxel per axis.
+constexpr int kMaxResample = 256;
+struct ResampleMaps {
+    uint16_t x[kMaxResample], y[kMaxResample], z[kMaxResample];
+};
+hipError_t launch_resample_db(const db_t *src, int64_t first, int64_t n, db_t *dst,
+                              const ResampleMaps &maps, hipStream_t s);
+hipError_t launch_resample_labels(int nq, const uint8_t *in, int nx, int ny, int nz, uint8_t *out,
+                                  int mx, int my, int mz, const ResampleMaps &maps, hipStream_t s);
+
 // Top-k over n entries per query. inter: [nq][n..][2] with row stride
 // inter_qstride; bcnt likewise (stride 0 = the database popcounts, shared).
 struct TopkArgs {

@@ -14,7 +14,7 @@ def declared_functions():
     names = set()
     for h in HEADERS:
         text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
-        names |= set(re.findall(r"\b((?:db|emb|nn)_[a-z0-9_]+)\s*\(", text))
+        names |= set(re.findall(r"\b((?:db|emb|nn|labels)_[a-z0-9_]+)\s*\(", text))
     return sorted(names)
 
 

@@ -269,3 +269,25 @@ def test_noisy_self_query_usually_finds_source():
         hits += int(idx[0] == src)
         assert sc[0] > 1.5
     assert hits >= 3
+
+
+# --- order-0 resampling (DS64 / DS32) ------------------------------------------------------
+
+def test_resample_nearest_pins():
+    # Identity when the shape is unchanged.
+    rng = np.random.default_rng(2)
+    lab = rng.integers(0, 4, size=(2, 6, 5, 64), dtype=np.uint8)
+    assert np.array_equal(oracle.resample_nearest(lab, (6, 5, 64)), lab)
+    # Samples spread evenly from the first to the last voxel: output o reads the voxel
+    # nearest to o (n_in - 1) / (n_out - 1); on a ramp the output is that index.
+    for n_in, n_out in ((128, 64), (128, 32), (64, 32), (37, 11)):
+        ramp = np.broadcast_to(np.arange(n_in, dtype=np.int64)[:, None, None], (n_in, 2, 2)).copy()
+        got = oracle.resample_nearest(ramp, (n_out, 2, 2))[:, 0, 0]
+        want = [int(np.floor(o * (n_in - 1) / (n_out - 1) + 0.5)) for o in range(n_out)]
+        assert got.tolist() == want
+        assert got[0] == 0 and got[-1] == n_in - 1
+    # Order 0 only copies values: thresholding before or after resampling is the same.
+    c = synth.SMALL.conc_cpu(0, 2)
+    a = oracle.resample_nearest(oracle.threshold(c, synth.T_LO, synth.T_HI), (32, 32, 32))
+    b = oracle.threshold(oracle.resample_nearest(c, (32, 32, 32)), synth.T_LO, synth.T_HI)
+    assert np.array_equal(a, b)
