@@ -72,7 +72,12 @@ enum {
  *   planes: uint32 [capacity][2][Wp], Wp = round_up(nx*ny*nz/32, 4); word w of
  *           mask m holds voxels 32w..32w+31 of that mask, LSB first; words
  *           past nx*ny*nz/32 are zero;
- *   popcount: uint32 [capacity][2] = |B_FLAIR|, |B_T1Gd| per entry.
+ *   popcount: uint32 [capacity][2] = |B_FLAIR|, |B_T1Gd| per entry;
+ *   box:      int32 [capacity][4] = z0, z1, y0, y1: the x-rows (z, y) holding
+ *             any set bit of either mask lie in [z0, z1) x [y0, y1) (all zero
+ *             for an entry without set bits);
+ *   moments:  uint64 [capacity][4] = sum of x, of y, of z over the FLAIR
+ *             voxels, and their count (the centre of mass is sum / count).
  * Returns 0 if the dimensions are invalid. */
 size_t db_storage_bytes(int nx, int ny, int nz, int64_t capacity);
 
@@ -87,7 +92,7 @@ int db_build(db_t **out, int nx, int ny, int nz, float t_lo, float t_hi, int64_t
  * 16-byte aligned) into entries db_size() .. db_size()+n-1 (Sec. 2.3: the
  * masks are extracted from the raw simulations once, before any query).
  * DB_ENOSPC if capacity would be exceeded. The input may be released once the
- * stream has passed this call. */
+ * stream has passed this call. Also fills the entries' box and moments. */
 int db_append(db_t *db, const float *conc, int64_t n, void *stream);
 
 /* Number of entries appended so far (-1 for an invalid handle). */
@@ -110,6 +115,14 @@ int db_scan(const db_t *db, const uint8_t *q_labels, uint32_t *inter, uint32_t *
  * counts: device db_counts_t [k] or NULL. 1 <= k <= min(db_size(), DB_KMAX). */
 int db_query(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx, double *score,
              db_counts_t *counts, void *ws, size_t ws_bytes, void *stream);
+
+/* Same contract and results, bit for bit, as db_query (same workspace size),
+ * computed by reading only the x-rows where both the entry's stored box and
+ * the query's box hold set bits: every other row is zero on one side and adds
+ * nothing to |A_m n B_m| (Sec. 2.3, Dice). Bytes read per entry scale with
+ * the tumour's extent instead of the grid (an addition to the paper's loop). */
+int db_query_sparse(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx, double *score,
+                    db_counts_t *counts, void *ws, size_t ws_bytes, void *stream);
 
 /* nq queries in one launch sequence, each optionally restricted to its own
  * box: both masks are cut to the box before Dice (an extension; the paper
@@ -174,6 +187,22 @@ int db_query_embed(const db_t *db, int fmt, int nq, int dim, const void *q_codes
                    int k, int32_t *idx, double *score, db_counts_t *counts, int32_t *cand_idx,
                    float *cand_d, void *ws, size_t ws_bytes, void *stream);
 
+/* ----------------------------------------- centre-of-mass prefilter --- */
+/* The location step of the paper's radiomics query (Sec. 2.3): keep the
+ * n_cand entries whose FLAIR centre of mass is nearest the query's, then
+ * score those exactly with Dice_T1Gd + Dice_FLAIR and return the k best (the
+ * paper ranks its 1,000 candidates by shape features instead; exact Dice is
+ * this library's choice). Key: squared distance of the centres, computed in
+ * double (centre = moment / count) and rounded once to float; ties by index;
+ * an empty FLAIR mask on either side gives +inf. q_labels: device uint8
+ * [nq][nz][ny][nx]; outputs idx [nq][k], score [nq][k], counts [nq][k] or
+ * NULL, cand_idx [nq][n_cand] or NULL, cand_d [nq][n_cand] or NULL (device).
+ * 1 <= k <= n_cand <= min(db_size(), DB_KMAX), nq <= 65535. */
+size_t db_query_com_workspace_bytes(const db_t *db, int nq, int n_cand);
+int db_query_com(const db_t *db, int nq, const uint8_t *q_labels, int n_cand, int k, int32_t *idx,
+                 double *score, db_counts_t *counts, int32_t *cand_idx, float *cand_d, void *ws,
+                 size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------- downsampled queries --- */
 /* The paper's cheaper exact variant (Sec. 2.3, DS64 / DS32 in Tables 1-2):
  * downsample database and query by order-0 (nearest-neighbour) spline
@@ -183,7 +212,7 @@ int db_query_embed(const db_t *db, int fmt, int nq, int dim, const void *q_codes
 
 /* Append entries [first, first + n) of src to dst, resampled to dst's grid
  * (thresholds must match). The masks are resampled directly: thresholding
- * commutes with order-0 sampling. */
+ * commutes with order-0 sampling. Fills dst's box and moments too. */
 int db_append_resampled(db_t *dst, const db_t *src, int64_t first, int64_t n, void *stream);
 
 /* Resample nq query label volumes uint8 [nq][nz][ny][nx] to [nq][mz][my][mx] (device). */

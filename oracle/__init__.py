@@ -168,3 +168,48 @@ def resample_nearest(labels: np.ndarray, shape) -> np.ndarray:
     out = nd.zoom(lab, factors, order=0)
     assert out.shape[lead:] == tuple(shape), (out.shape, shape)
     return out
+
+
+def moments(labels: np.ndarray) -> tuple:
+    """(sum x, sum y, sum z, count) over the FLAIR voxels (bit0) of labels [nz][ny][nx].
+
+    Their ratios are the tumour's centre of mass, the location feature of the
+    paper's radiomics query (Sec. 2.3)."""
+    z, y, x = np.nonzero(np.asarray(labels) & 1)
+    return int(x.sum()), int(y.sum()), int(z.sum()), int(x.size)
+
+
+def rowbox(labels: np.ndarray) -> tuple:
+    """(z0, z1, y0, y1): half-open range of the x-rows holding any FLAIR or T1Gd voxel;
+    (0, 0, 0, 0) when there is none."""
+    rows = np.any((np.asarray(labels) & 3) != 0, axis=2)   # [nz][ny]
+    z, y = np.nonzero(rows)
+    if z.size == 0:
+        return 0, 0, 0, 0
+    return int(z.min()), int(z.max()) + 1, int(y.min()), int(y.max()) + 1
+
+
+def com_key(qm: tuple, em: tuple) -> np.float32:
+    """Squared distance of two centres of mass from their moments, in double (centre =
+    sum / count; squares added x, y, z), rounded once to float32; +inf if either mask is
+    empty."""
+    if qm[3] == 0 or em[3] == 0:
+        return np.float32(np.inf)
+    d = [float(qm[i]) / float(qm[3]) - float(em[i]) / float(em[3]) for i in range(3)]
+    return np.float32(d[0] * d[0] + d[1] * d[1] + d[2] * d[2])
+
+
+def query_com(q: np.ndarray, labs: np.ndarray, n_cand: int, k: int):
+    """Centre-of-mass prefilter then exact Dice on the candidates (Sec. 2.3 radiomics
+    query's location step; candidates re-scored by the baseline score).
+
+    q: labels [nz][ny][nx]; labs: database labels [n][nz][ny][nx]. Returns
+    (cand [n_cand], cand_key float32 [n_cand], top [k], score [k], counts [k][6])."""
+    qm = moments(q)
+    keys = np.array([com_key(qm, moments(l)) for l in labs], dtype=np.float32)
+    cand = sorted(range(len(labs)), key=lambda n: (float(keys[n]), n))[:n_cand]
+    cnt = np.array([counts(q, labs[n]) for n in cand], dtype=np.uint64)
+    sc = np.array([score(c) for c in cnt])
+    order = rank(sc, k)
+    return (np.array(cand), keys[cand], np.array([cand[j] for j in order]), sc[order],
+            cnt[order])

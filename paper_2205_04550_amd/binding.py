@@ -21,7 +21,8 @@ SYMBOLS = ("db_storage_bytes", "db_build", "db_append", "db_size", "db_query_wor
            "db_scan", "db_query", "db_query_batch", "db_sync", "db_free", "db_last_error",
            "db_profile", "db_profile_read", "emb_quantize", "emb_distances", "emb_topk_min",
            "db_rerank_workspace_bytes", "db_rerank", "db_query_embed_workspace_bytes",
-           "db_query_embed", "db_tune_batch", "db_append_resampled", "labels_resample")
+           "db_query_embed", "db_tune_batch", "db_append_resampled", "labels_resample",
+           "db_query_sparse", "db_query_com_workspace_bytes", "db_query_com")
 EMB_BF16, EMB_FP8 = 0, 1
 
 
@@ -51,6 +52,9 @@ def _load():
         "db_scan": (i32, [vp, vp, vp, vp, vp, sz, vp]),
         "db_query": (i32, [vp, vp, i32, vp, vp, vp, vp, sz, vp]),
         "db_query_batch": (i32, [vp, i32, vp, vp, i32, vp, vp, vp, vp, sz, vp]),
+        "db_query_sparse": (i32, [vp, vp, i32, vp, vp, vp, vp, sz, vp]),
+        "db_query_com_workspace_bytes": (sz, [vp, i32, i32]),
+        "db_query_com": (i32, [vp, i32, vp, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp]),
         "db_sync": (i32, [vp, vp]),
         "db_free": (None, [vp]),
         "db_last_error": (ctypes.c_char_p, []),
@@ -135,11 +139,30 @@ class TumorDB:
         nb = self.capacity * 2 * self.Wp * 4
         return self.storage[:nb].view(torch.int32).view(self.capacity, 2, self.Wp)
 
+    def _offsets(self):
+        up = lambda b: (b + 255) // 256 * 256
+        pc = up(self.capacity * 2 * self.Wp * 4)
+        box = pc + up(self.capacity * 8)
+        mom = box + up(self.capacity * 16)
+        return pc, box, mom
+
     @property
     def popcounts(self) -> torch.Tensor:
         """int32 view [capacity][2] of |B_FLAIR|, |B_T1Gd|."""
-        off = (self.capacity * 2 * self.Wp * 4 + 255) // 256 * 256
+        off = self._offsets()[0]
         return self.storage[off:off + self.capacity * 8].view(torch.int32).view(self.capacity, 2)
+
+    @property
+    def boxes(self) -> torch.Tensor:
+        """int32 view [capacity][4] of the row boxes z0, z1, y0, y1 of the set bits."""
+        off = self._offsets()[1]
+        return self.storage[off:off + self.capacity * 16].view(torch.int32).view(self.capacity, 4)
+
+    @property
+    def moments(self) -> torch.Tensor:
+        """int64 view [capacity][4] of the FLAIR moments (sum x, sum y, sum z, count)."""
+        off = self._offsets()[2]
+        return self.storage[off:off + self.capacity * 32].view(torch.int64).view(self.capacity, 4)
 
     # ---- query --------------------------------------------------------------------------
     def workspace_bytes(self, nq: int, k: int) -> int:
@@ -181,6 +204,43 @@ class TumorDB:
         _check(LIB.db_query(self._h, q_labels.data_ptr(), k, idx.data_ptr(), score.data_ptr(),
                             _ptr(counts), ws.data_ptr(), ws.numel(), _stream(stream)))
         return idx, score, counts
+
+    def query_sparse(self, q_labels: torch.Tensor, k: int, with_counts: bool = True, out=None,
+                     ws: torch.Tensor | None = None, stream=None):
+        """query() computed over the rows inside both boxes only (same results)."""
+        dev = self.storage.device
+        if out is None:
+            idx = torch.empty(k, dtype=torch.int32, device=dev)
+            score = torch.empty(k, dtype=torch.float64, device=dev)
+            counts = torch.empty((k, 6), dtype=torch.int32, device=dev) if with_counts else None
+        else:
+            idx, score, counts = out
+        ws = self.workspace(1, k) if ws is None else ws
+        _check(LIB.db_query_sparse(self._h, q_labels.data_ptr(), k, idx.data_ptr(),
+                                   score.data_ptr(), _ptr(counts), ws.data_ptr(), ws.numel(),
+                                   _stream(stream)))
+        return idx, score, counts
+
+    def query_com(self, q_labels: torch.Tensor, n_cand: int, k: int, ws: torch.Tensor | None = None,
+                  out=None, stream=None):
+        """Centre-of-mass prefilter (n_cand nearest) + exact rerank ->
+        (idx, score, counts, cand_idx, cand_d)."""
+        nq = q_labels.shape[0]
+        dev = self.storage.device
+        if out is None:
+            out = (torch.empty((nq, k), dtype=torch.int32, device=dev),
+                   torch.empty((nq, k), dtype=torch.float64, device=dev),
+                   torch.empty((nq, k, 6), dtype=torch.int32, device=dev),
+                   torch.empty((nq, n_cand), dtype=torch.int32, device=dev),
+                   torch.empty((nq, n_cand), dtype=torch.float32, device=dev))
+        if ws is None:
+            ws = torch.empty(LIB.db_query_com_workspace_bytes(self._h, nq, n_cand),
+                             dtype=torch.uint8, device=dev)
+        idx, score, counts, ci, cd = out
+        _check(LIB.db_query_com(self._h, nq, q_labels.data_ptr(), n_cand, k, idx.data_ptr(),
+                                score.data_ptr(), _ptr(counts), _ptr(ci), _ptr(cd), ws.data_ptr(),
+                                ws.numel(), _stream(stream)))
+        return out
 
     def query_batch(self, q_labels: torch.Tensor, rois, k: int, with_counts: bool = True,
                     out=None, ws: torch.Tensor | None = None, stream=None):

@@ -78,9 +78,11 @@ WsLayout ws_layout(const db_t *db, int nq, int k, bool batched)
         return o;
     };
     L.qpack = take((size_t)nq * 2 * db->g.Wp * 4);
-    L.qpart = take((size_t)nq * kQueryParts * 2 * 4);
+    L.qpart = take((size_t)nq * kQueryParts * sizeof(QueryPart));
     L.acnt = take((size_t)nq * 2 * 4);
     L.rois = take((size_t)nq * 6 * 4);
+    L.qbox = take((size_t)nq * 4 * 4);
+    L.qmom = take((size_t)nq * 4 * 8);
     L.inter = take((size_t)nq * cap * 2 * 4);
     L.bcnt = batched ? take((size_t)nq * cap * 2 * 4) : off;
     // plan: query order [nq], 8 queue counters, slab list offsets [nq * nz + 1] and
@@ -189,8 +191,10 @@ static hipError_t enqueue_batch(const db_t *db, int nq, const uint8_t *q_labels,
     int32_t *counters = order + nq;
     int32_t *list_off = counters + 8;
     int32_t *list_q = list_off + (size_t)nq * db->g.nz + 1;
-    hipError_t e = launch_pack_queries(db, q_labels, nq, rois, qpack, at<uint32_t>(ws, L.qpart), s);
-    if (e == hipSuccess) e = launch_sum_parts(at<uint32_t>(ws, L.qpart), nq, acnt, s);
+    QueryPart *qpart = at<QueryPart>(ws, L.qpart);
+    hipError_t e = launch_pack_queries(db, q_labels, nq, rois, qpack, qpart, s);
+    if (e == hipSuccess)
+        e = launch_sum_parts(qpart, nq, acnt, at<int32_t>(ws, L.qbox), at<uint64_t>(ws, L.qmom), s);
     if (e == hipSuccess) e = launch_fill_u32(counters, 8, 0, s);
     if (e == hipSuccess)
         e = launch_batch_scan(db, db->count, nq, P, qpack, rois, order, list_off, list_q, counters,
@@ -226,7 +230,8 @@ size_t db_storage_bytes(int nx, int ny, int nz, int64_t capacity)
     if (!make_geometry(nx, ny, nz, &g) || capacity <= 0 || capacity > INT32_MAX)
         return 0;
     return align_up((size_t)capacity * 2 * g.Wp * 4, kAlign) +
-           align_up((size_t)capacity * 2 * 4, kAlign);
+           align_up((size_t)capacity * 2 * 4, kAlign) + align_up((size_t)capacity * 4 * 4, kAlign) +
+           align_up((size_t)capacity * 4 * 8, kAlign);
 }
 
 int db_build(db_t **out, int nx, int ny, int nz, float t_lo, float t_hi, int64_t capacity,
@@ -266,8 +271,12 @@ int db_build(db_t **out, int nx, int ny, int nz, float t_lo, float t_hi, int64_t
     db->capacity = capacity;
     db->count = 0;
     db->planes = static_cast<uint32_t *>(storage);
-    db->popcnt = reinterpret_cast<uint32_t *>(static_cast<char *>(storage) +
-                                              align_up((size_t)capacity * 2 * g.Wp * 4, kAlign));
+    const size_t o_pc = align_up((size_t)capacity * 2 * g.Wp * 4, kAlign);
+    const size_t o_box = o_pc + align_up((size_t)capacity * 2 * 4, kAlign);
+    const size_t o_mom = o_box + align_up((size_t)capacity * 4 * 4, kAlign);
+    db->popcnt = reinterpret_cast<uint32_t *>(static_cast<char *>(storage) + o_pc);
+    db->box = reinterpret_cast<int32_t *>(static_cast<char *>(storage) + o_box);
+    db->mom = reinterpret_cast<uint64_t *>(static_cast<char *>(storage) + o_mom);
     db->storage_bytes = storage_bytes;
     db->cus = cus;
     db->device = dev;
@@ -295,6 +304,8 @@ int db_append(db_t *db, const float *conc, int64_t n, void *stream)
     uint32_t *planes = db->planes + db->count * 2 * (int64_t)db->g.Wp;
     uint32_t *pc = db->popcnt + db->count * 2;
     hipError_t e = launch_pack_db(db, conc, n, planes, pc, s);
+    if (e == hipSuccess)
+        e = launch_meta(planes, n, db->g, db->box + db->count * 4, db->mom + db->count * 4, s);
     if (e != hipSuccess) return hip_fail(e, "db_append: launch");
     db->count += n;
     return DB_OK;
@@ -318,11 +329,11 @@ int db_scan(const db_t *db, const uint8_t *q_labels, uint32_t *inter, uint32_t *
     if (ws_bytes < L.total)
         return fail(DB_ENOSPC, "db_scan: workspace %zu bytes < %zu needed", ws_bytes, L.total);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = launch_pack_queries(db, q_labels, 1, nullptr, at<uint32_t>(ws, L.qpack),
-                                       at<uint32_t>(ws, L.qpart), s);
+    QueryPart *qpart = at<QueryPart>(ws, L.qpart);
+    hipError_t e = launch_pack_queries(db, q_labels, 1, nullptr, at<uint32_t>(ws, L.qpack), qpart, s);
     if (e == hipSuccess)
-        e = launch_sum_parts(at<uint32_t>(ws, L.qpart), 1,
-                             qcount ? qcount : at<uint32_t>(ws, L.acnt), s);
+        e = launch_sum_parts(qpart, 1, qcount ? qcount : at<uint32_t>(ws, L.acnt),
+                             at<int32_t>(ws, L.qbox), at<uint64_t>(ws, L.qmom), s);
     if (e == hipSuccess) e = prof_mark(db, s);
     if (e == hipSuccess) e = launch_scan(db, db->count, at<uint32_t>(ws, L.qpack), inter, s);
     if (e == hipSuccess) e = prof_mark(db, s);
@@ -345,9 +356,10 @@ int db_query(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx, doubl
     hipStream_t s = static_cast<hipStream_t>(stream);
     uint32_t *inter = at<uint32_t>(ws, L.inter);
     uint32_t *acnt = at<uint32_t>(ws, L.acnt);
-    hipError_t e = launch_pack_queries(db, q_labels, 1, nullptr, at<uint32_t>(ws, L.qpack),
-                                       at<uint32_t>(ws, L.qpart), s);
-    if (e == hipSuccess) e = launch_sum_parts(at<uint32_t>(ws, L.qpart), 1, acnt, s);
+    QueryPart *qpart = at<QueryPart>(ws, L.qpart);
+    hipError_t e = launch_pack_queries(db, q_labels, 1, nullptr, at<uint32_t>(ws, L.qpack), qpart, s);
+    if (e == hipSuccess)
+        e = launch_sum_parts(qpart, 1, acnt, at<int32_t>(ws, L.qbox), at<uint64_t>(ws, L.qmom), s);
     if (e == hipSuccess) e = prof_mark(db, s);
     if (e == hipSuccess) e = launch_scan(db, db->count, at<uint32_t>(ws, L.qpack), inter, s);
     if (e == hipSuccess) e = prof_mark(db, s);
@@ -372,6 +384,54 @@ int db_query(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx, doubl
         e = launch_topk(a, s);
     }
     if (e != hipSuccess) return hip_fail(e, "db_query: launch");
+    return DB_OK;
+}
+
+int db_query_sparse(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx, double *score,
+                    db_counts_t *counts, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_query_common("db_query_sparse", db, q_labels, ws);
+    if (rc) return rc;
+    if (k < 1 || k > DB_KMAX || k > db->count)
+        return fail(DB_EINVAL, "db_query_sparse: k = %d outside [1, min(%lld, %d)]", k,
+                    (long long)db->count, DB_KMAX);
+    if (!idx || !score) return fail(DB_EINVAL, "db_query_sparse: idx and score must be non-NULL");
+    const WsLayout L = ws_layout(db, 1, k, true);
+    if (ws_bytes < L.total)
+        return fail(DB_ENOSPC, "db_query_sparse: workspace %zu bytes < %zu needed", ws_bytes,
+                    L.total);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint32_t *qpack = at<uint32_t>(ws, L.qpack);
+    uint32_t *inter = at<uint32_t>(ws, L.inter);
+    uint32_t *acnt = at<uint32_t>(ws, L.acnt);
+    int32_t *qbox = at<int32_t>(ws, L.qbox);
+    QueryPart *qpart = at<QueryPart>(ws, L.qpart);
+    hipError_t e = launch_pack_queries(db, q_labels, 1, nullptr, qpack, qpart, s);
+    if (e == hipSuccess) e = launch_sum_parts(qpart, 1, acnt, qbox, at<uint64_t>(ws, L.qmom), s);
+    if (e == hipSuccess) e = prof_mark(db, s);
+    if (e == hipSuccess) e = launch_box_scan(db, db->count, qpack, qbox, inter, s);
+    if (e == hipSuccess) e = prof_mark(db, s);
+    if (e == hipSuccess) {
+        TopkArgs a{};
+        a.n = db->count;
+        a.nq = 1;
+        a.k = k;
+        a.inter = inter;
+        a.inter_qstride = 0;
+        a.bcnt = db->popcnt;
+        a.bcnt_qstride = 0;
+        a.acnt = acnt;
+        a.buf_s[0] = at<uint64_t>(ws, L.topk_a);
+        a.buf_s[1] = at<uint64_t>(ws, L.topk_b);
+        const size_t cand = topk_blocks(db->capacity) * (size_t)k;
+        a.buf_i[0] = reinterpret_cast<int32_t *>(a.buf_s[0] + cand);
+        a.buf_i[1] = reinterpret_cast<int32_t *>(a.buf_s[1] + cand);
+        a.out_idx = idx;
+        a.out_score = score;
+        a.out_counts = counts;
+        e = launch_topk(a, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "db_query_sparse: launch");
     return DB_OK;
 }
 
@@ -582,7 +642,7 @@ int emb_topk_min(int M, int N, const float *D, int k, int32_t *idx, float *d, vo
 
 // Rerank workspace: packed queries, per-block counts, query counts, row boxes.
 static size_t rerank_layout(const db_t *db, int nq, size_t *o_qpack, size_t *o_qpart,
-                            size_t *o_acnt, size_t *o_box)
+                            size_t *o_acnt, size_t *o_box, size_t *o_mom = nullptr)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -591,9 +651,11 @@ static size_t rerank_layout(const db_t *db, int nq, size_t *o_qpack, size_t *o_q
         return o;
     };
     *o_qpack = take((size_t)nq * 2 * db->g.Wp * 4);
-    *o_qpart = take((size_t)nq * kQueryParts * 2 * 4);
+    *o_qpart = take((size_t)nq * kQueryParts * sizeof(QueryPart));
     *o_acnt = take((size_t)nq * 2 * 4);
     *o_box = take((size_t)nq * 4 * 4);
+    const size_t om = take((size_t)nq * 4 * 8);
+    if (o_mom) *o_mom = om;
     return off;
 }
 
@@ -608,14 +670,14 @@ static hipError_t enqueue_rerank(const db_t *db, int nq, const uint8_t *q_labels
                                  const int32_t *cand, int nc, int k, int32_t *idx, double *score,
                                  db_counts_t *counts, void *ws, hipStream_t s)
 {
-    size_t oq, op, oa, ob;
-    rerank_layout(db, nq, &oq, &op, &oa, &ob);
+    size_t oq, op, oa, ob, om;
+    rerank_layout(db, nq, &oq, &op, &oa, &ob, &om);
     uint32_t *qpack = at<uint32_t>(ws, oq);
     uint32_t *acnt = at<uint32_t>(ws, oa);
     int32_t *box = at<int32_t>(ws, ob);
-    hipError_t e = launch_pack_queries(db, q_labels, nq, nullptr, qpack, at<uint32_t>(ws, op), s);
-    if (e == hipSuccess) e = launch_sum_parts(at<uint32_t>(ws, op), nq, acnt, s);
-    if (e == hipSuccess) e = launch_query_rowbox(db, nq, qpack, box, s);
+    QueryPart *qpart = at<QueryPart>(ws, op);
+    hipError_t e = launch_pack_queries(db, q_labels, nq, nullptr, qpack, qpart, s);
+    if (e == hipSuccess) e = launch_sum_parts(qpart, nq, acnt, box, at<uint64_t>(ws, om), s);
     if (e == hipSuccess) e = launch_rerank(db, nq, qpack, acnt, box, cand, nc, k, idx, score, counts, s);
     return e;
 }
@@ -692,6 +754,58 @@ int db_query_embed(const db_t *db, int fmt, int nq, int dim, const void *q_codes
     return DB_OK;
 }
 
+// ---- centre-of-mass prefilter + exact rerank ----
+
+static size_t com_layout(const db_t *db, int nq, int n_cand, size_t *o_D, size_t *o_ci,
+                         size_t *o_cd, size_t *o_rr)
+{
+    return embed_layout(db, nq, n_cand, o_D, o_ci, o_cd, o_rr);
+}
+
+size_t db_query_com_workspace_bytes(const db_t *db, int nq, int n_cand)
+{
+    if (!live(db) || nq <= 0 || n_cand <= 0) return 0;
+    size_t a, b, c, d;
+    return com_layout(db, nq, n_cand, &a, &b, &c, &d);
+}
+
+int db_query_com(const db_t *db, int nq, const uint8_t *q_labels, int n_cand, int k, int32_t *idx,
+                 double *score, db_counts_t *counts, int32_t *cand_idx, float *cand_d, void *ws,
+                 size_t ws_bytes, void *stream)
+{
+    int rc = check_query_common("db_query_com", db, q_labels, ws);
+    if (rc) return rc;
+    const int64_t n = db->count;
+    if (nq <= 0 || nq > 65535 || n_cand < 1 || n_cand > DB_KMAX || n_cand > n || k < 1 ||
+        k > n_cand || !idx || !score || n > INT32_MAX)
+        return fail(DB_EINVAL, "db_query_com: bad arguments (nq %d, n_cand %d, k %d)", nq,
+                    n_cand, k);
+    size_t oD, oci, ocd, orr;
+    const size_t need = com_layout(db, nq, n_cand, &oD, &oci, &ocd, &orr);
+    if (ws_bytes < need)
+        return fail(DB_ENOSPC, "db_query_com: workspace %zu bytes < %zu needed", ws_bytes, need);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float *D = at<float>(ws, oD);
+    int32_t *ci = cand_idx ? cand_idx : at<int32_t>(ws, oci);
+    float *cd = cand_d ? cand_d : at<float>(ws, ocd);
+    char *rr = at<char>(ws, orr);
+    size_t oq, op, oa, ob, om;
+    rerank_layout(db, nq, &oq, &op, &oa, &ob, &om);
+    uint32_t *qpack = at<uint32_t>(rr, oq);
+    uint32_t *acnt = at<uint32_t>(rr, oa);
+    int32_t *box = at<int32_t>(rr, ob);
+    uint64_t *qmom = at<uint64_t>(rr, om);
+    QueryPart *qpart = at<QueryPart>(rr, op);
+    hipError_t e = launch_pack_queries(db, q_labels, nq, nullptr, qpack, qpart, s);
+    if (e == hipSuccess) e = launch_sum_parts(qpart, nq, acnt, box, qmom, s);
+    if (e == hipSuccess) e = launch_com_dist(nq, qmom, db->mom, (int)n, D, s);
+    if (e == hipSuccess) e = launch_topk_min(nq, (int)n, n_cand, D, ci, cd, s);
+    if (e == hipSuccess)
+        e = launch_rerank(db, nq, qpack, acnt, box, ci, n_cand, k, idx, score, counts, s);
+    if (e != hipSuccess) return hip_fail(e, "db_query_com: launch");
+    return DB_OK;
+}
+
 // ---- order-0 resampling ----
 
 // Output voxel o of an axis of n_out samples reads source voxel
@@ -723,7 +837,11 @@ int db_append_resampled(db_t *dst, const db_t *src, int64_t first, int64_t n, vo
         !fill_map(maps.z, src->g.nz, dst->g.nz))
         return fail(DB_EINVAL, "db_append_resampled: output axes must be 1..%d voxels",
                     kMaxResample);
-    hipError_t e = launch_resample_db(src, first, n, dst, maps, static_cast<hipStream_t>(stream));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_resample_db(src, first, n, dst, maps, s);
+    if (e == hipSuccess)
+        e = launch_meta(dst->planes + dst->count * 2 * (int64_t)dst->g.Wp, n, dst->g,
+                        dst->box + dst->count * 4, dst->mom + dst->count * 4, s);
     if (e != hipSuccess) return hip_fail(e, "db_append_resampled: launch");
     dst->count += n;
     return DB_OK;

@@ -39,6 +39,39 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
     return v;
 }
 
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = min(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = max(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+// Sum over the bits set in word v of their positions 0..31: a position is the
+// sum of its binary digits 2^j, so count, for every digit j, the set bits whose
+// position has that digit.
+__device__ __forceinline__ uint32_t bit_position_sum(uint32_t v)
+{
+    return popc(v & 0xAAAAAAAAu) + 2u * popc(v & 0xCCCCCCCCu) + 4u * popc(v & 0xF0F0F0F0u) +
+           8u * popc(v & 0xFF00FF00u) + 16u * popc(v & 0xFFFF0000u);
+}
+
 // Block-wide sum of two counters; the result is valid in thread 0.
 // lds must hold 2 * (blockDim.x / 64) words.
 __device__ __forceinline__ void block_sum2(uint32_t &a, uint32_t &b, uint32_t *lds)

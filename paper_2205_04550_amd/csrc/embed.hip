@@ -423,69 +423,16 @@ __global__ void __launch_bounds__(kSelThreads) topk_min_kernel(const float *__re
 
 // ---- exact rerank ---------------------------------------------------------------------------
 
-// Rows (z, y) holding any set bit of either query mask: box [z0, z1) x [y0, y1).
-// grid nq, 256 threads.
-__global__ void __launch_bounds__(256) query_rowbox_kernel(const uint32_t *__restrict__ qpack,
-                                                           int Wp, int nxw, int ny, int nz,
-                                                           int32_t *__restrict__ box)
-{
-    __shared__ int red[4][4];
-    const int q = blockIdx.x;
-    const uint32_t *Q0 = qpack + (int64_t)q * 2 * Wp, *Q1 = Q0 + Wp;
-    const int rows = ny * nz;
-    int zlo = INT_MAX, zhi = -1, ylo = INT_MAX, yhi = -1;
-    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
-        uint32_t any = 0;
-        for (int w = 0; w < nxw; ++w) any |= Q0[r * nxw + w] | Q1[r * nxw + w];
-        if (any) {
-            const int z = r / ny, y = r - z * ny;
-            zlo = min(zlo, z);
-            zhi = max(zhi, z);
-            ylo = min(ylo, y);
-            yhi = max(yhi, y);
-        }
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        zlo = min(zlo, __shfl_xor(zlo, o, 64));
-        zhi = max(zhi, __shfl_xor(zhi, o, 64));
-        ylo = min(ylo, __shfl_xor(ylo, o, 64));
-        yhi = max(yhi, __shfl_xor(yhi, o, 64));
-    }
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        red[w][0] = zlo;
-        red[w][1] = zhi;
-        red[w][2] = ylo;
-        red[w][3] = yhi;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 1; i < 4; ++i) {
-            zlo = min(zlo, red[i][0]);
-            zhi = max(zhi, red[i][1]);
-            ylo = min(ylo, red[i][2]);
-            yhi = max(yhi, red[i][3]);
-        }
-        int32_t *b = box + 4 * q;
-        if (zhi < 0) {
-            b[0] = b[1] = b[2] = b[3] = 0;   // empty query: no rows
-        } else {
-            b[0] = zlo;
-            b[1] = zhi + 1;
-            b[2] = ylo;
-            b[3] = yhi + 1;
-        }
-    }
-}
-
 constexpr int kRerankMaxCand = 1024;
 
 // grid nq, 256 threads (4 waves). Wave w scores candidates w, w + 4, ...: lanes
-// sweep the query's row box, AND + popcount against the candidate's planes;
-// then the block ranks the candidates by (score desc, index asc) and writes k.
+// sweep the rows where the query's row box meets the candidates' stored row
+// boxes (outside either box one side is zero and adds nothing), AND +
+// popcount against the candidate's planes; then the block ranks the
+// candidates by (score desc, index asc) and writes k.
 __global__ void __launch_bounds__(256) rerank_kernel(const uint32_t *__restrict__ planes,
-                                                     const uint32_t *__restrict__ popcnt, int Wp,
+                                                     const uint32_t *__restrict__ popcnt,
+                                                     const int32_t *__restrict__ ebox, int Wp,
                                                      int nxw, int ny, const uint32_t *__restrict__ qpack,
                                                      const uint32_t *__restrict__ acnt,
                                                      const int32_t *__restrict__ box,
@@ -501,43 +448,64 @@ __global__ void __launch_bounds__(256) rerank_kernel(const uint32_t *__restrict_
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const uint32_t *Q0 = qpack + (int64_t)q * 2 * Wp, *Q1 = Q0 + Wp;
     const int32_t *b = box + 4 * q;
-    const int z0 = b[0], z1 = b[1], y0 = b[2], y1 = b[3];
-    const int nyr = y1 - y0;
-    const int nr = (z1 - z0) * nyr;
+    const int qz0 = b[0], qz1 = b[1], qy0 = b[2], qy1 = b[3];
     const uint32_t A0 = acnt[2 * q], A1 = acnt[2 * q + 1];
-    // Candidates in groups of kRC per wave: each query row is loaded once per group.
+    // Candidates in groups of kRC per wave: each query row is loaded once per group
+    // and the group sweeps the union of its members' boxes (each clipped to the
+    // query's); a member reads only the rows inside its own box.
     constexpr int kRC = 4;
     for (int c0 = wave * kRC; c0 < nc; c0 += nwaves * kRC) {
         const uint32_t *D0[kRC], *D1[kRC];
+        int z0[kRC], z1[kRC], y0[kRC], y1[kRC];
+        int uz0 = INT_MAX, uz1 = INT_MIN, uy0 = INT_MAX, uy1 = INT_MIN;
 #pragma unroll
         for (int j = 0; j < kRC; ++j) {
             const int c = min(c0 + j, nc - 1);          // a repeated candidate is discarded
             const int32_t e = cand[(int64_t)q * nc + c];
             D0[j] = planes + (int64_t)e * 2 * Wp;
             D1[j] = D0[j] + Wp;
+            const int32_t *eb = ebox + 4 * (int64_t)e;
+            z0[j] = max(eb[0], qz0);
+            z1[j] = min(eb[1], qz1);
+            y0[j] = max(eb[2], qy0);
+            y1[j] = min(eb[3], qy1);
+            if (z1[j] > z0[j] && y1[j] > y0[j]) {
+                uz0 = min(uz0, z0[j]);
+                uz1 = max(uz1, z1[j]);
+                uy0 = min(uy0, y0[j]);
+                uy1 = max(uy1, y1[j]);
+            }
         }
+        const int nyr = uy1 > uy0 ? uy1 - uy0 : 0;
+        const int nr = uz1 > uz0 ? (uz1 - uz0) * nyr : 0;
         uint32_t i0[kRC], i1[kRC];
 #pragma unroll
         for (int j = 0; j < kRC; ++j) i0[j] = i1[j] = 0;
         for (int r = lane; r < nr; r += 64) {
             const int zr = r / nyr;
-            const int base = ((z0 + zr) * ny + (y0 + r - zr * nyr)) * nxw;
+            const int z = uz0 + zr, y = uy0 + r - zr * nyr;
+            const int base = (z * ny + y) * nxw;
+            bool in[kRC];
+#pragma unroll
+            for (int j = 0; j < kRC; ++j) in[j] = z >= z0[j] && z < z1[j] && y >= y0[j] && y < y1[j];
             if (nxw == 4) {
                 const u32x4 qa = *reinterpret_cast<const u32x4 *>(Q0 + base);
                 const u32x4 qb = *reinterpret_cast<const u32x4 *>(Q1 + base);
 #pragma unroll
-                for (int j = 0; j < kRC; ++j) {
-                    i0[j] += popc_and4(qa, *reinterpret_cast<const u32x4 *>(D0[j] + base));
-                    i1[j] += popc_and4(qb, *reinterpret_cast<const u32x4 *>(D1[j] + base));
-                }
+                for (int j = 0; j < kRC; ++j)
+                    if (in[j]) {
+                        i0[j] += popc_and4(qa, *reinterpret_cast<const u32x4 *>(D0[j] + base));
+                        i1[j] += popc_and4(qb, *reinterpret_cast<const u32x4 *>(D1[j] + base));
+                    }
             } else {
                 for (int w = 0; w < nxw; ++w) {
                     const uint32_t qa = Q0[base + w], qb = Q1[base + w];
 #pragma unroll
-                    for (int j = 0; j < kRC; ++j) {
-                        i0[j] += popc(qa & D0[j][base + w]);
-                        i1[j] += popc(qb & D1[j][base + w]);
-                    }
+                    for (int j = 0; j < kRC; ++j)
+                        if (in[j]) {
+                            i0[j] += popc(qa & D0[j][base + w]);
+                            i1[j] += popc(qb & D1[j][base + w]);
+                        }
                 }
             }
         }
@@ -639,22 +607,13 @@ hipError_t launch_topk_min(int M, int N, int k, const float *D, int32_t *idx, fl
     return hipGetLastError();
 }
 
-hipError_t launch_query_rowbox(const db_t *db, int nq, const uint32_t *qpack, int32_t *box,
-                               hipStream_t s)
-{
-    const Geometry &g = db->g;
-    hipLaunchKernelGGL(query_rowbox_kernel, dim3(nq), dim3(256), 0, s, qpack, g.Wp, g.nxw, g.ny,
-                       g.nz, box);
-    return hipGetLastError();
-}
-
 hipError_t launch_rerank(const db_t *db, int nq, const uint32_t *qpack, const uint32_t *acnt,
                          const int32_t *box, const int32_t *cand, int nc, int k, int32_t *idx,
                          double *score, db_counts_t *counts, hipStream_t s)
 {
     const Geometry &g = db->g;
-    hipLaunchKernelGGL(rerank_kernel, dim3(nq), dim3(256), 0, s, db->planes, db->popcnt, g.Wp,
-                       g.nxw, g.ny, qpack, acnt, box, cand, nc, k, idx, score, counts);
+    hipLaunchKernelGGL(rerank_kernel, dim3(nq), dim3(256), 0, s, db->planes, db->popcnt, db->box,
+                       g.Wp, g.nxw, g.ny, qpack, acnt, box, cand, nc, k, idx, score, counts);
     return hipGetLastError();
 }
 

@@ -42,6 +42,8 @@ struct db_t {
     int64_t capacity, count;
     uint32_t *planes;   // [capacity][2][Wp]
     uint32_t *popcnt;   // [capacity][2]
+    int32_t *box;       // [capacity][4] row box z0, z1, y0, y1 of the set bits
+    uint64_t *mom;      // [capacity][4] FLAIR moments: sum x, sum y, sum z, count
     size_t storage_bytes;
     int cus;                 // compute units of the device the handle was built on
     int device;
@@ -57,15 +59,24 @@ namespace tdb {
 // Offsets of the pieces of a query workspace (bytes from its base).
 struct WsLayout {
     size_t qpack;    // uint32 [nq][2][Wp] packed (and ROI-masked) queries
-    size_t qpart;    // uint32 [nq][kQueryParts][2] per-block query counts
+    size_t qpart;    // QueryPart [nq][kQueryParts] per-block query partials
     size_t acnt;     // uint32 [nq][2] query counts |A_m (n R)|
     size_t rois;     // int32 [nq][6] ROI boxes (batched calls)
+    size_t qbox;     // int32 [nq][4] row boxes of the packed queries
+    size_t qmom;     // uint64 [nq][4] FLAIR moments of the packed queries
     size_t inter;    // uint32 [nq][capacity][2] intersections
     size_t bcnt;     // uint32 [nq][capacity][2] database counts inside the ROI (batched)
     size_t plan;     // int32: query order [nq], queue counters [8], slab lists (batched)
     size_t topk_a;   // ping-pong top-k candidate buffers: uint64 score bits + int32 index
     size_t topk_b;
     size_t total;
+};
+
+// What one block of the query-pack kernel found in its share of a query's words.
+struct QueryPart {
+    uint32_t cnt[2];   // set bits of the FLAIR and T1Gd masks
+    int32_t box[4];    // z min, z max, y min, y max of rows with a set bit (INT_MAX/-1: none)
+    uint64_t mom[3];   // sum of x, y, z over the FLAIR bits
 };
 
 WsLayout ws_layout(const db_t *db, int nq, int k, bool batched);
@@ -75,8 +86,11 @@ int64_t topk_blocks(int64_t n);
 hipError_t launch_pack_db(const db_t *db, const float *conc, int64_t n, uint32_t *planes,
                           uint32_t *popcnt, hipStream_t s);
 hipError_t launch_pack_queries(const db_t *db, const uint8_t *labels, int nq, const int32_t *rois,
-                               uint32_t *qpack, uint32_t *qpart, hipStream_t s);
-hipError_t launch_sum_parts(const uint32_t *qpart, int nq, uint32_t *acnt, hipStream_t s);
+                               uint32_t *qpack, QueryPart *qpart, hipStream_t s);
+// Per query: counts acnt [nq][2], row box qbox [nq][4] (z0, z1, y0, y1; all zero when
+// empty) and FLAIR moments qmom [nq][4] (sum x, sum y, sum z, count).
+hipError_t launch_sum_parts(const QueryPart *qpart, int nq, uint32_t *acnt, int32_t *qbox,
+                            uint64_t *qmom, hipStream_t s);
 hipError_t launch_scan(const db_t *db, int64_t n, const uint32_t *qpack, uint32_t *inter,
                        hipStream_t s);
 // Shape of a batched launch: LDS slabs of Z planes (use_lds) or the L2 fallback.
@@ -105,11 +119,17 @@ hipError_t launch_dist_fp8(int M, int N, int K, const uint8_t *Q, const float *q
                            hipStream_t s);
 hipError_t launch_topk_min(int M, int N, int k, const float *D, int32_t *idx, float *d,
                            hipStream_t s);
-hipError_t launch_query_rowbox(const db_t *db, int nq, const uint32_t *qpack, int32_t *box,
-                               hipStream_t s);
 hipError_t launch_rerank(const db_t *db, int nq, const uint32_t *qpack, const uint32_t *acnt,
                          const int32_t *box, const int32_t *cand, int nc, int k, int32_t *idx,
                          double *score, db_counts_t *counts, hipStream_t s);
+
+// Row boxes, moments, box-restricted scan, centre-of-mass distances (sparse.hip).
+hipError_t launch_meta(const uint32_t *recs, int64_t n, const Geometry &g, int32_t *box,
+                       uint64_t *mom, hipStream_t s);
+hipError_t launch_box_scan(const db_t *db, int64_t n, const uint32_t *qpack, const int32_t *qbox,
+                           uint32_t *inter, hipStream_t s);
+hipError_t launch_com_dist(int nq, const uint64_t *qmom, const uint64_t *mom, int n, float *D,
+                           hipStream_t s);
 
 // Order-0 resampling (resample.hip): source index of every output voxel per axis.
 constexpr int kMaxResample = 256;

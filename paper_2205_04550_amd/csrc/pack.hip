@@ -5,6 +5,8 @@
 // extracted by thresholding at a lower and a higher level. Here each mask is
 // stored as one bit per voxel (LSB-first in uint32 words, x fastest), which
 // is all a Dice overlap needs and is 32x smaller than float32.
+#include <limits.h>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -88,21 +90,27 @@ __device__ __forceinline__ uint32_t roi_word_mask(const int32_t *r, int w, int n
     return m;
 }
 
-// grid (kQueryParts, nq): labels uint8 [nq][V] -> packed [nq][2][Wp] and
-// per-block counts [nq][kQueryParts][2]. With rois, bits outside the box
-// are cleared, so later overlaps need no masking of the query side.
+// grid (kQueryParts, nq): labels uint8 [nq][V] -> packed [nq][2][Wp] and one
+// QueryPart per block: the block's mask counts, the row range of its set bits
+// and the FLAIR moments (for the row-box scan and the centre-of-mass key).
+// With rois, bits outside the box are cleared first, so later overlaps need no
+// masking of the query side.
 __global__ void __launch_bounds__(256) pack_query_kernel(const uint8_t *__restrict__ labels,
                                                          int64_t V, int W, int Wp, int nxw, int ny,
                                                          const int32_t *__restrict__ rois,
                                                          uint32_t *__restrict__ qpack,
-                                                         uint32_t *__restrict__ qpart)
+                                                         QueryPart *__restrict__ qpart)
 {
-    __shared__ uint32_t red[2 * 4];
+    __shared__ uint32_t rc[4][2];
+    __shared__ int rb[4][4];
+    __shared__ uint64_t rm[4][3];
     const int q = blockIdx.y;
     const u32x4 *lab = reinterpret_cast<const u32x4 *>(labels + (int64_t)q * V);
     uint32_t *o = qpack + (int64_t)q * 2 * Wp;
     const int32_t *r = rois ? rois + 6 * q : nullptr;
     uint32_t n0 = 0, n1 = 0;
+    int zlo = INT_MAX, zhi = -1, ylo = INT_MAX, yhi = -1;
+    uint64_t sx = 0, sy = 0, sz = 0;
     for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < Wp; w += gridDim.x * blockDim.x) {
         uint32_t b0 = 0, b1 = 0;
         if (w < W) {
@@ -126,22 +134,74 @@ __global__ void __launch_bounds__(256) pack_query_kernel(const uint8_t *__restri
                 b0 &= m;
                 b1 &= m;
             }
+            if (b0 | b1) {
+                const int row = w / nxw;
+                const int wx = w - row * nxw;
+                const int z = row / ny, y = row - z * ny;
+                zlo = min(zlo, z);
+                zhi = max(zhi, z);
+                ylo = min(ylo, y);
+                yhi = max(yhi, y);
+                const uint32_t c = popc(b0);
+                sx += (uint64_t)(32u * (uint32_t)wx) * c + bit_position_sum(b0);
+                sy += (uint64_t)y * c;
+                sz += (uint64_t)z * c;
+            }
         }
         o[w] = b0;
         o[Wp + w] = b1;
         n0 += popc(b0);
         n1 += popc(b1);
     }
-    block_sum2(n0, n1, red);
+    n0 = wave_sum(n0);
+    n1 = wave_sum(n1);
+    zlo = wave_min(zlo);
+    ylo = wave_min(ylo);
+    zhi = wave_max(zhi);
+    yhi = wave_max(yhi);
+    sx = wave_sum64(sx);
+    sy = wave_sum64(sy);
+    sz = wave_sum64(sz);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        rc[wv][0] = n0;
+        rc[wv][1] = n1;
+        rb[wv][0] = zlo;
+        rb[wv][1] = zhi;
+        rb[wv][2] = ylo;
+        rb[wv][3] = yhi;
+        rm[wv][0] = sx;
+        rm[wv][1] = sy;
+        rm[wv][2] = sz;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t *p = qpart + ((int64_t)q * kQueryParts + blockIdx.x) * 2;
-        p[0] = n0;
-        p[1] = n1;
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+            n0 += rc[i][0];
+            n1 += rc[i][1];
+            zlo = min(zlo, rb[i][0]);
+            zhi = max(zhi, rb[i][1]);
+            ylo = min(ylo, rb[i][2]);
+            yhi = max(yhi, rb[i][3]);
+            sx += rm[i][0];
+            sy += rm[i][1];
+            sz += rm[i][2];
+        }
+        QueryPart &p = qpart[(int64_t)q * kQueryParts + blockIdx.x];
+        p.cnt[0] = n0;
+        p.cnt[1] = n1;
+        p.box[0] = zlo;
+        p.box[1] = zhi;
+        p.box[2] = ylo;
+        p.box[3] = yhi;
+        p.mom[0] = sx;
+        p.mom[1] = sy;
+        p.mom[2] = sz;
     }
 }
 
 hipError_t launch_pack_queries(const db_t *db, const uint8_t *labels, int nq, const int32_t *rois,
-                               uint32_t *qpack, uint32_t *qpart, hipStream_t s)
+                               uint32_t *qpack, QueryPart *qpart, hipStream_t s)
 {
     const Geometry &g = db->g;
     hipLaunchKernelGGL(pack_query_kernel, dim3(kQueryParts, nq), dim3(256), 0, s, labels, g.V,
@@ -149,26 +209,61 @@ hipError_t launch_pack_queries(const db_t *db, const uint8_t *labels, int nq, co
     return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(64) sum_parts_kernel(const uint32_t *__restrict__ qpart,
-                                                      uint32_t *__restrict__ acnt)
+// One wave per query: combine its kQueryParts partials.
+__global__ void __launch_bounds__(64) sum_parts_kernel(const QueryPart *__restrict__ qpart,
+                                                      uint32_t *__restrict__ acnt,
+                                                      int32_t *__restrict__ qbox,
+                                                      uint64_t *__restrict__ qmom)
 {
     const int q = blockIdx.x;
     uint32_t a = 0, b = 0;
+    int zlo = INT_MAX, zhi = -1, ylo = INT_MAX, yhi = -1;
+    uint64_t sx = 0, sy = 0, sz = 0;
     for (int i = threadIdx.x; i < kQueryParts; i += 64) {
-        a += qpart[((int64_t)q * kQueryParts + i) * 2];
-        b += qpart[((int64_t)q * kQueryParts + i) * 2 + 1];
+        const QueryPart &p = qpart[(int64_t)q * kQueryParts + i];
+        a += p.cnt[0];
+        b += p.cnt[1];
+        zlo = min(zlo, p.box[0]);
+        zhi = max(zhi, p.box[1]);
+        ylo = min(ylo, p.box[2]);
+        yhi = max(yhi, p.box[3]);
+        sx += p.mom[0];
+        sy += p.mom[1];
+        sz += p.mom[2];
     }
     a = wave_sum(a);
     b = wave_sum(b);
+    zlo = wave_min(zlo);
+    ylo = wave_min(ylo);
+    zhi = wave_max(zhi);
+    yhi = wave_max(yhi);
+    sx = wave_sum64(sx);
+    sy = wave_sum64(sy);
+    sz = wave_sum64(sz);
     if (threadIdx.x == 0) {
         acnt[2 * q] = a;
         acnt[2 * q + 1] = b;
+        int32_t *bx = qbox + 4 * q;
+        if (zhi < 0) {
+            bx[0] = bx[1] = bx[2] = bx[3] = 0;   // no set bit: an empty box
+        } else {
+            bx[0] = zlo;
+            bx[1] = zhi + 1;
+            bx[2] = ylo;
+            bx[3] = yhi + 1;
+        }
+        uint64_t *m = qmom + 4 * q;
+        m[0] = sx;
+        m[1] = sy;
+        m[2] = sz;
+        m[3] = a;
     }
 }
 
-hipError_t launch_sum_parts(const uint32_t *qpart, int nq, uint32_t *acnt, hipStream_t s)
+hipError_t launch_sum_parts(const QueryPart *qpart, int nq, uint32_t *acnt, int32_t *qbox,
+                            uint64_t *qmom, hipStream_t s)
 {
-    hipLaunchKernelGGL(sum_parts_kernel, dim3(nq), dim3(64), 0, s, qpart, acnt);
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(nq), dim3(64), 0, s, qpart, acnt, qbox, qmom);
     return hipGetLastError();
 }
 

@@ -291,3 +291,69 @@ def test_resample_nearest_pins():
     a = oracle.resample_nearest(oracle.threshold(c, synth.T_LO, synth.T_HI), (32, 32, 32))
     b = oracle.threshold(oracle.resample_nearest(c, (32, 32, 32)), synth.T_LO, synth.T_HI)
     assert np.array_equal(a, b)
+
+
+def test_moments_rowbox_com_pins():
+    """Moments, row boxes and centre-of-mass keys against closed forms and brute force."""
+    nz, ny, nx = 6, 5, 64
+    lab = np.zeros((nz, ny, nx), np.uint8)
+    assert oracle.moments(lab) == (0, 0, 0, 0)
+    assert oracle.rowbox(lab) == (0, 0, 0, 0)
+    lab[4, 2, 37] = 1
+    assert oracle.moments(lab) == (37, 2, 4, 1)
+    assert oracle.rowbox(lab) == (4, 5, 2, 3)
+    # A T1Gd-only voxel widens the row box but is not part of the FLAIR moments.
+    lab[1, 0, 3] = 2
+    assert oracle.moments(lab) == (37, 2, 4, 1)
+    assert oracle.rowbox(lab) == (1, 5, 0, 3)
+    # Box [x0,x1) x [y0,y1) x [z0,z1): sum x = (area of the other two sides) * sum_{x0}^{x1-1} x.
+    box = np.zeros((nz, ny, nx), np.uint8)
+    x0, x1, y0, y1, z0, z1 = 5, 40, 1, 4, 2, 6
+    box[z0:z1, y0:y1, x0:x1] = 3
+    nxb, nyb, nzb = x1 - x0, y1 - y0, z1 - z0
+    sx = nyb * nzb * (x0 + x1 - 1) * nxb // 2
+    sy = nxb * nzb * (y0 + y1 - 1) * nyb // 2
+    sz = nxb * nyb * (z0 + z1 - 1) * nzb // 2
+    assert oracle.moments(box) == (sx, sy, sz, nxb * nyb * nzb)
+    assert oracle.rowbox(box) == (z0, z1, y0, y1)
+    # Brute-force loop over every voxel.
+    rng = np.random.default_rng(5)
+    r = (rng.random((nz, ny, nx)) < 0.1).astype(np.uint8) * rng.integers(1, 4, (nz, ny, nx),
+                                                                          dtype=np.uint8)
+    bx = by = bz = bc = 0
+    rows = set()
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                if r[z, y, x] & 1:
+                    bx, by, bz, bc = bx + x, by + y, bz + z, bc + 1
+                if r[z, y, x] & 3:
+                    rows.add((z, y))
+    assert oracle.moments(r) == (bx, by, bz, bc)
+    zs = [a for a, _ in rows]
+    ys = [b for _, b in rows]
+    assert oracle.rowbox(r) == (min(zs), max(zs) + 1, min(ys), max(ys) + 1)
+    # Keys: a 3-4-5 triangle; empty masks rank last.
+    assert oracle.com_key((3, 4, 0, 1), (0, 0, 0, 1)) == np.float32(25.0)
+    assert oracle.com_key((0, 0, 0, 0), (1, 1, 1, 1)) == np.float32(np.inf)
+    assert oracle.com_key((2, 2, 2, 2), (1, 1, 1, 1)) == 0.0
+
+
+def test_query_com_all_candidates_is_the_exact_query():
+    """With every entry a candidate the prefilter changes nothing: the exact top-k."""
+    rng = np.random.default_rng(11)
+    n, shape = 30, (4, 6, 32)
+    labs = np.stack([(rng.random(shape) < p).astype(np.uint8) * 1 +
+                     (rng.random(shape) < p / 3).astype(np.uint8) * 2
+                     for p in rng.uniform(0.02, 0.3, n)])
+    labs[7] = labs[3]              # an exact duplicate: the lower index must win
+    q = labs[3].copy()
+    cand, keys, top, sc, cnt = oracle.query_com(q, labs, n, 5)
+    exact = [oracle.score(oracle.counts(q, labs[i])) for i in range(n)]
+    assert list(top) == oracle.rank(exact, 5)
+    assert top[0] == 3 and sc[0] == 2.0
+    assert sorted(cand.tolist()) == list(range(n))
+    assert np.all(np.diff(keys) >= 0)
+    # Candidates are the n_cand smallest keys, ties by index.
+    cand4, keys4, *_ = oracle.query_com(q, labs, 4, 2)
+    assert list(cand4[:2]) == [3, 7] and keys4[0] == keys4[1] == 0.0
