@@ -334,6 +334,9 @@ def synth_t():
     return synth.T_LO, synth.T_HI
 
 
+HASH_GAMMA = 3.0   # weight of the Bi-half layer's pull of latents towards their codes
+
+
 def bench_embed(args, db, gen, n, build_s) -> int:
     """Held-out queries through encoder, BF16 MFMA distances, top-100 and exact rerank."""
     import numpy as np
@@ -417,6 +420,57 @@ def bench_embed(args, db, gen, n, build_s) -> int:
     top_n = {f"top{t}": float(np.mean([ex[q, 0] in got[q, :t] for q in range(nq)])) for t in (1, 5, 15)}
     cand_recall = float(np.mean([len(set(ci[q].cpu().numpy()) & set(ex[q, :10])) / 10
                                  for q in range(min(nq, 256))]))
+    # Other codes of the same search: FP8 latents of this encoder, and the hashing
+    # variant (an encoder trained with the Bi-half layer, Hamming search on its codes).
+    ex = ex_idx.cpu().numpy()
+
+    def leg(name, fmt, encode_q, Xl):
+        for _ in range(max(1, args.warmup)):
+            o = db.query_embed(fmt, encode_q(), Xl, lab_d, n_cand, k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            o = db.query_embed(fmt, encode_q(), Xl, lab_d, n_cand, k, out=o)
+        torch.cuda.synchronize()
+        lms = (time.perf_counter() - t0) * 1e3 / args.steps
+        g = o[0].cpu().numpy()
+        r = {"ms_per_batch": lms, "queries_per_s": nq / (lms * 1e-3),
+             "recall_at_10": float(np.mean([len(set(g[q, :10]) & set(ex[q, :10])) / 10
+                                            for q in range(nq)])),
+             **{f"top{t}": float(np.mean([ex[q, 0] in g[q, :t] for q in range(nq)]))
+                for t in (1, 5, 15)}}
+        log(f"{name}: {r['queries_per_s']:.0f} q/s, recall@10 {r['recall_at_10']:.3f}, "
+            f"Top-1/5/15 {r['top1']:.3f}/{r['top5']:.3f}/{r['top15']:.3f}")
+        return r
+
+    variants = {}
+    X8 = B.Latents(lat, B.EMB_FP8)
+
+    def enc_fp8():
+        with torch.no_grad():
+            return B.Latents(model.encode(nn.meanpool_labels(lab_d)), B.EMB_FP8)
+    variants["fp8_latents"] = leg("FP8 latents", B.EMB_FP8, enc_fp8, X8)
+    del X8
+    log(f"training the hashing encoder (Bi-half layer) for {args.train_steps} steps of 32")
+    model_h = nn.AutoEncoder(grid=gen.nx // 2, latent=512, seed=1, hash_gamma=HASH_GAMMA)
+    t0 = time.perf_counter()
+    _, losses_h = train_encoder(model_h, db, n, args.train_steps, 32)
+    torch.cuda.synchronize()
+    hash_train_s = time.perf_counter() - t0
+    with torch.no_grad():
+        for s0 in range(0, n, 500):
+            idx_b = torch.arange(s0, min(n, s0 + 500), dtype=torch.int32, device="cuda")
+            lat[s0:s0 + idx_b.numel()] = model_h.encode(nn.meanpool_db(db, idx_b))
+    Xh = B.BinaryCodes(lat)
+
+    def enc_hash():
+        with torch.no_grad():
+            return B.BinaryCodes(model_h.encode(nn.meanpool_labels(lab_d)), Xh.thr)
+    variants["bf_hash_512bit"] = leg("Bi-half codes (Hamming)", B.EMB_BIN, enc_hash, Xh)
+    variants["bf_hash_512bit"].update({"train_s": hash_train_s, "gamma": HASH_GAMMA,
+                                       "train_loss_first_last": [losses_h[0], losses_h[-1]]})
+    del Xh
+
     cpu = None
     if args.cpu_seconds > 0:
         log("timing the CPU oracle on a sample of the queries")
@@ -447,6 +501,7 @@ def bench_embed(args, db, gen, n, build_s) -> int:
                      "frac": gemm_flop / (stage[1] * 1e-3) / BF16_MFMA_PEAK, "traffic": None,
                      "kernel": "dist_bf16_kernel", "kernel_avg_ms": stage[1],
                      "dominant_stage": names[dom]},
+        "variants": variants,
         "cpu_baseline": cpu, "build_s": build_s, "train_s": train_s,
         "encode_db_s": encode_db_s, "train_loss_first_last": [losses[0], losses[-1]],
     }

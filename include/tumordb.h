@@ -148,7 +148,7 @@ int db_tune_batch(db_t *db, int slab_planes, int block_threads);
  * of the database latents belongs to entry i. Distances are the squared L2
  * distance in the expanded form |q|^2 + |x|^2 - 2 q.x, accumulated in FP32 on
  * the matrix cores (BF16, or FP8 e4m3 with a per-row scale). */
-enum { EMB_BF16 = 0, EMB_FP8 = 1 };
+enum { EMB_BF16 = 0, EMB_FP8 = 1, EMB_BIN = 2 };
 
 /* Quantise FP32 latents lat [n][dim] (device): EMB_BF16 writes uint16 codes
  * (round to nearest even); EMB_FP8 writes uint8 OCP e4m3 codes of lat/s with
@@ -159,10 +159,28 @@ int emb_quantize(int64_t n, int dim, const float *lat, int fmt, void *codes, flo
                  float *sqnorm, void *stream);
 
 /* D[m][n] = q_sq[m] + x_sq[n] - 2 <q_m, x_n> (FP32, device [M][N]); the
- * scales multiply the FP8 dot products and are ignored for BF16. */
+ * scales multiply the FP8 dot products and are ignored for BF16. EMB_BIN:
+ * codes are dim-bit strings (uint32 [.][dim/32], see emb_binarize) and
+ * D[m][n] is their Hamming distance as a float (exact); scales and squared
+ * norms are ignored (may be NULL). dim % 32 == 0 and dim <= 1024 for EMB_BIN. */
 int emb_distances(int fmt, int M, int N, int dim, const void *q_codes, const float *q_scale,
                   const float *q_sq, const void *x_codes, const float *x_scale, const float *x_sq,
                   float *D, void *stream);
+
+/* Binary codes (the paper's unsupervised hashing query, Sec. 2.3): its
+ * Bi-half layer makes, per latent coordinate, the larger half of a batch +1 and
+ * the rest -1, and codes are compared by L2, which for +-1 vectors is 4x their
+ * Hamming distance. Here bit d of a code (LSB first in uint32 words; 1 = +1)
+ * is lat[d] > thr[d], with thr[d] the lower median of coordinate d over the
+ * database (the Bi-half rule with the database as the batch); queries use the
+ * database's thresholds.
+ * emb_hash_thresholds: thr[d] = value of 0-based rank (n - 1) / 2 in
+ * ascending order of column d of lat [n][dim] (device; exact selection).
+ * emb_binarize: codes [n][dim/32] (device uint32). dim % 32 == 0, dim <= 1024,
+ * lat and thr 16-byte aligned. */
+int emb_hash_thresholds(int64_t n, int dim, const float *lat, float *thr, void *stream);
+int emb_binarize(int64_t n, int dim, const float *lat, const float *thr, uint32_t *codes,
+                 void *stream);
 
 /* Per row of D [M][N]: the k smallest values, ties by lower column, in
  * ascending order: idx [M][k] (int32), d [M][k]. 1 <= k <= min(N, DB_KMAX). */

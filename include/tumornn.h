@@ -107,6 +107,17 @@ int nn_mse_bwd(int dtype, int64_t n, const void *A, const void *B, const void *g
 int nn_adam_step(int64_t n, float *w, float *m, float *v, const float *g, uint16_t *w_bf16,
                  float lr, float b1, float b2, float eps, int t, void *stream);
 
+/* The Bi-half hash layer of the paper's hashing autoencoder (Sec. 2.3): for
+ * U [B][D] (NN_F32 or NN_F64), out[i][d] = +1 if row i is among the first
+ * floor(B/2) rows of column d ordered by (value desc, row asc), else -1.
+ * Backward (a surrogate, the layer is piecewise constant): the incoming
+ * gradient passes straight through, plus a pull of U towards its code:
+ * dU = G + gamma * ((U - Bc) / (B * D)), each operation rounded in the dtype
+ * in that order. B <= 4096. */
+int nn_bihalf_fwd(int dtype, int B, int D, const void *U, void *out, void *stream);
+int nn_bihalf_bwd(int dtype, int B, int D, double gamma, const void *U, const void *Bc,
+                  const void *G, void *dU, void *stream);
+
 /* FP32 -> BF16 bits, round to nearest even (NaN stays NaN). */
 int nn_to_bf16(int64_t n, const float *x, uint16_t *y, void *stream);
 

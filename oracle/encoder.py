@@ -126,3 +126,52 @@ def e4m3_encode(v: np.ndarray) -> np.ndarray:
             c = 0x80 if np.signbit(x) else 0x00
         res[i] = c
     return out
+
+
+# ---- binary codes (the paper's unsupervised hashing query, Sec. 2.3) ----
+
+def hash_thresholds(X: np.ndarray) -> np.ndarray:
+    """Per column of X [n][dim] the value of 0-based rank (n - 1) // 2 in ascending order
+    (the lower median): a full sort per column."""
+    X = np.asarray(X, dtype=np.float32)
+    return np.sort(X, axis=0)[(X.shape[0] - 1) // 2].astype(np.float32)
+
+
+def binarize(X: np.ndarray, thr: np.ndarray) -> np.ndarray:
+    """uint32 codes [n][dim/32]: bit d (LSB first) = X[d] > thr[d]."""
+    bits = np.asarray(X, dtype=np.float32) > np.asarray(thr, dtype=np.float32)[None, :]
+    return np.packbits(bits, axis=1, bitorder="little").view("<u4")
+
+
+def hamming(Qc: np.ndarray, Xc: np.ndarray) -> np.ndarray:
+    """float32 [M][N]: number of differing bits of every pair of codes."""
+    Q = np.asarray(Qc).view(np.uint8)
+    X = np.asarray(Xc).view(np.uint8)
+    out = np.empty((Q.shape[0], X.shape[0]), dtype=np.float32)
+    for m in range(Q.shape[0]):
+        out[m] = np.unpackbits(Q[m][None, :] ^ X, axis=1).sum(axis=1)
+    return out
+
+
+def bihalf_forward(U: np.ndarray) -> np.ndarray:
+    """Bi-half layer: per column, the floor(B/2) rows first by (value desc, row asc) -> +1,
+    the others -> -1 (same dtype as U)."""
+    U = np.asarray(U)
+    B, D = U.shape
+    out = -np.ones_like(U)
+    for d in range(D):
+        order = sorted(range(B), key=lambda i: (-float(U[i, d]), i))
+        out[order[:B // 2], d] = 1
+    return out
+
+
+def bihalf_backward(U: np.ndarray, Bc: np.ndarray, G: np.ndarray, gamma: float) -> np.ndarray:
+    """Straight-through gradient plus the pull towards the code:
+    G + gamma * ((U - Bc) / (B * D)), each step rounded in U's dtype."""
+    U = np.asarray(U)
+    t = U.dtype.type
+    B, D = U.shape
+    diff = U - np.asarray(Bc, dtype=U.dtype)
+    scaled = diff / t(B * D)
+    pull = t(gamma) * scaled
+    return np.asarray(G, dtype=U.dtype) + pull

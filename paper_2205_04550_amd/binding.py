@@ -22,8 +22,9 @@ SYMBOLS = ("db_storage_bytes", "db_build", "db_append", "db_size", "db_query_wor
            "db_profile", "db_profile_read", "emb_quantize", "emb_distances", "emb_topk_min",
            "db_rerank_workspace_bytes", "db_rerank", "db_query_embed_workspace_bytes",
            "db_query_embed", "db_tune_batch", "db_append_resampled", "labels_resample",
-           "db_query_sparse", "db_query_com_workspace_bytes", "db_query_com")
-EMB_BF16, EMB_FP8 = 0, 1
+           "db_query_sparse", "db_query_com_workspace_bytes", "db_query_com",
+           "emb_hash_thresholds", "emb_binarize")
+EMB_BF16, EMB_FP8, EMB_BIN = 0, 1, 2
 
 
 class DbError(RuntimeError):
@@ -65,6 +66,8 @@ def _load():
         "emb_quantize": (i32, [i64, i32, vp, i32, vp, vp, vp, vp]),
         "emb_distances": (i32, [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
         "emb_topk_min": (i32, [i32, i32, vp, i32, vp, vp, vp]),
+        "emb_hash_thresholds": (i32, [i64, i32, vp, vp, vp]),
+        "emb_binarize": (i32, [i64, i32, vp, vp, vp, vp]),
         "db_rerank_workspace_bytes": (sz, [vp, i32]),
         "db_rerank": (i32, [vp, i32, vp, vp, i32, i32, vp, vp, vp, vp, sz, vp]),
         "db_query_embed_workspace_bytes": (sz, [vp, i32, i32]),
@@ -295,7 +298,7 @@ class TumorDB:
                              dtype=torch.uint8, device=dev)
         idx, score, counts, ci, cd = out
         _check(LIB.db_query_embed(self._h, fmt, nq, q.dim, q.codes.data_ptr(), _ptr(q.scale),
-                                  q.sq.data_ptr(), x.codes.data_ptr(), _ptr(x.scale), x.sq.data_ptr(),
+                                  _ptr(q.sq), x.codes.data_ptr(), _ptr(x.scale), _ptr(x.sq),
                                   q_labels.data_ptr(), n_cand, k, idx.data_ptr(), score.data_ptr(),
                                   counts.data_ptr(), ci.data_ptr(), cd.data_ptr(), ws.data_ptr(),
                                   ws.numel(), _stream(stream)))
@@ -357,12 +360,39 @@ class Latents:
                                 self.sq.data_ptr(), _stream(stream)))
 
 
-def emb_distances(q: Latents, x: Latents, out: torch.Tensor | None = None, stream=None):
-    """Squared L2 distances [nq][n] (FP32) of quantised latents, expanded form on MFMA."""
+class BinaryCodes:
+    """Hash codes on the device: codes int32 [n][dim/32] holding uint32 words (bit d = lat[d] >
+    thr[d]), with the per-coordinate thresholds thr [dim] they were made with."""
+
+    def __init__(self, lat: torch.Tensor, thr: torch.Tensor | None = None, stream=None):
+        lat = lat.to(torch.float32).contiguous()
+        n, dim = lat.shape
+        self.fmt, self.n, self.dim = EMB_BIN, n, dim
+        self.scale = self.sq = None
+        if thr is None:
+            thr = hash_thresholds(lat, stream)
+        self.thr = thr.contiguous()
+        self.codes = torch.empty((n, dim // 32), dtype=torch.int32, device=lat.device)
+        _check(LIB.emb_binarize(n, dim, lat.data_ptr(), self.thr.data_ptr(), self.codes.data_ptr(),
+                                _stream(stream)))
+
+
+def hash_thresholds(lat: torch.Tensor, stream=None) -> torch.Tensor:
+    """Per coordinate the lower median of lat [n][dim] (the database's Bi-half split)."""
+    lat = lat.to(torch.float32).contiguous()
+    n, dim = lat.shape
+    thr = torch.empty(dim, dtype=torch.float32, device=lat.device)
+    _check(LIB.emb_hash_thresholds(n, dim, lat.data_ptr(), thr.data_ptr(), _stream(stream)))
+    return thr
+
+
+def emb_distances(q, x, out: torch.Tensor | None = None, stream=None):
+    """[nq][n] FP32: squared L2 of quantised latents (expanded form on MFMA), or the Hamming
+    distance of BinaryCodes."""
     if out is None:
         out = torch.empty((q.n, x.n), dtype=torch.float32, device=q.codes.device)
     _check(LIB.emb_distances(q.fmt, q.n, x.n, q.dim, q.codes.data_ptr(), _ptr(q.scale),
-                             q.sq.data_ptr(), x.codes.data_ptr(), _ptr(x.scale), x.sq.data_ptr(),
+                             _ptr(q.sq), x.codes.data_ptr(), _ptr(x.scale), _ptr(x.sq),
                              out.data_ptr(), _stream(stream)))
     return out
 

@@ -9,6 +9,7 @@
 #include <numeric>
 #include <vector>
 
+#include "../../include/tumornn.h"
 #include "internal.hpp"
 
 namespace {
@@ -606,12 +607,18 @@ int emb_distances(int fmt, int M, int N, int dim, const void *q_codes, const flo
                   const float *q_sq, const void *x_codes, const float *x_scale, const float *x_sq,
                   float *D, void *stream)
 {
-    if (M <= 0 || N <= 0 || dim <= 0 || !q_codes || !q_sq || !x_codes || !x_sq || !D ||
-        (M + 127) / 128 > 65535)
+    if (M <= 0 || N <= 0 || dim <= 0 || !q_codes || !x_codes || !D || (M + 127) / 128 > 65535)
         return fail(DB_EINVAL, "emb_distances: bad arguments");
+    if (fmt != EMB_BIN && (!q_sq || !x_sq))
+        return fail(DB_EINVAL, "emb_distances: squared norms are required");
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e;
-    if (fmt == EMB_BF16) {
+    if (fmt == EMB_BIN) {
+        if (dim % 32 || dim > 1024)
+            return fail(DB_EINVAL, "emb_distances: binary codes need dim %% 32 == 0, <= 1024");
+        e = launch_hamming(M, N, dim / 32, static_cast<const uint32_t *>(q_codes),
+                           static_cast<const uint32_t *>(x_codes), D, s);
+    } else if (fmt == EMB_BF16) {
         if (dim % 16) return fail(DB_EINVAL, "emb_distances: BF16 needs dim %% 16 == 0");
         if (!aligned(q_codes, 16) || !aligned(x_codes, 16))
             return fail(DB_EINVAL, "emb_distances: codes must be 16-byte aligned");
@@ -628,6 +635,48 @@ int emb_distances(int fmt, int M, int N, int dim, const void *q_codes, const flo
         return fail(DB_EINVAL, "emb_distances: unknown format %d", fmt);
     }
     if (e != hipSuccess) return hip_fail(e, "emb_distances: launch");
+    return DB_OK;
+}
+
+int emb_hash_thresholds(int64_t n, int dim, const float *lat, float *thr, void *stream)
+{
+    if (n <= 0 || dim <= 0 || dim > 65535 || !lat || !thr)
+        return fail(DB_EINVAL, "emb_hash_thresholds: bad arguments");
+    hipError_t e = launch_col_kth(lat, n, dim, (n - 1) / 2, thr, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "emb_hash_thresholds: launch");
+    return DB_OK;
+}
+
+int emb_binarize(int64_t n, int dim, const float *lat, const float *thr, uint32_t *codes,
+                 void *stream)
+{
+    if (n <= 0 || dim <= 0 || dim % 32 || dim > 1024 || !lat || !thr || !codes ||
+        !aligned(lat, 16) || !aligned(thr, 16))
+        return fail(DB_EINVAL, "emb_binarize: bad arguments (dim %d; dim %% 32 == 0, <= 1024, "
+                    "16-byte aligned inputs)", dim);
+    hipError_t e = launch_binarize(lat, n, dim, thr, codes, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "emb_binarize: launch");
+    return DB_OK;
+}
+
+int nn_bihalf_fwd(int dtype, int B, int D, const void *U, void *out, void *stream)
+{
+    if ((dtype != NN_F32 && dtype != NN_F64) || B <= 0 || B > 4096 || D <= 0 || !U || !out)
+        return fail(DB_EINVAL, "nn_bihalf_fwd: bad arguments");
+    hipError_t e = launch_bihalf_fwd(dtype == NN_F64, B, D, U, out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "nn_bihalf_fwd: launch");
+    return DB_OK;
+}
+
+int nn_bihalf_bwd(int dtype, int B, int D, double gamma, const void *U, const void *Bc,
+                  const void *G, void *dU, void *stream)
+{
+    if ((dtype != NN_F32 && dtype != NN_F64) || B <= 0 || B > 4096 || D <= 0 || !U || !Bc ||
+        !G || !dU)
+        return fail(DB_EINVAL, "nn_bihalf_bwd: bad arguments");
+    hipError_t e = launch_bihalf_bwd(dtype == NN_F64, B, D, gamma, U, Bc, G, dU,
+                                     static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "nn_bihalf_bwd: launch");
     return DB_OK;
 }
 

@@ -72,6 +72,21 @@ __device__ __forceinline__ uint32_t bit_position_sum(uint32_t v)
            8u * popc(v & 0xFF00FF00u) + 16u * popc(v & 0xFFFF0000u);
 }
 
+// Order-preserving map of a float to uint32 (negative values flipped); -0 is
+// folded onto +0 first so that equal values compare equal.
+__device__ __forceinline__ uint32_t fkey(float f)
+{
+    if (f == 0.0f) f = 0.0f;
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float fkey_inv(uint32_t k)
+{
+    const uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
+    return __uint_as_float(u);
+}
+
 // Block-wide sum of two counters; the result is valid in thread 0.
 // lds must hold 2 * (blockDim.x / 64) words.
 __device__ __forceinline__ void block_sum2(uint32_t &a, uint32_t &b, uint32_t *lds)

@@ -274,21 +274,6 @@ __global__ void __launch_bounds__(256) dist_fp8_kernel(int M, int N, int K,
 
 // ---- exact k smallest per row (radix select) ----------------------------------------------
 
-// Order-preserving map of a float to uint32 (negative values flipped); -0 is
-// folded onto +0 first so that equal values compare equal.
-__device__ __forceinline__ uint32_t fkey(float f)
-{
-    if (f == 0.0f) f = 0.0f;
-    const uint32_t u = __float_as_uint(f);
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-
-__device__ __forceinline__ float fkey_inv(uint32_t k)
-{
-    const uint32_t u = (k & 0x80000000u) ? (k & 0x7fffffffu) : ~k;
-    return __uint_as_float(u);
-}
-
 constexpr int kSelThreads = 1024;
 constexpr int kSelMaxK = 1024;
 

@@ -131,6 +131,16 @@ hipError_t launch_box_scan(const db_t *db, int64_t n, const uint32_t *qpack, con
 hipError_t launch_com_dist(int nq, const uint64_t *qmom, const uint64_t *mom, int n, float *D,
                            hipStream_t s);
 
+// Binary codes, Hamming distances, Bi-half layer (hash.hip).
+hipError_t launch_col_kth(const float *X, int64_t n, int dim, int64_t k, float *thr, hipStream_t s);
+hipError_t launch_binarize(const float *X, int64_t n, int dim, const float *thr, uint32_t *codes,
+                           hipStream_t s);
+hipError_t launch_hamming(int M, int N, int words, const uint32_t *Q, const uint32_t *X, float *D,
+                          hipStream_t s);
+hipError_t launch_bihalf_fwd(bool f64, int B, int D, const void *U, void *out, hipStream_t s);
+hipError_t launch_bihalf_bwd(bool f64, int B, int D, double gamma, const void *U, const void *Bc,
+                             const void *G, void *dU, hipStream_t s);
+
 // Order-0 resampling (resample.hip): source index of every output voxel per axis.
 constexpr int kMaxResample = 256;
 struct ResampleMaps {

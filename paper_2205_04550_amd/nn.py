@@ -44,6 +44,8 @@ _SIGS = {
     "nn_mse_bwd": (_i32, [_i32, _i64, _vp, _vp, _vp, _vp, _vp]),
     "nn_adam_step": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _f32, _f32, _f32, _f32, _i32, _vp]),
     "nn_to_bf16": (_i32, [_i64, _vp, _vp, _vp]),
+    "nn_bihalf_fwd": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp]),
+    "nn_bihalf_bwd": (_i32, [_i32, _i32, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]),
 }
 for _n, (_r, _a) in _SIGS.items():
     _f = getattr(LIB, _n)
@@ -261,6 +263,32 @@ class MSE(torch.autograd.Function):
         return da, None
 
 
+class BiHalf(torch.autograd.Function):
+    """The Bi-half hash layer (Sec. 2.3, unsupervised hashing): per coordinate the larger half
+    of the batch -> +1, the rest -> -1; backward passes the gradient straight through plus
+    gamma * (U - B) / (B * D)."""
+
+    @staticmethod
+    def forward(ctx, u, gamma):
+        u = _c(u)
+        B, D = u.shape
+        b = torch.empty_like(u)
+        _check(LIB.nn_bihalf_fwd(_dt(u), B, D, u.data_ptr(), b.data_ptr(), _s()))
+        ctx.save_for_backward(u, b)
+        ctx.gamma = float(gamma)
+        return b
+
+    @staticmethod
+    def backward(ctx, g):
+        u, b = ctx.saved_tensors
+        g = _c(g.to(u.dtype))
+        du = torch.empty_like(u)
+        B, D = u.shape
+        _check(LIB.nn_bihalf_bwd(_dt(u), B, D, ctx.gamma, u.data_ptr(), b.data_ptr(), g.data_ptr(),
+                                 du.data_ptr(), _s()))
+        return du, None
+
+
 # ---- model ----------------------------------------------------------------------------------
 
 class AutoEncoder:
@@ -271,9 +299,12 @@ class AutoEncoder:
     """
 
     def __init__(self, grid: int = 64, channels=(2, 8, 16, 32, 64), latent: int = 512,
-                 dtype=torch.float32, device="cuda", seed: int = 0):
+                 dtype=torch.float32, device="cuda", seed: int = 0, hash_gamma: float | None = None):
         assert grid % 16 == 0
         self.grid, self.channels, self.latent = grid, tuple(channels), latent
+        # With hash_gamma the decoder reads the Bi-half codes of the latent (the paper's
+        # hashing autoencoder); without, the latent itself.
+        self.hash_gamma = hash_gamma
         self.dtype = dtype
         self.bf16 = dtype == torch.float32
         g = torch.Generator().manual_seed(seed)
@@ -339,7 +370,10 @@ class AutoEncoder:
         return h
 
     def forward(self, x: torch.Tensor) -> torch.Tensor:
-        return self.decode(self.encode(x))
+        z = self.encode(x)
+        if self.hash_gamma is not None:
+            z = BiHalf.apply(z, self.hash_gamma)
+        return self.decode(z)
 
     def loss(self, x: torch.Tensor) -> torch.Tensor:
         return MSE.apply(self.forward(x), x)

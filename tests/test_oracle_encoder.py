@@ -108,3 +108,42 @@ def test_bf16_encode_pins():
     x = np.random.default_rng(0).standard_normal(1000).astype(np.float32)
     d = E.bf16_decode(E.bf16_encode(x))
     assert np.all(np.abs(d - x) <= np.abs(x) * 2.0 ** -8)
+
+
+def test_hash_oracle_pins():
+    """Thresholds, codes, Hamming distances and the Bi-half layer against hand values and
+    the identities that tie them to the paper's L2 ranking of +-1 codes."""
+    # Lower median: rank (n - 1) // 2.
+    X = np.array([[3, 4], [1, 1], [2, 3], [5, 2], [4, 5]], np.float32)
+    assert E.hash_thresholds(X).tolist() == [3.0, 3.0]
+    assert E.hash_thresholds(X[:4]).tolist() == [2.0, 2.0]
+    # Bits: x > t, LSB first; a ramp around 0 sets the upper 16 bits.
+    ramp = (np.arange(32, dtype=np.float32) - 15.5)[None, :]
+    assert E.binarize(ramp, np.zeros(32, np.float32)).tolist() == [[0xFFFF0000]]
+    # Distinct values: every coordinate splits the rows in two halves.
+    rng = np.random.default_rng(0)
+    for n in (8, 9):
+        Y = rng.standard_normal((n, 64)).astype(np.float32)
+        c = E.binarize(Y, E.hash_thresholds(Y))
+        bits = np.unpackbits(c.view(np.uint8), axis=1, bitorder="little")
+        assert np.all(bits.sum(axis=0) == n // 2)
+        # The Bi-half layer over the same rows gives the same split (+1 <-> bit 1).
+        assert np.array_equal(E.bihalf_forward(Y) > 0, bits.astype(bool))
+    # Hamming: 0 to itself, dim to the complement; 4 x Hamming = |b_q - b_x|^2 of the
+    # +-1 vectors, so Hamming ranks like the paper's L2 on binary codes.
+    Q = E.binarize(rng.standard_normal((5, 96)).astype(np.float32), np.zeros(96, np.float32))
+    Xc = E.binarize(rng.standard_normal((7, 96)).astype(np.float32), np.zeros(96, np.float32))
+    assert np.all(np.diag(E.hamming(Q, Q)) == 0)
+    assert np.all(np.diag(E.hamming(Q, (~Q.view(np.uint32)).view("<u4"))) == 96)
+    pm = lambda c: np.unpackbits(c.view(np.uint8), axis=1, bitorder="little").astype(np.float64) * 2 - 1
+    l2 = ((pm(Q)[:, None, :] - pm(Xc)[None, :, :]) ** 2).sum(-1)
+    assert np.array_equal(4 * E.hamming(Q, Xc).astype(np.float64), l2)
+    # Bi-half ties: equal values go to the lower row first; odd B gives floor(B/2) ones.
+    T = np.array([[1.0], [1.0], [1.0], [0.0], [1.0]], np.float32)
+    assert E.bihalf_forward(T)[:, 0].tolist() == [1, 1, -1, -1, -1]
+    # Backward by hand: B = D = 2, gamma = 4 -> dU = G + (U - B).
+    U = np.array([[0.5, -1.0], [2.0, 0.0]], np.float64)
+    Bc = E.bihalf_forward(U)
+    assert Bc.tolist() == [[-1, -1], [1, 1]]
+    dU = E.bihalf_backward(U, Bc, np.ones_like(U), 4.0)
+    assert dU.tolist() == [[2.5, 1.0], [2.0, 0.0]]
