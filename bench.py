@@ -245,7 +245,7 @@ def model_macs(model) -> int:
     return macs
 
 
-def train_encoder(model, db, n: int, steps: int, batch: int, seed: int = 7):
+def train_encoder(model, db, n: int, steps: int, batch: int, seed: int = 7, mask=None):
     import torch
     from paper_2205_04550_amd import nn
     opt = nn.Adam(model, lr=1e-3)
@@ -253,7 +253,7 @@ def train_encoder(model, db, n: int, steps: int, batch: int, seed: int = 7):
     losses = []
     for _ in range(steps):
         idx = torch.randint(0, n, (batch,), generator=g).to(torch.int32).cuda()
-        losses.append(nn.train_step(model, opt, nn.meanpool_db(db, idx)))
+        losses.append(nn.train_step(model, opt, nn.meanpool_db(db, idx, mask=mask)))
     return opt, [float(l) for l in losses]
 
 
@@ -335,6 +335,7 @@ def synth_t():
 
 
 HASH_GAMMA = 3.0   # weight of the Bi-half layer's pull of latents towards their codes
+VAE_BETA = 1e-5    # KL weight against the per-voxel mean MSE (about 2.6 against a voxel sum)
 
 
 def bench_embed(args, db, gen, n, build_s) -> int:
@@ -470,6 +471,56 @@ def bench_embed(args, db, gen, n, build_s) -> int:
     variants["bf_hash_512bit"].update({"train_s": hash_train_s, "gamma": HASH_GAMMA,
                                        "train_loss_first_last": [losses_h[0], losses_h[-1]]})
     del Xh
+
+    # The paper's own formulation: separate T1Gd and FLAIR encoders, distance
+    # L2_T1Gd + L2_FLAIR; plain autoencoders and variational ones (search on the mean).
+    for tag, kw in (("two_ae_l2sum", {}), ("two_vae_l2sum", {"vae_beta": VAE_BETA})):
+        log(f"training two single-mask encoders ({tag}) for {args.train_steps} steps of 32 each")
+        t0 = time.perf_counter()
+        pair, Xs, rec = [], [], []
+        for m in (1, 0):                                  # T1Gd, then FLAIR
+            mdl = nn.AutoEncoder(grid=gen.nx // 2, channels=(1, 8, 16, 32, 64), latent=512,
+                                 seed=2 + m, **kw)
+            _, lm = train_encoder(mdl, db, n, args.train_steps, 32, mask=m)
+            rec.append([lm[0], lm[-1]])
+            with torch.no_grad():
+                for s0 in range(0, n, 500):
+                    idx_b = torch.arange(s0, min(n, s0 + 500), dtype=torch.int32, device="cuda")
+                    lat[s0:s0 + idx_b.numel()] = mdl.encode(nn.meanpool_db(db, idx_b, mask=m))
+            Xs.append(B.Latents(lat, B.EMB_BF16))
+            pair.append((mdl, m))
+        torch.cuda.synchronize()
+        tr_s = time.perf_counter() - t0
+
+        def step_pair():
+            with torch.no_grad():
+                qs = [B.Latents(mdl.encode(nn.meanpool_labels(lab_d, mask=m)), B.EMB_BF16)
+                      for mdl, m in pair]
+            D = B.emb_distances_l2sum(qs[0], Xs[0], qs[1], Xs[1], out=Dbuf)
+            ci2, _ = B.emb_topk_min(D, n_cand)
+            return db.rerank(lab_d, ci2, k)
+
+        for _ in range(max(1, args.warmup)):
+            o = step_pair()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            o = step_pair()
+        torch.cuda.synchronize()
+        lms = (time.perf_counter() - t0) * 1e3 / args.steps
+        g2 = o[0].cpu().numpy()
+        r = {"ms_per_batch": lms, "queries_per_s": nq / (lms * 1e-3),
+             "recall_at_10": float(np.mean([len(set(g2[q, :10]) & set(ex[q, :10])) / 10
+                                            for q in range(nq)])),
+             **{f"top{t}": float(np.mean([ex[q, 0] in g2[q, :t] for q in range(nq)]))
+                for t in (1, 5, 15)},
+             "train_s": tr_s, "recon_loss_first_last_t1gd_flair": rec}
+        if "vae_beta" in kw:
+            r["beta"] = kw["vae_beta"]
+        log(f"{tag}: {r['queries_per_s']:.0f} q/s, recall@10 {r['recall_at_10']:.3f}, "
+            f"Top-1/5/15 {r['top1']:.3f}/{r['top5']:.3f}/{r['top15']:.3f}")
+        variants[tag] = r
+        del Xs, pair
 
     cpu = None
     if args.cpu_seconds > 0:

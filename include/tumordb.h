@@ -167,6 +167,19 @@ int emb_distances(int fmt, int M, int N, int dim, const void *q_codes, const flo
                   const float *q_sq, const void *x_codes, const float *x_scale, const float *x_sq,
                   float *D, void *stream);
 
+/* The paper's two-encoder distance (Sec. 2.3): separate FLAIR and T1Gd
+ * autoencoders give two latent sets, and a database entry's distance is the
+ * sum of the two L2 distances, L2_T1Gd + L2_FLAIR (lowest wins):
+ * D[m][n] = sqrt(max(d1, 0)) + sqrt(max(d2, 0)) with d1, d2 the squared
+ * distances emb_distances computes for the pairs (q1, x1) and (q2, x2), in
+ * that order (two launches; the second adds to D). Same fmt and dim for both
+ * pairs; BF16 or FP8. */
+int emb_distances_l2sum(int fmt, int M, int N, int dim, const void *q1_codes,
+                        const float *q1_scale, const float *q1_sq, const void *x1_codes,
+                        const float *x1_scale, const float *x1_sq, const void *q2_codes,
+                        const float *q2_scale, const float *q2_sq, const void *x2_codes,
+                        const float *x2_scale, const float *x2_sq, float *D, void *stream);
+
 /* Binary codes (the paper's unsupervised hashing query, Sec. 2.3): its
  * Bi-half layer makes, per latent coordinate, the larger half of a batch +1 and
  * the rest -1, and codes are compared by L2, which for +-1 vectors is 4x their

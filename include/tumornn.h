@@ -53,6 +53,13 @@ int nn_meanpool_db(const db_t *db, const int32_t *idx, int B, void *out, int dty
 int nn_meanpool_labels(const uint8_t *labels, int B, int nx, int ny, int nz, void *out, int dtype,
                        void *stream);
 
+/* One mask only (mask 0 = FLAIR, 1 = T1Gd): out [B][1][nz/2][ny/2][nx/2], for
+ * the paper's separate FLAIR and T1Gd autoencoders (Sec. 2.3). */
+int nn_meanpool_db_mask(const db_t *db, const int32_t *idx, int B, int mask, void *out, int dtype,
+                        void *stream);
+int nn_meanpool_labels_mask(const uint8_t *labels, int B, int nx, int ny, int nz, int mask,
+                            void *out, int dtype, void *stream);
+
 /* Y = act(conv(X)) with X [B][Ci][D][H][W], Y [B][Co][D/2][H/2][W/2];
  * bias [Co] or NULL; relu != 0 applies max(0, .). */
 int nn_conv3d_s2_fwd(int dtype, int B, int Ci, int Co, int D, int H, int W, const void *X,
@@ -117,6 +124,22 @@ int nn_adam_step(int64_t n, float *w, float *m, float *v, const float *g, uint16
 int nn_bihalf_fwd(int dtype, int B, int D, const void *U, void *out, void *stream);
 int nn_bihalf_bwd(int dtype, int B, int D, double gamma, const void *U, const void *Bc,
                   const void *G, void *dU, void *stream);
+
+/* Variational head of the paper's VAE (Sec. 2.3 "Autoencoders", Sec. 2.4: two
+ * linear layers give the latent mean and log-variance). ML [B][2L]: row b is
+ * mu_b (L values) then logvar_b (L values), as one linear layer of 2L outputs
+ * writes them. Forward: z [B][L] = mu + exp(logvar / 2) * eps (eps [B][L], a
+ * standard normal sample passed in), kl[0] = (1/B) sum -1/2 (1 + logvar - mu^2
+ * - exp(logvar)) (deterministic: fixed-order partial sums in ws of
+ * nn_vae_ws_bytes bytes). Backward of recon(z) + beta * kl, given dz:
+ *   d mu = dz + beta * mu / B,
+ *   d logvar = dz * eps * exp(logvar / 2) / 2 + beta * (exp(logvar) - 1) / (2B),
+ * written to dML [B][2L]. dtype NN_F32 or NN_F64. */
+size_t nn_vae_ws_bytes(int dtype, int B, int L);
+int nn_vae_head_fwd(int dtype, int B, int L, const void *ML, const void *eps, void *z, void *kl,
+                    void *ws, size_t ws_bytes, void *stream);
+int nn_vae_head_bwd(int dtype, int B, int L, double beta, const void *ML, const void *eps,
+                    const void *dz, void *dML, void *stream);
 
 /* FP32 -> BF16 bits, round to nearest even (NaN stays NaN). */
 int nn_to_bf16(int64_t n, const float *x, uint16_t *y, void *stream);

@@ -175,3 +175,27 @@ def bihalf_backward(U: np.ndarray, Bc: np.ndarray, G: np.ndarray, gamma: float) 
     scaled = diff / t(B * D)
     pull = t(gamma) * scaled
     return np.asarray(G, dtype=U.dtype) + pull
+
+
+# ---- two encoders and the variational head (Sec. 2.3 "Autoencoders") ----
+
+def l2sum_direct(Q1, X1, Q2, X2) -> np.ndarray:
+    """L2_T1Gd + L2_FLAIR of two latent sets [nq][n] in float64: sqrt of each direct-form
+    squared distance, added."""
+    return np.sqrt(sqdist_direct(Q1, X1)) + np.sqrt(sqdist_direct(Q2, X2))
+
+
+def vae_head(ml: torch.Tensor, eps: torch.Tensor):
+    """ml [B][2L] = [mu | logvar] -> (z = mu + exp(logvar / 2) eps,
+    KL = (1/B) sum -1/2 (1 + logvar - mu^2 - exp(logvar)))."""
+    L = ml.shape[1] // 2
+    mu, lv = ml[:, :L], ml[:, L:]
+    z = mu + torch.exp(0.5 * lv) * eps
+    kl = -0.5 * (1 + lv - mu * mu - torch.exp(lv)).sum() / ml.shape[0]
+    return z, kl
+
+
+def vae_loss(params: dict, x: torch.Tensor, eps: torch.Tensor, beta: float, channels: int, s: int):
+    """Reconstruction MSE + beta * KL of the variational autoencoder (float64)."""
+    z, kl = vae_head(encode(params, x), eps)
+    return mse(decode(params, z, channels, s), x) + beta * kl, kl

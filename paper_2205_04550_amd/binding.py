@@ -23,7 +23,7 @@ SYMBOLS = ("db_storage_bytes", "db_build", "db_append", "db_size", "db_query_wor
            "db_rerank_workspace_bytes", "db_rerank", "db_query_embed_workspace_bytes",
            "db_query_embed", "db_tune_batch", "db_append_resampled", "labels_resample",
            "db_query_sparse", "db_query_com_workspace_bytes", "db_query_com",
-           "emb_hash_thresholds", "emb_binarize")
+           "emb_hash_thresholds", "emb_binarize", "emb_distances_l2sum")
 EMB_BF16, EMB_FP8, EMB_BIN = 0, 1, 2
 
 
@@ -67,6 +67,7 @@ def _load():
         "emb_distances": (i32, [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
         "emb_topk_min": (i32, [i32, i32, vp, i32, vp, vp, vp]),
         "emb_hash_thresholds": (i32, [i64, i32, vp, vp, vp]),
+        "emb_distances_l2sum": (i32, [i32, i32, i32, i32] + [vp] * 12 + [vp, vp]),
         "emb_binarize": (i32, [i64, i32, vp, vp, vp, vp]),
         "db_rerank_workspace_bytes": (sz, [vp, i32]),
         "db_rerank": (i32, [vp, i32, vp, vp, i32, i32, vp, vp, vp, vp, sz, vp]),
@@ -394,6 +395,19 @@ def emb_distances(q, x, out: torch.Tensor | None = None, stream=None):
     _check(LIB.emb_distances(q.fmt, q.n, x.n, q.dim, q.codes.data_ptr(), _ptr(q.scale),
                              _ptr(q.sq), x.codes.data_ptr(), _ptr(x.scale), _ptr(x.sq),
                              out.data_ptr(), _stream(stream)))
+    return out
+
+
+def emb_distances_l2sum(q1, x1, q2, x2, out: torch.Tensor | None = None, stream=None):
+    """[nq][n] FP32: L2(q1, x1) + L2(q2, x2), the paper's L2_T1Gd + L2_FLAIR of two encoders."""
+    if out is None:
+        out = torch.empty((q1.n, x1.n), dtype=torch.float32, device=q1.codes.device)
+    _check(LIB.emb_distances_l2sum(q1.fmt, q1.n, x1.n, q1.dim,
+                                   q1.codes.data_ptr(), _ptr(q1.scale), _ptr(q1.sq),
+                                   x1.codes.data_ptr(), _ptr(x1.scale), _ptr(x1.sq),
+                                   q2.codes.data_ptr(), _ptr(q2.scale), _ptr(q2.sq),
+                                   x2.codes.data_ptr(), _ptr(x2.scale), _ptr(x2.sq),
+                                   out.data_ptr(), _stream(stream)))
     return out
 
 

@@ -223,6 +223,48 @@ static hipError_t enqueue_batch(const db_t *db, int nq, const uint8_t *q_labels,
     return e;
 }
 
+// Argument checks of a distance launch (nothing is enqueued).
+static int dist_check(const char *fn, int fmt, int M, int N, int dim, const void *q_codes,
+                      const float *q_scale, const float *q_sq, const void *x_codes,
+                      const float *x_scale, const float *x_sq, const float *D)
+{
+    if (M <= 0 || N <= 0 || dim <= 0 || !q_codes || !x_codes || !D || (M + 127) / 128 > 65535)
+        return fail(DB_EINVAL, "%s: bad arguments", fn);
+    if (fmt != EMB_BIN && (!q_sq || !x_sq))
+        return fail(DB_EINVAL, "%s: squared norms are required", fn);
+    if (fmt == EMB_BIN) {
+        if (dim % 32 || dim > 1024)
+            return fail(DB_EINVAL, "%s: binary codes need dim %% 32 == 0, <= 1024", fn);
+    } else if (fmt == EMB_BF16) {
+        if (dim % 16) return fail(DB_EINVAL, "%s: BF16 needs dim %% 16 == 0", fn);
+        if (!aligned(q_codes, 16) || !aligned(x_codes, 16))
+            return fail(DB_EINVAL, "%s: codes must be 16-byte aligned", fn);
+    } else if (fmt == EMB_FP8) {
+        if (dim % 64 || !q_scale || !x_scale)
+            return fail(DB_EINVAL, "%s: FP8 needs dim %% 64 == 0 and scales", fn);
+        if (!aligned(q_codes, 32) || !aligned(x_codes, 32))
+            return fail(DB_EINVAL, "%s: codes must be 32-byte aligned", fn);
+    } else {
+        return fail(DB_EINVAL, "%s: unknown format %d", fn, fmt);
+    }
+    return DB_OK;
+}
+
+static hipError_t dist_launch(int fmt, int M, int N, int dim, const void *q_codes,
+                              const float *q_scale, const float *q_sq, const void *x_codes,
+                              const float *x_scale, const float *x_sq, float *D, int mode,
+                              hipStream_t s)
+{
+    if (fmt == EMB_BIN)
+        return launch_hamming(M, N, dim / 32, static_cast<const uint32_t *>(q_codes),
+                              static_cast<const uint32_t *>(x_codes), D, s);
+    if (fmt == EMB_BF16)
+        return launch_dist_bf16(M, N, dim, static_cast<const uint16_t *>(q_codes), q_sq,
+                                static_cast<const uint16_t *>(x_codes), x_sq, D, mode, s);
+    return launch_dist_fp8(M, N, dim, static_cast<const uint8_t *>(q_codes), q_scale, q_sq,
+                           static_cast<const uint8_t *>(x_codes), x_scale, x_sq, D, mode, s);
+}
+
 extern "C" {
 
 size_t db_storage_bytes(int nx, int ny, int nz, int64_t capacity)
@@ -607,34 +649,35 @@ int emb_distances(int fmt, int M, int N, int dim, const void *q_codes, const flo
                   const float *q_sq, const void *x_codes, const float *x_scale, const float *x_sq,
                   float *D, void *stream)
 {
-    if (M <= 0 || N <= 0 || dim <= 0 || !q_codes || !x_codes || !D || (M + 127) / 128 > 65535)
-        return fail(DB_EINVAL, "emb_distances: bad arguments");
-    if (fmt != EMB_BIN && (!q_sq || !x_sq))
-        return fail(DB_EINVAL, "emb_distances: squared norms are required");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e;
-    if (fmt == EMB_BIN) {
-        if (dim % 32 || dim > 1024)
-            return fail(DB_EINVAL, "emb_distances: binary codes need dim %% 32 == 0, <= 1024");
-        e = launch_hamming(M, N, dim / 32, static_cast<const uint32_t *>(q_codes),
-                           static_cast<const uint32_t *>(x_codes), D, s);
-    } else if (fmt == EMB_BF16) {
-        if (dim % 16) return fail(DB_EINVAL, "emb_distances: BF16 needs dim %% 16 == 0");
-        if (!aligned(q_codes, 16) || !aligned(x_codes, 16))
-            return fail(DB_EINVAL, "emb_distances: codes must be 16-byte aligned");
-        e = launch_dist_bf16(M, N, dim, static_cast<const uint16_t *>(q_codes), q_sq,
-                             static_cast<const uint16_t *>(x_codes), x_sq, D, s);
-    } else if (fmt == EMB_FP8) {
-        if (dim % 64 || !q_scale || !x_scale)
-            return fail(DB_EINVAL, "emb_distances: FP8 needs dim %% 64 == 0 and scales");
-        if (!aligned(q_codes, 32) || !aligned(x_codes, 32))
-            return fail(DB_EINVAL, "emb_distances: codes must be 32-byte aligned");
-        e = launch_dist_fp8(M, N, dim, static_cast<const uint8_t *>(q_codes), q_scale, q_sq,
-                            static_cast<const uint8_t *>(x_codes), x_scale, x_sq, D, s);
-    } else {
-        return fail(DB_EINVAL, "emb_distances: unknown format %d", fmt);
-    }
+    int rc = dist_check("emb_distances", fmt, M, N, dim, q_codes, q_scale, q_sq, x_codes, x_scale,
+                        x_sq, D);
+    if (rc) return rc;
+    hipError_t e = dist_launch(fmt, M, N, dim, q_codes, q_scale, q_sq, x_codes, x_scale, x_sq, D,
+                               0, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "emb_distances: launch");
+    return DB_OK;
+}
+
+int emb_distances_l2sum(int fmt, int M, int N, int dim, const void *q1_codes,
+                        const float *q1_scale, const float *q1_sq, const void *x1_codes,
+                        const float *x1_scale, const float *x1_sq, const void *q2_codes,
+                        const float *q2_scale, const float *q2_sq, const void *x2_codes,
+                        const float *x2_scale, const float *x2_sq, float *D, void *stream)
+{
+    if (fmt == EMB_BIN) return fail(DB_EINVAL, "emb_distances_l2sum: BF16 or FP8 latents only");
+    int rc = dist_check("emb_distances_l2sum", fmt, M, N, dim, q1_codes, q1_scale, q1_sq, x1_codes,
+                        x1_scale, x1_sq, D);
+    if (!rc)
+        rc = dist_check("emb_distances_l2sum", fmt, M, N, dim, q2_codes, q2_scale, q2_sq, x2_codes,
+                        x2_scale, x2_sq, D);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = dist_launch(fmt, M, N, dim, q1_codes, q1_scale, q1_sq, x1_codes, x1_scale, x1_sq,
+                               D, 1, s);
+    if (e == hipSuccess)
+        e = dist_launch(fmt, M, N, dim, q2_codes, q2_scale, q2_sq, x2_codes, x2_scale, x2_sq, D, 2,
+                        s);
+    if (e != hipSuccess) return hip_fail(e, "emb_distances_l2sum: launch");
     return DB_OK;
 }
 

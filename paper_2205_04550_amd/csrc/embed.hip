@@ -133,12 +133,25 @@ __global__ void __launch_bounds__(256) quant_fp8_kernel(int dim, const float *__
 
 constexpr int kGT = 128;
 
+// Epilogue of the distance kernels. mode 0: D = d (squared L2); mode 1:
+// D = sqrt(max(d, 0)) (L2); mode 2: D += sqrt(max(d, 0)) (a second L2 added to
+// the first: the paper's L2_T1Gd + L2_FLAIR of two encoders, Sec. 2.3).
+__device__ __forceinline__ void dist_store(float *p, float d, int mode)
+{
+    if (mode == 0) {
+        *p = d;
+    } else {
+        const float l = __builtin_sqrtf(fmaxf(d, 0.0f));
+        *p = mode == 1 ? l : *p + l;
+    }
+}
+
 __global__ void __launch_bounds__(256) dist_bf16_kernel(int M, int N, int K,
                                                         const uint16_t *__restrict__ Q,
                                                         const float *__restrict__ qn,
                                                         const uint16_t *__restrict__ X,
                                                         const float *__restrict__ xn,
-                                                        float *__restrict__ D)
+                                                        float *__restrict__ D, int mode)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m0 = blockIdx.y * kGT + (wave >> 1) * 64;
@@ -192,7 +205,8 @@ __global__ void __launch_bounds__(256) dist_bf16_kernel(int M, int N, int K,
             for (int r = 0; r < 16; ++r) {
                 const int row = m0 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
                 if (row < M)
-                    D[(int64_t)row * N + col] = (qn[row] + xc) - 2.0f * acc[i][j][r];
+                    dist_store(D + (int64_t)row * N + col, (qn[row] + xc) - 2.0f * acc[i][j][r],
+                               mode);
             }
         }
 }
@@ -204,7 +218,7 @@ __global__ void __launch_bounds__(256) dist_fp8_kernel(int M, int N, int K,
                                                        const uint8_t *__restrict__ X,
                                                        const float *__restrict__ xs,
                                                        const float *__restrict__ xn,
-                                                       float *__restrict__ D)
+                                                       float *__restrict__ D, int mode)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m0 = blockIdx.y * kGT + (wave >> 1) * 64;
@@ -266,8 +280,8 @@ __global__ void __launch_bounds__(256) dist_fp8_kernel(int M, int N, int K,
             for (int r = 0; r < 16; ++r) {
                 const int row = m0 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
                 if (row < M)
-                    D[(int64_t)row * N + col] =
-                        (qn[row] + xc) - 2.0f * (qs[row] * sc) * acc[i][j][r];
+                    dist_store(D + (int64_t)row * N + col,
+                               (qn[row] + xc) - 2.0f * (qs[row] * sc) * acc[i][j][r], mode);
             }
         }
 }
@@ -569,19 +583,19 @@ hipError_t launch_quant_fp8(int64_t n, int dim, const float *x, uint8_t *y, floa
 }
 
 hipError_t launch_dist_bf16(int M, int N, int K, const uint16_t *Q, const float *qn,
-                            const uint16_t *X, const float *xn, float *D, hipStream_t s)
+                            const uint16_t *X, const float *xn, float *D, int mode, hipStream_t s)
 {
     hipLaunchKernelGGL(dist_bf16_kernel, dim3((N + kGT - 1) / kGT, (M + kGT - 1) / kGT), dim3(256),
-                       0, s, M, N, K, Q, qn, X, xn, D);
+                       0, s, M, N, K, Q, qn, X, xn, D, mode);
     return hipGetLastError();
 }
 
 hipError_t launch_dist_fp8(int M, int N, int K, const uint8_t *Q, const float *qs, const float *qn,
                            const uint8_t *X, const float *xs, const float *xn, float *D,
-                           hipStream_t s)
+                           int mode, hipStream_t s)
 {
     hipLaunchKernelGGL(dist_fp8_kernel, dim3((N + kGT - 1) / kGT, (M + kGT - 1) / kGT), dim3(256),
-                       0, s, M, N, K, Q, qs, qn, X, xs, xn, D);
+                       0, s, M, N, K, Q, qs, qn, X, xs, xn, D, mode);
     return hipGetLastError();
 }
 

@@ -112,11 +112,12 @@ hipError_t launch_quant_bf16(int64_t n, int dim, const float *x, uint16_t *y, fl
                              hipStream_t s);
 hipError_t launch_quant_fp8(int64_t n, int dim, const float *x, uint8_t *y, float *scale,
                             float *sq, hipStream_t s);
+// mode 0: squared L2; 1: L2; 2: add L2 to D (see dist_store in embed.hip).
 hipError_t launch_dist_bf16(int M, int N, int K, const uint16_t *Q, const float *qn,
-                            const uint16_t *X, const float *xn, float *D, hipStream_t s);
+                            const uint16_t *X, const float *xn, float *D, int mode, hipStream_t s);
 hipError_t launch_dist_fp8(int M, int N, int K, const uint8_t *Q, const float *qs, const float *qn,
                            const uint8_t *X, const float *xs, const float *xn, float *D,
-                           hipStream_t s);
+                           int mode, hipStream_t s);
 hipError_t launch_topk_min(int M, int N, int k, const float *D, int32_t *idx, float *d,
                            hipStream_t s);
 hipError_t launch_rerank(const db_t *db, int nq, const uint32_t *qpack, const uint32_t *acnt,

@@ -478,14 +478,15 @@ __global__ void to_bf16_kernel(int64_t n, const float *__restrict__ x, uint16_t 
 
 // ---- mean-pooling of the masks ------------------------------------------------------------
 
-// out [B][2][nz/2][ny/2][nx/2] = (number of set voxels in the 2x2x2 block) / 8.
+// out [B][nm][nz/2][ny/2][nx/2] = (number of set voxels of mask m0 + c in the
+// 2x2x2 block) / 8 for output channel c.
 template <class T>
 __global__ void meanpool_db_kernel(const uint32_t *__restrict__ planes, int Wp, int nxw, int ny,
-                                   int nz, int nx, const int32_t *__restrict__ idx, int B,
-                                   T *__restrict__ out)
+                                   int nz, int nx, const int32_t *__restrict__ idx, int B, int m0,
+                                   int nm, T *__restrict__ out)
 {
     const int X = nx / 2, Y = ny / 2, Z = nz / 2;
-    const int64_t per = (int64_t)2 * Z * Y * X;
+    const int64_t per = (int64_t)nm * Z * Y * X;
     const int64_t total = per * B;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
@@ -496,7 +497,7 @@ __global__ void meanpool_db_kernel(const uint32_t *__restrict__ planes, int Wp, 
         const int y = (int)(r % Y);
         r /= Y;
         const int z = (int)(r % Z);
-        const int m = (int)(r / Z);
+        const int m = m0 + (int)(r / Z);
         const uint32_t *pl = planes + (int64_t)idx[b] * 2 * Wp + (int64_t)m * Wp;
         const int wx = (2 * x) >> 5, bit = (2 * x) & 31;
         int c = 0;
@@ -513,10 +514,10 @@ __global__ void meanpool_db_kernel(const uint32_t *__restrict__ planes, int Wp, 
 
 template <class T>
 __global__ void meanpool_labels_kernel(const uint8_t *__restrict__ lab, int B, int nx, int ny,
-                                       int nz, T *__restrict__ out)
+                                       int nz, int m0, int nm, T *__restrict__ out)
 {
     const int X = nx / 2, Y = ny / 2, Z = nz / 2;
-    const int64_t per = (int64_t)2 * Z * Y * X;
+    const int64_t per = (int64_t)nm * Z * Y * X;
     const int64_t total = per * B;
     const int64_t V = (int64_t)nx * ny * nz;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
@@ -528,7 +529,7 @@ __global__ void meanpool_labels_kernel(const uint8_t *__restrict__ lab, int B, i
         const int y = (int)(r % Y);
         r /= Y;
         const int z = (int)(r % Z);
-        const int m = (int)(r / Z);
+        const int m = m0 + (int)(r / Z);
         const uint8_t *l = lab + (int64_t)b * V;
         int c = 0;
 #pragma unroll
@@ -584,39 +585,67 @@ int launched(const char *what)
 
 extern "C" {
 
-int nn_meanpool_db(const db_t *db, const int32_t *idx, int B, void *out, int dtype, void *stream)
+static int meanpool_db(const char *fn, const db_t *db, const int32_t *idx, int B, int m0, int nm,
+                       void *out, int dtype, void *stream)
 {
-    if (!tdb_live(db)) return tdb_set_error(DB_ESTATE, "nn_meanpool_db: invalid handle");
+    if (!tdb_live(db)) return tdb_set_error(DB_ESTATE, "%s: invalid handle", fn);
     const Geometry &g = db->g;
     if (!idx || !out || B <= 0 || (g.nx & 1) || (g.ny & 1) || (g.nz & 1) ||
         (dtype != NN_F32 && dtype != NN_F64))
-        return tdb_set_error(DB_EINVAL, "nn_meanpool_db: bad arguments");
+        return tdb_set_error(DB_EINVAL, "%s: bad arguments", fn);
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t total = (int64_t)B * 2 * (g.nz / 2) * (g.ny / 2) * (g.nx / 2);
+    const int64_t total = (int64_t)B * nm * (g.nz / 2) * (g.ny / 2) * (g.nx / 2);
     if (dtype == NN_F32)
         hipLaunchKernelGGL(meanpool_db_kernel<float>, dim3(grid1(total)), dim3(256), 0, s,
-                           db->planes, g.Wp, g.nxw, g.ny, g.nz, g.nx, idx, B, (float *)out);
+                           db->planes, g.Wp, g.nxw, g.ny, g.nz, g.nx, idx, B, m0, nm, (float *)out);
     else
         hipLaunchKernelGGL(meanpool_db_kernel<double>, dim3(grid1(total)), dim3(256), 0, s,
-                           db->planes, g.Wp, g.nxw, g.ny, g.nz, g.nx, idx, B, (double *)out);
-    return launched("nn_meanpool_db");
+                           db->planes, g.Wp, g.nxw, g.ny, g.nz, g.nx, idx, B, m0, nm, (double *)out);
+    return launched(fn);
+}
+
+static int meanpool_labels(const char *fn, const uint8_t *labels, int B, int nx, int ny, int nz,
+                           int m0, int nm, void *out, int dtype, void *stream)
+{
+    if (!labels || !out || B <= 0 || nx <= 0 || ny <= 0 || nz <= 0 || (nx & 1) || (ny & 1) ||
+        (nz & 1) || (dtype != NN_F32 && dtype != NN_F64))
+        return tdb_set_error(DB_EINVAL, "%s: bad arguments", fn);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t total = (int64_t)B * nm * (nz / 2) * (ny / 2) * (nx / 2);
+    if (dtype == NN_F32)
+        hipLaunchKernelGGL(meanpool_labels_kernel<float>, dim3(grid1(total)), dim3(256), 0, s,
+                           labels, B, nx, ny, nz, m0, nm, (float *)out);
+    else
+        hipLaunchKernelGGL(meanpool_labels_kernel<double>, dim3(grid1(total)), dim3(256), 0, s,
+                           labels, B, nx, ny, nz, m0, nm, (double *)out);
+    return launched(fn);
+}
+
+int nn_meanpool_db(const db_t *db, const int32_t *idx, int B, void *out, int dtype, void *stream)
+{
+    return meanpool_db("nn_meanpool_db", db, idx, B, 0, 2, out, dtype, stream);
 }
 
 int nn_meanpool_labels(const uint8_t *labels, int B, int nx, int ny, int nz, void *out, int dtype,
                        void *stream)
 {
-    if (!labels || !out || B <= 0 || nx <= 0 || ny <= 0 || nz <= 0 || (nx & 1) || (ny & 1) ||
-        (nz & 1) || (dtype != NN_F32 && dtype != NN_F64))
-        return tdb_set_error(DB_EINVAL, "nn_meanpool_labels: bad arguments");
-    const hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t total = (int64_t)B * 2 * (nz / 2) * (ny / 2) * (nx / 2);
-    if (dtype == NN_F32)
-        hipLaunchKernelGGL(meanpool_labels_kernel<float>, dim3(grid1(total)), dim3(256), 0, s,
-                           labels, B, nx, ny, nz, (float *)out);
-    else
-        hipLaunchKernelGGL(meanpool_labels_kernel<double>, dim3(grid1(total)), dim3(256), 0, s,
-                           labels, B, nx, ny, nz, (double *)out);
-    return launched("nn_meanpool_labels");
+    return meanpool_labels("nn_meanpool_labels", labels, B, nx, ny, nz, 0, 2, out, dtype, stream);
+}
+
+int nn_meanpool_db_mask(const db_t *db, const int32_t *idx, int B, int mask, void *out, int dtype,
+                        void *stream)
+{
+    if (mask != 0 && mask != 1) return tdb_set_error(DB_EINVAL, "nn_meanpool_db_mask: mask %d", mask);
+    return meanpool_db("nn_meanpool_db_mask", db, idx, B, mask, 1, out, dtype, stream);
+}
+
+int nn_meanpool_labels_mask(const uint8_t *labels, int B, int nx, int ny, int nz, int mask,
+                            void *out, int dtype, void *stream)
+{
+    if (mask != 0 && mask != 1)
+        return tdb_set_error(DB_EINVAL, "nn_meanpool_labels_mask: mask %d", mask);
+    return meanpool_labels("nn_meanpool_labels_mask", labels, B, nx, ny, nz, mask, 1, out, dtype,
+                           stream);
 }
 
 int nn_conv3d_s2_fwd(int dtype, int B, int Ci, int Co, int D, int H, int W, const void *X,

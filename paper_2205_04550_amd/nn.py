@@ -45,6 +45,11 @@ _SIGS = {
     "nn_adam_step": (_i32, [_i64, _vp, _vp, _vp, _vp, _vp, _f32, _f32, _f32, _f32, _i32, _vp]),
     "nn_to_bf16": (_i32, [_i64, _vp, _vp, _vp]),
     "nn_bihalf_fwd": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp]),
+    "nn_meanpool_db_mask": (_i32, [_vp, _vp, _i32, _i32, _vp, _i32, _vp]),
+    "nn_meanpool_labels_mask": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _vp, _i32, _vp]),
+    "nn_vae_ws_bytes": (_sz, [_i32, _i32, _i32]),
+    "nn_vae_head_fwd": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "nn_vae_head_bwd": (_i32, [_i32, _i32, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]),
     "nn_bihalf_bwd": (_i32, [_i32, _i32, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]),
 }
 for _n, (_r, _a) in _SIGS.items():
@@ -80,24 +85,37 @@ def _c(t):
 
 # ---- pooling ------------------------------------------------------------------------------
 
-def meanpool_db(db, idx: torch.Tensor, dtype=torch.float32) -> torch.Tensor:
-    """2x2x2 mean of the masks of database entries idx (int32, device): [B][2][nz/2][ny/2][nx/2]."""
+def meanpool_db(db, idx: torch.Tensor, dtype=torch.float32, mask: int | None = None) -> torch.Tensor:
+    """2x2x2 mean of the masks of database entries idx (int32, device): [B][2][nz/2][ny/2][nx/2],
+    or [B][1][...] of one mask (0 FLAIR, 1 T1Gd)."""
     nx, ny, nz = db.dims
     idx = _c(idx.to(torch.int32))
     B = idx.numel()
-    out = torch.empty((B, 2, nz // 2, ny // 2, nx // 2), dtype=dtype, device=idx.device)
-    _check(LIB.nn_meanpool_db(db._h, idx.data_ptr(), B, out.data_ptr(), _dt(out), _s()))
+    out = torch.empty((B, 2 if mask is None else 1, nz // 2, ny // 2, nx // 2), dtype=dtype,
+                      device=idx.device)
+    if mask is None:
+        _check(LIB.nn_meanpool_db(db._h, idx.data_ptr(), B, out.data_ptr(), _dt(out), _s()))
+    else:
+        _check(LIB.nn_meanpool_db_mask(db._h, idx.data_ptr(), B, mask, out.data_ptr(), _dt(out),
+                                       _s()))
     return out
 
 
-def meanpool_labels(labels: torch.Tensor, dtype=torch.float32) -> torch.Tensor:
-    """2x2x2 mean of query labels uint8 [B][nz][ny][nx] (bit0 FLAIR, bit1 T1Gd)."""
+def meanpool_labels(labels: torch.Tensor, dtype=torch.float32, mask: int | None = None) -> torch.Tensor:
+    """2x2x2 mean of query labels uint8 [B][nz][ny][nx] (bit0 FLAIR, bit1 T1Gd); one mask with
+    mask = 0 / 1."""
     labels = _c(labels)
     if labels.dim() == 3:
         labels = labels[None]
     B, nz, ny, nx = labels.shape
-    out = torch.empty((B, 2, nz // 2, ny // 2, nx // 2), dtype=dtype, device=labels.device)
-    _check(LIB.nn_meanpool_labels(labels.data_ptr(), B, nx, ny, nz, out.data_ptr(), _dt(out), _s()))
+    out = torch.empty((B, 2 if mask is None else 1, nz // 2, ny // 2, nx // 2), dtype=dtype,
+                      device=labels.device)
+    if mask is None:
+        _check(LIB.nn_meanpool_labels(labels.data_ptr(), B, nx, ny, nz, out.data_ptr(), _dt(out),
+                                      _s()))
+    else:
+        _check(LIB.nn_meanpool_labels_mask(labels.data_ptr(), B, nx, ny, nz, mask, out.data_ptr(),
+                                           _dt(out), _s()))
     return out
 
 
@@ -289,6 +307,35 @@ class BiHalf(torch.autograd.Function):
         return du, None
 
 
+class VaeHead(torch.autograd.Function):
+    """z = mu + exp(logvar / 2) * eps from ML = [mu | logvar] (one linear layer of 2L outputs);
+    the backward also carries beta * KL, whose value is left in ctx-free `kl_out`."""
+
+    @staticmethod
+    def forward(ctx, ml, eps, beta, kl_out):
+        ml, eps = _c(ml), _c(eps)
+        B, L2 = ml.shape
+        L = L2 // 2
+        z = torch.empty((B, L), dtype=ml.dtype, device=ml.device)
+        nb = LIB.nn_vae_ws_bytes(_dt(ml), B, L)
+        ws = torch.empty(nb, dtype=torch.uint8, device=ml.device)
+        _check(LIB.nn_vae_head_fwd(_dt(ml), B, L, ml.data_ptr(), eps.data_ptr(), z.data_ptr(),
+                                   kl_out.data_ptr(), ws.data_ptr(), nb, _s()))
+        ctx.save_for_backward(ml, eps)
+        ctx.beta = float(beta)
+        return z
+
+    @staticmethod
+    def backward(ctx, dz):
+        ml, eps = ctx.saved_tensors
+        dz = _c(dz.to(ml.dtype))
+        B, L2 = ml.shape
+        dml = torch.empty_like(ml)
+        _check(LIB.nn_vae_head_bwd(_dt(ml), B, L2 // 2, ctx.beta, ml.data_ptr(), eps.data_ptr(),
+                                   dz.data_ptr(), dml.data_ptr(), _s()))
+        return dml, None, None, None
+
+
 # ---- model ----------------------------------------------------------------------------------
 
 class AutoEncoder:
@@ -299,12 +346,19 @@ class AutoEncoder:
     """
 
     def __init__(self, grid: int = 64, channels=(2, 8, 16, 32, 64), latent: int = 512,
-                 dtype=torch.float32, device="cuda", seed: int = 0, hash_gamma: float | None = None):
+                 dtype=torch.float32, device="cuda", seed: int = 0, hash_gamma: float | None = None,
+                 vae_beta: float | None = None):
         assert grid % 16 == 0
+        assert hash_gamma is None or vae_beta is None
         self.grid, self.channels, self.latent = grid, tuple(channels), latent
         # With hash_gamma the decoder reads the Bi-half codes of the latent (the paper's
-        # hashing autoencoder); without, the latent itself.
+        # hashing autoencoder); with vae_beta the encoder's last layer gives mean and
+        # log-variance (the paper's VAE) and training adds vae_beta * KL; otherwise the
+        # decoder reads the latent itself.
         self.hash_gamma = hash_gamma
+        self.vae_beta = vae_beta
+        self.kl = None          # KL of the last variational forward (device scalar)
+        self._eps_gen = None
         self.dtype = dtype
         self.bf16 = dtype == torch.float32
         g = torch.Generator().manual_seed(seed)
@@ -320,8 +374,9 @@ class AutoEncoder:
             ci, co = channels[i], channels[i + 1]
             self.params[f"enc{i}.w"] = uni((co, ci, 3, 3, 3), ci * 27)
             self.params[f"enc{i}.b"] = torch.zeros(co, dtype=torch.float64)
-        self.params["enc_fc.w"] = uni((latent, self.flat), self.flat)
-        self.params["enc_fc.b"] = torch.zeros(latent, dtype=torch.float64)
+        heads = 2 if vae_beta is not None else 1   # [mu | logvar] rows for the VAE
+        self.params["enc_fc.w"] = uni((heads * latent, self.flat), self.flat)
+        self.params["enc_fc.b"] = torch.zeros(heads * latent, dtype=torch.float64)
         self.params["dec_fc.w"] = uni((self.flat, latent), latent)
         self.params["dec_fc.b"] = torch.zeros(self.flat, dtype=torch.float64)
         for i in reversed(range(4)):
@@ -350,14 +405,21 @@ class AutoEncoder:
     def _w(self, name):
         return self.params[name + ".w"], self.params[name + ".b"], self.work[name + ".w"]
 
-    def encode(self, x: torch.Tensor) -> torch.Tensor:
+    def _features(self, x: torch.Tensor) -> torch.Tensor:
         h = x
         for i in range(4):
             w, b, wc = self._w(f"enc{i}")
             h = Conv3dS2.apply(h, w, b, wc, True)
-        h = h.reshape(h.shape[0], -1)
+        return h.reshape(h.shape[0], -1)
+
+    def encode(self, x: torch.Tensor) -> torch.Tensor:
+        """The latent (for the VAE: the mean, from the first `latent` rows of the head)."""
+        h = self._features(x)
         w, b, wc = self._w("enc_fc")
-        return Linear.apply(h, w, b, wc, False)
+        if self.vae_beta is None:
+            return Linear.apply(h, w, b, wc, False)
+        L = self.latent
+        return Linear.apply(h, w[:L], b[:L], wc[:L], False)
 
     def decode(self, z: torch.Tensor) -> torch.Tensor:
         w, b, wc = self._w("dec_fc")
@@ -369,14 +431,28 @@ class AutoEncoder:
             h = ConvT3dS2.apply(h, w, b, wc, i != 0)
         return h
 
-    def forward(self, x: torch.Tensor) -> torch.Tensor:
+    def forward(self, x: torch.Tensor, eps: torch.Tensor | None = None) -> torch.Tensor:
+        if self.vae_beta is not None:
+            h = self._features(x)
+            w, b, wc = self._w("enc_fc")
+            ml = Linear.apply(h, w, b, wc, False)
+            if eps is None:
+                if self._eps_gen is None:
+                    self._eps_gen = torch.Generator(device=x.device).manual_seed(12345)
+                eps = torch.randn((x.shape[0], self.latent), generator=self._eps_gen,
+                                  dtype=x.dtype, device=x.device)
+            self.kl = torch.empty((), dtype=x.dtype, device=x.device)
+            z = VaeHead.apply(ml, eps, self.vae_beta, self.kl)
+            return self.decode(z)
         z = self.encode(x)
         if self.hash_gamma is not None:
             z = BiHalf.apply(z, self.hash_gamma)
         return self.decode(z)
 
-    def loss(self, x: torch.Tensor) -> torch.Tensor:
-        return MSE.apply(self.forward(x), x)
+    def loss(self, x: torch.Tensor, eps: torch.Tensor | None = None) -> torch.Tensor:
+        """Reconstruction MSE. For the VAE the backward also applies vae_beta * KL (its value
+        is in self.kl after the call)."""
+        return MSE.apply(self.forward(x, eps), x)
 
     def n_params(self) -> int:
         return sum(p.numel() for p in self.params.values())

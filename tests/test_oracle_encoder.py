@@ -147,3 +147,32 @@ def test_hash_oracle_pins():
     assert Bc.tolist() == [[-1, -1], [1, 1]]
     dU = E.bihalf_backward(U, Bc, np.ones_like(U), 4.0)
     assert dU.tolist() == [[2.5, 1.0], [2.0, 0.0]]
+
+
+def test_vae_and_l2sum_oracle_pins():
+    """KL closed forms, the reparameterisation and the summed L2 of two latent sets."""
+    B, L = 3, 4
+    ml = torch.zeros(B, 2 * L, dtype=torch.float64)
+    eps = torch.randn(B, L, dtype=torch.float64, generator=torch.Generator().manual_seed(0))
+    z, kl = E.vae_head(ml, eps)
+    assert float(kl) == 0.0 and torch.equal(z, eps)          # N(0, 1) itself
+    ml[0, 0] = 1.0                                             # one mean of 1: KL = 1/2 / B
+    ml[1, L + 2] = np.log(4.0)                                 # one variance of 4
+    z, kl = E.vae_head(ml, eps)
+    want = (0.5 + -0.5 * (1 + np.log(4.0) - 4.0)) / B
+    assert abs(float(kl) - want) < 1e-15
+    assert float(z[1, 2]) == 2.0 * float(eps[1, 2]) and float(z[0, 0]) == 1.0 + float(eps[0, 0])
+    # Summed L2: orthogonal unit vectors are sqrt(2) apart in each set; a set with itself is 0.
+    e = np.eye(4)
+    d = E.l2sum_direct(e[:1], e[1:2], e[:1], e[:1])
+    assert abs(d[0, 0] - np.sqrt(2.0)) < 1e-15
+    rng = np.random.default_rng(1)
+    A, Bm = rng.standard_normal((3, 8)), rng.standard_normal((5, 8))
+    assert np.allclose(E.l2sum_direct(A, Bm, A, Bm), 2 * np.sqrt(E.sqdist_direct(A, Bm)))
+    # Triangle inequality holds for the sum of two metrics.
+    C = rng.standard_normal((5, 8))
+    lhs = E.l2sum_direct(A, C, A, C)
+    rhs = E.l2sum_direct(A, Bm, A, Bm)[:, :, None] + E.l2sum_direct(Bm, C, Bm, C)[None, :, :]
+    for i in range(3):
+        for j in range(5):
+            assert lhs[i, j] <= min(rhs[i, m, j] for m in range(5)) + 1e-12
