@@ -196,8 +196,14 @@ int emb_binarize(int64_t n, int dim, const float *lat, const float *thr, uint32_
                  void *stream);
 
 /* Per row of D [M][N]: the k smallest values, ties by lower column, in
- * ascending order: idx [M][k] (int32), d [M][k]. 1 <= k <= min(N, DB_KMAX). */
-int emb_topk_min(int M, int N, const float *D, int k, int32_t *idx, float *d, void *stream);
+ * ascending order: idx [M][k] (int32), d [M][k]. 1 <= k <= min(N, DB_KMAX).
+ * ws (device, 16-byte aligned) of emb_topk_min_workspace_bytes bytes lets the
+ * rows be split into chunks selected by many blocks and then merged; with ws
+ * NULL (or that size 0: too many candidates for the merge) one block selects
+ * each row. Results are identical either way. */
+size_t emb_topk_min_workspace_bytes(int M, int N, int k);
+int emb_topk_min(int M, int N, const float *D, int k, int32_t *idx, float *d, void *ws,
+                 size_t ws_bytes, void *stream);
 
 /* Exact re-scoring: for query q (labels [nq][nz][ny][nx]) and its candidate
  * entries cand [nq][nc] (device int32, each in [0, db_size())), the k best by

@@ -20,6 +20,7 @@ DB_KMAX = 1024
 SYMBOLS = ("db_storage_bytes", "db_build", "db_append", "db_size", "db_query_workspace_bytes",
            "db_scan", "db_query", "db_query_batch", "db_sync", "db_free", "db_last_error",
            "db_profile", "db_profile_read", "emb_quantize", "emb_distances", "emb_topk_min",
+           "emb_topk_min_workspace_bytes",
            "db_rerank_workspace_bytes", "db_rerank", "db_query_embed_workspace_bytes",
            "db_query_embed", "db_tune_batch", "db_append_resampled", "labels_resample",
            "db_query_sparse", "db_query_com_workspace_bytes", "db_query_com",
@@ -65,7 +66,8 @@ def _load():
         "labels_resample": (i32, [i32, vp, i32, i32, i32, vp, i32, i32, i32, vp]),
         "emb_quantize": (i32, [i64, i32, vp, i32, vp, vp, vp, vp]),
         "emb_distances": (i32, [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
-        "emb_topk_min": (i32, [i32, i32, vp, i32, vp, vp, vp]),
+        "emb_topk_min": (i32, [i32, i32, vp, i32, vp, vp, vp, sz, vp]),
+        "emb_topk_min_workspace_bytes": (sz, [i32, i32, i32]),
         "emb_hash_thresholds": (i32, [i64, i32, vp, vp, vp]),
         "emb_distances_l2sum": (i32, [i32, i32, i32, i32] + [vp] * 12 + [vp, vp]),
         "emb_binarize": (i32, [i64, i32, vp, vp, vp, vp]),
@@ -411,13 +413,16 @@ def emb_distances_l2sum(q1, x1, q2, x2, out: torch.Tensor | None = None, stream=
     return out
 
 
-def emb_topk_min(D: torch.Tensor, k: int, stream=None):
-    """Per row the k smallest (ties by lower column), ascending: (idx int32, values)."""
+def emb_topk_min(D: torch.Tensor, k: int, stream=None, chunked: bool = True):
+    """Per row the k smallest (ties by lower column), ascending: (idx int32, values). With
+    chunked, rows are split over many blocks and merged (same results)."""
     M, N = D.shape
     idx = torch.empty((M, k), dtype=torch.int32, device=D.device)
     val = torch.empty((M, k), dtype=torch.float32, device=D.device)
+    nb = LIB.emb_topk_min_workspace_bytes(M, N, k) if chunked else 0
+    ws = torch.empty(nb, dtype=torch.uint8, device=D.device) if nb else None
     _check(LIB.emb_topk_min(M, N, D.contiguous().data_ptr(), k, idx.data_ptr(), val.data_ptr(),
-                            _stream(stream)))
+                            _ptr(ws), nb, _stream(stream)))
     return idx, val
 
 

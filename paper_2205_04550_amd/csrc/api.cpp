@@ -683,7 +683,7 @@ int emb_distances_l2sum(int fmt, int M, int N, int dim, const void *q1_codes,
 
 int emb_hash_thresholds(int64_t n, int dim, const float *lat, float *thr, void *stream)
 {
-    if (n <= 0 || dim <= 0 || dim > 65535 || !lat || !thr)
+    if (n <= 0 || n > INT32_MAX || dim <= 0 || dim > 65535 || !lat || !thr)
         return fail(DB_EINVAL, "emb_hash_thresholds: bad arguments");
     hipError_t e = launch_col_kth(lat, n, dim, (n - 1) / 2, thr, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "emb_hash_thresholds: launch");
@@ -723,11 +723,20 @@ int nn_bihalf_bwd(int dtype, int B, int D, double gamma, const void *U, const vo
     return DB_OK;
 }
 
-int emb_topk_min(int M, int N, const float *D, int k, int32_t *idx, float *d, void *stream)
+size_t emb_topk_min_workspace_bytes(int M, int N, int k)
+{
+    if (M <= 0 || N <= 0 || k < 1 || k > N || k > DB_KMAX) return 0;
+    return topk_min_ws_bytes(M, N, k);
+}
+
+int emb_topk_min(int M, int N, const float *D, int k, int32_t *idx, float *d, void *ws,
+                 size_t ws_bytes, void *stream)
 {
     if (M <= 0 || N <= 0 || !D || !idx || !d || k < 1 || k > N || k > DB_KMAX)
         return fail(DB_EINVAL, "emb_topk_min: bad arguments (k = %d, N = %d)", k, N);
-    hipError_t e = launch_topk_min(M, N, k, D, idx, d, static_cast<hipStream_t>(stream));
+    if (ws && !aligned(ws, 16)) return fail(DB_EINVAL, "emb_topk_min: workspace not 16-byte aligned");
+    hipError_t e = launch_topk_min(M, N, k, D, idx, d, ws, ws_bytes,
+                                   static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "emb_topk_min: launch");
     return DB_OK;
 }
@@ -792,7 +801,8 @@ int db_rerank(const db_t *db, int nq, const uint8_t *q_labels, const int32_t *ca
 }
 
 static size_t embed_layout(const db_t *db, int nq, int n_cand, size_t *o_D, size_t *o_ci,
-                           size_t *o_cd, size_t *o_rr)
+                           size_t *o_cd, size_t *o_rr, size_t *o_sel = nullptr,
+                           size_t *sel_bytes = nullptr)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -805,6 +815,11 @@ static size_t embed_layout(const db_t *db, int nq, int n_cand, size_t *o_D, size
     *o_cd = take((size_t)nq * n_cand * 4);
     size_t a, b, c, d;
     *o_rr = take(rerank_layout(db, nq, &a, &b, &c, &d));
+    const int ncap = db->capacity > INT32_MAX ? INT32_MAX : (int)db->capacity;
+    const size_t sb = n_cand <= ncap ? topk_min_ws_bytes(nq, ncap, n_cand) : 0;
+    const size_t os = take(sb);
+    if (o_sel) *o_sel = os;
+    if (sel_bytes) *sel_bytes = sb;
     return off;
 }
 
@@ -838,7 +853,10 @@ int db_query_embed(const db_t *db, int fmt, int nq, int dim, const void *q_codes
     rc = emb_distances(fmt, nq, (int)n, dim, q_codes, q_scale, q_sq, x_codes, x_scale, x_sq, D,
                        stream);
     if (rc) return rc;
-    rc = emb_topk_min(nq, (int)n, D, n_cand, ci, cd, stream);
+    size_t osel, sel_bytes;
+    embed_layout(db, nq, n_cand, &oD, &oci, &ocd, &orr, &osel, &sel_bytes);
+    rc = emb_topk_min(nq, (int)n, D, n_cand, ci, cd, sel_bytes ? at<char>(ws, osel) : nullptr,
+                      sel_bytes, stream);
     if (rc) return rc;
     hipError_t e = enqueue_rerank(db, nq, q_labels, ci, n_cand, k, idx, score, counts,
                                   at<char>(ws, orr), static_cast<hipStream_t>(stream));
@@ -891,7 +909,11 @@ int db_query_com(const db_t *db, int nq, const uint8_t *q_labels, int n_cand, in
     hipError_t e = launch_pack_queries(db, q_labels, nq, nullptr, qpack, qpart, s);
     if (e == hipSuccess) e = launch_sum_parts(qpart, nq, acnt, box, qmom, s);
     if (e == hipSuccess) e = launch_com_dist(nq, qmom, db->mom, (int)n, D, s);
-    if (e == hipSuccess) e = launch_topk_min(nq, (int)n, n_cand, D, ci, cd, s);
+    size_t osel, sel_bytes;
+    embed_layout(db, nq, n_cand, &oD, &oci, &ocd, &orr, &osel, &sel_bytes);
+    if (e == hipSuccess)
+        e = launch_topk_min(nq, (int)n, n_cand, D, ci, cd, sel_bytes ? at<char>(ws, osel) : nullptr,
+                            sel_bytes, s);
     if (e == hipSuccess)
         e = launch_rerank(db, nq, qpack, acnt, box, ci, n_cand, k, idx, score, counts, s);
     if (e != hipSuccess) return hip_fail(e, "db_query_com: launch");

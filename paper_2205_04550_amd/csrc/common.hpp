@@ -87,6 +87,33 @@ __device__ __forceinline__ float fkey_inv(uint32_t k)
     return __uint_as_float(u);
 }
 
+// One step of a radix select. counts[256] (LDS) holds the histogram of the
+// current digit among the still-eligible keys; it is overwritten with its
+// inclusive prefix sums, and the one thread whose bin holds the
+// `remaining`-th smallest key writes out[0] = bin, out[1] = remaining minus
+// the keys in lower bins. All threads of the block must call it (barriers);
+// blockDim.x >= 256 and 1 <= remaining <= total count.
+__device__ __forceinline__ void select_bin(uint32_t *counts, uint32_t remaining, uint32_t *out)
+{
+    const int t = threadIdx.x;
+    for (int off = 1; off < 256; off <<= 1) {
+        uint32_t v = 0;
+        if (t < 256 && t >= off) v = counts[t - off];
+        __syncthreads();
+        if (t < 256) counts[t] += v;
+        __syncthreads();
+    }
+    if (t < 256) {
+        const uint32_t incl = counts[t];
+        const uint32_t excl = t ? counts[t - 1] : 0u;
+        if (excl < remaining && incl >= remaining) {
+            out[0] = (uint32_t)t;
+            out[1] = remaining - excl;
+        }
+    }
+    __syncthreads();
+}
+
 // Block-wide sum of two counters; the result is valid in thread 0.
 // lds must hold 2 * (blockDim.x / 64) words.
 __device__ __forceinline__ void block_sum2(uint32_t &a, uint32_t &b, uint32_t *lds)

@@ -288,6 +288,22 @@ __global__ void __launch_bounds__(256) dist_fp8_kernel(int M, int N, int K,
 
 // ---- exact k smallest per row (radix select) ----------------------------------------------
 
+// LDS histogram increment for the pending lanes of a wave: a single add when
+// they all fall into one bin (distances of a row are often concentrated, and
+// same-address atomics serialise), else one atomic per lane.
+__device__ __forceinline__ void hist_add(uint32_t *hist, bool pending, uint32_t bin, int lane)
+{
+    const uint64_t m = __ballot(pending);
+    if (!m) return;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    const uint32_t b = __shfl(bin, leader, 64);
+    if (__ballot(pending && bin != b) == 0) {
+        if (lane == leader) atomicAdd(&hist[b], (uint32_t)__popcll(m));
+    } else if (pending) {
+        atomicAdd(&hist[bin], 1u);
+    }
+}
+
 constexpr int kSelThreads = 1024;
 constexpr int kSelMaxK = 1024;
 
@@ -320,32 +336,11 @@ __global__ void __launch_bounds__(kSelThreads) topk_min_kernel(const float *__re
                 pending = (u & mask) == prefix;
                 bin = (u >> shift) & 255u;
             }
-            // Wave-aggregated increments: one LDS atomic per distinct bin in the wave.
-            uint64_t m = __ballot(pending);
-            while (m) {
-                const int leader = __ffsll((unsigned long long)m) - 1;
-                const uint32_t b = __shfl(bin, leader, 64);
-                const uint64_t same = __ballot(pending && bin == b);
-                if (lane == leader) atomicAdd(&hist[b], (uint32_t)__popcll(same));
-                if (pending && bin == b) pending = false;
-                m = __ballot(pending);
-            }
+            hist_add(hist, pending, bin, lane);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t cum = 0, sel = 255;
-            for (int b = 0; b < 256; ++b) {
-                if (cum + hist[b] >= remaining) {
-                    sel = (uint32_t)b;
-                    break;
-                }
-                cum += hist[b];
-            }
-            s_sel[0] = prefix | (sel << shift);
-            s_sel[1] = remaining - cum;
-        }
-        __syncthreads();
-        prefix = s_sel[0];
+        select_bin(hist, remaining, s_sel);
+        prefix |= s_sel[0] << shift;
         remaining = s_sel[1];
         mask |= 255u << shift;
         __syncthreads();
@@ -566,6 +561,212 @@ __global__ void __launch_bounds__(256) rerank_kernel(const uint32_t *__restrict_
     }
 }
 
+// ---- two-stage exact k smallest: per chunk, then a merge ------------------------------------
+
+constexpr int kChunkThreads = 512;
+constexpr int kChunkPer = 24;                          // keys per thread, held in registers
+constexpr int kChunk = kChunkThreads * kChunkPer;      // 12,288 row entries per block
+constexpr int kChunkWaves = kChunkThreads / 64;
+constexpr int kMergeMax = 8192;                        // candidates per row the merge sorts
+
+// grid (chunks, M), kChunkThreads threads; entry base + u * kChunkThreads + tid
+// of the row is key u of thread tid. The key T of the chunk's k-th smallest
+// entry is found by bisection on the key range [min, max]: the smallest T
+// with at least k keys <= T (at most 32 block-wide counts, no histograms).
+// The block writes its k smallest (key, index) pairs, ties at T by lowest
+// index, unsorted (a chunk shorter than k writes all of its entries and pads
+// with (max key, INT_MAX)). The union of the chunks' k smallest holds the
+// row's k smallest under the (key, index) order.
+__global__ void __launch_bounds__(kChunkThreads) topk_chunk_kernel(const float *__restrict__ D,
+                                                                   int N, int k,
+                                                                   uint32_t *__restrict__ ck,
+                                                                   int32_t *__restrict__ ci)
+{
+    __shared__ uint32_t red[3][kChunkWaves];
+    __shared__ uint32_t wcnt[kChunkPer * kChunkWaves];
+    __shared__ uint32_t scan[256];
+    __shared__ uint32_t s_lt;
+    static_assert(kChunkPer * kChunkWaves <= 256, "scan size");
+    const int c = blockIdx.x, nch = gridDim.x;
+    const int base = c * kChunk;
+    const int len = min(kChunk, N - base);
+    const float *row = D + (int64_t)blockIdx.y * N + base;
+    uint32_t *okey = ck + ((int64_t)blockIdx.y * nch + c) * k;
+    int32_t *oidx = ci + ((int64_t)blockIdx.y * nch + c) * k;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t key[kChunkPer];
+#pragma unroll
+    for (int u = 0; u < kChunkPer; ++u) {
+        const int i = u * kChunkThreads + tid;
+        key[u] = i < len ? fkey(row[i]) : 0u;
+    }
+    auto valid = [&](int u) { return u * kChunkThreads + tid < len; };
+    if (len <= k) {
+#pragma unroll
+        for (int u = 0; u < kChunkPer; ++u) {
+            const int i = u * kChunkThreads + tid;
+            if (i < k) {
+                okey[i] = i < len ? key[u] : 0xffffffffu;
+                oidx[i] = i < len ? base + i : INT_MAX;
+            }
+        }
+        return;                          // k <= DB_KMAX < kChunk: every slot was written
+    }
+    // Key range of the chunk.
+    uint32_t lo = 0xffffffffu, hi = 0u;
+#pragma unroll
+    for (int u = 0; u < kChunkPer; ++u)
+        if (valid(u)) {
+            lo = min(lo, key[u]);
+            hi = max(hi, key[u]);
+        }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = min(lo, (uint32_t)__shfl_xor((int)lo, o, 64));
+        hi = max(hi, (uint32_t)__shfl_xor((int)hi, o, 64));
+    }
+    if (lane == 0) {
+        red[0][wave] = lo;
+        red[1][wave] = hi;
+    }
+    __syncthreads();
+    lo = red[0][0];
+    hi = red[1][0];
+    for (int w = 1; w < kChunkWaves; ++w) {
+        lo = min(lo, red[0][w]);
+        hi = max(hi, red[1][w]);
+    }
+    __syncthreads();
+    // Bisection: smallest T in [lo, hi] with count(key <= T) >= k. Each round's
+    // block-wide count goes through red[round % 3]: a slot is cleared two rounds
+    // before its next use, after every thread has read it.
+    const uint32_t kk = (uint32_t)k;
+    uint32_t below = 0;                 // count(key <= lo - 1) once lo has moved
+    int round = 0;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int u = 0; u < kChunkPer; ++u) cnt += (valid(u) && key[u] <= mid) ? 1u : 0u;
+        cnt = wave_sum(cnt);
+        const int slot = round % 3;
+        if (lane == 0) red[slot][wave] = cnt;
+        __syncthreads();
+        uint32_t total = 0;
+        for (int w = 0; w < kChunkWaves; ++w) total += red[slot][w];
+        if (total >= kk) {
+            hi = mid;
+        } else {
+            lo = mid + 1;
+            below = total;
+        }
+        ++round;
+    }
+    const uint32_t T = lo;
+    const uint32_t remaining = kk - below;
+    // Keys below T: any order. Keys equal to T: the first `remaining` by index.
+    uint32_t eq = 0;
+#pragma unroll
+    for (int u = 0; u < kChunkPer; ++u) eq += (valid(u) && key[u] == T) ? 1u : 0u;
+    eq = wave_sum(eq);
+    if (tid == 0) s_lt = 0;
+    __syncthreads();
+    if (lane == 0) atomicAdd(&s_lt, eq);   // s_lt temporarily holds count(key == T)
+    __syncthreads();
+    const bool all_eq = s_lt == remaining;
+    __syncthreads();
+    if (tid == 0) s_lt = 0;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < kChunkPer; ++u) {
+        const int i = u * kChunkThreads + tid;
+        if (valid(u) && (key[u] < T || (all_eq && key[u] == T))) {
+            const uint32_t slot = atomicAdd(&s_lt, 1u);
+            okey[slot] = key[u];
+            oidx[slot] = base + i;
+        }
+    }
+    if (all_eq) return;
+    // Ordered pick among the keys equal to T: per (register, wave) counts in
+    // index order, an exclusive scan, then each lane's rank.
+#pragma unroll
+    for (int u = 0; u < kChunkPer; ++u) {
+        const uint64_t bm = __ballot(valid(u) && key[u] == T);
+        if (lane == 0) wcnt[u * kChunkWaves + wave] = (uint32_t)__popcll(bm);
+    }
+    __syncthreads();
+    {   // exclusive scan of the kChunkPer * kChunkWaves (<= 256) counts
+        constexpr int n = kChunkPer * kChunkWaves;
+        const uint32_t v = tid < n ? wcnt[tid] : 0u;
+        if (tid < 256) scan[tid] = v;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {
+            const uint32_t y = (tid < 256 && tid >= off) ? scan[tid - off] : 0u;
+            __syncthreads();
+            if (tid < 256) scan[tid] += y;
+            __syncthreads();
+        }
+        if (tid < n) wcnt[tid] = scan[tid] - v;
+        __syncthreads();
+    }
+    const uint32_t n_lt = kk - remaining;
+    const uint64_t lower = lane ? (~0ull >> (64 - lane)) : 0ull;
+#pragma unroll
+    for (int u = 0; u < kChunkPer; ++u) {
+        const bool p = valid(u) && key[u] == T;
+        const uint64_t bm = __ballot(p);
+        if (p) {
+            const uint32_t r = wcnt[u * kChunkWaves + wave] + (uint32_t)__popcll(bm & lower);
+            if (r < remaining) {
+                okey[n_lt + r] = T;
+                oidx[n_lt + r] = base + u * kChunkThreads + tid;
+            }
+        }
+    }
+}
+
+// grid M, kSelThreads threads: sort the row's nc <= kMergeMax candidates by
+// (key, index) in LDS (bitonic) and write the first k.
+__global__ void __launch_bounds__(kSelThreads) topk_merge_kernel(int nc, int k,
+                                                                 const uint32_t *__restrict__ ck,
+                                                                 const int32_t *__restrict__ ci,
+                                                                 int32_t *__restrict__ out_idx,
+                                                                 float *__restrict__ out_d)
+{
+    __shared__ uint32_t sk[kMergeMax];
+    __shared__ int32_t si[kMergeMax];
+    const int64_t r = blockIdx.x;
+    int P = 1;
+    while (P < nc) P <<= 1;
+    for (int t = threadIdx.x; t < P; t += blockDim.x) {
+        sk[t] = t < nc ? ck[r * nc + t] : 0xffffffffu;
+        si[t] = t < nc ? ci[r * nc + t] : INT_MAX;
+    }
+    for (int size = 2; size <= P; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < P / 2; t += blockDim.x) {
+                const int i = 2 * t - (t & (stride - 1));
+                const int j = i + stride;
+                const bool up = (i & size) == 0;
+                const uint32_t ki = sk[i], kj = sk[j];
+                const int32_t ii = si[i], ij = si[j];
+                const bool j_first = kj < ki || (kj == ki && ij < ii);
+                if (j_first == up) {
+                    sk[i] = kj;
+                    sk[j] = ki;
+                    si[i] = ij;
+                    si[j] = ii;
+                }
+            }
+        }
+    __syncthreads();
+    for (int t = threadIdx.x; t < k; t += blockDim.x) {
+        out_idx[r * k + t] = si[t];
+        out_d[r * k + t] = fkey_inv(sk[t]);
+    }
+}
+
 // ---- launchers ---------------------------------------------------------------------------------
 
 hipError_t launch_quant_bf16(int64_t n, int dim, const float *x, uint16_t *y, float *sq,
@@ -599,10 +800,29 @@ hipError_t launch_dist_fp8(int M, int N, int K, const uint8_t *Q, const float *q
     return hipGetLastError();
 }
 
-hipError_t launch_topk_min(int M, int N, int k, const float *D, int32_t *idx, float *d,
-                           hipStream_t s)
+size_t topk_min_ws_bytes(int M, int N, int k)
 {
-    hipLaunchKernelGGL(topk_min_kernel, dim3(M), dim3(kSelThreads), 0, s, D, N, k, idx, d);
+    const int64_t nch = ((int64_t)N + kChunk - 1) / kChunk;
+    if (nch * k > kMergeMax) return 0;       // the two-stage path does not apply
+    return (size_t)M * nch * k * 8;
+}
+
+hipError_t launch_topk_min(int M, int N, int k, const float *D, int32_t *idx, float *d, void *ws,
+                           size_t ws_bytes, hipStream_t s)
+{
+    const size_t need = topk_min_ws_bytes(M, N, k);
+    if (!ws || need == 0 || ws_bytes < need) {
+        hipLaunchKernelGGL(topk_min_kernel, dim3(M), dim3(kSelThreads), 0, s, D, N, k, idx, d);
+        return hipGetLastError();
+    }
+    const int nch = (N + kChunk - 1) / kChunk;
+    uint32_t *ck = static_cast<uint32_t *>(ws);
+    int32_t *ci = reinterpret_cast<int32_t *>(ck + (size_t)M * nch * k);
+    hipLaunchKernelGGL(topk_chunk_kernel, dim3(nch, M), dim3(kChunkThreads), 0, s, D, N, k, ck, ci);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(topk_merge_kernel, dim3(M), dim3(kSelThreads), 0, s, nch * k, k, ck, ci, idx,
+                       d);
     return hipGetLastError();
 }
 

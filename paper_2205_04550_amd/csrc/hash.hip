@@ -22,7 +22,7 @@ __global__ void __launch_bounds__(1024) col_kth_kernel(const float *__restrict__
                                                        int dim, int64_t k, float *__restrict__ thr)
 {
     __shared__ uint32_t hist[256];
-    __shared__ uint32_t s_prefix, s_mask;
+    __shared__ uint32_t s_prefix, s_mask, s_sel[2];
     __shared__ int64_t s_rank;
     const int d = blockIdx.x;
     if (threadIdx.x == 0) {
@@ -39,15 +39,10 @@ __global__ void __launch_bounds__(1024) col_kth_kernel(const float *__restrict__
             if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
         }
         __syncthreads();
+        select_bin(hist, (uint32_t)(s_rank + 1), s_sel);   // 1-based rank in this digit
         if (threadIdx.x == 0) {
-            int64_t r = s_rank;
-            int b = 0;
-            while (b < 255 && r >= (int64_t)hist[b]) {
-                r -= hist[b];
-                ++b;
-            }
-            s_rank = r;
-            s_prefix = prefix | ((uint32_t)b << shift);
+            s_rank = (int64_t)s_sel[1] - 1;
+            s_prefix = prefix | (s_sel[0] << shift);
             s_mask = mask | (255u << shift);
         }
         __syncthreads();

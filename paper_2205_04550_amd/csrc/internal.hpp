@@ -118,8 +118,11 @@ hipError_t launch_dist_bf16(int M, int N, int K, const uint16_t *Q, const float 
 hipError_t launch_dist_fp8(int M, int N, int K, const uint8_t *Q, const float *qs, const float *qn,
                            const uint8_t *X, const float *xs, const float *xn, float *D,
                            int mode, hipStream_t s);
-hipError_t launch_topk_min(int M, int N, int k, const float *D, int32_t *idx, float *d,
-                           hipStream_t s);
+// k smallest per row of D [M][N]. With a workspace of topk_min_ws_bytes (> 0) the rows
+// are split into chunks selected in parallel and merged; without, one block per row.
+size_t topk_min_ws_bytes(int M, int N, int k);
+hipError_t launch_topk_min(int M, int N, int k, const float *D, int32_t *idx, float *d, void *ws,
+                           size_t ws_bytes, hipStream_t s);
 hipError_t launch_rerank(const db_t *db, int nq, const uint32_t *qpack, const uint32_t *acnt,
                          const int32_t *box, const int32_t *cand, int nc, int k, int32_t *idx,
                          double *score, db_counts_t *counts, hipStream_t s);

@@ -78,10 +78,20 @@ def test_topk_min_exact_with_ties():
     D[3, 100:110] = -1.5                                         # negatives
     Dd = torch.from_numpy(D).cuda()
     for k in (1, 10, 100, 1000):
-        idx, val = b.emb_topk_min(Dd, k)
         want = E.topk_by_distance(D, k)
-        assert np.array_equal(idx.cpu().numpy(), want), k
-        assert np.array_equal(val.cpu().numpy(), np.take_along_axis(D, want, 1)), k
+        for chunked in (False, True):            # one block per row / chunks + merge
+            idx, val = b.emb_topk_min(Dd, k, chunked=chunked)
+            assert np.array_equal(idx.cpu().numpy(), want), (k, chunked)
+            assert np.array_equal(val.cpu().numpy(), np.take_along_axis(D, want, 1)), (k, chunked)
+    # A last chunk shorter than k (12288-entry chunks), a single chunk, and a row whose
+    # k smallest all sit in the last chunk.
+    for N, k in ((2 * 12288 + 50, 100), (700, 333), (3 * 12288 + 7, 64)):
+        D2 = rng.integers(0, 50, size=(4, N)).astype(np.float32)
+        D2[3, -k:] = -1.0
+        want = E.topk_by_distance(D2, k)
+        idx, val = b.emb_topk_min(torch.from_numpy(D2).cuda(), k, chunked=True)
+        assert np.array_equal(idx.cpu().numpy(), want), (N, k)
+        assert np.array_equal(val.cpu().numpy(), np.take_along_axis(D2, want, 1)), (N, k)
 
 
 def test_rerank_bit_exact_and_full_candidate_set_equals_scan():
