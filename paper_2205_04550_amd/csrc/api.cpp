@@ -743,7 +743,8 @@ int emb_topk_min(int M, int N, const float *D, int k, int32_t *idx, float *d, vo
 
 // Rerank workspace: packed queries, per-block counts, query counts, row boxes.
 static size_t rerank_layout(const db_t *db, int nq, size_t *o_qpack, size_t *o_qpart,
-                            size_t *o_acnt, size_t *o_box, size_t *o_mom = nullptr)
+                            size_t *o_acnt, size_t *o_box, size_t *o_mom = nullptr,
+                            size_t *o_scored = nullptr)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -757,6 +758,8 @@ static size_t rerank_layout(const db_t *db, int nq, size_t *o_qpack, size_t *o_q
     *o_box = take((size_t)nq * 4 * 4);
     const size_t om = take((size_t)nq * 4 * 8);
     if (o_mom) *o_mom = om;
+    const size_t osc = take(rerank_ws_bytes(nq));
+    if (o_scored) *o_scored = osc;
     return off;
 }
 
@@ -771,15 +774,17 @@ static hipError_t enqueue_rerank(const db_t *db, int nq, const uint8_t *q_labels
                                  const int32_t *cand, int nc, int k, int32_t *idx, double *score,
                                  db_counts_t *counts, void *ws, hipStream_t s)
 {
-    size_t oq, op, oa, ob, om;
-    rerank_layout(db, nq, &oq, &op, &oa, &ob, &om);
+    size_t oq, op, oa, ob, om, osc;
+    rerank_layout(db, nq, &oq, &op, &oa, &ob, &om, &osc);
     uint32_t *qpack = at<uint32_t>(ws, oq);
     uint32_t *acnt = at<uint32_t>(ws, oa);
     int32_t *box = at<int32_t>(ws, ob);
     QueryPart *qpart = at<QueryPart>(ws, op);
     hipError_t e = launch_pack_queries(db, q_labels, nq, nullptr, qpack, qpart, s);
     if (e == hipSuccess) e = launch_sum_parts(qpart, nq, acnt, box, at<uint64_t>(ws, om), s);
-    if (e == hipSuccess) e = launch_rerank(db, nq, qpack, acnt, box, cand, nc, k, idx, score, counts, s);
+    if (e == hipSuccess)
+        e = launch_rerank(db, nq, qpack, acnt, box, cand, nc, k, idx, score, counts,
+                          at<char>(ws, osc), s);
     return e;
 }
 
@@ -899,8 +904,8 @@ int db_query_com(const db_t *db, int nq, const uint8_t *q_labels, int n_cand, in
     int32_t *ci = cand_idx ? cand_idx : at<int32_t>(ws, oci);
     float *cd = cand_d ? cand_d : at<float>(ws, ocd);
     char *rr = at<char>(ws, orr);
-    size_t oq, op, oa, ob, om;
-    rerank_layout(db, nq, &oq, &op, &oa, &ob, &om);
+    size_t oq, op, oa, ob, om, osc;
+    rerank_layout(db, nq, &oq, &op, &oa, &ob, &om, &osc);
     uint32_t *qpack = at<uint32_t>(rr, oq);
     uint32_t *acnt = at<uint32_t>(rr, oa);
     int32_t *box = at<int32_t>(rr, ob);
@@ -915,7 +920,8 @@ int db_query_com(const db_t *db, int nq, const uint8_t *q_labels, int n_cand, in
         e = launch_topk_min(nq, (int)n, n_cand, D, ci, cd, sel_bytes ? at<char>(ws, osel) : nullptr,
                             sel_bytes, s);
     if (e == hipSuccess)
-        e = launch_rerank(db, nq, qpack, acnt, box, ci, n_cand, k, idx, score, counts, s);
+        e = launch_rerank(db, nq, qpack, acnt, box, ci, n_cand, k, idx, score, counts,
+                          at<char>(rr, osc), s);
     if (e != hipSuccess) return hip_fail(e, "db_query_com: launch");
     return DB_OK;
 }

@@ -419,114 +419,131 @@ __global__ void __launch_bounds__(kSelThreads) topk_min_kernel(const float *__re
 
 constexpr int kRerankMaxCand = 1024;
 
-// grid nq, 256 threads (4 waves). Wave w scores candidates w, w + 4, ...: lanes
-// sweep the rows where the query's row box meets the candidates' stored row
-// boxes (outside either box one side is zero and adds nothing), AND +
-// popcount against the candidate's planes; then the block ranks the
-// candidates by (score desc, index asc) and writes k.
-__global__ void __launch_bounds__(256) rerank_kernel(const uint32_t *__restrict__ planes,
-                                                     const uint32_t *__restrict__ popcnt,
-                                                     const int32_t *__restrict__ ebox, int Wp,
-                                                     int nxw, int ny, const uint32_t *__restrict__ qpack,
-                                                     const uint32_t *__restrict__ acnt,
-                                                     const int32_t *__restrict__ box,
-                                                     const int32_t *__restrict__ cand, int nc, int k,
-                                                     int32_t *__restrict__ out_idx,
-                                                     double *__restrict__ out_score,
-                                                     db_counts_t *__restrict__ out_counts)
+constexpr int kRerankPerBlock = 16;    // candidates scored per block (4 waves x 4)
+
+// grid (ceil(nc / kRerankPerBlock), nq), 256 threads (4 waves). Each wave scores
+// kRC candidates of query q at once: lanes sweep the rows where the query's row
+// box meets the candidates' stored row boxes (outside either box one side is
+// zero and adds nothing), AND + popcount against each candidate's planes; the
+// score and overlaps go to ws (score bits [nq][nc], index [nq][nc], I [nq][nc][2]).
+__global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__restrict__ planes,
+                                                           const uint32_t *__restrict__ popcnt,
+                                                           const int32_t *__restrict__ ebox, int Wp,
+                                                           int nxw, int ny,
+                                                           const uint32_t *__restrict__ qpack,
+                                                           const uint32_t *__restrict__ acnt,
+                                                           const int32_t *__restrict__ box,
+                                                           const int32_t *__restrict__ cand, int nc,
+                                                           uint64_t *__restrict__ ws_s,
+                                                           int32_t *__restrict__ ws_i,
+                                                           uint32_t *__restrict__ ws_I)
 {
-    __shared__ uint64_t ks[kRerankMaxCand];
-    __shared__ int32_t ki[kRerankMaxCand];
-    __shared__ uint32_t kI[kRerankMaxCand][2];
-    const int q = blockIdx.x;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int q = blockIdx.y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t *Q0 = qpack + (int64_t)q * 2 * Wp, *Q1 = Q0 + Wp;
     const int32_t *b = box + 4 * q;
     const int qz0 = b[0], qz1 = b[1], qy0 = b[2], qy1 = b[3];
     const uint32_t A0 = acnt[2 * q], A1 = acnt[2 * q + 1];
-    // Candidates in groups of kRC per wave: each query row is loaded once per group
-    // and the group sweeps the union of its members' boxes (each clipped to the
-    // query's); a member reads only the rows inside its own box.
+    // kRC candidates per wave: each query row is loaded once per group, and the
+    // group sweeps the union of its members' boxes (each clipped to the query's);
+    // a member reads only the rows inside its own box.
     constexpr int kRC = 4;
-    for (int c0 = wave * kRC; c0 < nc; c0 += nwaves * kRC) {
-        const uint32_t *D0[kRC], *D1[kRC];
-        int z0[kRC], z1[kRC], y0[kRC], y1[kRC];
-        int uz0 = INT_MAX, uz1 = INT_MIN, uy0 = INT_MAX, uy1 = INT_MIN;
+    const int c0 = blockIdx.x * kRerankPerBlock + wave * kRC;
+    if (c0 >= nc) return;   // a whole wave leaves; no block barrier below
+    const uint32_t *D0[kRC], *D1[kRC];
+    int z0[kRC], z1[kRC], y0[kRC], y1[kRC];
+    int uz0 = INT_MAX, uz1 = INT_MIN, uy0 = INT_MAX, uy1 = INT_MIN;
 #pragma unroll
-        for (int j = 0; j < kRC; ++j) {
-            const int c = min(c0 + j, nc - 1);          // a repeated candidate is discarded
-            const int32_t e = cand[(int64_t)q * nc + c];
-            D0[j] = planes + (int64_t)e * 2 * Wp;
-            D1[j] = D0[j] + Wp;
-            const int32_t *eb = ebox + 4 * (int64_t)e;
-            z0[j] = max(eb[0], qz0);
-            z1[j] = min(eb[1], qz1);
-            y0[j] = max(eb[2], qy0);
-            y1[j] = min(eb[3], qy1);
-            if (z1[j] > z0[j] && y1[j] > y0[j]) {
-                uz0 = min(uz0, z0[j]);
-                uz1 = max(uz1, z1[j]);
-                uy0 = min(uy0, y0[j]);
-                uy1 = max(uy1, y1[j]);
-            }
+    for (int j = 0; j < kRC; ++j) {
+        const int c = min(c0 + j, nc - 1);          // a repeated candidate is discarded
+        const int32_t e = cand[(int64_t)q * nc + c];
+        D0[j] = planes + (int64_t)e * 2 * Wp;
+        D1[j] = D0[j] + Wp;
+        const int32_t *eb = ebox + 4 * (int64_t)e;
+        z0[j] = max(eb[0], qz0);
+        z1[j] = min(eb[1], qz1);
+        y0[j] = max(eb[2], qy0);
+        y1[j] = min(eb[3], qy1);
+        if (z1[j] > z0[j] && y1[j] > y0[j]) {
+            uz0 = min(uz0, z0[j]);
+            uz1 = max(uz1, z1[j]);
+            uy0 = min(uy0, y0[j]);
+            uy1 = max(uy1, y1[j]);
         }
-        const int nyr = uy1 > uy0 ? uy1 - uy0 : 0;
-        const int nr = uz1 > uz0 ? (uz1 - uz0) * nyr : 0;
-        uint32_t i0[kRC], i1[kRC];
+    }
+    const int nyr = uy1 > uy0 ? uy1 - uy0 : 0;
+    const int nr = uz1 > uz0 ? (uz1 - uz0) * nyr : 0;
+    uint32_t i0[kRC], i1[kRC];
 #pragma unroll
-        for (int j = 0; j < kRC; ++j) i0[j] = i1[j] = 0;
-        for (int r = lane; r < nr; r += 64) {
-            const int zr = r / nyr;
-            const int z = uz0 + zr, y = uy0 + r - zr * nyr;
-            const int base = (z * ny + y) * nxw;
-            bool in[kRC];
+    for (int j = 0; j < kRC; ++j) i0[j] = i1[j] = 0;
+    for (int r = lane; r < nr; r += 64) {
+        const int zr = r / nyr;
+        const int z = uz0 + zr, y = uy0 + r - zr * nyr;
+        const int base = (z * ny + y) * nxw;
+        bool in[kRC];
 #pragma unroll
-            for (int j = 0; j < kRC; ++j) in[j] = z >= z0[j] && z < z1[j] && y >= y0[j] && y < y1[j];
-            if (nxw == 4) {
-                const u32x4 qa = *reinterpret_cast<const u32x4 *>(Q0 + base);
-                const u32x4 qb = *reinterpret_cast<const u32x4 *>(Q1 + base);
+        for (int j = 0; j < kRC; ++j) in[j] = z >= z0[j] && z < z1[j] && y >= y0[j] && y < y1[j];
+        if (nxw == 4) {
+            const u32x4 qa = *reinterpret_cast<const u32x4 *>(Q0 + base);
+            const u32x4 qb = *reinterpret_cast<const u32x4 *>(Q1 + base);
+#pragma unroll
+            for (int j = 0; j < kRC; ++j)
+                if (in[j]) {
+                    i0[j] += popc_and4(qa, *reinterpret_cast<const u32x4 *>(D0[j] + base));
+                    i1[j] += popc_and4(qb, *reinterpret_cast<const u32x4 *>(D1[j] + base));
+                }
+        } else {
+            for (int w = 0; w < nxw; ++w) {
+                const uint32_t qa = Q0[base + w], qb = Q1[base + w];
 #pragma unroll
                 for (int j = 0; j < kRC; ++j)
                     if (in[j]) {
-                        i0[j] += popc_and4(qa, *reinterpret_cast<const u32x4 *>(D0[j] + base));
-                        i1[j] += popc_and4(qb, *reinterpret_cast<const u32x4 *>(D1[j] + base));
+                        i0[j] += popc(qa & D0[j][base + w]);
+                        i1[j] += popc(qb & D1[j][base + w]);
                     }
-            } else {
-                for (int w = 0; w < nxw; ++w) {
-                    const uint32_t qa = Q0[base + w], qb = Q1[base + w];
-#pragma unroll
-                    for (int j = 0; j < kRC; ++j)
-                        if (in[j]) {
-                            i0[j] += popc(qa & D0[j][base + w]);
-                            i1[j] += popc(qb & D1[j][base + w]);
-                        }
-                }
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < kRC; ++j) {
-            const uint32_t a0 = wave_sum(i0[j]), a1 = wave_sum(i1[j]);
-            const int c = c0 + j;
-            if (lane == 0 && c < nc) {
-                const int32_t e = cand[(int64_t)q * nc + c];
-                const double sc = dice(a1, A1, popcnt[2 * (int64_t)e + 1]) +
-                                  dice(a0, A0, popcnt[2 * (int64_t)e]);
-                ks[c] = (uint64_t)__double_as_longlong(sc);
-                ki[c] = e;
-                kI[c][0] = a0;
-                kI[c][1] = a1;
             }
         }
     }
+#pragma unroll
+    for (int j = 0; j < kRC; ++j) {
+        const uint32_t a0 = wave_sum(i0[j]), a1 = wave_sum(i1[j]);
+        const int c = c0 + j;
+        if (lane == 0 && c < nc) {
+            const int64_t o = (int64_t)q * nc + c;
+            const int32_t e = cand[o];
+            const double sc = dice(a1, A1, popcnt[2 * (int64_t)e + 1]) +
+                              dice(a0, A0, popcnt[2 * (int64_t)e]);
+            ws_s[o] = (uint64_t)__double_as_longlong(sc);
+            ws_i[o] = e;
+            ws_I[2 * o] = a0;
+            ws_I[2 * o + 1] = a1;
+        }
+    }
+}
+
+// grid nq, 256 threads: rank the query's nc scored candidates by (score desc,
+// index asc) in LDS (bitonic over slot numbers) and write the first k.
+__global__ void __launch_bounds__(256) rerank_rank_kernel(const uint32_t *__restrict__ popcnt,
+                                                          const uint32_t *__restrict__ acnt, int nc,
+                                                          int k, const uint64_t *__restrict__ ws_s,
+                                                          const int32_t *__restrict__ ws_i,
+                                                          const uint32_t *__restrict__ ws_I,
+                                                          int32_t *__restrict__ out_idx,
+                                                          double *__restrict__ out_score,
+                                                          db_counts_t *__restrict__ out_counts)
+{
+    __shared__ uint64_t ks[kRerankMaxCand];
+    __shared__ int32_t ki[kRerankMaxCand];
+    __shared__ int16_t slot[kRerankMaxCand];
+    const int q = blockIdx.x;
     int P = 1;
     while (P < nc) P <<= 1;
-    for (int t = nc + threadIdx.x; t < P; t += blockDim.x) {
-        ks[t] = 0;
-        ki[t] = INT_MAX;
+    for (int t = threadIdx.x; t < P; t += blockDim.x) {
+        const bool in = t < nc;
+        ks[t] = in ? ws_s[(int64_t)q * nc + t] : 0ull;
+        ki[t] = in ? ws_i[(int64_t)q * nc + t] : INT_MAX;
+        slot[t] = (int16_t)t;
     }
-    // Bitonic sort of slot numbers by (score desc, index asc), carrying the counts.
-    __shared__ int16_t slot[kRerankMaxCand];
-    for (int t = threadIdx.x; t < P; t += blockDim.x) slot[t] = (int16_t)t;
     for (int size = 2; size <= P; size <<= 1)
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
             __syncthreads();
@@ -542,16 +559,17 @@ __global__ void __launch_bounds__(256) rerank_kernel(const uint32_t *__restrict_
             }
         }
     __syncthreads();
+    const uint32_t A0 = acnt[2 * q], A1 = acnt[2 * q + 1];
     for (int t = threadIdx.x; t < k; t += blockDim.x) {
-        const int s = slot[t];
+        const int sl = slot[t];
         const int64_t o = (int64_t)q * k + t;
-        const int32_t e = ki[s];
+        const int32_t e = ki[sl];
         out_idx[o] = e;
-        out_score[o] = __longlong_as_double((long long)ks[s]);
+        out_score[o] = __longlong_as_double((long long)ks[sl]);
         if (out_counts) {
             db_counts_t cc;
-            cc.inter[0] = kI[s][0];
-            cc.inter[1] = kI[s][1];
+            cc.inter[0] = ws_I[2 * ((int64_t)q * nc + sl)];
+            cc.inter[1] = ws_I[2 * ((int64_t)q * nc + sl) + 1];
             cc.a[0] = A0;
             cc.a[1] = A1;
             cc.b[0] = popcnt[2 * (int64_t)e];
@@ -826,13 +844,24 @@ hipError_t launch_topk_min(int M, int N, int k, const float *D, int32_t *idx, fl
     return hipGetLastError();
 }
 
+size_t rerank_ws_bytes(int nq) { return (size_t)nq * kRerankMaxCand * 20; }  // 8 + 4 + 2 * 4 bytes per candidate
+
 hipError_t launch_rerank(const db_t *db, int nq, const uint32_t *qpack, const uint32_t *acnt,
                          const int32_t *box, const int32_t *cand, int nc, int k, int32_t *idx,
-                         double *score, db_counts_t *counts, hipStream_t s)
+                         double *score, db_counts_t *counts, void *ws, hipStream_t s)
 {
     const Geometry &g = db->g;
-    hipLaunchKernelGGL(rerank_kernel, dim3(nq), dim3(256), 0, s, db->planes, db->popcnt, db->box,
-                       g.Wp, g.nxw, g.ny, qpack, acnt, box, cand, nc, k, idx, score, counts);
+    uint64_t *ws_s = static_cast<uint64_t *>(ws);
+    int32_t *ws_i = reinterpret_cast<int32_t *>(ws_s + (size_t)nq * nc);
+    uint32_t *ws_I = reinterpret_cast<uint32_t *>(ws_i + (size_t)nq * nc);
+    hipLaunchKernelGGL(rerank_score_kernel,
+                       dim3((unsigned)((nc + kRerankPerBlock - 1) / kRerankPerBlock), (unsigned)nq),
+                       dim3(256), 0, s, db->planes, db->popcnt, db->box, g.Wp, g.nxw, g.ny, qpack,
+                       acnt, box, cand, nc, ws_s, ws_i, ws_I);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(rerank_rank_kernel, dim3(nq), dim3(256), 0, s, db->popcnt, acnt, nc, k, ws_s,
+                       ws_i, ws_I, idx, score, counts);
     return hipGetLastError();
 }
 

@@ -123,9 +123,12 @@ hipError_t launch_dist_fp8(int M, int N, int K, const uint8_t *Q, const float *q
 size_t topk_min_ws_bytes(int M, int N, int k);
 hipError_t launch_topk_min(int M, int N, int k, const float *D, int32_t *idx, float *d, void *ws,
                            size_t ws_bytes, hipStream_t s);
+// Exact rerank of nc <= DB_KMAX candidates per query; ws of rerank_ws_bytes(nq) holds the
+// scored candidates between the scoring and the ranking kernel.
+size_t rerank_ws_bytes(int nq);
 hipError_t launch_rerank(const db_t *db, int nq, const uint32_t *qpack, const uint32_t *acnt,
                          const int32_t *box, const int32_t *cand, int nc, int k, int32_t *idx,
-                         double *score, db_counts_t *counts, hipStream_t s);
+                         double *score, db_counts_t *counts, void *ws, hipStream_t s);
 
 // Row boxes, moments, box-restricted scan, centre-of-mass distances (sparse.hip).
 hipError_t launch_meta(const uint32_t *recs, int64_t n, const Geometry &g, int32_t *box,

@@ -60,9 +60,10 @@ __device__ __forceinline__ void stage_weights(T *wsh, const WT *__restrict__ Wt,
     }
 }
 
-// grid (ceil(OD*OH*OW / 256), ceil(Co / kCB), B)
+// grid (ceil(B*OD*OH*OW / 256), ceil(Co / kCB)): one thread per (sample, output
+// voxel), so small late layers still fill whole waves.
 template <class T, class WT>
-__global__ void __launch_bounds__(256) conv_fwd_kernel(int Ci, int Co, int D, int H, int W,
+__global__ void __launch_bounds__(256) conv_fwd_kernel(int B, int Ci, int Co, int D, int H, int W,
                                                        const T *__restrict__ X,
                                                        const WT *__restrict__ Wt,
                                                        const T *__restrict__ bias, int relu,
@@ -71,10 +72,13 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(int Ci, int Co, int D, in
     __shared__ T wsh[kCC * 27 * kCB];
     const int OD = D / 2, OH = H / 2, OW = W / 2;
     const int osp = OD * OH * OW;
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = o < osp;
-    const int oo = active ? o : 0;
-    const int co0 = blockIdx.y * kCB, b = blockIdx.z;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = t < (int64_t)B * osp;
+    const int64_t tt = active ? t : 0;
+    const int b = (int)(tt / osp);
+    const int o = (int)(tt - (int64_t)b * osp);
+    const int oo = o;
+    const int co0 = blockIdx.y * kCB;
     const int nco = min(kCB, Co - co0);
     const int ow = oo % OW, oh = (oo / OW) % OH, od = oo / (OW * OH);
     const int64_t isp = (int64_t)D * H * W;
@@ -120,11 +124,11 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(int Ci, int Co, int D, in
     }
 }
 
-// Adjoint map: grid (ceil(D*H*W / 256), ceil(Ci / kCB), B); one thread per input voxel
-// and kCB input channels (each dY tap is loaded once for all of them).
+// Adjoint map: grid (ceil(B*D*H*W / 256), ceil(Ci / kCB)); one thread per (sample,
+// input voxel) and kCB input channels (each dY tap is loaded once for all of them).
 template <class T, class WT>
-__global__ void __launch_bounds__(256) conv_bwd_data_kernel(int Ci, int Co, int D, int H, int W,
-                                                            const T *__restrict__ dY,
+__global__ void __launch_bounds__(256) conv_bwd_data_kernel(int B, int Ci, int Co, int D, int H,
+                                                            int W, const T *__restrict__ dY,
                                                             const WT *__restrict__ Wt,
                                                             const T *__restrict__ bias, int relu,
                                                             T *__restrict__ dX)
@@ -133,10 +137,13 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(int Ci, int Co, int 
     const int OD = D / 2, OH = H / 2, OW = W / 2;
     const int osp = OD * OH * OW;
     const int isp = D * H * W;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = i < isp;
-    const int ii = active ? i : 0;
-    const int ci0 = blockIdx.y * kCB, b = blockIdx.z;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = t < (int64_t)B * isp;
+    const int64_t tt = active ? t : 0;
+    const int b = (int)(tt / isp);
+    const int i = (int)(tt - (int64_t)b * isp);
+    const int ii = i;
+    const int ci0 = blockIdx.y * kCB;
     const int nci = min(kCB, Ci - ci0);
     const int iw = ii % W, ih = (ii / W) % H, id = ii / (W * H);
     T acc[kCB];
@@ -543,6 +550,106 @@ __global__ void meanpool_labels_kernel(const uint8_t *__restrict__ lab, int B, i
     }
 }
 
+// Fast paths of the two pooling kernels above (same results): a thread reads the
+// four 2-row slabs of a 2x2x2 block row with wide loads and writes 8 (labels) or
+// 16 (packed masks) consecutive outputs per channel.
+//
+// Labels: nx % 16 == 0. Thread = (b, z, y, group of 8 output x = 16 input bytes per row).
+template <class T>
+__global__ void __launch_bounds__(256) meanpool_labels_fast_kernel(const uint8_t *__restrict__ lab,
+                                                                   int B, int nx, int ny, int nz,
+                                                                   int m0, int nm,
+                                                                   T *__restrict__ out)
+{
+    const int X = nx / 2, Y = ny / 2, Z = nz / 2, G = X / 8;
+    const int64_t total = (int64_t)B * Z * Y * G;
+    const int64_t V = (int64_t)nx * ny * nz;
+    const int64_t per = (int64_t)Z * Y * X;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int g = (int)(t % G);
+        int64_t r = t / G;
+        const int y = (int)(r % Y);
+        r /= Y;
+        const int z = (int)(r % Z);
+        const int b = (int)(r / Z);
+        // Per mask: SWAR byte sums over the 4 rows (each byte counts 0..4).
+        uint32_t f[4] = {0u, 0u, 0u, 0u}, h[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy) {
+                const u32x4 v = *reinterpret_cast<const u32x4 *>(
+                    lab + b * V + ((int64_t)(2 * z + dz) * ny + (2 * y + dy)) * nx + 16 * g);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    f[e] += v[e] & 0x01010101u;
+                    h[e] += (v[e] >> 1) & 0x01010101u;
+                }
+            }
+        const int64_t o = ((int64_t)b * nm) * per + ((int64_t)z * Y + y) * X + 8 * g;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int m = m0 + c;
+            if (c >= nm) break;
+            const uint32_t *s = m == 0 ? f : h;
+            T v8[8];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t w = s[e];
+                v8[2 * e] = (T)((w & 0xffu) + ((w >> 8) & 0xffu)) * T(0.125);
+                v8[2 * e + 1] = (T)(((w >> 16) & 0xffu) + (w >> 24)) * T(0.125);
+            }
+            T *dst = out + o + (int64_t)c * per;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) dst[e] = v8[e];
+        }
+    }
+}
+
+// Packed masks: nx % 32 == 0. Thread = (b, mask, z, y, word of 32 input x = 16 outputs).
+template <class T>
+__global__ void __launch_bounds__(256) meanpool_db_fast_kernel(const uint32_t *__restrict__ planes,
+                                                               int Wp, int nxw, int ny, int nz,
+                                                               const int32_t *__restrict__ idx,
+                                                               int B, int m0, int nm,
+                                                               T *__restrict__ out)
+{
+    const int X = nxw * 16, Y = ny / 2, Z = nz / 2;
+    const int64_t total = (int64_t)B * nm * Z * Y * nxw;
+    const int64_t per = (int64_t)Z * Y * X;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int wx = (int)(t % nxw);
+        int64_t r = t / nxw;
+        const int y = (int)(r % Y);
+        r /= Y;
+        const int z = (int)(r % Z);
+        r /= Z;
+        const int c = (int)(r % nm);
+        const int b = (int)(r / nm);
+        const uint32_t *pl = planes + (int64_t)idx[b] * 2 * Wp + (int64_t)(m0 + c) * Wp;
+        // Set bits per 2-bit pair, summed over the 4 rows in 4-bit fields (0..8):
+        // even pairs in qe, odd pairs in qo.
+        uint32_t qe = 0, qo = 0;
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy) {
+                const uint32_t w = pl[((int64_t)(2 * z + dz) * ny + (2 * y + dy)) * nxw + wx];
+                const uint32_t p = (w & 0x55555555u) + ((w >> 1) & 0x55555555u);
+                qe += p & 0x33333333u;
+                qo += (p >> 2) & 0x33333333u;
+            }
+        T *dst = out + ((int64_t)b * nm + c) * per + ((int64_t)z * Y + y) * X + 16 * wx;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            dst[2 * j] = (T)((qe >> (4 * j)) & 15u) * T(0.125);
+            dst[2 * j + 1] = (T)((qo >> (4 * j)) & 15u) * T(0.125);
+        }
+    }
+}
+
 }  // namespace tdb
 
 // ---- C ABI ----------------------------------------------------------------------------------
@@ -595,6 +702,17 @@ static int meanpool_db(const char *fn, const db_t *db, const int32_t *idx, int B
         return tdb_set_error(DB_EINVAL, "%s: bad arguments", fn);
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t total = (int64_t)B * nm * (g.nz / 2) * (g.ny / 2) * (g.nx / 2);
+    if (!(g.nx % 32)) {
+        const int64_t tf = total / 16;
+        if (dtype == NN_F32)
+            hipLaunchKernelGGL(meanpool_db_fast_kernel<float>, dim3(grid1(tf, 65535)), dim3(256), 0, s,
+                               db->planes, g.Wp, g.nxw, g.ny, g.nz, idx, B, m0, nm, (float *)out);
+        else
+            hipLaunchKernelGGL(meanpool_db_fast_kernel<double>, dim3(grid1(tf, 65535)), dim3(256), 0,
+                               s, db->planes, g.Wp, g.nxw, g.ny, g.nz, idx, B, m0, nm,
+                               (double *)out);
+        return launched(fn);
+    }
     if (dtype == NN_F32)
         hipLaunchKernelGGL(meanpool_db_kernel<float>, dim3(grid1(total)), dim3(256), 0, s,
                            db->planes, g.Wp, g.nxw, g.ny, g.nz, g.nx, idx, B, m0, nm, (float *)out);
@@ -612,6 +730,16 @@ static int meanpool_labels(const char *fn, const uint8_t *labels, int B, int nx,
         return tdb_set_error(DB_EINVAL, "%s: bad arguments", fn);
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t total = (int64_t)B * nm * (nz / 2) * (ny / 2) * (nx / 2);
+    if (!(nx % 16) && !((uintptr_t)labels % 16)) {
+        const int64_t tf = total / nm / 8;
+        if (dtype == NN_F32)
+            hipLaunchKernelGGL(meanpool_labels_fast_kernel<float>, dim3(grid1(tf, 65535)), dim3(256),
+                               0, s, labels, B, nx, ny, nz, m0, nm, (float *)out);
+        else
+            hipLaunchKernelGGL(meanpool_labels_fast_kernel<double>, dim3(grid1(tf, 65535)),
+                               dim3(256), 0, s, labels, B, nx, ny, nz, m0, nm, (double *)out);
+        return launched(fn);
+    }
     if (dtype == NN_F32)
         hipLaunchKernelGGL(meanpool_labels_kernel<float>, dim3(grid1(total)), dim3(256), 0, s,
                            labels, B, nx, ny, nz, m0, nm, (float *)out);
@@ -655,18 +783,18 @@ int nn_conv3d_s2_fwd(int dtype, int B, int Ci, int Co, int D, int H, int W, cons
     if (pair < 0 || !conv_dims_ok(B, Ci, Co, D, H, W) || !X || !Wt || !Y)
         return tdb_set_error(DB_EINVAL, "nn_conv3d_s2_fwd: bad arguments");
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    const int osp = (D / 2) * (H / 2) * (W / 2);
-    const dim3 grid((osp + 255) / 256, (Co + kCB - 1) / kCB, B);
+    const int64_t osp = (int64_t)(D / 2) * (H / 2) * (W / 2);
+    const dim3 grid((unsigned)((B * osp + 255) / 256), (Co + kCB - 1) / kCB);
     if (pair == 0)
-        hipLaunchKernelGGL((conv_fwd_kernel<float, uint16_t>), grid, dim3(256), 0, s, Ci, Co, D, H,
+        hipLaunchKernelGGL((conv_fwd_kernel<float, uint16_t>), grid, dim3(256), 0, s, B, Ci, Co, D, H,
                            W, (const float *)X, (const uint16_t *)Wt, (const float *)bias, relu,
                            (float *)Y);
     else if (pair == 1)
-        hipLaunchKernelGGL((conv_fwd_kernel<float, float>), grid, dim3(256), 0, s, Ci, Co, D, H, W,
+        hipLaunchKernelGGL((conv_fwd_kernel<float, float>), grid, dim3(256), 0, s, B, Ci, Co, D, H, W,
                            (const float *)X, (const float *)Wt, (const float *)bias, relu,
                            (float *)Y);
     else
-        hipLaunchKernelGGL((conv_fwd_kernel<double, double>), grid, dim3(256), 0, s, Ci, Co, D, H,
+        hipLaunchKernelGGL((conv_fwd_kernel<double, double>), grid, dim3(256), 0, s, B, Ci, Co, D, H,
                            W, (const double *)X, (const double *)Wt, (const double *)bias, relu,
                            (double *)Y);
     return launched("nn_conv3d_s2_fwd");
@@ -680,18 +808,18 @@ int nn_conv3d_s2_bwd_data(int dtype, int B, int Ci, int Co, int D, int H, int W,
     if (pair < 0 || !conv_dims_ok(B, Ci, Co, D, H, W) || !dY || !Wt || !dX)
         return tdb_set_error(DB_EINVAL, "nn_conv3d_s2_bwd_data: bad arguments");
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    const int isp = D * H * W;
-    const dim3 grid((isp + 255) / 256, (Ci + kCB - 1) / kCB, B);
+    const int64_t isp = (int64_t)D * H * W;
+    const dim3 grid((unsigned)((B * isp + 255) / 256), (Ci + kCB - 1) / kCB);
     if (pair == 0)
-        hipLaunchKernelGGL((conv_bwd_data_kernel<float, uint16_t>), grid, dim3(256), 0, s, Ci, Co,
+        hipLaunchKernelGGL((conv_bwd_data_kernel<float, uint16_t>), grid, dim3(256), 0, s, B, Ci, Co,
                            D, H, W, (const float *)dY, (const uint16_t *)Wt, (const float *)bias,
                            relu, (float *)dX);
     else if (pair == 1)
-        hipLaunchKernelGGL((conv_bwd_data_kernel<float, float>), grid, dim3(256), 0, s, Ci, Co, D,
+        hipLaunchKernelGGL((conv_bwd_data_kernel<float, float>), grid, dim3(256), 0, s, B, Ci, Co, D,
                            H, W, (const float *)dY, (const float *)Wt, (const float *)bias, relu,
                            (float *)dX);
     else
-        hipLaunchKernelGGL((conv_bwd_data_kernel<double, double>), grid, dim3(256), 0, s, Ci, Co,
+        hipLaunchKernelGGL((conv_bwd_data_kernel<double, double>), grid, dim3(256), 0, s, B, Ci, Co,
                            D, H, W, (const double *)dY, (const double *)Wt, (const double *)bias,
                            relu, (double *)dX);
     return launched("nn_conv3d_s2_bwd_data");
