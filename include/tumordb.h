@@ -77,7 +77,9 @@ enum {
  *             any set bit of either mask lie in [z0, z1) x [y0, y1) (all zero
  *             for an entry without set bits);
  *   moments:  uint64 [capacity][4] = sum of x, of y, of z over the FLAIR
- *             voxels, and their count (the centre of mass is sum / count).
+ *             voxels, and their count (the centre of mass is sum / count);
+ *   order:    int32 [capacity], the entries grouped by row-box centre for
+ *             db_query_batch (library-internal).
  * Returns 0 if the dimensions are invalid. */
 size_t db_storage_bytes(int nx, int ny, int nz, int64_t capacity);
 
@@ -130,7 +132,9 @@ int db_query_sparse(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx
  * rois: HOST array [nq] (validated before enqueue: inside the grid, non-empty)
  * or NULL for whole grids; outputs idx [nq][k], score [nq][k], counts
  * [nq][k] or NULL (device). The kernel sequence is recorded once into a HIP
- * graph per (handle, shape, pointers) and replayed. */
+ * graph per (handle, shape, pointers) and replayed. The first call after
+ * entries were appended synchronises the device once to regroup the entries
+ * by their row boxes. */
 int db_query_batch(const db_t *db, int nq, const uint8_t *q_labels, const db_roi_t *rois, int k,
                    int32_t *idx, double *score, db_counts_t *counts, void *ws, size_t ws_bytes,
                    void *stream);

@@ -150,7 +150,8 @@ class TumorDB:
         pc = up(self.capacity * 2 * self.Wp * 4)
         box = pc + up(self.capacity * 8)
         mom = box + up(self.capacity * 16)
-        return pc, box, mom
+        order = mom + up(self.capacity * 32)
+        return pc, box, mom, order
 
     @property
     def popcounts(self) -> torch.Tensor:
@@ -163,6 +164,13 @@ class TumorDB:
         """int32 view [capacity][4] of the row boxes z0, z1, y0, y1 of the set bits."""
         off = self._offsets()[1]
         return self.storage[off:off + self.capacity * 16].view(torch.int32).view(self.capacity, 4)
+
+    @property
+    def tile_order(self) -> torch.Tensor:
+        """int32 view [capacity] of the entry order of the batched scan's tiles (valid after a
+        batched query)."""
+        off = self._offsets()[3]
+        return self.storage[off:off + self.capacity * 4].view(torch.int32)
 
     @property
     def moments(self) -> torch.Tensor:

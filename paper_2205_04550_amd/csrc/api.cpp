@@ -265,6 +265,32 @@ static hipError_t dist_launch(int fmt, int M, int N, int dim, const void *q_code
                            static_cast<const uint8_t *>(x_codes), x_scale, x_sq, D, mode, s);
 }
 
+// Sort the entries by the centre of their row boxes (z in bands of 8 planes,
+// then y), so that the batched kernel's 4-entry tiles hold overlapping boxes.
+// Reads the boxes back after a device synchronisation; host sort; one upload.
+static int build_tile_order(db_t *db)
+{
+    const int64_t n = db->count;
+    std::vector<int32_t> box((size_t)n * 4);
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(box.data(), db->box, (size_t)n * 16, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "db_query_batch: read row boxes");
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    auto key = [&](int32_t i) {
+        const int32_t *b = &box[(size_t)i * 4];
+        const bool empty = !(b[1] > b[0] && b[3] > b[2]);
+        const int64_t zc = b[0] + b[1], yc = b[2] + b[3];
+        return empty ? INT64_MAX : ((zc / 16) << 32) | (yc << 16) | (b[1] - b[0]);
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return key(a) < key(b); });
+    e = hipMemcpy(db->tile_order, order.data(), (size_t)n * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "db_query_batch: upload tile order");
+    db->tile_order_n = n;
+    return DB_OK;
+}
+
 extern "C" {
 
 size_t db_storage_bytes(int nx, int ny, int nz, int64_t capacity)
@@ -274,7 +300,7 @@ size_t db_storage_bytes(int nx, int ny, int nz, int64_t capacity)
         return 0;
     return align_up((size_t)capacity * 2 * g.Wp * 4, kAlign) +
            align_up((size_t)capacity * 2 * 4, kAlign) + align_up((size_t)capacity * 4 * 4, kAlign) +
-           align_up((size_t)capacity * 4 * 8, kAlign);
+           align_up((size_t)capacity * 4 * 8, kAlign) + align_up((size_t)capacity * 4, kAlign);
 }
 
 int db_build(db_t **out, int nx, int ny, int nz, float t_lo, float t_hi, int64_t capacity,
@@ -320,6 +346,9 @@ int db_build(db_t **out, int nx, int ny, int nz, float t_lo, float t_hi, int64_t
     db->popcnt = reinterpret_cast<uint32_t *>(static_cast<char *>(storage) + o_pc);
     db->box = reinterpret_cast<int32_t *>(static_cast<char *>(storage) + o_box);
     db->mom = reinterpret_cast<uint64_t *>(static_cast<char *>(storage) + o_mom);
+    const size_t o_ord = o_mom + align_up((size_t)capacity * 4 * 8, kAlign);
+    db->tile_order = reinterpret_cast<int32_t *>(static_cast<char *>(storage) + o_ord);
+    db->tile_order_n = 0;
     db->storage_bytes = storage_bytes;
     db->cus = cus;
     db->device = dev;
@@ -532,6 +561,11 @@ int db_query_batch(const db_t *db_c, int nq, const uint8_t *q_labels, const db_r
             }
     }
 
+    // Entries grouped by row-box centre for the LDS kernel's tiles (rebuilt after appends).
+    if (P.use_lds && db->tile_order_n != db->count) {
+        rc = build_tile_order(db);
+        if (rc) return rc;
+    }
     if (!db->graph) {
         db->graph = new (std::nothrow) BatchGraph();
         if (!db->graph) return fail(DB_ENOMEM, "db_query_batch: out of host memory");

@@ -24,6 +24,8 @@
 // round-robin over XCDs) and steals from the others when its queue is empty,
 // so every item is done whatever the dispatch order; the mapping only affects
 // L2 locality. Every block exits once all 8 queues are empty.
+#include <limits.h>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -136,10 +138,17 @@ __device__ __forceinline__ void count_rows4(uint32_t (&acc)[16], const uint32_t 
 //   cnt uint32 [nqc][kTile][4]            I_FLAIR, I_T1Gd, |B_FLAIR n R|, |B_T1Gd n R|
 // list_off [chunks * nslabs + 1] / list_q: per (chunk, slab) the queries whose
 // box meets the slab.
+//
+// A tile holds entries tile_order[4t .. 4t+3] (entries sorted by the centre of
+// their stored row boxes, so a tile's members overlap). Rows outside the union
+// of the members' row boxes are zero in every member and add nothing to I or
+// |B n R|: slabs outside it are neither staged nor scanned, and each query's
+// rows are clipped to it.
 __global__ void __launch_bounds__(kBatchThreads) batch_lds_kernel(
     const uint32_t *__restrict__ planes, int Wp, int nxw, int ny, int nz, int64_t n, int Z,
     int nslabs, const uint32_t *__restrict__ qpack, const int32_t *__restrict__ rois,
     const int32_t *__restrict__ list_off, const int32_t *__restrict__ list_q, int qchunk, int nq,
+    const int32_t *__restrict__ tile_order, const int32_t *__restrict__ ebox,
     uint32_t *__restrict__ inter, uint32_t *__restrict__ bcnt, int64_t out_qstride)
 {
     extern __shared__ u32x4 lds4[];
@@ -158,11 +167,27 @@ __global__ void __launch_bounds__(kBatchThreads) batch_lds_kernel(
 
     for (int i = threadIdx.x; i < nqc * kTile * 4; i += blockDim.x)
         cnt[i] = 0;
+    // The tile's members and the union of their row boxes.
+    int64_t ent[kTile];
+    int uz0 = INT_MAX, uz1 = INT_MIN, uy0 = INT_MAX, uy1 = INT_MIN;
+#pragma unroll
+    for (int s = 0; s < kTile; ++s) {
+        const int64_t p = (e0 + s < n) ? e0 + s : n - 1;   // alias past the end
+        ent[s] = tile_order ? (int64_t)tile_order[p] : p;
+        const int32_t *b = ebox + 4 * ent[s];
+        if (b[1] > b[0] && b[3] > b[2]) {
+            uz0 = min(uz0, b[0]);
+            uz1 = max(uz1, b[1]);
+            uy0 = min(uy0, b[2]);
+            uy1 = max(uy1, b[3]);
+        }
+    }
 
     for (int slab = 0; slab < nslabs; ++slab) {
         const int zs0 = slab * Z;
         const int zn = min(Z, nz - zs0);
         const int words = zn * plane_w;
+        if (zs0 >= uz1 || zs0 + zn <= uz0) continue;   // block-uniform: no member has a row here
         __syncthreads();  // the previous slab is consumed; counters are zeroed
         // Stage the tile's slab: kTile entries x 2 masks x `words` words.
         if ((plane_w & 3) == 0) {
@@ -171,7 +196,7 @@ __global__ void __launch_bounds__(kBatchThreads) batch_lds_kernel(
                 const int sm = i / w4;
                 const int j = i - sm * w4;
                 const int s = sm >> 1, m = sm & 1;
-                const int64_t e = (e0 + s < n) ? e0 + s : n - 1;  // alias past the end
+                const int64_t e = ent[s];
                 const u32x4 *g = reinterpret_cast<const u32x4 *>(
                     planes + e * 2 * (int64_t)Wp + (int64_t)m * Wp + (int64_t)zs0 * plane_w);
                 reinterpret_cast<u32x4 *>(D + sm * slab_w)[j] = load_stream(g + j);
@@ -181,7 +206,7 @@ __global__ void __launch_bounds__(kBatchThreads) batch_lds_kernel(
                 const int sm = i / words;
                 const int j = i - sm * words;
                 const int s = sm >> 1, m = sm & 1;
-                const int64_t e = (e0 + s < n) ? e0 + s : n - 1;
+                const int64_t e = ent[s];
                 D[sm * slab_w + j] =
                     planes[e * 2 * (int64_t)Wp + (int64_t)m * Wp + (int64_t)zs0 * plane_w + j];
             }
@@ -192,9 +217,10 @@ __global__ void __launch_bounds__(kBatchThreads) batch_lds_kernel(
         for (int li = lo + wave; li < hi; li += nwaves) {
             const int q = list_q[li];
             const int32_t *R = rois + 6 * q;
-            const int x0 = R[0], y0 = R[1], z0 = R[2], x1 = R[3], y1 = R[4], z1 = R[5];
-            const int zlo = max(z0, zs0), zhi = min(z1, zs0 + zn);
-            const uint32_t nyr = (uint32_t)(y1 - y0);
+            const int x0 = R[0], x1 = R[3];
+            const int y0 = max(R[1], uy0), y1 = min(R[4], uy1);
+            const int zlo = max(max(R[2], zs0), uz0), zhi = min(min(R[5], zs0 + zn), uz1);
+            const uint32_t nyr = y1 > y0 ? (uint32_t)(y1 - y0) : 0u;
             const uint32_t nr = (zhi > zlo) ? (uint32_t)(zhi - zlo) * nyr : 0u;
             const uint32_t M = nyr > 1 ? magic_u32(nyr) : 0u;
             const uint32_t *Q0 = qpack + (int64_t)q * 2 * Wp;
@@ -257,8 +283,8 @@ __global__ void __launch_bounds__(kBatchThreads) batch_lds_kernel(
     __syncthreads();
     for (int i = threadIdx.x; i < nqc * kTile; i += blockDim.x) {
         const int qi = i / kTile, s = i - qi * kTile;
-        const int64_t e = e0 + s;
-        if (e < n) {
+        const int64_t e = ent[s];
+        if (e0 + s < n) {
             const uint32_t *c = cnt + i * 4;
             uint32_t *io = inter + (int64_t)(q0 + qi) * out_qstride + 2 * e;
             uint32_t *bo = bcnt + (int64_t)(q0 + qi) * out_qstride + 2 * e;
@@ -396,10 +422,11 @@ hipError_t launch_batch_scan(const db_t *db, int64_t n, int nq, const BatchPlan 
     const Geometry &g = db->g;
     const int64_t ntiles = (n + kTile - 1) / kTile;
     if (p.use_lds) {
+        const int32_t *tile_order = db->tile_order_n == n ? db->tile_order : nullptr;
         hipLaunchKernelGGL(batch_lds_kernel, dim3((unsigned)ntiles, p.nchunks), dim3(p.threads),
                            p.lds_bytes, s, db->planes, g.Wp, g.nxw, g.ny, g.nz, n, p.Z, p.nslabs,
-                           qpack, rois, list_off, list_q, p.qchunk, nq, inter, bcnt,
-                           2 * db->capacity);
+                           qpack, rois, list_off, list_q, p.qchunk, nq, tile_order, db->box, inter,
+                           bcnt, 2 * db->capacity);
     } else {
         hipLaunchKernelGGL(batch_rows_kernel, dim3(db->cus * 8), dim3(256), 0, s, db->planes, g.Wp,
                            g.nxw, g.ny, n, nq, qpack, rois, order, ntiles, counters, inter, bcnt,

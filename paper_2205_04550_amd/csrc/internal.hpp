@@ -44,6 +44,8 @@ struct db_t {
     uint32_t *popcnt;   // [capacity][2]
     int32_t *box;       // [capacity][4] row box z0, z1, y0, y1 of the set bits
     uint64_t *mom;      // [capacity][4] FLAIR moments: sum x, sum y, sum z, count
+    int32_t *tile_order;  // [capacity] entries sorted by row-box centre (batched scan tiles)
+    int64_t tile_order_n; // entries the tile order covers (it is rebuilt when count differs)
     size_t storage_bytes;
     int cus;                 // compute units of the device the handle was built on
     int device;

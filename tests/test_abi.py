@@ -40,11 +40,11 @@ def test_storage_bytes():
     # row boxes 16 and moments 32 bytes per entry; each piece 256-byte aligned.
     up = lambda b: (b + 255) // 256 * 256
     planes = 50000 * 2 * 65536 * 4
-    meta = up(50000 * 8) + up(50000 * 16) + up(50000 * 32)
+    meta = up(50000 * 8) + up(50000 * 16) + up(50000 * 32) + up(50000 * 4)
     assert binding.storage_bytes(128, 128, 128, 50000) == planes + meta
-    # Ragged plane: 32x3x1 = 3 words, padded to 4: 10*2*4*4 = 320 -> 512; then 80, 160
-    # and 320 bytes -> 256, 256 and 512.
-    assert binding.storage_bytes(32, 3, 1, 10) == 512 + 256 + 256 + 512
+    # Ragged plane: 32x3x1 = 3 words, padded to 4: 10*2*4*4 = 320 -> 512; then 80, 160,
+    # 320 and 40 bytes -> 256, 256, 512 and 256.
+    assert binding.storage_bytes(32, 3, 1, 10) == 512 + 256 + 256 + 512 + 256
     assert binding.storage_bytes(33, 4, 4, 10) == 0      # nx not a multiple of 32
     assert binding.storage_bytes(32, 0, 4, 10) == 0
     assert binding.storage_bytes(32, 4, 4, 0) == 0
