@@ -265,9 +265,11 @@ int labels_resample(int nq, const uint8_t *in, int nx, int ny, int nz, uint8_t *
 /* Wait for `stream` and report any asynchronous device error as DB_EHIP. */
 int db_sync(const db_t *db, void *stream);
 
-/* Timing of the dominant kernel: while enabled, every db_scan / db_query
- * records a HIP event pair on its stream around the overlap-scan kernel and
- * every db_query_batch one around its graph launch. db_profile_read waits
+/* Timing of the dominant kernel: while enabled, every db_scan / db_query /
+ * db_query_sparse records a HIP event pair on its stream around the overlap-
+ * scan kernel, every db_rerank / db_query_embed / db_query_com one around the
+ * candidate-scoring kernel and every db_query_batch one around its graph
+ * launch. db_profile_read waits
  * for the recorded events, returns their summed elapsed milliseconds and the
  * number of pairs, and clears them. For measurement, not for production. */
 int db_profile(db_t *db, int enable);

@@ -804,6 +804,19 @@ size_t db_rerank_workspace_bytes(const db_t *db, int nq)
     return rerank_layout(db, nq, &a, &b, &c, &d);
 }
 
+// Score the candidates (the dominant kernel of a rerank: profiled), then rank them.
+static hipError_t rerank_launches(const db_t *db, int nq, const uint32_t *qpack,
+                                  const uint32_t *acnt, const int32_t *box, const int32_t *cand,
+                                  int nc, int k, int32_t *idx, double *score, db_counts_t *counts,
+                                  void *ws, hipStream_t s)
+{
+    hipError_t e = prof_mark(db, s);
+    if (e == hipSuccess) e = launch_rerank_score(db, nq, qpack, acnt, box, cand, nc, ws, s);
+    if (e == hipSuccess) e = prof_mark(db, s);
+    if (e == hipSuccess) e = launch_rerank_rank(db, nq, acnt, nc, k, idx, score, counts, ws, s);
+    return e;
+}
+
 static hipError_t enqueue_rerank(const db_t *db, int nq, const uint8_t *q_labels,
                                  const int32_t *cand, int nc, int k, int32_t *idx, double *score,
                                  db_counts_t *counts, void *ws, hipStream_t s)
@@ -816,9 +829,8 @@ static hipError_t enqueue_rerank(const db_t *db, int nq, const uint8_t *q_labels
     QueryPart *qpart = at<QueryPart>(ws, op);
     hipError_t e = launch_pack_queries(db, q_labels, nq, nullptr, qpack, qpart, s);
     if (e == hipSuccess) e = launch_sum_parts(qpart, nq, acnt, box, at<uint64_t>(ws, om), s);
-    if (e == hipSuccess)
-        e = launch_rerank(db, nq, qpack, acnt, box, cand, nc, k, idx, score, counts,
-                          at<char>(ws, osc), s);
+    if (e == hipSuccess) e = rerank_launches(db, nq, qpack, acnt, box, cand, nc, k, idx, score,
+                                             counts, at<char>(ws, osc), s);
     return e;
 }
 
@@ -953,9 +965,8 @@ int db_query_com(const db_t *db, int nq, const uint8_t *q_labels, int n_cand, in
     if (e == hipSuccess)
         e = launch_topk_min(nq, (int)n, n_cand, D, ci, cd, sel_bytes ? at<char>(ws, osel) : nullptr,
                             sel_bytes, s);
-    if (e == hipSuccess)
-        e = launch_rerank(db, nq, qpack, acnt, box, ci, n_cand, k, idx, score, counts,
-                          at<char>(rr, osc), s);
+    if (e == hipSuccess) e = rerank_launches(db, nq, qpack, acnt, box, ci, n_cand, k, idx, score,
+                                             counts, at<char>(rr, osc), s);
     if (e != hipSuccess) return hip_fail(e, "db_query_com: launch");
     return DB_OK;
 }

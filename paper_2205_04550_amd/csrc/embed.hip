@@ -846,9 +846,9 @@ hipError_t launch_topk_min(int M, int N, int k, const float *D, int32_t *idx, fl
 
 size_t rerank_ws_bytes(int nq) { return (size_t)nq * kRerankMaxCand * 20; }  // 8 + 4 + 2 * 4 bytes per candidate
 
-hipError_t launch_rerank(const db_t *db, int nq, const uint32_t *qpack, const uint32_t *acnt,
-                         const int32_t *box, const int32_t *cand, int nc, int k, int32_t *idx,
-                         double *score, db_counts_t *counts, void *ws, hipStream_t s)
+hipError_t launch_rerank_score(const db_t *db, int nq, const uint32_t *qpack, const uint32_t *acnt,
+                               const int32_t *box, const int32_t *cand, int nc, void *ws,
+                               hipStream_t s)
 {
     const Geometry &g = db->g;
     uint64_t *ws_s = static_cast<uint64_t *>(ws);
@@ -858,8 +858,16 @@ hipError_t launch_rerank(const db_t *db, int nq, const uint32_t *qpack, const ui
                        dim3((unsigned)((nc + kRerankPerBlock - 1) / kRerankPerBlock), (unsigned)nq),
                        dim3(256), 0, s, db->planes, db->popcnt, db->box, g.Wp, g.nxw, g.ny, qpack,
                        acnt, box, cand, nc, ws_s, ws_i, ws_I);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_rerank_rank(const db_t *db, int nq, const uint32_t *acnt, int nc, int k,
+                              int32_t *idx, double *score, db_counts_t *counts, const void *ws,
+                              hipStream_t s)
+{
+    const uint64_t *ws_s = static_cast<const uint64_t *>(ws);
+    const int32_t *ws_i = reinterpret_cast<const int32_t *>(ws_s + (size_t)nq * nc);
+    const uint32_t *ws_I = reinterpret_cast<const uint32_t *>(ws_i + (size_t)nq * nc);
     hipLaunchKernelGGL(rerank_rank_kernel, dim3(nq), dim3(256), 0, s, db->popcnt, acnt, nc, k, ws_s,
                        ws_i, ws_I, idx, score, counts);
     return hipGetLastError();

@@ -128,9 +128,12 @@ hipError_t launch_topk_min(int M, int N, int k, const float *D, int32_t *idx, fl
 // Exact rerank of nc <= DB_KMAX candidates per query; ws of rerank_ws_bytes(nq) holds the
 // scored candidates between the scoring and the ranking kernel.
 size_t rerank_ws_bytes(int nq);
-hipError_t launch_rerank(const db_t *db, int nq, const uint32_t *qpack, const uint32_t *acnt,
-                         const int32_t *box, const int32_t *cand, int nc, int k, int32_t *idx,
-                         double *score, db_counts_t *counts, void *ws, hipStream_t s);
+hipError_t launch_rerank_score(const db_t *db, int nq, const uint32_t *qpack, const uint32_t *acnt,
+                               const int32_t *box, const int32_t *cand, int nc, void *ws,
+                               hipStream_t s);
+hipError_t launch_rerank_rank(const db_t *db, int nq, const uint32_t *acnt, int nc, int k,
+                              int32_t *idx, double *score, db_counts_t *counts, const void *ws,
+                              hipStream_t s);
 
 // Row boxes, moments, box-restricted scan, centre-of-mass distances (sparse.hip).
 hipError_t launch_meta(const uint32_t *recs, int64_t n, const Geometry &g, int32_t *box,

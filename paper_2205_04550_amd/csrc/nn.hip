@@ -42,13 +42,13 @@ constexpr int kCC = 8;   // channels of the other side staged in LDS per step
 // Weights of kCB output channels x kCC input channels, laid out [cc][tap][c] so that
 // one tap's kCB weights are contiguous (vector reads, same address across the wave).
 // `other` = the summed-over channel index base, `own` = this block's channel base.
-template <class T, class WT>
+template <class T, class WT, int CB = kCB>
 __device__ __forceinline__ void stage_weights(T *wsh, const WT *__restrict__ Wt, int Ci, int Co,
                                               int own0, int nown, int other0, int nother,
                                               bool own_is_co)
 {
-    for (int t = threadIdx.x; t < kCC * 27 * kCB; t += blockDim.x) {
-        const int c = t % kCB, tap = (t / kCB) % 27, cc = t / (kCB * 27);
+    for (int t = threadIdx.x; t < kCC * 27 * CB; t += blockDim.x) {
+        const int c = t % CB, tap = (t / CB) % 27, cc = t / (CB * 27);
         T v = T(0);
         if (c < nown && cc < nother) {
             const int own = own0 + c, oth = other0 + cc;
@@ -60,67 +60,87 @@ __device__ __forceinline__ void stage_weights(T *wsh, const WT *__restrict__ Wt,
     }
 }
 
-// grid (ceil(B*OD*OH*OW / 256), ceil(Co / kCB)): one thread per (sample, output
-// voxel), so small late layers still fill whole waves.
-template <class T, class WT>
+// grid (ceil(B*OD*OH*OW / (256 VX)), ceil(Co / CB)): one thread per (sample, VX
+// adjacent output voxels along x) and CB output channels, so small late layers
+// still fill whole waves. Each weight read from LDS feeds VX * CB multiply-adds
+// and neighbouring outputs share their common input taps.
+template <class T, class WT, int CB, int VX>
 __global__ void __launch_bounds__(256) conv_fwd_kernel(int B, int Ci, int Co, int D, int H, int W,
                                                        const T *__restrict__ X,
                                                        const WT *__restrict__ Wt,
                                                        const T *__restrict__ bias, int relu,
                                                        T *__restrict__ Y)
 {
-    __shared__ T wsh[kCC * 27 * kCB];
+    __shared__ T wsh[kCC * 27 * CB];
     const int OD = D / 2, OH = H / 2, OW = W / 2;
     const int osp = OD * OH * OW;
+    const int gpr = OW / VX;                          // thread groups per output row
+    const int gsp = OD * OH * gpr;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = t < (int64_t)B * osp;
+    const bool active = t < (int64_t)B * gsp;
     const int64_t tt = active ? t : 0;
-    const int b = (int)(tt / osp);
-    const int o = (int)(tt - (int64_t)b * osp);
-    const int oo = o;
-    const int co0 = blockIdx.y * kCB;
-    const int nco = min(kCB, Co - co0);
-    const int ow = oo % OW, oh = (oo / OW) % OH, od = oo / (OW * OH);
+    const int b = (int)(tt / gsp);
+    const int gi = (int)(tt - (int64_t)b * gsp);
+    const int ow0 = (gi % gpr) * VX, oh = (gi / gpr) % OH, od = gi / (gpr * OH);
+    const int co0 = blockIdx.y * CB;
+    const int nco = min(CB, Co - co0);
     const int64_t isp = (int64_t)D * H * W;
-    T acc[kCB];
+    T acc[VX][CB];
 #pragma unroll
-    for (int c = 0; c < kCB; ++c) acc[c] = bias ? bias[min(co0 + c, Co - 1)] : T(0);
+    for (int c = 0; c < CB; ++c) {
+        const T b0 = bias ? bias[min(co0 + c, Co - 1)] : T(0);
+#pragma unroll
+        for (int v = 0; v < VX; ++v) acc[v][c] = b0;
+    }
     for (int ci0 = 0; ci0 < Ci; ci0 += kCC) {
         const int ncc = min(kCC, Ci - ci0);
         __syncthreads();
-        stage_weights(wsh, Wt, Ci, Co, co0, nco, ci0, ncc, true);
+        stage_weights<T, WT, CB>(wsh, Wt, Ci, Co, co0, nco, ci0, ncc, true);
         __syncthreads();
         for (int cc = 0; cc < ncc; ++cc) {
             const T *x = X + ((int64_t)b * Ci + ci0 + cc) * isp;
-            const T *w = wsh + cc * 27 * kCB;
-            // Not unrolled over kd: keeps the live weights to one 3x3 plane (9 x kCB).
+            const T *w = wsh + cc * 27 * CB;
+            // Not unrolled over kd: keeps the live weights to one 3x3 plane.
 #pragma unroll 1
             for (int kd = 0; kd < 3; ++kd) {
                 const int id = 2 * od + kd - 1;
 #pragma unroll
                 for (int kh = 0; kh < 3; ++kh) {
                     const int ih = 2 * oh + kh - 1;
+                    const bool row_in = id >= 0 && id < D && ih >= 0 && ih < H;
+                    const int64_t row = row_in ? ((int64_t)id * H + ih) * W : 0;
+                    T xr[2 * VX + 1];
+#pragma unroll
+                    for (int j = 0; j < 2 * VX + 1; ++j) {
+                        const int iw = 2 * ow0 - 1 + j;
+                        const bool in = row_in && iw >= 0 && iw < W;
+                        xr[j] = in ? x[row + iw] : T(0);
+                    }
 #pragma unroll
                     for (int kw = 0; kw < 3; ++kw) {
-                        const int iw = 2 * ow + kw - 1;
-                        const bool in = id >= 0 && id < D && ih >= 0 && ih < H && iw >= 0 && iw < W;
-                        const int64_t off = in ? ((int64_t)id * H + ih) * W + iw : 0;
-                        const T xv = in ? x[off] : T(0);
-                        const T *wt = w + (kd * 9 + kh * 3 + kw) * kCB;
+                        const T *wt = w + (kd * 9 + kh * 3 + kw) * CB;
 #pragma unroll
-                        for (int c = 0; c < kCB; ++c) acc[c] += wt[c] * xv;
+                        for (int c = 0; c < CB; ++c) {
+                            const T wv = wt[c];
+#pragma unroll
+                            for (int v = 0; v < VX; ++v) acc[v][c] += wv * xr[2 * v + kw];
+                        }
                     }
                 }
             }
         }
     }
     if (!active) return;
+    const int o0 = (od * OH + oh) * OW + ow0;
 #pragma unroll
-    for (int c = 0; c < kCB; ++c) {
+    for (int c = 0; c < CB; ++c) {
         if (c >= nco) break;
-        T v = acc[c];
-        if (relu && v < T(0)) v = T(0);
-        Y[((int64_t)b * Co + co0 + c) * osp + o] = v;
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            T r = acc[v][c];
+            if (relu && r < T(0)) r = T(0);
+            Y[((int64_t)b * Co + co0 + c) * osp + o0 + v] = r;
+        }
     }
 }
 
@@ -784,19 +804,34 @@ int nn_conv3d_s2_fwd(int dtype, int B, int Ci, int Co, int D, int H, int W, cons
         return tdb_set_error(DB_EINVAL, "nn_conv3d_s2_fwd: bad arguments");
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t osp = (int64_t)(D / 2) * (H / 2) * (W / 2);
-    const dim3 grid((unsigned)((B * osp + 255) / 256), (Co + kCB - 1) / kCB);
-    if (pair == 0)
-        hipLaunchKernelGGL((conv_fwd_kernel<float, uint16_t>), grid, dim3(256), 0, s, B, Ci, Co, D, H,
-                           W, (const float *)X, (const uint16_t *)Wt, (const float *)bias, relu,
-                           (float *)Y);
-    else if (pair == 1)
-        hipLaunchKernelGGL((conv_fwd_kernel<float, float>), grid, dim3(256), 0, s, B, Ci, Co, D, H, W,
-                           (const float *)X, (const float *)Wt, (const float *)bias, relu,
-                           (float *)Y);
-    else
-        hipLaunchKernelGGL((conv_fwd_kernel<double, double>), grid, dim3(256), 0, s, B, Ci, Co, D, H,
-                           W, (const double *)X, (const double *)Wt, (const double *)bias, relu,
-                           (double *)Y);
+    // 16 output channels per thread for the small late layers (Co >= 16, at most 16^3
+    // input voxels): every input tap loaded then feeds twice the multiply-adds. The
+    // large early layers keep 8, which leaves room for more waves per SIMD.
+    const bool wide = Co >= 16 && (int64_t)D * H * W <= 4096;
+    const int cb = wide ? 16 : kCB;
+    // Two adjacent outputs per thread on the first layer (few input channels, the
+    // largest grid, even output rows): the shared input taps are loaded once.
+    const int vx = (!wide && Ci <= 2 && (W / 2) % 2 == 0) ? 2 : 1;
+    const dim3 grid((unsigned)((B * osp / vx + 255) / 256), (Co + cb - 1) / cb);
+#define TDB_CONV_FWD(T_, WT_, CB_)                                                                 \
+    do {                                                                                           \
+        if (vx == 2)                                                                               \
+            hipLaunchKernelGGL((conv_fwd_kernel<T_, WT_, CB_, 2>), grid, dim3(256), 0, s, B, Ci, Co, \
+                               D, H, W, (const T_ *)X, (const WT_ *)Wt, (const T_ *)bias, relu,    \
+                               (T_ *)Y);                                                           \
+        else                                                                                       \
+            hipLaunchKernelGGL((conv_fwd_kernel<T_, WT_, CB_, 1>), grid, dim3(256), 0, s, B, Ci, Co, \
+                               D, H, W, (const T_ *)X, (const WT_ *)Wt, (const T_ *)bias, relu,    \
+                               (T_ *)Y);                                                           \
+    } while (0)
+    if (pair == 0) {
+        if (wide) TDB_CONV_FWD(float, uint16_t, 16); else TDB_CONV_FWD(float, uint16_t, kCB);
+    } else if (pair == 1) {
+        if (wide) TDB_CONV_FWD(float, float, 16); else TDB_CONV_FWD(float, float, kCB);
+    } else {
+        if (wide) TDB_CONV_FWD(double, double, 16); else TDB_CONV_FWD(double, double, kCB);
+    }
+#undef TDB_CONV_FWD
     return launched("nn_conv3d_s2_fwd");
 }
 

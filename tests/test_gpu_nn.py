@@ -253,3 +253,21 @@ def test_training_overfits_one_batch():
     say(f"loss {losses[0]:.5f} -> {min(losses):.5f} (last {losses[-1]:.5f})")
     assert all(math.isfinite(l) for l in losses)
     assert np.mean(losses[-10:]) < 0.5 * losses[0]
+
+
+@pytest.mark.parametrize("shape", [(2, 2, 8, 64), (2, 8, 16, 32), (1, 3, 12, 32), (2, 16, 32, 16)])
+def test_conv_forward_large_layers(shape):
+    """The encoder's large layers (LDS-tiled kernel) against the float64 oracle."""
+    need_gpu()
+    from paper_2205_04550_amd import nn
+    B, Ci, Co, G = shape
+    g = torch.Generator().manual_seed(Ci * 100 + Co)
+    x64 = torch.rand(B, Ci, G, G, G, generator=g, dtype=torch.float64)
+    w64 = torch.randn(Co, Ci, 3, 3, 3, generator=g, dtype=torch.float64) * 0.2
+    b64 = torch.randn(Co, generator=g, dtype=torch.float64)
+    wc = w64.to(torch.bfloat16)
+    for relu in (False, True):
+        y = nn.Conv3dS2.apply(x64.to("cuda", torch.float32), w64.cuda().float(), b64.cuda().float(),
+                              wc.cuda(), relu)
+        yr = E.conv(x64, wc.to(torch.float64), b64, relu)
+        assert _rel(_cpu64(y), yr) < 2e-5, (shape, relu)
