@@ -310,9 +310,8 @@ constexpr int kSelMaxK = 1024;
 // grid M, kSelThreads threads. Four 8-bit digit passes find the key T of the
 // k-th smallest element; entries with key < T are taken, then the lowest
 // indices among key == T; the k winners are sorted by (key, index).
-__global__ void __launch_bounds__(kSelThreads) topk_min_kernel(const float *__restrict__ D, int N,
-                                                               int k, int32_t *__restrict__ out_idx,
-                                                               float *__restrict__ out_d)
+__device__ __forceinline__ void select_row_radix(const float *__restrict__ row, int N, int k,
+                                                 int32_t *__restrict__ oidx, float *__restrict__ od)
 {
     __shared__ uint32_t hist[256];
     __shared__ uint32_t s_sel[2];
@@ -320,7 +319,6 @@ __global__ void __launch_bounds__(kSelThreads) topk_min_kernel(const float *__re
     __shared__ uint32_t sk[kSelMaxK];
     __shared__ int32_t si[kSelMaxK];
     __shared__ uint32_t s_lt;
-    const float *row = D + (int64_t)blockIdx.x * N;
     const int lane = threadIdx.x & 63;
     uint32_t prefix = 0, mask = 0, remaining = (uint32_t)k;
     for (int pass = 0; pass < 4; ++pass) {
@@ -410,9 +408,17 @@ __global__ void __launch_bounds__(kSelThreads) topk_min_kernel(const float *__re
         }
     __syncthreads();
     for (int t = threadIdx.x; t < k; t += blockDim.x) {
-        out_idx[(int64_t)blockIdx.x * k + t] = si[t];
-        out_d[(int64_t)blockIdx.x * k + t] = fkey_inv(sk[t]);
+        oidx[t] = si[t];
+        od[t] = fkey_inv(sk[t]);
     }
+}
+
+__global__ void __launch_bounds__(kSelThreads) topk_min_kernel(const float *__restrict__ D, int N,
+                                                               int k, int32_t *__restrict__ out_idx,
+                                                               float *__restrict__ out_d)
+{
+    const int64_t r = blockIdx.x;
+    select_row_radix(D + r * N, N, k, out_idx + r * k, out_d + r * k);
 }
 
 // ---- exact rerank ---------------------------------------------------------------------------
@@ -785,6 +791,170 @@ __global__ void __launch_bounds__(kSelThreads) topk_merge_kernel(int nc, int k,
     }
 }
 
+// ---- k smallest by a bound and a filter (long rows, small k) -------------------------------
+//
+// For a row of N entries cut into C full chunks of kTauChunk, let tau_c be the
+// m-th smallest of the chunk's per-thread minima (m = ceil(k / C)). At least m
+// entries of chunk c are <= tau_c, so at least C * m >= k entries of the row
+// are <= tau = max_c tau_c: the row's k smallest are all <= tau. One streaming
+// pass finds tau (an atomic max per chunk) and keeps every thread's minimum; a
+// block per row then reads only the entries of threads whose minimum is <= tau
+// (a few hundred entries per row at the workloads here), and sorts them by
+// (key, index). A row with more than kTauCap such entries is selected by the
+// one-block radix path instead.
+
+constexpr int kTauThreads = 512;
+constexpr int kTauPer = 16;
+constexpr int kTauChunk = kTauThreads * kTauPer;   // 8,192 entries
+constexpr int kTauMaxM = 4;
+constexpr int kTauCap = 4096;
+
+// Rank of lane value x among the first n lanes' values of the wave (ties by lane):
+// a permutation of 0..n-1 over those lanes.
+__device__ __forceinline__ int wave_rank(uint32_t x, int lane, int n)
+{
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+        const uint32_t y = (uint32_t)__shfl((int)x, j, 64);
+        rank += (y < x) || (y == x && j < lane);
+    }
+    return rank;
+}
+
+// grid (C, M), kTauThreads threads: tau[row] = max(tau[row], m-th smallest thread minimum);
+// each thread's minimum is kept in tmin [M][C][kTauThreads] for the filter pass.
+__global__ void __launch_bounds__(kTauThreads) topk_tau_kernel(const float *__restrict__ D, int N,
+                                                               int m, uint32_t *__restrict__ tau,
+                                                               uint32_t *__restrict__ tmin)
+{
+    __shared__ uint32_t wl[kTauThreads / 64][kTauMaxM];
+    const int64_t r = blockIdx.y;
+    const int base = blockIdx.x * kTauChunk;
+    if (N - base < kTauChunk) return;                 // partial chunk: no bound from it
+    const float *row = D + r * N + base;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    uint32_t mn = 0xffffffffu;
+    if ((N & 3) == 0) {      // 16-byte aligned rows: 4 entries per load
+        const f32x4 *row4 = reinterpret_cast<const f32x4 *>(row);
+#pragma unroll
+        for (int u = 0; u < kTauPer / 4; ++u) {
+            const f32x4 x = __builtin_nontemporal_load(row4 + u * kTauThreads + tid);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) mn = min(mn, fkey(x[e]));
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < kTauPer; ++u) mn = min(mn, fkey(row[u * kTauThreads + tid]));
+    }
+    tmin[((int64_t)r * gridDim.x + blockIdx.x) * kTauThreads + tid] = mn;
+    // The kTauMaxM smallest thread minima of each wave, then the m-th smallest of those
+    // across the block: lane ranks by shuffles, no serial merges.
+    const int rk = wave_rank(mn, lane, 64);
+    if (rk < kTauMaxM) wl[wave][rk] = mn;
+    __syncthreads();
+    if (wave == 0) {
+        constexpr int n = (kTauThreads / 64) * kTauMaxM;
+        const uint32_t x = lane < n ? wl[lane / kTauMaxM][lane % kTauMaxM] : 0xffffffffu;
+        const int r2 = wave_rank(x, lane, n);
+        if (lane < n && r2 == m - 1) atomicMax(&tau[r], x);
+    }
+}
+
+// grid M, kSelThreads threads: gather the row's entries with key <= tau[row] into
+// LDS (in a full chunk only the threads whose minimum is <= tau hold any: their
+// 16 entries are read; the partial last chunk is read whole), sort them by
+// (key, index) and write the first k. A list longer than kTauCap falls back to
+// the one-block radix selection of the whole row.
+__global__ void __launch_bounds__(kSelThreads) topk_list_kernel(const float *__restrict__ D, int N,
+                                                                int k, const uint32_t *__restrict__ tau,
+                                                                const uint32_t *__restrict__ tmin,
+                                                                int32_t *__restrict__ out_idx,
+                                                                float *__restrict__ out_d)
+{
+    __shared__ uint32_t sk[kTauCap];
+    __shared__ int32_t si[kTauCap];
+    __shared__ uint32_t s_n;
+    const int64_t r = blockIdx.x;
+    const float *row = D + r * N;
+    const uint32_t t = tau[r];
+    const int cfull = N / kTauChunk;
+    const int slots = cfull * kTauThreads;
+    const bool v4 = (N & 3) == 0;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    auto push = [&](uint32_t key, int i) {
+        const uint32_t pos = atomicAdd(&s_n, 1u);
+        if (pos < (uint32_t)kTauCap) {
+            sk[pos] = key;
+            si[pos] = i;
+        }
+    };
+    for (int sl = threadIdx.x; sl < slots; sl += blockDim.x) {
+        if (tmin[r * slots + sl] > t) continue;
+        const int c = sl / kTauThreads, th = sl - c * kTauThreads;
+        const int base = c * kTauChunk;
+        if (v4) {
+            const f32x4 *row4 = reinterpret_cast<const f32x4 *>(row + base);
+#pragma unroll
+            for (int u = 0; u < kTauPer / 4; ++u) {
+                const int j = u * kTauThreads + th;
+                const f32x4 x = row4[j];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t key = fkey(x[e]);
+                    if (key <= t) push(key, base + 4 * j + e);
+                }
+            }
+        } else {
+#pragma unroll 4
+            for (int u = 0; u < kTauPer; ++u) {
+                const int i = base + u * kTauThreads + th;
+                const uint32_t key = fkey(row[i]);
+                if (key <= t) push(key, i);
+            }
+        }
+    }
+    for (int i = cfull * kTauChunk + threadIdx.x; i < N; i += blockDim.x) {
+        const uint32_t key = fkey(row[i]);
+        if (key <= t) push(key, i);
+    }
+    __syncthreads();
+    const uint32_t nc = s_n;
+    if (nc > (uint32_t)kTauCap) {
+        select_row_radix(row, N, k, out_idx + r * k, out_d + r * k);
+        return;
+    }
+    int P = 1;
+    while (P < (int)nc) P <<= 1;
+    for (int q = (int)nc + threadIdx.x; q < P; q += blockDim.x) {
+        sk[q] = 0xffffffffu;
+        si[q] = INT_MAX;
+    }
+    for (int size = 2; size <= P; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int q = threadIdx.x; q < P / 2; q += blockDim.x) {
+                const int i = 2 * q - (q & (stride - 1));
+                const int j = i + stride;
+                const bool up = (i & size) == 0;
+                const uint32_t ki = sk[i], kj = sk[j];
+                const int32_t ii = si[i], ij = si[j];
+                const bool j_first = kj < ki || (kj == ki && ij < ii);
+                if (j_first == up) {
+                    sk[i] = kj;
+                    sk[j] = ki;
+                    si[i] = ij;
+                    si[j] = ii;
+                }
+            }
+        }
+    __syncthreads();
+    for (int q = threadIdx.x; q < k; q += blockDim.x) {
+        out_idx[r * k + q] = si[q];
+        out_d[r * k + q] = fkey_inv(sk[q]);
+    }
+}
+
 // ---- launchers ---------------------------------------------------------------------------------
 
 hipError_t launch_quant_bf16(int64_t n, int dim, const float *x, uint16_t *y, float *sq,
@@ -818,8 +988,19 @@ hipError_t launch_dist_fp8(int M, int N, int K, const uint8_t *Q, const float *q
     return hipGetLastError();
 }
 
+// m of the bound-and-filter path, or 0 when it does not apply (too few full chunks).
+static int tau_m(int N, int k)
+{
+    const int full = N / kTauChunk;
+    if (full < 1) return 0;
+    const int m = (k + full - 1) / full;
+    return m <= kTauMaxM ? m : 0;
+}
+
 size_t topk_min_ws_bytes(int M, int N, int k)
 {
+    if (tau_m(N, k))
+        return align_up((size_t)M * 4, kAlign) + (size_t)M * (N / kTauChunk) * kTauThreads * 4;
     const int64_t nch = ((int64_t)N + kChunk - 1) / kChunk;
     if (nch * k > kMergeMax) return 0;       // the two-stage path does not apply
     return (size_t)M * nch * k * 8;
@@ -832,6 +1013,24 @@ hipError_t launch_topk_min(int M, int N, int k, const float *D, int32_t *idx, fl
     if (!ws || need == 0 || ws_bytes < need) {
         hipLaunchKernelGGL(topk_min_kernel, dim3(M), dim3(kSelThreads), 0, s, D, N, k, idx, d);
         return hipGetLastError();
+    }
+    if (const int m = tau_m(N, k)) {
+        uint32_t *tau = static_cast<uint32_t *>(ws);
+        uint32_t *tmin = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) +
+                                                      align_up((size_t)M * 4, kAlign));
+        const int cfull = N / kTauChunk;
+        hipError_t e = launch_fill_u32(reinterpret_cast<int32_t *>(tau), M, 0, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(topk_tau_kernel, dim3(cfull, M), dim3(kTauThreads), 0, s, D, N, m, tau,
+                               tmin);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(topk_list_kernel, dim3(M), dim3(kSelThreads), 0, s, D, N, k, tau, tmin,
+                               idx, d);
+            e = hipGetLastError();
+        }
+        return e;
     }
     const int nch = (N + kChunk - 1) / kChunk;
     uint32_t *ck = static_cast<uint32_t *>(ws);

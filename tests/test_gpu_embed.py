@@ -94,6 +94,27 @@ def test_topk_min_exact_with_ties():
         assert np.array_equal(val.cpu().numpy(), np.take_along_axis(D2, want, 1)), (N, k)
 
 
+def test_topk_min_long_rows_bound_and_filter():
+    """Rows of 300,000 (the bound-and-filter path for k <= 4 x full chunks): random
+    distances, heavy ties, an all-equal row (its list overflows: one-block fallback),
+    negatives, and the smallest entries packed in the last, partial chunk."""
+    need_gpu()
+    from paper_2205_04550_amd import binding as b
+    rng = np.random.default_rng(12)
+    M, N = 5, 300_000
+    D = rng.standard_normal((M, N)).astype(np.float32) * 50 + 900
+    D[1] = rng.integers(0, 40, N).astype(np.float32)          # ties
+    D[2] = 3.0                                                 # all equal
+    D[3, ::997] = -2.0                                         # negatives spread out
+    D[4, -200:] = 1.0                                          # minima in the partial chunk
+    Dd = torch.from_numpy(D).cuda()
+    for k in (1, 7, 100):
+        want = E.topk_by_distance(D, k)
+        idx, val = b.emb_topk_min(Dd, k, chunked=True)
+        assert np.array_equal(idx.cpu().numpy(), want), k
+        assert np.array_equal(val.cpu().numpy(), np.take_along_axis(D, want, 1)), k
+
+
 def test_rerank_bit_exact_and_full_candidate_set_equals_scan():
     need_gpu()
     gen = synth.SMALL
