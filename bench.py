@@ -618,7 +618,7 @@ def bench_embed(args, db, gen, n, build_s) -> int:
         "distance_gemm": {"bound": "mfma", "achieved_tflops": gemm_flop / (stage[1] * 1e-3) / 1e12,
                           "peak_tflops": BF16_MFMA_PEAK / 1e12,
                           "frac": gemm_flop / (stage[1] * 1e-3) / BF16_MFMA_PEAK,
-                          "kernel": "dist_bf16_kernel", "ms": stage[1]},
+                          "kernel": "dist_lds_kernel<false>", "ms": stage[1]},
         "variants": variants,
         "cpu_baseline": cpu, "build_s": build_s, "train_s": train_s,
         "encode_db_s": encode_db_s, "train_loss_first_last": [losses[0], losses[-1]],
@@ -721,7 +721,7 @@ def bench_embed500k(args, db, gen, n, build_s, n_big: int = 500_000) -> int:
         "roofline": {"bound": "mfma", "achieved": flop / (g8 * 1e-3) / 1e12,
                      "peak": FP8_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
                      "frac": flop / (g8 * 1e-3) / FP8_MFMA_PEAK, "traffic": None,
-                     "kernel": "dist_fp8_kernel", "kernel_avg_ms": g8,
+                     "kernel": "dist_lds_kernel<true>", "kernel_avg_ms": g8,
                      "note": "writes 2.05 GB of distances per launch"},
         "cpu_baseline": None, "build_s": build_s,
     }

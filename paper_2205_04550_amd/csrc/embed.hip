@@ -122,17 +122,6 @@ __global__ void __launch_bounds__(256) quant_fp8_kernel(int dim, const float *__
     }
 }
 
-// ---- distance GEMM -----------------------------------------------------------------------------
-//
-// Block tile 128 queries x 128 database rows, 4 waves as 2 x 2 of 64 x 64,
-// each wave 2 x 2 MFMA 32x32 tiles. Operands are K-contiguous rows, so lane l
-// reads 16 (bf16) or 32 (fp8) bytes of row l % 32 at k-chunk l / 32 straight
-// from global memory / L2 (the tiles are tiny next to the distance matrix
-// written out). Result register r of lane l is row 8 (r / 4) + 4 (l / 32) +
-// r % 4, column l % 32 of the 32 x 32 tile.
-
-constexpr int kGT = 128;
-
 // Epilogue of the distance kernels. mode 0: D = d (squared L2); mode 1:
 // D = sqrt(max(d, 0)) (L2); mode 2: D += sqrt(max(d, 0)) (a second L2 added to
 // the first: the paper's L2_T1Gd + L2_FLAIR of two encoders, Sec. 2.3).
@@ -146,92 +135,62 @@ __device__ __forceinline__ void dist_store(float *p, float d, int mode)
     }
 }
 
-__global__ void __launch_bounds__(256) dist_bf16_kernel(int M, int N, int K,
-                                                        const uint16_t *__restrict__ Q,
-                                                        const float *__restrict__ qn,
-                                                        const uint16_t *__restrict__ X,
-                                                        const float *__restrict__ xn,
-                                                        float *__restrict__ D, int mode)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int m0 = blockIdx.y * kGT + (wave >> 1) * 64;
-    const int n0 = blockIdx.x * kGT + (wave & 1) * 64;
-    const int half = lane >> 5, r32 = lane & 31;
-    const bf16x8 *pa[2], *pb[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int ra = min(m0 + i * 32 + r32, M - 1);
-        const int rb = min(n0 + i * 32 + r32, N - 1);
-        pa[i] = reinterpret_cast<const bf16x8 *>(Q + (int64_t)ra * K) + half;
-        pb[i] = reinterpret_cast<const bf16x8 *>(X + (int64_t)rb * K) + half;
-    }
-    f32x16 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-    const int steps = K / 16;
-    for (int s = 0; s < steps; s += 4) {
-        bf16x8 a[4][2], b[4][2];
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int c = 2 * (s + u < steps ? s + u : steps - 1);
-                a[u][i] = pa[i][c];
-                b[u][i] = pb[i][c];
-            }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (s + u >= steps) break;
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[u][i], b[u][j], acc[i][j],
-                                                                        0, 0, 0);
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int col = n0 + j * 32 + r32;
-            if (col >= N) continue;
-            const float xc = xn[col];
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = m0 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                if (row < M)
-                    dist_store(D + (int64_t)row * N + col, (qn[row] + xc) - 2.0f * acc[i][j][r],
-                               mode);
-            }
-        }
-}
+// ---- distance GEMM, LDS-staged --------------------------------------------------------------
+//
+// Block tile 128 queries x 256 database rows, 8 waves as 2 x 4 of 64 x 64 (2 x 2
+// MFMA 32x32 tiles each). K is staged through LDS in slices of 64 bytes (32
+// bf16 or 64 fp8 values) for both operands, double-buffered with a register
+// prefetch of the next slice, so each operand row is read from L2 once per
+// block instead of once per wave. LDS rows are padded to 80 bytes to spread
+// the 16-byte fragment reads over the banks. Blocks are numbered so that the
+// query tiles of one database tile run one after another on the same XCD
+// (consecutive block numbers go to different XCDs): the database rows then
+// come from HBM once into that XCD's L2 and are reused by every query tile.
+constexpr int kDM = 128, kDN = 256, kDSlice = 64, kDRow = 80, kDThreads = 512;
+constexpr int kXcds = 8;
 
-__global__ void __launch_bounds__(256) dist_fp8_kernel(int M, int N, int K,
-                                                       const uint8_t *__restrict__ Q,
-                                                       const float *__restrict__ qs,
-                                                       const float *__restrict__ qn,
-                                                       const uint8_t *__restrict__ X,
-                                                       const float *__restrict__ xs,
-                                                       const float *__restrict__ xn,
-                                                       float *__restrict__ D, int mode)
+template <bool FP8>
+__global__ void __launch_bounds__(kDThreads) dist_lds_kernel(int M, int N, int K, int mt, int nt,
+                                                             const uint8_t *__restrict__ Q,
+                                                             const float *__restrict__ qs,
+                                                             const float *__restrict__ qn,
+                                                             const uint8_t *__restrict__ X,
+                                                             const float *__restrict__ xs,
+                                                             const float *__restrict__ xn,
+                                                             float *__restrict__ D, int mode)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int m0 = blockIdx.y * kGT + (wave >> 1) * 64;
-    const int n0 = blockIdx.x * kGT + (wave & 1) * 64;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2][(kDM + kDN) * kDRow];
+    const int p = blockIdx.x, xcd = p % kXcds, q = p / kXcds;
+    const int mtile = q % mt, ntile = (q / mt) * kXcds + xcd;
+    if (ntile >= nt) return;                       // whole block, before any barrier
+    const int m0 = mtile * kDM, n0 = ntile * kDN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 2, wn = wave & 3;
     const int half = lane >> 5, r32 = lane & 31;
-    const i32x8 *pa[2], *pb[2];
+    const int Kb = FP8 ? K : 2 * K;                 // bytes per row
+    const int nslices = (Kb + kDSlice - 1) / kDSlice;
+    // Staging: 384 rows x 4 chunks of 16 bytes = 1536 chunks, 3 per thread.
+    u32x4 pre[3];
+    auto fetch = [&](int sl) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int ra = min(m0 + i * 32 + r32, M - 1);
-        const int rb = min(n0 + i * 32 + r32, N - 1);
-        pa[i] = reinterpret_cast<const i32x8 *>(Q + (int64_t)ra * K) + half;
-        pb[i] = reinterpret_cast<const i32x8 *>(X + (int64_t)rb * K) + half;
-    }
+        for (int j = 0; j < 3; ++j) {
+            const int c = j * kDThreads + tid;
+            const int row = c >> 2, part = c & 3;
+            const int kb = sl * kDSlice + part * 16;
+            const uint8_t *src;
+            if (row < kDM) src = Q + (int64_t)min(m0 + row, M - 1) * Kb;
+            else src = X + (int64_t)min(n0 + row - kDM, N - 1) * Kb;
+            pre[j] = kb < Kb ? *reinterpret_cast<const u32x4 *>(src + kb) : (u32x4){0u, 0u, 0u, 0u};
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const int c = j * kDThreads + tid;
+            const int row = c >> 2, part = c & 3;
+            *reinterpret_cast<u32x4 *>(&lds[buf][row * kDRow + part * 16]) = pre[j];
+        }
+    };
     f32x16 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -239,49 +198,79 @@ __global__ void __launch_bounds__(256) dist_fp8_kernel(int M, int N, int K,
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-    const int steps = K / 64;
     f32x16 zero16;
 #pragma unroll
     for (int r = 0; r < 16; ++r) zero16[r] = 0.f;
-    for (int s = 0; s < steps; s += 2) {
-        i32x8 a[2][2], b[2][2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
+    fetch(0);
+    stash(0);
+    __syncthreads();
+    for (int sl = 0; sl < nslices; ++sl) {
+        const int buf = sl & 1;
+        if (sl + 1 < nslices) fetch(sl + 1);
+        const uint8_t *A = &lds[buf][0], *B = &lds[buf][kDM * kDRow];
+        if (FP8) {
+            i32x8 a[2], b[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                const int c = 2 * (s + u < steps ? s + u : steps - 1);
-                a[u][i] = pa[i][c];
-                b[u][i] = pb[i][c];
+                const uint8_t *pa = A + (wm * 64 + i * 32 + r32) * kDRow + half * 32;
+                const uint8_t *pb = B + (wn * 64 + i * 32 + r32) * kDRow + half * 32;
+                const u32x4 a0 = *reinterpret_cast<const u32x4 *>(pa);
+                const u32x4 a1 = *reinterpret_cast<const u32x4 *>(pa + 16);
+                const u32x4 b0 = *reinterpret_cast<const u32x4 *>(pb);
+                const u32x4 b1 = *reinterpret_cast<const u32x4 *>(pb + 16);
+                a[i] = (i32x8){(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w,
+                               (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
+                b[i] = (i32x8){(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w,
+                               (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
             }
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            if (s + u >= steps) break;
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
-                    // formats 0/0 = fp8 e4m3 for both operands; E8M0 scales 127 = 2^0.
-                    // Each 64-wide step starts from zero and is added in FP32 on the
-                    // VALU: accumulating inside the instruction loses more precision.
+                    // OCP e4m3 for both operands, unit scales; each 64-wide step starts
+                    // from zero and is added in FP32 on the vector ALUs (more precise
+                    // than accumulating inside the instruction).
                     const f32x16 part = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                        a[u][i], b[u][j], zero16, 0, 0, 0, 127, 0, 127);
+                        a[i], b[j], zero16, 0, 0, 0, 127, 0, 127);
                     acc[i][j] += part;
                 }
+        } else {
+#pragma unroll
+            for (int st = 0; st < 2; ++st) {
+                bf16x8 a[2], b[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    a[i] = *reinterpret_cast<const bf16x8 *>(
+                        A + (wm * 64 + i * 32 + r32) * kDRow + st * 32 + half * 16);
+                    b[i] = *reinterpret_cast<const bf16x8 *>(
+                        B + (wn * 64 + i * 32 + r32) * kDRow + st * 32 + half * 16);
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j],
+                                                                            0, 0, 0);
+            }
         }
+        if (sl + 1 < nslices) stash(buf ^ 1);
+        __syncthreads();
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            const int col = n0 + j * 32 + r32;
+            const int col = n0 + wn * 64 + j * 32 + r32;
             if (col >= N) continue;
-            const float xc = xn[col], sc = xs[col];
+            const float xc = xn[col];
+            const float sc = FP8 ? xs[col] : 1.0f;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int row = m0 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                if (row < M)
-                    dist_store(D + (int64_t)row * N + col,
-                               (qn[row] + xc) - 2.0f * (qs[row] * sc) * acc[i][j][r], mode);
+                const int row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                if (row < M) {
+                    const float dot = FP8 ? (qs[row] * sc) * acc[i][j][r] : acc[i][j][r];
+                    dist_store(D + (int64_t)row * N + col, (qn[row] + xc) - 2.0f * dot, mode);
+                }
             }
         }
 }
@@ -971,11 +960,21 @@ hipError_t launch_quant_fp8(int64_t n, int dim, const float *x, uint8_t *y, floa
     return hipGetLastError();
 }
 
+static unsigned dist_lds_grid(int M, int N, int *mt, int *nt)
+{
+    *mt = (M + kDM - 1) / kDM;
+    *nt = (N + kDN - 1) / kDN;
+    return (unsigned)(kXcds * *mt * ((*nt + kXcds - 1) / kXcds));
+}
+
 hipError_t launch_dist_bf16(int M, int N, int K, const uint16_t *Q, const float *qn,
                             const uint16_t *X, const float *xn, float *D, int mode, hipStream_t s)
 {
-    hipLaunchKernelGGL(dist_bf16_kernel, dim3((N + kGT - 1) / kGT, (M + kGT - 1) / kGT), dim3(256),
-                       0, s, M, N, K, Q, qn, X, xn, D, mode);
+    int mt, nt;
+    const unsigned g = dist_lds_grid(M, N, &mt, &nt);
+    hipLaunchKernelGGL(dist_lds_kernel<false>, dim3(g), dim3(kDThreads), 0, s, M, N, K, mt, nt,
+                       reinterpret_cast<const uint8_t *>(Q), nullptr, qn,
+                       reinterpret_cast<const uint8_t *>(X), nullptr, xn, D, mode);
     return hipGetLastError();
 }
 
@@ -983,8 +982,10 @@ hipError_t launch_dist_fp8(int M, int N, int K, const uint8_t *Q, const float *q
                            const uint8_t *X, const float *xs, const float *xn, float *D,
                            int mode, hipStream_t s)
 {
-    hipLaunchKernelGGL(dist_fp8_kernel, dim3((N + kGT - 1) / kGT, (M + kGT - 1) / kGT), dim3(256),
-                       0, s, M, N, K, Q, qs, qn, X, xs, xn, D, mode);
+    int mt, nt;
+    const unsigned g = dist_lds_grid(M, N, &mt, &nt);
+    hipLaunchKernelGGL(dist_lds_kernel<true>, dim3(g), dim3(kDThreads), 0, s, M, N, K, mt, nt, Q, qs,
+                       qn, X, xs, xn, D, mode);
     return hipGetLastError();
 }
 
