@@ -144,6 +144,140 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(int B, int Ci, int Co, in
     }
 }
 
+// Forward on the FP32 matrix cores for float activations (Ci % 4 == 0, W % 4 ==
+// 0): an implicit GEMM Y[co][voxel] = sum over (tap, ci) of W[co][ci][tap]
+// X[ci][voxel + tap], each product exact in FP32 as with FMA (only the summation
+// order differs). A block takes a TD x TH x TW box of output voxels of one sample
+// and all output channels. Per chunk of CC input channels it stages in LDS the
+// input patch, (2TD+1) x (2TH+1) rows of 2TW+8 floats (the 2TW+1 needed, widened
+// to whole aligned 16-byte groups; zeros outside the volume), and the chunk's
+// weights (bf16 widened to float). Each wave owns MT tiles of 16 voxels along x
+// and NT tiles of 16 output channels; one 16 x 16 x 4 product takes four input
+// channels of one tap, lane l giving channel l / 16 for voxel (or output
+// channel) l % 16.
+constexpr int kCvLds = 12288;   // floats of LDS per block (48 KB: three blocks per CU)
+constexpr int kCvBatch = 8;     // staging loads in flight per thread
+
+template <class WT, int TD, int TH, int TW, int MT, int NT>
+__global__ void __launch_bounds__(256) conv_mfma_kernel(int Ci, int Co, int D, int H, int W, int CC,
+                                                        int tiles_h, int tiles_w,
+                                                        const float *__restrict__ X,
+                                                        const WT *__restrict__ Wt,
+                                                        const float *__restrict__ bias, int relu,
+                                                        float *__restrict__ Y)
+{
+    static_assert(TD * TH * TW == 64 * MT, "a wave owns MT tiles of 16 voxels");
+    constexpr int PWA = 2 * TW + 8, SEGS = PWA / 4, PH = 2 * TH + 1, PD = 2 * TD + 1;
+    constexpr int PROWS = PD * PH, PVA = PROWS * PWA;
+    __shared__ __attribute__((aligned(16))) float lds[kCvLds];
+    float *xs = lds;
+    float *ws = lds + CC * PVA;                // [co][ci in chunk][tap], rows of 27 CC + 1
+    const int wrow = 27 * CC + 1;
+    const int OD = D / 2, OH = H / 2, OW = W / 2;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kq = lane >> 4;
+    const int b = blockIdx.y;
+    const int tix = blockIdx.x;
+    const int tw = tix % tiles_w, th = (tix / tiles_w) % tiles_h, td = tix / (tiles_w * tiles_h);
+    const int od0 = td * TD, oh0 = th * TH, ow0 = tw * TW;
+    // Patch origin: row (z, y) = input (2 od0 - 1 + z, 2 oh0 - 1 + y); column c = input
+    // x 2 ow0 - 4 + c, so tap kw of output x-offset ox sits at column 2 ox + kw + 3.
+    const int iz0 = 2 * od0 - 1, iy0 = 2 * oh0 - 1, ix0 = 2 * ow0 - 4;
+    int vb[MT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        const int v = (wave * MT + m) * 16 + (lane & 15);
+        const int z = v / (TH * TW), y = (v / TW) % TH, x = v % TW;
+        vb[m] = kq * PVA + (2 * z * PH + 2 * y) * PWA + 2 * x + 3;
+    }
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[m][n] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const int64_t isp = (int64_t)D * H * W;
+    const float *Xb = X + (int64_t)b * Ci * isp;
+    const int nx4 = CC * PROWS * SEGS, nw = NT * 16 * 27 * CC;
+    for (int c0 = 0; c0 < Ci; c0 += CC) {
+        const int cc = min(CC, Ci - c0);
+        __syncthreads();
+        for (int t0 = 0; t0 < nx4; t0 += 256 * kCvBatch) {
+            f32x4 v[kCvBatch];
+#pragma unroll
+            for (int j = 0; j < kCvBatch; ++j) {
+                const int t = t0 + j * 256 + tid;
+                const int row = t / SEGS, seg = t - row * SEGS;
+                const int ci = row / PROWS, rr = row - ci * PROWS;
+                const int gz = iz0 + rr / PH, gy = iy0 + rr % PH, gx = ix0 + 4 * seg;
+                v[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+                if (t < nx4 && ci < cc && gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 &&
+                    gx < W)
+                    v[j] = *reinterpret_cast<const f32x4 *>(
+                        Xb + (int64_t)(c0 + ci) * isp + ((int64_t)gz * H + gy) * W + gx);
+            }
+#pragma unroll
+            for (int j = 0; j < kCvBatch; ++j) {
+                const int t = t0 + j * 256 + tid;
+                if (t < nx4) *reinterpret_cast<f32x4 *>(&xs[4 * t]) = v[j];
+            }
+        }
+        for (int t0 = 0; t0 < nw; t0 += 256 * kCvBatch) {
+            float v[kCvBatch];
+#pragma unroll
+            for (int j = 0; j < kCvBatch; ++j) {
+                const int t = t0 + j * 256 + tid;
+                const int co = t / (27 * CC), r = t - co * (27 * CC);
+                v[j] = 0.f;
+                if (t < nw && co < Co && r < 27 * cc) v[j] = ld_w(Wt, ((int64_t)co * Ci + c0) * 27 + r);
+            }
+#pragma unroll
+            for (int j = 0; j < kCvBatch; ++j) {
+                const int t = t0 + j * 256 + tid;
+                const int co = t / (27 * CC), r = t - co * (27 * CC);
+                if (t < nw) ws[co * wrow + r] = v[j];
+            }
+        }
+        __syncthreads();
+        const int nq = cc >> 2;
+        for (int q = 0; q < nq; ++q) {
+            const float *xq = xs + 4 * q * PVA;
+            const float *wq = ws + (4 * q + kq) * 27 + (lane & 15) * wrow;
+#pragma unroll 9
+            for (int tap = 0; tap < 27; ++tap) {
+                const int toff = ((tap / 9) * PH + (tap / 3) % 3) * PWA + tap % 3;
+                float a[NT];
+#pragma unroll
+                for (int n = 0; n < NT; ++n) a[n] = wq[n * 16 * wrow + tap];
+#pragma unroll
+                for (int m = 0; m < MT; ++m) {
+                    const float bv = xq[vb[m] + toff];
+#pragma unroll
+                    for (int n = 0; n < NT; ++n)
+                        acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[n], bv, acc[m][n], 0, 0, 0);
+                }
+            }
+        }
+    }
+    const int64_t osp = (int64_t)OD * OH * OW;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+        const int v = (wave * MT + m) * 16 + (lane & 15);
+        const int oz = od0 + v / (TH * TW), oy = oh0 + (v / TW) % TH, ox = ow0 + v % TW;
+        if (oz >= OD || oy >= OH || ox >= OW) continue;
+        const int64_t o = ((int64_t)oz * OH + oy) * OW + ox;
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = n * 16 + 4 * kq + r;
+                if (co < Co) {
+                    float y = acc[m][n][r] + (bias ? bias[co] : 0.f);
+                    if (relu && y < 0.f) y = 0.f;
+                    Y[((int64_t)b * Co + co) * osp + o] = y;
+                }
+            }
+    }
+}
+
 // Adjoint map: grid (ceil(B*D*H*W / 256), ceil(Ci / kCB)); one thread per (sample,
 // input voxel) and kCB input channels (each dY tap is loaded once for all of them).
 template <class T, class WT>
@@ -412,6 +546,85 @@ __global__ void __launch_bounds__(256) linear_gemm_kernel(int M, int N, int K,
             if (n >= N) continue;
             T v = acc[i][j] + (bias ? bias[n] : T(0));
             if (relu && v < T(0)) v = T(0);
+            C[(int64_t)m * N + n] = v;
+        }
+    }
+}
+
+// Forward C[m][n] = act(bias[n] + sum_k A[m][k] W[n][k]) in float on the FP32
+// matrix cores (products exact in FP32 as with FMA; only the summation order
+// differs). Block tile 64 x 64, four waves of 32 x 32; K in steps of 32 staged
+// in LDS with the next step's loads in flight. In product s of a step, lane l
+// supplies row (or column) l % 32 at k = 16 (l / 32) + s, so a lane reads 16
+// consecutive k of its row as four 16-byte LDS loads. Needs K % 4 == 0.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int kMM = 64, kMK = 32, kMPad = 36;
+
+__device__ __forceinline__ f32x4 ld4_w(const float *p) { return *reinterpret_cast<const f32x4 *>(p); }
+__device__ __forceinline__ f32x4 ld4_w(const uint16_t *p)
+{
+    const uint2 u = *reinterpret_cast<const uint2 *>(p);
+    return (f32x4){__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                   __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u)};
+}
+
+template <class WT>
+__global__ void __launch_bounds__(256) linear_mfma_kernel(int M, int N, int K,
+                                                          const float *__restrict__ A,
+                                                          const WT *__restrict__ Wt,
+                                                          const float *__restrict__ bias, int relu,
+                                                          float *__restrict__ C)
+{
+    __shared__ __attribute__((aligned(16))) float As[kMM * kMPad];
+    __shared__ __attribute__((aligned(16))) float Bs[kMM * kMPad];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1, h = lane >> 5, r32 = lane & 31;
+    const int m0 = blockIdx.y * kMM, n0 = blockIdx.x * kMM;
+    // Staging: 64 rows x 8 float4 per operand, two of each per thread.
+    const int srow = tid >> 3, sk = (tid & 7) * 4;
+    f32x4 pa[2], pb[2];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int row = srow + 32 * j, k = k0 + sk;
+            const int m = m0 + row, n = n0 + row;
+            pa[j] = (m < M && k < K) ? ld4_w(A + (int64_t)m * K + k) : (f32x4){0.f, 0.f, 0.f, 0.f};
+            pb[j] = (n < N && k < K) ? ld4_w(Wt + (int64_t)n * K + k) : (f32x4){0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += kMK) {
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            *reinterpret_cast<f32x4 *>(&As[(srow + 32 * j) * kMPad + sk]) = pa[j];
+            *reinterpret_cast<f32x4 *>(&Bs[(srow + 32 * j) * kMPad + sk]) = pb[j];
+        }
+        __syncthreads();
+        if (k0 + kMK < K) fetch(k0 + kMK);
+        const float *ar = &As[(wm * 32 + r32) * kMPad + 16 * h];
+        const float *br = &Bs[(wn * 32 + r32) * kMPad + 16 * h];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const f32x4 a = *reinterpret_cast<const f32x4 *>(ar + 4 * q);
+            const f32x4 b = *reinterpret_cast<const f32x4 *>(br + 4 * q);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[e], b[e], acc, 0, 0, 0);
+        }
+    }
+    const int n = n0 + wn * 32 + r32;
+    if (n >= N) return;
+    const float bn = bias ? bias[n] : 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int m = m0 + wm * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        if (m < M) {
+            float v = acc[r] + bn;
+            if (relu && v < 0.f) v = 0.f;
             C[(int64_t)m * N + n] = v;
         }
     }
@@ -708,6 +921,52 @@ int launched(const char *what)
     return DB_OK;
 }
 
+// Matrix-core forward for float activations: picks the voxel box from the output
+// width and the channel chunk that fits the LDS budget. Returns 1 when the shape
+// is not covered (the caller then takes the vector kernel).
+template <class WT, int TD, int TH, int TW, int MT>
+int conv_mfma_launch(int B, int Ci, int Co, int D, int H, int W, const void *X,
+                            const void *Wt, const void *bias, int relu, void *Y, hipStream_t s)
+{
+    constexpr int PV = (2 * TD + 1) * (2 * TH + 1) * (2 * TW + 8);
+    const int nt = (Co + 15) / 16;
+    int cc = Ci < 16 ? Ci : 16;
+    while (cc > 0 && (int64_t)cc * PV + (int64_t)nt * 16 * (27 * cc + 1) > kCvLds) cc -= 4;
+    if (cc <= 0) return 1;
+    const int OD = D / 2, OH = H / 2, OW = W / 2;
+    const int th = (OH + TH - 1) / TH, tw = (OW + TW - 1) / TW;
+    const dim3 grid((unsigned)(((OD + TD - 1) / TD) * th * tw), (unsigned)B);
+#define TDB_CONV_MFMA(NT_)                                                                         \
+    hipLaunchKernelGGL((conv_mfma_kernel<WT, TD, TH, TW, MT, NT_>), grid, dim3(256), 0, s, Ci, Co, D, \
+                       H, W, cc, th, tw, (const float *)X, (const WT *)Wt, (const float *)bias,    \
+                       relu, (float *)Y)
+    switch (nt) {
+    case 1: TDB_CONV_MFMA(1); break;
+    case 2: TDB_CONV_MFMA(2); break;
+    case 3: TDB_CONV_MFMA(3); break;
+    default: TDB_CONV_MFMA(4); break;
+    }
+#undef TDB_CONV_MFMA
+    return launched("nn_conv3d_s2_fwd");
+}
+
+template <class WT>
+int conv_mfma_shape(int B, int Ci, int Co, int D, int H, int W, const void *X,
+                           const void *Wt, const void *bias, int relu, void *Y, hipStream_t s)
+{
+    const int OW = W / 2;
+    if (OW >= 16) return conv_mfma_launch<WT, 2, 4, 16, 2>(B, Ci, Co, D, H, W, X, Wt, bias, relu, Y, s);
+    if (OW >= 8) return conv_mfma_launch<WT, 4, 4, 8, 2>(B, Ci, Co, D, H, W, X, Wt, bias, relu, Y, s);
+    return conv_mfma_launch<WT, 4, 4, 4, 1>(B, Ci, Co, D, H, W, X, Wt, bias, relu, Y, s);
+}
+
+int conv_fwd_mfma(bool bf16w, int B, int Ci, int Co, int D, int H, int W, const void *X,
+                         const void *Wt, const void *bias, int relu, void *Y, hipStream_t s)
+{
+    return bf16w ? conv_mfma_shape<uint16_t>(B, Ci, Co, D, H, W, X, Wt, bias, relu, Y, s)
+                 : conv_mfma_shape<float>(B, Ci, Co, D, H, W, X, Wt, bias, relu, Y, s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -803,6 +1062,11 @@ int nn_conv3d_s2_fwd(int dtype, int B, int Ci, int Co, int D, int H, int W, cons
     if (pair < 0 || !conv_dims_ok(B, Ci, Co, D, H, W) || !X || !Wt || !Y)
         return tdb_set_error(DB_EINVAL, "nn_conv3d_s2_fwd: bad arguments");
     const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (pair <= 1 && Ci % 4 == 0 && W % 4 == 0 && (uintptr_t)X % 16 == 0 && Co <= 64 &&
+        B <= 65535) {
+        const int e = conv_fwd_mfma(pair == 0, B, Ci, Co, D, H, W, X, Wt, bias, relu, Y, s);
+        if (e <= 0) return e;                     // launched (or failed); > 0: shape not covered
+    }
     const int64_t osp = (int64_t)(D / 2) * (H / 2) * (W / 2);
     // 16 output channels per thread for the small late layers (Co >= 16, at most 16^3
     // input voxels): every input tap loaded then feeds twice the multiply-adds. The
@@ -905,7 +1169,19 @@ int nn_linear_fwd(int dtype, int B, int In, int Out, const void *X, const void *
         return tdb_set_error(DB_EINVAL, "nn_linear_fwd: bad arguments");
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const dim3 grid((Out + kLN - 1) / kLN, (B + kLM - 1) / kLM);
-    if (pair == 0)
+    const dim3 mgrid((Out + kMM - 1) / kMM, (B + kMM - 1) / kMM);
+    // The matrix-core path loads four k at a time: rows and bases must be aligned to that.
+    const size_t wal = pair == 0 ? 8 : 16;
+    const bool vec = In % 4 == 0 && (uintptr_t)X % 16 == 0 && (uintptr_t)Wt % wal == 0;
+    if (pair == 0 && vec)
+        hipLaunchKernelGGL(linear_mfma_kernel<uint16_t>, mgrid, dim3(256), 0, s, B, Out, In,
+                           (const float *)X, (const uint16_t *)Wt, (const float *)bias, relu,
+                           (float *)Y);
+    else if (pair == 1 && vec)
+        hipLaunchKernelGGL(linear_mfma_kernel<float>, mgrid, dim3(256), 0, s, B, Out, In,
+                           (const float *)X, (const float *)Wt, (const float *)bias, relu,
+                           (float *)Y);
+    else if (pair == 0)
         hipLaunchKernelGGL((linear_gemm_kernel<float, uint16_t, false>), grid, dim3(256), 0, s, B,
                            Out, In, (const float *)X, (const uint16_t *)Wt, (const float *)bias,
                            relu, (float *)Y);

@@ -271,3 +271,49 @@ def test_conv_forward_large_layers(shape):
                               wc.cuda(), relu)
         yr = E.conv(x64, wc.to(torch.float64), b64, relu)
         assert _rel(_cpu64(y), yr) < 2e-5, (shape, relu)
+
+
+@pytest.mark.parametrize("shape", [(70, 4100, 130), (1024, 4096, 512), (32, 512, 4096), (5, 8, 3)])
+def test_linear_forward_matrix_core(shape):
+    """Float linear forward on the FP32 matrix cores (K a multiple of 4), several tiles with
+    ragged edges in M, N and K, BF16 and float weights, against the float64 oracle product."""
+    need_gpu()
+    from paper_2205_04550_amd import nn
+    B, In, Out = shape
+    g = torch.Generator().manual_seed(B + In + Out)
+    x64 = torch.randn(B, In, generator=g, dtype=torch.float64)
+    w64 = torch.randn(Out, In, generator=g, dtype=torch.float64) * (1.0 / math.sqrt(In))
+    b64 = torch.randn(Out, generator=g, dtype=torch.float64)
+    for wdt in (torch.bfloat16, torch.float32):
+        wc = w64.to(wdt)
+        for relu in (False, True):
+            say(f"linear mfma {shape} {wdt} relu={relu}")
+            y = nn.Linear.apply(x64.to("cuda", torch.float32), w64.cuda().float(),
+                                b64.cuda().float(), wc.cuda(), relu)
+            yr = x64 @ wc.to(torch.float64).T + b64
+            yr = torch.relu(yr) if relu else yr
+            assert _rel(_cpu64(y), yr) < 2e-5, (shape, wdt, relu)
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 20, 14, 10, 40), (2, 32, 64, 8, 8, 8), (2, 20, 16, 18, 12, 20),
+                                   (1, 8, 16, 32, 32, 32), (2, 16, 33, 6, 22, 12), (2, 12, 8, 4, 6, 36)])
+def test_conv_forward_matrix_core(shape):
+    """Float convolution forward on the FP32 matrix cores (Ci, W % 4 == 0): every voxel-box
+    shape, one to four 16-channel output tiles with a ragged last tile, several input
+    channel chunks, ragged boxes at the volume's edges; BF16 and float weights."""
+    need_gpu()
+    from paper_2205_04550_amd import nn
+    B, Ci, Co, D, H, W = shape
+    g = torch.Generator().manual_seed(Ci * 1000 + Co * 10 + D)
+    x64 = torch.rand(B, Ci, D, H, W, generator=g, dtype=torch.float64) - 0.3
+    w64 = torch.randn(Co, Ci, 3, 3, 3, generator=g, dtype=torch.float64) * 0.2
+    b64 = torch.randn(Co, generator=g, dtype=torch.float64)
+    for wdt in (torch.bfloat16, torch.float32):
+        wc = w64.to(wdt)
+        for relu in (False, True):
+            say(f"conv mfma {shape} {wdt} relu={relu}")
+            y = nn.Conv3dS2.apply(x64.to("cuda", torch.float32), w64.cuda().float(),
+                                  b64.cuda().float(), wc.cuda(), relu)
+            yr = E.conv(x64, wc.to(torch.float64), b64, relu)
+            assert y.shape == yr.shape
+            assert _rel(_cpu64(y), yr) < 2e-5, (shape, wdt, relu)
