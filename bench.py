@@ -442,7 +442,7 @@ def bench_embed(args, db, gen, n, build_s) -> int:
         if timed:
             ev[0].record()
         with torch.no_grad():
-            ql = model.encode(nn.meanpool_labels(lab_d))
+            ql = model.encode_labels(lab_d)
         Q = B.Latents(ql, B.EMB_BF16)
         if timed:
             ev[1].record()
@@ -509,7 +509,7 @@ def bench_embed(args, db, gen, n, build_s) -> int:
 
     def enc_fp8():
         with torch.no_grad():
-            return B.Latents(model.encode(nn.meanpool_labels(lab_d)), B.EMB_FP8)
+            return B.Latents(model.encode_labels(lab_d), B.EMB_FP8)
     variants["fp8_latents"] = leg("FP8 latents", B.EMB_FP8, enc_fp8, X8)
     del X8
     log(f"training the hashing encoder (Bi-half layer) for {args.train_steps} steps of 32")
@@ -526,7 +526,7 @@ def bench_embed(args, db, gen, n, build_s) -> int:
 
     def enc_hash():
         with torch.no_grad():
-            return B.BinaryCodes(model_h.encode(nn.meanpool_labels(lab_d)), Xh.thr)
+            return B.BinaryCodes(model_h.encode_labels(lab_d), Xh.thr)
     variants["bf_hash_512bit"] = leg("Bi-half codes (Hamming)", B.EMB_BIN, enc_hash, Xh)
     variants["bf_hash_512bit"].update({"train_s": hash_train_s, "gamma": HASH_GAMMA,
                                        "train_loss_first_last": [losses_h[0], losses_h[-1]]})
@@ -554,7 +554,7 @@ def bench_embed(args, db, gen, n, build_s) -> int:
 
         def step_pair():
             with torch.no_grad():
-                qs = [B.Latents(mdl.encode(nn.meanpool_labels(lab_d, mask=m)), B.EMB_BF16)
+                qs = [B.Latents(mdl.encode_labels(lab_d, mask=m), B.EMB_BF16)
                       for mdl, m in pair]
             D = B.emb_distances_l2sum(qs[0], Xs[0], qs[1], Xs[1], out=Dbuf)
             ci2, _ = B.emb_topk_min(D, n_cand)
@@ -672,7 +672,7 @@ def bench_embed500k(args, db, gen, n, build_s, n_big: int = 500_000) -> int:
     lab_d = torch.from_numpy(labels).cuda()
     del labels
     with torch.no_grad():
-        ql = model.encode(nn.meanpool_labels(lab_d))
+        ql = model.encode_labels(lab_d)
     Q8, Q16 = B.Latents(ql, B.EMB_FP8), B.Latents(ql, B.EMB_BF16)
     D = torch.empty((nq, n_big), dtype=torch.float32, device="cuda")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]

@@ -60,6 +60,19 @@ int nn_meanpool_db_mask(const db_t *db, const int32_t *idx, int B, int mask, voi
 int nn_meanpool_labels_mask(const uint8_t *labels, int B, int nx, int ny, int nz, int mask,
                             void *out, int dtype, void *stream);
 
+/* First encoder layer read straight from query labels: Y = act(conv(P) + bias)
+ * where P is the 2x2x2 mean of the masks (as nn_meanpool_labels, or
+ * nn_meanpool_labels_mask for one mask) and conv the stride-2 convolution
+ * below; one pass, the pooled volume never goes to memory. mask -1: P has two
+ * channels (FLAIR, T1Gd), Wt is [Co][2][3][3][3]; mask 0 / 1: that mask alone,
+ * Wt [Co][1][3][3][3]. Wt bfloat16 bits (uint16), bias float [Co] or NULL,
+ * Y float [B][Co][nz/4][ny/4][nx/4]. Pooled values (multiples of 1/8) and
+ * weights are exact in the BF16 matrix-core products, sums are FP32, so Y
+ * equals the two-call result up to summation order. Needs nx % 128 == 0,
+ * ny % 4 == 0, nz % 4 == 0, Co <= 16, B <= 65535, labels 16-byte aligned. */
+int nn_pool_conv_labels(const uint8_t *labels, int B, int nx, int ny, int nz, int mask, int Co,
+                        const void *Wt, const float *bias, int relu, float *Y, void *stream);
+
 /* Y = act(conv(X)) with X [B][Ci][D][H][W], Y [B][Co][D/2][H/2][W/2];
  * bias [Co] or NULL; relu != 0 applies max(0, .). */
 int nn_conv3d_s2_fwd(int dtype, int B, int Ci, int Co, int D, int H, int W, const void *X,

@@ -147,41 +147,61 @@ __global__ void __launch_bounds__(256) conv_fwd_kernel(int B, int Ci, int Co, in
 // Forward on the FP32 matrix cores for float activations (Ci % 4 == 0, W % 4 ==
 // 0): an implicit GEMM Y[co][voxel] = sum over (tap, ci) of W[co][ci][tap]
 // X[ci][voxel + tap], each product exact in FP32 as with FMA (only the summation
-// order differs). A block takes a TD x TH x TW box of output voxels of one sample
-// and all output channels. Per chunk of CC input channels it stages in LDS the
-// input patch, (2TD+1) x (2TH+1) rows of 2TW+8 floats (the 2TW+1 needed, widened
-// to whole aligned 16-byte groups; zeros outside the volume), and the chunk's
-// weights (bf16 widened to float). Each wave owns MT tiles of 16 voxels along x
-// and NT tiles of 16 output channels; one 16 x 16 x 4 product takes four input
+// order differs). A tile is a TD x TH x TW box of output voxels of one sample
+// with all output channels; a block takes npb tiles in turn. Per tile and chunk
+// of four input channels (a stage) it stages in LDS the input patch, (2TD+1) x
+// (2TH+1) rows of 2TW+8 floats (the 2TW+1 needed, widened to whole aligned
+// 16-byte groups; zeros outside the volume), and the chunk's weights (bf16
+// widened to float); the next stage's loads are in flight in registers while
+// the current one is multiplied. Each wave owns MT tiles of 16 voxels along x
+// and NT tiles of 16 output channels; one 16 x 16 x 4 product takes the four
 // channels of one tap, lane l giving channel l / 16 for voxel (or output
 // channel) l % 16.
-constexpr int kCvLds = 12288;   // floats of LDS per block (48 KB: three blocks per CU)
-constexpr int kCvBatch = 8;     // staging loads in flight per thread
+__device__ __forceinline__ void ld_w2(const uint16_t *p, float *o)
+{
+    const uint32_t u = *reinterpret_cast<const uint32_t *>(p);
+    o[0] = __uint_as_float(u << 16);
+    o[1] = __uint_as_float(u & 0xffff0000u);
+}
+__device__ __forceinline__ void ld_w2(const float *p, float *o)
+{
+    const float2 v = *reinterpret_cast<const float2 *>(p);
+    o[0] = v.x;
+    o[1] = v.y;
+}
+
+template <int TD, int TH, int TW, int NT>
+struct ConvTile {
+    static constexpr int PWA = 2 * TW + 8, SEGS = PWA / 4, PH = 2 * TH + 1, PD = 2 * TD + 1;
+    static constexpr int PROWS = PD * PH, PVA = PROWS * PWA;
+    static constexpr int NX4 = 4 * PROWS * SEGS;              // float4 groups of a stage
+    static constexpr int NW = NT * 16 * 108;                  // weights of a stage
+    static constexpr int WROW = 109;                          // LDS row of one output channel
+    static constexpr int XB = (NX4 + 255) / 256, WB = (NW / 2 + 255) / 256;   // WB: pairs
+    static constexpr int LDS = 4 * PVA + NT * 16 * WROW;      // floats
+};
 
 template <class WT, int TD, int TH, int TW, int MT, int NT>
-__global__ void __launch_bounds__(256) conv_mfma_kernel(int Ci, int Co, int D, int H, int W, int CC,
-                                                        int tiles_h, int tiles_w,
+__global__ void __launch_bounds__(256) conv_mfma_kernel(int Ci, int Co, int D, int H, int W,
+                                                        int tiles_h, int tiles_w, int T, int npb,
                                                         const float *__restrict__ X,
                                                         const WT *__restrict__ Wt,
                                                         const float *__restrict__ bias, int relu,
                                                         float *__restrict__ Y)
 {
     static_assert(TD * TH * TW == 64 * MT, "a wave owns MT tiles of 16 voxels");
-    constexpr int PWA = 2 * TW + 8, SEGS = PWA / 4, PH = 2 * TH + 1, PD = 2 * TD + 1;
-    constexpr int PROWS = PD * PH, PVA = PROWS * PWA;
-    __shared__ __attribute__((aligned(16))) float lds[kCvLds];
+    using G = ConvTile<TD, TH, TW, NT>;
+    constexpr int PWA = G::PWA, SEGS = G::SEGS, PH = G::PH, PROWS = G::PROWS, PVA = G::PVA;
+    __shared__ __attribute__((aligned(16))) float lds[G::LDS];
     float *xs = lds;
-    float *ws = lds + CC * PVA;                // [co][ci in chunk][tap], rows of 27 CC + 1
-    const int wrow = 27 * CC + 1;
+    float *ws = lds + 4 * PVA;                 // [co][ci in chunk][tap], rows of WROW
     const int OD = D / 2, OH = H / 2, OW = W / 2;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kq = lane >> 4;
     const int b = blockIdx.y;
-    const int tix = blockIdx.x;
-    const int tw = tix % tiles_w, th = (tix / tiles_w) % tiles_h, td = tix / (tiles_w * tiles_h);
-    const int od0 = td * TD, oh0 = th * TH, ow0 = tw * TW;
-    // Patch origin: row (z, y) = input (2 od0 - 1 + z, 2 oh0 - 1 + y); column c = input
-    // x 2 ow0 - 4 + c, so tap kw of output x-offset ox sits at column 2 ox + kw + 3.
-    const int iz0 = 2 * od0 - 1, iy0 = 2 * oh0 - 1, ix0 = 2 * ow0 - 4;
+    int t0 = blockIdx.x * npb;
+    if (T % (8 * npb) == 0) t0 = (blockIdx.x % 8) * (T / 8) + (blockIdx.x / 8) * npb;
+    const int nt_blk = min(npb, T - t0);
+    const int nc = Ci / 4, K = nt_blk * nc;
     int vb[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
@@ -189,92 +209,105 @@ __global__ void __launch_bounds__(256) conv_mfma_kernel(int Ci, int Co, int D, i
         const int z = v / (TH * TW), y = (v / TW) % TH, x = v % TW;
         vb[m] = kq * PVA + (2 * z * PH + 2 * y) * PWA + 2 * x + 3;
     }
+    const int64_t isp = (int64_t)D * H * W;
+    const float *Xb = X + (int64_t)b * Ci * isp;
+    f32x4 xin[G::XB];
+    float wv[G::WB][2];
+    // Loads of stage k: tile t0 + k / nc, input channels 4 (k % nc) .. + 3. Patch origin:
+    // row (z, y) = input (2 od0 - 1 + z, 2 oh0 - 1 + y); column c = input x 2 ow0 - 4 + c,
+    // so tap kw of output x-offset ox sits at column 2 ox + kw + 3.
+    auto fetch = [&](int k) {
+        const int t = t0 + k / nc, c0 = 4 * (k % nc);
+        const int tw = t % tiles_w, th = (t / tiles_w) % tiles_h, td = t / (tiles_w * tiles_h);
+        const int iz0 = 2 * td * TD - 1, iy0 = 2 * th * TH - 1, ix0 = 2 * tw * TW - 4;
+#pragma unroll
+        for (int j = 0; j < G::XB; ++j) {
+            const int e = j * 256 + tid;
+            const int row = e / SEGS, seg = e - row * SEGS;
+            const int ci = row / PROWS, rr = row - ci * PROWS;
+            const int gz = iz0 + rr / PH, gy = iy0 + rr % PH, gx = ix0 + 4 * seg;
+            xin[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            if (e < G::NX4 && gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 && gx < W)
+                xin[j] = *reinterpret_cast<const f32x4 *>(
+                    Xb + (int64_t)(c0 + ci) * isp + ((int64_t)gz * H + gy) * W + gx);
+        }
+        // Weights in pairs (r even; 108 per output channel and chunk, so a pair never
+        // straddles two channels, and Ci % 4 == 0 keeps the pair 2-element aligned).
+#pragma unroll
+        for (int j = 0; j < G::WB; ++j) {
+            const int e = 2 * (j * 256 + tid);
+            const int co = e / 108, r = e - co * 108;
+            wv[j][0] = wv[j][1] = 0.f;
+            if (e < G::NW && co < Co) ld_w2(Wt + ((int64_t)co * Ci + c0) * 27 + r, wv[j]);
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int j = 0; j < G::XB; ++j) {
+            const int e = j * 256 + tid;
+            if (e < G::NX4) *reinterpret_cast<f32x4 *>(&xs[4 * e]) = xin[j];
+        }
+#pragma unroll
+        for (int j = 0; j < G::WB; ++j) {
+            const int e = 2 * (j * 256 + tid);
+            const int co = e / 108, r = e - co * 108;
+            if (e < G::NW) {
+                ws[co * G::WROW + r] = wv[j][0];
+                ws[co * G::WROW + r + 1] = wv[j][1];
+            }
+        }
+    };
     f32x4 acc[MT][NT];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[m][n] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    const int64_t isp = (int64_t)D * H * W;
-    const float *Xb = X + (int64_t)b * Ci * isp;
-    const int nx4 = CC * PROWS * SEGS, nw = NT * 16 * 27 * CC;
-    for (int c0 = 0; c0 < Ci; c0 += CC) {
-        const int cc = min(CC, Ci - c0);
-        __syncthreads();
-        for (int t0 = 0; t0 < nx4; t0 += 256 * kCvBatch) {
-            f32x4 v[kCvBatch];
-#pragma unroll
-            for (int j = 0; j < kCvBatch; ++j) {
-                const int t = t0 + j * 256 + tid;
-                const int row = t / SEGS, seg = t - row * SEGS;
-                const int ci = row / PROWS, rr = row - ci * PROWS;
-                const int gz = iz0 + rr / PH, gy = iy0 + rr % PH, gx = ix0 + 4 * seg;
-                v[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-                if (t < nx4 && ci < cc && gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 &&
-                    gx < W)
-                    v[j] = *reinterpret_cast<const f32x4 *>(
-                        Xb + (int64_t)(c0 + ci) * isp + ((int64_t)gz * H + gy) * W + gx);
-            }
-#pragma unroll
-            for (int j = 0; j < kCvBatch; ++j) {
-                const int t = t0 + j * 256 + tid;
-                if (t < nx4) *reinterpret_cast<f32x4 *>(&xs[4 * t]) = v[j];
-            }
-        }
-        for (int t0 = 0; t0 < nw; t0 += 256 * kCvBatch) {
-            float v[kCvBatch];
-#pragma unroll
-            for (int j = 0; j < kCvBatch; ++j) {
-                const int t = t0 + j * 256 + tid;
-                const int co = t / (27 * CC), r = t - co * (27 * CC);
-                v[j] = 0.f;
-                if (t < nw && co < Co && r < 27 * cc) v[j] = ld_w(Wt, ((int64_t)co * Ci + c0) * 27 + r);
-            }
-#pragma unroll
-            for (int j = 0; j < kCvBatch; ++j) {
-                const int t = t0 + j * 256 + tid;
-                const int co = t / (27 * CC), r = t - co * (27 * CC);
-                if (t < nw) ws[co * wrow + r] = v[j];
-            }
-        }
-        __syncthreads();
-        const int nq = cc >> 2;
-        for (int q = 0; q < nq; ++q) {
-            const float *xq = xs + 4 * q * PVA;
-            const float *wq = ws + (4 * q + kq) * 27 + (lane & 15) * wrow;
-#pragma unroll 9
-            for (int tap = 0; tap < 27; ++tap) {
-                const int toff = ((tap / 9) * PH + (tap / 3) % 3) * PWA + tap % 3;
-                float a[NT];
-#pragma unroll
-                for (int n = 0; n < NT; ++n) a[n] = wq[n * 16 * wrow + tap];
-#pragma unroll
-                for (int m = 0; m < MT; ++m) {
-                    const float bv = xq[vb[m] + toff];
-#pragma unroll
-                    for (int n = 0; n < NT; ++n)
-                        acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[n], bv, acc[m][n], 0, 0, 0);
-                }
-            }
-        }
-    }
     const int64_t osp = (int64_t)OD * OH * OW;
+    if (K > 0) fetch(0);
+    for (int k = 0; k < K; ++k) {
+        stash();
+        __syncthreads();
+        if (k + 1 < K) fetch(k + 1);
+        const float *wq = ws + kq * 27 + (lane & 15) * G::WROW;
+#pragma unroll 9
+        for (int tap = 0; tap < 27; ++tap) {
+            const int toff = ((tap / 9) * PH + (tap / 3) % 3) * PWA + tap % 3;
+            float a[NT];
 #pragma unroll
-    for (int m = 0; m < MT; ++m) {
-        const int v = (wave * MT + m) * 16 + (lane & 15);
-        const int oz = od0 + v / (TH * TW), oy = oh0 + (v / TW) % TH, ox = ow0 + v % TW;
-        if (oz >= OD || oy >= OH || ox >= OW) continue;
-        const int64_t o = ((int64_t)oz * OH + oy) * OW + ox;
+            for (int n = 0; n < NT; ++n) a[n] = wq[n * 16 * G::WROW + tap];
 #pragma unroll
-        for (int n = 0; n < NT; ++n)
+            for (int m = 0; m < MT; ++m) {
+                const float bv = xs[vb[m] + toff];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int co = n * 16 + 4 * kq + r;
-                if (co < Co) {
-                    float y = acc[m][n][r] + (bias ? bias[co] : 0.f);
-                    if (relu && y < 0.f) y = 0.f;
-                    Y[((int64_t)b * Co + co) * osp + o] = y;
-                }
+                for (int n = 0; n < NT; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[n], bv, acc[m][n], 0, 0, 0);
             }
+        }
+        if (k % nc == nc - 1) {                 // last chunk of this tile: write it out
+            const int t = t0 + k / nc;
+            const int tw = t % tiles_w, th = (t / tiles_w) % tiles_h, td = t / (tiles_w * tiles_h);
+#pragma unroll
+            for (int m = 0; m < MT; ++m) {
+                const int v = (wave * MT + m) * 16 + (lane & 15);
+                const int oz = td * TD + v / (TH * TW), oy = th * TH + (v / TW) % TH;
+                const int ox = tw * TW + v % TW;
+                const bool ok = oz < OD && oy < OH && ox < OW;
+                const int64_t o = ((int64_t)oz * OH + oy) * OW + ox;
+#pragma unroll
+                for (int n = 0; n < NT; ++n)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int co = n * 16 + 4 * kq + r;
+                        if (ok && co < Co) {
+                            float y = acc[m][n][r] + (bias ? bias[co] : 0.f);
+                            if (relu && y < 0.f) y = 0.f;
+                            Y[((int64_t)b * Co + co) * osp + o] = y;
+                        }
+                        acc[m][n][r] = 0.f;
+                    }
+            }
+        }
+        __syncthreads();                        // the next stash overwrites the stage
     }
 }
 
@@ -841,6 +874,177 @@ __global__ void __launch_bounds__(256) meanpool_labels_fast_kernel(const uint8_t
 }
 
 // Packed masks: nx % 32 == 0. Thread = (b, mask, z, y, word of 32 input x = 16 outputs).
+// First encoder layer straight from query labels: pooled = 2x2x2 mean of the
+// masks (values k/8, exact in bfloat16), then the stride-2 convolution on the
+// BF16 matrix cores (each product of two bfloat16 values is exact in FP32; the
+// sum is FP32). A block takes 2 x 4 x 32 output voxels of one sample: it pools
+// the 5 x 9 x 65 patch of pooled voxels it reads into LDS, one 32-bit word per
+// pooled voxel (channel 0 in the low half, channel 1 in the high half), rows of
+// kPlRow words with pooled x = 2 ow0 - 1 + c at column c + 3. The reduction
+// index k < 64 of the two 16 x 16 x 32 products is tap 16 s + k / 2 (s = step),
+// channel k % 2, so a lane's eight values of one step are four whole words.
+// Each wave owns four tiles of 16 voxels along x; output channels are the 16
+// rows (Co <= 16). XCD-aware: the tiles one XCD receives are neighbours, so the
+// pooled halo rows they share come from its L2.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kPlRow = 68;
+
+__device__ __forceinline__ uint32_t pooled_word(uint32_t f, uint32_t h, int e)
+{
+    // Byte pair e of the row sums: counts of the two label columns of one pooled x.
+    const uint32_t cf = ((f >> (16 * e)) & 0xffu) + ((f >> (16 * e + 8)) & 0xffu);
+    const uint32_t ch = ((h >> (16 * e)) & 0xffu) + ((h >> (16 * e + 8)) & 0xffu);
+    const uint32_t bf = __float_as_uint((float)cf * 0.125f) >> 16;   // exact: k/8
+    const uint32_t bh = __float_as_uint((float)ch * 0.125f) >> 16;
+    return bf | (bh << 16);
+}
+
+__global__ void __launch_bounds__(256) pool_conv_labels_kernel(const uint8_t *__restrict__ lab,
+                                                               int nx, int ny, int nz, int mask,
+                                                               int Ci, int Co, int npb,
+                                                               const uint16_t *__restrict__ Wt,
+                                                               const float *__restrict__ bias,
+                                                               int relu, float *__restrict__ Y)
+{
+    __shared__ __attribute__((aligned(16))) uint32_t pl[45 * kPlRow];
+    const int PZ = nz / 2, PY = ny / 2;
+    const int OD = nz / 4, OH = ny / 4, OW = nx / 4;
+    const int tw_n = OW / 32, th_n = (OH + 3) / 4, td_n = (OD + 1) / 2;
+    const int T = tw_n * th_n * td_n;
+    // This block's npb consecutive tiles; with T % (8 npb) == 0 the tiles one XCD
+    // receives (blocks x, x + 8, ...) form one contiguous run.
+    int t0 = blockIdx.x * npb;
+    if (T % (8 * npb) == 0) t0 = (blockIdx.x % 8) * (T / 8) + (blockIdx.x / 8) * npb;
+    const int b = blockIdx.y;
+    const uint8_t *L = lab + (int64_t)b * nz * ny * nx;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, j = lane & 15;
+    // Weights of both steps for this lane: row co = j, eight k from 8 g.
+    bf16x8 a[2];
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int tap = 16 * st + 4 * g + (e >> 1), c = e & 1;
+            uint16_t bits = 0;
+            if (j < Co && tap < 27 && c < Ci) bits = Wt[((int64_t)j * Ci + c) * 27 + tap];
+            a[st][e] = __builtin_bit_cast(__bf16, bits);
+        }
+    float bco[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bco[r] = (bias && 4 * g + r < Co) ? bias[4 * g + r] : 0.f;
+    // LDS offsets of this lane's four taps per step (tap >= 27: weight zero, any word).
+    int toff[2][4];
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int tap = 16 * st + 4 * g + i;
+            toff[st][i] = tap < 27 ? ((tap / 9) * 9 + (tap / 3) % 3) * kPlRow + tap % 3 : 0;
+        }
+    // Pooling items: 45 pooled rows x 8 groups of 8 pooled x (16 label bytes per label
+    // row), plus one halo column per row (pooled x = 2 ow0 - 1): 405, at most two per
+    // thread. The labels of the next tile are loaded while the current one is computed.
+    bool halo[2];
+    int row[2], seg[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int it = tid + 256 * u;
+        halo[u] = it >= 360;
+        row[u] = halo[u] ? it - 360 : it >> 3;
+        seg[u] = it & 7;
+    }
+    u32x4 v[2][4];
+    auto load = [&](int t) {
+        const int twi = t % tw_n, thi = (t / tw_n) % th_n, tdi = t / (tw_n * th_n);
+        const int od0 = 2 * tdi, oh0 = 4 * thi, ow0 = 32 * twi;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int Z = 2 * od0 - 1 + row[u] / 9, Yp = 2 * oh0 - 1 + row[u] % 9;
+            const bool in = tid + 256 * u < 405 && Z >= 0 && Z < PZ && Yp >= 0 && Yp < PY &&
+                            !(halo[u] && ow0 == 0);
+            const uint8_t *r0 = L + ((int64_t)(2 * Z) * ny + 2 * Yp) * nx;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint8_t *r = r0 + ((int64_t)(q >> 1) * ny + (q & 1)) * nx;
+                v[u][q] = (u32x4){0u, 0u, 0u, 0u};
+                if (in && !halo[u])
+                    v[u][q] = *reinterpret_cast<const u32x4 *>(r + 4 * ow0 + 16 * seg[u]);
+                else if (in)
+                    v[u][q].x = *reinterpret_cast<const uint16_t *>(r + 4 * ow0 - 2);
+            }
+        }
+    };
+    load(t0);
+    const int64_t osp = (int64_t)OD * OH * OW;
+    for (int n = 0; n < npb; ++n) {
+        const int t = t0 + n;
+        if (t >= T) break;                         // uniform over the block
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (tid + 256 * u >= 405) break;
+            uint32_t f[4] = {0u, 0u, 0u, 0u}, h[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    f[e] += v[u][q][e] & 0x01010101u;
+                    h[e] += (v[u][q][e] >> 1) & 0x01010101u;
+                }
+            if (Ci == 1) {       // one mask: it goes to channel 0, channel 1 stays zero
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (mask == 1) f[e] = h[e];
+                    h[e] = 0u;
+                }
+            }
+            if (!halo[u]) {
+                uint32_t w[8];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    w[2 * e] = pooled_word(f[e], h[e], 0);
+                    w[2 * e + 1] = pooled_word(f[e], h[e], 1);
+                }
+                u32x4 *dst = reinterpret_cast<u32x4 *>(&pl[row[u] * kPlRow + 4 + 8 * seg[u]]);
+                dst[0] = (u32x4){w[0], w[1], w[2], w[3]};
+                dst[1] = (u32x4){w[4], w[5], w[6], w[7]};
+            } else {
+                pl[row[u] * kPlRow + 3] = pooled_word(f[0], h[0], 0);
+            }
+        }
+        __syncthreads();
+        if (n + 1 < npb && t + 1 < T) load(t + 1);
+        const int twi = t % tw_n, thi = (t / tw_n) % th_n, tdi = t / (tw_n * th_n);
+        const int od0 = 2 * tdi, oh0 = 4 * thi, ow0 = 32 * twi;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int vx = (wave * 4 + m) * 16 + j;
+            const int z = vx >> 7, y = (vx >> 5) & 3, x = vx & 31;
+            const int base = (2 * z * 9 + 2 * y) * kPlRow + 2 * x + 3;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int st = 0; st < 2; ++st) {
+                const u32x4 bw = {pl[base + toff[st][0]], pl[base + toff[st][1]],
+                                  pl[base + toff[st][2]], pl[base + toff[st][3]]};
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[st], __builtin_bit_cast(bf16x8, bw),
+                                                              acc, 0, 0, 0);
+            }
+            const int oz = od0 + z, oy = oh0 + y, ox = ow0 + x;
+            if (oz >= OD || oy >= OH) continue;
+            const int64_t o = ((int64_t)oz * OH + oy) * OW + ox;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = 4 * g + r;
+                if (co < Co) {
+                    float yv = acc[r] + bco[r];
+                    if (relu && yv < 0.f) yv = 0.f;
+                    Y[((int64_t)b * Co + co) * osp + o] = yv;
+                }
+            }
+        }
+        __syncthreads();                           // the next tile overwrites pl
+    }
+}
+
 template <class T>
 __global__ void __launch_bounds__(256) meanpool_db_fast_kernel(const uint32_t *__restrict__ planes,
                                                                int Wp, int nxw, int ny, int nz,
@@ -922,24 +1126,23 @@ int launched(const char *what)
 }
 
 // Matrix-core forward for float activations: picks the voxel box from the output
-// width and the channel chunk that fits the LDS budget. Returns 1 when the shape
-// is not covered (the caller then takes the vector kernel).
+// width; a block takes npb tiles of one sample (fewer blocks than tiles keeps the
+// loads of the next stage in flight). Returns 1 when the shape is not covered (the
+// caller then takes the vector kernel).
 template <class WT, int TD, int TH, int TW, int MT>
 int conv_mfma_launch(int B, int Ci, int Co, int D, int H, int W, const void *X,
                             const void *Wt, const void *bias, int relu, void *Y, hipStream_t s)
 {
-    constexpr int PV = (2 * TD + 1) * (2 * TH + 1) * (2 * TW + 8);
     const int nt = (Co + 15) / 16;
-    int cc = Ci < 16 ? Ci : 16;
-    while (cc > 0 && (int64_t)cc * PV + (int64_t)nt * 16 * (27 * cc + 1) > kCvLds) cc -= 4;
-    if (cc <= 0) return 1;
     const int OD = D / 2, OH = H / 2, OW = W / 2;
     const int th = (OH + TH - 1) / TH, tw = (OW + TW - 1) / TW;
-    const dim3 grid((unsigned)(((OD + TD - 1) / TD) * th * tw), (unsigned)B);
+    const int T = ((OD + TD - 1) / TD) * th * tw;
+    const int npb = T >= 64 ? 4 : (T >= 16 ? 2 : 1);
+    const dim3 grid((unsigned)((T + npb - 1) / npb), (unsigned)B);
 #define TDB_CONV_MFMA(NT_)                                                                         \
     hipLaunchKernelGGL((conv_mfma_kernel<WT, TD, TH, TW, MT, NT_>), grid, dim3(256), 0, s, Ci, Co, D, \
-                       H, W, cc, th, tw, (const float *)X, (const WT *)Wt, (const float *)bias,    \
-                       relu, (float *)Y)
+                       H, W, th, tw, T, npb, (const float *)X, (const WT *)Wt,                     \
+                       (const float *)bias, relu, (float *)Y)
     switch (nt) {
     case 1: TDB_CONV_MFMA(1); break;
     case 2: TDB_CONV_MFMA(2); break;
@@ -1053,6 +1256,21 @@ int nn_meanpool_labels_mask(const uint8_t *labels, int B, int nx, int ny, int nz
         return tdb_set_error(DB_EINVAL, "nn_meanpool_labels_mask: mask %d", mask);
     return meanpool_labels("nn_meanpool_labels_mask", labels, B, nx, ny, nz, mask, 1, out, dtype,
                            stream);
+}
+
+int nn_pool_conv_labels(const uint8_t *labels, int B, int nx, int ny, int nz, int mask, int Co,
+                        const void *Wt, const float *bias, int relu, float *Y, void *stream)
+{
+    if (!labels || !Wt || !Y || B <= 0 || B > 65535 || nx <= 0 || ny <= 0 || nz <= 0 ||
+        nx % 128 || ny % 4 || nz % 4 || Co <= 0 || Co > 16 || mask < -1 || mask > 1 ||
+        (uintptr_t)labels % 16 || (int64_t)nx * ny * nz >= ((int64_t)1 << 31))
+        return tdb_set_error(DB_EINVAL, "nn_pool_conv_labels: bad arguments");
+    const int T = (nx / 128) * ((ny / 4 + 3) / 4) * ((nz / 4 + 1) / 2);
+    const int npb = T % 32 == 0 ? 4 : 1;           // tiles per block
+    hipLaunchKernelGGL(pool_conv_labels_kernel, dim3((unsigned)((T + npb - 1) / npb), (unsigned)B),
+                       dim3(256), 0, static_cast<hipStream_t>(stream), labels, nx, ny, nz, mask,
+                       mask < 0 ? 2 : 1, Co, npb, static_cast<const uint16_t *>(Wt), bias, relu, Y);
+    return launched("nn_pool_conv_labels");
 }
 
 int nn_conv3d_s2_fwd(int dtype, int B, int Ci, int Co, int D, int H, int W, const void *X,

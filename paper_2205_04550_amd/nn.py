@@ -47,6 +47,8 @@ _SIGS = {
     "nn_bihalf_fwd": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp]),
     "nn_meanpool_db_mask": (_i32, [_vp, _vp, _i32, _i32, _vp, _i32, _vp]),
     "nn_meanpool_labels_mask": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _vp, _i32, _vp]),
+    "nn_pool_conv_labels": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _i32, _vp,
+                                   _vp]),
     "nn_vae_ws_bytes": (_sz, [_i32, _i32, _i32]),
     "nn_vae_head_fwd": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "nn_vae_head_bwd": (_i32, [_i32, _i32, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]),
@@ -117,6 +119,24 @@ def meanpool_labels(labels: torch.Tensor, dtype=torch.float32, mask: int | None 
         _check(LIB.nn_meanpool_labels_mask(labels.data_ptr(), B, nx, ny, nz, mask, out.data_ptr(),
                                            _dt(out), _s()))
     return out
+
+
+def pool_conv_labels(labels: torch.Tensor, w_bf16: torch.Tensor, bias: torch.Tensor | None,
+                     relu: bool = True, mask: int | None = None) -> torch.Tensor:
+    """First encoder layer read straight from query labels (forward only): conv(meanpool(labels))
+    in one kernel. w_bf16 [Co][Ci][3][3][3] bfloat16 with Ci = 2 (both masks) or 1 (`mask`)."""
+    labels = _c(labels)
+    if labels.dim() == 3:
+        labels = labels[None]
+    B, nz, ny, nx = labels.shape
+    Co = w_bf16.shape[0]
+    assert w_bf16.dtype == torch.bfloat16 and w_bf16.shape[1] == (2 if mask is None else 1)
+    w_bf16 = _c(w_bf16)
+    bias = None if bias is None else _c(bias.detach())
+    y = torch.empty((B, Co, nz // 4, ny // 4, nx // 4), dtype=torch.float32, device=labels.device)
+    _check(LIB.nn_pool_conv_labels(labels.data_ptr(), B, nx, ny, nz, -1 if mask is None else mask,
+                                   Co, w_bf16.data_ptr(), _p(bias), int(relu), y.data_ptr(), _s()))
+    return y
 
 
 # ---- autograd functions ---------------------------------------------------------------------
@@ -414,7 +434,24 @@ class AutoEncoder:
 
     def encode(self, x: torch.Tensor) -> torch.Tensor:
         """The latent (for the VAE: the mean, from the first `latent` rows of the head)."""
-        h = self._features(x)
+        return self._head(self._features(x))
+
+    def encode_labels(self, labels: torch.Tensor, mask: int | None = None) -> torch.Tensor:
+        """encode(meanpool_labels(labels, mask=mask)) for inference, the pooling fused into the
+        first convolution when the shapes allow it (BF16 weights, nx % 128 == 0)."""
+        nz, ny, nx = labels.shape[-3:]
+        if not (self.bf16 and nx % 128 == 0 and ny % 4 == 0 and nz % 4 == 0
+                and self.channels[1] <= 16):
+            return self.encode(meanpool_labels(labels, mask=mask))
+        with torch.no_grad():
+            w, b, wc = self._w("enc0")
+            h = pool_conv_labels(labels, wc, b, True, mask)
+            for i in range(1, 4):
+                w, b, wc = self._w(f"enc{i}")
+                h = Conv3dS2.apply(h, w, b, wc, True)
+            return self._head(h.reshape(h.shape[0], -1))
+
+    def _head(self, h: torch.Tensor) -> torch.Tensor:
         w, b, wc = self._w("enc_fc")
         if self.vae_beta is None:
             return Linear.apply(h, w, b, wc, False)

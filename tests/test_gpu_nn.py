@@ -317,3 +317,48 @@ def test_conv_forward_matrix_core(shape):
             yr = E.conv(x64, wc.to(torch.float64), b64, relu)
             assert y.shape == yr.shape
             assert _rel(_cpu64(y), yr) < 2e-5, (shape, wdt, relu)
+
+
+@pytest.mark.parametrize("dims", [(12, 20, 256), (8, 8, 128), (128, 128, 128)])
+def test_pool_conv_labels_matches_oracle(dims):
+    """The first encoder layer read straight from labels (pooling fused, BF16 matrix cores)
+    against the float64 oracle conv of the oracle mean-pool: both masks and each mask alone,
+    ragged output boxes in z and y, two x tiles (the left halo column of the second)."""
+    need_gpu()
+    from paper_2205_04550_amd import nn
+    nz, ny, nx = dims
+    B = 3 if nz < 128 else 2
+    rng = np.random.default_rng(nz + ny + nx)
+    lab = rng.integers(0, 4, size=(B, nz, ny, nx), dtype=np.uint8)
+    lab[:, : nz // 3] = 0                                    # an empty slab
+    lab[0, :, :, nx // 2:] &= 1                              # FLAIR without T1Gd
+    pooled = E.meanpool(lab)
+    g = torch.Generator().manual_seed(nx)
+    lab_d = torch.from_numpy(lab).cuda()
+    for mask in (None, 0, 1):
+        ci = 2 if mask is None else 1
+        w64 = torch.randn(8, ci, 3, 3, 3, generator=g, dtype=torch.float64) * 0.3
+        b64 = torch.randn(8, generator=g, dtype=torch.float64)
+        wc = w64.to(torch.bfloat16)
+        x64 = torch.from_numpy(pooled if mask is None else pooled[:, mask:mask + 1].copy())
+        for relu in (True, False):
+            say(f"pool_conv_labels {dims} mask={mask} relu={relu}")
+            y = nn.pool_conv_labels(lab_d, wc.cuda(), b64.cuda().float(), relu, mask)
+            yr = E.conv(x64, wc.to(torch.float64), b64, relu)
+            assert y.shape == yr.shape
+            assert _rel(_cpu64(y), yr) < 2e-5, (dims, mask, relu)
+
+
+def test_encode_labels_matches_two_step_encode():
+    """AutoEncoder.encode_labels (fused first layer) equals encode(meanpool_labels(.)) up to
+    FP32 summation order, for the two-mask encoder and a one-mask encoder."""
+    need_gpu()
+    from paper_2205_04550_amd import nn
+    rng = np.random.default_rng(5)
+    lab = torch.from_numpy(rng.integers(0, 4, size=(4, 128, 128, 128), dtype=np.uint8)).cuda()
+    for mask, ch in ((None, (2, 8, 16, 32, 64)), (1, (1, 8, 16, 32, 64))):
+        model = nn.AutoEncoder(grid=64, channels=ch, latent=512, seed=3)
+        with torch.no_grad():
+            z1 = model.encode_labels(lab, mask=mask)
+            z2 = model.encode(nn.meanpool_labels(lab, mask=mask))
+        assert _rel(z1.double().cpu(), z2.double().cpu()) < 1e-4, mask
