@@ -414,7 +414,8 @@ __global__ void __launch_bounds__(kSelThreads) topk_min_kernel(const float *__re
 
 constexpr int kRerankMaxCand = 1024;
 
-constexpr int kRerankPerBlock = 16;    // candidates scored per block (4 waves x 4)
+constexpr int kRC = 2;                 // candidates per wave
+constexpr int kRerankPerBlock = 4 * kRC;   // candidates scored per block (4 waves)
 
 // grid (ceil(nc / kRerankPerBlock), nq), 256 threads (4 waves). Each wave scores
 // kRC candidates of query q at once: lanes sweep the rows where the query's row
@@ -442,7 +443,6 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
     // kRC candidates per wave: each query row is loaded once per group, and the
     // group sweeps the union of its members' boxes (each clipped to the query's);
     // a member reads only the rows inside its own box.
-    constexpr int kRC = 4;
     const int c0 = blockIdx.x * kRerankPerBlock + wave * kRC;
     if (c0 >= nc) return;   // a whole wave leaves; no block barrier below
     const uint32_t *D0[kRC], *D1[kRC];
@@ -471,23 +471,52 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
     uint32_t i0[kRC], i1[kRC];
 #pragma unroll
     for (int j = 0; j < kRC; ++j) i0[j] = i1[j] = 0;
-    for (int r = lane; r < nr; r += 64) {
-        const int zr = r / nyr;
-        const int z = uz0 + zr, y = uy0 + r - zr * nyr;
-        const int base = (z * ny + y) * nxw;
-        bool in[kRC];
+    if (nxw == 4) {
+        // Rows of 128 voxels: one 16-byte load per plane; two rows per lane per pass, all
+        // loads of the pass issued before any is used.
+        constexpr int U = 4;
+        for (int r0 = lane; r0 < nr; r0 += 64 * U) {
+            u32x4 qa[U], qb[U], da[U][kRC], db[U][kRC];
+            bool in[U][kRC];
 #pragma unroll
-        for (int j = 0; j < kRC; ++j) in[j] = z >= z0[j] && z < z1[j] && y >= y0[j] && y < y1[j];
-        if (nxw == 4) {
-            const u32x4 qa = *reinterpret_cast<const u32x4 *>(Q0 + base);
-            const u32x4 qb = *reinterpret_cast<const u32x4 *>(Q1 + base);
+            for (int u = 0; u < U; ++u) {
+                const int r = r0 + 64 * u;
+                const int zr = r / nyr;
+                const int z = uz0 + zr, y = uy0 + r - zr * nyr;
+                const int base = (z * ny + y) * 4;
+                const bool live = r < nr;
+                qa[u] = qb[u] = (u32x4){0u, 0u, 0u, 0u};
+                if (live) {
+                    qa[u] = *reinterpret_cast<const u32x4 *>(Q0 + base);
+                    qb[u] = *reinterpret_cast<const u32x4 *>(Q1 + base);
+                }
+#pragma unroll
+                for (int j = 0; j < kRC; ++j) {
+                    in[u][j] = live && z >= z0[j] && z < z1[j] && y >= y0[j] && y < y1[j];
+                    da[u][j] = db[u][j] = (u32x4){0u, 0u, 0u, 0u};
+                    if (in[u][j]) {
+                        da[u][j] = load_stream(reinterpret_cast<const u32x4 *>(D0[j] + base));
+                        db[u][j] = load_stream(reinterpret_cast<const u32x4 *>(D1[j] + base));
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int j = 0; j < kRC; ++j) {
+                    i0[j] += popc_and4(qa[u], da[u][j]);
+                    i1[j] += popc_and4(qb[u], db[u][j]);
+                }
+        }
+    } else {
+        for (int r = lane; r < nr; r += 64) {
+            const int zr = r / nyr;
+            const int z = uz0 + zr, y = uy0 + r - zr * nyr;
+            const int base = (z * ny + y) * nxw;
+            bool in[kRC];
 #pragma unroll
             for (int j = 0; j < kRC; ++j)
-                if (in[j]) {
-                    i0[j] += popc_and4(qa, *reinterpret_cast<const u32x4 *>(D0[j] + base));
-                    i1[j] += popc_and4(qb, *reinterpret_cast<const u32x4 *>(D1[j] + base));
-                }
-        } else {
+                in[j] = z >= z0[j] && z < z1[j] && y >= y0[j] && y < y1[j];
             for (int w = 0; w < nxw; ++w) {
                 const uint32_t qa = Q0[base + w], qb = Q1[base + w];
 #pragma unroll

@@ -176,12 +176,16 @@ struct ConvTile {
     static constexpr int PROWS = PD * PH, PVA = PROWS * PWA;
     static constexpr int NX4 = 4 * PROWS * SEGS;              // float4 groups of a stage
     static constexpr int NW = NT * 16 * 108;                  // weights of a stage
-    static constexpr int WROW = 109;                          // LDS row of one output channel
     static constexpr int XB = (NX4 + 255) / 256, WB = (NW / 2 + 255) / 256;   // WB: pairs
-    static constexpr int LDS = 4 * PVA + NT * 16 * WROW;      // floats
+    static constexpr int WALL = 4096;                         // floats: all weights at once
+    static constexpr int WLDS = NW > WALL ? NW : WALL;
+    static constexpr int LDS = 4 * PVA + WLDS;                // floats
 };
 
-template <class WT, int TD, int TH, int TW, int MT, int NT>
+// WALL: every weight of the layer sits in LDS for the whole block ([co][ci][tap], rows of
+// 27 Ci + 1 floats), staged once; otherwise each stage brings its chunk's weights
+// ([co][4][27], rows of 108).
+template <class WT, int TD, int TH, int TW, int MT, int NT, bool WALL>
 __global__ void __launch_bounds__(256) conv_mfma_kernel(int Ci, int Co, int D, int H, int W,
                                                         int tiles_h, int tiles_w, int T, int npb,
                                                         const float *__restrict__ X,
@@ -194,7 +198,8 @@ __global__ void __launch_bounds__(256) conv_mfma_kernel(int Ci, int Co, int D, i
     constexpr int PWA = G::PWA, SEGS = G::SEGS, PH = G::PH, PROWS = G::PROWS, PVA = G::PVA;
     __shared__ __attribute__((aligned(16))) float lds[G::LDS];
     float *xs = lds;
-    float *ws = lds + 4 * PVA;                 // [co][ci in chunk][tap], rows of WROW
+    float *ws = lds + 4 * PVA;
+    const int wrow = WALL ? 27 * Ci + 1 : 108;
     const int OD = D / 2, OH = H / 2, OW = W / 2;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, kq = lane >> 4;
     const int b = blockIdx.y;
@@ -209,10 +214,29 @@ __global__ void __launch_bounds__(256) conv_mfma_kernel(int Ci, int Co, int D, i
         const int z = v / (TH * TW), y = (v / TW) % TH, x = v % TW;
         vb[m] = kq * PVA + (2 * z * PH + 2 * y) * PWA + 2 * x + 3;
     }
-    const int64_t isp = (int64_t)D * H * W;
+    const int HW = H * W;
+    const int isp = D * HW;
     const float *Xb = X + (int64_t)b * Ci * isp;
+    // Per staged float4 of this thread: patch row (z, y), 16-byte group seg and channel,
+    // packed, and its offset from the patch origin (the same for every stage).
+    int pk[G::XB], rel[G::XB];
+#pragma unroll
+    for (int j = 0; j < G::XB; ++j) {
+        const int e = j * 256 + tid;
+        const int row = e / SEGS, seg = e - row * SEGS;
+        const int ci = row / PROWS, rr = row - ci * PROWS;
+        const int z = rr / PH, y = rr % PH;
+        pk[j] = e < G::NX4 ? z | (y << 8) | (seg << 16) : -1;
+        rel[j] = ci * isp + z * HW + y * W + 4 * seg;
+    }
+    if (WALL) {                                 // all weights, once
+        for (int e = tid; e < NT * 16 * 27 * Ci; e += 256) {
+            const int co = e / (27 * Ci), r = e - co * (27 * Ci);
+            ws[co * wrow + r] = co < Co ? ld_w(Wt, (int64_t)co * 27 * Ci + r) : 0.f;
+        }
+    }
     f32x4 xin[G::XB];
-    float wv[G::WB][2];
+    float wv[WALL ? 1 : G::WB][2];
     // Loads of stage k: tile t0 + k / nc, input channels 4 (k % nc) .. + 3. Patch origin:
     // row (z, y) = input (2 od0 - 1 + z, 2 oh0 - 1 + y); column c = input x 2 ow0 - 4 + c,
     // so tap kw of output x-offset ox sits at column 2 ox + kw + 3.
@@ -220,25 +244,25 @@ __global__ void __launch_bounds__(256) conv_mfma_kernel(int Ci, int Co, int D, i
         const int t = t0 + k / nc, c0 = 4 * (k % nc);
         const int tw = t % tiles_w, th = (t / tiles_w) % tiles_h, td = t / (tiles_w * tiles_h);
         const int iz0 = 2 * td * TD - 1, iy0 = 2 * th * TH - 1, ix0 = 2 * tw * TW - 4;
+        const float *org = Xb + (int64_t)c0 * isp + (int64_t)iz0 * HW + iy0 * W + ix0;
 #pragma unroll
         for (int j = 0; j < G::XB; ++j) {
-            const int e = j * 256 + tid;
-            const int row = e / SEGS, seg = e - row * SEGS;
-            const int ci = row / PROWS, rr = row - ci * PROWS;
-            const int gz = iz0 + rr / PH, gy = iy0 + rr % PH, gx = ix0 + 4 * seg;
+            const int z = pk[j] & 0xff, y = (pk[j] >> 8) & 0xff, seg = (pk[j] >> 16) & 0xff;
             xin[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-            if (e < G::NX4 && gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 && gx < W)
-                xin[j] = *reinterpret_cast<const f32x4 *>(
-                    Xb + (int64_t)(c0 + ci) * isp + ((int64_t)gz * H + gy) * W + gx);
+            if (pk[j] >= 0 && (unsigned)(iz0 + z) < (unsigned)D &&
+                (unsigned)(iy0 + y) < (unsigned)H && (unsigned)(ix0 + 4 * seg) < (unsigned)W)
+                xin[j] = *reinterpret_cast<const f32x4 *>(org + rel[j]);
         }
-        // Weights in pairs (r even; 108 per output channel and chunk, so a pair never
-        // straddles two channels, and Ci % 4 == 0 keeps the pair 2-element aligned).
+        if (!WALL) {
+            // Weights in pairs (r even; 108 per output channel and chunk, so a pair never
+            // straddles two channels, and Ci % 4 == 0 keeps the pair 2-element aligned).
 #pragma unroll
-        for (int j = 0; j < G::WB; ++j) {
-            const int e = 2 * (j * 256 + tid);
-            const int co = e / 108, r = e - co * 108;
-            wv[j][0] = wv[j][1] = 0.f;
-            if (e < G::NW && co < Co) ld_w2(Wt + ((int64_t)co * Ci + c0) * 27 + r, wv[j]);
+            for (int j = 0; j < G::WB; ++j) {
+                const int e = 2 * (j * 256 + tid);
+                const int co = e / 108, r = e - co * 108;
+                wv[j][0] = wv[j][1] = 0.f;
+                if (e < G::NW && co < Co) ld_w2(Wt + ((int64_t)co * Ci + c0) * 27 + r, wv[j]);
+            }
         }
     };
     auto stash = [&]() {
@@ -247,13 +271,14 @@ __global__ void __launch_bounds__(256) conv_mfma_kernel(int Ci, int Co, int D, i
             const int e = j * 256 + tid;
             if (e < G::NX4) *reinterpret_cast<f32x4 *>(&xs[4 * e]) = xin[j];
         }
+        if (!WALL) {
 #pragma unroll
-        for (int j = 0; j < G::WB; ++j) {
-            const int e = 2 * (j * 256 + tid);
-            const int co = e / 108, r = e - co * 108;
-            if (e < G::NW) {
-                ws[co * G::WROW + r] = wv[j][0];
-                ws[co * G::WROW + r + 1] = wv[j][1];
+            for (int j = 0; j < G::WB; ++j) {
+                const int e = 2 * (j * 256 + tid);
+                if (e < G::NW) {
+                    ws[e] = wv[j][0];
+                    ws[e + 1] = wv[j][1];
+                }
             }
         }
     };
@@ -268,13 +293,13 @@ __global__ void __launch_bounds__(256) conv_mfma_kernel(int Ci, int Co, int D, i
         stash();
         __syncthreads();
         if (k + 1 < K) fetch(k + 1);
-        const float *wq = ws + kq * 27 + (lane & 15) * G::WROW;
+        const float *wq = ws + (lane & 15) * wrow + (WALL ? 4 * (k % nc) + kq : kq) * 27;
 #pragma unroll 9
         for (int tap = 0; tap < 27; ++tap) {
             const int toff = ((tap / 9) * PH + (tap / 3) % 3) * PWA + tap % 3;
             float a[NT];
 #pragma unroll
-            for (int n = 0; n < NT; ++n) a[n] = wq[n * 16 * G::WROW + tap];
+            for (int n = 0; n < NT; ++n) a[n] = wq[n * 16 * wrow + tap];
 #pragma unroll
             for (int m = 0; m < MT; ++m) {
                 const float bv = xs[vb[m] + toff];
@@ -1139,10 +1164,20 @@ int conv_mfma_launch(int B, int Ci, int Co, int D, int H, int W, const void *X,
     const int T = ((OD + TD - 1) / TD) * th * tw;
     const int npb = T >= 64 ? 4 : (T >= 16 ? 2 : 1);
     const dim3 grid((unsigned)((T + npb - 1) / npb), (unsigned)B);
+    // All weights in LDS at once when they fit (ConvTile::WALL floats).
+    const bool wall = (int64_t)nt * 16 * (27 * Ci + 1) <= 4096;
 #define TDB_CONV_MFMA(NT_)                                                                         \
-    hipLaunchKernelGGL((conv_mfma_kernel<WT, TD, TH, TW, MT, NT_>), grid, dim3(256), 0, s, Ci, Co, D, \
-                       H, W, th, tw, T, npb, (const float *)X, (const WT *)Wt,                     \
-                       (const float *)bias, relu, (float *)Y)
+    do {                                                                                           \
+        if (wall)                                                                                  \
+            hipLaunchKernelGGL((conv_mfma_kernel<WT, TD, TH, TW, MT, NT_, true>), grid, dim3(256), \
+                               0, s, Ci, Co, D, H, W, th, tw, T, npb, (const float *)X,            \
+                               (const WT *)Wt, (const float *)bias, relu, (float *)Y);             \
+        else                                                                                       \
+            hipLaunchKernelGGL((conv_mfma_kernel<WT, TD, TH, TW, MT, NT_, false>), grid,           \
+                               dim3(256), 0, s, Ci, Co, D, H, W, th, tw, T, npb,                   \
+                               (const float *)X, (const WT *)Wt, (const float *)bias, relu,        \
+                               (float *)Y);                                                        \
+    } while (0)
     switch (nt) {
     case 1: TDB_CONV_MFMA(1); break;
     case 2: TDB_CONV_MFMA(2); break;
@@ -1281,7 +1316,7 @@ int nn_conv3d_s2_fwd(int dtype, int B, int Ci, int Co, int D, int H, int W, cons
         return tdb_set_error(DB_EINVAL, "nn_conv3d_s2_fwd: bad arguments");
     const hipStream_t s = static_cast<hipStream_t>(stream);
     if (pair <= 1 && Ci % 4 == 0 && W % 4 == 0 && (uintptr_t)X % 16 == 0 && Co <= 64 &&
-        B <= 65535) {
+        B <= 65535 && (int64_t)D * H * W * 4 < ((int64_t)1 << 31)) {
         const int e = conv_fwd_mfma(pair == 0, B, Ci, Co, D, H, W, X, Wt, bias, relu, Y, s);
         if (e <= 0) return e;                     // launched (or failed); > 0: shape not covered
     }
