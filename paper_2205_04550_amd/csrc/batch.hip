@@ -35,6 +35,7 @@ constexpr int kTile = 4;
 constexpr int kXcd = 8;
 constexpr int kBatchThreads = 1024;
 constexpr int kQueryChunk = 256;   // queries whose counters share one block's LDS
+constexpr int kStageBatch = 8;     // slab-staging loads in flight per thread
 
 // ceil(2^32 / d) for d >= 2 (d = 1 is handled by the caller: it would need 2^32).
 // floor(r * M / 2^32) == r / d whenever r * d < 2^32, which the host
@@ -103,30 +104,43 @@ __device__ __forceinline__ void count_rows4(uint32_t (&acc)[16], const uint32_t 
                                             uint32_t nyr, uint32_t M, int zlo, int y0, int zs0,
                                             int ny, uint32_t mlo, uint32_t mhi, int lane)
 {
-    for (uint32_t r = lane; r < nr; r += 64) {
-        const uint32_t zr = div_magic(r, nyr, M);
-        const int z = zlo + (int)zr;
-        const int y = y0 + (int)(r - zr * nyr);
-        const int gw = (z * ny + y) * 4;
-        const int lw = ((z - zs0) * ny + y) * 4;
-        const u32x4 qa = *reinterpret_cast<const u32x4 *>(Q0 + gw);
-        const u32x4 qb = *reinterpret_cast<const u32x4 *>(Q1 + gw);
+    // Two rows per lane per pass: both rows' query loads (L2) are issued before either
+    // row is counted; a second row past nr loads row 0 of the box and is not counted.
+    for (uint32_t r0 = lane; r0 < nr; r0 += 128) {
+        u32x4 qa[2], qb[2];
+        int lw[2];
 #pragma unroll
-        for (int s = 0; s < kTile; ++s) {
-            const u32x4 da = *reinterpret_cast<const u32x4 *>(D + (2 * s) * slab_w + lw);
-            const u32x4 db = *reinterpret_cast<const u32x4 *>(D + (2 * s + 1) * slab_w + lw);
+        for (int u = 0; u < 2; ++u) {
+            const uint32_t r = r0 + 64 * u < nr ? r0 + 64 * u : 0u;
+            const uint32_t zr = div_magic(r, nyr, M);
+            const int z = zlo + (int)zr;
+            const int y = y0 + (int)(r - zr * nyr);
+            const int gw = (z * ny + y) * 4;
+            lw[u] = ((z - zs0) * ny + y) * 4;
+            qa[u] = *reinterpret_cast<const u32x4 *>(Q0 + gw);
+            qb[u] = *reinterpret_cast<const u32x4 *>(Q1 + gw);
+        }
+        const bool live1 = r0 + 64 < nr;
 #pragma unroll
-            for (int w = W0; w <= W1; ++w) {
-                const uint32_t dwa = da[w], dwb = db[w];
-                acc[4 * s + 0] += popc(qa[w] & dwa);
-                acc[4 * s + 1] += popc(qb[w] & dwb);
-                if (w == W0 || w == W1) {
-                    const uint32_t m = (W0 == W1) ? (mlo & mhi) : (w == W0 ? mlo : mhi);
-                    acc[4 * s + 2] += popc(dwa & m);
-                    acc[4 * s + 3] += popc(dwb & m);
-                } else {
-                    acc[4 * s + 2] += popc(dwa);
-                    acc[4 * s + 3] += popc(dwb);
+        for (int u = 0; u < 2; ++u) {
+            if (u == 1 && !live1) break;
+#pragma unroll
+            for (int s = 0; s < kTile; ++s) {
+                const u32x4 da = *reinterpret_cast<const u32x4 *>(D + (2 * s) * slab_w + lw[u]);
+                const u32x4 db = *reinterpret_cast<const u32x4 *>(D + (2 * s + 1) * slab_w + lw[u]);
+#pragma unroll
+                for (int w = W0; w <= W1; ++w) {
+                    const uint32_t dwa = da[w], dwb = db[w];
+                    acc[4 * s + 0] = popc_acc(qa[u][w] & dwa, acc[4 * s + 0]);
+                    acc[4 * s + 1] = popc_acc(qb[u][w] & dwb, acc[4 * s + 1]);
+                    if (w == W0 || w == W1) {
+                        const uint32_t m = (W0 == W1) ? (mlo & mhi) : (w == W0 ? mlo : mhi);
+                        acc[4 * s + 2] = popc_acc(dwa & m, acc[4 * s + 2]);
+                        acc[4 * s + 3] = popc_acc(dwb & m, acc[4 * s + 3]);
+                    } else {
+                        acc[4 * s + 2] = popc_acc(dwa, acc[4 * s + 2]);
+                        acc[4 * s + 3] = popc_acc(dwb, acc[4 * s + 3]);
+                    }
                 }
             }
         }
@@ -191,15 +205,30 @@ __global__ void __launch_bounds__(kBatchThreads) batch_lds_kernel(
         __syncthreads();  // the previous slab is consumed; counters are zeroed
         // Stage the tile's slab: kTile entries x 2 masks x `words` words.
         if ((plane_w & 3) == 0) {
+            // kStageBatch loads per thread in flight before any is stored.
             const int w4 = words >> 2;
-            for (int i = threadIdx.x; i < kTile * 2 * w4; i += blockDim.x) {
-                const int sm = i / w4;
-                const int j = i - sm * w4;
-                const int s = sm >> 1, m = sm & 1;
-                const int64_t e = ent[s];
-                const u32x4 *g = reinterpret_cast<const u32x4 *>(
-                    planes + e * 2 * (int64_t)Wp + (int64_t)m * Wp + (int64_t)zs0 * plane_w);
-                reinterpret_cast<u32x4 *>(D + sm * slab_w)[j] = load_stream(g + j);
+            const int tot = kTile * 2 * w4;
+            for (int i0 = threadIdx.x; i0 < tot; i0 += kStageBatch * blockDim.x) {
+                u32x4 v[kStageBatch];
+                int dst[kStageBatch];
+#pragma unroll
+                for (int u = 0; u < kStageBatch; ++u) {
+                    const int i = i0 + u * blockDim.x;
+                    const int sm = i / w4;
+                    const int j = i - sm * w4;
+                    const int s = sm >> 1, m = sm & 1;
+                    dst[u] = -1;
+                    if (i < tot) {
+                        const int64_t e = ent[s & (kTile - 1)];
+                        const u32x4 *g = reinterpret_cast<const u32x4 *>(
+                            planes + e * 2 * (int64_t)Wp + (int64_t)m * Wp + (int64_t)zs0 * plane_w);
+                        v[u] = load_stream(g + j);
+                        dst[u] = sm * (slab_w >> 2) + j;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kStageBatch; ++u)
+                    if (dst[u] >= 0) reinterpret_cast<u32x4 *>(D)[dst[u]] = v[u];
             }
         } else {
             for (int i = threadIdx.x; i < kTile * 2 * words; i += blockDim.x) {

@@ -20,6 +20,16 @@ __device__ __forceinline__ u32x4 load_stream(const u32x4 *p)
 
 __device__ __forceinline__ uint32_t popc(uint32_t x) { return (uint32_t)__builtin_popcount(x); }
 
+// acc + popcount(x) as the single instruction the hardware has for it. Written out
+// because the compiler otherwise pairs two popcounts into one three-way add, one
+// instruction more per pair on count-bound loops.
+__device__ __forceinline__ uint32_t popc_acc(uint32_t x, uint32_t acc)
+{
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
 __device__ __forceinline__ uint32_t popc_and4(u32x4 a, u32x4 b)
 {
     return popc(a.x & b.x) + popc(a.y & b.y) + popc(a.z & b.z) + popc(a.w & b.w);
