@@ -90,6 +90,20 @@ __device__ __forceinline__ uint32_t roi_word_mask(const int32_t *r, int w, int n
     return m;
 }
 
+constexpr int kPackBatch = 4;
+
+// Bit 0 (FLAIR) and bit 1 (T1Gd) of the four label bytes of x as two nibbles
+// (byte i -> bit i). Bytes 0..2 by one 24-bit multiply: with a = b0 + b1 2^8 +
+// b2 2^16 (each 0 or 1), a * (2^16 + 2^9 + 2^2) holds b0, b1, b2 at bits 16..18,
+// every other partial product on a distinct bit outside them (no carries); byte
+// 3 by a shift.
+__device__ __forceinline__ void label_nibbles(uint32_t x, uint32_t &n0, uint32_t &n1)
+{
+    const uint32_t a = x & 0x00010101u, b = (x >> 1) & 0x00010101u;
+    n0 = ((__umul24(a, 0x010204u) >> 16) & 7u) | ((x >> 21) & 8u);
+    n1 = ((__umul24(b, 0x010204u) >> 16) & 7u) | ((x >> 22) & 8u);
+}
+
 // grid (kQueryParts, nq): labels uint8 [nq][V] -> packed [nq][2][Wp] and one
 // QueryPart per block: the block's mask counts, the row range of its set bits
 // and the FLAIR moments (for the row-box scan and the centre-of-mass key).
@@ -111,47 +125,59 @@ __global__ void __launch_bounds__(256) pack_query_kernel(const uint8_t *__restri
     uint32_t n0 = 0, n1 = 0;
     int zlo = INT_MAX, zhi = -1, ylo = INT_MAX, yhi = -1;
     uint64_t sx = 0, sy = 0, sz = 0;
-    for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < Wp; w += gridDim.x * blockDim.x) {
-        uint32_t b0 = 0, b1 = 0;
-        if (w < W) {
-            u32x4 v[2];
-            v[0] = lab[2 * (int64_t)w];
-            v[1] = lab[2 * (int64_t)w + 1];
+    // Two lanes per packed word, 16 label bytes each, so one load instruction covers
+    // 1 KiB of contiguous labels; kPackBatch words per lane pair and pass, all their
+    // loads issued first. The even lane assembles the word from both halves.
+    const int half = threadIdx.x & 1;
+    const int stride = gridDim.x * (blockDim.x >> 1);
+    for (int w0 = blockIdx.x * (blockDim.x >> 1) + (threadIdx.x >> 1); w0 < Wp;
+         w0 += kPackBatch * stride) {
+        u32x4 vb[kPackBatch];
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const uint32_t x = v[h][e];
-#pragma unroll
-                    for (int by = 0; by < 4; ++by) {
-                        const int bit = 16 * h + 4 * e + by;
-                        b0 |= ((x >> (8 * by)) & 1u) << bit;
-                        b1 |= ((x >> (8 * by + 1)) & 1u) << bit;
-                    }
-                }
-            if (r) {
-                const uint32_t m = roi_word_mask(r, w, nxw, ny);
-                b0 &= m;
-                b1 &= m;
-            }
-            if (b0 | b1) {
-                const int row = w / nxw;
-                const int wx = w - row * nxw;
-                const int z = row / ny, y = row - z * ny;
-                zlo = min(zlo, z);
-                zhi = max(zhi, z);
-                ylo = min(ylo, y);
-                yhi = max(yhi, y);
-                const uint32_t c = popc(b0);
-                sx += (uint64_t)(32u * (uint32_t)wx) * c + bit_position_sum(b0);
-                sy += (uint64_t)y * c;
-                sz += (uint64_t)z * c;
-            }
+        for (int u = 0; u < kPackBatch; ++u) {
+            const int w = w0 + u * stride;
+            vb[u] = (u32x4){0u, 0u, 0u, 0u};
+            if (w < W) vb[u] = load_stream(lab + 2 * (int64_t)w + half);
         }
-        o[w] = b0;
-        o[Wp + w] = b1;
-        n0 += popc(b0);
-        n1 += popc(b1);
+#pragma unroll
+        for (int u = 0; u < kPackBatch; ++u) {
+            const int w = w0 + u * stride;
+            uint32_t h0 = 0, h1 = 0;   // this lane's 16 bits of each mask
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                uint32_t f4, t4;
+                label_nibbles(vb[u][e], f4, t4);
+                h0 |= f4 << (4 * e);
+                h1 |= t4 << (4 * e);
+            }
+            const uint32_t g0 = __shfl_down(h0, 1, 64), g1 = __shfl_down(h1, 1, 64);
+            if (half || w >= Wp) continue;
+            uint32_t b0 = h0 | (g0 << 16), b1 = h1 | (g1 << 16);
+            if (w < W) {
+                if (r) {
+                    const uint32_t m = roi_word_mask(r, w, nxw, ny);
+                    b0 &= m;
+                    b1 &= m;
+                }
+                if (b0 | b1) {
+                    const int row = w / nxw;
+                    const int wx = w - row * nxw;
+                    const int z = row / ny, y = row - z * ny;
+                    zlo = min(zlo, z);
+                    zhi = max(zhi, z);
+                    ylo = min(ylo, y);
+                    yhi = max(yhi, y);
+                    const uint32_t c = popc(b0);
+                    sx += (uint64_t)(32u * (uint32_t)wx) * c + bit_position_sum(b0);
+                    sy += (uint64_t)y * c;
+                    sz += (uint64_t)z * c;
+                }
+            }
+            o[w] = b0;
+            o[Wp + w] = b1;
+            n0 += popc(b0);
+            n1 += popc(b1);
+        }
     }
     n0 = wave_sum(n0);
     n1 = wave_sum(n1);
