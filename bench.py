@@ -372,9 +372,11 @@ HASH_GAMMA = 3.0   # weight of the Bi-half layer's pull of latents towards their
 VAE_BETA = 1e-5    # KL weight against the per-voxel mean MSE (about 2.6 against a voxel sum)
 
 
-def rerank_bytes(db, lab_d, cand, gen) -> float:
+def rerank_bytes(db, lab_d, cand, gen, lines: bool = False) -> float:
     """Database bytes the candidate-scoring kernel reads: per (query, candidate), the rows
-    inside both the query's and the candidate's row box, 2 masks (measurement bookkeeping)."""
+    inside both the query's and the candidate's row box, 2 masks (measurement bookkeeping).
+    lines=True counts the 128-byte cache lines those rows touch instead (the rows of one
+    z-slice are contiguous, so a slice's run starts and ends inside a line)."""
     import torch
     nxw = gen.nx // 32
     rows = ((lab_d & 3).reshape(lab_d.shape[0], gen.nz, gen.ny, gen.nx).amax(dim=3) != 0)
@@ -388,7 +390,13 @@ def rerank_bytes(db, lab_d, cand, gen) -> float:
     qy1 = torch.where(yany, ar_y + 1, -big).amax(1)
     eb = db.boxes[cand.to(torch.int64)].to(torch.int64)           # [nq][nc][4]
     dz = (torch.minimum(eb[..., 1], qz1[:, None]) - torch.maximum(eb[..., 0], qz0[:, None])).clamp(min=0)
-    dy = (torch.minimum(eb[..., 3], qy1[:, None]) - torch.maximum(eb[..., 2], qy0[:, None])).clamp(min=0)
+    y0 = torch.maximum(eb[..., 2], qy0[:, None])
+    y1 = torch.minimum(eb[..., 3], qy1[:, None])
+    if lines:
+        rb = nxw * 4
+        ln = torch.where(y1 > y0, (y1 * rb + 127) // 128 - (y0 * rb) // 128, torch.zeros_like(y0))
+        return float((dz * ln).sum()) * 2 * 128
+    dy = (y1 - y0).clamp(min=0)
     return float((dz * dy).sum()) * 2 * nxw * 4
 
 
@@ -890,15 +898,23 @@ def bench_sparse(args, db, gen, n, build_s) -> int:
         wsc = torch.empty(LIB_ws_com(db, nqc, n_cand), dtype=torch.uint8, device="cuda")
         o = db.query_com(held_d, n_cand, ks, ws=wsc)
         torch.cuda.synchronize()
+        db.profile(True)
+        db.profile_read()
         t0 = time.perf_counter()
         o = db.query_com(held_d, n_cand, ks, ws=wsc, out=o)
         torch.cuda.synchronize()
         el_c = time.perf_counter() - t0
+        rr_ms, rr_n = db.profile_read()
+        db.profile(False)
         got = o[0].cpu().numpy()
         topn = {f"top{t}": float(np.mean([best[q] in got[q, :t] for q in range(nqc)]))
                 for t in (1, 5, 15)}
+        rr_alg = rerank_bytes(db, held_d, o[3], gen)
+        rr_lines = rerank_bytes(db, held_d, o[3], gen, lines=True)
         com[f"n_cand_{n_cand}"] = {"queries_per_s": nqc / el_c, "ms_per_query": el_c * 1e3 / nqc,
-                                   **topn}
+                                   **topn, "rerank_score_ms": rr_ms / max(1, rr_n),
+                                   "rerank_algorithmic_bytes": rr_alg,
+                                   "rerank_line_bytes": rr_lines}
         log(f"COM prefilter {n_cand}: {nqc / el_c:.0f} q/s, Top-1/5/15 {topn['top1']:.3f} / "
             f"{topn['top5']:.3f} / {topn['top15']:.3f}")
         del wsc

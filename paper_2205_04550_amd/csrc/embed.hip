@@ -417,7 +417,10 @@ constexpr int kRerankMaxCand = 1024;
 constexpr int kRC = 2;                 // candidates per wave
 constexpr int kRerankPerBlock = 4 * kRC;   // candidates scored per block (4 waves)
 
-// grid (ceil(nc / kRerankPerBlock), nq), 256 threads (4 waves). Each wave scores
+// 1-D grid of nbq * 8 * ceil(nq / 8) blocks (nbq = ceil(nc / kRerankPerBlock)),
+// 256 threads (4 waves). Blocks go to the 8 XCDs round-robin; the mapping below
+// gives every block of query q to XCD q % 8, so the query's rows are fetched into
+// one L2 only. Each wave scores
 // kRC candidates of query q at once: lanes sweep the rows where the query's row
 // box meets the candidates' stored row boxes (outside either box one side is
 // zero and adds nothing), AND + popcount against each candidate's planes; the
@@ -432,9 +435,12 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
                                                            const int32_t *__restrict__ cand, int nc,
                                                            uint64_t *__restrict__ ws_s,
                                                            int32_t *__restrict__ ws_i,
-                                                           uint32_t *__restrict__ ws_I)
+                                                           uint32_t *__restrict__ ws_I, int nq,
+                                                           int nbq)
 {
-    const int q = blockIdx.y;
+    const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
+    const int q = (slot / nbq) * 8 + xcd, qb = slot % nbq;
+    if (q >= nq) return;                       // whole block, before any barrier
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t *Q0 = qpack + (int64_t)q * 2 * Wp, *Q1 = Q0 + Wp;
     const int32_t *b = box + 4 * q;
@@ -443,7 +449,7 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
     // kRC candidates per wave: each query row is loaded once per group, and the
     // group sweeps the union of its members' boxes (each clipped to the query's);
     // a member reads only the rows inside its own box.
-    const int c0 = blockIdx.x * kRerankPerBlock + wave * kRC;
+    const int c0 = qb * kRerankPerBlock + wave * kRC;
     if (c0 >= nc) return;   // a whole wave leaves; no block barrier below
     const uint32_t *D0[kRC], *D1[kRC];
     int z0[kRC], z1[kRC], y0[kRC], y1[kRC];
@@ -1083,10 +1089,11 @@ hipError_t launch_rerank_score(const db_t *db, int nq, const uint32_t *qpack, co
     uint64_t *ws_s = static_cast<uint64_t *>(ws);
     int32_t *ws_i = reinterpret_cast<int32_t *>(ws_s + (size_t)nq * nc);
     uint32_t *ws_I = reinterpret_cast<uint32_t *>(ws_i + (size_t)nq * nc);
-    hipLaunchKernelGGL(rerank_score_kernel,
-                       dim3((unsigned)((nc + kRerankPerBlock - 1) / kRerankPerBlock), (unsigned)nq),
-                       dim3(256), 0, s, db->planes, db->popcnt, db->box, g.Wp, g.nxw, g.ny, qpack,
-                       acnt, box, cand, nc, ws_s, ws_i, ws_I);
+    const int nbq = (nc + kRerankPerBlock - 1) / kRerankPerBlock;
+    const int64_t blocks = (int64_t)nbq * 8 * ((nq + 7) / 8);
+    hipLaunchKernelGGL(rerank_score_kernel, dim3((unsigned)blocks), dim3(256), 0, s, db->planes,
+                       db->popcnt, db->box, g.Wp, g.nxw, g.ny, qpack, acnt, box, cand, nc, ws_s,
+                       ws_i, ws_I, nq, nbq);
     return hipGetLastError();
 }
 
