@@ -847,20 +847,28 @@ def bench_sparse(args, db, gen, n, build_s) -> int:
     # (measurement bookkeeping from the stored boxes and the query's set rows).
     nxw = gen.nx // 32
     eb = db.boxes[:n].to(torch.int64)
-    rows_read = []
+    rows_read, lines_read = [], []
+    rb = nxw * 4
     for q in range(nq):
         rows = (lab_d[q] & 3).reshape(gen.nz, gen.ny, gen.nx).amax(dim=2) != 0
         zi = torch.nonzero(rows.any(dim=1)).flatten()
         yi = torch.nonzero(rows.any(dim=0)).flatten()
         if zi.numel() == 0:
             rows_read.append(0)
+            lines_read.append(0)
             continue
         qz0, qz1, qy0, qy1 = int(zi.min()), int(zi.max()) + 1, int(yi.min()), int(yi.max()) + 1
         dz = (torch.minimum(eb[:, 1], torch.tensor(qz1)) - torch.maximum(eb[:, 0], torch.tensor(qz0))).clamp(min=0)
-        dy = (torch.minimum(eb[:, 3], torch.tensor(qy1)) - torch.maximum(eb[:, 2], torch.tensor(qy0))).clamp(min=0)
+        y0 = torch.maximum(eb[:, 2], torch.tensor(qy0))
+        y1 = torch.minimum(eb[:, 3], torch.tensor(qy1))
+        dy = (y1 - y0).clamp(min=0)
         rows_read.append(int((dz * dy).sum()))
+        # the 128-byte lines those rows touch (a z-slice's run starts and ends inside one)
+        ln = torch.where(y1 > y0, (y1 * rb + 127) // 128 - (y0 * rb) // 128, torch.zeros_like(y0))
+        lines_read.append(int((dz * ln).sum()))
     rows_read = np.array(rows_read, dtype=np.float64)
-    bytes_read = rows_read * 2 * nxw * 4
+    bytes_read = rows_read * 2 * rb
+    line_bytes = np.array(lines_read, dtype=np.float64) * 2 * 128
     for _ in range(args.warmup):
         for q in range(min(nq, 8)):
             db.query_sparse(lab_d[q], k, out=out_s, ws=ws)
@@ -931,6 +939,7 @@ def bench_sparse(args, db, gen, n, build_s) -> int:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "box_scan_kernel", "kernel_avg_ms": kern_ms,
                      "bytes_read_per_launch_mean": float(bytes_read.mean()),
+                     "line_bytes_per_launch_mean": float(line_bytes.mean()),
                      "dense_algorithmic_bytes_per_launch": alg},
         "parity": {"sparse_equals_dense_on_all_queries": bool(same)},
         "com_prefilter": com, "cpu_baseline": None, "build_s": build_s,
