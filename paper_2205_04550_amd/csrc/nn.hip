@@ -245,13 +245,15 @@ __global__ void __launch_bounds__(256) conv_mfma_kernel(int Ci, int Co, int D, i
         const int tw = t % tiles_w, th = (t / tiles_w) % tiles_h, td = t / (tiles_w * tiles_h);
         const int iz0 = 2 * td * TD - 1, iy0 = 2 * th * TH - 1, ix0 = 2 * tw * TW - 4;
         const float *org = Xb + (int64_t)c0 * isp + (int64_t)iz0 * HW + iy0 * W + ix0;
+        // Branch-free: an element outside the volume loads the sample's first group
+        // (always valid) and is replaced by zeros.
 #pragma unroll
         for (int j = 0; j < G::XB; ++j) {
             const int z = pk[j] & 0xff, y = (pk[j] >> 8) & 0xff, seg = (pk[j] >> 16) & 0xff;
-            xin[j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-            if (pk[j] >= 0 && (unsigned)(iz0 + z) < (unsigned)D &&
-                (unsigned)(iy0 + y) < (unsigned)H && (unsigned)(ix0 + 4 * seg) < (unsigned)W)
-                xin[j] = *reinterpret_cast<const f32x4 *>(org + rel[j]);
+            const bool ok = pk[j] >= 0 && (unsigned)(iz0 + z) < (unsigned)D &&
+                            (unsigned)(iy0 + y) < (unsigned)H && (unsigned)(ix0 + 4 * seg) < (unsigned)W;
+            const f32x4 t = *reinterpret_cast<const f32x4 *>(ok ? org + rel[j] : Xb);
+            xin[j] = ok ? t : (f32x4){0.f, 0.f, 0.f, 0.f};
         }
         if (!WALL) {
             // Weights in pairs (r even; 108 per output channel and chunk, so a pair never
@@ -294,7 +296,7 @@ __global__ void __launch_bounds__(256) conv_mfma_kernel(int Ci, int Co, int D, i
         __syncthreads();
         if (k + 1 < K) fetch(k + 1);
         const float *wq = ws + (lane & 15) * wrow + (WALL ? 4 * (k % nc) + kq : kq) * 27;
-#pragma unroll 9
+#pragma unroll
         for (int tap = 0; tap < 27; ++tap) {
             const int toff = ((tap / 9) * PH + (tap / 3) % 3) * PWA + tap % 3;
             float a[NT];
