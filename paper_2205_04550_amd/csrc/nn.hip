@@ -628,7 +628,7 @@ __device__ __forceinline__ f32x4 ld4_w(const uint16_t *p)
                    __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u)};
 }
 
-template <class WT>
+template <class WT, bool B_KN>
 __global__ void __launch_bounds__(256) linear_mfma_kernel(int M, int N, int K,
                                                           const float *__restrict__ A,
                                                           const WT *__restrict__ Wt,
@@ -640,8 +640,10 @@ __global__ void __launch_bounds__(256) linear_mfma_kernel(int M, int N, int K,
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1, h = lane >> 5, r32 = lane & 31;
     const int m0 = blockIdx.y * kMM, n0 = blockIdx.x * kMM;
-    // Staging: 64 rows x 8 float4 per operand, two of each per thread.
+    // Staging: 64 rows x 8 float4 per operand, two of each per thread. With B_KN the
+    // weights are [K][N] (the input gradient dY W): four consecutive n of one k.
     const int srow = tid >> 3, sk = (tid & 7) * 4;
+    const int bk = tid >> 4, bq = (tid & 15) * 4;
     f32x4 pa[2], pb[2];
     auto fetch = [&](int k0) {
 #pragma unroll
@@ -649,7 +651,14 @@ __global__ void __launch_bounds__(256) linear_mfma_kernel(int M, int N, int K,
             const int row = srow + 32 * j, k = k0 + sk;
             const int m = m0 + row, n = n0 + row;
             pa[j] = (m < M && k < K) ? ld4_w(A + (int64_t)m * K + k) : (f32x4){0.f, 0.f, 0.f, 0.f};
-            pb[j] = (n < N && k < K) ? ld4_w(Wt + (int64_t)n * K + k) : (f32x4){0.f, 0.f, 0.f, 0.f};
+            if (B_KN) {
+                const int kb = k0 + bk + 16 * j, nb = n0 + bq;
+                pb[j] = (kb < K && nb < N) ? ld4_w(Wt + (int64_t)kb * N + nb)
+                                           : (f32x4){0.f, 0.f, 0.f, 0.f};
+            } else {
+                pb[j] = (n < N && k < K) ? ld4_w(Wt + (int64_t)n * K + k)
+                                         : (f32x4){0.f, 0.f, 0.f, 0.f};
+            }
         }
     };
     f32x16 acc;
@@ -661,7 +670,12 @@ __global__ void __launch_bounds__(256) linear_mfma_kernel(int M, int N, int K,
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             *reinterpret_cast<f32x4 *>(&As[(srow + 32 * j) * kMPad + sk]) = pa[j];
-            *reinterpret_cast<f32x4 *>(&Bs[(srow + 32 * j) * kMPad + sk]) = pb[j];
+            if (B_KN) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) Bs[(bq + e) * kMPad + bk + 16 * j] = pb[j][e];
+            } else {
+                *reinterpret_cast<f32x4 *>(&Bs[(srow + 32 * j) * kMPad + sk]) = pb[j];
+            }
         }
         __syncthreads();
         if (k0 + kMK < K) fetch(k0 + kMK);
@@ -1429,11 +1443,11 @@ int nn_linear_fwd(int dtype, int B, int In, int Out, const void *X, const void *
     const size_t wal = pair == 0 ? 8 : 16;
     const bool vec = In % 4 == 0 && (uintptr_t)X % 16 == 0 && (uintptr_t)Wt % wal == 0;
     if (pair == 0 && vec)
-        hipLaunchKernelGGL(linear_mfma_kernel<uint16_t>, mgrid, dim3(256), 0, s, B, Out, In,
+        hipLaunchKernelGGL((linear_mfma_kernel<uint16_t, false>), mgrid, dim3(256), 0, s, B, Out, In,
                            (const float *)X, (const uint16_t *)Wt, (const float *)bias, relu,
                            (float *)Y);
     else if (pair == 1 && vec)
-        hipLaunchKernelGGL(linear_mfma_kernel<float>, mgrid, dim3(256), 0, s, B, Out, In,
+        hipLaunchKernelGGL((linear_mfma_kernel<float, false>), mgrid, dim3(256), 0, s, B, Out, In,
                            (const float *)X, (const float *)Wt, (const float *)bias, relu,
                            (float *)Y);
     else if (pair == 0)
@@ -1459,7 +1473,20 @@ int nn_linear_bwd_data(int dtype, int B, int In, int Out, const void *dY, const 
         return tdb_set_error(DB_EINVAL, "nn_linear_bwd_data: bad arguments");
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const dim3 grid((In + kLN - 1) / kLN, (B + kLM - 1) / kLM);
-    if (pair == 0)
+    const dim3 mgrid((In + kMM - 1) / kMM, (B + kMM - 1) / kMM);
+    // Matrix-core path: dY rows (K = Out) and W rows (N = In) in groups of four.
+    const size_t wal = pair == 0 ? 8 : 16;
+    const bool vec = In % 4 == 0 && Out % 4 == 0 && (uintptr_t)dY % 16 == 0 &&
+                     (uintptr_t)Wt % wal == 0;
+    if (pair == 0 && vec)
+        hipLaunchKernelGGL((linear_mfma_kernel<uint16_t, true>), mgrid, dim3(256), 0, s, B, In, Out,
+                           (const float *)dY, (const uint16_t *)Wt, (const float *)nullptr, 0,
+                           (float *)dX);
+    else if (pair == 1 && vec)
+        hipLaunchKernelGGL((linear_mfma_kernel<float, true>), mgrid, dim3(256), 0, s, B, In, Out,
+                           (const float *)dY, (const float *)Wt, (const float *)nullptr, 0,
+                           (float *)dX);
+    else if (pair == 0)
         hipLaunchKernelGGL((linear_gemm_kernel<float, uint16_t, true>), grid, dim3(256), 0, s, B, In,
                            Out, (const float *)dY, (const uint16_t *)Wt, (const float *)nullptr, 0,
                            (float *)dX);

@@ -362,3 +362,24 @@ def test_encode_labels_matches_two_step_encode():
             z1 = model.encode_labels(lab, mask=mask)
             z2 = model.encode(nn.meanpool_labels(lab, mask=mask))
         assert _rel(z1.double().cpu(), z2.double().cpu()) < 1e-4, mask
+
+
+@pytest.mark.parametrize("shape", [(70, 4100, 132), (32, 4096, 512), (32, 512, 4096), (5, 8, 4)])
+def test_linear_input_gradient_matrix_core(shape):
+    """Input gradient dY W of the linear layer on the FP32 matrix cores (In, Out % 4 == 0),
+    ragged tiles in every dimension, BF16 and float weights, against the float64 product."""
+    need_gpu()
+    from paper_2205_04550_amd import nn
+    B, In, Out = shape
+    g = torch.Generator().manual_seed(B * 7 + In + Out)
+    x64 = torch.randn(B, In, generator=g, dtype=torch.float64)
+    w64 = torch.randn(Out, In, generator=g, dtype=torch.float64) * (1.0 / math.sqrt(Out))
+    gy64 = torch.randn(B, Out, generator=g, dtype=torch.float64)
+    for wdt in (torch.bfloat16, torch.float32):
+        wc = w64.to(wdt)
+        say(f"linear dX mfma {shape} {wdt}")
+        x = x64.to("cuda", torch.float32).requires_grad_(True)
+        y = nn.Linear.apply(x, w64.cuda().float(), None, wc.cuda(), False)
+        (gx,) = torch.autograd.grad(y, (x,), gy64.to("cuda", torch.float32))
+        ref = gy64 @ wc.to(torch.float64)
+        assert _rel(_cpu64(gx), ref) < 2e-5, (shape, wdt)
