@@ -40,6 +40,18 @@ __device__ __forceinline__ uint32_t popc4(u32x4 a)
     return popc(a.x) + popc(a.y) + popc(a.z) + popc(a.w);
 }
 
+// Bit 0 (FLAIR) and bit 1 (T1Gd) of the four label bytes of x as two nibbles
+// (byte i -> bit i). Bytes 0..2 by one 24-bit multiply: with a = b0 + b1 2^8 +
+// b2 2^16 (each 0 or 1), a * (2^16 + 2^9 + 2^2) holds b0, b1, b2 at bits 16..18,
+// every other partial product on a distinct bit outside them (no carries); byte
+// 3 by a shift.
+__device__ __forceinline__ void label_nibbles(uint32_t x, uint32_t &n0, uint32_t &n1)
+{
+    const uint32_t a = x & 0x00010101u, b = (x >> 1) & 0x00010101u;
+    n0 = ((__umul24(a, 0x010204u) >> 16) & 7u) | ((x >> 21) & 8u);
+    n1 = ((__umul24(b, 0x010204u) >> 16) & 7u) | ((x >> 22) & 8u);
+}
+
 // Sum over the 64 lanes of a wave; every lane receives the total.
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 {

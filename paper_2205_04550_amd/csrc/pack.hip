@@ -92,17 +92,85 @@ __device__ __forceinline__ uint32_t roi_word_mask(const int32_t *r, int w, int n
 
 constexpr int kPackBatch = 4;
 
-// Bit 0 (FLAIR) and bit 1 (T1Gd) of the four label bytes of x as two nibbles
-// (byte i -> bit i). Bytes 0..2 by one 24-bit multiply: with a = b0 + b1 2^8 +
-// b2 2^16 (each 0 or 1), a * (2^16 + 2^9 + 2^2) holds b0, b1, b2 at bits 16..18,
-// every other partial product on a distinct bit outside them (no carries); byte
-// 3 by a shift.
-__device__ __forceinline__ void label_nibbles(uint32_t x, uint32_t &n0, uint32_t &n1)
-{
-    const uint32_t a = x & 0x00010101u, b = (x >> 1) & 0x00010101u;
-    n0 = ((__umul24(a, 0x010204u) >> 16) & 7u) | ((x >> 21) & 8u);
-    n1 = ((__umul24(b, 0x010204u) >> 16) & 7u) | ((x >> 22) & 8u);
-}
+
+// A block's share of a query's statistics: mask counts, the row range of set bits
+// and the FLAIR moments (sum of x, y, z over its bits), summed over packed words.
+struct PartAcc {
+    uint32_t n0 = 0, n1 = 0;
+    int zlo = INT_MAX, zhi = -1, ylo = INT_MAX, yhi = -1;
+    uint64_t sx = 0, sy = 0, sz = 0;
+
+    __device__ void add(uint32_t b0, uint32_t b1, int w, int nxw, int ny)
+    {
+        n0 += popc(b0);
+        n1 += popc(b1);
+        if (b0 | b1) {
+            const int row = w / nxw;
+            const int wx = w - row * nxw;
+            const int z = row / ny, y = row - z * ny;
+            zlo = min(zlo, z);
+            zhi = max(zhi, z);
+            ylo = min(ylo, y);
+            yhi = max(yhi, y);
+            const uint32_t c = popc(b0);
+            sx += (uint64_t)(32u * (uint32_t)wx) * c + bit_position_sum(b0);
+            sy += (uint64_t)y * c;
+            sz += (uint64_t)z * c;
+        }
+    }
+
+    // Block-wide sum (at most 4 waves); thread 0 writes the part.
+    __device__ void write(QueryPart &p)
+    {
+        __shared__ uint32_t rc[4][2];
+        __shared__ int rb[4][4];
+        __shared__ uint64_t rm[4][3];
+        n0 = wave_sum(n0);
+        n1 = wave_sum(n1);
+        zlo = wave_min(zlo);
+        ylo = wave_min(ylo);
+        zhi = wave_max(zhi);
+        yhi = wave_max(yhi);
+        sx = wave_sum64(sx);
+        sy = wave_sum64(sy);
+        sz = wave_sum64(sz);
+        const int wv = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            rc[wv][0] = n0;
+            rc[wv][1] = n1;
+            rb[wv][0] = zlo;
+            rb[wv][1] = zhi;
+            rb[wv][2] = ylo;
+            rb[wv][3] = yhi;
+            rm[wv][0] = sx;
+            rm[wv][1] = sy;
+            rm[wv][2] = sz;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+                n0 += rc[i][0];
+                n1 += rc[i][1];
+                zlo = min(zlo, rb[i][0]);
+                zhi = max(zhi, rb[i][1]);
+                ylo = min(ylo, rb[i][2]);
+                yhi = max(yhi, rb[i][3]);
+                sx += rm[i][0];
+                sy += rm[i][1];
+                sz += rm[i][2];
+            }
+            p.cnt[0] = n0;
+            p.cnt[1] = n1;
+            p.box[0] = zlo;
+            p.box[1] = zhi;
+            p.box[2] = ylo;
+            p.box[3] = yhi;
+            p.mom[0] = sx;
+            p.mom[1] = sy;
+            p.mom[2] = sz;
+        }
+    }
+};
 
 // grid (kQueryParts, nq): labels uint8 [nq][V] -> packed [nq][2][Wp] and one
 // QueryPart per block: the block's mask counts, the row range of its set bits
@@ -115,16 +183,11 @@ __global__ void __launch_bounds__(256) pack_query_kernel(const uint8_t *__restri
                                                          uint32_t *__restrict__ qpack,
                                                          QueryPart *__restrict__ qpart)
 {
-    __shared__ uint32_t rc[4][2];
-    __shared__ int rb[4][4];
-    __shared__ uint64_t rm[4][3];
     const int q = blockIdx.y;
     const u32x4 *lab = reinterpret_cast<const u32x4 *>(labels + (int64_t)q * V);
     uint32_t *o = qpack + (int64_t)q * 2 * Wp;
     const int32_t *r = rois ? rois + 6 * q : nullptr;
-    uint32_t n0 = 0, n1 = 0;
-    int zlo = INT_MAX, zhi = -1, ylo = INT_MAX, yhi = -1;
-    uint64_t sx = 0, sy = 0, sz = 0;
+    PartAcc acc;
     // Two lanes per packed word, 16 label bytes each, so one load instruction covers
     // 1 KiB of contiguous labels; kPackBatch words per lane pair and pass, all their
     // loads issued first. The even lane assembles the word from both halves.
@@ -153,77 +216,17 @@ __global__ void __launch_bounds__(256) pack_query_kernel(const uint8_t *__restri
             const uint32_t g0 = __shfl_down(h0, 1, 64), g1 = __shfl_down(h1, 1, 64);
             if (half || w >= Wp) continue;
             uint32_t b0 = h0 | (g0 << 16), b1 = h1 | (g1 << 16);
-            if (w < W) {
-                if (r) {
-                    const uint32_t m = roi_word_mask(r, w, nxw, ny);
-                    b0 &= m;
-                    b1 &= m;
-                }
-                if (b0 | b1) {
-                    const int row = w / nxw;
-                    const int wx = w - row * nxw;
-                    const int z = row / ny, y = row - z * ny;
-                    zlo = min(zlo, z);
-                    zhi = max(zhi, z);
-                    ylo = min(ylo, y);
-                    yhi = max(yhi, y);
-                    const uint32_t c = popc(b0);
-                    sx += (uint64_t)(32u * (uint32_t)wx) * c + bit_position_sum(b0);
-                    sy += (uint64_t)y * c;
-                    sz += (uint64_t)z * c;
-                }
+            if (w < W && r) {
+                const uint32_t m = roi_word_mask(r, w, nxw, ny);
+                b0 &= m;
+                b1 &= m;
             }
+            if (w < W) acc.add(b0, b1, w, nxw, ny);
             o[w] = b0;
             o[Wp + w] = b1;
-            n0 += popc(b0);
-            n1 += popc(b1);
         }
     }
-    n0 = wave_sum(n0);
-    n1 = wave_sum(n1);
-    zlo = wave_min(zlo);
-    ylo = wave_min(ylo);
-    zhi = wave_max(zhi);
-    yhi = wave_max(yhi);
-    sx = wave_sum64(sx);
-    sy = wave_sum64(sy);
-    sz = wave_sum64(sz);
-    const int wv = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        rc[wv][0] = n0;
-        rc[wv][1] = n1;
-        rb[wv][0] = zlo;
-        rb[wv][1] = zhi;
-        rb[wv][2] = ylo;
-        rb[wv][3] = yhi;
-        rm[wv][0] = sx;
-        rm[wv][1] = sy;
-        rm[wv][2] = sz;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
-            n0 += rc[i][0];
-            n1 += rc[i][1];
-            zlo = min(zlo, rb[i][0]);
-            zhi = max(zhi, rb[i][1]);
-            ylo = min(ylo, rb[i][2]);
-            yhi = max(yhi, rb[i][3]);
-            sx += rm[i][0];
-            sy += rm[i][1];
-            sz += rm[i][2];
-        }
-        QueryPart &p = qpart[(int64_t)q * kQueryParts + blockIdx.x];
-        p.cnt[0] = n0;
-        p.cnt[1] = n1;
-        p.box[0] = zlo;
-        p.box[1] = zhi;
-        p.box[2] = ylo;
-        p.box[3] = yhi;
-        p.mom[0] = sx;
-        p.mom[1] = sy;
-        p.mom[2] = sz;
-    }
+    acc.write(qpart[(int64_t)q * kQueryParts + blockIdx.x]);
 }
 
 hipError_t launch_pack_queries(const db_t *db, const uint8_t *labels, int nq, const int32_t *rois,
