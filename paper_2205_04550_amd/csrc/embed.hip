@@ -414,7 +414,7 @@ __global__ void __launch_bounds__(kSelThreads) topk_min_kernel(const float *__re
 
 constexpr int kRerankMaxCand = 1024;
 
-constexpr int kRC = 2;                 // candidates per wave
+constexpr int kRC = 4;                 // candidates per wave
 constexpr int kRerankPerBlock = 4 * kRC;   // candidates scored per block (4 waves)
 
 // 1-D grid of nbq * 8 * ceil(nq / 8) blocks (nbq = ceil(nc / kRerankPerBlock)),
@@ -480,7 +480,7 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
     if (nxw == 4) {
         // Rows of 128 voxels: one 16-byte load per plane; two rows per lane per pass, all
         // loads of the pass issued before any is used.
-        constexpr int U = 4;
+        constexpr int U = 2;
         for (int r0 = lane; r0 < nr; r0 += 64 * U) {
             u32x4 qa[U], qb[U], da[U][kRC], db[U][kRC];
             bool in[U][kRC];
