@@ -90,7 +90,7 @@ __device__ __forceinline__ uint32_t roi_word_mask(const int32_t *r, int w, int n
     return m;
 }
 
-constexpr int kPackBatch = 4;
+constexpr int kPackBatch = 8;
 
 
 // A block's share of a query's statistics: mask counts, the row range of set bits
@@ -189,18 +189,21 @@ __global__ void __launch_bounds__(256) pack_query_kernel(const uint8_t *__restri
     const int32_t *r = rois ? rois + 6 * q : nullptr;
     PartAcc acc;
     // Two lanes per packed word, 16 label bytes each, so one load instruction covers
-    // 1 KiB of contiguous labels; kPackBatch words per lane pair and pass, all their
-    // loads issued first. The even lane assembles the word from both halves.
+    // 1 KiB of contiguous labels; each block packs one contiguous run of words,
+    // kPackBatch words per lane pair and pass with all their loads issued first. The
+    // even lane assembles the word from both halves.
     const int half = threadIdx.x & 1;
-    const int stride = gridDim.x * (blockDim.x >> 1);
-    for (int w0 = blockIdx.x * (blockDim.x >> 1) + (threadIdx.x >> 1); w0 < Wp;
+    const int stride = blockDim.x >> 1;
+    const int seg = (Wp + gridDim.x - 1) / gridDim.x;
+    const int wbeg = blockIdx.x * seg, wend = min(Wp, wbeg + seg);
+    for (int w0 = wbeg + (threadIdx.x >> 1); w0 - (int)(threadIdx.x >> 1) < wend;
          w0 += kPackBatch * stride) {
         u32x4 vb[kPackBatch];
 #pragma unroll
         for (int u = 0; u < kPackBatch; ++u) {
             const int w = w0 + u * stride;
             vb[u] = (u32x4){0u, 0u, 0u, 0u};
-            if (w < W) vb[u] = load_stream(lab + 2 * (int64_t)w + half);
+            if (w < W && w < wend) vb[u] = load_stream(lab + 2 * (int64_t)w + half);
         }
 #pragma unroll
         for (int u = 0; u < kPackBatch; ++u) {
@@ -214,7 +217,7 @@ __global__ void __launch_bounds__(256) pack_query_kernel(const uint8_t *__restri
                 h1 |= t4 << (4 * e);
             }
             const uint32_t g0 = __shfl_down(h0, 1, 64), g1 = __shfl_down(h1, 1, 64);
-            if (half || w >= Wp) continue;
+            if (half || w >= wend) continue;
             uint32_t b0 = h0 | (g0 << 16), b1 = h1 | (g1 << 16);
             if (w < W && r) {
                 const uint32_t m = roi_word_mask(r, w, nxw, ny);
