@@ -828,10 +828,10 @@ __global__ void __launch_bounds__(kSelThreads) topk_merge_kernel(int nc, int k,
 // one-block radix path instead.
 
 constexpr int kTauThreads = 512;
-constexpr int kTauPer = 16;
-constexpr int kTauChunk = kTauThreads * kTauPer;   // 8,192 entries
-constexpr int kTauMaxM = 4;
+constexpr int kTauMaxM = 8;     // m <= 8: the 8 waves' 8 smallest minima fill one wave
 constexpr int kTauCap = 4096;
+// Entries per thread: 16 (chunks of 8,192) for long rows, 4 (chunks of 2,048) where
+// that gives too few chunks for m <= kTauMaxM.
 
 // Rank of lane value x among the first n lanes' values of the wave (ties by lane):
 // a permutation of 0..n-1 over those lanes.
@@ -847,10 +847,12 @@ __device__ __forceinline__ int wave_rank(uint32_t x, int lane, int n)
 
 // grid (C, M), kTauThreads threads: tau[row] = max(tau[row], m-th smallest thread minimum);
 // each thread's minimum is kept in tmin [M][C][kTauThreads] for the filter pass.
+template <int kTauPer>
 __global__ void __launch_bounds__(kTauThreads) topk_tau_kernel(const float *__restrict__ D, int N,
                                                                int m, uint32_t *__restrict__ tau,
                                                                uint32_t *__restrict__ tmin)
 {
+    constexpr int kTauChunk = kTauThreads * kTauPer;
     __shared__ uint32_t wl[kTauThreads / 64][kTauMaxM];
     const int64_t r = blockIdx.y;
     const int base = blockIdx.x * kTauChunk;
@@ -889,12 +891,14 @@ __global__ void __launch_bounds__(kTauThreads) topk_tau_kernel(const float *__re
 // 16 entries are read; the partial last chunk is read whole), sort them by
 // (key, index) and write the first k. A list longer than kTauCap falls back to
 // the one-block radix selection of the whole row.
+template <int kTauPer>
 __global__ void __launch_bounds__(kSelThreads) topk_list_kernel(const float *__restrict__ D, int N,
                                                                 int k, const uint32_t *__restrict__ tau,
                                                                 const uint32_t *__restrict__ tmin,
                                                                 int32_t *__restrict__ out_idx,
                                                                 float *__restrict__ out_d)
 {
+    constexpr int kTauChunk = kTauThreads * kTauPer;
     __shared__ uint32_t sk[kTauCap];
     __shared__ int32_t si[kTauCap];
     __shared__ uint32_t s_n;
@@ -1025,18 +1029,29 @@ hipError_t launch_dist_fp8(int M, int N, int K, const uint8_t *Q, const float *q
 }
 
 // m of the bound-and-filter path, or 0 when it does not apply (too few full chunks).
-static int tau_m(int N, int k)
+// m of the bound-and-filter path with `per` entries per thread, or 0 when it does not
+// apply (too few full chunks).
+static int tau_m_per(int N, int k, int per)
 {
-    const int full = N / kTauChunk;
+    const int full = N / (kTauThreads * per);
     if (full < 1) return 0;
     const int m = (k + full - 1) / full;
     return m <= kTauMaxM ? m : 0;
 }
 
+// Entries per thread of the bound-and-filter path for (N, k): 16, else 4, else 0 (n/a).
+static int tau_per(int N, int k)
+{
+    if (tau_m_per(N, k, 16)) return 16;
+    if (tau_m_per(N, k, 4)) return 4;
+    return 0;
+}
+
 size_t topk_min_ws_bytes(int M, int N, int k)
 {
-    if (tau_m(N, k))
-        return align_up((size_t)M * 4, kAlign) + (size_t)M * (N / kTauChunk) * kTauThreads * 4;
+    if (const int per = tau_per(N, k))
+        return align_up((size_t)M * 4, kAlign) +
+               (size_t)M * (N / (kTauThreads * per)) * kTauThreads * 4;
     const int64_t nch = ((int64_t)N + kChunk - 1) / kChunk;
     if (nch * k > kMergeMax) return 0;       // the two-stage path does not apply
     return (size_t)M * nch * k * 8;
@@ -1050,20 +1065,29 @@ hipError_t launch_topk_min(int M, int N, int k, const float *D, int32_t *idx, fl
         hipLaunchKernelGGL(topk_min_kernel, dim3(M), dim3(kSelThreads), 0, s, D, N, k, idx, d);
         return hipGetLastError();
     }
-    if (const int m = tau_m(N, k)) {
+    if (const int per = tau_per(N, k)) {
+        const int m = tau_m_per(N, k, per);
         uint32_t *tau = static_cast<uint32_t *>(ws);
         uint32_t *tmin = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) +
                                                       align_up((size_t)M * 4, kAlign));
-        const int cfull = N / kTauChunk;
+        const int cfull = N / (kTauThreads * per);
         hipError_t e = launch_fill_u32(reinterpret_cast<int32_t *>(tau), M, 0, s);
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(topk_tau_kernel, dim3(cfull, M), dim3(kTauThreads), 0, s, D, N, m, tau,
-                               tmin);
+            if (per == 16)
+                hipLaunchKernelGGL(topk_tau_kernel<16>, dim3(cfull, M), dim3(kTauThreads), 0, s, D, N,
+                                   m, tau, tmin);
+            else
+                hipLaunchKernelGGL(topk_tau_kernel<4>, dim3(cfull, M), dim3(kTauThreads), 0, s, D, N,
+                                   m, tau, tmin);
             e = hipGetLastError();
         }
         if (e == hipSuccess) {
-            hipLaunchKernelGGL(topk_list_kernel, dim3(M), dim3(kSelThreads), 0, s, D, N, k, tau, tmin,
-                               idx, d);
+            if (per == 16)
+                hipLaunchKernelGGL(topk_list_kernel<16>, dim3(M), dim3(kSelThreads), 0, s, D, N, k, tau,
+                                   tmin, idx, d);
+            else
+                hipLaunchKernelGGL(topk_list_kernel<4>, dim3(M), dim3(kSelThreads), 0, s, D, N, k, tau,
+                                   tmin, idx, d);
             e = hipGetLastError();
         }
         return e;

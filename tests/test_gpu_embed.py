@@ -94,14 +94,16 @@ def test_topk_min_exact_with_ties():
         assert np.array_equal(val.cpu().numpy(), np.take_along_axis(D2, want, 1)), (N, k)
 
 
-def test_topk_min_long_rows_bound_and_filter():
-    """Rows of 300,000 (the bound-and-filter path for k <= 4 x full chunks): random
-    distances, heavy ties, an all-equal row (its list overflows: one-block fallback),
-    negatives, and the smallest entries packed in the last, partial chunk."""
+@pytest.mark.parametrize("N", [300_000, 50_000])
+def test_topk_min_long_rows_bound_and_filter(N):
+    """Rows of 300,000 (bound-and-filter with 8,192-entry chunks) and 50,000 (2,048-entry
+    chunks for k = 100): random distances, heavy ties, an all-equal row (its list
+    overflows: one-block fallback), negatives, and the smallest entries packed in the
+    last, partial chunk."""
     need_gpu()
     from paper_2205_04550_amd import binding as b
     rng = np.random.default_rng(12)
-    M, N = 5, 300_000
+    M = 5
     D = rng.standard_normal((M, N)).astype(np.float32) * 50 + 900
     D[1] = rng.integers(0, 40, N).astype(np.float32)          # ties
     D[2] = 3.0                                                 # all equal
