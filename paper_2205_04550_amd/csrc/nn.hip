@@ -618,7 +618,7 @@ __global__ void __launch_bounds__(256) linear_gemm_kernel(int M, int N, int K,
 // supplies row (or column) l % 32 at k = 16 (l / 32) + s, so a lane reads 16
 // consecutive k of its row as four 16-byte LDS loads. Needs K % 4 == 0.
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-constexpr int kMM = 64, kMK = 32, kMPad = 36;
+constexpr int kMM = 64, kMK = 64, kMPad = kMK + 4;
 
 __device__ __forceinline__ f32x4 ld4_w(const float *p) { return *reinterpret_cast<const f32x4 *>(p); }
 __device__ __forceinline__ f32x4 ld4_w(const uint16_t *p)
@@ -629,7 +629,7 @@ __device__ __forceinline__ f32x4 ld4_w(const uint16_t *p)
 }
 
 template <class WT, bool B_KN>
-__global__ void __launch_bounds__(256) linear_mfma_kernel(int M, int N, int K,
+__global__ void __launch_bounds__(512) linear_mfma_kernel(int M, int N, int K,
                                                           const float *__restrict__ A,
                                                           const WT *__restrict__ Wt,
                                                           const float *__restrict__ bias, int relu,
@@ -637,22 +637,28 @@ __global__ void __launch_bounds__(256) linear_mfma_kernel(int M, int N, int K,
 {
     __shared__ __attribute__((aligned(16))) float As[kMM * kMPad];
     __shared__ __attribute__((aligned(16))) float Bs[kMM * kMPad];
+    __shared__ float red[4 * 16 * 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1, h = lane >> 5, r32 = lane & 31;
+    // Eight waves: kh = wave / 4 takes half of each 32-wide K step, so twice as many
+    // waves share a tile; the two halves are added at the end (fixed order).
+    const int kh = wave >> 2, w4 = wave & 3;
+    const int wm = w4 >> 1, wn = w4 & 1, h = lane >> 5, r32 = lane & 31;
     const int m0 = blockIdx.y * kMM, n0 = blockIdx.x * kMM;
-    // Staging: 64 rows x 8 float4 per operand, two of each per thread. With B_KN the
-    // weights are [K][N] (the input gradient dY W): four consecutive n of one k.
-    const int srow = tid >> 3, sk = (tid & 7) * 4;
-    const int bk = tid >> 4, bq = (tid & 15) * 4;
-    f32x4 pa[2], pb[2];
+    // Staging: 64 rows x kMK / 4 float4 per operand, kSt of each per thread. With B_KN
+    // the weights are [K][N] (the input gradient dY W): four consecutive n of one k.
+    constexpr int kF4 = kMK / 4, kRows = 512 / kF4, kSt = kMM / kRows;
+    static_assert(kSt == kMK / 32, "both operands take kSt passes");
+    const int srow = tid / kF4, sk = (tid % kF4) * 4;    // + kRows j rows
+    const int bk = tid >> 4, bq = (tid & 15) * 4;        // + 32 j k
+    f32x4 pa[kSt], pb[kSt];
     auto fetch = [&](int k0) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int row = srow + 32 * j, k = k0 + sk;
-            const int m = m0 + row, n = n0 + row;
+        for (int j = 0; j < kSt; ++j) {
+            const int k = k0 + sk;
+            const int m = m0 + srow + kRows * j, n = n0 + srow + kRows * j;
             pa[j] = (m < M && k < K) ? ld4_w(A + (int64_t)m * K + k) : (f32x4){0.f, 0.f, 0.f, 0.f};
             if (B_KN) {
-                const int kb = k0 + bk + 16 * j, nb = n0 + bq;
+                const int kb = k0 + bk + 32 * j, nb = n0 + bq;
                 pb[j] = (kb < K && nb < N) ? ld4_w(Wt + (int64_t)kb * N + nb)
                                            : (f32x4){0.f, 0.f, 0.f, 0.f};
             } else {
@@ -668,21 +674,23 @@ __global__ void __launch_bounds__(256) linear_mfma_kernel(int M, int N, int K,
     for (int k0 = 0; k0 < K; k0 += kMK) {
         __syncthreads();
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            *reinterpret_cast<f32x4 *>(&As[(srow + 32 * j) * kMPad + sk]) = pa[j];
+        for (int j = 0; j < kSt; ++j) {
+            *reinterpret_cast<f32x4 *>(&As[(srow + kRows * j) * kMPad + sk]) = pa[j];
             if (B_KN) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) Bs[(bq + e) * kMPad + bk + 16 * j] = pb[j][e];
+                for (int e = 0; e < 4; ++e) Bs[(bq + e) * kMPad + bk + 32 * j] = pb[j][e];
             } else {
-                *reinterpret_cast<f32x4 *>(&Bs[(srow + 32 * j) * kMPad + sk]) = pb[j];
+                *reinterpret_cast<f32x4 *>(&Bs[(srow + kRows * j) * kMPad + sk]) = pb[j];
             }
         }
         __syncthreads();
         if (k0 + kMK < K) fetch(k0 + kMK);
-        const float *ar = &As[(wm * 32 + r32) * kMPad + 16 * h];
-        const float *br = &Bs[(wn * 32 + r32) * kMPad + 16 * h];
+        // In product s of this wave's half, lane l supplies row (or column) l % 32 at
+        // k = (kMK / 2) (l / 32) + (kMK / 4) kh + s.
+        const float *ar = &As[(wm * 32 + r32) * kMPad + (kMK / 2) * h + (kMK / 4) * kh];
+        const float *br = &Bs[(wn * 32 + r32) * kMPad + (kMK / 2) * h + (kMK / 4) * kh];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < kMK / 16; ++q) {
             const f32x4 a = *reinterpret_cast<const f32x4 *>(ar + 4 * q);
             const f32x4 b = *reinterpret_cast<const f32x4 *>(br + 4 * q);
 #pragma unroll
@@ -690,6 +698,12 @@ __global__ void __launch_bounds__(256) linear_mfma_kernel(int M, int N, int K,
                 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[e], b[e], acc, 0, 0, 0);
         }
     }
+    if (kh == 1) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) red[(w4 * 16 + r) * 64 + lane] = acc[r];
+    }
+    __syncthreads();
+    if (kh == 1) return;
     const int n = n0 + wn * 32 + r32;
     if (n >= N) return;
     const float bn = bias ? bias[n] : 0.f;
@@ -697,7 +711,7 @@ __global__ void __launch_bounds__(256) linear_mfma_kernel(int M, int N, int K,
     for (int r = 0; r < 16; ++r) {
         const int m = m0 + wm * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
         if (m < M) {
-            float v = acc[r] + bn;
+            float v = (acc[r] + red[(w4 * 16 + r) * 64 + lane]) + bn;
             if (relu && v < 0.f) v = 0.f;
             C[(int64_t)m * N + n] = v;
         }
@@ -1443,11 +1457,11 @@ int nn_linear_fwd(int dtype, int B, int In, int Out, const void *X, const void *
     const size_t wal = pair == 0 ? 8 : 16;
     const bool vec = In % 4 == 0 && (uintptr_t)X % 16 == 0 && (uintptr_t)Wt % wal == 0;
     if (pair == 0 && vec)
-        hipLaunchKernelGGL((linear_mfma_kernel<uint16_t, false>), mgrid, dim3(256), 0, s, B, Out, In,
+        hipLaunchKernelGGL((linear_mfma_kernel<uint16_t, false>), mgrid, dim3(512), 0, s, B, Out, In,
                            (const float *)X, (const uint16_t *)Wt, (const float *)bias, relu,
                            (float *)Y);
     else if (pair == 1 && vec)
-        hipLaunchKernelGGL((linear_mfma_kernel<float, false>), mgrid, dim3(256), 0, s, B, Out, In,
+        hipLaunchKernelGGL((linear_mfma_kernel<float, false>), mgrid, dim3(512), 0, s, B, Out, In,
                            (const float *)X, (const float *)Wt, (const float *)bias, relu,
                            (float *)Y);
     else if (pair == 0)
@@ -1479,11 +1493,11 @@ int nn_linear_bwd_data(int dtype, int B, int In, int Out, const void *dY, const 
     const bool vec = In % 4 == 0 && Out % 4 == 0 && (uintptr_t)dY % 16 == 0 &&
                      (uintptr_t)Wt % wal == 0;
     if (pair == 0 && vec)
-        hipLaunchKernelGGL((linear_mfma_kernel<uint16_t, true>), mgrid, dim3(256), 0, s, B, In, Out,
+        hipLaunchKernelGGL((linear_mfma_kernel<uint16_t, true>), mgrid, dim3(512), 0, s, B, In, Out,
                            (const float *)dY, (const uint16_t *)Wt, (const float *)nullptr, 0,
                            (float *)dX);
     else if (pair == 1 && vec)
-        hipLaunchKernelGGL((linear_mfma_kernel<float, true>), mgrid, dim3(256), 0, s, B, In, Out,
+        hipLaunchKernelGGL((linear_mfma_kernel<float, true>), mgrid, dim3(512), 0, s, B, In, Out,
                            (const float *)dY, (const float *)Wt, (const float *)nullptr, 0,
                            (float *)dX);
     else if (pair == 0)
