@@ -340,6 +340,9 @@ __global__ void __launch_bounds__(256) conv_mfma_kernel(int Ci, int Co, int D, i
 
 // Adjoint map: grid (ceil(B*D*H*W / 256), ceil(Ci / kCB)); one thread per (sample,
 // input voxel) and kCB input channels (each dY tap is loaded once for all of them).
+// Threads are numbered by parity class: the voxels of one sample with the same
+// (z, y, x) parities are consecutive, so the lanes of a wave share the set of taps
+// that reach them (1 or 2 per axis) and skip the others together.
 template <class T, class WT>
 __global__ void __launch_bounds__(256) conv_bwd_data_kernel(int B, int Ci, int Co, int D, int H,
                                                             int W, const T *__restrict__ dY,
@@ -355,11 +358,14 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(int B, int Ci, int C
     const bool active = t < (int64_t)B * isp;
     const int64_t tt = active ? t : 0;
     const int b = (int)(tt / isp);
-    const int i = (int)(tt - (int64_t)b * isp);
-    const int ii = i;
+    const int r = (int)(tt - (int64_t)b * isp);
+    const int cls = r / osp, jv = r - cls * osp;
+    const int iw = 2 * (jv % OW) + (cls & 1);
+    const int ih = 2 * ((jv / OW) % OH) + ((cls >> 1) & 1);
+    const int id = 2 * (jv / (OW * OH)) + (cls >> 2);
+    const int i = (id * H + ih) * W + iw;
     const int ci0 = blockIdx.y * kCB;
     const int nci = min(kCB, Ci - ci0);
-    const int iw = ii % W, ih = (ii / W) % H, id = ii / (W * H);
     T acc[kCB];
 #pragma unroll
     for (int c = 0; c < kCB; ++c) acc[c] = bias ? bias[min(ci0 + c, Ci - 1)] : T(0);
