@@ -410,29 +410,36 @@ __global__ void __launch_bounds__(256) conv_bwd_data_kernel(int B, int Ci, int C
 
 constexpr int kWgChunk = 4096;  // (batch, output voxel) positions per weight-gradient block
 
-// Stage 1: grid (chunks, Ci, Co). partial [chunks][Co][Ci][28]: 27 taps + sum of dY.
-template <class T>
+// Stage 1: grid (chunks, Ci, ceil(Co / CB)). partial [chunks][Co][Ci][28]: 27 taps + sum
+// of dY. A thread takes CB output channels at once, so each input tap it loads feeds CB
+// products; each (co, ci, tap) sum is formed in the same order whatever CB is.
+template <class T, int CB>
 __global__ void __launch_bounds__(256) conv_bwd_weight_partial(int B, int Ci, int Co, int D, int H,
                                                                int W, const T *__restrict__ X,
                                                                const T *__restrict__ dY,
                                                                T *__restrict__ partial)
 {
-    __shared__ T red[4][28];
+    __shared__ T red[4][CB][28];
     const int OD = D / 2, OH = H / 2, OW = W / 2;
     const int osp = OD * OH * OW;
     const int64_t isp = (int64_t)D * H * W;
-    const int co = blockIdx.z, ci = blockIdx.y;
+    const int co0 = blockIdx.z * CB, ci = blockIdx.y;
     const int64_t P = (int64_t)B * osp;
     const int64_t p0 = (int64_t)blockIdx.x * kWgChunk;
     const int64_t p1 = p0 + kWgChunk < P ? p0 + kWgChunk : P;
-    T acc[28];
+    T acc[CB][28];
 #pragma unroll
-    for (int k = 0; k < 28; ++k) acc[k] = T(0);
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int k = 0; k < 28; ++k) acc[c][k] = T(0);
     for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
         const int b = (int)(p / osp);
         const int o = (int)(p - (int64_t)b * osp);
         const int ow = o % OW, oh = (o / OW) % OH, od = o / (OW * OH);
-        const T g = dY[((int64_t)b * Co + co) * osp + o];
+        T g[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            g[c] = co0 + c < Co ? dY[((int64_t)b * Co + co0 + c) * osp + o] : T(0);
         const T *x = X + ((int64_t)b * Ci + ci) * isp;
 #pragma unroll
         for (int kd = 0; kd < 3; ++kd) {
@@ -447,23 +454,28 @@ __global__ void __launch_bounds__(256) conv_bwd_weight_partial(int B, int Ci, in
                     // Out-of-range taps read element 0 (always valid) and count as zero.
                     const int64_t off = in ? ((int64_t)id * H + ih) * W + iw : 0;
                     const T xv = in ? x[off] : T(0);
-                    acc[kd * 9 + kh * 3 + kw] += g * xv;
+#pragma unroll
+                    for (int c = 0; c < CB; ++c) acc[c][kd * 9 + kh * 3 + kw] += g[c] * xv;
                 }
             }
         }
-        acc[27] += g;
+#pragma unroll
+        for (int c = 0; c < CB; ++c) acc[c][27] += g[c];
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < 28; ++k) {
-        const T s = wsum(acc[k]);
-        if (lane == 0) red[wave][k] = s;
-    }
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int k = 0; k < 28; ++k) {
+            const T sm = wsum(acc[c][k]);
+            if (lane == 0) red[wave][c][k] = sm;
+        }
     __syncthreads();
-    if (threadIdx.x < 28) {
-        const int k = threadIdx.x;
-        const T s = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
-        partial[(((int64_t)blockIdx.x * Co + co) * Ci + ci) * 28 + k] = s;
+    for (int t = threadIdx.x; t < CB * 28; t += blockDim.x) {
+        const int c = t / 28, k = t - c * 28;
+        if (co0 + c >= Co) continue;
+        const T sm = ((red[0][c][k] + red[1][c][k]) + red[2][c][k]) + red[3][c][k];
+        partial[(((int64_t)blockIdx.x * Co + co0 + c) * Ci + ci) * 28 + k] = sm;
     }
 }
 
@@ -1434,16 +1446,18 @@ int nn_conv3d_s2_bwd_weight(int dtype, int B, int Ci, int Co, int D, int H, int 
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t P = (int64_t)B * (D / 2) * (H / 2) * (W / 2);
     const int chunks = (int)((P + kWgChunk - 1) / kWgChunk);
+    constexpr int kWgCB = 4;   // output channels per thread (float)
     const dim3 g1(chunks, Ci, Co);
+    const dim3 g1f(chunks, Ci, (Co + kWgCB - 1) / kWgCB);
     const unsigned g2 = (unsigned)((Co * Ci * 28 + 255) / 256);
     if (dtype == NN_F32) {
-        hipLaunchKernelGGL(conv_bwd_weight_partial<float>, g1, dim3(256), 0, s, B, Ci, Co, D, H, W,
-                           (const float *)X, (const float *)dY, (float *)ws);
+        hipLaunchKernelGGL((conv_bwd_weight_partial<float, kWgCB>), g1f, dim3(256), 0, s, B, Ci, Co,
+                           D, H, W, (const float *)X, (const float *)dY, (float *)ws);
         hipLaunchKernelGGL(conv_bwd_weight_final<float>, dim3(g2), dim3(256), 0, s, chunks, Ci, Co,
                            (const float *)ws, (float *)dWt, (float *)dbias);
     } else {
-        hipLaunchKernelGGL(conv_bwd_weight_partial<double>, g1, dim3(256), 0, s, B, Ci, Co, D, H,
-                           W, (const double *)X, (const double *)dY, (double *)ws);
+        hipLaunchKernelGGL((conv_bwd_weight_partial<double, 1>), g1, dim3(256), 0, s, B, Ci, Co, D,
+                           H, W, (const double *)X, (const double *)dY, (double *)ws);
         hipLaunchKernelGGL(conv_bwd_weight_final<double>, dim3(g2), dim3(256), 0, s, chunks, Ci,
                            Co, (const double *)ws, (double *)dWt, (double *)dbias);
     }
