@@ -218,6 +218,18 @@ int db_rerank(const db_t *db, int nq, const uint8_t *q_labels, const int32_t *ca
               int32_t *idx, double *score, db_counts_t *counts, void *ws, size_t ws_bytes,
               void *stream);
 
+/* db_rerank in two calls, so the packing of the queries (one read of their
+ * labels) can run on another stream while the candidates are being found:
+ * db_rerank_pack writes the queries' bit planes, mask counts and row boxes into
+ * ws; db_rerank_packed then scores cand against them. Same ws (same nq, at
+ * least db_rerank_workspace_bytes(db, nq) bytes, 256-byte aligned) for both
+ * calls; the second must be ordered after the first (same stream, or an event).
+ * Results equal db_rerank's bit for bit. Argument rules as db_rerank's. */
+int db_rerank_pack(const db_t *db, int nq, const uint8_t *q_labels, void *ws, size_t ws_bytes,
+                   void *stream);
+int db_rerank_packed(const db_t *db, int nq, const int32_t *cand, int nc, int k, int32_t *idx,
+                     double *score, db_counts_t *counts, void *ws, size_t ws_bytes, void *stream);
+
 /* The chain distances -> n_cand nearest latents -> exact rerank -> k best.
  * Database latents x_* have n_lat = db_size() rows. cand_idx / cand_d [nq][n_cand]
  * receive the latent candidates (or pass NULL to keep them in the workspace). */

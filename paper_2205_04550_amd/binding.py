@@ -24,7 +24,8 @@ SYMBOLS = ("db_storage_bytes", "db_build", "db_append", "db_size", "db_query_wor
            "db_rerank_workspace_bytes", "db_rerank", "db_query_embed_workspace_bytes",
            "db_query_embed", "db_tune_batch", "db_append_resampled", "labels_resample",
            "db_query_sparse", "db_query_com_workspace_bytes", "db_query_com",
-           "emb_hash_thresholds", "emb_binarize", "emb_distances_l2sum")
+           "emb_hash_thresholds", "emb_binarize", "emb_distances_l2sum", "db_rerank_pack",
+           "db_rerank_packed")
 EMB_BF16, EMB_FP8, EMB_BIN = 0, 1, 2
 
 
@@ -73,6 +74,8 @@ def _load():
         "emb_binarize": (i32, [i64, i32, vp, vp, vp, vp]),
         "db_rerank_workspace_bytes": (sz, [vp, i32]),
         "db_rerank": (i32, [vp, i32, vp, vp, i32, i32, vp, vp, vp, vp, sz, vp]),
+        "db_rerank_pack": (i32, [vp, i32, vp, vp, sz, vp]),
+        "db_rerank_packed": (i32, [vp, i32, vp, i32, i32, vp, vp, vp, vp, sz, vp]),
         "db_query_embed_workspace_bytes": (sz, [vp, i32, i32]),
         "db_query_embed": (i32, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp,
                                  vp, vp, vp, vp, sz, vp]),
@@ -291,6 +294,29 @@ class TumorDB:
         _check(LIB.db_rerank(self._h, nq, q_labels.data_ptr(), cand.data_ptr(), nc, k,
                              idx.data_ptr(), score.data_ptr(), counts.data_ptr(), ws.data_ptr(), nb,
                              _stream(stream)))
+        return idx, score, counts
+
+    def rerank_workspace(self, nq: int) -> torch.Tensor:
+        """A workspace for rerank / rerank_pack + rerank_packed of nq queries."""
+        nb = LIB.db_rerank_workspace_bytes(self._h, nq)
+        return torch.empty(nb, dtype=torch.uint8, device=self.storage.device)
+
+    def rerank_pack(self, q_labels: torch.Tensor, ws: torch.Tensor, stream=None) -> None:
+        """First half of rerank: pack the queries q_labels [nq][nz][ny][nx] into ws."""
+        _check(LIB.db_rerank_pack(self._h, q_labels.shape[0], q_labels.data_ptr(), ws.data_ptr(),
+                                  ws.numel(), _stream(stream)))
+
+    def rerank_packed(self, ws: torch.Tensor, cand: torch.Tensor, k: int, stream=None):
+        """Second half of rerank: score cand [nq][nc] against the queries packed into ws."""
+        nq, nc = cand.shape
+        dev = self.storage.device
+        idx = torch.empty((nq, k), dtype=torch.int32, device=dev)
+        score = torch.empty((nq, k), dtype=torch.float64, device=dev)
+        counts = torch.empty((nq, k, 6), dtype=torch.int32, device=dev)
+        cand = cand.to(torch.int32).contiguous()
+        _check(LIB.db_rerank_packed(self._h, nq, cand.data_ptr(), nc, k, idx.data_ptr(),
+                                    score.data_ptr(), counts.data_ptr(), ws.data_ptr(), ws.numel(),
+                                    _stream(stream)))
         return idx, score, counts
 
     def query_embed(self, fmt: int, q: "Latents", x: "Latents", q_labels: torch.Tensor,

@@ -817,21 +817,70 @@ static hipError_t rerank_launches(const db_t *db, int nq, const uint32_t *qpack,
     return e;
 }
 
+// Pack the queries into the rerank workspace: bit planes, counts, row boxes, moments.
+static hipError_t enqueue_rerank_pack(const db_t *db, int nq, const uint8_t *q_labels, void *ws,
+                                      hipStream_t s)
+{
+    size_t oq, op, oa, ob, om, osc;
+    rerank_layout(db, nq, &oq, &op, &oa, &ob, &om, &osc);
+    hipError_t e = launch_pack_queries(db, q_labels, nq, nullptr, at<uint32_t>(ws, oq),
+                                       at<QueryPart>(ws, op), s);
+    if (e == hipSuccess)
+        e = launch_sum_parts(at<QueryPart>(ws, op), nq, at<uint32_t>(ws, oa), at<int32_t>(ws, ob),
+                             at<uint64_t>(ws, om), s);
+    return e;
+}
+
+// Score and rank the candidates of queries packed into ws.
+static hipError_t enqueue_rerank_score(const db_t *db, int nq, const int32_t *cand, int nc, int k,
+                                       int32_t *idx, double *score, db_counts_t *counts, void *ws,
+                                       hipStream_t s)
+{
+    size_t oq, op, oa, ob, om, osc;
+    rerank_layout(db, nq, &oq, &op, &oa, &ob, &om, &osc);
+    return rerank_launches(db, nq, at<uint32_t>(ws, oq), at<uint32_t>(ws, oa), at<int32_t>(ws, ob),
+                           cand, nc, k, idx, score, counts, at<char>(ws, osc), s);
+}
+
 static hipError_t enqueue_rerank(const db_t *db, int nq, const uint8_t *q_labels,
                                  const int32_t *cand, int nc, int k, int32_t *idx, double *score,
                                  db_counts_t *counts, void *ws, hipStream_t s)
 {
-    size_t oq, op, oa, ob, om, osc;
-    rerank_layout(db, nq, &oq, &op, &oa, &ob, &om, &osc);
-    uint32_t *qpack = at<uint32_t>(ws, oq);
-    uint32_t *acnt = at<uint32_t>(ws, oa);
-    int32_t *box = at<int32_t>(ws, ob);
-    QueryPart *qpart = at<QueryPart>(ws, op);
-    hipError_t e = launch_pack_queries(db, q_labels, nq, nullptr, qpack, qpart, s);
-    if (e == hipSuccess) e = launch_sum_parts(qpart, nq, acnt, box, at<uint64_t>(ws, om), s);
-    if (e == hipSuccess) e = rerank_launches(db, nq, qpack, acnt, box, cand, nc, k, idx, score,
-                                             counts, at<char>(ws, osc), s);
+    hipError_t e = enqueue_rerank_pack(db, nq, q_labels, ws, s);
+    if (e == hipSuccess) e = enqueue_rerank_score(db, nq, cand, nc, k, idx, score, counts, ws, s);
     return e;
+}
+
+int db_rerank_pack(const db_t *db, int nq, const uint8_t *q_labels, void *ws, size_t ws_bytes,
+                   void *stream)
+{
+    int rc = check_query_common("db_rerank_pack", db, q_labels, ws);
+    if (rc) return rc;
+    if (nq <= 0) return fail(DB_EINVAL, "db_rerank_pack: nq %d", nq);
+    const size_t need = db_rerank_workspace_bytes(db, nq);
+    if (ws_bytes < need)
+        return fail(DB_ENOSPC, "db_rerank_pack: workspace %zu bytes < %zu needed", ws_bytes, need);
+    hipError_t e = enqueue_rerank_pack(db, nq, q_labels, ws, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "db_rerank_pack: launch");
+    return DB_OK;
+}
+
+int db_rerank_packed(const db_t *db, int nq, const int32_t *cand, int nc, int k, int32_t *idx,
+                     double *score, db_counts_t *counts, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!live(db)) return fail(DB_ESTATE, "db_rerank_packed: invalid handle");
+    if (db->count <= 0) return fail(DB_EINVAL, "db_rerank_packed: database is empty");
+    if (!ws || !aligned(ws, kAlign))
+        return fail(DB_EINVAL, "db_rerank_packed: workspace must be non-NULL and 256-byte aligned");
+    if (nq <= 0 || !cand || !idx || !score || nc < 1 || nc > DB_KMAX || k < 1 || k > nc)
+        return fail(DB_EINVAL, "db_rerank_packed: bad arguments (nq %d, nc %d, k %d)", nq, nc, k);
+    const size_t need = db_rerank_workspace_bytes(db, nq);
+    if (ws_bytes < need)
+        return fail(DB_ENOSPC, "db_rerank_packed: workspace %zu bytes < %zu needed", ws_bytes, need);
+    hipError_t e = enqueue_rerank_score(db, nq, cand, nc, k, idx, score, counts, ws,
+                                        static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "db_rerank_packed: launch");
+    return DB_OK;
 }
 
 int db_rerank(const db_t *db, int nq, const uint8_t *q_labels, const int32_t *cand, int nc, int k,

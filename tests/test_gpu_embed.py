@@ -166,3 +166,31 @@ def test_query_embed_chain_matches_its_parts():
         assert torch.equal(ci, ti) and torch.equal(cd, tv)
         ri, rs, rc = db.rerank(lab_d, ci, 10)
         assert torch.equal(idx, ri) and torch.equal(score, rs) and torch.equal(counts, rc)
+
+
+def test_rerank_in_two_calls_matches_rerank():
+    """db_rerank_pack on a second stream, then db_rerank_packed after an event: the same
+    top-k, scores and counts as db_rerank, bit for bit (an empty query included)."""
+    need_gpu()
+    gen = synth.SMALL
+    n, nq = 200, 7
+    db, _ = build_db_from_host(gen, n, synth.T_LO, synth.T_HI)
+    labels, _ = synth.make_queries(gen, n, nq, synth.BATCH_QUERY_SEED)
+    labels[3] = 0
+    lab_d = torch.from_numpy(labels).cuda()
+    rng = np.random.default_rng(21)
+    cand = torch.from_numpy(np.stack([rng.choice(n, 40, replace=False) for _ in range(nq)])
+                            .astype(np.int32)).cuda()
+    want = db.rerank(lab_d, cand, 9)
+    ws = db.rerank_workspace(nq)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        db.rerank_pack(lab_d, ws)
+    done = torch.cuda.Event()
+    done.record(side)
+    torch.cuda.current_stream().wait_event(done)
+    got = db.rerank_packed(ws, cand, 9)
+    db.sync()
+    for a, w in zip(got, want):
+        assert torch.equal(a, w)
