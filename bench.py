@@ -607,7 +607,7 @@ def bench_embed(args, db, gen, n, build_s) -> int:
         cpu = cpu_baseline_embed(model, X, lab_host_sample, gen, n, n_cand, k, args.cpu_seconds)
         log(f"cpu oracle {cpu['value']:.3f} queries/s on {cpu['cores']} threads")
     gemm_flop = 2.0 * nq * n * model.latent
-    names = ["encode queries (packing overlapped)", "distance GEMM (BF16 MFMA)", "top-100 select",
+    names = ["encode + pack queries (two streams)", "distance GEMM (BF16 MFMA)", "top-100 select",
              "exact rerank"]
     dom = int(np.argmax(stage))
     log(f"{ms:.2f} ms per {nq} queries ({nq / (ms * 1e-3):.0f} q/s); stages "
