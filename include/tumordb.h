@@ -166,7 +166,9 @@ int emb_quantize(int64_t n, int dim, const float *lat, int fmt, void *codes, flo
  * scales multiply the FP8 dot products and are ignored for BF16. EMB_BIN:
  * codes are dim-bit strings (uint32 [.][dim/32], see emb_binarize) and
  * D[m][n] is their Hamming distance as a float (exact); scales and squared
- * norms are ignored (may be NULL). dim % 32 == 0 and dim <= 1024 for EMB_BIN. */
+ * norms are ignored (may be NULL). dim % 32 == 0 and dim <= 1024 for EMB_BIN.
+ * BF16 / FP8: the query codes (M x dim x 2 or 1 bytes) must stay below 2 GiB
+ * (DB_EINVAL otherwise); database codes of any size are taken in chunks. */
 int emb_distances(int fmt, int M, int N, int dim, const void *q_codes, const float *q_scale,
                   const float *q_sq, const void *x_codes, const float *x_scale, const float *x_sq,
                   float *D, void *stream);

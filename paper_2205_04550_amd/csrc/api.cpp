@@ -232,6 +232,8 @@ static int dist_check(const char *fn, int fmt, int M, int N, int dim, const void
         return fail(DB_EINVAL, "%s: bad arguments", fn);
     if (fmt != EMB_BIN && (!q_sq || !x_sq))
         return fail(DB_EINVAL, "%s: squared norms are required", fn);
+    if (fmt != EMB_BIN && (int64_t)M * dim * (fmt == EMB_BF16 ? 2 : 1) >= ((int64_t)1 << 31))
+        return fail(DB_EINVAL, "%s: query codes must stay below 2 GiB", fn);
     if (fmt == EMB_BIN) {
         if (dim % 32 || dim > 1024)
             return fail(DB_EINVAL, "%s: binary codes need dim %% 32 == 0, <= 1024", fn);

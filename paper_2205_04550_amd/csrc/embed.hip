@@ -122,73 +122,106 @@ __global__ void __launch_bounds__(256) quant_fp8_kernel(int dim, const float *__
     }
 }
 
-// Epilogue of the distance kernels. mode 0: D = d (squared L2); mode 1:
-// D = sqrt(max(d, 0)) (L2); mode 2: D += sqrt(max(d, 0)) (a second L2 added to
-// the first: the paper's L2_T1Gd + L2_FLAIR of two encoders, Sec. 2.3).
-__device__ __forceinline__ void dist_store(float *p, float d, int mode)
-{
-    if (mode == 0) {
-        *p = d;
-    } else {
-        const float l = __builtin_sqrtf(fmaxf(d, 0.0f));
-        *p = mode == 1 ? l : *p + l;
-    }
-}
-
-// ---- distance GEMM, LDS-staged --------------------------------------------------------------
+// ---- distance GEMM, LDS-staged ----------------------------------------------------------------
 //
-// Block tile 128 queries x 256 database rows, 8 waves as 2 x 4 of 64 x 64 (2 x 2
-// MFMA 32x32 tiles each). K is staged through LDS in slices of 64 bytes (32
-// bf16 or 64 fp8 values) for both operands, double-buffered with a register
-// prefetch of the next slice, so each operand row is read from L2 once per
-// block instead of once per wave. LDS rows are padded to 80 bytes to spread
-// the 16-byte fragment reads over the banks. Blocks are numbered so that the
-// query tiles of one database tile run one after another on the same XCD
-// (consecutive block numbers go to different XCDs): the database rows then
-// come from HBM once into that XCD's L2 and are reused by every query tile.
+// Tile 128 queries x 256 database rows, 8 waves as 2 x 4 of 64 x 64 (2 x 2 MFMA
+// 32x32 tiles each). K is staged through LDS in slices of 64 bytes (32 bf16 or
+// 64 fp8 values) for both operands, double-buffered, so each operand row is
+// read from L2 once per tile instead of once per wave. LDS rows are padded to
+// 80 bytes to spread the 16-byte fragment reads over the banks.
+//
+// The grid is persistent: block b of G (G a multiple of 8) takes the virtual
+// tiles b, b + G, b + 2G, ..., and the K slices of all its tiles form one
+// stream, loaded DEPTH slices ahead into a ring of registers. The loads of the
+// next tile are in flight while the current one finishes and writes its
+// distances, and DEPTH slices of load latency are covered instead of one.
+// Virtual tiles are numbered so that consecutive numbers go to different XCDs
+// (block b runs on XCD b % 8, and so do all its tiles): the blocks of one XCD
+// work on a few database tiles at a time with every query tile, so a database
+// tile comes from HBM into that XCD's L2 once and is reused there.
 constexpr int kDM = 128, kDN = 256, kDSlice = 64, kDRow = 80, kDThreads = 512;
 constexpr int kXcds = 8;
+// Row offsets into Q and X are 32-bit: the host splits X into chunks below this.
+constexpr int64_t kDChunkBytes = (int64_t)1 << 31;
 
-template <bool FP8>
-__global__ void __launch_bounds__(kDThreads) dist_lds_kernel(int M, int N, int K, int mt, int nt,
+template <bool FP8, bool TAIL, int DEPTH>
+__global__ void __launch_bounds__(kDThreads) dist_lds_kernel(int M, int N, int K, int mt,
+                                                             int ntiles,
                                                              const uint8_t *__restrict__ Q,
                                                              const float *__restrict__ qs,
                                                              const float *__restrict__ qn,
                                                              const uint8_t *__restrict__ X,
                                                              const float *__restrict__ xs,
                                                              const float *__restrict__ xn,
-                                                             float *__restrict__ D, int mode)
+                                                             float *__restrict__ D, int64_t ldd,
+                                                             int mode)
 {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2][(kDM + kDN) * kDRow];
-    const int p = blockIdx.x, xcd = p % kXcds, q = p / kXcds;
-    const int mtile = q % mt, ntile = (q / mt) * kXcds + xcd;
-    if (ntile >= nt) return;                       // whole block, before any barrier
-    const int m0 = mtile * kDM, n0 = ntile * kDN;
+    // Squared norms (and FP8 scales) of the rows of a tile, by tile parity:
+    // [0..127] query rows, [128..383] database rows.
+    __shared__ float tv[2][2][kDM + kDN];
+    const int G = gridDim.x, b = blockIdx.x;
+    const int Kb = FP8 ? K : 2 * K;                 // bytes per row
+    const int nslices = (Kb + kDSlice - 1) / kDSlice;
+    const int mytiles = b < ntiles ? (ntiles - 1 - b) / G + 1 : 0;
+    const int U = mytiles * nslices;                // K slices this block streams
+    if (U == 0) return;                             // whole block, before any barrier
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 2, wn = wave & 3;
     const int half = lane >> 5, r32 = lane & 31;
-    const int Kb = FP8 ? K : 2 * K;                 // bytes per row
-    const int nslices = (Kb + kDSlice - 1) / kDSlice;
-    // Staging: 384 rows x 4 chunks of 16 bytes = 1536 chunks, 3 per thread.
-    u32x4 pre[3];
-    auto fetch = [&](int sl) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const int c = j * kDThreads + tid;
-            const int row = c >> 2, part = c & 3;
-            const int kb = sl * kDSlice + part * 16;
-            const uint8_t *src;
-            if (row < kDM) src = Q + (int64_t)min(m0 + row, M - 1) * Kb;
-            else src = X + (int64_t)min(n0 + row - kDM, N - 1) * Kb;
-            pre[j] = kb < Kb ? *reinterpret_cast<const u32x4 *>(src + kb) : (u32x4){0u, 0u, 0u, 0u};
+    // Origin of the i-th tile of this block. A virtual tile past the last
+    // database tile (nt not a multiple of 8) has n0 >= N: its loads are clamped
+    // to the last row and it stores nothing.
+    auto origin = [&](int i, int &m0, int &n0) {
+        const int p = b + i * G, q = p / kXcds;
+        m0 = (q % mt) * kDM;
+        n0 = ((q / mt) * kXcds + p % kXcds) * kDN;
+    };
+    // Staging: 384 rows x 4 chunks of 16 bytes, 3 chunks per thread: chunk
+    // tid % 4 of query row tid / 4 and of database rows tid / 4 and 128 + tid / 4.
+    // With the first slice of a tile, threads 0..383 also load the norm (and
+    // scale) of row tid of the tile; they travel through the ring into tv
+    // (loads issued at the epilogue would wait for every load in flight, as the
+    // vector memory counter is in order).
+    const int frow = tid >> 2, fpart = (tid & 3) * 16;
+    u32x4 pre[DEPTH][3];
+    float prv[DEPTH][2];
+    auto fetch = [&](int v, u32x4 (&dst)[3], float (&dv)[2]) {
+        const int i = v / nslices, sl = v - i * nslices;
+        int m0, n0;
+        origin(i, m0, n0);
+        const uint32_t kb = (uint32_t)(sl * kDSlice + fpart);
+        if (!TAIL || (int)kb < Kb) {
+            const uint32_t o0 = (uint32_t)min(m0 + frow, M - 1) * (uint32_t)Kb + kb;
+            const uint32_t o1 = (uint32_t)min(n0 + frow, N - 1) * (uint32_t)Kb + kb;
+            const uint32_t o2 = (uint32_t)min(n0 + kDM + frow, N - 1) * (uint32_t)Kb + kb;
+            dst[0] = *reinterpret_cast<const u32x4 *>(Q + o0);
+            dst[1] = *reinterpret_cast<const u32x4 *>(X + o1);
+            dst[2] = *reinterpret_cast<const u32x4 *>(X + o2);
+        } else {
+            dst[0] = dst[1] = dst[2] = (u32x4){0u, 0u, 0u, 0u};
+        }
+        if (sl == 0 && tid < kDM + kDN) {
+            if (tid < kDM) {
+                const int row = min(m0 + tid, M - 1);
+                dv[0] = qn[row];
+                if (FP8) dv[1] = qs[row];
+            } else {
+                const int col = min(n0 + tid - kDM, N - 1);
+                dv[0] = xn[col];
+                if (FP8) dv[1] = xs[col];
+            }
         }
     };
-    auto stash = [&](int buf) {
+    auto stash = [&](int v, const u32x4 (&src)[3], const float (&sv)[2]) {
+        uint8_t *L = &lds[v & 1][0];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const int c = j * kDThreads + tid;
-            const int row = c >> 2, part = c & 3;
-            *reinterpret_cast<u32x4 *>(&lds[buf][row * kDRow + part * 16]) = pre[j];
+        for (int j = 0; j < 3; ++j)
+            *reinterpret_cast<u32x4 *>(&L[(j * kDM + frow) * kDRow + fpart]) = src[j];
+        const int i = v / nslices;
+        if (v - i * nslices == 0 && tid < kDM + kDN) {
+            tv[i & 1][0][tid] = sv[0];
+            if (FP8) tv[i & 1][1][tid] = sv[1];
         }
     };
     f32x16 acc[2][2];
@@ -201,12 +234,7 @@ __global__ void __launch_bounds__(kDThreads) dist_lds_kernel(int M, int N, int K
     f32x16 zero16;
 #pragma unroll
     for (int r = 0; r < 16; ++r) zero16[r] = 0.f;
-    fetch(0);
-    stash(0);
-    __syncthreads();
-    for (int sl = 0; sl < nslices; ++sl) {
-        const int buf = sl & 1;
-        if (sl + 1 < nslices) fetch(sl + 1);
+    auto compute = [&](int buf) {
         const uint8_t *A = &lds[buf][0], *B = &lds[buf][kDM * kDRow];
         if (FP8) {
             i32x8 a[2], b[2];
@@ -253,26 +281,69 @@ __global__ void __launch_bounds__(kDThreads) dist_lds_kernel(int M, int N, int K
                                                                             0, 0, 0);
             }
         }
-        if (sl + 1 < nslices) stash(buf ^ 1);
-        __syncthreads();
-    }
+    };
+    // Epilogue. mode 0: D = d (squared L2); mode 1: D = sqrt(max(d, 0)) (L2);
+    // mode 2: D += sqrt(max(d, 0)) (a second L2 added to the first: the paper's
+    // L2_T1Gd + L2_FLAIR of two encoders, Sec. 2.3).
+    auto epilogue = [&](int i_tile) {
+        int m0, n0;
+        origin(i_tile, m0, n0);
+        const float(&t)[2][kDM + kDN] = tv[i_tile & 1];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int col = n0 + wn * 64 + j * 32 + r32;
-            if (col >= N) continue;
-            const float xc = xn[col];
-            const float sc = FP8 ? xs[col] : 1.0f;
+            for (int j = 0; j < 2; ++j) {
+                const int cl = wn * 64 + j * 32 + r32, col = n0 + cl;
+                const int rl0 = wm * 64 + i * 32 + 4 * half;
+                const float xc = t[0][kDM + cl];
+                const float sc = FP8 ? t[1][kDM + cl] : 1.0f;
+                float *out = D + (int64_t)(m0 + rl0) * ldd + col;
+                const int rows = col < N ? M - (m0 + rl0) : 0;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = m0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                if (row < M) {
-                    const float dot = FP8 ? (qs[row] * sc) * acc[i][j][r] : acc[i][j][r];
-                    dist_store(D + (int64_t)row * N + col, (qn[row] + xc) - 2.0f * dot, mode);
+                for (int r = 0; r < 16; ++r) {
+                    const int rr = 8 * (r >> 2) + (r & 3), rl = rl0 + rr;
+                    const float dot = FP8 ? (t[1][rl] * sc) * acc[i][j][r] : acc[i][j][r];
+                    const float dv = (t[0][rl] + xc) - 2.0f * dot;
+                    if (rr < rows) {
+                        if (mode == 0) out[rr * ldd] = dv;
+                        else {
+                            const float l = __builtin_sqrtf(fmaxf(dv, 0.0f));
+                            out[rr * ldd] = mode == 1 ? l : out[rr * ldd] + l;
+                        }
+                    }
+                    acc[i][j][r] = 0.f;
                 }
             }
+    };
+    // Ring invariant: slot s holds the slice of step v with v % DEPTH == s, for
+    // the steps u + 1 .. u + DEPTH while step u is multiplied.
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d)
+        if (d < U) fetch(d, pre[d], prv[d]);
+    stash(0, pre[0], prv[0]);
+    if (DEPTH < U) fetch(DEPTH, pre[0], prv[0]);
+    __syncthreads();
+    int tile = 0, sl = 0;
+    for (int u0 = 0; u0 < U; u0 += DEPTH) {
+#pragma unroll
+        for (int d = 0; d < DEPTH; ++d) {
+            const int u = u0 + d;
+            if (u < U) {
+                compute(u & 1);
+                if (u + 1 < U) {
+                    const int nx = (d + 1) % DEPTH;
+                    stash(u + 1, pre[nx], prv[nx]);
+                    if (u + 1 + DEPTH < U) fetch(u + 1 + DEPTH, pre[nx], prv[nx]);
+                }
+                if (++sl == nslices) {
+                    epilogue(tile);
+                    ++tile;
+                    sl = 0;
+                }
+                __syncthreads();
+            }
         }
+    }
 }
 
 // ---- exact k smallest per row (radix select) ----------------------------------------------
@@ -999,36 +1070,73 @@ hipError_t launch_quant_fp8(int64_t n, int dim, const float *x, uint8_t *y, floa
     return hipGetLastError();
 }
 
-static unsigned dist_lds_grid(int M, int N, int *mt, int *nt)
+// Persistent grid of the distance kernel: as many blocks as fit on the device
+// at once (a multiple of 8, so each block keeps its XCD), at most one per tile.
+// X is taken in chunks of fewer than 2^31 bytes (32-bit row offsets), each
+// chunk one launch writing its columns of D.
+template <bool FP8, bool TAIL, int DEPTH>
+static hipError_t dist_lds_launch(int M, int N, int K, const uint8_t *Q, const float *qs,
+                                  const float *qn, const uint8_t *X, const float *xs,
+                                  const float *xn, float *D, int mode, hipStream_t s)
 {
-    *mt = (M + kDM - 1) / kDM;
-    *nt = (N + kDN - 1) / kDN;
-    return (unsigned)(kXcds * *mt * ((*nt + kXcds - 1) / kXcds));
+    static int resident[64];                        // per device: blocks resident at once
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (resident[dev] == 0) {
+        int cus = 0, per_cu = 0;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, dist_lds_kernel<FP8, TAIL, DEPTH>, kDThreads, 0);
+        if (e != hipSuccess) return e;
+        resident[dev] = max(kXcds, (cus * max(per_cu, 1)) / kXcds * kXcds);
+    }
+    const int64_t Kb = FP8 ? K : 2 * (int64_t)K;
+    if ((int64_t)M * Kb >= kDChunkBytes) return hipErrorInvalidValue;
+    const int chunk = (int)(((kDChunkBytes - 1) / Kb) / kDN * kDN);
+    const int mt = (M + kDM - 1) / kDM;
+    for (int c0 = 0; c0 < N; c0 += chunk) {
+        const int n = min(chunk, N - c0);
+        const int nt = (n + kDN - 1) / kDN;
+        const int ntiles = kXcds * mt * ((nt + kXcds - 1) / kXcds);   // a multiple of 8
+        const int g = min(ntiles, resident[dev]);
+        hipLaunchKernelGGL((dist_lds_kernel<FP8, TAIL, DEPTH>), dim3(g), dim3(kDThreads), 0, s, M,
+                           n, K, mt, ntiles, Q, qs, qn, X + c0 * Kb, FP8 ? xs + c0 : nullptr,
+                           xn + c0, D + c0, (int64_t)N, mode);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
+
+// Register ring depth (K slices in flight per block). BF16 stays at one, which
+// keeps it within 128 VGPRs (two blocks per CU); FP8 holds one block per CU in
+// any case (the separate FP32 accumulation needs more registers) and uses the
+// room for three slices in flight.
+constexpr int kDDepthBf16 = 1, kDDepthFp8 = 3;
 
 hipError_t launch_dist_bf16(int M, int N, int K, const uint16_t *Q, const float *qn,
                             const uint16_t *X, const float *xn, float *D, int mode, hipStream_t s)
 {
-    int mt, nt;
-    const unsigned g = dist_lds_grid(M, N, &mt, &nt);
-    hipLaunchKernelGGL(dist_lds_kernel<false>, dim3(g), dim3(kDThreads), 0, s, M, N, K, mt, nt,
-                       reinterpret_cast<const uint8_t *>(Q), nullptr, qn,
-                       reinterpret_cast<const uint8_t *>(X), nullptr, xn, D, mode);
-    return hipGetLastError();
+    const auto *q = reinterpret_cast<const uint8_t *>(Q);
+    const auto *x = reinterpret_cast<const uint8_t *>(X);
+    if ((2 * K) % kDSlice)
+        return dist_lds_launch<false, true, kDDepthBf16>(M, N, K, q, nullptr, qn, x, nullptr, xn,
+                                                         D, mode, s);
+    return dist_lds_launch<false, false, kDDepthBf16>(M, N, K, q, nullptr, qn, x, nullptr, xn, D,
+                                                      mode, s);
 }
 
 hipError_t launch_dist_fp8(int M, int N, int K, const uint8_t *Q, const float *qs, const float *qn,
                            const uint8_t *X, const float *xs, const float *xn, float *D,
                            int mode, hipStream_t s)
 {
-    int mt, nt;
-    const unsigned g = dist_lds_grid(M, N, &mt, &nt);
-    hipLaunchKernelGGL(dist_lds_kernel<true>, dim3(g), dim3(kDThreads), 0, s, M, N, K, mt, nt, Q, qs,
-                       qn, X, xs, xn, D, mode);
-    return hipGetLastError();
+    if (K % kDSlice) return hipErrorInvalidValue;   // FP8 rows are whole slices
+    return dist_lds_launch<true, false, kDDepthFp8>(M, N, K, Q, qs, qn, X, xs, xn, D, mode, s);
 }
 
-// m of the bound-and-filter path, or 0 when it does not apply (too few full chunks).
 // m of the bound-and-filter path with `per` entries per thread, or 0 when it does not
 // apply (too few full chunks).
 static int tau_m_per(int N, int k, int per)
