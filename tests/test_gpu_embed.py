@@ -68,6 +68,40 @@ def test_distances_within_contract(fmt, dim):
     assert np.all(err <= bound)
 
 
+@pytest.mark.parametrize("fmt,M,N,dim", [(0, 300, 50_021, 512), (1, 300, 50_021, 512),
+                                         (0, 3, 1_100_000, 1024)])
+def test_distances_many_tiles_and_chunks(fmt, M, N, dim):
+    """Many tiles per block of the persistent grid, a ragged last query tile, and (BF16,
+    dim 1024, 1.1M rows = 2.25 GB of codes) a database taken in two chunks: sampled
+    columns (both ends, the chunk boundary at row 1,048,320, random) within the contract."""
+    need_gpu()
+    from paper_2205_04550_amd import binding as b
+    g = torch.Generator(device="cuda").manual_seed(31)
+    Qf = torch.randn(M, dim, generator=g, device="cuda")
+    Xf = torch.randn(N, dim, generator=g, device="cuda")
+    Q, X = b.Latents(Qf, fmt), b.Latents(Xf, fmt)
+    del Xf
+    D = b.emb_distances(Q, X)
+    rng = np.random.default_rng(3)
+    cols = np.unique(np.concatenate([np.arange(200), np.arange(N - 300, N),
+                                     np.arange(1_048_320 - 64, 1_048_320 + 64) if N > 1_048_384
+                                     else np.arange(0),
+                                     rng.integers(0, N, 500)]))
+    cols_d = torch.from_numpy(cols).cuda()
+    class Sub:                                    # the sampled database rows, as Latents
+        pass
+    xs = Sub()
+    xs.fmt, xs.codes = fmt, X.codes[cols_d].cpu()
+    xs.scale = X.scale[cols_d].cpu() if X.scale is not None else None
+    q, x = _dequant(Q), _dequant(xs)
+    d64 = E.sqdist_direct(q, x)
+    got = D[:, cols_d].cpu().numpy().astype(np.float64)
+    rel = 1e-5 if fmt == b.EMB_BF16 else 5e-5
+    bound = rel * ((q ** 2).sum(1)[:, None] + (x ** 2).sum(1)[None, :])
+    say(f"fmt {fmt} {M} x {N} x {dim}: max |d - d64| / bound = {(np.abs(got - d64) / bound).max():.3g}")
+    assert np.all(np.abs(got - d64) <= bound)
+
+
 def test_topk_min_exact_with_ties():
     need_gpu()
     from paper_2205_04550_amd import binding as b
