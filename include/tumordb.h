@@ -211,6 +211,24 @@ size_t emb_topk_min_workspace_bytes(int M, int N, int k);
 int emb_topk_min(int M, int N, const float *D, int k, int32_t *idx, float *d, void *ws,
                  size_t ws_bytes, void *stream);
 
+/* The same distances and selection in two calls that share a workspace ws
+ * (device, 16-byte aligned) of emb_groups_workspace_bytes(M, N) bytes:
+ * emb_distances_groups writes D exactly as emb_distances (BF16 or FP8 only) and
+ * also, into ws, the smallest value of every whole group of 16 consecutive
+ * entries of each row; emb_topk_groups then gives exactly what emb_topk_min
+ * gives for that D, but bounds the k smallest from the group minima (1/16 of
+ * D's bytes) and reads only the groups that can hold them. Where k is too
+ * large for the bound (more than 8 per full chunk of 2,048 entries) it selects
+ * each row with one block. ws must not change between the two calls, which
+ * take the same M and N; DB_ENOSPC if ws is missing or too small. */
+size_t emb_groups_workspace_bytes(int M, int N);
+int emb_distances_groups(int fmt, int M, int N, int dim, const void *q_codes,
+                         const float *q_scale, const float *q_sq, const void *x_codes,
+                         const float *x_scale, const float *x_sq, float *D, void *ws,
+                         size_t ws_bytes, void *stream);
+int emb_topk_groups(int M, int N, const float *D, int k, int32_t *idx, float *d, void *ws,
+                    size_t ws_bytes, void *stream);
+
 /* Exact re-scoring: for query q (labels [nq][nz][ny][nx]) and its candidate
  * entries cand [nq][nc] (device int32, each in [0, db_size())), the k best by
  * Dice_T1Gd + Dice_FLAIR (score desc, index asc) among the candidates.

@@ -25,7 +25,8 @@ SYMBOLS = ("db_storage_bytes", "db_build", "db_append", "db_size", "db_query_wor
            "db_query_embed", "db_tune_batch", "db_append_resampled", "labels_resample",
            "db_query_sparse", "db_query_com_workspace_bytes", "db_query_com",
            "emb_hash_thresholds", "emb_binarize", "emb_distances_l2sum", "db_rerank_pack",
-           "db_rerank_packed")
+           "db_rerank_packed", "emb_groups_workspace_bytes", "emb_distances_groups",
+           "emb_topk_groups")
 EMB_BF16, EMB_FP8, EMB_BIN = 0, 1, 2
 
 
@@ -69,6 +70,9 @@ def _load():
         "emb_distances": (i32, [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]),
         "emb_topk_min": (i32, [i32, i32, vp, i32, vp, vp, vp, sz, vp]),
         "emb_topk_min_workspace_bytes": (sz, [i32, i32, i32]),
+        "emb_groups_workspace_bytes": (sz, [i32, i32]),
+        "emb_distances_groups": (i32, [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+        "emb_topk_groups": (i32, [i32, i32, vp, i32, vp, vp, vp, sz, vp]),
         "emb_hash_thresholds": (i32, [i64, i32, vp, vp, vp]),
         "emb_distances_l2sum": (i32, [i32, i32, i32, i32] + [vp] * 12 + [vp, vp]),
         "emb_binarize": (i32, [i64, i32, vp, vp, vp, vp]),
@@ -457,6 +461,31 @@ def emb_topk_min(D: torch.Tensor, k: int, stream=None, chunked: bool = True):
     ws = torch.empty(nb, dtype=torch.uint8, device=D.device) if nb else None
     _check(LIB.emb_topk_min(M, N, D.contiguous().data_ptr(), k, idx.data_ptr(), val.data_ptr(),
                             _ptr(ws), nb, _stream(stream)))
+    return idx, val
+
+
+def groups_workspace(M: int, N: int, device="cuda") -> torch.Tensor:
+    """Workspace shared by emb_distances_groups and emb_topk_groups for [M][N] distances."""
+    return torch.empty(LIB.emb_groups_workspace_bytes(M, N), dtype=torch.uint8, device=device)
+
+
+def emb_distances_groups(q, x, ws: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+    """emb_distances (BF16 / FP8), also leaving each row's 16-entry group minima in ws."""
+    if out is None:
+        out = torch.empty((q.n, x.n), dtype=torch.float32, device=q.codes.device)
+    _check(LIB.emb_distances_groups(q.fmt, q.n, x.n, q.dim, q.codes.data_ptr(), _ptr(q.scale),
+                                    _ptr(q.sq), x.codes.data_ptr(), _ptr(x.scale), _ptr(x.sq),
+                                    out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return out
+
+
+def emb_topk_groups(D: torch.Tensor, k: int, ws: torch.Tensor, stream=None):
+    """emb_topk_min's result for D, bounded by the group minima emb_distances_groups left in ws."""
+    M, N = D.shape
+    idx = torch.empty((M, k), dtype=torch.int32, device=D.device)
+    val = torch.empty((M, k), dtype=torch.float32, device=D.device)
+    _check(LIB.emb_topk_groups(M, N, D.data_ptr(), k, idx.data_ptr(), val.data_ptr(),
+                               ws.data_ptr(), ws.numel(), _stream(stream)))
     return idx, val
 
 

@@ -255,16 +255,16 @@ static int dist_check(const char *fn, int fmt, int M, int N, int dim, const void
 static hipError_t dist_launch(int fmt, int M, int N, int dim, const void *q_codes,
                               const float *q_scale, const float *q_sq, const void *x_codes,
                               const float *x_scale, const float *x_sq, float *D, int mode,
-                              hipStream_t s)
+                              hipStream_t s, uint32_t *gmin = nullptr)
 {
     if (fmt == EMB_BIN)
         return launch_hamming(M, N, dim / 32, static_cast<const uint32_t *>(q_codes),
                               static_cast<const uint32_t *>(x_codes), D, s);
     if (fmt == EMB_BF16)
         return launch_dist_bf16(M, N, dim, static_cast<const uint16_t *>(q_codes), q_sq,
-                                static_cast<const uint16_t *>(x_codes), x_sq, D, mode, s);
+                                static_cast<const uint16_t *>(x_codes), x_sq, D, mode, gmin, s);
     return launch_dist_fp8(M, N, dim, static_cast<const uint8_t *>(q_codes), q_scale, q_sq,
-                           static_cast<const uint8_t *>(x_codes), x_scale, x_sq, D, mode, s);
+                           static_cast<const uint8_t *>(x_codes), x_scale, x_sq, D, mode, gmin, s);
 }
 
 // Sort the entries by the centre of their row boxes (z in bands of 8 planes,
@@ -759,6 +759,45 @@ int nn_bihalf_bwd(int dtype, int B, int D, double gamma, const void *U, const vo
     return DB_OK;
 }
 
+size_t emb_groups_workspace_bytes(int M, int N)
+{
+    if (M <= 0 || N <= 0) return 0;
+    return topk_groups_ws_bytes(M, N);
+}
+
+int emb_distances_groups(int fmt, int M, int N, int dim, const void *q_codes,
+                         const float *q_scale, const float *q_sq, const void *x_codes,
+                         const float *x_scale, const float *x_sq, float *D, void *ws,
+                         size_t ws_bytes, void *stream)
+{
+    int rc = dist_check("emb_distances_groups", fmt, M, N, dim, q_codes, q_scale, q_sq, x_codes,
+                        x_scale, x_sq, D);
+    if (rc) return rc;
+    if (fmt == EMB_BIN) return fail(DB_EINVAL, "emb_distances_groups: BF16 or FP8 latents only");
+    const size_t need = topk_groups_ws_bytes(M, N);
+    if (!ws || !aligned(ws, 16) || ws_bytes < need)
+        return fail(DB_ENOSPC, "emb_distances_groups: workspace %zu bytes < %zu needed (16-byte "
+                    "aligned)", ws ? ws_bytes : 0, need);
+    hipError_t e = dist_launch(fmt, M, N, dim, q_codes, q_scale, q_sq, x_codes, x_scale, x_sq, D,
+                               0, static_cast<hipStream_t>(stream), topk_groups_gmin(ws, M));
+    if (e != hipSuccess) return hip_fail(e, "emb_distances_groups: launch");
+    return DB_OK;
+}
+
+int emb_topk_groups(int M, int N, const float *D, int k, int32_t *idx, float *d, void *ws,
+                    size_t ws_bytes, void *stream)
+{
+    if (M <= 0 || N <= 0 || !D || !idx || !d || k < 1 || k > N || k > DB_KMAX)
+        return fail(DB_EINVAL, "emb_topk_groups: bad arguments (k = %d, N = %d)", k, N);
+    const size_t need = topk_groups_ws_bytes(M, N);
+    if (!ws || !aligned(ws, 16) || ws_bytes < need)
+        return fail(DB_ENOSPC, "emb_topk_groups: workspace %zu bytes < %zu needed (16-byte "
+                    "aligned)", ws ? ws_bytes : 0, need);
+    hipError_t e = launch_topk_groups(M, N, k, D, ws, idx, d, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "emb_topk_groups: launch");
+    return DB_OK;
+}
+
 size_t emb_topk_min_workspace_bytes(int M, int N, int k)
 {
     if (M <= 0 || N <= 0 || k < 1 || k > N || k > DB_KMAX) return 0;
@@ -918,7 +957,9 @@ static size_t embed_layout(const db_t *db, int nq, int n_cand, size_t *o_D, size
     size_t a, b, c, d;
     *o_rr = take(rerank_layout(db, nq, &a, &b, &c, &d));
     const int ncap = db->capacity > INT32_MAX ? INT32_MAX : (int)db->capacity;
-    const size_t sb = n_cand <= ncap ? topk_min_ws_bytes(nq, ncap, n_cand) : 0;
+    const size_t sb = n_cand <= ncap ? std::max(topk_min_ws_bytes(nq, ncap, n_cand),
+                                                topk_groups_ws_bytes(nq, ncap))
+                                     : 0;
     const size_t os = take(sb);
     if (o_sel) *o_sel = os;
     if (sel_bytes) *sel_bytes = sb;
@@ -952,13 +993,21 @@ int db_query_embed(const db_t *db, int fmt, int nq, int dim, const void *q_codes
     float *D = at<float>(ws, oD);
     int32_t *ci = cand_idx ? cand_idx : at<int32_t>(ws, oci);
     float *cd = cand_d ? cand_d : at<float>(ws, ocd);
-    rc = emb_distances(fmt, nq, (int)n, dim, q_codes, q_scale, q_sq, x_codes, x_scale, x_sq, D,
-                       stream);
-    if (rc) return rc;
     size_t osel, sel_bytes;
     embed_layout(db, nq, n_cand, &oD, &oci, &ocd, &orr, &osel, &sel_bytes);
-    rc = emb_topk_min(nq, (int)n, D, n_cand, ci, cd, sel_bytes ? at<char>(ws, osel) : nullptr,
-                      sel_bytes, stream);
+    void *sel = sel_bytes ? at<char>(ws, osel) : nullptr;
+    if (fmt != EMB_BIN && sel && sel_bytes >= topk_groups_ws_bytes(nq, (int)n)) {
+        // Distances with their group minima, then the bound read from those.
+        rc = emb_distances_groups(fmt, nq, (int)n, dim, q_codes, q_scale, q_sq, x_codes, x_scale,
+                                  x_sq, D, sel, sel_bytes, stream);
+        if (rc) return rc;
+        rc = emb_topk_groups(nq, (int)n, D, n_cand, ci, cd, sel, sel_bytes, stream);
+    } else {
+        rc = emb_distances(fmt, nq, (int)n, dim, q_codes, q_scale, q_sq, x_codes, x_scale, x_sq,
+                           D, stream);
+        if (rc) return rc;
+        rc = emb_topk_min(nq, (int)n, D, n_cand, ci, cd, sel, sel_bytes, stream);
+    }
     if (rc) return rc;
     hipError_t e = enqueue_rerank(db, nq, q_labels, ci, n_cand, k, idx, score, counts,
                                   at<char>(ws, orr), static_cast<hipStream_t>(stream));

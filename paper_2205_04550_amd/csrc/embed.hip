@@ -144,8 +144,39 @@ constexpr int kXcds = 8;
 // Row offsets into Q and X are 32-bit: the host splits X into chunks below this.
 constexpr int64_t kDChunkBytes = (int64_t)1 << 31;
 
-template <bool FP8, bool TAIL, int DEPTH>
-__global__ void __launch_bounds__(kDThreads) dist_lds_kernel(int M, int N, int K, int mt,
+// v of the lane that DPP control `ctrl` names within this lane's row of 16 (all lanes active).
+template <int ctrl>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, ctrl, 0xf, 0xf, false);
+}
+
+// Reduce-scatter of minima over each row of 16 lanes: lane l returns the minimum of
+// k[l % 16] over the 16 lanes of its row. Four exchange steps (row mirror, half-row
+// mirror, xor 2, xor 1); in each a lane keeps the half of its values that the lane
+// bit of that step selects and sends the other half to its partner.
+__device__ __forceinline__ uint32_t row16_min_scatter(const uint32_t (&k)[16], int lane)
+{
+    const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
+    uint32_t k1[8], k2[4], k3[2];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        k1[q] = min(b3 ? k[q + 8] : k[q], dpp_u32<0x140>(b3 ? k[q] : k[q + 8]));      // mirror
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        k2[q] = min(b2 ? k1[q + 4] : k1[q], dpp_u32<0x141>(b2 ? k1[q] : k1[q + 4]));  // half mirror
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+        k3[q] = min(b1 ? k2[q + 2] : k2[q], dpp_u32<0x4e>(b1 ? k2[q] : k2[q + 2]));   // xor 2
+    return min(b0 ? k3[1] : k3[0], dpp_u32<0xb1>(b0 ? k3[0] : k3[1]));                // xor 1
+}
+
+// GMIN: also write, for every row and every whole group of 16 consecutive columns
+// g < ngroups, the smallest order key (fkey) of the group's distances to
+// gmin[row * gld + g]; the bound of the top-k selection below then reads these
+// instead of the distances (mode 0 only).
+template <bool FP8, bool TAIL, int DEPTH, bool GMIN>
+__global__ void __launch_bounds__(kDThreads, FP8 ? 1 : 4) dist_lds_kernel(int M, int N, int K, int mt,
                                                              int ntiles,
                                                              const uint8_t *__restrict__ Q,
                                                              const float *__restrict__ qs,
@@ -154,7 +185,8 @@ __global__ void __launch_bounds__(kDThreads) dist_lds_kernel(int M, int N, int K
                                                              const float *__restrict__ xs,
                                                              const float *__restrict__ xn,
                                                              float *__restrict__ D, int64_t ldd,
-                                                             int mode)
+                                                             int mode, uint32_t *__restrict__ gmin,
+                                                             int64_t gld, int ngroups)
 {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2][(kDM + kDN) * kDRow];
     // Squared norms (and FP8 scales) of the rows of a tile, by tile parity:
@@ -299,6 +331,7 @@ __global__ void __launch_bounds__(kDThreads) dist_lds_kernel(int M, int N, int K
                 const float sc = FP8 ? t[1][kDM + cl] : 1.0f;
                 float *out = D + (int64_t)(m0 + rl0) * ldd + col;
                 const int rows = col < N ? M - (m0 + rl0) : 0;
+                uint32_t key[16];
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int rr = 8 * (r >> 2) + (r & 3), rl = rl0 + rr;
@@ -311,7 +344,15 @@ __global__ void __launch_bounds__(kDThreads) dist_lds_kernel(int M, int N, int K
                             out[rr * ldd] = mode == 1 ? l : out[rr * ldd] + l;
                         }
                     }
+                    key[r] = col < N ? fkey(dv) : 0xffffffffu;
                     acc[i][j][r] = 0.f;
+                }
+                if (GMIN) {                   // all 64 lanes active: DPP reads whole rows
+                    const uint32_t gm = row16_min_scatter(key, lane);   // row rl0 + rr(lane % 16)
+                    const int rr = 8 * ((lane & 15) >> 2) + (lane & 3);
+                    const int g = (n0 + wn * 64 + j * 32 + (lane & 16)) >> 4;
+                    if (m0 + rl0 + rr < M && g < ngroups)
+                        gmin[(int64_t)(m0 + rl0 + rr) * gld + g] = gm;
                 }
             }
     };
@@ -904,16 +945,52 @@ constexpr int kTauCap = 4096;
 // Entries per thread: 16 (chunks of 8,192) for long rows, 4 (chunks of 2,048) where
 // that gives too few chunks for m <= kTauMaxM.
 
-// Rank of lane value x among the first n lanes' values of the wave (ties by lane):
-// a permutation of 0..n-1 over those lanes.
-__device__ __forceinline__ int wave_rank(uint32_t x, int lane, int n)
+// Minimum of v over the wave (all lanes active), the same in every lane: DPP
+// rotations within each row of 16, then the four row results.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
 {
-    int rank = 0;
-    for (int j = 0; j < n; ++j) {
-        const uint32_t y = (uint32_t)__shfl((int)x, j, 64);
-        rank += (y < x) || (y == x && j < lane);
+    v = min(v, dpp_u32<0x128>(v));   // row_ror 8
+    v = min(v, dpp_u32<0x124>(v));   // row_ror 4
+    v = min(v, dpp_u32<0x122>(v));   // row_ror 2
+    v = min(v, dpp_u32<0x121>(v));   // row_ror 1
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32);
+    const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+    return min(min(a, b), min(c, d));
+}
+
+// The m smallest of the wave's values v (one per lane; m <= kTauMaxM), ascending, into
+// out[0..m) (written by lane 0): m rounds of a wave minimum, each removing one lane
+// holding it (the lowest), so equal values count once per lane.
+__device__ __forceinline__ void wave_smallest(uint32_t v, int m, int lane, uint32_t *out)
+{
+    for (int i = 0; i < m; ++i) {
+        const uint32_t mn = wave_min_u32(v);
+        const uint64_t hold = __ballot(v == mn);
+        if (lane == __ffsll((unsigned long long)hold) - 1) v = 0xffffffffu;
+        if (lane == 0) out[i] = mn;
     }
-    return rank;
+}
+
+// m-th smallest (1 <= m <= kTauMaxM) of one value per thread of a block of W waves:
+// each wave's m smallest into wl, then the m smallest of those W * m in wave 0. The
+// result is valid in wave 0 (returned there; other waves return 0).
+template <int W>
+__device__ __forceinline__ uint32_t block_mth_smallest(uint32_t v, int m, uint32_t (&wl)[W][kTauMaxM])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    wave_smallest(v, m, lane, wl[wave]);
+    __syncthreads();
+    if (wave != 0) return 0;
+    uint32_t x = lane < W * m ? wl[lane / m][lane % m] : 0xffffffffu;
+    uint32_t mth = 0;
+    for (int i = 0; i < m; ++i) {
+        mth = wave_min_u32(x);
+        const uint64_t hold = __ballot(x == mth);
+        if (lane == __ffsll((unsigned long long)hold) - 1) x = 0xffffffffu;
+    }
+    return mth;
 }
 
 // grid (C, M), kTauThreads threads: tau[row] = max(tau[row], m-th smallest thread minimum);
@@ -929,7 +1006,7 @@ __global__ void __launch_bounds__(kTauThreads) topk_tau_kernel(const float *__re
     const int base = blockIdx.x * kTauChunk;
     if (N - base < kTauChunk) return;                 // partial chunk: no bound from it
     const float *row = D + r * N + base;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     uint32_t mn = 0xffffffffu;
     if ((N & 3) == 0) {      // 16-byte aligned rows: 4 entries per load
         const f32x4 *row4 = reinterpret_cast<const f32x4 *>(row);
@@ -944,16 +1021,50 @@ __global__ void __launch_bounds__(kTauThreads) topk_tau_kernel(const float *__re
         for (int u = 0; u < kTauPer; ++u) mn = min(mn, fkey(row[u * kTauThreads + tid]));
     }
     tmin[((int64_t)r * gridDim.x + blockIdx.x) * kTauThreads + tid] = mn;
-    // The kTauMaxM smallest thread minima of each wave, then the m-th smallest of those
-    // across the block: lane ranks by shuffles, no serial merges.
-    const int rk = wave_rank(mn, lane, 64);
-    if (rk < kTauMaxM) wl[wave][rk] = mn;
+    const uint32_t mth = block_mth_smallest<kTauThreads / 64>(mn, m, wl);
+    if (tid == 0) atomicMax(&tau[r], mth);
+}
+
+// The list of nc (key, index) pairs in LDS (the block's gather, after a barrier):
+// sort by (key, index) and write the first k. A list longer than kTauCap was not
+// kept whole: the row is selected by the one-block radix path instead.
+__device__ __forceinline__ void list_sort_emit(uint32_t *sk, int32_t *si, uint32_t nc,
+                                               const float *__restrict__ row, int N, int k,
+                                               int32_t *__restrict__ out_idx,
+                                               float *__restrict__ out_d)
+{
+    if (nc > (uint32_t)kTauCap) {
+        select_row_radix(row, N, k, out_idx, out_d);
+        return;
+    }
+    int P = 1;
+    while (P < (int)nc) P <<= 1;
+    for (int q = (int)nc + threadIdx.x; q < P; q += blockDim.x) {
+        sk[q] = 0xffffffffu;
+        si[q] = INT_MAX;
+    }
+    for (int size = 2; size <= P; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int q = threadIdx.x; q < P / 2; q += blockDim.x) {
+                const int i = 2 * q - (q & (stride - 1));
+                const int j = i + stride;
+                const bool up = (i & size) == 0;
+                const uint32_t ki = sk[i], kj = sk[j];
+                const int32_t ii = si[i], ij = si[j];
+                const bool j_first = kj < ki || (kj == ki && ij < ii);
+                if (j_first == up) {
+                    sk[i] = kj;
+                    sk[j] = ki;
+                    si[i] = ij;
+                    si[j] = ii;
+                }
+            }
+        }
     __syncthreads();
-    if (wave == 0) {
-        constexpr int n = (kTauThreads / 64) * kTauMaxM;
-        const uint32_t x = lane < n ? wl[lane / kTauMaxM][lane % kTauMaxM] : 0xffffffffu;
-        const int r2 = wave_rank(x, lane, n);
-        if (lane < n && r2 == m - 1) atomicMax(&tau[r], x);
+    for (int q = threadIdx.x; q < k; q += blockDim.x) {
+        out_idx[q] = si[q];
+        out_d[q] = fkey_inv(sk[q]);
     }
 }
 
@@ -1018,40 +1129,171 @@ __global__ void __launch_bounds__(kSelThreads) topk_list_kernel(const float *__r
         if (key <= t) push(key, i);
     }
     __syncthreads();
-    const uint32_t nc = s_n;
-    if (nc > (uint32_t)kTauCap) {
-        select_row_radix(row, N, k, out_idx + r * k, out_d + r * k);
-        return;
+    list_sort_emit(sk, si, s_n, row, N, k, out_idx + r * k, out_d + r * k);
+}
+
+// ---- the same bound from the distance kernel's group minima ------------------------------
+//
+// With GMIN the distance kernel leaves, per row, the minimum key of every whole
+// group of 16 consecutive entries. A chunk of CG groups (CG * 16 entries) has
+// at least m entries <= the m-th smallest of its group minima, so the bound
+// above holds with groups in place of threads, and it is found by reading
+// 1/16 of the distances' bytes; the gather reads only the groups whose minimum
+// is <= tau (and the entries after the last whole chunk).
+
+// grid (ceil(C / 4), M), 256 threads: wave w of block x takes chunk 4x + w (< C) of
+// 64 * PER group minima, PER per lane, and raises tau[row] to the m-th smallest of
+// them (m rounds of a wave minimum over the lanes' smallest remaining values, each
+// round removing one copy of it).
+template <int PER>
+__global__ void __launch_bounds__(256) topk_tau_groups_kernel(const uint32_t *__restrict__ gmin,
+                                                             int64_t gld, int chunks, int m,
+                                                             uint32_t *__restrict__ tau)
+{
+    const int lane = threadIdx.x & 63, c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (c >= chunks) return;                      // whole wave; no barriers here
+    const int64_t r = blockIdx.y;
+    const uint32_t *p = gmin + r * gld + (int64_t)c * 64 * PER;
+    uint32_t v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) v[q] = p[q * 64 + lane];
+    auto lane_min = [&]() {
+        uint32_t x = v[0];
+#pragma unroll
+        for (int q = 1; q < PER; ++q) x = min(x, v[q]);
+        return x;
+    };
+    uint32_t lm = lane_min(), mn = 0;
+    for (int i = 0;; ++i) {
+        mn = wave_min_u32(lm);
+        if (i + 1 == m) break;
+        const uint64_t hold = __ballot(lm == mn);
+        if (lane == __ffsll((unsigned long long)hold) - 1) {
+            bool done = false;
+#pragma unroll
+            for (int q = 0; q < PER; ++q)
+                if (!done && v[q] == mn) {
+                    v[q] = 0xffffffffu;
+                    done = true;
+                }
+            lm = lane_min();
+        }
     }
-    int P = 1;
-    while (P < (int)nc) P <<= 1;
-    for (int q = (int)nc + threadIdx.x; q < P; q += blockDim.x) {
-        sk[q] = 0xffffffffu;
-        si[q] = INT_MAX;
-    }
-    for (int size = 2; size <= P; size <<= 1)
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            __syncthreads();
-            for (int q = threadIdx.x; q < P / 2; q += blockDim.x) {
-                const int i = 2 * q - (q & (stride - 1));
-                const int j = i + stride;
-                const bool up = (i & size) == 0;
-                const uint32_t ki = sk[i], kj = sk[j];
-                const int32_t ii = si[i], ij = si[j];
-                const bool j_first = kj < ki || (kj == ki && ij < ii);
-                if (j_first == up) {
-                    sk[i] = kj;
-                    sk[j] = ki;
-                    si[i] = ij;
-                    si[j] = ii;
+    if (lane == 0) atomicMax(&tau[r], mn);
+}
+
+// grid M, kSelThreads threads: the entries of row r with key <= tau[r], from the
+// groups g < nslots whose minimum is <= tau and from entries nslots * 16 .. N - 1;
+// sorted, the first k written.
+__global__ void __launch_bounds__(kSelThreads) topk_list_groups_kernel(
+    const float *__restrict__ D, int N, int k, const uint32_t *__restrict__ tau,
+    const uint32_t *__restrict__ gmin, int64_t gld, int nslots, int32_t *__restrict__ out_idx,
+    float *__restrict__ out_d)
+{
+    __shared__ uint32_t sk[kTauCap];
+    __shared__ int32_t si[kTauCap];
+    __shared__ uint32_t s_n;
+    const int64_t r = blockIdx.x;
+    const float *row = D + r * N;
+    const uint32_t t = tau[r];
+    const bool v4 = (N & 3) == 0;                 // 16-byte aligned rows
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    auto push = [&](uint32_t key, int i) {
+        const uint32_t pos = atomicAdd(&s_n, 1u);
+        if (pos < (uint32_t)kTauCap) {
+            sk[pos] = key;
+            si[pos] = i;
+        }
+    };
+    auto gather = [&](int g) {                    // the 16 entries of group g
+        const int base = 16 * g;
+        if (v4) {
+            const f32x4 *p = reinterpret_cast<const f32x4 *>(row + base);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const f32x4 x = p[q];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t key = fkey(x[e]);
+                    if (key <= t) push(key, base + 4 * q + e);
                 }
             }
+        } else {
+#pragma unroll 4
+            for (int e = 0; e < 16; ++e) {
+                const uint32_t key = fkey(row[base + e]);
+                if (key <= t) push(key, base + e);
+            }
         }
-    __syncthreads();
-    for (int q = threadIdx.x; q < k; q += blockDim.x) {
-        out_idx[r * k + q] = si[q];
-        out_d[r * k + q] = fkey_inv(sk[q]);
+    };
+    // Four group minima in flight per thread, then the groups that pass.
+    for (int g0 = threadIdx.x; g0 < nslots; g0 += 4 * kSelThreads) {
+        uint32_t gv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int g = g0 + u * kSelThreads;
+            gv[u] = g < nslots ? gmin[r * gld + g] : 0xffffffffu;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (gv[u] <= t) gather(g0 + u * kSelThreads);
     }
+    for (int i = 16 * nslots + threadIdx.x; i < N; i += blockDim.x) {
+        const uint32_t key = fkey(row[i]);
+        if (key <= t) push(key, i);
+    }
+    __syncthreads();
+    list_sort_emit(sk, si, s_n, row, N, k, out_idx + r * k, out_d + r * k);
+}
+
+// Groups per chunk for (N, k): 512 (8,192 entries) for long rows, else 128 (2,048),
+// whichever gives m = ceil(k / full chunks) <= kTauMaxM; 0 when neither does.
+static int groups_cg(int N, int k)
+{
+    for (int cg : {512, 128}) {
+        const int full = N / (cg * 16);
+        if (full >= 1 && (k + full - 1) / full <= kTauMaxM) return cg;
+    }
+    return 0;
+}
+
+size_t topk_groups_ws_bytes(int M, int N)
+{
+    return align_up((size_t)M * 4, kAlign) + (size_t)M * (N / 16) * 4;
+}
+
+uint32_t *topk_groups_gmin(void *ws, int M)
+{
+    return reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + align_up((size_t)M * 4, kAlign));
+}
+
+hipError_t launch_topk_groups(int M, int N, int k, const float *D, void *ws, int32_t *idx,
+                              float *d, hipStream_t s)
+{
+    const int cg = groups_cg(N, k);
+    if (cg == 0) {                                 // no bound: one block per row
+        hipLaunchKernelGGL(topk_min_kernel, dim3(M), dim3(kSelThreads), 0, s, D, N, k, idx, d);
+        return hipGetLastError();
+    }
+    const int full = N / (cg * 16), m = (k + full - 1) / full;
+    uint32_t *tau = static_cast<uint32_t *>(ws);
+    const uint32_t *gmin = topk_groups_gmin(ws, M);
+    const int64_t gld = N / 16;
+    hipError_t e = launch_fill_u32(reinterpret_cast<int32_t *>(tau), M, 0, s);
+    if (e != hipSuccess) return e;
+    const unsigned bx = (unsigned)((full + 3) / 4);
+    if (cg == 512)
+        hipLaunchKernelGGL(topk_tau_groups_kernel<8>, dim3(bx, M), dim3(256), 0, s, gmin, gld, full, m,
+                           tau);
+    else
+        hipLaunchKernelGGL(topk_tau_groups_kernel<2>, dim3(bx, M), dim3(256), 0, s, gmin, gld, full, m,
+                           tau);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(topk_list_groups_kernel, dim3(M), dim3(kSelThreads), 0, s, D, N, k, tau, gmin,
+                       gld, full * cg, idx, d);
+    return hipGetLastError();
 }
 
 // ---- launchers ---------------------------------------------------------------------------------
@@ -1073,11 +1315,12 @@ hipError_t launch_quant_fp8(int64_t n, int dim, const float *x, uint8_t *y, floa
 // Persistent grid of the distance kernel: as many blocks as fit on the device
 // at once (a multiple of 8, so each block keeps its XCD), at most one per tile.
 // X is taken in chunks of fewer than 2^31 bytes (32-bit row offsets), each
-// chunk one launch writing its columns of D.
-template <bool FP8, bool TAIL, int DEPTH>
+// chunk one launch writing its columns of D (and its groups of gmin).
+template <bool FP8, bool TAIL, int DEPTH, bool GMIN>
 static hipError_t dist_lds_launch(int M, int N, int K, const uint8_t *Q, const float *qs,
                                   const float *qn, const uint8_t *X, const float *xs,
-                                  const float *xn, float *D, int mode, hipStream_t s)
+                                  const float *xn, float *D, int mode, uint32_t *gmin,
+                                  hipStream_t s)
 {
     static int resident[64];                        // per device: blocks resident at once
     int dev = 0;
@@ -1089,22 +1332,23 @@ static hipError_t dist_lds_launch(int M, int N, int K, const uint8_t *Q, const f
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess)
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, dist_lds_kernel<FP8, TAIL, DEPTH>, kDThreads, 0);
+                &per_cu, dist_lds_kernel<FP8, TAIL, DEPTH, GMIN>, kDThreads, 0);
         if (e != hipSuccess) return e;
         resident[dev] = max(kXcds, (cus * max(per_cu, 1)) / kXcds * kXcds);
     }
     const int64_t Kb = FP8 ? K : 2 * (int64_t)K;
     if ((int64_t)M * Kb >= kDChunkBytes) return hipErrorInvalidValue;
-    const int chunk = (int)(((kDChunkBytes - 1) / Kb) / kDN * kDN);
+    const int chunk = (int)(((kDChunkBytes - 1) / Kb) / kDN * kDN);   // a multiple of 16
     const int mt = (M + kDM - 1) / kDM;
     for (int c0 = 0; c0 < N; c0 += chunk) {
         const int n = min(chunk, N - c0);
         const int nt = (n + kDN - 1) / kDN;
         const int ntiles = kXcds * mt * ((nt + kXcds - 1) / kXcds);   // a multiple of 8
         const int g = min(ntiles, resident[dev]);
-        hipLaunchKernelGGL((dist_lds_kernel<FP8, TAIL, DEPTH>), dim3(g), dim3(kDThreads), 0, s, M,
-                           n, K, mt, ntiles, Q, qs, qn, X + c0 * Kb, FP8 ? xs + c0 : nullptr,
-                           xn + c0, D + c0, (int64_t)N, mode);
+        hipLaunchKernelGGL((dist_lds_kernel<FP8, TAIL, DEPTH, GMIN>), dim3(g), dim3(kDThreads), 0, s,
+                           M, n, K, mt, ntiles, Q, qs, qn, X + c0 * Kb, FP8 ? xs + c0 : nullptr,
+                           xn + c0, D + c0, (int64_t)N, mode, GMIN ? gmin + c0 / 16 : nullptr,
+                           (int64_t)(N / 16), n / 16);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -1118,23 +1362,38 @@ static hipError_t dist_lds_launch(int M, int N, int K, const uint8_t *Q, const f
 constexpr int kDDepthBf16 = 1, kDDepthFp8 = 3;
 
 hipError_t launch_dist_bf16(int M, int N, int K, const uint16_t *Q, const float *qn,
-                            const uint16_t *X, const float *xn, float *D, int mode, hipStream_t s)
+                            const uint16_t *X, const float *xn, float *D, int mode,
+                            uint32_t *gmin, hipStream_t s)
 {
     const auto *q = reinterpret_cast<const uint8_t *>(Q);
     const auto *x = reinterpret_cast<const uint8_t *>(X);
+    if (gmin) {
+        if (mode != 0) return hipErrorInvalidValue;
+        if ((2 * K) % kDSlice)
+            return dist_lds_launch<false, true, kDDepthBf16, true>(M, N, K, q, nullptr, qn, x,
+                                                                   nullptr, xn, D, 0, gmin, s);
+        return dist_lds_launch<false, false, kDDepthBf16, true>(M, N, K, q, nullptr, qn, x,
+                                                                nullptr, xn, D, 0, gmin, s);
+    }
     if ((2 * K) % kDSlice)
-        return dist_lds_launch<false, true, kDDepthBf16>(M, N, K, q, nullptr, qn, x, nullptr, xn,
-                                                         D, mode, s);
-    return dist_lds_launch<false, false, kDDepthBf16>(M, N, K, q, nullptr, qn, x, nullptr, xn, D,
-                                                      mode, s);
+        return dist_lds_launch<false, true, kDDepthBf16, false>(M, N, K, q, nullptr, qn, x, nullptr,
+                                                                xn, D, mode, nullptr, s);
+    return dist_lds_launch<false, false, kDDepthBf16, false>(M, N, K, q, nullptr, qn, x, nullptr,
+                                                             xn, D, mode, nullptr, s);
 }
 
 hipError_t launch_dist_fp8(int M, int N, int K, const uint8_t *Q, const float *qs, const float *qn,
                            const uint8_t *X, const float *xs, const float *xn, float *D,
-                           int mode, hipStream_t s)
+                           int mode, uint32_t *gmin, hipStream_t s)
 {
     if (K % kDSlice) return hipErrorInvalidValue;   // FP8 rows are whole slices
-    return dist_lds_launch<true, false, kDDepthFp8>(M, N, K, Q, qs, qn, X, xs, xn, D, mode, s);
+    if (gmin) {
+        if (mode != 0) return hipErrorInvalidValue;
+        return dist_lds_launch<true, false, kDDepthFp8, true>(M, N, K, Q, qs, qn, X, xs, xn, D, 0,
+                                                              gmin, s);
+    }
+    return dist_lds_launch<true, false, kDDepthFp8, false>(M, N, K, Q, qs, qn, X, xs, xn, D, mode,
+                                                           nullptr, s);
 }
 
 // m of the bound-and-filter path with `per` entries per thread, or 0 when it does not

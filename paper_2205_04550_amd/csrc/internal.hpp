@@ -114,12 +114,22 @@ hipError_t launch_quant_bf16(int64_t n, int dim, const float *x, uint16_t *y, fl
                              hipStream_t s);
 hipError_t launch_quant_fp8(int64_t n, int dim, const float *x, uint8_t *y, float *scale,
                             float *sq, hipStream_t s);
-// mode 0: squared L2; 1: L2; 2: add L2 to D (see dist_store in embed.hip).
+// mode 0: squared L2; 1: L2; 2: add L2 to D. gmin (mode 0 only, else NULL): also the
+// minimum key of every whole group of 16 entries of each row, [M][N / 16], for
+// launch_topk_groups.
 hipError_t launch_dist_bf16(int M, int N, int K, const uint16_t *Q, const float *qn,
-                            const uint16_t *X, const float *xn, float *D, int mode, hipStream_t s);
+                            const uint16_t *X, const float *xn, float *D, int mode,
+                            uint32_t *gmin, hipStream_t s);
 hipError_t launch_dist_fp8(int M, int N, int K, const uint8_t *Q, const float *qs, const float *qn,
                            const uint8_t *X, const float *xs, const float *xn, float *D,
-                           int mode, hipStream_t s);
+                           int mode, uint32_t *gmin, hipStream_t s);
+// k smallest per row of D [M][N] from the group minima a distance launch left in ws
+// (topk_groups_ws_bytes; the minima at topk_groups_gmin(ws, M)); one block per row
+// when no bound applies to (N, k).
+size_t topk_groups_ws_bytes(int M, int N);
+uint32_t *topk_groups_gmin(void *ws, int M);
+hipError_t launch_topk_groups(int M, int N, int k, const float *D, void *ws, int32_t *idx,
+                              float *d, hipStream_t s);
 // k smallest per row of D [M][N]. With a workspace of topk_min_ws_bytes (> 0) the rows
 // are split into chunks selected in parallel and merged; without, one block per row.
 size_t topk_min_ws_bytes(int M, int N, int k);

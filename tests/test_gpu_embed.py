@@ -102,6 +102,61 @@ def test_distances_many_tiles_and_chunks(fmt, M, N, dim):
     assert np.all(np.abs(got - d64) <= bound)
 
 
+@pytest.mark.parametrize("fmt,M,N,dim,ks", [
+    (0, 9, 50_021, 64, (1, 10, 100, 1000)),     # ragged N (not a multiple of 4 or 16)
+    (1, 9, 50_021, 64, (1, 10, 100)),
+    (0, 5, 3000, 48, (7, 100)),                 # k too large for a bound: one block per row
+    (0, 4, 300_000, 64, (1, 7, 100)),           # 8,192-entry chunks
+])
+def test_groups_path_equals_plain_path(fmt, M, N, dim, ks):
+    """emb_distances_groups writes the same D as emb_distances, and emb_topk_groups gives
+    emb_topk_min's indices and values bit for bit: database rows repeated (exact ties
+    across groups and chunks), one query equal to a database row, and one database of
+    identical rows (every distance equal: the gather overflows and the row is selected
+    by the one-block path)."""
+    need_gpu()
+    from paper_2205_04550_amd import binding as b
+    g = torch.Generator(device="cuda").manual_seed(17)
+    base = torch.randn(701, dim, generator=g, device="cuda")
+    Xf = base.repeat(N // 701 + 1, 1)[:N].contiguous()
+    Qf = torch.randn(M, dim, generator=g, device="cuda")
+    Qf[1] = base[3]
+    for Xlat in (Xf, base[:1].repeat(N, 1)):
+        Q, X = b.Latents(Qf, fmt), b.Latents(Xlat, fmt)
+        D0 = b.emb_distances(Q, X)
+        ws = b.groups_workspace(M, N)
+        D1 = b.emb_distances_groups(Q, X, ws)
+        assert torch.equal(D0.view(torch.int32), D1.view(torch.int32))
+        for k in ks:
+            i0, v0 = b.emb_topk_min(D0, k)
+            i1, v1 = b.emb_topk_groups(D1, k, ws)
+            assert torch.equal(i0, i1) and torch.equal(v0.view(torch.int32), v1.view(torch.int32)), k
+        want = E.topk_by_distance(D0.cpu().numpy(), ks[-1])
+        assert np.array_equal(i1.cpu().numpy(), want)
+
+
+def test_groups_path_chunked_database():
+    """A BF16 database of 2.25 GB of codes (two launches of the distance kernel): group
+    minima written at the right offsets on both sides of the chunk boundary."""
+    need_gpu()
+    from paper_2205_04550_amd import binding as b
+    g = torch.Generator(device="cuda").manual_seed(23)
+    N = 1_100_000
+    Xf = torch.randn(N, 1024, generator=g, device="cuda")
+    Qf = torch.randn(3, 1024, generator=g, device="cuda")
+    Qf[2] = Xf[1_048_330]                         # its nearest entry just past the boundary
+    Q, X = b.Latents(Qf, 0), b.Latents(Xf, 0)
+    del Xf
+    D0 = b.emb_distances(Q, X)
+    ws = b.groups_workspace(3, N)
+    D1 = b.emb_distances_groups(Q, X, ws)
+    assert torch.equal(D0.view(torch.int32), D1.view(torch.int32))
+    i0, v0 = b.emb_topk_min(D0, 10)
+    i1, v1 = b.emb_topk_groups(D1, 10, ws)
+    assert torch.equal(i0, i1) and torch.equal(v0, v1)
+    assert int(i1[2, 0]) == 1_048_330
+
+
 def test_topk_min_exact_with_ties():
     need_gpu()
     from paper_2205_04550_amd import binding as b
