@@ -74,3 +74,25 @@ def test_calls_on_invalid_handle():
     assert b.LIB.db_sync(None, None) == b.DB_ESTATE
     assert b.LIB.db_query_workspace_bytes(None, 1, 10) == 0
     b.LIB.db_free(None)  # no-op
+
+
+def test_group_path_sizes_and_argument_errors_before_any_gpu_call():
+    from paper_2205_04550_amd import binding as b
+    # tau (M words, 256-byte aligned) + the group minima [M][N / 16] (whole groups only).
+    assert b.LIB.emb_groups_workspace_bytes(1024, 50_000) == 4096 + 1024 * 3125 * 4
+    assert b.LIB.emb_groups_workspace_bytes(3, 50_021) == 256 + 3 * 3126 * 4
+    assert b.LIB.emb_groups_workspace_bytes(0, 100) == 0
+    fake = 1 << 20                                  # aligned non-null pointers, never dereferenced
+    assert b.LIB.emb_topk_groups(4, 100, None, 5, fake, fake, fake, 1 << 20, None) == b.DB_EINVAL
+    assert b.LIB.emb_topk_groups(4, 100, fake, 101, fake, fake, fake, 1 << 20, None) == b.DB_EINVAL
+    assert b.LIB.emb_topk_groups(4, 100, fake, 5, fake, fake, None, 1 << 20, None) == b.DB_ENOSPC
+    assert b.LIB.emb_topk_groups(4, 100, fake, 5, fake, fake, fake, 16, None) == b.DB_ENOSPC
+    sq = fake
+    assert b.LIB.emb_distances_groups(b.EMB_BIN, 4, 100, 64, fake, None, None, fake, None, None,
+                                      fake, fake, 1 << 20, None) == b.DB_EINVAL
+    assert b.LIB.emb_distances_groups(b.EMB_BF16, 4, 100, 64, fake, None, sq, fake, None, sq,
+                                      fake, fake, 16, None) == b.DB_ENOSPC
+    assert b"needed" in b.LIB.db_last_error()
+    # Query codes of 2 GiB or more are refused (32-bit row offsets in the distance kernel).
+    assert b.LIB.emb_distances(b.EMB_BF16, 1 << 20, 100, 1024, fake, None, sq, fake, None, sq,
+                               fake, None) == b.DB_EINVAL
