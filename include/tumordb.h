@@ -244,7 +244,11 @@ int db_rerank(const db_t *db, int nq, const uint8_t *q_labels, const int32_t *ca
  * ws; db_rerank_packed then scores cand against them. Same ws (same nq, at
  * least db_rerank_workspace_bytes(db, nq) bytes, 256-byte aligned) for both
  * calls; the second must be ordered after the first (same stream, or an event).
- * Results equal db_rerank's bit for bit. Argument rules as db_rerank's. */
+ * Results equal db_rerank's bit for bit. Argument rules as db_rerank's.
+ * After db_rerank_pack, ws begins with the queries' packed masks, uint32
+ * [nq][2][Wp] in the database's plane layout (LSB-first, x fastest; plane 0
+ * FLAIR, plane 1 T1Gd; Wp = nx ny nz / 32 rounded up to a multiple of 4),
+ * which nn_pool_conv_planes can encode without reading the labels again. */
 int db_rerank_pack(const db_t *db, int nq, const uint8_t *q_labels, void *ws, size_t ws_bytes,
                    void *stream);
 int db_rerank_packed(const db_t *db, int nq, const int32_t *cand, int nc, int k, int32_t *idx,

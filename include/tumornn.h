@@ -73,6 +73,20 @@ int nn_meanpool_labels_mask(const uint8_t *labels, int B, int nx, int ny, int nz
 int nn_pool_conv_labels(const uint8_t *labels, int B, int nx, int ny, int nz, int mask, int Co,
                         const void *Wt, const float *bias, int relu, float *Y, void *stream);
 
+/* nn_pool_conv_labels from packed masks instead of label bytes: sample b's
+ * masks are the LSB-first uint32 bit planes (x fastest; plane 0 FLAIR, plane 1
+ * T1Gd, sample_words / 2 words each) at planes + s * sample_words with
+ * s = idx[b] (device int32 [B]) or s = b when idx is NULL: the database's
+ * planes (sample_words = 2 Wp, idx = entries) or the queries packed by
+ * db_rerank_pack. Y equals nn_pool_conv_labels' for the labels that packed to
+ * these masks, bit for bit (same pooled values, same products and order). A
+ * pooled row reads 4 x 16 bits per mask instead of 4 x 16 bytes. Same shape
+ * rules as nn_pool_conv_labels; sample_words even and at least
+ * 2 nx ny nz / 32. */
+int nn_pool_conv_planes(const uint32_t *planes, int64_t sample_words, const int32_t *idx, int B,
+                        int nx, int ny, int nz, int mask, int Co, const void *Wt,
+                        const float *bias, int relu, float *Y, void *stream);
+
 /* Y = act(conv(X)) with X [B][Ci][D][H][W], Y [B][Co][D/2][H/2][W/2];
  * bias [Co] or NULL; relu != 0 applies max(0, .). */
 int nn_conv3d_s2_fwd(int dtype, int B, int Ci, int Co, int D, int H, int W, const void *X,

@@ -310,6 +310,11 @@ class TumorDB:
         _check(LIB.db_rerank_pack(self._h, q_labels.shape[0], q_labels.data_ptr(), ws.data_ptr(),
                                   ws.numel(), _stream(stream)))
 
+    def packed_queries(self, ws: torch.Tensor, nq: int) -> torch.Tensor:
+        """int32 view [nq][2][Wp] of the queries' packed masks that rerank_pack left at the start
+        of ws (the database's plane layout)."""
+        return ws[:nq * 2 * self.Wp * 4].view(torch.int32).view(nq, 2, self.Wp)
+
     def rerank_packed(self, ws: torch.Tensor, cand: torch.Tensor, k: int, stream=None):
         """Second half of rerank: score cand [nq][nc] against the queries packed into ws."""
         nq, nc = cand.shape

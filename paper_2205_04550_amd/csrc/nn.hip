@@ -972,7 +972,33 @@ __device__ __forceinline__ uint32_t pooled_word(uint32_t f, uint32_t h, int e)
     return bf | (bh << 16);
 }
 
+// The pooled word of counts cf, ch (0..8 set voxels of the two masks in a 2x2x2 block).
+__device__ __forceinline__ uint32_t pooled_counts(uint32_t cf, uint32_t ch)
+{
+    const uint32_t bf = __float_as_uint((float)cf * 0.125f) >> 16;   // exact: k/8
+    const uint32_t bh = __float_as_uint((float)ch * 0.125f) >> 16;
+    return bf | (bh << 16);
+}
+
+// 16 mask bits (8 pairs of x-neighbours) -> the pair counts, 4 bits per pair:
+// pair p in bits 4p .. 4p + 3 (room for the sum over four rows, at most 8).
+__device__ __forceinline__ uint32_t pair_counts4(uint32_t x16)
+{
+    uint32_t t = (x16 & 0x5555u) + ((x16 >> 1) & 0x5555u);   // 2-bit pair counts
+    t = (t | (t << 8)) & 0x00ff00ffu;
+    t = (t | (t << 4)) & 0x0f0f0f0fu;
+    return (t | (t << 2)) & 0x33333333u;
+}
+
+// PLANES: the masks come packed (LSB-first uint32 words, x fastest; plane 0
+// FLAIR, plane 1 T1Gd, sample_words = 2 Wp per sample, sample b at
+// planes + (idx ? idx[b] : b) * sample_words) instead of as label bytes: a
+// pooled row is 4 x 16 bits per mask instead of 4 x 16 bytes.
+template <bool PLANES>
 __global__ void __launch_bounds__(256) pool_conv_labels_kernel(const uint8_t *__restrict__ lab,
+                                                               const uint32_t *__restrict__ planes,
+                                                               int64_t sample_words,
+                                                               const int32_t *__restrict__ idx,
                                                                int nx, int ny, int nz, int mask,
                                                                int Ci, int Co, int npb,
                                                                const uint16_t *__restrict__ Wt,
@@ -980,6 +1006,9 @@ __global__ void __launch_bounds__(256) pool_conv_labels_kernel(const uint8_t *__
                                                                int relu, float *__restrict__ Y)
 {
     __shared__ __attribute__((aligned(16))) uint32_t pl[45 * kPlRow];
+    // PLANES: the raw mask words of the patch, [pooled row][label row q][mask][halo word,
+    // 4 words of 128 label x], loaded whole (one 16-byte load per row and mask).
+    __shared__ __attribute__((aligned(16))) uint32_t rb[PLANES ? 45 * 8 * 5 : 1];
     const int PZ = nz / 2, PY = ny / 2;
     const int OD = nz / 4, OH = ny / 4, OW = nx / 4;
     const int tw_n = OW / 32, th_n = (OH + 3) / 4, td_n = (OD + 1) / 2;
@@ -989,7 +1018,10 @@ __global__ void __launch_bounds__(256) pool_conv_labels_kernel(const uint8_t *__
     int t0 = blockIdx.x * npb;
     if (T % (8 * npb) == 0) t0 = (blockIdx.x % 8) * (T / 8) + (blockIdx.x / 8) * npb;
     const int b = blockIdx.y;
-    const uint8_t *L = lab + (int64_t)b * nz * ny * nx;
+    const uint8_t *L = PLANES ? nullptr : lab + (int64_t)b * nz * ny * nx;
+    const uint32_t *P = PLANES ? planes + (int64_t)(idx ? idx[b] : b) * sample_words : nullptr;
+    const int64_t Wp = sample_words / 2;
+    const int nxw = nx / 32;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, j = lane & 15;
     // Weights of both steps for this lane: row co = j, eight k from 8 g.
     bf16x8 a[2];
@@ -1026,8 +1058,34 @@ __global__ void __launch_bounds__(256) pool_conv_labels_kernel(const uint8_t *__
         row[u] = halo[u] ? it - 360 : it >> 3;
         seg[u] = it & 7;
     }
-    u32x4 v[2][4];
+    u32x4 v[2][4];             // label bytes: 16 per row
+    // PLANES: raw row i < 360 (pooled row i / 8, label row q = (i / 2) % 4, mask i % 2) is
+    // the 4 words of label x 4 ow0 .. + 127 and the word before (the halo); thread tid
+    // loads rows tid and tid + 256.
+    u32x4 rw[2] = {{0u, 0u, 0u, 0u}, {0u, 0u, 0u, 0u}};
+    uint32_t rh[2] = {0u, 0u};
+    auto load_raw = [&](int t) {
+        const int twi = t % tw_n, thi = (t / tw_n) % th_n, tdi = t / (tw_n * th_n);
+        const int od0 = 2 * tdi, oh0 = 4 * thi, ow0 = 32 * twi;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int i = tid + 256 * u, rrow = i >> 3, rq = (i >> 1) & 3, rm = i & 1;
+            const int Z = 2 * od0 - 1 + rrow / 9, Yp = 2 * oh0 - 1 + rrow % 9;
+            rw[u] = (u32x4){0u, 0u, 0u, 0u};
+            rh[u] = 0u;
+            if (i < 360 && Z >= 0 && Z < PZ && Yp >= 0 && Yp < PY) {
+                const int64_t w = ((int64_t)(2 * Z + (rq >> 1)) * ny + 2 * Yp + (rq & 1)) * nxw +
+                                  (4 * ow0) / 32 + rm * Wp;
+                rw[u] = *reinterpret_cast<const u32x4 *>(P + w);
+                if (ow0 > 0) rh[u] = P[w - 1];
+            }
+        }
+    };
     auto load = [&](int t) {
+        if (PLANES) {
+            load_raw(t);
+            return;
+        }
         const int twi = t % tw_n, thi = (t / tw_n) % th_n, tdi = t / (tw_n * th_n);
         const int od0 = 2 * tdi, oh0 = 4 * thi, ow0 = 32 * twi;
 #pragma unroll
@@ -1052,9 +1110,53 @@ __global__ void __launch_bounds__(256) pool_conv_labels_kernel(const uint8_t *__
     for (int n = 0; n < npb; ++n) {
         const int t = t0 + n;
         if (t >= T) break;                         // uniform over the block
+        if (PLANES) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (tid + 256 * u >= 360) break;
+                uint32_t *d = &rb[(tid + 256 * u) * 5];
+                d[0] = rh[u];
+                d[1] = rw[u].x;
+                d[2] = rw[u].y;
+                d[3] = rw[u].z;
+                d[4] = rw[u].w;
+            }
+            __syncthreads();
+            if (n + 1 < npb && t + 1 < T) load_raw(t + 1);
+        }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (tid + 256 * u >= 405) break;
+            if (PLANES) {
+                // Item (row, seg): label x 16 seg .. + 15 of the patch = bits 16 (seg % 2)
+                // .. + 15 of raw word 1 + seg / 2; the halo's two columns are bits 30, 31
+                // of the word before.
+                const int wi = halo[u] ? 0 : 1 + (seg[u] >> 1);
+                const int sh = halo[u] ? 30 : 16 * (seg[u] & 1);
+                const uint32_t fm = halo[u] ? 3u : 0xffffu;
+                uint32_t F = 0u, H = 0u;     // counts of pooled x 0..7, 4 bits each
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t *src = &rb[(row[u] * 8 + q * 2) * 5];
+                    F += pair_counts4((src[wi] >> sh) & fm);
+                    H += pair_counts4((src[5 + wi] >> sh) & fm);
+                }
+                if (Ci == 1) {               // one mask: channel 0, channel 1 zero
+                    if (mask == 1) F = H;
+                    H = 0u;
+                }
+                if (!halo[u]) {
+                    uint32_t w[8];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) w[e] = pooled_counts((F >> (4 * e)) & 15u, (H >> (4 * e)) & 15u);
+                    u32x4 *dst = reinterpret_cast<u32x4 *>(&pl[row[u] * kPlRow + 4 + 8 * seg[u]]);
+                    dst[0] = (u32x4){w[0], w[1], w[2], w[3]};
+                    dst[1] = (u32x4){w[4], w[5], w[6], w[7]};
+                } else {
+                    pl[row[u] * kPlRow + 3] = pooled_counts(F & 15u, H & 15u);
+                }
+                continue;
+            }
             uint32_t f[4] = {0u, 0u, 0u, 0u}, h[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
             for (int q = 0; q < 4; ++q)
@@ -1085,7 +1187,7 @@ __global__ void __launch_bounds__(256) pool_conv_labels_kernel(const uint8_t *__
             }
         }
         __syncthreads();
-        if (n + 1 < npb && t + 1 < T) load(t + 1);
+        if (!PLANES && n + 1 < npb && t + 1 < T) load(t + 1);
         const int twi = t % tw_n, thi = (t / tw_n) % th_n, tdi = t / (tw_n * th_n);
         const int od0 = 2 * tdi, oh0 = 4 * thi, ow0 = 32 * twi;
 #pragma unroll
@@ -1350,10 +1452,29 @@ int nn_pool_conv_labels(const uint8_t *labels, int B, int nx, int ny, int nz, in
         return tdb_set_error(DB_EINVAL, "nn_pool_conv_labels: bad arguments");
     const int T = (nx / 128) * ((ny / 4 + 3) / 4) * ((nz / 4 + 1) / 2);
     const int npb = T % 32 == 0 ? 4 : 1;           // tiles per block
-    hipLaunchKernelGGL(pool_conv_labels_kernel, dim3((unsigned)((T + npb - 1) / npb), (unsigned)B),
-                       dim3(256), 0, static_cast<hipStream_t>(stream), labels, nx, ny, nz, mask,
-                       mask < 0 ? 2 : 1, Co, npb, static_cast<const uint16_t *>(Wt), bias, relu, Y);
+    hipLaunchKernelGGL(pool_conv_labels_kernel<false>, dim3((unsigned)((T + npb - 1) / npb), (unsigned)B),
+                       dim3(256), 0, static_cast<hipStream_t>(stream), labels, nullptr, (int64_t)0,
+                       nullptr, nx, ny, nz, mask, mask < 0 ? 2 : 1, Co, npb,
+                       static_cast<const uint16_t *>(Wt), bias, relu, Y);
     return launched("nn_pool_conv_labels");
+}
+
+int nn_pool_conv_planes(const uint32_t *planes, int64_t sample_words, const int32_t *idx, int B,
+                        int nx, int ny, int nz, int mask, int Co, const void *Wt,
+                        const float *bias, int relu, float *Y, void *stream)
+{
+    const int64_t words = (int64_t)nx * ny * nz / 32;
+    if (!planes || !Wt || !Y || B <= 0 || B > 65535 || nx <= 0 || ny <= 0 || nz <= 0 ||
+        nx % 128 || ny % 4 || nz % 4 || Co <= 0 || Co > 16 || mask < -1 || mask > 1 ||
+        sample_words % 2 || sample_words / 2 < words || (int64_t)nx * ny * nz >= ((int64_t)1 << 31))
+        return tdb_set_error(DB_EINVAL, "nn_pool_conv_planes: bad arguments");
+    const int T = (nx / 128) * ((ny / 4 + 3) / 4) * ((nz / 4 + 1) / 2);
+    const int npb = T % 32 == 0 ? 4 : 1;           // tiles per block
+    hipLaunchKernelGGL(pool_conv_labels_kernel<true>, dim3((unsigned)((T + npb - 1) / npb), (unsigned)B),
+                       dim3(256), 0, static_cast<hipStream_t>(stream), nullptr, planes,
+                       sample_words, idx, nx, ny, nz, mask, mask < 0 ? 2 : 1, Co, npb,
+                       static_cast<const uint16_t *>(Wt), bias, relu, Y);
+    return launched("nn_pool_conv_planes");
 }
 
 int nn_conv3d_s2_fwd(int dtype, int B, int Ci, int Co, int D, int H, int W, const void *X,

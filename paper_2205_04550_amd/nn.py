@@ -49,6 +49,8 @@ _SIGS = {
     "nn_meanpool_labels_mask": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _vp, _i32, _vp]),
     "nn_pool_conv_labels": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _i32, _vp,
                                    _vp]),
+    "nn_pool_conv_planes": (_i32, [_vp, _i64, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp,
+                                   _i32, _vp, _vp]),
     "nn_vae_ws_bytes": (_sz, [_i32, _i32, _i32]),
     "nn_vae_head_fwd": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "nn_vae_head_bwd": (_i32, [_i32, _i32, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]),
@@ -136,6 +138,28 @@ def pool_conv_labels(labels: torch.Tensor, w_bf16: torch.Tensor, bias: torch.Ten
     y = torch.empty((B, Co, nz // 4, ny // 4, nx // 4), dtype=torch.float32, device=labels.device)
     _check(LIB.nn_pool_conv_labels(labels.data_ptr(), B, nx, ny, nz, -1 if mask is None else mask,
                                    Co, w_bf16.data_ptr(), _p(bias), int(relu), y.data_ptr(), _s()))
+    return y
+
+
+def pool_conv_planes(planes: torch.Tensor, dims, w_bf16: torch.Tensor, bias: torch.Tensor | None,
+                     relu: bool = True, mask: int | None = None,
+                     idx: torch.Tensor | None = None) -> torch.Tensor:
+    """pool_conv_labels from packed masks: planes int32 [S][2][Wp] (the database's planes, or
+    the queries packed by TumorDB.rerank_pack), samples idx (int32, device) or all S; dims =
+    (nx, ny, nz). Equal to pool_conv_labels of the labels that packed to them, bit for bit."""
+    nx, ny, nz = dims
+    S, two, Wp = planes.shape
+    assert two == 2 and planes.is_contiguous()
+    B = S if idx is None else idx.numel()
+    Co = w_bf16.shape[0]
+    assert w_bf16.dtype == torch.bfloat16 and w_bf16.shape[1] == (2 if mask is None else 1)
+    w_bf16 = _c(w_bf16)
+    bias = None if bias is None else _c(bias.detach())
+    idx = None if idx is None else _c(idx.to(torch.int32))
+    y = torch.empty((B, Co, nz // 4, ny // 4, nx // 4), dtype=torch.float32, device=planes.device)
+    _check(LIB.nn_pool_conv_planes(planes.data_ptr(), 2 * Wp, _p(idx), B, nx, ny, nz,
+                                   -1 if mask is None else mask, Co, w_bf16.data_ptr(), _p(bias),
+                                   int(relu), y.data_ptr(), _s()))
     return y
 
 
@@ -446,6 +470,20 @@ class AutoEncoder:
         with torch.no_grad():
             w, b, wc = self._w("enc0")
             h = pool_conv_labels(labels, wc, b, True, mask)
+            for i in range(1, 4):
+                w, b, wc = self._w(f"enc{i}")
+                h = Conv3dS2.apply(h, w, b, wc, True)
+            return self._head(h.reshape(h.shape[0], -1))
+
+    def encode_planes(self, planes: torch.Tensor, dims, idx: torch.Tensor | None = None,
+                      mask: int | None = None) -> torch.Tensor:
+        """encode_labels from packed masks (planes int32 [S][2][Wp], samples idx or all): the
+        first layer pools the bit planes (pool_conv_planes); needs the fused path's shapes."""
+        nx, ny, nz = dims
+        assert self.bf16 and nx % 128 == 0 and ny % 4 == 0 and nz % 4 == 0 and self.channels[1] <= 16
+        with torch.no_grad():
+            w, b, wc = self._w("enc0")
+            h = pool_conv_planes(planes, dims, wc, b, True, mask, idx)
             for i in range(1, 4):
                 w, b, wc = self._w(f"enc{i}")
                 h = Conv3dS2.apply(h, w, b, wc, True)

@@ -349,6 +349,57 @@ def test_pool_conv_labels_matches_oracle(dims):
             assert _rel(_cpu64(y), yr) < 2e-5, (dims, mask, relu)
 
 
+@pytest.mark.parametrize("dims", [(12, 20, 256), (8, 8, 128), (128, 128, 128)])
+def test_pool_conv_planes_equals_pool_conv_labels(dims):
+    """The first layer from the queries' packed masks (as db_rerank_pack leaves them) equals
+    the first layer from their label bytes bit for bit: both masks and each alone, ragged
+    output boxes, two x tiles, samples chosen and reordered by idx."""
+    need_gpu()
+    from paper_2205_04550_amd import TumorDB, nn
+    nz, ny, nx = dims
+    B = 3
+    rng = np.random.default_rng(nz * ny + nx)
+    lab = rng.integers(0, 4, size=(B, nz, ny, nx), dtype=np.uint8)
+    lab[:, : nz // 3] = 0
+    lab[1, :, :, : nx // 2] &= 2                             # T1Gd without FLAIR
+    lab_d = torch.from_numpy(lab).cuda()
+    db = TumorDB(nx, ny, nz, 1, synth.T_LO, synth.T_HI)
+    db.append(torch.zeros((1, nz, ny, nx), dtype=torch.float32, device="cuda"))
+    ws = db.rerank_workspace(B)
+    db.rerank_pack(lab_d, ws)
+    planes = db.packed_queries(ws, B).clone()
+    g = torch.Generator().manual_seed(nz)
+    idx = torch.tensor([2, 0], dtype=torch.int32, device="cuda")
+    for mask in (None, 0, 1):
+        ci = 2 if mask is None else 1
+        wc = (torch.randn(8, ci, 3, 3, 3, generator=g) * 0.3).to(torch.bfloat16).cuda()
+        b = torch.randn(8, generator=g).cuda()
+        for relu in (True, False):
+            y1 = nn.pool_conv_labels(lab_d, wc, b, relu, mask)
+            y2 = nn.pool_conv_planes(planes, (nx, ny, nz), wc, b, relu, mask)
+            assert torch.equal(y1.view(torch.int32), y2.view(torch.int32)), (mask, relu)
+        y3 = nn.pool_conv_planes(planes, (nx, ny, nz), wc, b, True, mask, idx)
+        assert torch.equal(y3, nn.pool_conv_labels(lab_d[[2, 0]].contiguous(), wc, b, True, mask))
+
+
+def test_pool_conv_planes_from_the_database():
+    """Database entries (their stored bit planes, idx) encode as the labels thresholded from
+    the same densities: the fused first layer from planes equals the one from labels."""
+    need_gpu()
+    from paper_2205_04550_amd import nn
+    gen = synth.FULL
+    db, conc = build_db_from_host(gen, 4, synth.T_LO, synth.T_HI)
+    c = conc.reshape(4, gen.nz, gen.ny, gen.nx)
+    lab = (c >= np.float32(synth.T_LO)).astype(np.uint8) | ((c >= np.float32(synth.T_HI)).astype(np.uint8) << 1)
+    g = torch.Generator().manual_seed(2)
+    wc = (torch.randn(8, 2, 3, 3, 3, generator=g) * 0.3).to(torch.bfloat16).cuda()
+    b = torch.randn(8, generator=g).cuda()
+    idx = torch.tensor([3, 1, 1], dtype=torch.int32, device="cuda")
+    y_p = nn.pool_conv_planes(db.planes, (gen.nx, gen.ny, gen.nz), wc, b, True, None, idx)
+    y_l = nn.pool_conv_labels(torch.from_numpy(lab[[3, 1, 1]]).cuda(), wc, b, True, None)
+    assert torch.equal(y_p, y_l)
+
+
 def test_encode_labels_matches_two_step_encode():
     """AutoEncoder.encode_labels (fused first layer) equals encode(meanpool_labels(.)) up to
     FP32 summation order, for the two-mask encoder and a one-mask encoder."""
