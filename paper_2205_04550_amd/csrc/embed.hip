@@ -144,6 +144,19 @@ constexpr int kXcds = 8;
 // Row offsets into Q and X are 32-bit: the host splits X into chunks below this.
 constexpr int64_t kDChunkBytes = (int64_t)1 << 31;
 
+// fkey without its folding of -0 onto +0 (three instructions instead of five): the same
+// order, except that -0 sorts just below +0. The minimum of a set under raw_key, passed
+// through fold_zero_key, is the minimum under fkey.
+__device__ __forceinline__ uint32_t raw_key(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);
+}
+__device__ __forceinline__ uint32_t fold_zero_key(uint32_t k)
+{
+    return k == 0x7fffffffu ? 0x80000000u : k;   // raw_key(-0) -> fkey(+0)
+}
+
 // v of the lane that DPP control `ctrl` names within this lane's row of 16 (all lanes active).
 template <int ctrl>
 __device__ __forceinline__ uint32_t dpp_u32(uint32_t v)
@@ -344,11 +357,11 @@ __global__ void __launch_bounds__(kDThreads, FP8 ? 1 : 4) dist_lds_kernel(int M,
                             out[rr * ldd] = mode == 1 ? l : out[rr * ldd] + l;
                         }
                     }
-                    key[r] = col < N ? fkey(dv) : 0xffffffffu;
+                    key[r] = col < N ? raw_key(dv) : 0xffffffffu;
                     acc[i][j][r] = 0.f;
                 }
                 if (GMIN) {                   // all 64 lanes active: DPP reads whole rows
-                    const uint32_t gm = row16_min_scatter(key, lane);   // row rl0 + rr(lane % 16)
+                    const uint32_t gm = fold_zero_key(row16_min_scatter(key, lane));   // row rl0 + rr(lane % 16)
                     const int rr = 8 * ((lane & 15) >> 2) + (lane & 3);
                     const int g = (n0 + wn * 64 + j * 32 + (lane & 16)) >> 4;
                     if (m0 + rl0 + rr < M && g < ngroups)
