@@ -6,11 +6,14 @@
 // dense contraction on the matrix cores:
 //   - BF16 latents: v_mfma_f32_32x32x16_bf16, FP32 accumulation;
 //   - FP8 (OCP e4m3) latents with a per-row scale: v_mfma_scale_f32_32x32x64_f8f6f4.
-// Each query keeps its k nearest latents (exact radix select on the FP32
-// distances, ties by lower index), and those candidates are re-scored with
-// the exact Dice_T1Gd + Dice_FLAIR of the packed masks (Sec. 2.3 score),
-// reading only the rows of the query's bounding box (outside it the query
-// has no set bit, so those words contribute nothing to the overlap).
+// Each query keeps its k nearest latents, exactly, ties by lower index: a
+// bound from per-chunk minima (the distance kernel can leave the minimum of
+// every 16 consecutive entries for it) and a gather of the entries within the
+// bound, or a radix select / chunked selection of the FP32 distances. Those
+// candidates are re-scored with the exact Dice_T1Gd + Dice_FLAIR of the packed
+// masks (Sec. 2.3 score), reading only the rows of the query's bounding box
+// (outside it the query has no set bit, so those words add nothing to the
+// overlap).
 #include <limits.h>
 
 #include "common.hpp"
