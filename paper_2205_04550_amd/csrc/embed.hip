@@ -1157,45 +1157,56 @@ __global__ void __launch_bounds__(kSelThreads) topk_list_kernel(const float *__r
 // 1/16 of the distances' bytes; the gather reads only the groups whose minimum
 // is <= tau (and the entries after the last whole chunk).
 
-// grid (ceil(C / 4), M), 256 threads: wave w of block x takes chunk 4x + w (< C) of
-// 64 * PER group minima, PER per lane, and raises tau[row] to the m-th smallest of
-// them (m rounds of a wave minimum over the lanes' smallest remaining values, each
-// round removing one copy of it).
-template <int PER>
+// grid (ceil(C / (4 CPW)), M), 256 threads: wave w of block x takes chunks
+// CPW (4x + w) .. + CPW - 1 (those < C) of 64 * PER group minima each, PER per lane,
+// all loaded before any is used; for each it finds the m-th smallest (m rounds of a
+// wave minimum over the lanes' smallest remaining values, each round removing one
+// copy of it) and raises tau[row] to the largest of those.
+template <int PER, int CPW>
 __global__ void __launch_bounds__(256) topk_tau_groups_kernel(const uint32_t *__restrict__ gmin,
                                                              int64_t gld, int chunks, int m,
                                                              uint32_t *__restrict__ tau)
 {
-    const int lane = threadIdx.x & 63, c = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (c >= chunks) return;                      // whole wave; no barriers here
+    const int lane = threadIdx.x & 63;
+    const int c0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * CPW;
+    if (c0 >= chunks) return;                     // whole wave; no barriers here
+    const int nc = min(CPW, chunks - c0);
     const int64_t r = blockIdx.y;
-    const uint32_t *p = gmin + r * gld + (int64_t)c * 64 * PER;
-    uint32_t v[PER];
+    const uint32_t *p = gmin + r * gld + (int64_t)c0 * 64 * PER;
+    uint32_t v[CPW][PER];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) v[q] = p[q * 64 + lane];
-    auto lane_min = [&]() {
-        uint32_t x = v[0];
+    for (int c = 0; c < CPW; ++c)
 #pragma unroll
-        for (int q = 1; q < PER; ++q) x = min(x, v[q]);
-        return x;
-    };
-    uint32_t lm = lane_min(), mn = 0;
-    for (int i = 0;; ++i) {
-        mn = wave_min_u32(lm);
-        if (i + 1 == m) break;
-        const uint64_t hold = __ballot(lm == mn);
-        if (lane == __ffsll((unsigned long long)hold) - 1) {
-            bool done = false;
+        for (int q = 0; q < PER; ++q) v[c][q] = c < nc ? p[(c * PER + q) * 64 + lane] : 0u;
+    uint32_t best = 0;
 #pragma unroll
-            for (int q = 0; q < PER; ++q)
-                if (!done && v[q] == mn) {
-                    v[q] = 0xffffffffu;
-                    done = true;
-                }
-            lm = lane_min();
+    for (int c = 0; c < CPW; ++c) {
+        if (c >= nc) break;                       // uniform over the wave
+        auto lane_min = [&]() {
+            uint32_t x = v[c][0];
+#pragma unroll
+            for (int q = 1; q < PER; ++q) x = min(x, v[c][q]);
+            return x;
+        };
+        uint32_t lm = lane_min(), mn = 0;
+        for (int i = 0;; ++i) {
+            mn = wave_min_u32(lm);
+            if (i + 1 == m) break;
+            const uint64_t hold = __ballot(lm == mn);
+            if (lane == __ffsll((unsigned long long)hold) - 1) {
+                bool done = false;
+#pragma unroll
+                for (int q = 0; q < PER; ++q)
+                    if (!done && v[c][q] == mn) {
+                        v[c][q] = 0xffffffffu;
+                        done = true;
+                    }
+                lm = lane_min();
+            }
         }
+        best = max(best, mn);
     }
-    if (lane == 0) atomicMax(&tau[r], mn);
+    if (lane == 0) atomicMax(&tau[r], best);
 }
 
 // grid M, kSelThreads threads: the entries of row r with key <= tau[r], from the
@@ -1298,13 +1309,14 @@ hipError_t launch_topk_groups(int M, int N, int k, const float *D, void *ws, int
     const int64_t gld = N / 16;
     hipError_t e = launch_fill_u32(reinterpret_cast<int32_t *>(tau), M, 0, s);
     if (e != hipSuccess) return e;
-    const unsigned bx = (unsigned)((full + 3) / 4);
+    constexpr int kCpw = 4;                        // chunks per wave
+    const unsigned bx = (unsigned)((full + 4 * kCpw - 1) / (4 * kCpw));
     if (cg == 512)
-        hipLaunchKernelGGL(topk_tau_groups_kernel<8>, dim3(bx, M), dim3(256), 0, s, gmin, gld, full, m,
-                           tau);
+        hipLaunchKernelGGL((topk_tau_groups_kernel<8, kCpw>), dim3(bx, M), dim3(256), 0, s, gmin, gld,
+                           full, m, tau);
     else
-        hipLaunchKernelGGL(topk_tau_groups_kernel<2>, dim3(bx, M), dim3(256), 0, s, gmin, gld, full, m,
-                           tau);
+        hipLaunchKernelGGL((topk_tau_groups_kernel<2, kCpw>), dim3(bx, M), dim3(256), 0, s, gmin, gld,
+                           full, m, tau);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(topk_list_groups_kernel, dim3(M), dim3(kSelThreads), 0, s, D, N, k, tau, gmin,
