@@ -107,6 +107,7 @@ def test_distances_many_tiles_and_chunks(fmt, M, N, dim):
     (1, 9, 50_021, 64, (1, 10, 100)),
     (0, 5, 3000, 48, (7, 100)),                 # k too large for a bound: one block per row
     (0, 4, 300_000, 64, (1, 7, 100)),           # 8,192-entry chunks
+    (1, 3, 10, 64, (1, 5)),                      # fewer entries than one group
 ])
 def test_groups_path_equals_plain_path(fmt, M, N, dim, ks):
     """emb_distances_groups writes the same D as emb_distances, and emb_topk_groups gives
