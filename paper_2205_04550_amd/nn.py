@@ -467,9 +467,18 @@ class AutoEncoder:
         if not (self.bf16 and nx % 128 == 0 and ny % 4 == 0 and nz % 4 == 0
                 and self.channels[1] <= 16):
             return self.encode(meanpool_labels(labels, mask=mask))
+        return self.encode_after_first(self.first_layer_labels(labels, mask))
+
+    def first_layer_labels(self, labels: torch.Tensor, mask: int | None = None) -> torch.Tensor:
+        """The fused first layer of encode_labels alone (pooling + convolution from the label
+        bytes), so a caller can start other work between it and encode_after_first."""
         with torch.no_grad():
             w, b, wc = self._w("enc0")
-            h = pool_conv_labels(labels, wc, b, True, mask)
+            return pool_conv_labels(labels, wc, b, True, mask)
+
+    def encode_after_first(self, h: torch.Tensor) -> torch.Tensor:
+        """The rest of the encoder after the first layer's output h."""
+        with torch.no_grad():
             for i in range(1, 4):
                 w, b, wc = self._w(f"enc{i}")
                 h = Conv3dS2.apply(h, w, b, wc, True)
