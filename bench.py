@@ -87,14 +87,25 @@ def source_sha(*rel: str) -> str:
     return h.hexdigest()
 
 
+# Committed counter files per workload and the sources of the kernel they measured.
+TRAFFIC_FILES = {
+    "full": ("scan_full_traffic.json", SCAN_SOURCES),
+    "embed500k": ("dist_fp8_500k_traffic.json", ("paper_2205_04550_amd/csrc/embed.hip",
+                                                  "paper_2205_04550_amd/csrc/common.hpp")),
+}
+
+
 def load_traffic(workload: str):
     """HBM traffic per launch from committed rocprofv3 counter runs, if still current."""
-    path = os.path.join(ROOT, "profiles", f"scan_{workload}_traffic.json")
+    if workload not in TRAFFIC_FILES:
+        return None
+    name, sources = TRAFFIC_FILES[workload]
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_sha256") != source_sha(*SCAN_SOURCES):
+    if t.get("kernel_source_sha256") != source_sha(*sources):
         return None
     return t.get("bytes_per_launch")
 
@@ -747,7 +758,8 @@ def bench_embed500k(args, db, gen, n, build_s, n_big: int = 500_000) -> int:
         "paths": res, "generate_and_encode_s": gen_s,
         "roofline": {"bound": "mfma", "achieved": flop / (g8 * 1e-3) / 1e12,
                      "peak": FP8_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
-                     "frac": flop / (g8 * 1e-3) / FP8_MFMA_PEAK, "traffic": None,
+                     "frac": flop / (g8 * 1e-3) / FP8_MFMA_PEAK,
+                     "traffic": load_traffic("embed500k"),
                      "kernel": "dist_lds_kernel<true, false, 3, true>", "kernel_avg_ms": g8,
                      "note": "writes 2.05 GB of distances and 128 MB of 16-entry group minima "
                              "per launch"},
