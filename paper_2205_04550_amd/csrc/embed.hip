@@ -354,10 +354,13 @@ __global__ void __launch_bounds__(kDThreads, FP8 ? 1 : 4) dist_lds_kernel(int M,
                     const float dot = FP8 ? (t[1][rl] * sc) * acc[i][j][r] : acc[i][j][r];
                     const float dv = (t[0][rl] + xc) - 2.0f * dot;
                     if (rr < rows) {
-                        if (mode == 0) out[rr * ldd] = dv;
+                        // Non-temporal: the distances stream past L2, where the
+                        // database tiles are meant to stay.
+                        if (mode == 0) __builtin_nontemporal_store(dv, &out[rr * ldd]);
                         else {
                             const float l = __builtin_sqrtf(fmaxf(dv, 0.0f));
-                            out[rr * ldd] = mode == 1 ? l : out[rr * ldd] + l;
+                            __builtin_nontemporal_store(mode == 1 ? l : out[rr * ldd] + l,
+                                                        &out[rr * ldd]);
                         }
                     }
                     key[r] = col < N ? raw_key(dv) : 0xffffffffu;
