@@ -52,16 +52,42 @@ def _L():
         lib.oracle_scan_block.argtypes = [vp, i64, i32, i32, i32, ctypes.c_float, ctypes.c_float,
                                           vp, vp, vp, vp, i32]
         lib.oracle_scan_block.restype = None
+        lib.oracle_scan_block_multi.argtypes = [vp, i64, i32, i32, i32, ctypes.c_float,
+                                                ctypes.c_float, i32, vp, vp, vp, vp, i32]
+        lib.oracle_scan_block_multi.restype = None
         _lib = lib
     return _lib
 
 
-def _threads() -> int:
+def host_cores() -> int:
+    """Cores this process may run on (its CPU affinity set)."""
     try:
-        n = len(os.sched_getaffinity(0))
+        return len(os.sched_getaffinity(0))
     except AttributeError:
-        n = os.cpu_count() or 1
-    return max(1, min(n, 16))
+        return os.cpu_count() or 1
+
+
+def _threads() -> int:
+    """Threads of the oracle's loops: every core of the affinity set, unless
+    OMP_NUM_THREADS names fewer (a host that shares its cores between jobs sets it
+    to this job's share)."""
+    n = host_cores()
+    env = os.environ.get("OMP_NUM_THREADS", "").strip()
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_model() -> str:
+    """The host CPU's model name from /proc/cpuinfo ("unknown" if absent)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def _roi_arg(roi):
@@ -118,6 +144,32 @@ def scan_block(conc: np.ndarray, q: np.ndarray, t_lo: float, t_hi: float, roi=No
     if n:
         _L().oracle_scan_block(conc.ctypes.data, n, nx, ny, nz, t_lo, t_hi, q.ctypes.data, rp,
                                cnt.ctypes.data, sc.ctypes.data, threads or _threads())
+    return cnt, sc
+
+
+def scan_block_multi(conc: np.ndarray, queries: np.ndarray, t_lo: float, t_hi: float, rois=None,
+                     threads: int | None = None):
+    """scan_block for several queries at once (each entry thresholded once).
+
+    queries: uint8 [nq][nz][ny][nx]; rois: int [nq][6] or None (whole grids).
+    Returns (counts uint64 [nq][n][6], score float64 [nq][n]).
+    """
+    conc = np.ascontiguousarray(conc, dtype=np.float32)
+    qs = np.ascontiguousarray(queries, dtype=np.uint8)
+    n = conc.shape[0]
+    nz, ny, nx = conc.shape[1:]
+    nq = qs.shape[0]
+    assert qs.shape[1:] == (nz, ny, nx)
+    cnt = np.zeros((nq, n, 6), dtype=np.uint64)
+    sc = np.zeros((nq, n), dtype=np.float64)
+    rp = None
+    if rois is not None:
+        r = np.ascontiguousarray(np.asarray(rois, dtype=np.int32).reshape(nq, 6))
+        rp = r.ctypes.data
+    if n and nq:
+        _L().oracle_scan_block_multi(conc.ctypes.data, n, nx, ny, nz, t_lo, t_hi, nq,
+                                     qs.ctypes.data, rp, cnt.ctypes.data, sc.ctypes.data,
+                                     threads or _threads())
     return cnt, sc
 
 

@@ -111,3 +111,31 @@ void oracle_scan_block(const float *conc, int64_t n, int nx, int ny, int nz, flo
         free(L);
     }
 }
+
+/*
+ * The same for-loop with several queries: entry n is thresholded once and then
+ * counted against each query j (labels q + j*V, box rois + 6j, or the whole grid
+ * when rois is NULL). counts[j][n][6], score[j][n].
+ */
+void oracle_scan_block_multi(const float *conc, int64_t n, int nx, int ny, int nz, float t_lo,
+                             float t_hi, int nq, const uint8_t *q, const int32_t *rois,
+                             uint64_t *counts, double *score, int nthreads)
+{
+    int64_t V = (int64_t)nx * ny * nz;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
+    {
+        uint8_t *L = (uint8_t *)malloc((size_t)V);
+        if (!L)
+            abort();
+#pragma omp for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            oracle_threshold(conc + i * V, V, t_lo, t_hi, L);
+            for (int j = 0; j < nq; ++j) {
+                uint64_t *c = counts + 6 * ((int64_t)j * n + i);
+                oracle_counts(q + (int64_t)j * V, L, nx, ny, nz, rois ? rois + 6 * j : NULL, c);
+                score[(int64_t)j * n + i] = oracle_score(c);
+            }
+        }
+        free(L);
+    }
+}

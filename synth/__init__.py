@@ -89,11 +89,15 @@ def uniform(seed: int, item: int, draw: int) -> float:
 
 
 def default_threads() -> int:
+    """Every core of the affinity set, unless OMP_NUM_THREADS names fewer."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
         n = os.cpu_count() or 1
-    return max(1, min(n, 16))
+    env = os.environ.get("OMP_NUM_THREADS", "").strip()
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
 
 
 @dataclasses.dataclass(frozen=True)

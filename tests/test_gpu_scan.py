@@ -10,7 +10,7 @@ import torch
 
 import oracle
 import synth
-from gpu_util import build_db_from_host, build_db_on_gpu, need_gpu, say, unpack_planes
+from gpu_util import build_db_from_host, need_gpu, say, unpack_planes
 
 pytestmark = pytest.mark.gpu
 
@@ -147,44 +147,3 @@ def test_errors_write_nothing():
     torch.cuda.synchronize()
     assert bool((idx == -7).all()) and bool((score == -7.0).all())
     assert len(db) == 12
-
-
-def test_full_size_sampled_parity():
-    """50,000 sims on 128^3 (26.2 GB packed), the benchmark's query and launch path.
-
-    The oracle recomputes a sample of entries one by one (CPU-generated
-    volumes): 48 random entries plus the returned top-10; the top-10 itself
-    must equal a full sort of the scores implied by the GPU's own counts.
-    """
-    need_gpu()
-    gen, n, k = synth.FULL, synth.FULL_N, 10
-    say("full config: GPU-generated build of 50,000 x 128^3")
-    db = build_db_on_gpu(gen, n, T_LO, T_HI, log=say)
-    src = synth.query_source(n, synth.QUERY_SEED, 0)
-    q = gen.query(src, T_LO, T_HI, synth.QUERY_SEED, 0)
-    qd = torch.from_numpy(q).cuda()
-    say("full config: query")
-    idx, score, counts = db.query(qd, k)
-    inter, qcount = db.scan(qd)
-    db.sync()
-    inter = _host(inter).view(np.uint32).astype(np.uint64)
-    pcs = _host(db.popcounts).view(np.uint32).astype(np.uint64)
-    a = _host(qcount).view(np.uint32).astype(np.uint64)
-    # Scores implied by the GPU counts, through the oracle's Dice -> full sort.
-    implied = np.array([oracle.score((inter[e, 0], inter[e, 1], a[0], a[1], pcs[e, 0], pcs[e, 1]))
-                        for e in range(n)])
-    top = oracle.rank(implied, k)
-    assert list(_host(idx)) == top
-    assert np.array_equal(_host(score).view(np.uint64), implied[top].view(np.uint64))
-    # Sampled entries recomputed from scratch by the oracle.
-    rng = np.random.default_rng(2205)
-    sample = sorted(set(rng.choice(n, 48, replace=False).tolist()) | set(top))
-    say(f"full config: oracle on {len(sample)} sampled entries")
-    _, o_cnt, o_sc = oracle.scan(gen, n, q, T_LO, T_HI, indices=sample)
-    for j, e in enumerate(sample):
-        assert (inter[e, 0], inter[e, 1], a[0], a[1], pcs[e, 0], pcs[e, 1]) == tuple(o_cnt[j])
-        assert implied[e] == o_sc[j]
-    say(f"full config: source entry {src} ranks {top.index(src) if src in top else '>10'}")
-    c = _host(counts).view(np.uint32).astype(np.uint64)
-    for r, e in enumerate(top):
-        assert tuple(c[r]) == (inter[e, 0], inter[e, 1], a[0], a[1], pcs[e, 0], pcs[e, 1])

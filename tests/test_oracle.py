@@ -258,6 +258,43 @@ def test_scan_duplicates_and_self_retrieval():
         assert tuple(int(v) for v in cnt[i]) == oracle.counts(q, lab)
 
 
+def test_scan_block_multi_box_closed_form_and_per_query_loop():
+    """The several-query loop gives, per query and box, the closed-form box overlaps and the
+    same counts as thresholding each entry and counting it on its own."""
+    rng = np.random.default_rng(11)
+    shape = (6, 5, 64)                                  # nz, ny, nx
+    n = 7
+    conc = np.zeros((n,) + shape, dtype=np.float32)
+    boxes = []
+    for i in range(n):
+        lo = [int(rng.integers(0, d - 1)) for d in (64, 5, 6)]
+        hi = [int(rng.integers(l + 1, d + 1)) for l, d in zip(lo, (64, 5, 6))]
+        boxes.append((lo[0], lo[1], lo[2], hi[0], hi[1], hi[2]))
+        conc[i, lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = 0.9   # in both masks
+    qboxes = [(3, 0, 1, 40, 4, 6), (0, 0, 0, 64, 5, 6), (31, 2, 2, 33, 3, 3)]
+    queries = np.stack([box_labels(shape, b, b) for b in qboxes])
+    rois = np.array([(0, 0, 0, 64, 5, 6), (10, 1, 0, 50, 5, 4), (30, 2, 2, 34, 3, 3)], np.int32)
+
+    def inter(a, b):
+        return math.prod(max(0, min(a[d + 3], b[d + 3]) - max(a[d], b[d])) for d in range(3))
+
+    for use_roi in (False, True):
+        cnt, sc = oracle.scan_block_multi(conc, queries, synth.T_LO, synth.T_HI,
+                                          rois=rois if use_roi else None, threads=3)
+        for j, qb in enumerate(qboxes):
+            R = tuple(rois[j]) if use_roi else (0, 0, 0, 64, 5, 6)
+            a = inter(qb, R)
+            for i in range(n):
+                b = inter(boxes[i], R)
+                I = math.prod(max(0, min(qb[d + 3], boxes[i][d + 3], R[d + 3])
+                                     - max(qb[d], boxes[i][d], R[d])) for d in range(3))
+                assert tuple(int(v) for v in cnt[j, i]) == (I, I, a, a, b, b)
+                lab = oracle.threshold(conc[i], synth.T_LO, synth.T_HI)
+                assert tuple(int(v) for v in cnt[j, i]) == oracle.counts(
+                    queries[j], lab, roi=R if use_roi else None)
+                assert sc[j, i] == oracle.score(cnt[j, i])
+
+
 def test_noisy_self_query_usually_finds_source():
     gen = synth.SMALL
     n_db = 64
