@@ -118,6 +118,24 @@ int db_scan(const db_t *db, const uint8_t *q_labels, uint32_t *inter, uint32_t *
 int db_query(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx, double *score,
              db_counts_t *counts, void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory at query time (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the same
+ * query as db_query, same arguments and results bit for bit, but without a
+ * workspace argument. The workspace is carved from a fixed device array of
+ * DB_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on until
+ * the process ends; this call allocates nothing. The database's workspace
+ * (db_query_workspace_bytes without the batched parts: about 8 bytes per entry
+ * of capacity plus 2 V / 8 bytes for the packed query) must fit in it, else
+ * DB_ENOSPC and nothing is enqueued. The current device must be the one the
+ * database was built on (DB_EINVAL otherwise). Every call on one GPU shares
+ * that GPU's array: calls that overlap in time on one GPU (other streams, other
+ * threads) race and give undefined results; calls ordered on one stream are
+ * safe. The array keeps the last call's contents; each call overwrites every
+ * part it reads. */
+#define DB_NOALLOC_SCRATCH_BYTES ((size_t)4 << 20)
+int db_query_noalloc(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx, double *score,
+                     db_counts_t *counts, void *stream);
+
 /* Same contract and results, bit for bit, as db_query (same workspace size),
  * computed by reading only the x-rows where both the entry's stored box and
  * the query's box hold set bits: every other row is zero on one side and adds

@@ -26,7 +26,7 @@ SYMBOLS = ("db_storage_bytes", "db_build", "db_append", "db_size", "db_query_wor
            "db_query_sparse", "db_query_com_workspace_bytes", "db_query_com",
            "emb_hash_thresholds", "emb_binarize", "emb_distances_l2sum", "db_rerank_pack",
            "db_rerank_packed", "emb_groups_workspace_bytes", "emb_distances_groups",
-           "emb_topk_groups")
+           "emb_topk_groups", "db_query_noalloc")
 EMB_BF16, EMB_FP8, EMB_BIN = 0, 1, 2
 
 
@@ -55,6 +55,7 @@ def _load():
         "db_query_workspace_bytes": (sz, [vp, i32, i32]),
         "db_scan": (i32, [vp, vp, vp, vp, vp, sz, vp]),
         "db_query": (i32, [vp, vp, i32, vp, vp, vp, vp, sz, vp]),
+        "db_query_noalloc": (i32, [vp, vp, i32, vp, vp, vp, vp]),
         "db_query_batch": (i32, [vp, i32, vp, vp, i32, vp, vp, vp, vp, sz, vp]),
         "db_query_sparse": (i32, [vp, vp, i32, vp, vp, vp, vp, sz, vp]),
         "db_query_com_workspace_bytes": (sz, [vp, i32, i32]),
@@ -224,6 +225,22 @@ class TumorDB:
         ws = self.workspace(1, k) if ws is None else ws
         _check(LIB.db_query(self._h, q_labels.data_ptr(), k, idx.data_ptr(), score.data_ptr(),
                             _ptr(counts), ws.data_ptr(), ws.numel(), _stream(stream)))
+        return idx, score, counts
+
+    def query_noalloc(self, q_labels: torch.Tensor, k: int, with_counts: bool = True, out=None,
+                      stream=None):
+        """query() with the library's fixed device scratch array instead of a workspace
+        (db_query_noalloc: nothing is allocated by the call; outputs are allocated here
+        unless given in out)."""
+        dev = self.storage.device
+        if out is None:
+            idx = torch.empty(k, dtype=torch.int32, device=dev)
+            score = torch.empty(k, dtype=torch.float64, device=dev)
+            counts = torch.empty((k, 6), dtype=torch.int32, device=dev) if with_counts else None
+        else:
+            idx, score, counts = out
+        _check(LIB.db_query_noalloc(self._h, q_labels.data_ptr(), k, idx.data_ptr(),
+                                    score.data_ptr(), _ptr(counts), _stream(stream)))
         return idx, score, counts
 
     def query_sparse(self, q_labels: torch.Tensor, k: int, with_counts: bool = True, out=None,

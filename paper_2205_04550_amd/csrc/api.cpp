@@ -415,19 +415,15 @@ int db_scan(const db_t *db, const uint8_t *q_labels, uint32_t *inter, uint32_t *
     return DB_OK;
 }
 
-int db_query(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx, double *score,
-             db_counts_t *counts, void *ws, size_t ws_bytes, void *stream)
+}  // extern "C"
+
+namespace tdb {
+
+// The launches of one exact query (pack, scan, Dice + top-k) into ws laid out as L.
+hipError_t enqueue_query(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx,
+                         double *score, db_counts_t *counts, void *ws, const WsLayout &L,
+                         hipStream_t s)
 {
-    int rc = check_query_common("db_query", db, q_labels, ws);
-    if (rc) return rc;
-    if (k < 1 || k > DB_KMAX || k > db->count)
-        return fail(DB_EINVAL, "db_query: k = %d outside [1, min(%lld, %d)]", k,
-                    (long long)db->count, DB_KMAX);
-    if (!idx || !score) return fail(DB_EINVAL, "db_query: idx and score must be non-NULL");
-    const WsLayout L = ws_layout(db, 1, k, true);
-    if (ws_bytes < L.total)
-        return fail(DB_ENOSPC, "db_query: workspace %zu bytes < %zu needed", ws_bytes, L.total);
-    hipStream_t s = static_cast<hipStream_t>(stream);
     uint32_t *inter = at<uint32_t>(ws, L.inter);
     uint32_t *acnt = at<uint32_t>(ws, L.acnt);
     QueryPart *qpart = at<QueryPart>(ws, L.qpart);
@@ -457,6 +453,40 @@ int db_query(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx, doubl
         a.out_counts = counts;
         e = launch_topk(a, s);
     }
+    return e;
+}
+
+// Argument checks of a single exact query (everything but the workspace size).
+int check_query_args(const char *fn, const db_t *db, const uint8_t *q_labels, int k,
+                     const int32_t *idx, const double *score)
+{
+    if (!live(db)) return fail(DB_ESTATE, "%s: invalid handle", fn);
+    if (db->count <= 0) return fail(DB_EINVAL, "%s: database is empty", fn);
+    if (!q_labels || !aligned(q_labels, 16))
+        return fail(DB_EINVAL, "%s: q_labels must be non-NULL and 16-byte aligned", fn);
+    if (k < 1 || k > DB_KMAX || k > db->count)
+        return fail(DB_EINVAL, "%s: k = %d outside [1, min(%lld, %d)]", fn, k,
+                    (long long)db->count, DB_KMAX);
+    if (!idx || !score) return fail(DB_EINVAL, "%s: idx and score must be non-NULL", fn);
+    return DB_OK;
+}
+
+}  // namespace tdb
+
+extern "C" {
+
+int db_query(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx, double *score,
+             db_counts_t *counts, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_query_common("db_query", db, q_labels, ws);
+    if (rc) return rc;
+    rc = check_query_args("db_query", db, q_labels, k, idx, score);
+    if (rc) return rc;
+    const WsLayout L = ws_layout(db, 1, k, true);
+    if (ws_bytes < L.total)
+        return fail(DB_ENOSPC, "db_query: workspace %zu bytes < %zu needed", ws_bytes, L.total);
+    hipError_t e = enqueue_query(db, q_labels, k, idx, score, counts, ws, L,
+                                 static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "db_query: launch");
     return DB_OK;
 }

@@ -82,6 +82,13 @@ struct QueryPart {
 };
 
 WsLayout ws_layout(const db_t *db, int nq, int k, bool batched);
+// One exact query (pack, scan, Dice + top-k) enqueued on s into ws laid out as L
+// (ws_layout(db, 1, k, .)); arguments checked by check_query_args beforehand.
+hipError_t enqueue_query(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx,
+                         double *score, db_counts_t *counts, void *ws, const WsLayout &L,
+                         hipStream_t s);
+int check_query_args(const char *fn, const db_t *db, const uint8_t *q_labels, int k,
+                     const int32_t *idx, const double *score);
 int64_t topk_blocks(int64_t n);
 
 // ---- launchers (each returns hipGetLastError of its launch) ----
