@@ -169,7 +169,10 @@ int db_tune_batch(db_t *db, int slab_planes, int block_threads);
  * candidates with the Dice score above. Latents are row-major [n][dim]; row i
  * of the database latents belongs to entry i. Distances are the squared L2
  * distance in the expanded form |q|^2 + |x|^2 - 2 q.x, accumulated in FP32 on
- * the matrix cores (BF16, or FP8 e4m3 with a per-row scale). */
+ * the BF16 matrix cores: BF16 codes as stored, FP8 e4m3 codes decoded exactly
+ * to BF16 (the products of codes are exact; the per-row scales multiply the
+ * finished dot product). Accuracy: |d - d64| <= 1e-5 (|q|^2 + |x|^2), d64 the
+ * float64 direct-form distance of the stored (dequantised) vectors. */
 enum { EMB_BF16 = 0, EMB_FP8 = 1, EMB_BIN = 2 };
 
 /* Quantise FP32 latents lat [n][dim] (device): EMB_BF16 writes uint16 codes
@@ -247,6 +250,22 @@ int emb_distances_groups(int fmt, int M, int N, int dim, const void *q_codes,
 int emb_topk_groups(int M, int N, const float *D, int k, int32_t *idx, float *d, void *ws,
                     size_t ws_bytes, void *stream);
 
+/* The k nearest database latents of each query in one pass, without a distance
+ * matrix in memory: idx [M][k] (int32, device) holds, per query row, the k
+ * smallest expanded-form distances of emb_distances in ascending order, ties
+ * by lower index -- exactly what emb_topk_min returns for those distances.
+ * d [M][k] (float, device): with direct = 0 those same expanded-form values;
+ * with direct != 0 the direct form sum_i (q_i - x_i)^2 of each selected pair,
+ * over the stored (dequantised) values, summed in float64 and rounded once to
+ * float (within 2^-24 relative of the float64 value; exactly 0 for identical
+ * codes and scales). BF16 or FP8 only; 1 <= k <= min(N, 256); ws (device,
+ * 256-byte aligned) of emb_knn_workspace_bytes bytes; other argument rules as
+ * emb_distances (the query codes below 2 GiB; database codes of any size). */
+size_t emb_knn_workspace_bytes(int M, int N, int k);
+int emb_knn(int fmt, int M, int N, int dim, const void *q_codes, const float *q_scale,
+            const float *q_sq, const void *x_codes, const float *x_scale, const float *x_sq, int k,
+            int direct, int32_t *idx, float *d, void *ws, size_t ws_bytes, void *stream);
+
 /* Exact re-scoring: for query q (labels [nq][nz][ny][nx]) and its candidate
  * entries cand [nq][nc] (device int32, each in [0, db_size())), the k best by
  * Dice_T1Gd + Dice_FLAIR (score desc, index asc) among the candidates.
@@ -274,7 +293,11 @@ int db_rerank_packed(const db_t *db, int nq, const int32_t *cand, int nc, int k,
 
 /* The chain distances -> n_cand nearest latents -> exact rerank -> k best.
  * Database latents x_* have n_lat = db_size() rows. cand_idx / cand_d [nq][n_cand]
- * receive the latent candidates (or pass NULL to keep them in the workspace). */
+ * receive the latent candidates (or pass NULL to keep them in the workspace):
+ * the n_cand nearest by expanded-form distance (ties by index), and for BF16 /
+ * FP8 with n_cand <= 256 (the emb_knn path, no distance matrix) their direct-
+ * form distances as emb_knn(direct = 1) reports them; otherwise (binary codes,
+ * larger n_cand) the distances the selection ranked. */
 size_t db_query_embed_workspace_bytes(const db_t *db, int nq, int n_cand);
 int db_query_embed(const db_t *db, int fmt, int nq, int dim, const void *q_codes,
                    const float *q_scale, const float *q_sq, const void *x_codes,

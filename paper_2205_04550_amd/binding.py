@@ -26,7 +26,7 @@ SYMBOLS = ("db_storage_bytes", "db_build", "db_append", "db_size", "db_query_wor
            "db_query_sparse", "db_query_com_workspace_bytes", "db_query_com",
            "emb_hash_thresholds", "emb_binarize", "emb_distances_l2sum", "db_rerank_pack",
            "db_rerank_packed", "emb_groups_workspace_bytes", "emb_distances_groups",
-           "emb_topk_groups", "db_query_noalloc")
+           "emb_topk_groups", "db_query_noalloc", "emb_knn_workspace_bytes", "emb_knn")
 EMB_BF16, EMB_FP8, EMB_BIN = 0, 1, 2
 
 
@@ -74,6 +74,8 @@ def _load():
         "emb_groups_workspace_bytes": (sz, [i32, i32]),
         "emb_distances_groups": (i32, [i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
         "emb_topk_groups": (i32, [i32, i32, vp, i32, vp, vp, vp, sz, vp]),
+        "emb_knn_workspace_bytes": (sz, [i32, i32, i32]),
+        "emb_knn": (i32, [i32, i32, i32, i32] + [vp] * 6 + [i32, i32, vp, vp, vp, sz, vp]),
         "emb_hash_thresholds": (i32, [i64, i32, vp, vp, vp]),
         "emb_distances_l2sum": (i32, [i32, i32, i32, i32] + [vp] * 12 + [vp, vp]),
         "emb_binarize": (i32, [i64, i32, vp, vp, vp, vp]),
@@ -509,6 +511,30 @@ def emb_topk_groups(D: torch.Tensor, k: int, ws: torch.Tensor, stream=None):
     _check(LIB.emb_topk_groups(M, N, D.data_ptr(), k, idx.data_ptr(), val.data_ptr(),
                                ws.data_ptr(), ws.numel(), _stream(stream)))
     return idx, val
+
+
+def knn_workspace(M: int, N: int, k: int, device="cuda") -> torch.Tensor:
+    """Workspace of emb_knn for M queries, N database latents and k nearest."""
+    nb = LIB.emb_knn_workspace_bytes(M, N, k)
+    if nb == 0:
+        raise DbError(DB_EINVAL, f"emb_knn: bad sizes M={M} N={N} k={k}")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def emb_knn(q, x, k: int, direct: bool = True, ws: torch.Tensor | None = None, out=None,
+            stream=None):
+    """The k nearest database latents per query in one pass (no distance matrix):
+    (idx int32 [M][k], d float32 [M][k]); d in direct form unless direct=False."""
+    if ws is None:
+        ws = knn_workspace(q.n, x.n, k, q.codes.device)
+    if out is None:
+        out = (torch.empty((q.n, k), dtype=torch.int32, device=q.codes.device),
+               torch.empty((q.n, k), dtype=torch.float32, device=q.codes.device))
+    idx, d = out
+    _check(LIB.emb_knn(q.fmt, q.n, x.n, q.dim, q.codes.data_ptr(), _ptr(q.scale), _ptr(q.sq),
+                       x.codes.data_ptr(), _ptr(x.scale), _ptr(x.sq), k, 1 if direct else 0,
+                       idx.data_ptr(), d.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return idx, d
 
 
 def labels_resample(labels: torch.Tensor, shape, stream=None) -> torch.Tensor:

@@ -12,7 +12,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtumordb.so")
 
 SOURCES = ["api.cpp", "pack.hip", "scan.hip", "select.hip", "batch.hip", "nn.hip", "embed.hip",
-           "resample.hip", "sparse.hip", "hash.hip", "vae.hip", "noalloc.hip"]
+           "resample.hip", "sparse.hip", "hash.hip", "vae.hip", "noalloc.hip", "knn.hip"]
 # Sources with floating-point arithmetic that may be contracted into FMAs.
 CONTRACT_OK = {"nn.hip"}
 

@@ -847,6 +847,33 @@ int emb_topk_min(int M, int N, const float *D, int k, int32_t *idx, float *d, vo
 }
 
 // Rerank workspace: packed queries, per-block counts, query counts, row boxes.
+size_t emb_knn_workspace_bytes(int M, int N, int k)
+{
+    if (M <= 0 || N <= 0 || k < 1 || k > kKnnMaxKPublic || k > N) return 0;
+    return knn_ws_bytes(M, N);
+}
+
+int emb_knn(int fmt, int M, int N, int dim, const void *q_codes, const float *q_scale,
+            const float *q_sq, const void *x_codes, const float *x_scale, const float *x_sq, int k,
+            int direct, int32_t *idx, float *d, void *ws, size_t ws_bytes, void *stream)
+{
+    if (fmt == EMB_BIN) return fail(DB_EINVAL, "emb_knn: BF16 or FP8 latents only");
+    int rc = dist_check("emb_knn", fmt, M, N, dim, q_codes, q_scale, q_sq, x_codes, x_scale,
+                        x_sq, d);
+    if (rc) return rc;
+    if (k < 1 || k > kKnnMaxKPublic || k > N || !idx)
+        return fail(DB_EINVAL, "emb_knn: k = %d outside [1, min(N, %d)] or idx NULL", k,
+                    kKnnMaxKPublic);
+    const size_t need = knn_ws_bytes(M, N);
+    if (!ws || !aligned(ws, kAlign) || ws_bytes < need)
+        return fail(DB_ENOSPC, "emb_knn: workspace %zu bytes < %zu needed (256-byte aligned)",
+                    ws ? ws_bytes : (size_t)0, need);
+    hipError_t e = launch_knn(fmt == EMB_FP8, M, N, dim, q_codes, q_scale, q_sq, x_codes, x_scale,
+                              x_sq, k, direct != 0, idx, d, ws, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "emb_knn: launch");
+    return DB_OK;
+}
+
 static size_t rerank_layout(const db_t *db, int nq, size_t *o_qpack, size_t *o_qpart,
                             size_t *o_acnt, size_t *o_box, size_t *o_mom = nullptr,
                             size_t *o_scored = nullptr)
@@ -971,6 +998,9 @@ int db_rerank(const db_t *db, int nq, const uint8_t *q_labels, const int32_t *ca
     return DB_OK;
 }
 
+// Workspace of db_query_embed: one region used either by the fused nearest-latent search
+// (its lists) or by the distance matrix and its selection workspace (binary codes, or
+// n_cand above the fused search's limit), then the candidates and the rerank's part.
 static size_t embed_layout(const db_t *db, int nq, int n_cand, size_t *o_D, size_t *o_ci,
                            size_t *o_cd, size_t *o_rr, size_t *o_sel = nullptr,
                            size_t *sel_bytes = nullptr)
@@ -981,17 +1011,18 @@ static size_t embed_layout(const db_t *db, int nq, int n_cand, size_t *o_D, size
         off = align_up(off + bytes, kAlign);
         return o;
     };
-    *o_D = take((size_t)nq * db->capacity * 4);
+    const int ncap = db->capacity > INT32_MAX ? INT32_MAX : (int)db->capacity;
+    const size_t dbytes = align_up((size_t)nq * db->capacity * 4, kAlign);
+    const size_t sb = n_cand <= ncap ? std::max(topk_min_ws_bytes(nq, ncap, n_cand),
+                                                topk_groups_ws_bytes(nq, ncap))
+                                     : 0;
+    const size_t kb = n_cand <= kKnnMaxKPublic ? knn_ws_bytes(nq, ncap) : 0;
+    *o_D = take(std::max(dbytes + sb, kb));
     *o_ci = take((size_t)nq * n_cand * 4);
     *o_cd = take((size_t)nq * n_cand * 4);
     size_t a, b, c, d;
     *o_rr = take(rerank_layout(db, nq, &a, &b, &c, &d));
-    const int ncap = db->capacity > INT32_MAX ? INT32_MAX : (int)db->capacity;
-    const size_t sb = n_cand <= ncap ? std::max(topk_min_ws_bytes(nq, ncap, n_cand),
-                                                topk_groups_ws_bytes(nq, ncap))
-                                     : 0;
-    const size_t os = take(sb);
-    if (o_sel) *o_sel = os;
+    if (o_sel) *o_sel = *o_D + dbytes;
     if (sel_bytes) *sel_bytes = sb;
     return off;
 }
@@ -1026,7 +1057,12 @@ int db_query_embed(const db_t *db, int fmt, int nq, int dim, const void *q_codes
     size_t osel, sel_bytes;
     embed_layout(db, nq, n_cand, &oD, &oci, &ocd, &orr, &osel, &sel_bytes);
     void *sel = sel_bytes ? at<char>(ws, osel) : nullptr;
-    if (fmt != EMB_BIN && sel && sel_bytes >= topk_groups_ws_bytes(nq, (int)n)) {
+    if (fmt != EMB_BIN && n_cand <= kKnnMaxKPublic) {
+        // Distances and the nearest n_cand in one pass (no distance matrix); the reported
+        // candidate distances are recomputed in direct form.
+        rc = emb_knn(fmt, nq, (int)n, dim, q_codes, q_scale, q_sq, x_codes, x_scale, x_sq,
+                     n_cand, 1, ci, cd, at<char>(ws, oD), knn_ws_bytes(nq, (int)n), stream);
+    } else if (fmt != EMB_BIN && sel && sel_bytes >= topk_groups_ws_bytes(nq, (int)n)) {
         // Distances with their group minima, then the bound read from those.
         rc = emb_distances_groups(fmt, nq, (int)n, dim, q_codes, q_scale, q_sq, x_codes, x_scale,
                                   x_sq, D, sel, sel_bytes, stream);

@@ -3,9 +3,13 @@
 // Paper Sec. 2.3 ("Autoencoders"): the database and the query are encoded to
 // latents and compared by L2 distance, lowest wins. Here the squared distance
 // is expanded, d(q, x) = |q|^2 + |x|^2 - 2 q.x, so the dominant work is one
-// dense contraction on the matrix cores:
-//   - BF16 latents: v_mfma_f32_32x32x16_bf16, FP32 accumulation;
-//   - FP8 (OCP e4m3) latents with a per-row scale: v_mfma_scale_f32_32x32x64_f8f6f4.
+// dense contraction on the matrix cores, v_mfma_f32_32x32x16_bf16 with FP32
+// accumulation, for both storage formats:
+//   - BF16 latents are staged as they are;
+//   - FP8 (OCP e4m3) latents with a per-row scale are decoded to BF16 while they
+//     are staged into LDS (every e4m3 value is a BF16 value, so the decode is
+//     exact); the products of the codes are then exact in FP32, and the scales
+//     multiply the finished dot product.
 // Each query keeps its k nearest latents, exactly, ties by lower index: a
 // bound from per-chunk minima (the distance kernel can leave the minimum of
 // every 16 consecutive entries for it) and a gather of the entries within the
@@ -17,13 +21,10 @@
 #include <limits.h>
 
 #include "common.hpp"
+#include "embed_core.hpp"
 #include "internal.hpp"
 
 namespace tdb {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 // ---- quantisation ---------------------------------------------------------------------------
 
@@ -35,7 +36,6 @@ __device__ __forceinline__ uint16_t bf16_rne(float f)
     return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 
-__device__ __forceinline__ float bf16_val(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // OCP FP8 e4m3 (bias 7, no infinities, largest finite 448): round to nearest
 // even, saturating at +-448. Written from the format definition.
@@ -60,13 +60,6 @@ __device__ __forceinline__ uint8_t e4m3_rne(float v)
     uint32_t code = ((uint32_t)E << 3) | (uint32_t)m;
     if (code > 0x7e) code = 0x7e;
     return (uint8_t)(sign | code);
-}
-
-__device__ __forceinline__ float e4m3_val(uint8_t c)
-{
-    const int E = (c >> 3) & 15, m = c & 7;
-    const float mag = E == 0 ? (float)m * 0.001953125f : ldexpf(1.0f + (float)m * 0.125f, E - 7);
-    return (c & 0x80) ? -mag : mag;
 }
 
 // One block (256 threads) per row: BF16 copy and |x|^2 of the stored values.
@@ -142,8 +135,6 @@ __global__ void __launch_bounds__(256) quant_fp8_kernel(int dim, const float *__
 // (block b runs on XCD b % 8, and so do all its tiles): the blocks of one XCD
 // work on a few database tiles at a time with every query tile, so a database
 // tile comes from HBM into that XCD's L2 once and is reused there.
-constexpr int kDM = 128, kDN = 256, kDSlice = 64, kDRow = 80, kDThreads = 512;
-constexpr int kXcds = 8;
 // Row offsets into Q and X are 32-bit: the host splits X into chunks below this.
 constexpr int64_t kDChunkBytes = (int64_t)1 << 31;
 
@@ -192,7 +183,7 @@ __device__ __forceinline__ uint32_t row16_min_scatter(const uint32_t (&k)[16], i
 // gmin[row * gld + g]; the bound of the top-k selection below then reads these
 // instead of the distances (mode 0 only).
 template <bool FP8, bool TAIL, int DEPTH, bool GMIN>
-__global__ void __launch_bounds__(kDThreads, FP8 ? 1 : 4) dist_lds_kernel(int M, int N, int K, int mt,
+__global__ void __launch_bounds__(kDThreads, 4) dist_lds_kernel(int M, int N, int K, int mt,
                                                              int ntiles,
                                                              const uint8_t *__restrict__ Q,
                                                              const float *__restrict__ qs,
@@ -209,8 +200,8 @@ __global__ void __launch_bounds__(kDThreads, FP8 ? 1 : 4) dist_lds_kernel(int M,
     // [0..127] query rows, [128..383] database rows.
     __shared__ float tv[2][2][kDM + kDN];
     const int G = gridDim.x, b = blockIdx.x;
-    const int Kb = FP8 ? K : 2 * K;                 // bytes per row
-    const int nslices = (Kb + kDSlice - 1) / kDSlice;
+    const int Kb = FP8 ? K : 2 * K;                 // bytes per row in Q and X
+    const int nslices = (2 * K + kDSlice - 1) / kDSlice;   // 32 values per slice
     const int mytiles = b < ntiles ? (ntiles - 1 - b) / G + 1 : 0;
     const int U = mytiles * nslices;                // K slices this block streams
     if (U == 0) return;                             // whole block, before any barrier
@@ -238,14 +229,22 @@ __global__ void __launch_bounds__(kDThreads, FP8 ? 1 : 4) dist_lds_kernel(int M,
         const int i = v / nslices, sl = v - i * nslices;
         int m0, n0;
         origin(i, m0, n0);
-        const uint32_t kb = (uint32_t)(sl * kDSlice + fpart);
+        // Byte offset of this thread's 8 values (FP8) or 16 bytes (BF16) in its rows.
+        const uint32_t kb = FP8 ? (uint32_t)(sl * (kDSlice / 2) + (fpart >> 1))
+                                : (uint32_t)(sl * kDSlice + fpart);
         if (!TAIL || (int)kb < Kb) {
             const uint32_t o0 = (uint32_t)min(m0 + frow, M - 1) * (uint32_t)Kb + kb;
             const uint32_t o1 = (uint32_t)min(n0 + frow, N - 1) * (uint32_t)Kb + kb;
             const uint32_t o2 = (uint32_t)min(n0 + kDM + frow, N - 1) * (uint32_t)Kb + kb;
-            dst[0] = *reinterpret_cast<const u32x4 *>(Q + o0);
-            dst[1] = *reinterpret_cast<const u32x4 *>(X + o1);
-            dst[2] = *reinterpret_cast<const u32x4 *>(X + o2);
+            if (FP8) {
+                dst[0] = e4m3x8_to_bf16(*reinterpret_cast<const u32x2 *>(Q + o0));
+                dst[1] = e4m3x8_to_bf16(*reinterpret_cast<const u32x2 *>(X + o1));
+                dst[2] = e4m3x8_to_bf16(*reinterpret_cast<const u32x2 *>(X + o2));
+            } else {
+                dst[0] = *reinterpret_cast<const u32x4 *>(Q + o0);
+                dst[1] = *reinterpret_cast<const u32x4 *>(X + o1);
+                dst[2] = *reinterpret_cast<const u32x4 *>(X + o2);
+            }
         } else {
             dst[0] = dst[1] = dst[2] = (u32x4){0u, 0u, 0u, 0u};
         }
@@ -279,55 +278,24 @@ __global__ void __launch_bounds__(kDThreads, FP8 ? 1 : 4) dist_lds_kernel(int M,
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-    f32x16 zero16;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) zero16[r] = 0.f;
     auto compute = [&](int buf) {
         const uint8_t *A = &lds[buf][0], *B = &lds[buf][kDM * kDRow];
-        if (FP8) {
-            i32x8 a[2], b[2];
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+            bf16x8 a[2], b[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                const uint8_t *pa = A + (wm * 64 + i * 32 + r32) * kDRow + half * 32;
-                const uint8_t *pb = B + (wn * 64 + i * 32 + r32) * kDRow + half * 32;
-                const u32x4 a0 = *reinterpret_cast<const u32x4 *>(pa);
-                const u32x4 a1 = *reinterpret_cast<const u32x4 *>(pa + 16);
-                const u32x4 b0 = *reinterpret_cast<const u32x4 *>(pb);
-                const u32x4 b1 = *reinterpret_cast<const u32x4 *>(pb + 16);
-                a[i] = (i32x8){(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w,
-                               (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
-                b[i] = (i32x8){(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w,
-                               (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
+                a[i] = *reinterpret_cast<const bf16x8 *>(
+                    A + (wm * 64 + i * 32 + r32) * kDRow + st * 32 + half * 16);
+                b[i] = *reinterpret_cast<const bf16x8 *>(
+                    B + (wn * 64 + i * 32 + r32) * kDRow + st * 32 + half * 16);
             }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    // OCP e4m3 for both operands, unit scales; each 64-wide step starts
-                    // from zero and is added in FP32 on the vector ALUs (more precise
-                    // than accumulating inside the instruction).
-                    const f32x16 part = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                        a[i], b[j], zero16, 0, 0, 0, 127, 0, 127);
-                    acc[i][j] += part;
-                }
-        } else {
-#pragma unroll
-            for (int st = 0; st < 2; ++st) {
-                bf16x8 a[2], b[2];
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    a[i] = *reinterpret_cast<const bf16x8 *>(
-                        A + (wm * 64 + i * 32 + r32) * kDRow + st * 32 + half * 16);
-                    b[i] = *reinterpret_cast<const bf16x8 *>(
-                        B + (wn * 64 + i * 32 + r32) * kDRow + st * 32 + half * 16);
-                }
-#pragma unroll
-                for (int i = 0; i < 2; ++i)
-#pragma unroll
-                    for (int j = 0; j < 2; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j],
-                                                                            0, 0, 0);
-            }
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j],
+                                                                        0, 0, 0);
         }
     };
     // Epilogue. mode 0: D = d (squared L2); mode 1: D = sqrt(max(d, 0)) (L2);
@@ -407,22 +375,6 @@ __global__ void __launch_bounds__(kDThreads, FP8 ? 1 : 4) dist_lds_kernel(int M,
 }
 
 // ---- exact k smallest per row (radix select) ----------------------------------------------
-
-// LDS histogram increment for the pending lanes of a wave: a single add when
-// they all fall into one bin (distances of a row are often concentrated, and
-// same-address atomics serialise), else one atomic per lane.
-__device__ __forceinline__ void hist_add(uint32_t *hist, bool pending, uint32_t bin, int lane)
-{
-    const uint64_t m = __ballot(pending);
-    if (!m) return;
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    const uint32_t b = __shfl(bin, leader, 64);
-    if (__ballot(pending && bin != b) == 0) {
-        if (lane == leader) atomicAdd(&hist[b], (uint32_t)__popcll(m));
-    } else if (pending) {
-        atomicAdd(&hist[bin], 1u);
-    }
-}
 
 constexpr int kSelThreads = 1024;
 constexpr int kSelMaxK = 1024;
@@ -1386,11 +1338,9 @@ static hipError_t dist_lds_launch(int M, int N, int K, const uint8_t *Q, const f
     return hipSuccess;
 }
 
-// Register ring depth (K slices in flight per block). BF16 stays at one, which
-// keeps it within 128 VGPRs (two blocks per CU); FP8 holds one block per CU in
-// any case (the separate FP32 accumulation needs more registers) and uses the
-// room for three slices in flight.
-constexpr int kDDepthBf16 = 1, kDDepthFp8 = 3;
+// Register ring depth (K slices in flight per block): one, which keeps the kernel
+// within 128 VGPRs (two blocks per CU) for both formats.
+constexpr int kDDepthBf16 = 1, kDDepthFp8 = 1;
 
 hipError_t launch_dist_bf16(int M, int N, int K, const uint16_t *Q, const float *qn,
                             const uint16_t *X, const float *xn, float *D, int mode,

@@ -142,6 +142,14 @@ hipError_t launch_topk_groups(int M, int N, int k, const float *D, void *ws, int
 size_t topk_min_ws_bytes(int M, int N, int k);
 hipError_t launch_topk_min(int M, int N, int k, const float *D, int32_t *idx, float *d, void *ws,
                            size_t ws_bytes, hipStream_t s);
+// Fused distances + k nearest per query (knn.hip): k <= knn_max_k(), no distance matrix.
+// ws of knn_ws_bytes(M, N) bytes (256-byte aligned). direct: d holds the direct-form
+// distances of the selected pairs (float64 sum, rounded once) instead of the expanded ones.
+constexpr int kKnnMaxKPublic = 256;
+size_t knn_ws_bytes(int M, int N);
+hipError_t launch_knn(bool fp8, int M, int N, int K, const void *Q, const float *qs,
+                      const float *qn, const void *X, const float *xs, const float *xn, int k,
+                      bool direct, int32_t *idx, float *d, void *ws, hipStream_t s);
 // Exact rerank of nc <= DB_KMAX candidates per query; ws of rerank_ws_bytes(nq) holds the
 // scored candidates between the scoring and the ranking kernel.
 size_t rerank_ws_bytes(int nq);

@@ -1,0 +1,117 @@
+"""The fused nearest-latent search (emb_knn): distances and the k nearest per query in one
+pass, with no distance matrix. Its indices and expanded-form values must equal, bit for
+bit, emb_distances followed by emb_topk_min (and the oracle's stable sort of those
+distances); its direct-form distances must be within 1e-5 relative of the float64
+direct form of the stored vectors, and exactly 0 for a query equal to a database row."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import need_gpu, say
+from oracle import encoder as E
+
+pytestmark = pytest.mark.gpu
+
+
+def _dequant(L, rows=None):
+    from paper_2205_04550_amd import binding as b
+    codes = L.codes if rows is None else L.codes[rows]
+    if L.fmt == b.EMB_BF16:
+        return E.bf16_decode(codes.view(torch.int16).cpu().numpy())
+    sc = (L.scale if rows is None else L.scale[rows]).cpu().numpy().astype(np.float64)
+    return E.e4m3_decode(codes.cpu().numpy()) * sc[..., None]
+
+
+def _check_equal(Q, X, k):
+    from paper_2205_04550_amd import binding as b
+    D = b.emb_distances(Q, X)
+    i0, v0 = b.emb_topk_min(D, k)
+    i1, v1 = b.emb_knn(Q, X, k, direct=False)
+    torch.cuda.synchronize()
+    assert torch.equal(i0, i1), k
+    assert torch.equal(v0.view(torch.int32), v1.view(torch.int32)), k
+    return D, i1
+
+
+@pytest.mark.parametrize("fmt,M,N,dim,ks", [
+    (0, 77, 1301, 512, (1, 10, 100, 256)),       # ragged M and N against the 128 x 256 tiles
+    (1, 77, 1301, 512, (1, 10, 100, 256)),
+    (0, 5, 3000, 48, (7, 100)),                  # K not a whole number of 32-value slices
+    (0, 300, 50_021, 64, (1, 100)),              # many tiles per split, lists compacted
+    (1, 9, 50_021, 64, (10, 256)),
+    (0, 3, 150, 32, (1, 150)),                   # one partial tile: k = N
+])
+def test_knn_equals_distances_then_topk(fmt, M, N, dim, ks):
+    need_gpu()
+    from paper_2205_04550_amd import binding as b
+    g = torch.Generator(device="cuda").manual_seed(41)
+    base = torch.randn(701, dim, generator=g, device="cuda")
+    Xf = base.repeat(N // 701 + 1, 1)[:N].contiguous()     # repeated rows: exact ties
+    Qf = torch.randn(M, dim, generator=g, device="cuda")
+    Qf[min(1, M - 1)] = base[3]
+    Q, X = b.Latents(Qf, fmt), b.Latents(Xf, fmt)
+    for k in ks:
+        say(f"knn fmt {fmt} {M} x {N} x {dim} k = {k}")
+        D, i1 = _check_equal(Q, X, k)
+    want = E.topk_by_distance(D.cpu().numpy(), ks[-1])
+    assert np.array_equal(i1.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_knn_all_distances_equal(fmt):
+    """Every database row identical: every distance of a query row ties, so each list's
+    bound must fall back to the exact k-th entry; the lowest indices win."""
+    need_gpu()
+    from paper_2205_04550_amd import binding as b
+    g = torch.Generator(device="cuda").manual_seed(5)
+    N = 20_000
+    Xf = torch.randn(1, 64, generator=g, device="cuda").repeat(N, 1)
+    Qf = torch.randn(6, 64, generator=g, device="cuda")
+    Q, X = b.Latents(Qf, fmt), b.Latents(Xf, fmt)
+    for k in (1, 100, 256):
+        _, i1 = _check_equal(Q, X, k)
+        assert np.array_equal(i1.cpu().numpy(), np.tile(np.arange(k), (6, 1)))
+
+
+@pytest.mark.parametrize("fmt,N", [(0, 50_000), (1, 50_000), (1, 500_000)])
+def test_knn_direct_form_distances(fmt, N):
+    """direct = 1: each reported distance within 1e-5 of the float64 direct form of the
+    stored vectors, and 0 exactly for the queries that are copies of database rows."""
+    need_gpu()
+    from paper_2205_04550_amd import binding as b
+    g = torch.Generator(device="cuda").manual_seed(9)
+    M, dim, k = 300, 512, 100
+    Xf = torch.randn(N, dim, generator=g, device="cuda")
+    Qf = torch.randn(M, dim, generator=g, device="cuda")
+    self_rows = [0, 17, 299]
+    Qf[self_rows] = Xf[[5, N // 2, N - 1]]
+    Q, X = b.Latents(Qf, fmt), b.Latents(Xf, fmt)
+    idx, d = b.emb_knn(Q, X, k, direct=True)
+    i_exp, _ = b.emb_knn(Q, X, k, direct=False)
+    torch.cuda.synchronize()
+    assert torch.equal(idx, i_exp)
+    q = _dequant(Q)
+    idx_h = idx.cpu().numpy()
+    x = _dequant(X, idx.view(-1).to(torch.int64)).reshape(M, k, dim)
+    d64 = ((x - q[:, None, :]) ** 2).sum(axis=2)
+    got = d.cpu().numpy().astype(np.float64)
+    err = np.abs(got - d64)
+    say(f"knn direct fmt {fmt} N {N}: max |d - d64| / d64 = {(err / np.maximum(d64, 1e-300)).max():.3g}")
+    assert np.all(err <= 1e-5 * d64)
+    for qi, xi in zip(self_rows, [5, N // 2, N - 1]):
+        assert idx_h[qi, 0] == xi and got[qi, 0] == 0.0
+
+
+@pytest.mark.parametrize("fmt,N", [(0, 50_000), (1, 500_000)])
+def test_knn_workload_shapes(fmt, N):
+    """The embedding workloads' shapes: 1,024 queries x 50,000 BF16 / 500,000 FP8 latents of
+    dimension 512, top-100: the fused search equals distances + top-k bit for bit."""
+    need_gpu()
+    from paper_2205_04550_amd import binding as b
+    g = torch.Generator(device="cuda").manual_seed(77)
+    Xf = torch.randn(N, 512, generator=g, device="cuda")
+    Qf = torch.randn(1024, 512, generator=g, device="cuda") * 0.5 + Xf[:1024] * 0.5
+    Q, X = b.Latents(Qf, fmt), b.Latents(Xf, fmt)
+    del Xf
+    say(f"knn workload fmt {fmt}: 1024 x {N}")
+    _check_equal(Q, X, 100)

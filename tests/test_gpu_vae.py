@@ -55,7 +55,7 @@ def test_l2sum_within_contract(fmt):
     want = E.l2sum_direct(q1, x1, q2, x2)
     # Each squared distance is within rel * (|q|^2 + |x|^2) (the distance contract);
     # |sqrt(a) - sqrt(b)| <= sqrt(|a - b|), plus float rounding of the roots and the sum.
-    rel = 1e-5 if fmt == b.EMB_BF16 else 5e-5
+    rel = 1e-5                     # the distance contract, both formats
     bnd = sum(np.sqrt(rel * ((q ** 2).sum(1)[:, None] + (x ** 2).sum(1)[None, :]))
               for q, x in ((q1, x1), (q2, x2)))
     err = np.abs(D - want)
