@@ -259,8 +259,9 @@ int emb_topk_groups(int M, int N, const float *D, int k, int32_t *idx, float *d,
  * over the stored (dequantised) values, summed in float64 and rounded once to
  * float (within 2^-24 relative of the float64 value; exactly 0 for identical
  * codes and scales). BF16 or FP8 only; 1 <= k <= min(N, 256); ws (device,
- * 256-byte aligned) of emb_knn_workspace_bytes bytes; other argument rules as
- * emb_distances (the query codes below 2 GiB; database codes of any size). */
+ * 256-byte aligned) of emb_knn_workspace_bytes bytes; query codes below 2 GiB
+ * and database codes below 4 GiB (DB_EINVAL otherwise); other argument rules as
+ * emb_distances. */
 size_t emb_knn_workspace_bytes(int M, int N, int k);
 int emb_knn(int fmt, int M, int N, int dim, const void *q_codes, const float *q_scale,
             const float *q_sq, const void *x_codes, const float *x_scale, const float *x_sq, int k,

@@ -864,6 +864,8 @@ int emb_knn(int fmt, int M, int N, int dim, const void *q_codes, const float *q_
     if (k < 1 || k > kKnnMaxKPublic || k > N || !idx)
         return fail(DB_EINVAL, "emb_knn: k = %d outside [1, min(N, %d)] or idx NULL", k,
                     kKnnMaxKPublic);
+    if ((int64_t)N * dim * (fmt == EMB_BF16 ? 2 : 1) >= ((int64_t)1 << 32))
+        return fail(DB_EINVAL, "emb_knn: database codes must stay below 4 GiB");
     const size_t need = knn_ws_bytes(M, N);
     if (!ws || !aligned(ws, kAlign) || ws_bytes < need)
         return fail(DB_ENOSPC, "emb_knn: workspace %zu bytes < %zu needed (256-byte aligned)",

@@ -38,6 +38,7 @@ namespace tdb {
 constexpr int kKnnCap = 1024;                 // list entries per (block, row)
 constexpr int kKnnTrigger = kKnnCap - kDN;    // a list holding more is compacted
 constexpr int kKnnKeepMax = 512;              // more kept by the key bound: exact bound
+constexpr int kKnnFinal = 512;                // a longer list is tightened at the end
 constexpr int kKnnMaxK = kKnnMaxKPublic;
 constexpr int kKnnMaxSplit = 64;
 
@@ -55,24 +56,51 @@ __device__ __forceinline__ int wave_count_le(const uint32_t (&v)[4], uint32_t x)
     return c;
 }
 
-// Tighten the bound of one row and drop the entries above it (one wave, every lane
-// active; L is the row's list, *cnt and *bound its LDS state).
-__device__ __forceinline__ void knn_compact(uint64_t *__restrict__ L, uint32_t *cnt,
-                                                     uint64_t *bound, int k, int lane)
+// The float whose key is the high half of bound B: every distance whose packed value is
+// <= B is <= it (+inf while B has no key yet).
+__device__ __forceinline__ float bound_float(uint64_t B)
 {
+    const uint32_t key = (uint32_t)(B >> 32);
+    return key == ~0u ? __int_as_float(0x7f800000) : fkey_inv(key);
+}
+
+// The row part of a conservative test on the dot product: with tau the bound's float,
+// a distance dv = fl(fl(qn + xn) - 2 dot) <= tau implies dot >= (qn + xn - tau) / 2 - e
+// with e below 2^-24 (qn + xn + 2 |tau|) (qn, xn >= 0). The test dot >= alpha + beta, with
+// alpha = (qn - tau) / 2 - m (qn + |tau|) and beta = xn / 2 - m xn (m = 4e-7, above six
+// units of rounding, which also covers the rounding of alpha + beta), never fails for such
+// a distance; distances passing it are tested exactly.
+__device__ __forceinline__ float knn_alpha(float qn, float tau)
+{
+    if (!(tau < __int_as_float(0x7f800000))) return __int_as_float(0xff800000);   // -inf
+    return (qn - tau) * 0.5f - 4e-7f * (qn + fabsf(tau));
+}
+
+// Tighten the bound of one row and drop the entries above it (one wave, every lane
+// active; L is the row's list of n <= kKnnCap entries, *cnt, *bound and *tauf its LDS
+// state). The whole list is loaded once, 16 entries per lane.
+__device__ __forceinline__ void knn_compact(uint64_t *__restrict__ L, uint32_t *cnt,
+                                            uint64_t *bound, float *tauf, float *alpha, float qn,
+                                            int k, int lane)
+{
+    constexpr int R = kKnnCap / 64;
     const int n = (int)*cnt;
     uint64_t B = *bound;
-    // The four smallest keys among this lane's entries (lane, lane + 64, ...).
+    // Opaque lane index: keeps the compiler from hoisting the 16 entry offsets of the
+    // lane out of the kernel's tile loop (they would hold registers for the whole kernel).
+    asm volatile("" : "+v"(lane));
+    uint64_t e[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        const int i = u * 64 + lane;
+        e[u] = ~0ull;
+        if (u * 64 < n && i < n) e[u] = L[i];
+    }
+    // The four smallest keys among this lane's entries.
     uint32_t best[4] = {~0u, ~0u, ~0u, ~0u};
-    for (int j0 = 0; j0 * 64 < n; j0 += 4) {
-        uint64_t e[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = (j0 + u) * 64 + lane;
-            e[u] = i < n ? L[i] : ~0ull;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < R; ++u) {
+        if (u * 64 < n) {                          // uniform: past n the groups are empty
             uint32_t x = (uint32_t)(e[u] >> 32);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -84,7 +112,8 @@ __device__ __forceinline__ void knn_compact(uint64_t *__restrict__ L, uint32_t *
     }
     // T = the k-th smallest of the 256 (smallest x with at least k values <= x). A value
     // below all ones is a real entry, so k distinct entries have key <= T; T = all ones
-    // (too few entries) leaves B as it is.
+    // (too few entries) leaves B as it is. With at most four entries per lane the 256 are
+    // all the entries and T is the exact k-th smallest key.
     uint32_t lo = 0, hi = ~0u;
     while (lo < hi) {
         const uint32_t mid = lo + ((hi - lo) >> 1);
@@ -94,24 +123,14 @@ __device__ __forceinline__ void knn_compact(uint64_t *__restrict__ L, uint32_t *
     const uint64_t Bk = ((uint64_t)lo << 32) | 0xffffffffull;
     if (Bk < B) B = Bk;
     const uint64_t lt = lanemask_lt64(lane);
-    // Keep the entries <= B in order, in place: a chunk's loads all precede its stores,
-    // and stores only reach positions below the chunk's first entry plus its kept count.
+    // Keep the entries <= B, in order (all of them are in registers).
     int kept = 0;
-    for (int j0 = 0; j0 * 64 < n; j0 += 4) {
-        uint64_t e[4];
-        bool keep[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = (j0 + u) * 64 + lane;
-            e[u] = i < n ? L[i] : ~0ull;
-            keep[u] = i < n && e[u] <= B;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint64_t m = __ballot(keep[u]);
-            if (keep[u]) L[kept + __popcll(m & lt)] = e[u];
-            kept += __popcll(m);
-        }
+    for (int u = 0; u < R; ++u) {
+        const bool keep = u * 64 + lane < n && e[u] <= B;
+        const uint64_t m = __ballot(keep);
+        if (keep) L[kept + __popcll(m & lt)] = e[u];
+        kept += __popcll(m);
     }
     if (kept > kKnnKeepMax) {
         // Many entries share the bound's key: B = the exact k-th smallest packed value.
@@ -119,28 +138,26 @@ __device__ __forceinline__ void knn_compact(uint64_t *__restrict__ L, uint32_t *
         while (lo64 < hi64) {
             const uint64_t mid = lo64 + ((hi64 - lo64) >> 1);
             int c = 0;
-            for (int i0 = 0; i0 < kept; i0 += 64) {
-                const int i = i0 + lane;
-                c += __popcll(__ballot(i < kept && L[i] <= mid));
-            }
+#pragma unroll
+            for (int u = 0; u < R; ++u) c += __popcll(__ballot(u * 64 + lane < n && e[u] <= mid));
             if (c >= k) hi64 = mid;
             else lo64 = mid + 1;
         }
         B = lo64;
-        int kk = 0;
-        for (int i0 = 0; i0 < kept; i0 += 64) {
-            const int i = i0 + lane;
-            const uint64_t e = i < kept ? L[i] : ~0ull;
-            const bool keep = i < kept && e <= B;
+        kept = 0;
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const bool keep = u * 64 + lane < n && e[u] <= B;
             const uint64_t m = __ballot(keep);
-            if (keep) L[kk + __popcll(m & lt)] = e;
-            kk += __popcll(m);
+            if (keep) L[kept + __popcll(m & lt)] = e[u];
+            kept += __popcll(m);
         }
-        kept = kk;
     }
     if (lane == 0) {
         *cnt = (uint32_t)kept;
         *bound = B;
+        *tauf = bound_float(B);
+        *alpha = knn_alpha(qn, *tauf);
     }
 }
 
@@ -148,17 +165,21 @@ __device__ __forceinline__ void knn_compact(uint64_t *__restrict__ L, uint32_t *
 // so the blocks of one split (all query tiles) share an XCD and its L2 copy of the split's
 // database tiles. Split s takes database tiles [s nt / nsplit, (s + 1) nt / nsplit).
 // Outputs per (block, row): the list lists[b][row][0 .. cnt), cnt, and the bound.
-template <bool FP8, bool TAIL>
+// SEEDB: no bound is given; the block's first tile provides one (the sample pass).
+template <bool FP8, bool TAIL, bool SEEDB>
 __global__ void __launch_bounds__(kDThreads, 4) knn_kernel(
     int M, int N, int K, int k, int mt, int nsplit, int nt, const uint8_t *__restrict__ Q,
     const float *__restrict__ qs, const float *__restrict__ qn, const uint8_t *__restrict__ X,
-    const float *__restrict__ xs, const float *__restrict__ xn, uint64_t *__restrict__ lists,
-    uint32_t *__restrict__ cnt_out, uint64_t *__restrict__ bound_out)
+    const float *__restrict__ xs, const float *__restrict__ xn, const uint64_t *__restrict__ seed,
+    uint64_t *__restrict__ lists, uint32_t *__restrict__ cnt_out, uint64_t *__restrict__ bound_out)
 {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2][(kDM + kDN) * kDRow];
     __shared__ float tv[2][2][kDM + kDN];
     __shared__ uint64_t s_bound[kDM];
     __shared__ uint32_t s_cnt[kDM];
+    __shared__ float s_tauf[kDM];
+    __shared__ float s_alpha[kDM], s_qn[kDM];
+    __shared__ uint32_t s_seed[kDM];
     const int b = blockIdx.x;
     const int m = (b / kXcds) % mt, s = (b / kXcds) / mt * kXcds + b % kXcds;
     const int m0 = m * kDM;
@@ -166,8 +187,15 @@ __global__ void __launch_bounds__(kDThreads, 4) knn_kernel(
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint64_t *const Lb = lists + (size_t)b * kDM * kKnnCap;
     if (tid < kDM) {
-        s_bound[tid] = ~0ull;
+        // A bound given for the whole row (from a sample of the database) holds for every
+        // split; without one, the block's first tile provides the first bound.
+        const uint64_t B = !SEEDB && m0 + tid < M ? seed[m0 + tid] : ~0ull;
+        s_bound[tid] = B;
         s_cnt[tid] = 0;
+        s_tauf[tid] = bound_float(B);
+        s_qn[tid] = qn[min(m0 + tid, M - 1)];
+        s_alpha[tid] = knn_alpha(s_qn[tid], s_tauf[tid]);
+        s_seed[tid] = 0;
     }
     const int Kb = FP8 ? K : 2 * K;                        // bytes per row in Q and X
     const int nslices = (2 * K + kDSlice - 1) / kDSlice;   // 32 values per slice
@@ -183,9 +211,10 @@ __global__ void __launch_bounds__(kDThreads, 4) knn_kernel(
         const uint32_t kb = FP8 ? (uint32_t)(sl * (kDSlice / 2) + (fpart >> 1))
                                 : (uint32_t)(sl * kDSlice + fpart);
         if (!TAIL || (int)kb < Kb) {
-            const uint64_t o0 = (uint64_t)min(m0 + frow, M - 1) * (uint64_t)Kb + kb;
-            const uint64_t o1 = (uint64_t)min(n0 + frow, N - 1) * (uint64_t)Kb + kb;
-            const uint64_t o2 = (uint64_t)min(n0 + kDM + frow, N - 1) * (uint64_t)Kb + kb;
+            // 32-bit offsets: the host keeps N Kb (and M Kb) below 4 GiB.
+            const uint32_t o0 = (uint32_t)min(m0 + frow, M - 1) * (uint32_t)Kb + kb;
+            const uint32_t o1 = (uint32_t)min(n0 + frow, N - 1) * (uint32_t)Kb + kb;
+            const uint32_t o2 = (uint32_t)min(n0 + kDM + frow, N - 1) * (uint32_t)Kb + kb;
             if (FP8) {
                 dst[0] = e4m3x8_to_bf16(*reinterpret_cast<const u32x2 *>(Q + o0));
                 dst[1] = e4m3x8_to_bf16(*reinterpret_cast<const u32x2 *>(X + o1));
@@ -222,13 +251,9 @@ __global__ void __launch_bounds__(kDThreads, 4) knn_kernel(
         }
     };
     f32x16 acc[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-    auto compute = [&](int buf) {
+    // The first slice of a tile starts its products from zero (not from the accumulators),
+    // so the accumulators are free between a tile's epilogue and its successor's first slice.
+    auto compute = [&](int buf, bool first) {
         const uint8_t *A = &lds[buf][0], *Bm = &lds[buf][kDM * kDRow];
 #pragma unroll
         for (int st = 0; st < 2; ++st) {
@@ -243,44 +268,151 @@ __global__ void __launch_bounds__(kDThreads, 4) knn_kernel(
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], bb[j], acc[i][j],
-                                                                        0, 0, 0);
+                for (int j = 0; j < 2; ++j) {
+                    if (st == 0 && first) {
+                        const f32x16 z = {};
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], bb[j], z, 0, 0,
+                                                                            0);
+                    } else {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], bb[j],
+                                                                            acc[i][j], 0, 0, 0);
+                    }
+                }
         }
     };
     // The distances of a finished tile (the arithmetic of the distance kernel's epilogue),
     // appended to the lists of their rows where they are within the rows' bounds.
-    auto epilogue = [&](int i_tile) {
+    //
+    // seed (the block's first tile, when no bound was given): first a bound from the tile
+    // itself. The 64 distances a wave holds for one row are split over the 32 lanes of a
+    // half-wave (two per lane); each of the 4 waves sharing the row finds the q-th
+    // smallest key of its 64 (q = ceil(k / 4); bisection on the key, ballot counts), and
+    // the row's bound is the largest of the 4: at least 4 q >= k distinct entries of the
+    // tile lie at or below it.
+    auto epilogue = [&](int i_tile, bool seedb) {
         const int n0 = (t0 + i_tile) * kDN;
         const float(&t)[2][kDM + kDN] = tv[i_tile & 1];
         // The lane's first row, made opaque here so that the compiler does not hoist the
         // 32 row addresses of the lists out of the tile loop (they would be spilled).
         int rbase = wm * 64 + 4 * half;
         asm volatile("" : "+v"(rbase));
+        auto dist = [&](int i, int j, int r, int rl) {
+            const int cl = wn * 64 + j * 32 + r32;
+            const float xc = t[0][kDM + cl];
+            const float sc = FP8 ? t[1][kDM + cl] : 1.0f;
+            const float dot = FP8 ? (t[1][rl] * sc) * acc[i][j][r] : acc[i][j][r];
+            const float dv = (t[0][rl] + xc) - 2.0f * dot;
+            // An entry outside the matrix gets NaN: it passes no test below.
+            return (m0 + rl < M && n0 + cl < N) ? dv : __int_as_float(0x7fc00000);
+        };
+        if constexpr (SEEDB) {
+            // The block's first tile: distances into the accumulators, then the bound.
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int rl0 = rbase + i * 32;
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int rl = rl0 + 8 * (r >> 2) + (r & 3);
-                const uint64_t B = s_bound[rl];
-                const bool row_ok = m0 + rl < M;
+                for (int r = 0; r < 16; ++r)
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const int cl = wn * 64 + j * 32 + r32, col = n0 + cl;
-                    const float xc = t[0][kDM + cl];
-                    const float sc = FP8 ? t[1][kDM + cl] : 1.0f;
-                    const float dot = FP8 ? (t[1][rl] * sc) * acc[i][j][r] : acc[i][j][r];
-                    const float dv = (t[0][rl] + xc) - 2.0f * dot;
-                    acc[i][j][r] = 0.f;
-                    const uint64_t p = ((uint64_t)fkey(dv) << 32) | (uint32_t)col;
-                    if (row_ok && col < N && p <= B) {
-                        const uint32_t pos = atomicAdd(&s_cnt[rl], 1u);
-                        Lb[(size_t)rl * kKnnCap + pos] = p;
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j][r] = dist(i, j, r, rbase + i * 32 + 8 * (r >> 2) + (r & 3));
+            if (seedb) {
+                const int q = (k + 3) / 4;
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int rl = rbase + i * 32 + 8 * (r >> 2) + (r & 3);
+                        uint32_t kj[2];
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) {
+                            const float v = acc[i][j][r];
+                            kj[j] = v == v ? fkey(v) : ~0u;
+                        }
+                        uint32_t lo = 0, hi = ~0u;          // uniform within each half-wave
+                        for (int step = 0; step < 32; ++step) {
+                            const uint32_t mid = lo + ((hi - lo) >> 1);
+                            const uint64_t a = __ballot(kj[0] <= mid), bb = __ballot(kj[1] <= mid);
+                            const uint32_t c =
+                                half ? __popc((uint32_t)(a >> 32)) + __popc((uint32_t)(bb >> 32))
+                                     : __popc((uint32_t)a) + __popc((uint32_t)bb);
+                            if (c >= (uint32_t)q) hi = mid;
+                            else lo = mid + 1;
+                        }
+                        if (r32 == 0) atomicMax(&s_seed[rl], lo);
+                    }
+                __syncthreads();
+                if (tid < kDM) {
+                    const uint32_t T = s_seed[tid];
+                    const uint64_t Bt = T == ~0u ? ~0ull : (((uint64_t)T << 32) | 0xffffffffull);
+                    if (Bt < s_bound[tid]) {
+                        s_bound[tid] = Bt;
+                        s_tauf[tid] = bound_float(Bt);
+                        s_alpha[tid] = knn_alpha(s_qn[tid], s_tauf[tid]);
                     }
                 }
+                __syncthreads();
             }
         }
+        // Appends: a float test against the bound first (most distances fail it), then the
+        // exact test on the packed value; the lanes of a half-wave (one row) reserve their
+        // places in the row's list with one LDS atomic.
+        const uint64_t hmask = half ? 0xffffffff00000000ull : 0x00000000ffffffffull;
+        float beta[2], scol[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const float xn_c = t[0][kDM + wn * 64 + j * 32 + r32];
+            beta[j] = xn_c * 0.5f - 4e-7f * xn_c;
+            scol[j] = FP8 ? t[1][kDM + wn * 64 + j * 32 + r32] : 1.0f;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int rl = rbase + i * 32 + 8 * (r >> 2) + (r & 3);
+                float dv[2];
+                bool pre0, pre1;
+                if constexpr (SEEDB) {
+                    const float tau = s_tauf[rl];
+                    dv[0] = acc[i][0][r];
+                    dv[1] = acc[i][1][r];
+                    pre0 = dv[0] <= tau;
+                    pre1 = dv[1] <= tau;
+                } else {
+                    // The conservative test on the dot product (two operations per entry).
+                    const float al = s_alpha[rl];
+                    float dt[2];
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        dt[j] = FP8 ? (t[1][rl] * scol[j]) * acc[i][j][r] : acc[i][j][r];
+                    pre0 = dt[0] >= al + beta[0];
+                    pre1 = dt[1] >= al + beta[1];
+                    if (__ballot(pre0 || pre1) == 0) continue;      // uniform
+                    dv[0] = dist(i, 0, r, rl);
+                    dv[1] = dist(i, 1, r, rl);
+                }
+                if (__ballot(pre0 || pre1) == 0) continue;          // uniform
+                const uint64_t B = s_bound[rl];
+                uint64_t p[2];
+                bool ok[2];
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int col = n0 + wn * 64 + j * 32 + r32;
+                    p[j] = ((uint64_t)fkey(dv[j]) << 32) | (uint32_t)col;
+                    ok[j] = (j ? pre1 : pre0) && p[j] <= B;
+                }
+                const uint64_t m0b = __ballot(ok[0]) & hmask, m1b = __ballot(ok[1]) & hmask;
+                const uint32_t c0 = (uint32_t)__popcll(m0b), c = c0 + (uint32_t)__popcll(m1b);
+                uint32_t base = 0;
+                if (r32 == 0 && c) base = atomicAdd(&s_cnt[rl], c);
+                base = __shfl(base, half * 32, 64);
+                // mbcnt: set bits of the mask in the lanes below this one.
+                const uint32_t b0 = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(m0b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m0b, 0u));
+                const uint32_t b1 = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(m1b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m1b, 0u));
+                uint64_t *Lr = Lb + (size_t)rl * kKnnCap + base;
+                if (ok[0]) Lr[b0] = p[0];
+                if (ok[1]) Lr[c0 + b1] = p[1];
+            }
     };
     __syncthreads();
     if (U > 0) {
@@ -289,28 +421,40 @@ __global__ void __launch_bounds__(kDThreads, 4) knn_kernel(
         if (1 < U) fetch(1, pre, prv);
         __syncthreads();
     }
-    int tile = 0, sl = 0;
-    for (int u = 0; u < U; ++u) {
-        compute(u & 1);
+    // Slice u of the block's stream: tile u / nslices, K slice u % nslices. The first
+    // slice of a tile is peeled off the slice loop, so the accumulators are dead between
+    // a tile's epilogue and the next tile (the list compaction uses those registers).
+    int u = 0;
+    for (int tile = 0; tile < t1 - t0; ++tile) {
+        compute(u & 1, true);
         if (u + 1 < U) {
             stash(u + 1, pre, prv);
             if (u + 2 < U) fetch(u + 2, pre, prv);
         }
-        if (++sl == nslices) {
-            epilogue(tile);
-            __syncthreads();                       // every append of the tile is done
-            for (int rl = wave; rl < kDM; rl += kDThreads / 64)
-                if (s_cnt[rl] > (uint32_t)kKnnTrigger)
-                    knn_compact(Lb + (size_t)rl * kKnnCap, &s_cnt[rl], &s_bound[rl], k, lane);
-            ++tile;
-            sl = 0;
+        for (int sl = 1; sl < nslices; ++sl) {
+            __syncthreads();
+            ++u;
+            compute(u & 1, false);
+            if (u + 1 < U) {
+                stash(u + 1, pre, prv);
+                if (u + 2 < U) fetch(u + 2, pre, prv);
+            }
         }
+        ++u;
+        epilogue(tile, tile == 0);
+        __syncthreads();                           // every append of the tile is done
+        // A list that outgrows the trigger is tightened.
+        for (int rl = wave; rl < kDM; rl += kDThreads / 64)
+            if (s_cnt[rl] > (uint32_t)kKnnTrigger)
+                knn_compact(Lb + (size_t)rl * kKnnCap, &s_cnt[rl], &s_bound[rl], &s_tauf[rl],
+                            &s_alpha[rl], s_qn[rl], k, lane);
         __syncthreads();
     }
-    // Last tightening (fewer entries for the merge), then the per-row results.
+    // Long lists are tightened once more (fewer entries for the merge); then the results.
     for (int rl = wave; rl < kDM; rl += kDThreads / 64)
-        if (s_cnt[rl] > (uint32_t)k)
-            knn_compact(Lb + (size_t)rl * kKnnCap, &s_cnt[rl], &s_bound[rl], k, lane);
+        if (s_cnt[rl] > (uint32_t)kKnnFinal)
+            knn_compact(Lb + (size_t)rl * kKnnCap, &s_cnt[rl], &s_bound[rl], &s_tauf[rl],
+                        &s_alpha[rl], s_qn[rl], k, lane);
     __syncthreads();
     if (tid < kDM) {
         cnt_out[(size_t)b * kDM + tid] = s_cnt[tid];
@@ -325,14 +469,15 @@ constexpr int kMergeCap = 8192;     // gathered candidates held in LDS
 __global__ void __launch_bounds__(kMergeThreads) knn_merge_kernel(
     int k, int mt, int nsplit, const uint64_t *__restrict__ lists,
     const uint32_t *__restrict__ cnt, const uint64_t *__restrict__ bound, int32_t *__restrict__ idx,
-    float *__restrict__ dout)
+    float *__restrict__ dout, uint64_t *__restrict__ kth_out)
 {
     __shared__ uint64_t buf[kMergeCap];
     __shared__ uint64_t win[kKnnMaxK];
     __shared__ uint32_t hist[256];
-    __shared__ uint32_t s_blk[kKnnMaxSplit], s_n[kKnnMaxSplit];
+    __shared__ uint32_t s_blk[kKnnMaxSplit], s_n[kKnnMaxSplit], s_off[kKnnMaxSplit + 1];
     __shared__ uint64_t s_B;
     __shared__ uint32_t s_gather, s_win, s_sel[3];
+    __shared__ unsigned long long s_lo, s_hi;
     const int q = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     const int m = q / kDM, r = q % kDM;
     if (tid < nsplit) {
@@ -344,30 +489,58 @@ __global__ void __launch_bounds__(kMergeThreads) knn_merge_kernel(
     if (tid == 0) {
         s_gather = 0;
         s_win = 0;
+        s_lo = ~0ull;
+        s_hi = 0;
     }
     __syncthreads();
     if (tid == 0) {
         uint64_t B = ~0ull;
+        uint32_t off = 0;
         for (int s = 0; s < nsplit; ++s) {
             const uint64_t v = bound[(size_t)s_blk[s] * kDM + r];
             B = v < B ? v : B;
+            s_off[s] = off;
+            off += s_n[s];
         }
+        s_off[nsplit] = off;
         s_B = B;
     }
     __syncthreads();
     const uint64_t Bs = s_B;
-    // Gather the entries <= B* into LDS while they fit.
-    for (int s = 0; s < nsplit; ++s) {
-        const uint64_t *L = lists + ((size_t)s_blk[s] * kDM + r) * kKnnCap;
-        const int n = (int)s_n[s];
-        for (int j = tid; j < n; j += kMergeThreads) {
-            const uint64_t e = L[j];
-            if (e <= Bs) {
+    const uint32_t n_all = s_off[nsplit];
+    // Entry f of the row's lists laid end to end (split by binary search on the offsets).
+    auto entry = [&](uint32_t f) {
+        int lo = 0, hi = nsplit - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= f) lo = mid;
+            else hi = mid - 1;
+        }
+        return lists[((size_t)s_blk[lo] * kDM + r) * kKnnCap + (f - s_off[lo])];
+    };
+    // Gather the entries <= B* into LDS while they fit; four loads in flight per thread.
+    // Their smallest and largest values fix the bits all of them share.
+    uint64_t lo_t = ~0ull, hi_t = 0;
+    for (uint32_t f0 = 0; f0 < n_all; f0 += 4 * kMergeThreads) {
+        uint64_t e[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t f = f0 + u * kMergeThreads + tid;
+            e[u] = f < n_all ? entry(f) : ~0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t f = f0 + u * kMergeThreads + tid;
+            if (f < n_all && e[u] <= Bs) {
                 const uint32_t pos = atomicAdd(&s_gather, 1u);
-                if (pos < (uint32_t)kMergeCap) buf[pos] = e;
+                if (pos < (uint32_t)kMergeCap) buf[pos] = e[u];
+                lo_t = e[u] < lo_t ? e[u] : lo_t;
+                hi_t = e[u] > hi_t ? e[u] : hi_t;
             }
         }
     }
+    atomicMin(&s_lo, (unsigned long long)lo_t);
+    atomicMax(&s_hi, (unsigned long long)hi_t);
     __syncthreads();
     const uint32_t total = s_gather;
     const bool in_lds = total <= (uint32_t)kMergeCap;
@@ -375,7 +548,11 @@ __global__ void __launch_bounds__(kMergeThreads) knn_merge_kernel(
     // the bin holding the k-th smallest is fixed; once that bin's count equals what is
     // still needed, every candidate whose fixed bits are <= the prefix is a winner.
     const int kk = min(k, (int)min(total, (uint32_t)INT_MAX));
-    if (kk == 0) {                          // no candidate (cannot happen for k <= N)
+    if (kk < k) {                           // fewer candidates than k (cannot happen for k <= N)
+        if (kth_out && tid == 0) kth_out[q] = ~0ull;
+        if (kth_out) return;
+    }
+    if (kk == 0) {
         if (tid < k) {
             idx[(size_t)q * k + tid] = -1;
             dout[(size_t)q * k + tid] = __int_as_float(0x7fc00000);
@@ -383,9 +560,14 @@ __global__ void __launch_bounds__(kMergeThreads) knn_merge_kernel(
         return;
     }
     if (tid == 0) s_sel[0] = s_sel[1] = s_sel[2] = 0;
-    uint64_t prefix = 0, mask = 0;
+    // The radix passes start at the highest byte in which the candidates differ.
+    const uint64_t diff = (uint64_t)s_lo ^ (uint64_t)s_hi;
+    const int top = diff ? 63 - __clzll(diff) : 0;
+    const int pass0 = 7 - top / 8;
+    uint64_t mask = pass0 ? ~0ull << (64 - 8 * pass0) : 0ull;
+    uint64_t prefix = (uint64_t)s_lo & mask;
     uint32_t remaining = (uint32_t)kk;
-    for (int pass = 0; pass < 8; ++pass) {
+    for (int pass = pass0; pass < 8; ++pass) {
         const int shift = 56 - 8 * pass;
         for (int i = tid; i < 256; i += kMergeThreads) hist[i] = 0;
         __syncthreads();
@@ -397,15 +579,11 @@ __global__ void __launch_bounds__(kMergeThreads) knn_merge_kernel(
                 hist_add(hist, pend, (uint32_t)(e >> shift) & 255u, lane);
             }
         } else {
-            for (int s = 0; s < nsplit; ++s) {
-                const uint64_t *L = lists + ((size_t)s_blk[s] * kDM + r) * kKnnCap;
-                const int n = (int)s_n[s];
-                for (int j0 = 0; j0 < n; j0 += kMergeThreads) {
-                    const int j = j0 + tid;
-                    const uint64_t e = j < n ? L[j] : ~0ull;
-                    const bool pend = j < n && e <= Bs && (e & mask) == prefix;
-                    hist_add(hist, pend, (uint32_t)(e >> shift) & 255u, lane);
-                }
+            for (uint32_t f0 = 0; f0 < n_all; f0 += kMergeThreads) {
+                const uint32_t f = f0 + tid;
+                const uint64_t e = f < n_all ? entry(f) : ~0ull;
+                const bool pend = f < n_all && e <= Bs && (e & mask) == prefix;
+                hist_add(hist, pend, (uint32_t)(e >> shift) & 255u, lane);
             }
         }
         __syncthreads();
@@ -453,30 +631,56 @@ __global__ void __launch_bounds__(kMergeThreads) knn_merge_kernel(
     if (in_lds) {
         for (uint32_t i = tid; i < total; i += kMergeThreads) take(buf[i], true);
     } else {
-        for (int s = 0; s < nsplit; ++s) {
-            const uint64_t *L = lists + ((size_t)s_blk[s] * kDM + r) * kKnnCap;
-            const int n = (int)s_n[s];
-            for (int j = tid; j < n; j += kMergeThreads) {
-                const uint64_t e = L[j];
-                take(e, e <= Bs);
-            }
+        for (uint32_t f = tid; f < n_all; f += kMergeThreads) {
+            const uint64_t e = entry(f);
+            take(e, e <= Bs);
         }
     }
     __syncthreads();
-    // Sort the winners (padded to 256) ascending: bitonic, one element per thread.
-    uint64_t v = tid < kk ? win[tid] : ~0ull;
+    // Sort the winners (padded to 256) ascending in one wave: four per lane, element
+    // e = 64 u + lane, bitonic network (partners across lanes by shuffle, across
+    // registers in place); no block barrier.
+    if (tid >= 64) return;
+    uint64_t w[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) w[u] = 64 * u + lane < kk ? win[64 * u + lane] : ~0ull;
+    auto shfl64 = [&](uint64_t x, int src) {
+        const uint32_t lo = __shfl((uint32_t)x, src, 64), hi = __shfl((uint32_t)(x >> 32), src, 64);
+        return ((uint64_t)hi << 32) | lo;
+    };
+#pragma unroll
     for (int size = 2; size <= kKnnMaxK; size <<= 1)
+#pragma unroll
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            __syncthreads();
-            win[tid] = v;
-            __syncthreads();
-            const uint64_t o = win[tid ^ stride];
-            const bool up = (tid & size) == 0, lower = (tid & stride) == 0;
-            v = (lower == up) ? (o < v ? o : v) : (o > v ? o : v);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = 64 * u + lane;
+                const bool up = (e & size) == 0, lower = (e & stride) == 0;
+                uint64_t o;
+                if (stride >= 64) {
+                    const int pu = u ^ (stride >> 6);
+                    if (pu < u) continue;               // the pair is handled once, from below
+                    o = w[pu];
+                    const uint64_t mn = o < w[u] ? o : w[u], mx = o < w[u] ? w[u] : o;
+                    w[u] = up ? mn : mx;
+                    w[pu] = up ? mx : mn;
+                    continue;
+                }
+                o = shfl64(w[u], lane ^ stride);
+                w[u] = (lower == up) ? (o < w[u] ? o : w[u]) : (o > w[u] ? o : w[u]);
+            }
         }
-    if (tid < k) {
-        idx[(size_t)q * k + tid] = tid < kk ? (int32_t)(uint32_t)v : -1;
-        dout[(size_t)q * k + tid] = tid < kk ? fkey_inv((uint32_t)(v >> 32)) : __int_as_float(0x7fc00000);
+    uint64_t v = w[0];
+    (void)v;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int e = 64 * u + lane;
+        if (kth_out) {
+            if (e == k - 1) kth_out[q] = w[u];     // the k-th smallest packed value
+        } else if (e < k) {
+            idx[(size_t)q * k + e] = e < kk ? (int32_t)(uint32_t)w[u] : -1;
+            dout[(size_t)q * k + e] = e < kk ? fkey_inv((uint32_t)(w[u] >> 32)) : __int_as_float(0x7fc00000);
+        }
     }
 }
 
@@ -499,21 +703,27 @@ __global__ void __launch_bounds__(256) knn_direct_kernel(int M, int N, int k, in
     const int32_t e = idx[pair];
     if (e < 0 || e >= N) return;
     double acc = 0.0;
-    if (FP8) {
-        const double sq = qs[q], sx = xs[e];
-        for (int i = lane; i < K; i += 64) {
-            const double a = sq * (double)e4m3_val(Q[(int64_t)q * K + i]);
-            const double c = sx * (double)e4m3_val(X[(int64_t)e * K + i]);
-            acc += (a - c) * (a - c);
+    // Eight values per lane per step (K % 8 == 0; rows 8-byte (FP8) / 16-byte (BF16) aligned).
+    for (int i0 = lane * 8; i0 < K; i0 += 512) {
+        u32x4 a, c;
+        double sa = 1.0, sc = 1.0;
+        if (FP8) {
+            a = e4m3x8_to_bf16(*reinterpret_cast<const u32x2 *>(Q + (int64_t)q * K + i0));
+            c = e4m3x8_to_bf16(*reinterpret_cast<const u32x2 *>(X + (int64_t)e * K + i0));
+            sa = qs[q];
+            sc = xs[e];
+        } else {
+            a = *reinterpret_cast<const u32x4 *>(Q + ((int64_t)q * K + i0) * 2);
+            c = *reinterpret_cast<const u32x4 *>(X + ((int64_t)e * K + i0) * 2);
         }
-    } else {
-        const uint16_t *q16 = reinterpret_cast<const uint16_t *>(Q);
-        const uint16_t *x16 = reinterpret_cast<const uint16_t *>(X);
-        for (int i = lane; i < K; i += 64) {
-            const double a = bf16_val(q16[(int64_t)q * K + i]);
-            const double c = bf16_val(x16[(int64_t)e * K + i]);
-            acc += (a - c) * (a - c);
-        }
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const double va = sa * (double)bf16_val((uint16_t)(a[w] >> (16 * h)));
+                const double vc = sc * (double)bf16_val((uint16_t)(c[w] >> (16 * h)));
+                acc += (va - vc) * (va - vc);
+            }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
@@ -526,44 +736,88 @@ int knn_splits(int M, int N)
 {
     (void)M;
     const int nt = (N + kDN - 1) / kDN;
-    const int ns = kXcds * (nt / (6 * kXcds));   // at least six tiles per split
+    const int ns = kXcds * (nt / (3 * kXcds));   // at least three tiles per split
     return max(kXcds, min(kKnnMaxSplit, ns));
+}
+
+// Columns of the sample whose exact k-th smallest distance bounds every row before the
+// full pass (0: no sample pass). One tile per split, so its blocks are short.
+static int knn_sample_cols(int N)
+{
+    if (N < 8 * kXcds * kDN) return 0;
+    const int t = min(kKnnMaxSplit, max(kXcds, (N / 8 / kDN) / kXcds * kXcds));
+    return t * kDN;
 }
 
 size_t knn_ws_bytes(int M, int N)
 {
     const size_t G = (size_t)((M + kDM - 1) / kDM) * knn_splits(M, N);
     return align_up(G * kDM * kKnnCap * 8, kAlign) + align_up(G * kDM * 4, kAlign) +
-           align_up(G * kDM * 8, kAlign);
+           align_up(G * kDM * 8, kAlign) + align_up((size_t)M * 8, kAlign);
+}
+
+template <bool FP8, bool TAIL, bool SEEDB>
+static hipError_t knn_pass(int M, int N, int K, int k, int nsplit, const uint8_t *q, const float *qs,
+                           const float *qn, const uint8_t *x, const float *xs, const float *xn,
+                           const uint64_t *seed, uint64_t *lists, uint32_t *cnt, uint64_t *bound,
+                           hipStream_t s)
+{
+    const int mt = (M + kDM - 1) / kDM, nt = (N + kDN - 1) / kDN;
+    hipLaunchKernelGGL((knn_kernel<FP8, TAIL, SEEDB>), dim3((unsigned)(mt * nsplit)), dim3(kDThreads), 0, s,
+                       M, N, K, k, mt, nsplit, nt, q, qs, qn, x, xs, xn, seed, lists, cnt, bound);
+    return hipGetLastError();
 }
 
 hipError_t launch_knn(bool fp8, int M, int N, int K, const void *Q, const float *qs,
                       const float *qn, const void *X, const float *xs, const float *xn, int k,
                       bool direct, int32_t *idx, float *d, void *ws, hipStream_t s)
 {
-    const int mt = (M + kDM - 1) / kDM, nsplit = knn_splits(M, N), nt = (N + kDN - 1) / kDN;
+    const int mt = (M + kDM - 1) / kDM, nsplit = knn_splits(M, N);
     const size_t G = (size_t)mt * nsplit;
     uint64_t *lists = static_cast<uint64_t *>(ws);
     char *p = static_cast<char *>(ws) + align_up(G * kDM * kKnnCap * 8, kAlign);
     uint32_t *cnt = reinterpret_cast<uint32_t *>(p);
-    uint64_t *bound = reinterpret_cast<uint64_t *>(p + align_up(G * kDM * 4, kAlign));
+    p += align_up(G * kDM * 4, kAlign);
+    uint64_t *bound = reinterpret_cast<uint64_t *>(p);
+    p += align_up(G * kDM * 8, kAlign);
+    uint64_t *seed = reinterpret_cast<uint64_t *>(p);
     const auto *q = static_cast<const uint8_t *>(Q);
     const auto *x = static_cast<const uint8_t *>(X);
-    if (fp8)
-        hipLaunchKernelGGL((knn_kernel<true, false>), dim3((unsigned)G), dim3(kDThreads), 0, s, M,
-                           N, K, k, mt, nsplit, nt, q, qs, qn, x, xs, xn, lists, cnt, bound);
-    else if ((2 * K) % kDSlice)
-        hipLaunchKernelGGL((knn_kernel<false, true>), dim3((unsigned)G), dim3(kDThreads), 0, s, M,
-                           N, K, k, mt, nsplit, nt, q, nullptr, qn, x, nullptr, xn, lists, cnt,
-                           bound);
-    else
-        hipLaunchKernelGGL((knn_kernel<false, false>), dim3((unsigned)G), dim3(kDThreads), 0, s, M,
-                           N, K, k, mt, nsplit, nt, q, nullptr, qn, x, nullptr, xn, lists, cnt,
-                           bound);
-    hipError_t e = hipGetLastError();
+    const bool tail = !fp8 && (2 * K) % kDSlice;
+    auto pass = [&](int n, int ns, const uint64_t *sd) {
+        if (!sd) {
+            if (fp8) return knn_pass<true, false, true>(M, n, K, k, ns, q, qs, qn, x, xs, xn, sd,
+                                                        lists, cnt, bound, s);
+            if (tail) return knn_pass<false, true, true>(M, n, K, k, ns, q, nullptr, qn, x,
+                                                         nullptr, xn, sd, lists, cnt, bound, s);
+            return knn_pass<false, false, true>(M, n, K, k, ns, q, nullptr, qn, x, nullptr, xn,
+                                                sd, lists, cnt, bound, s);
+        }
+        if (fp8) return knn_pass<true, false, false>(M, n, K, k, ns, q, qs, qn, x, xs, xn, sd,
+                                                     lists, cnt, bound, s);
+        if (tail) return knn_pass<false, true, false>(M, n, K, k, ns, q, nullptr, qn, x, nullptr,
+                                                      xn, sd, lists, cnt, bound, s);
+        return knn_pass<false, false, false>(M, n, K, k, ns, q, nullptr, qn, x, nullptr, xn, sd,
+                                             lists, cnt, bound, s);
+    };
+    hipError_t e = hipSuccess;
+    const uint64_t *sd = nullptr;
+    if (const int S = knn_sample_cols(N)) {
+        // The first S entries, one tile per split: the exact k-th smallest (distance, index)
+        // of each row over them bounds the row for the whole database.
+        const int ns1 = S / kDN;
+        e = pass(S, ns1, nullptr);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(knn_merge_kernel, dim3((unsigned)M), dim3(kMergeThreads), 0, s, k, mt,
+                           ns1, lists, cnt, bound, nullptr, nullptr, seed);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        sd = seed;
+    }
+    e = pass(N, nsplit, sd);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(knn_merge_kernel, dim3((unsigned)M), dim3(kMergeThreads), 0, s, k, mt,
-                       nsplit, lists, cnt, bound, idx, d);
+                       nsplit, lists, cnt, bound, idx, d, nullptr);
     e = hipGetLastError();
     if (e != hipSuccess || !direct) return e;
     const int64_t pairs = (int64_t)M * k;
