@@ -7,7 +7,9 @@ T1Gd masks and bit-packed (26.2 GB resident in HBM), one noisy patient-like
 query, exact top-10 by Dice_T1Gd + Dice_FLAIR. One step = one full query:
 pack the query, AND+popcount scan of every entry, Dice + score, top-10.
 The database build (threshold + pack of the float volumes) is done once
-before timing, as the paper's preprocessing is (Sec. 2.3).
+before timing, as the paper's preprocessing is (Sec. 2.3). The line also
+carries an "embed" object: the embedding half of the metric (queries/s at a
+stated recall@10 against the exact scan) measured in the same run.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -59,6 +61,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target duration of the CPU-oracle sample (0 disables it)")
     ap.add_argument("--build-chunk", type=int, default=2048)
+    ap.add_argument("--no-embed", action="store_true",
+                    help="full workload only: skip the embedding-search object of the line")
     ap.add_argument("--copy-calibration", type=float, default=0,
                     help="only run a device-to-device copy of this many bytes (3 times), as the "
                          "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE, and exit")
@@ -90,8 +94,9 @@ def source_sha(*rel: str) -> str:
 # Committed counter files per workload and the sources of the kernel they measured.
 TRAFFIC_FILES = {
     "full": ("scan_full_traffic.json", SCAN_SOURCES),
-    "embed500k": ("dist_fp8_500k_traffic.json", ("paper_2205_04550_amd/csrc/embed.hip",
-                                                  "paper_2205_04550_amd/csrc/common.hpp")),
+    "embed500k": ("knn_fp8_500k_traffic.json", ("paper_2205_04550_amd/csrc/knn.hip",
+                                                 "paper_2205_04550_amd/csrc/embed_core.hpp",
+                                                 "paper_2205_04550_amd/csrc/common.hpp")),
 }
 
 
@@ -110,24 +115,38 @@ def load_traffic(workload: str):
     return t.get("bytes_per_launch")
 
 
+def host_info(threads: int) -> dict:
+    """What the CPU baseline ran on: threads used, the process's cores, the CPU model."""
+    import oracle
+    return {"cores": threads, "host_cores": oracle.host_cores(), "cpu_count": os.cpu_count(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS"), "cpu_model": oracle.cpu_model()}
+
+
 def cpu_baseline(gen, q, t_lo, t_hi, target_s: float):
-    """The oracle's for-loop on a bounded sample of the same database (host cores)."""
-    import numpy as np
+    """The oracle's for-loop on a bounded sample of the same database: every thread the
+    oracle uses on this host, then one thread."""
     import oracle
     threads = oracle._threads()
     n_s = 256
     conc = gen.conc_cpu(0, n_s, threads)            # generation is not timed
     oracle.scan_block(conc[:8], q, t_lo, t_hi, threads=threads)  # warm
-    passes, elapsed = 0, 0.0
-    t0 = time.perf_counter()
-    while elapsed < target_s or passes == 0:
-        oracle.scan_block(conc, q, t_lo, t_hi, threads=threads)
-        passes += 1
-        elapsed = time.perf_counter() - t0
-    vox = passes * n_s * gen.nvox
-    return {"value": vox / elapsed, "unit": "voxels/s", "cores": threads, "kind": "oracle",
+
+    def rate(th, vols, budget):
+        passes, elapsed = 0, 0.0
+        t0 = time.perf_counter()
+        while elapsed < budget or passes == 0:
+            oracle.scan_block(vols, q, t_lo, t_hi, threads=th)
+            passes += 1
+            elapsed = time.perf_counter() - t0
+        return passes * len(vols) * gen.nvox / elapsed, passes, elapsed
+
+    v, passes, elapsed = rate(threads, conc, target_s)
+    v1, p1, e1 = rate(1, conc[:16], max(2.0, target_s / 4))
+    return {"value": v, "unit": "voxels/s", **host_info(threads), "kind": "oracle",
+            "value_1thread": v1,
             "sample": f"{n_s} of the {gen.nx}^3 database volumes (float32, host RAM), "
-                      f"{passes} passes of the plain for-loop, {elapsed:.1f} s"}
+                      f"{passes} passes of the plain for-loop, {elapsed:.1f} s; one thread: 16 "
+                      f"volumes, {p1} passes, {e1:.1f} s"}
 
 
 def cpu_baseline_batch(gen, labels, rois, t_lo, t_hi, target_s: float):
@@ -146,7 +165,7 @@ def cpu_baseline_batch(gen, labels, rois, t_lo, t_hi, target_s: float):
         pairs += 64 * int((r[3] - r[0]) * (r[4] - r[1]) * (r[5] - r[2]))
         q += 1
     el = time.perf_counter() - t0
-    return {"value": pairs / el, "unit": "voxels/s", "cores": threads, "kind": "oracle",
+    return {"value": pairs / el, "unit": "voxels/s", **host_info(threads), "kind": "oracle",
             "sample": f"64 of the {gen.nx}^3 database volumes (float32, host RAM) x {q} box-"
                       f"restricted queries, plain for-loop, {el:.1f} s"}
 
@@ -161,17 +180,17 @@ def roi_work(rois, n: int):
     return vox * n, 2 * words * n
 
 
-def executed_batch_ops(db, rois, n: int) -> float:
-    """Integer VALU ops of one batched launch over the rows it scans: per query and 4-entry
-    tile, the box rows clipped to the union of the tile members' row boxes, times the box's
-    words per row, 2 masks, 4 members and 3 ops (measurement bookkeeping)."""
+def executed_batch_ops(db, rois, n: int, tile: int = 4) -> float:
+    """Integer VALU ops of one batched launch over the rows it scans: per query and tile of
+    `tile` entries, the box rows clipped to the union of the tile members' row boxes, times
+    the box's words per row, 2 masks, the members and 3 ops (measurement bookkeeping)."""
     import torch
     order = db.tile_order[:n].to(torch.int64)
     b = db.boxes[:n].to(torch.int64)[order]
-    pad = (-n) % 4
+    pad = (-n) % tile
     if pad:
         b = torch.cat([b, b[-1:].expand(pad, 4)])
-    t = b.view(-1, 4, 4)
+    t = b.view(-1, tile, 4)
     empty = ~((t[..., 1] > t[..., 0]) & (t[..., 3] > t[..., 2]))
     big, small = 1 << 30, -(1 << 30)
     uz0 = torch.where(empty, big, t[..., 0]).amin(1)
@@ -184,7 +203,7 @@ def executed_batch_ops(db, rois, n: int) -> float:
         dy = (torch.clamp(uy1, max=y1) - torch.clamp(uy0, min=y0)).clamp(min=0)
         nw = ((x1 - 1) >> 5) - (x0 >> 5) + 1
         total += int((dz * dy).sum()) * nw
-    return float(total) * 2 * 4 * 3
+    return float(total) * 2 * tile * 3
 
 
 def bench_batch(args, db, gen, n, build_s) -> int:
@@ -216,9 +235,11 @@ def bench_batch(args, db, gen, n, build_s) -> int:
     log(f"returned entries of queries 0 and {nq - 1} re-checked by the oracle: "
         f"{'ok' if ok else 'MISMATCH'}")
     from paper_2205_04550_amd import autotune
-    log("autotuning the launch shape (z-planes per LDS slab x block size)")
+    log("autotuning the launch shape (z-planes per LDS slab x block size x entries per tile x "
+        "queries per chunk)")
     best, table = autotune.tune_batch(db, lab_d, rois, k, reps=3, log=log)
-    log(f"picked {best[0] or 'max'} planes x {best[1]} threads ({best[2]:.2f} ms)")
+    log(f"picked {best[0] or 'max'} planes x {best[1]} threads, tile {best[2] or 4}, chunk "
+        f"{best[3] or 256} ({best[4]:.2f} ms)")
     for _ in range(args.warmup):
         db.query_batch(lab_d, rois, k, out=out, ws=ws)
     torch.cuda.synchronize()
@@ -235,7 +256,7 @@ def bench_batch(args, db, gen, n, build_s) -> int:
     pairs_vox, words = roi_work(rois, n)
     g_avg = g_ms / max(1, launches)
     dense_ops = 3 * words   # per packed word and mask: AND, popcount-add (I), popcount-add (B)
-    ops = executed_batch_ops(db, rois, n)
+    ops = executed_batch_ops(db, rois, n, best[2] or 4)
     achieved = ops / (g_avg * 1e-3)
     cpu = None
     if args.cpu_seconds > 0:
@@ -256,14 +277,18 @@ def bench_batch(args, db, gen, n, build_s) -> int:
         "queries_per_s": nq / (ms * 1e-3),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                      "unit": "Tops/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
-                     "kernel": "batch_lds_kernel (graph)", "kernel_avg_ms": g_avg,
+                     "kernel": "batch_lds_kernel (persistent, from a HIP graph)",
+                     "kernel_avg_ms": g_avg,
                      "algorithmic_ops_per_launch": ops,
                      "dense_box_ops_per_launch": dense_ops,
                      "note": "ops over the rows of each box clipped to the union of the tile's "
                              "row boxes, the rows the kernel scans; the dense count treats every "
                              "box row of every entry as work",
                      "hbm_floor_gb_per_launch": n * 2 * gen.nvox / 8 / 1e9},
-        "autotune": {"picked": {"slab_planes": best[0], "block_threads": best[1]},
+        "autotune": {"picked": {"slab_planes": best[0], "block_threads": best[1],
+                                "tile_entries": best[2], "query_chunk": best[3]},
+                     "table_columns": ["slab_planes", "block_threads", "tile_entries",
+                                       "query_chunk", "median_ms"],
                      "table_ms": [list(t) for t in table]},
         "cpu_baseline": cpu,
         "parity": {"returned_entries_rechecked_by_oracle": ok},
@@ -273,7 +298,10 @@ def bench_batch(args, db, gen, n, build_s) -> int:
     return 0 if ok else 1
 
 
-FP32_VECTOR_PEAK = 157.3e12      # MI355X vector FP32 (packed) FLOP/s
+# MI355X vector FP32 without packed instructions (which are not used: 157.3 TFLOP/s is the
+# packed-FP32 figure): 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA) x 2.4 GHz.
+FP32_VECTOR_PEAK = 78.6e12
+FP32_MFMA_PEAK = 157.3e12        # MI355X dense FP32 matrix FLOP/s
 BF16_MFMA_PEAK = 2.5e15          # MI355X dense BF16 matrix FLOP/s
 FP8_MFMA_PEAK = 5.0e15           # MI355X dense FP8 matrix FLOP/s
 
@@ -336,7 +364,9 @@ def bench_train(args, db, gen, n, build_s) -> int:
         "roofline": {"bound": "alu", "achieved": flop / (ms * 1e-3) / 1e12,
                      "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
                      "frac": flop / (ms * 1e-3) / FP32_VECTOR_PEAK, "traffic": None,
-                     "kernel": "whole step (direct convolutions on the vector ALUs)",
+                     "kernel": "whole step (forward convolutions and linear layers on the FP32 "
+                               "matrix cores, backward kernels on the vector ALUs)",
+                     "note": "peak = the vector FP32 rate without packed instructions",
                      "algorithmic_flop_per_step": flop},
         "loss_first_last": [losses[0], losses[-1]],
         "cpu_baseline": None, "build_s": build_s,
@@ -369,7 +399,7 @@ def cpu_baseline_embed(model, X, labels, gen, n, n_cand, k, target_s: float):
         oracle.rank(sc, k)
         done += 1
     el = time.perf_counter() - t0
-    return {"value": done / el, "unit": "queries/s", "cores": threads, "kind": "oracle",
+    return {"value": done / el, "unit": "queries/s", **host_info(threads), "kind": "oracle",
             "sample": f"{done} of the held-out queries, one at a time (encoder, float64 "
                       f"distances to {n} latents, top-{n_cand}, for-loop Dice), {el:.1f} s"}
 
@@ -411,8 +441,17 @@ def rerank_bytes(db, lab_d, cand, gen, lines: bool = False) -> float:
     return float((dz * dy).sum()) * 2 * nxw * 4
 
 
-def bench_embed(args, db, gen, n, build_s) -> int:
-    """Held-out queries through encoder, BF16 MFMA distances, top-100 and exact rerank."""
+def encoder_forward_flop(model, nq: int) -> float:
+    """FLOP of the encoder's forward pass (convolutions and linear layer) for nq samples."""
+    g, c = model.grid, model.channels
+    macs = sum((g >> (i + 1)) ** 3 * c[i + 1] * c[i] * 27 for i in range(4))
+    macs += model.flat * model.latent
+    return 2.0 * macs * nq
+
+
+def embed_run(args, db, gen, n, with_variants: bool) -> dict:
+    """Held-out queries through the encoder, the fused latent search (distances + top-100 in
+    one pass) and the exact rerank. Returns the measurements as a dict."""
     import numpy as np
     import torch
 
@@ -454,13 +493,16 @@ def bench_embed(args, db, gen, n, build_s) -> int:
     exact_ms_per_query = (time.perf_counter() - t0) * 1e3 / nq
     log(f"exact scan: {exact_ms_per_query:.3f} ms per query")
 
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
-    stage = np.zeros(4)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    stage = np.zeros(3)
 
     # The rerank's packing of the query labels (HBM-bound) runs on a second stream
     # (default priority) beside the encoder's later layers (latency-bound), after the
     # first layer, which reads the same labels; the scoring waits for it with an event.
     ws_rr = db.rerank_workspace(nq)
+    kws = B.knn_workspace(nq, n, n_cand)
+    kout = (torch.empty((nq, n_cand), dtype=torch.int32, device="cuda"),
+            torch.empty((nq, n_cand), dtype=torch.float32, device="cuda"))
     side = torch.cuda.Stream()
 
     def step(timed: bool):
@@ -476,20 +518,15 @@ def bench_embed(args, db, gen, n, build_s) -> int:
         Q = B.Latents(ql, B.EMB_BF16)
         if timed:
             ev[1].record()
-        D = B.emb_distances_groups(Q, X, gws, out=Dbuf)
+        ci, cd = B.emb_knn(Q, X, n_cand, direct=True, ws=kws, out=kout)
         if timed:
             ev[2].record()
-        ci, cd = B.emb_topk_groups(D, n_cand, gws)
-        if timed:
-            ev[3].record()
         torch.cuda.current_stream().wait_event(packed)
         out = db.rerank_packed(ws_rr, ci, k)
         if timed:
-            ev[4].record()
+            ev[3].record()
         return out, ci
 
-    Dbuf = torch.empty((nq, n), dtype=torch.float32, device="cuda")
-    gws = B.groups_workspace(nq, n)
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -499,7 +536,7 @@ def bench_embed(args, db, gen, n, build_s) -> int:
     for _ in range(args.steps):
         (idx, score, counts), ci = step(True)
         torch.cuda.synchronize()
-        stage += [ev[i].elapsed_time(ev[i + 1]) for i in range(4)]
+        stage += [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
     t1 = time.perf_counter()
     rr_ms, rr_launches = db.profile_read()
     db.profile(False)
@@ -513,9 +550,71 @@ def bench_embed(args, db, gen, n, build_s) -> int:
     top_n = {f"top{t}": float(np.mean([ex[q, 0] in got[q, :t] for q in range(nq)])) for t in (1, 5, 15)}
     cand_recall = float(np.mean([len(set(ci[q].cpu().numpy()) & set(ex[q, :10])) / 10
                                  for q in range(min(nq, 256))]))
-    # Other codes of the same search: FP8 latents of this encoder, and the hashing
-    # variant (an encoder trained with the Bi-half layer, Hamming search on its codes).
-    ex = ex_idx.cpu().numpy()
+    cpu = None
+    if args.cpu_seconds > 0:
+        log("timing the CPU oracle on a sample of the queries")
+        cpu = cpu_baseline_embed(model, X, lab_host_sample, gen, n, n_cand, k, args.cpu_seconds)
+        log(f"cpu oracle {cpu['value']:.3f} queries/s on {cpu['cores']} threads")
+    gemm_flop = 2.0 * nq * n * model.latent
+    enc_flop = encoder_forward_flop(model, nq)
+    names = ["encode + pack queries (two streams)",
+             "latent distances + top-100 in one pass (BF16 MFMA), direct-form candidate distances",
+             "exact rerank"]
+    dom = int(np.argmax(stage))
+    log(f"{ms:.2f} ms per {nq} queries ({nq / (ms * 1e-3):.0f} q/s); stages "
+        + ", ".join(f"{a} {b:.3f} ms" for a, b in zip(names, stage))
+        + f"; recall@10 {recall10:.3f}; {top_n}; speed-up vs exact "
+          f"{exact_ms_per_query * nq / ms:.0f}x")
+    out = {
+        "metric": "queries/sec at recall@10", "value": nq / (ms * 1e-3), "unit": "queries/s",
+        "ms_per_step": ms, "steps": args.steps, "warmup": args.warmup, "dtype": "bf16",
+        "config": {"workload": f"embedding search, {nq} held-out queries x {n} latents (512-d "
+                               f"BF16), top-{n_cand} by MFMA distance, exact 128^3 Dice rerank, "
+                               f"top-{k}", "n_db": n, "nq": nq, "n_cand": n_cand,
+                   "train_steps": args.train_steps},
+        "recall_at_10": recall10, **top_n, "candidate_recall_at_10": cand_recall,
+        "speedup_vs_exact_scan": exact_ms_per_query * nq / ms,
+        "exact_ms_per_query": exact_ms_per_query,
+        "stages_ms": dict(zip(names, stage.tolist())),
+        "dominant_stage": names[dom],
+        "roofline": {"bound": "hbm", "achieved": rr_bytes / (rr_avg * 1e-3) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": rr_bytes / (rr_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "rerank_score_kernel", "kernel_avg_ms": rr_avg,
+                     "algorithmic_bytes_per_launch": rr_bytes,
+                     "note": "the longest single launch of the step; bytes = database rows inside "
+                             "(query row box n candidate row box), both masks"},
+        "encode_stage_roofline": {
+            "bound": "mfma", "achieved": enc_flop / (stage[0] * 1e-3) / 1e12,
+            "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+            "frac": enc_flop / (stage[0] * 1e-3) / FP32_MFMA_PEAK,
+            "algorithmic_flop": enc_flop, "stage_ms": stage[0],
+            "note": "the encoder's forward FLOP over the whole stage (five kernels, with the query "
+                    "packing on a second stream beside them) against the FP32 matrix peak; the "
+                    "first layer runs on the BF16 matrix cores"},
+        "latent_search": {"bound": "mfma", "achieved_tflops": gemm_flop / (stage[1] * 1e-3) / 1e12,
+                          "peak_tflops": BF16_MFMA_PEAK / 1e12,
+                          "frac": gemm_flop / (stage[1] * 1e-3) / BF16_MFMA_PEAK,
+                          "kernels": "knn_kernel<false, false> + knn_merge_kernel + "
+                                     "knn_direct_kernel<false>", "ms": stage[1],
+                          "note": "no distance matrix is written"},
+        "cpu_baseline": cpu, "train_s": train_s,
+        "encode_db_s": encode_db_s, "train_loss_first_last": [losses[0], losses[-1]],
+    }
+    if with_variants:
+        out["variants"] = embed_variants(args, db, gen, n, model, lat, lab_d, ex, Dbuf_shape=(nq, n))
+    return out
+
+
+def embed_variants(args, db, gen, n, model, lat, lab_d, ex, Dbuf_shape) -> dict:
+    """Other codes of the same search: FP8 latents of the encoder, the hashing variant, and
+    the paper's two single-mask encoders (plain and variational) with summed L2."""
+    import numpy as np
+    import torch
+
+    from paper_2205_04550_amd import binding as B, nn
+    nq, n_cand, k = args.embed_nq, 100, 15
+    Dbuf = torch.empty(Dbuf_shape, dtype=torch.float32, device="cuda")
 
     def leg(name, fmt, encode_q, Xl):
         for _ in range(max(1, args.warmup)):
@@ -614,51 +713,18 @@ def bench_embed(args, db, gen, n, build_s) -> int:
         variants[tag] = r
         del Xs, pair
 
-    cpu = None
-    if args.cpu_seconds > 0:
-        log("timing the CPU oracle on a sample of the queries")
-        cpu = cpu_baseline_embed(model, X, lab_host_sample, gen, n, n_cand, k, args.cpu_seconds)
-        log(f"cpu oracle {cpu['value']:.3f} queries/s on {cpu['cores']} threads")
-    gemm_flop = 2.0 * nq * n * model.latent
-    names = ["encode + pack queries (two streams)",
-             "distance GEMM (BF16 MFMA) + 16-entry group minima", "top-100 from the group bound",
-             "exact rerank"]
-    dom = int(np.argmax(stage))
-    log(f"{ms:.2f} ms per {nq} queries ({nq / (ms * 1e-3):.0f} q/s); stages "
-        + ", ".join(f"{a} {b:.3f} ms" for a, b in zip(names, stage))
-        + f"; recall@10 {recall10:.3f}; {top_n}; speed-up vs exact "
-          f"{exact_ms_per_query * nq / ms:.0f}x")
-    line = {
-        "metric": "queries/sec at recall@10", "value": nq / (ms * 1e-3), "unit": "queries/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
-        "data": "synthetic",
-        "config": {"workload": f"embedding search, {nq} held-out queries x {n} latents (512-d "
-                               f"BF16), top-{n_cand} by MFMA distance, exact 128^3 Dice rerank, "
-                               f"top-{k}", "n_db": n, "nq": nq, "n_cand": n_cand,
-                   "train_steps": args.train_steps},
-        "recall_at_10": recall10, **top_n, "candidate_recall_at_10": cand_recall,
-        "speedup_vs_exact_scan": exact_ms_per_query * nq / ms,
-        "exact_ms_per_query": exact_ms_per_query,
-        "stages_ms": dict(zip(names, stage.tolist())),
-        "roofline": {"bound": "hbm", "achieved": rr_bytes / (rr_avg * 1e-3) / 1e9,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": rr_bytes / (rr_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "rerank_score_kernel", "kernel_avg_ms": rr_avg,
-                     "algorithmic_bytes_per_launch": rr_bytes,
-                     "note": "the longest single launch of the step; bytes = database rows inside "
-                             "(query row box n candidate row box), both masks",
-                     "dominant_stage": names[dom]},
-        "distance_gemm": {"bound": "mfma", "achieved_tflops": gemm_flop / (stage[1] * 1e-3) / 1e12,
-                          "peak_tflops": BF16_MFMA_PEAK / 1e12,
-                          "frac": gemm_flop / (stage[1] * 1e-3) / BF16_MFMA_PEAK,
-                          "kernel": "dist_lds_kernel<false, false, 1, true>", "ms": stage[1],
-                          "note": "also writes each row's 16-entry group minima (1/16 of the "
-                                  "distances) for the top-k bound"},
-        "variants": variants,
-        "cpu_baseline": cpu, "build_s": build_s, "train_s": train_s,
-        "encode_db_s": encode_db_s, "train_loss_first_last": [losses[0], losses[-1]],
-    }
+    return variants
+
+
+def bench_embed(args, db, gen, n, build_s) -> int:
+    """Held-out queries through encoder, fused BF16 MFMA latent search and exact rerank, and
+    the other codes of the same search."""
+    r = embed_run(args, db, gen, n, with_variants=True)
+    line = {"metric": r.pop("metric"), "value": r.pop("value"), "unit": r.pop("unit"),
+            "n_gpus": 1, "steps": r.pop("steps"), "warmup": r.pop("warmup"),
+            "ms_per_step": r.pop("ms_per_step"), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": r.pop("dtype"), "data": "synthetic",
+            "config": r.pop("config"), **r, "build_s": build_s}
     print(json.dumps(line), flush=True)
     return 0
 
@@ -710,12 +776,42 @@ def bench_embed500k(args, db, gen, n, build_s, n_big: int = 500_000) -> int:
     with torch.no_grad():
         ql = model.encode_labels(lab_d)
     Q8, Q16 = B.Latents(ql, B.EMB_FP8), B.Latents(ql, B.EMB_BF16)
-    D = torch.empty((nq, n_big), dtype=torch.float32, device="cuda")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    kws = B.knn_workspace(nq, n_big, n_cand)
 
+    def run_fused(Q, X):
+        ev[0].record()
+        ci, _ = B.emb_knn(Q, X, n_cand, direct=True, ws=kws)
+        ev[1].record()
+        return ci
+
+    def timed(fn, Q, X, two_stage=False):
+        for _ in range(max(1, args.warmup)):
+            fn(Q, X)
+        torch.cuda.synchronize()
+        a_ms = b_ms = 0.0
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ci = fn(Q, X)
+            torch.cuda.synchronize()
+            a_ms += ev[0].elapsed_time(ev[1])
+            if two_stage:
+                b_ms += ev[1].elapsed_time(ev[2])
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        return ms, a_ms / args.steps, b_ms / args.steps, ci
+
+    res = {}
+    for name, Q, X in (("bf16", Q16, X16), ("fp8", Q8, X8)):
+        ms, k_ms, _, ci = timed(run_fused, Q, X)
+        res[name] = {"ms_per_batch": ms, "emb_knn_ms": k_ms, "cand": ci.cpu().numpy()}
+        log(f"{name}: {ms:.3f} ms per {nq} queries (fused distances + top-{n_cand}: "
+            f"{k_ms:.3f} ms)")
+    # The earlier two-pass path for comparison: the [M][N] distance matrix with group
+    # minima, then the top-100 bounded by those minima.
+    D = torch.empty((nq, n_big), dtype=torch.float32, device="cuda")
     gws = B.groups_workspace(nq, n_big)
 
-    def run(Q, X):
+    def run_matrix(Q, X):
         ev[0].record()
         B.emb_distances_groups(Q, X, gws, out=D)
         ev[1].record()
@@ -723,29 +819,24 @@ def bench_embed500k(args, db, gen, n, build_s, n_big: int = 500_000) -> int:
         ev[2].record()
         return ci
 
-    res = {}
-    for name, Q, X in (("bf16", Q16, X16), ("fp8", Q8, X8)):
-        for _ in range(max(1, args.warmup)):
-            run(Q, X)
-        torch.cuda.synchronize()
-        g_ms = s_ms = 0.0
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            ci = run(Q, X)
-            torch.cuda.synchronize()
-            g_ms += ev[0].elapsed_time(ev[1])
-            s_ms += ev[1].elapsed_time(ev[2])
-        ms = (time.perf_counter() - t0) * 1e3 / args.steps
-        res[name] = {"ms_per_batch": ms, "gemm_ms": g_ms / args.steps, "select_ms": s_ms / args.steps,
-                     "cand": ci.cpu().numpy()}
-        log(f"{name}: {ms:.2f} ms per {nq} queries (GEMM {g_ms / args.steps:.3f} ms, top-{n_cand} "
-            f"{s_ms / args.steps:.3f} ms)")
+    ms_m, g_m, s_m, ci_m = timed(run_matrix, Q8, X8, two_stage=True)
+    same = bool(np.array_equal(ci_m.cpu().numpy(), res["fp8"]["cand"]))
+    log(f"fp8 with the distance matrix: {ms_m:.3f} ms (distances {g_m:.3f}, top-{n_cand} "
+        f"{s_m:.3f}); same candidates as the fused path: {same}")
+    del D, gws
+    res["fp8_distance_matrix_path"] = {"ms_per_batch": ms_m, "distances_ms": g_m,
+                                       "select_ms": s_m, "same_candidates": same}
     c8, c16 = res["fp8"].pop("cand"), res["bf16"].pop("cand")
     recall10 = float(np.mean([len(set(c8[q, :10]) & set(c16[q, :10])) / 10 for q in range(nq)]))
     cover = float(np.mean([len(set(c8[q]) & set(c16[q, :10])) / 10 for q in range(nq)]))
     flop = 2.0 * nq * n_big * 512
-    g8 = res["fp8"]["gemm_ms"]
+    k8 = res["fp8"]["emb_knn_ms"]
     log(f"FP8 recall@10 vs BF16 {recall10:.3f}; BF16 top-10 inside FP8 top-{n_cand}: {cover:.3f}")
+    cpu = None
+    if args.cpu_seconds > 0:
+        log("timing the CPU oracle: float64 direct distances to every FP8 latent, top-100")
+        cpu = cpu_baseline_latents(Q8, X8, n_cand, args.cpu_seconds)
+        log(f"cpu oracle {cpu['value']:.3f} queries/s on {cpu['cores']} threads")
     line = {
         "metric": "queries/sec at recall@10", "value": nq / (res["fp8"]["ms_per_batch"] * 1e-3),
         "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -756,17 +847,48 @@ def bench_embed500k(args, db, gen, n, build_s, n_big: int = 500_000) -> int:
                    "n_db": n_big, "nq": nq, "n_cand": n_cand},
         "recall_at_10_vs_bf16": recall10, "bf16_top10_within_fp8_top100": cover,
         "paths": res, "generate_and_encode_s": gen_s,
-        "roofline": {"bound": "mfma", "achieved": flop / (g8 * 1e-3) / 1e12,
-                     "peak": FP8_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
-                     "frac": flop / (g8 * 1e-3) / FP8_MFMA_PEAK,
+        "roofline": {"bound": "mfma", "achieved": flop / (k8 * 1e-3) / 1e12,
+                     "peak": BF16_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": flop / (k8 * 1e-3) / BF16_MFMA_PEAK,
                      "traffic": load_traffic("embed500k"),
-                     "kernel": "dist_lds_kernel<true, false, 3, true>", "kernel_avg_ms": g8,
-                     "note": "writes 2.05 GB of distances and 128 MB of 16-entry group minima "
-                             "per launch"},
-        "cpu_baseline": None, "build_s": build_s,
+                     "kernel": "emb_knn: knn_kernel<true, false> + knn_merge_kernel + "
+                               "knn_direct_kernel<true>", "kernel_avg_ms": k8,
+                     "algorithmic_flop_per_launch": flop,
+                     "note": "e4m3 codes decoded exactly to BF16 in LDS and multiplied on the BF16 "
+                             "matrix cores (peak 2.5 PFLOP/s); no distance matrix is written; "
+                             "time of the whole call (three kernels)"},
+        "cpu_baseline": cpu, "build_s": build_s,
     }
     print(json.dumps(line), flush=True)
     return 0
+
+
+def cpu_baseline_latents(Q, X, n_cand: int, target_s: float):
+    """The oracle's latent search on host cores, one query at a time: float64 direct-form
+    distances to every stored (dequantised) database latent, then the n_cand smallest."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from oracle import encoder as E
+    from paper_2205_04550_amd import binding as B
+
+    def deq(L):
+        if L.fmt == B.EMB_BF16:
+            return E.bf16_decode(L.codes.view(torch.int16).cpu().numpy())
+        return E.e4m3_decode(L.codes.cpu().numpy()) * L.scale.cpu().numpy().astype(np.float64)[:, None]
+    x, q = deq(X), deq(Q)
+    threads = 1                      # numpy's einsum and sort run on one thread
+    t0 = time.perf_counter()
+    done = 0
+    while time.perf_counter() - t0 < target_s or done == 0:
+        d = E.sqdist_direct(q[done % len(q)][None], x)
+        E.topk_by_distance(d, n_cand)
+        done += 1
+    el = time.perf_counter() - t0
+    return {"value": done / el, "unit": "queries/s", **host_info(threads), "kind": "oracle",
+            "sample": f"{done} queries, float64 direct distances to {x.shape[0]} latents and a "
+                      f"stable sort, {el:.1f} s (numpy, one thread)"}
 
 
 def bench_ds(args, db, gen, n, build_s) -> int:
@@ -1086,6 +1208,11 @@ def main() -> int:
         cpu = cpu_baseline(gen, q, t_lo, t_hi, args.cpu_seconds)
         log(f"cpu oracle {cpu['value']:.3e} voxels/s on {cpu['cores']} threads")
 
+    embed = None
+    if args.workload == "full" and not args.no_embed:
+        log("embedding search: held-out queries, fused latent search, exact rerank")
+        embed = embed_run(args, db, gen, n, with_variants=False)
+
     line = {
         "metric": "database voxels compared/sec",
         "value": vox_per_s,
@@ -1110,6 +1237,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "parity": {"top_k_rechecked_by_oracle": ok},
         "build_s": build_s,
+        "embed": embed,
     }
     print(json.dumps(line), flush=True)
     return 0 if ok else 1

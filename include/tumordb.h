@@ -146,7 +146,9 @@ int db_query_sparse(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx
 
 /* nq queries in one launch sequence, each optionally restricted to its own
  * box: both masks are cut to the box before Dice (an extension; the paper
- * compares whole volumes). q_labels: device uint8 [nq][nz][ny][nx];
+ * compares whole volumes). The scan is one persistent kernel: resident blocks
+ * take (tile of database entries, chunk of queries) items, costliest tiles
+ * first, from a counter until none is left. q_labels: device uint8 [nq][nz][ny][nx];
  * rois: HOST array [nq] (validated before enqueue: inside the grid, non-empty)
  * or NULL for whole grids; outputs idx [nq][k], score [nq][k], counts
  * [nq][k] or NULL (device). The kernel sequence is recorded once into a HIP
@@ -157,11 +159,15 @@ int db_query_batch(const db_t *db, int nq, const uint8_t *q_labels, const db_roi
                    int32_t *idx, double *score, db_counts_t *counts, void *ws, size_t ws_bytes,
                    void *stream);
 
-/* Launch shape of db_query_batch: z-planes per LDS slab (0 = as many as fit)
- * and block size (0 = 1024; else 256, 512 or 1024). Results do not depend on
- * it; the autotuner (paper_2205_04550_amd/autotune.py) picks it by timing. A
- * change takes effect at the next recording of the batch graph. */
-int db_tune_batch(db_t *db, int slab_planes, int block_threads);
+/* Launch shape of db_query_batch: z-planes per LDS slab (0 = as many as fit;
+ * -1 = no LDS slabs: the kernel that reads the database through L2), block
+ * size (0 = 1024; else 256, 512 or 1024), database entries per tile (0 = 4;
+ * 4 or 8) and queries per chunk (0 = 256; 1 .. 1024; the queries of a chunk
+ * keep their counters in one block's LDS). Results do not depend on it; the
+ * autotuner (paper_2205_04550_amd/autotune.py) picks it by timing. A change
+ * takes effect at the next recording of the batch graph. */
+int db_tune_batch(db_t *db, int slab_planes, int block_threads, int tile_entries,
+                  int query_chunk);
 
 /* ---------------------------------------------------- embedding search --- */
 /* Latent search (Sec. 2.3, "Autoencoders": encoded database and query are

@@ -64,7 +64,7 @@ def _load():
         "db_free": (None, [vp]),
         "db_last_error": (ctypes.c_char_p, []),
         "db_profile": (i32, [vp, i32]),
-        "db_tune_batch": (i32, [vp, i32, i32]),
+        "db_tune_batch": (i32, [vp, i32, i32, i32, i32]),
         "db_append_resampled": (i32, [vp, vp, i64, i64, vp]),
         "labels_resample": (i32, [i32, vp, i32, i32, i32, vp, i32, i32, i32, vp]),
         "emb_quantize": (i32, [i64, i32, vp, i32, vp, vp, vp, vp]),
@@ -375,9 +375,11 @@ class TumorDB:
         n = len(src) - first if n is None else n
         _check(LIB.db_append_resampled(self._h, src._h, first, n, _stream(stream)))
 
-    def tune_batch(self, slab_planes: int = 0, block_threads: int = 0) -> None:
-        """Launch shape of query_batch (0 = defaults); results are the same for any shape."""
-        _check(LIB.db_tune_batch(self._h, slab_planes, block_threads))
+    def tune_batch(self, slab_planes: int = 0, block_threads: int = 0, tile_entries: int = 0,
+                   query_chunk: int = 0) -> None:
+        """Launch shape of query_batch (0 = defaults; slab_planes = -1 selects the kernel that
+        reads the database through L2); results are the same for any shape."""
+        _check(LIB.db_tune_batch(self._h, slab_planes, block_threads, tile_entries, query_chunk))
 
     def profile(self, enable: bool) -> None:
         """Record HIP events around the dominant kernel of every later query call."""

@@ -98,7 +98,7 @@ WsLayout ws_layout(const db_t *db, int nq, int k, bool batched)
 
 // Host state of a cached batched-query graph.
 struct BatchGraph {
-    int nq = 0, k = 0, Z = 0, threads = 0;
+    int nq = 0, k = 0, Z = 0, threads = 0, tile = 0, qchunk = 0;
     int64_t n = 0;
     const void *labels = nullptr, *ws = nullptr, *idx = nullptr, *score = nullptr,
                *counts = nullptr;
@@ -268,9 +268,12 @@ static hipError_t dist_launch(int fmt, int M, int N, int dim, const void *q_code
 }
 
 // Sort the entries by the centre of their row boxes (z in bands of 8 planes,
-// then y), so that the batched kernel's 4-entry tiles hold overlapping boxes.
-// Reads the boxes back after a device synchronisation; host sort; one upload.
-static int build_tile_order(db_t *db)
+// then y), so that the batched kernel's tiles (groups of `tile` consecutive
+// entries) hold overlapping boxes; then order the tiles by the size of the union
+// of their members' row boxes, largest first (the persistent kernel takes tiles
+// in this order, so the longest items start first). Reads the boxes back after a
+// device synchronisation; host sort; one upload.
+static int build_tile_order(db_t *db, int tile)
 {
     const int64_t n = db->count;
     std::vector<int32_t> box((size_t)n * 4);
@@ -279,17 +282,46 @@ static int build_tile_order(db_t *db)
     if (e != hipSuccess) return hip_fail(e, "db_query_batch: read row boxes");
     std::vector<int32_t> order(n);
     std::iota(order.begin(), order.end(), 0);
+    auto empty = [&](int32_t i) {
+        const int32_t *b = &box[(size_t)i * 4];
+        return !(b[1] > b[0] && b[3] > b[2]);
+    };
     auto key = [&](int32_t i) {
         const int32_t *b = &box[(size_t)i * 4];
-        const bool empty = !(b[1] > b[0] && b[3] > b[2]);
         const int64_t zc = b[0] + b[1], yc = b[2] + b[3];
-        return empty ? INT64_MAX : ((zc / 16) << 32) | (yc << 16) | (b[1] - b[0]);
+        return empty(i) ? INT64_MAX : ((zc / 16) << 32) | (yc << 16) | (b[1] - b[0]);
     };
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t b) { return key(a) < key(b); });
-    e = hipMemcpy(db->tile_order, order.data(), (size_t)n * 4, hipMemcpyHostToDevice);
+    const int64_t ntiles = (n + tile - 1) / tile;
+    std::vector<int64_t> tcost(ntiles, 0);
+    for (int64_t t = 0; t < ntiles; ++t) {
+        int z0 = INT32_MAX, z1 = INT32_MIN, y0 = INT32_MAX, y1 = INT32_MIN;
+        for (int64_t j = t * tile; j < std::min<int64_t>(n, (t + 1) * tile); ++j) {
+            if (empty(order[j])) continue;
+            const int32_t *b = &box[(size_t)order[j] * 4];
+            z0 = std::min(z0, b[0]);
+            z1 = std::max(z1, b[1]);
+            y0 = std::min(y0, b[2]);
+            y1 = std::max(y1, b[3]);
+        }
+        tcost[t] = z1 > z0 ? (int64_t)(z1 - z0) * (y1 - y0) : 0;
+    }
+    // The last (partial) tile keeps its place: tiles are read as groups of `tile` entries.
+    std::vector<int64_t> tperm(ntiles);
+    std::iota(tperm.begin(), tperm.end(), 0);
+    const int64_t nfull = n / tile;
+    std::stable_sort(tperm.begin(), tperm.begin() + nfull,
+                     [&](int64_t a, int64_t b) { return tcost[a] > tcost[b]; });
+    std::vector<int32_t> sorted;
+    sorted.reserve(n);
+    for (int64_t t : tperm)
+        for (int64_t j = t * tile; j < std::min<int64_t>(n, (t + 1) * tile); ++j)
+            sorted.push_back(order[j]);
+    e = hipMemcpy(db->tile_order, sorted.data(), (size_t)n * 4, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "db_query_batch: upload tile order");
     db->tile_order_n = n;
+    db->tile_order_tile = tile;
     return DB_OK;
 }
 
@@ -357,6 +389,9 @@ int db_build(db_t **out, int nx, int ny, int nz, float t_lo, float t_hi, int64_t
     db->lds_max = lds;
     db->batch_planes = 0;
     db->batch_threads = 0;
+    db->batch_tile = 0;
+    db->batch_qchunk = 0;
+    db->tile_order_tile = 0;
     db->graph = nullptr;
     db->prof = nullptr;
     *out = db;
@@ -594,8 +629,8 @@ int db_query_batch(const db_t *db_c, int nq, const uint8_t *q_labels, const db_r
     }
 
     // Entries grouped by row-box centre for the LDS kernel's tiles (rebuilt after appends).
-    if (P.use_lds && db->tile_order_n != db->count) {
-        rc = build_tile_order(db);
+    if (P.use_lds && (db->tile_order_n != db->count || db->tile_order_tile != P.tile)) {
+        rc = build_tile_order(db, P.tile);
         if (rc) return rc;
     }
     if (!db->graph) {
@@ -633,7 +668,7 @@ int db_query_batch(const db_t *db_c, int nq, const uint8_t *q_labels, const db_r
 
     // (Re)record the graph when the shape or any pointer changed.
     const bool same = G.exec && G.nq == nq && G.k == k && G.n == db->count && G.Z == P.Z &&
-                      G.threads == P.threads &&
+                      G.threads == P.threads && G.tile == P.tile && G.qchunk == P.qchunk &&
                       G.labels == q_labels && G.ws == ws && G.idx == idx && G.score == score &&
                       G.counts == counts;
     if (!same) {
@@ -659,6 +694,8 @@ int db_query_batch(const db_t *db_c, int nq, const uint8_t *q_labels, const db_r
         G.n = db->count;
         G.Z = P.Z;
         G.threads = P.threads;
+        G.tile = P.tile;
+        G.qchunk = P.qchunk;
         G.labels = q_labels;
         G.ws = ws;
         G.idx = idx;
@@ -1203,17 +1240,24 @@ int db_sync(const db_t *db, void *stream)
     return DB_OK;
 }
 
-int db_tune_batch(db_t *db, int slab_planes, int block_threads)
+int db_tune_batch(db_t *db, int slab_planes, int block_threads, int tile_entries,
+                  int query_chunk)
 {
     if (!live(db)) return fail(DB_ESTATE, "db_tune_batch: invalid handle");
-    if (slab_planes < 0 || slab_planes > db->g.nz)
-        return fail(DB_EINVAL, "db_tune_batch: slab_planes %d outside [0, %d]", slab_planes,
+    if (slab_planes < -1 || slab_planes > db->g.nz)
+        return fail(DB_EINVAL, "db_tune_batch: slab_planes %d outside [-1, %d]", slab_planes,
                     db->g.nz);
     if (block_threads != 0 && block_threads != 256 && block_threads != 512 &&
         block_threads != 1024)
         return fail(DB_EINVAL, "db_tune_batch: block_threads must be 0, 256, 512 or 1024");
+    if (tile_entries != 0 && tile_entries != 4 && tile_entries != 8)
+        return fail(DB_EINVAL, "db_tune_batch: tile_entries must be 0, 4 or 8");
+    if (query_chunk < 0 || query_chunk > 1024)
+        return fail(DB_EINVAL, "db_tune_batch: query_chunk %d outside [0, 1024]", query_chunk);
     db->batch_planes = slab_planes;
     db->batch_threads = block_threads;
+    db->batch_tile = tile_entries;
+    db->batch_qchunk = query_chunk;
     return DB_OK;
 }
 

@@ -6,9 +6,12 @@
 // counted on the fly (it depends on the box). The query words were ROI-masked
 // when packed, so only the database side needs x-edge masks.
 //
-// Main kernel (batch_lds_kernel): one block owns a tile of kTile entries and
-// streams them through LDS in z-slabs of Z planes, so every database word is
-// read from HBM exactly once per launch. For each slab, the block's waves
+// Main kernel (batch_lds_kernel): a persistent grid (as many blocks as are
+// resident) takes work items (tile, query chunk) from one atomic counter until
+// none is left. Tiles are groups of TILE entries (4 or 8) ordered by their cost,
+// largest first, so long items start early and short ones fill in at the end.
+// An item streams its tile's entries through LDS in z-slabs of Z planes, so
+// every database word is read from HBM once per query chunk. For each slab, the block's waves
 // take the queries whose box meets the slab (a host-built list, costliest
 // first) and run them against the LDS copy: a lane per box row, the packed
 // query row from L2 reused for the kTile entries. Per-(query, entry) counters
@@ -26,12 +29,14 @@
 // L2 locality. Every block exits once all 8 queues are empty.
 #include <limits.h>
 
+#include <algorithm>
+
 #include "common.hpp"
 #include "internal.hpp"
 
 namespace tdb {
 
-constexpr int kTile = 4;
+constexpr int kTile = 4;        // entries per item of the L2 fallback kernel
 constexpr int kXcd = 8;
 constexpr int kBatchThreads = 1024;
 constexpr int kQueryChunk = 256;   // queries whose counters share one block's LDS
@@ -98,8 +103,8 @@ __device__ __forceinline__ uint32_t reduce16(const uint32_t (&v)[16], int lane)
 // Rows of 128 voxels (4 words per mask) for a box whose x-range covers words
 // W0..W1: only those words are counted; the database side needs a mask only on
 // the two edge words (the query side was masked when packed).
-template <int W0, int W1>
-__device__ __forceinline__ void count_rows4(uint32_t (&acc)[16], const uint32_t *D, int slab_w,
+template <int TILE, int W0, int W1>
+__device__ __forceinline__ void count_rows4(uint32_t (&acc)[4 * TILE], const uint32_t *D, int slab_w,
                                             const uint32_t *Q0, const uint32_t *Q1, uint32_t nr,
                                             uint32_t nyr, uint32_t M, int zlo, int y0, int zs0,
                                             int ny, uint32_t mlo, uint32_t mhi, int lane)
@@ -125,7 +130,7 @@ __device__ __forceinline__ void count_rows4(uint32_t (&acc)[16], const uint32_t 
         for (int u = 0; u < 2; ++u) {
             if (u == 1 && !live1) break;
 #pragma unroll
-            for (int s = 0; s < kTile; ++s) {
+            for (int s = 0; s < TILE; ++s) {
                 const u32x4 da = *reinterpret_cast<const u32x4 *>(D + (2 * s) * slab_w + lw[u]);
                 const u32x4 db = *reinterpret_cast<const u32x4 *>(D + (2 * s + 1) * slab_w + lw[u]);
 #pragma unroll
@@ -147,180 +152,203 @@ __device__ __forceinline__ void count_rows4(uint32_t (&acc)[16], const uint32_t 
     }
 }
 
-// grid (tiles, query chunks), kBatchThreads threads. Dynamic LDS:
-//   D   uint32 [kTile][2][Z * ny * nxw]   the tile's slab, both masks
-//   cnt uint32 [nqc][kTile][4]            I_FLAIR, I_T1Gd, |B_FLAIR n R|, |B_T1Gd n R|
-// list_off [chunks * nslabs + 1] / list_q: per (chunk, slab) the queries whose
-// box meets the slab.
+// Persistent grid, kBatchThreads (or the tuned block size) threads. Dynamic LDS:
+//   D   uint32 [TILE][2][Z * ny * nxw]    the tile's slab, both masks
+//   cnt uint32 [qchunk][TILE][4]          I_FLAIR, I_T1Gd, |B_FLAIR n R|, |B_T1Gd n R|
+// Item i (from *counter, which the caller zeroes before the launch) is tile i / nchunks
+// and query chunk i % nchunks. list_off [nchunks * nslabs + 1] / list_q: per (chunk,
+// slab) the queries whose box meets the slab.
 //
-// A tile holds entries tile_order[4t .. 4t+3] (entries sorted by the centre of
-// their stored row boxes, so a tile's members overlap). Rows outside the union
-// of the members' row boxes are zero in every member and add nothing to I or
-// |B n R|: slabs outside it are neither staged nor scanned, and each query's
-// rows are clipped to it.
+// Tile t holds entries tile_order[TILE t .. TILE t + TILE - 1] (entries sorted by the
+// centre of their stored row boxes, so a tile's members overlap; tiles ordered by the
+// size of the union of their members' row boxes, largest first). Rows outside that
+// union are zero in every member and add nothing to I or |B n R|: slabs outside it are
+// neither staged nor scanned, and each query's rows are clipped to it.
+template <int TILE>
 __global__ void __launch_bounds__(kBatchThreads) batch_lds_kernel(
     const uint32_t *__restrict__ planes, int Wp, int nxw, int ny, int nz, int64_t n, int Z,
     int nslabs, const uint32_t *__restrict__ qpack, const int32_t *__restrict__ rois,
     const int32_t *__restrict__ list_off, const int32_t *__restrict__ list_q, int qchunk, int nq,
-    const int32_t *__restrict__ tile_order, const int32_t *__restrict__ ebox,
-    uint32_t *__restrict__ inter, uint32_t *__restrict__ bcnt, int64_t out_qstride)
+    int nchunks, int32_t *__restrict__ counter, const int32_t *__restrict__ tile_order,
+    const int32_t *__restrict__ ebox, uint32_t *__restrict__ inter, uint32_t *__restrict__ bcnt,
+    int64_t out_qstride)
 {
     extern __shared__ u32x4 lds4[];
+    __shared__ int32_t s_item;
     uint32_t *lds = reinterpret_cast<uint32_t *>(lds4);
     const int plane_w = ny * nxw;              // words per z-plane of one mask
     const int slab_w = Z * plane_w;            // words per slab of one mask
-    uint32_t *D = lds;                         // [kTile][2][slab_w]
-    uint32_t *cnt = lds + kTile * 2 * slab_w;  // [nqc][kTile][4]
-    const int chunk = blockIdx.y;
-    const int q0 = chunk * qchunk;
-    const int nqc = min(qchunk, nq - q0);
-    const int64_t e0 = (int64_t)blockIdx.x * kTile;
+    uint32_t *D = lds;                         // [TILE][2][slab_w]
+    uint32_t *cnt = lds + TILE * 2 * slab_w;   // [qchunk][TILE][4]
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nwaves = blockDim.x >> 6;
+    const int64_t ntiles = (n + TILE - 1) / TILE;
+    const int64_t nitems = ntiles * nchunks;
 
-    for (int i = threadIdx.x; i < nqc * kTile * 4; i += blockDim.x)
-        cnt[i] = 0;
-    // The tile's members and the union of their row boxes.
-    int64_t ent[kTile];
-    int uz0 = INT_MAX, uz1 = INT_MIN, uy0 = INT_MAX, uy1 = INT_MIN;
-#pragma unroll
-    for (int s = 0; s < kTile; ++s) {
-        const int64_t p = (e0 + s < n) ? e0 + s : n - 1;   // alias past the end
-        ent[s] = tile_order ? (int64_t)tile_order[p] : p;
-        const int32_t *b = ebox + 4 * ent[s];
-        if (b[1] > b[0] && b[3] > b[2]) {
-            uz0 = min(uz0, b[0]);
-            uz1 = max(uz1, b[1]);
-            uy0 = min(uy0, b[2]);
-            uy1 = max(uy1, b[3]);
-        }
-    }
-
-    for (int slab = 0; slab < nslabs; ++slab) {
-        const int zs0 = slab * Z;
-        const int zn = min(Z, nz - zs0);
-        const int words = zn * plane_w;
-        if (zs0 >= uz1 || zs0 + zn <= uz0) continue;   // block-uniform: no member has a row here
-        __syncthreads();  // the previous slab is consumed; counters are zeroed
-        // Stage the tile's slab: kTile entries x 2 masks x `words` words.
-        if ((plane_w & 3) == 0) {
-            // kStageBatch loads per thread in flight before any is stored.
-            const int w4 = words >> 2;
-            const int tot = kTile * 2 * w4;
-            for (int i0 = threadIdx.x; i0 < tot; i0 += kStageBatch * blockDim.x) {
-                u32x4 v[kStageBatch];
-                int dst[kStageBatch];
-#pragma unroll
-                for (int u = 0; u < kStageBatch; ++u) {
-                    const int i = i0 + u * blockDim.x;
-                    const int sm = i / w4;
-                    const int j = i - sm * w4;
-                    const int s = sm >> 1, m = sm & 1;
-                    dst[u] = -1;
-                    if (i < tot) {
-                        const int64_t e = ent[s & (kTile - 1)];
-                        const u32x4 *g = reinterpret_cast<const u32x4 *>(
-                            planes + e * 2 * (int64_t)Wp + (int64_t)m * Wp + (int64_t)zs0 * plane_w);
-                        v[u] = load_stream(g + j);
-                        dst[u] = sm * (slab_w >> 2) + j;
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < kStageBatch; ++u)
-                    if (dst[u] >= 0) reinterpret_cast<u32x4 *>(D)[dst[u]] = v[u];
-            }
-        } else {
-            for (int i = threadIdx.x; i < kTile * 2 * words; i += blockDim.x) {
-                const int sm = i / words;
-                const int j = i - sm * words;
-                const int s = sm >> 1, m = sm & 1;
-                const int64_t e = ent[s];
-                D[sm * slab_w + j] =
-                    planes[e * 2 * (int64_t)Wp + (int64_t)m * Wp + (int64_t)zs0 * plane_w + j];
-            }
-        }
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
         __syncthreads();
-        const int lo = list_off[chunk * nslabs + slab];
-        const int hi = list_off[chunk * nslabs + slab + 1];
-        for (int li = lo + wave; li < hi; li += nwaves) {
-            const int q = list_q[li];
-            const int32_t *R = rois + 6 * q;
-            const int x0 = R[0], x1 = R[3];
-            const int y0 = max(R[1], uy0), y1 = min(R[4], uy1);
-            const int zlo = max(max(R[2], zs0), uz0), zhi = min(min(R[5], zs0 + zn), uz1);
-            const uint32_t nyr = y1 > y0 ? (uint32_t)(y1 - y0) : 0u;
-            const uint32_t nr = (zhi > zlo) ? (uint32_t)(zhi - zlo) * nyr : 0u;
-            const uint32_t M = nyr > 1 ? magic_u32(nyr) : 0u;
-            const uint32_t *Q0 = qpack + (int64_t)q * 2 * Wp;
-            const uint32_t *Q1 = Q0 + Wp;
-            uint32_t acc[16];
+        const int64_t item = s_item;
+        __syncthreads();   // every thread has the item before s_item is written again
+        if (item >= nitems) return;   // block-uniform: every wave leaves here
+        const int64_t tile = item / nchunks;
+        const int chunk = (int)(item - tile * nchunks);
+        const int q0 = chunk * qchunk;
+        const int nqc = min(qchunk, nq - q0);
+        const int64_t e0 = tile * TILE;
+
+        for (int i = threadIdx.x; i < nqc * TILE * 4; i += blockDim.x)
+            cnt[i] = 0;
+        // The tile's members and the union of their row boxes.
+        int64_t ent[TILE];
+        int uz0 = INT_MAX, uz1 = INT_MIN, uy0 = INT_MAX, uy1 = INT_MIN;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) acc[j] = 0;
-            if (nxw == 4) {
-                // 128-voxel rows: one 16-byte word group per row and mask, counted
-                // over the box's words only (10 word ranges, each its own loop).
-                const int wx0 = x0 >> 5, wx1 = (x1 - 1) >> 5;
-                const uint32_t mlo = 0xffffffffu << (x0 & 31);
-                const uint32_t mhi = (x1 & 31) ? ((1u << (x1 & 31)) - 1u) : 0xffffffffu;
-#define TDB_ROWS(a, b)                                                                          \
-    count_rows4<a, b>(acc, D, slab_w, Q0, Q1, nr, nyr, M, zlo, y0, zs0, ny, mlo, mhi, lane)
-                switch (wx0 * 4 + wx1) {
-                case 0: TDB_ROWS(0, 0); break;
-                case 1: TDB_ROWS(0, 1); break;
-                case 2: TDB_ROWS(0, 2); break;
-                case 3: TDB_ROWS(0, 3); break;
-                case 5: TDB_ROWS(1, 1); break;
-                case 6: TDB_ROWS(1, 2); break;
-                case 7: TDB_ROWS(1, 3); break;
-                case 10: TDB_ROWS(2, 2); break;
-                case 11: TDB_ROWS(2, 3); break;
-                default: TDB_ROWS(3, 3); break;
+        for (int s = 0; s < TILE; ++s) {
+            const int64_t p = (e0 + s < n) ? e0 + s : n - 1;   // alias past the end
+            ent[s] = tile_order ? (int64_t)tile_order[p] : p;
+            const int32_t *b = ebox + 4 * ent[s];
+            if (b[1] > b[0] && b[3] > b[2]) {
+                uz0 = min(uz0, b[0]);
+                uz1 = max(uz1, b[1]);
+                uy0 = min(uy0, b[2]);
+                uy1 = max(uy1, b[3]);
+            }
+        }
+
+        for (int slab = 0; slab < nslabs; ++slab) {
+            const int zs0 = slab * Z;
+            const int zn = min(Z, nz - zs0);
+            const int words = zn * plane_w;
+            if (zs0 >= uz1 || zs0 + zn <= uz0) continue;   // block-uniform: no member has a row here
+            __syncthreads();  // the previous slab is consumed; counters are zeroed
+            // Stage the tile's slab: TILE entries x 2 masks x `words` words.
+            if ((plane_w & 3) == 0) {
+                // kStageBatch loads per thread in flight before any is stored.
+                const int w4 = words >> 2;
+                const int tot = TILE * 2 * w4;
+                for (int i0 = threadIdx.x; i0 < tot; i0 += kStageBatch * blockDim.x) {
+                    u32x4 v[kStageBatch];
+                    int dst[kStageBatch];
+#pragma unroll
+                    for (int u = 0; u < kStageBatch; ++u) {
+                        const int i = i0 + u * blockDim.x;
+                        const int sm = i / w4;
+                        const int j = i - sm * w4;
+                        const int s = sm >> 1, m = sm & 1;
+                        dst[u] = -1;
+                        if (i < tot) {
+                            const int64_t e = ent[s & (TILE - 1)];
+                            const u32x4 *g = reinterpret_cast<const u32x4 *>(
+                                planes + e * 2 * (int64_t)Wp + (int64_t)m * Wp +
+                                (int64_t)zs0 * plane_w);
+                            v[u] = load_stream(g + j);
+                            dst[u] = sm * (slab_w >> 2) + j;
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < kStageBatch; ++u)
+                        if (dst[u] >= 0) reinterpret_cast<u32x4 *>(D)[dst[u]] = v[u];
                 }
-#undef TDB_ROWS
             } else {
-                const int wx0 = x0 >> 5, wx1 = (x1 - 1) >> 5;
-                for (uint32_t r = lane; r < nr; r += 64) {
-                    const uint32_t zr = div_magic(r, nyr, M);
-                    const int z = zlo + (int)zr;
-                    const int y = y0 + (int)(r - zr * nyr);
-                    const int gw = (z * ny + y) * nxw;
-                    const int lw = ((z - zs0) * ny + y) * nxw;
-                    for (int wx = wx0; wx <= wx1; ++wx) {
-                        const uint32_t xm = xmask(wx, x0, x1);
-                        const uint32_t qa = Q0[gw + wx], qb = Q1[gw + wx];
+                for (int i = threadIdx.x; i < TILE * 2 * words; i += blockDim.x) {
+                    const int sm = i / words;
+                    const int j = i - sm * words;
+                    const int s = sm >> 1, m = sm & 1;
+                    const int64_t e = ent[s];
+                    D[sm * slab_w + j] =
+                        planes[e * 2 * (int64_t)Wp + (int64_t)m * Wp + (int64_t)zs0 * plane_w + j];
+                }
+            }
+            __syncthreads();
+            const int lo = list_off[chunk * nslabs + slab];
+            const int hi = list_off[chunk * nslabs + slab + 1];
+            for (int li = lo + wave; li < hi; li += nwaves) {
+                const int q = list_q[li];
+                const int32_t *R = rois + 6 * q;
+                const int x0 = R[0], x1 = R[3];
+                const int y0 = max(R[1], uy0), y1 = min(R[4], uy1);
+                const int zlo = max(max(R[2], zs0), uz0), zhi = min(min(R[5], zs0 + zn), uz1);
+                const uint32_t nyr = y1 > y0 ? (uint32_t)(y1 - y0) : 0u;
+                const uint32_t nr = (zhi > zlo) ? (uint32_t)(zhi - zlo) * nyr : 0u;
+                const uint32_t M = nyr > 1 ? magic_u32(nyr) : 0u;
+                const uint32_t *Q0 = qpack + (int64_t)q * 2 * Wp;
+                const uint32_t *Q1 = Q0 + Wp;
+                uint32_t acc[4 * TILE];
 #pragma unroll
-                        for (int s = 0; s < kTile; ++s) {
-                            const uint32_t da = D[(2 * s) * slab_w + lw + wx];
-                            const uint32_t db = D[(2 * s + 1) * slab_w + lw + wx];
-                            acc[4 * s + 0] += popc(qa & da);
-                            acc[4 * s + 1] += popc(qb & db);
-                            acc[4 * s + 2] += popc(da & xm);
-                            acc[4 * s + 3] += popc(db & xm);
+                for (int j = 0; j < 4 * TILE; ++j) acc[j] = 0;
+                if (nxw == 4) {
+                    // 128-voxel rows: one 16-byte word group per row and mask, counted
+                    // over the box's words only (10 word ranges, each its own loop).
+                    const int wx0 = x0 >> 5, wx1 = (x1 - 1) >> 5;
+                    const uint32_t mlo = 0xffffffffu << (x0 & 31);
+                    const uint32_t mhi = (x1 & 31) ? ((1u << (x1 & 31)) - 1u) : 0xffffffffu;
+#define TDB_ROWS(a, b)                                                                          \
+    count_rows4<TILE, a, b>(acc, D, slab_w, Q0, Q1, nr, nyr, M, zlo, y0, zs0, ny, mlo, mhi, lane)
+                    switch (wx0 * 4 + wx1) {
+                    case 0: TDB_ROWS(0, 0); break;
+                    case 1: TDB_ROWS(0, 1); break;
+                    case 2: TDB_ROWS(0, 2); break;
+                    case 3: TDB_ROWS(0, 3); break;
+                    case 5: TDB_ROWS(1, 1); break;
+                    case 6: TDB_ROWS(1, 2); break;
+                    case 7: TDB_ROWS(1, 3); break;
+                    case 10: TDB_ROWS(2, 2); break;
+                    case 11: TDB_ROWS(2, 3); break;
+                    default: TDB_ROWS(3, 3); break;
+                    }
+#undef TDB_ROWS
+                } else {
+                    const int wx0 = x0 >> 5, wx1 = (x1 - 1) >> 5;
+                    for (uint32_t r = lane; r < nr; r += 64) {
+                        const uint32_t zr = div_magic(r, nyr, M);
+                        const int z = zlo + (int)zr;
+                        const int y = y0 + (int)(r - zr * nyr);
+                        const int gw = (z * ny + y) * nxw;
+                        const int lw = ((z - zs0) * ny + y) * nxw;
+                        for (int wx = wx0; wx <= wx1; ++wx) {
+                            const uint32_t xm = xmask(wx, x0, x1);
+                            const uint32_t qa = Q0[gw + wx], qb = Q1[gw + wx];
+#pragma unroll
+                            for (int s = 0; s < TILE; ++s) {
+                                const uint32_t da = D[(2 * s) * slab_w + lw + wx];
+                                const uint32_t db = D[(2 * s + 1) * slab_w + lw + wx];
+                                acc[4 * s + 0] += popc(qa & da);
+                                acc[4 * s + 1] += popc(qb & db);
+                                acc[4 * s + 2] += popc(da & xm);
+                                acc[4 * s + 3] += popc(db & xm);
+                            }
                         }
                     }
                 }
-            }
-            const uint32_t tot = reduce16(acc, lane);
-            if ((lane & 3) == 0) {
-                const int vidx = (((lane >> 5) & 1) << 3) | (((lane >> 4) & 1) << 2) |
-                                 (((lane >> 3) & 1) << 1) | ((lane >> 2) & 1);
-                atomicAdd(&cnt[(q - q0) * kTile * 4 + vidx], tot);
+                // Fold the lanes' counters 16 at a time (four entries per group).
+#pragma unroll
+                for (int g = 0; g < TILE / 4; ++g) {
+                    uint32_t part[16];
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) part[j] = acc[16 * g + j];
+                    const uint32_t tot = reduce16(part, lane);
+                    if ((lane & 3) == 0) {
+                        const int vidx = (((lane >> 5) & 1) << 3) | (((lane >> 4) & 1) << 2) |
+                                         (((lane >> 3) & 1) << 1) | ((lane >> 2) & 1);
+                        atomicAdd(&cnt[(q - q0) * TILE * 4 + 16 * g + vidx], tot);
+                    }
+                }
             }
         }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < nqc * kTile; i += blockDim.x) {
-        const int qi = i / kTile, s = i - qi * kTile;
-        const int64_t e = ent[s];
-        if (e0 + s < n) {
-            const uint32_t *c = cnt + i * 4;
-            uint32_t *io = inter + (int64_t)(q0 + qi) * out_qstride + 2 * e;
-            uint32_t *bo = bcnt + (int64_t)(q0 + qi) * out_qstride + 2 * e;
-            io[0] = c[0];
-            io[1] = c[1];
-            bo[0] = c[2];
-            bo[1] = c[3];
+        __syncthreads();
+        for (int i = threadIdx.x; i < nqc * TILE; i += blockDim.x) {
+            const int qi = i / TILE, s = i - qi * TILE;
+            const int64_t e = ent[s];
+            if (e0 + s < n) {
+                const uint32_t *c = cnt + i * 4;
+                uint32_t *io = inter + (int64_t)(q0 + qi) * out_qstride + 2 * e;
+                uint32_t *bo = bcnt + (int64_t)(q0 + qi) * out_qstride + 2 * e;
+                io[0] = c[0];
+                io[1] = c[1];
+                bo[0] = c[2];
+                bo[1] = c[3];
+            }
         }
     }
 }
@@ -417,30 +445,55 @@ __global__ void __launch_bounds__(256) batch_rows_kernel(
     }
 }
 
+int batch_tile(const db_t *db) { return db->batch_tile == 8 ? 8 : 4; }
+
+template <int TILE>
+static const void *lds_kernel_ptr()
+{
+    return reinterpret_cast<const void *>(&batch_lds_kernel<TILE>);
+}
+
 BatchPlan batch_plan(const db_t *db, int nq)
 {
     BatchPlan p{};
     const Geometry &g = db->g;
-    p.qchunk = nq < kQueryChunk ? nq : kQueryChunk;
+    const int tile = batch_tile(db);
+    const int qc = db->batch_qchunk > 0 ? db->batch_qchunk : kQueryChunk;
+    p.tile = tile;
+    p.qchunk = nq < qc ? nq : qc;
     p.nchunks = (nq + p.qchunk - 1) / p.qchunk;
     const int64_t plane_bytes = (int64_t)g.ny * g.nxw * 4;
-    const int64_t cnt_bytes = (int64_t)p.qchunk * kTile * 4 * 4;
+    const int64_t cnt_bytes = (int64_t)p.qchunk * tile * 4 * 4;
     const int64_t budget = (int64_t)db->lds_max - cnt_bytes;
-    int64_t Z = budget > 0 ? budget / (kTile * 2 * plane_bytes) : 0;
+    int64_t Z = budget > 0 ? budget / (tile * 2 * plane_bytes) : 0;
     if (db->batch_planes > 0 && db->batch_planes < Z) Z = db->batch_planes;  // tuned depth
+    if (db->batch_planes < 0) Z = 0;                                           // L2 kernel forced
     if (Z > g.nz) Z = g.nz;
     p.threads = db->batch_threads > 0 ? db->batch_threads : kBatchThreads;
     p.Z = (int)Z;
     p.use_lds = Z >= 1;
     p.nslabs = p.use_lds ? (g.nz + p.Z - 1) / p.Z : 0;
-    p.lds_bytes = p.use_lds ? (size_t)(kTile * 2 * plane_bytes * Z + cnt_bytes) : 0;
+    p.lds_bytes = p.use_lds ? (size_t)(tile * 2 * plane_bytes * Z + cnt_bytes) : 0;
+    p.grid = 0;
+    if (p.use_lds) {
+        int per_cu = 0;
+        const void *fn = tile == 8 ? lds_kernel_ptr<8>() : lds_kernel_ptr<4>();
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, p.threads, p.lds_bytes) !=
+                hipSuccess || per_cu < 1)
+            per_cu = 1;
+        p.grid = db->cus * per_cu;
+    }
     return p;
 }
 
 hipError_t batch_set_lds_limit(int bytes)
 {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&batch_lds_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    hipError_t e = hipFuncSetAttribute(lds_kernel_ptr<4>(),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(lds_kernel_ptr<8>(), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                bytes);
+    return e;
 }
 
 hipError_t launch_batch_scan(const db_t *db, int64_t n, int nq, const BatchPlan &p,
@@ -449,14 +502,23 @@ hipError_t launch_batch_scan(const db_t *db, int64_t n, int nq, const BatchPlan 
                              uint32_t *inter, uint32_t *bcnt, hipStream_t s)
 {
     const Geometry &g = db->g;
-    const int64_t ntiles = (n + kTile - 1) / kTile;
     if (p.use_lds) {
-        const int32_t *tile_order = db->tile_order_n == n ? db->tile_order : nullptr;
-        hipLaunchKernelGGL(batch_lds_kernel, dim3((unsigned)ntiles, p.nchunks), dim3(p.threads),
-                           p.lds_bytes, s, db->planes, g.Wp, g.nxw, g.ny, g.nz, n, p.Z, p.nslabs,
-                           qpack, rois, list_off, list_q, p.qchunk, nq, tile_order, db->box, inter,
-                           bcnt, 2 * db->capacity);
+        const int32_t *tile_order =
+            db->tile_order_n == n && db->tile_order_tile == p.tile ? db->tile_order : nullptr;
+        const int64_t items = ((n + p.tile - 1) / p.tile) * p.nchunks;
+        const unsigned grid = (unsigned)std::min<int64_t>(items, p.grid);
+        if (p.tile == 8)
+            hipLaunchKernelGGL(batch_lds_kernel<8>, dim3(grid), dim3(p.threads), p.lds_bytes, s,
+                               db->planes, g.Wp, g.nxw, g.ny, g.nz, n, p.Z, p.nslabs, qpack, rois,
+                               list_off, list_q, p.qchunk, nq, p.nchunks, counters, tile_order,
+                               db->box, inter, bcnt, 2 * db->capacity);
+        else
+            hipLaunchKernelGGL(batch_lds_kernel<4>, dim3(grid), dim3(p.threads), p.lds_bytes, s,
+                               db->planes, g.Wp, g.nxw, g.ny, g.nz, n, p.Z, p.nslabs, qpack, rois,
+                               list_off, list_q, p.qchunk, nq, p.nchunks, counters, tile_order,
+                               db->box, inter, bcnt, 2 * db->capacity);
     } else {
+        const int64_t ntiles = (n + kTile - 1) / kTile;
         hipLaunchKernelGGL(batch_rows_kernel, dim3(db->cus * 8), dim3(256), 0, s, db->planes, g.Wp,
                            g.nxw, g.ny, n, nq, qpack, rois, order, ntiles, counters, inter, bcnt,
                            2 * db->capacity);

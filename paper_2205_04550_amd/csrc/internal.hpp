@@ -44,14 +44,17 @@ struct db_t {
     uint32_t *popcnt;   // [capacity][2]
     int32_t *box;       // [capacity][4] row box z0, z1, y0, y1 of the set bits
     uint64_t *mom;      // [capacity][4] FLAIR moments: sum x, sum y, sum z, count
-    int32_t *tile_order;  // [capacity] entries sorted by row-box centre (batched scan tiles)
+    int32_t *tile_order;  // [capacity] entries sorted by row-box centre, in tiles by cost
     int64_t tile_order_n; // entries the tile order covers (it is rebuilt when count differs)
+    int tile_order_tile;  // entries per tile it was built for
     size_t storage_bytes;
     int cus;                 // compute units of the device the handle was built on
     int device;
     int lds_max;             // LDS bytes one block may use on that device
     int batch_planes;        // tuned z-planes per LDS slab of the batched scan (0 = most that fit)
     int batch_threads;       // tuned block size of the batched scan (0 = default)
+    int batch_tile;          // tuned entries per tile (0 = 4; 4 or 8)
+    int batch_qchunk;        // tuned queries per chunk (0 = 256)
     tdb::BatchGraph *graph;
     tdb::Profiler *prof;
 };
@@ -105,10 +108,11 @@ hipError_t launch_scan(const db_t *db, int64_t n, const uint32_t *qpack, uint32_
 // Shape of a batched launch: LDS slabs of Z planes (use_lds) or the L2 fallback.
 struct BatchPlan {
     bool use_lds;
-    int Z, nslabs, qchunk, nchunks, threads;
+    int Z, nslabs, qchunk, nchunks, threads, tile, grid;
     size_t lds_bytes;
 };
 BatchPlan batch_plan(const db_t *db, int nq);
+int batch_tile(const db_t *db);   // entries per tile of the LDS kernel (4 or 8)
 hipError_t batch_set_lds_limit(int bytes);
 hipError_t launch_batch_scan(const db_t *db, int64_t n, int nq, const BatchPlan &p,
                              const uint32_t *qpack, const int32_t *rois, const int32_t *order,

@@ -120,7 +120,9 @@ def test_batch_boxes_of_the_workload_generator():
 
 
 def test_batch_results_do_not_depend_on_launch_shape():
-    """Every slab depth / block size the autotuner may pick gives the same bytes."""
+    """Every launch shape the autotuner may pick (slab depth, block size, entries per tile,
+    queries per chunk) and the kernel that reads the database through L2 (slab_planes
+    = -1) give the same bytes."""
     need_gpu()
     gen = synth.GenConfig(128, 24, 20, 2.0, 10.0, 0.5, 3.0, 31)
     n, nq, k = 75, 9, 7
@@ -129,9 +131,29 @@ def test_batch_results_do_not_depend_on_launch_shape():
     rois = _edge_rois((gen.nx, gen.ny, gen.nz), nq, np.random.default_rng(3))
     ref = _oracle_batch(conc, labels, rois, k)
     lab_d = torch.from_numpy(labels).cuda()
-    for planes, threads in [(0, 0), (1, 256), (2, 512), (3, 1024), (7, 512), (20, 1024)]:
-        say(f"shape planes={planes} threads={threads}")
-        db.tune_batch(planes, threads)
+    for shape in [(0, 0, 0, 0), (1, 256, 4, 0), (2, 512, 8, 0), (3, 1024, 8, 4), (7, 512, 4, 2),
+                  (20, 1024, 8, 1), (0, 1024, 8, 9), (-1, 0, 0, 0)]:
+        say(f"shape planes, threads, tile, chunk = {shape}")
+        db.tune_batch(*shape)
         res = db.query_batch(lab_d, rois, k)
         db.sync()
         _compare(res, ref, k)
+
+
+@pytest.mark.parametrize("planes,tile", [(0, 4), (0, 8), (-1, 0)])
+def test_batch_more_queries_than_one_chunk(planes, tile):
+    """300 queries (more than the 256 of one query chunk: two chunks, each an item of the
+    persistent grid per tile) with uneven boxes, against the oracle's loop over every entry;
+    also through the kernel that reads the database through L2."""
+    need_gpu()
+    gen = synth.GenConfig(128, 24, 20, 2.0, 10.0, 0.5, 3.0, 37)
+    n, nq, k = 61, 300, 5
+    say(f"batch: {nq} queries, planes {planes}, tile {tile}")
+    db, conc = build_db_from_host(gen, n, T_LO, T_HI)
+    labels, _ = synth.make_queries(gen, n, nq, synth.BATCH_QUERY_SEED)
+    rois = _edge_rois((gen.nx, gen.ny, gen.nz), nq, np.random.default_rng(5))
+    cnt, sc = oracle.scan_block_multi(conc, labels, T_LO, T_HI, rois)
+    db.tune_batch(planes, 0, tile, 0)
+    res = db.query_batch(torch.from_numpy(labels).cuda(), rois, k)
+    db.sync()
+    _compare(res, [(cnt[q], sc[q], oracle.rank(sc[q], k)) for q in range(nq)], k)
