@@ -407,6 +407,18 @@ class TumorDB:
             pass
 
 
+def _hand_to(stream, *tensors) -> None:
+    """Use on `stream` of tensors made on the current stream: the stream waits for the
+    current stream's work so far (the tensors' contents), and the caching allocator keeps
+    their memory until the stream's work on them is done (record_stream)."""
+    if stream is None or stream == torch.cuda.current_stream(stream.device):
+        return
+    stream.wait_stream(torch.cuda.current_stream(stream.device))
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
+
+
 class Latents:
     """Quantised latents on the device: codes [n][dim] (bf16 bits or e4m3 bytes), per-row
     scale (FP8 only) and squared norm of the stored vectors."""
@@ -423,6 +435,7 @@ class Latents:
             self.codes = torch.empty((n, dim), dtype=torch.uint8, device=dev)
             self.scale = torch.empty(n, dtype=torch.float32, device=dev)
         self.sq = torch.empty(n, dtype=torch.float32, device=dev)
+        _hand_to(stream, lat, self.codes, self.scale, self.sq)
         _check(LIB.emb_quantize(n, dim, lat.data_ptr(), fmt, self.codes.data_ptr(), _ptr(self.scale),
                                 self.sq.data_ptr(), _stream(stream)))
 
@@ -440,6 +453,7 @@ class BinaryCodes:
             thr = hash_thresholds(lat, stream)
         self.thr = thr.contiguous()
         self.codes = torch.empty((n, dim // 32), dtype=torch.int32, device=lat.device)
+        _hand_to(stream, lat, self.thr, self.codes)
         _check(LIB.emb_binarize(n, dim, lat.data_ptr(), self.thr.data_ptr(), self.codes.data_ptr(),
                                 _stream(stream)))
 
@@ -449,6 +463,7 @@ def hash_thresholds(lat: torch.Tensor, stream=None) -> torch.Tensor:
     lat = lat.to(torch.float32).contiguous()
     n, dim = lat.shape
     thr = torch.empty(dim, dtype=torch.float32, device=lat.device)
+    _hand_to(stream, lat, thr)
     _check(LIB.emb_hash_thresholds(n, dim, lat.data_ptr(), thr.data_ptr(), _stream(stream)))
     return thr
 

@@ -3,13 +3,17 @@
 // The paper's autoencoder (Sec. 2.4 "Implementation"): strided 3-D
 // convolutions (stride 2, kernel 3), a linear layer to the latent, and a
 // mirrored decoder of strided transposed convolutions; trained to reconstruct
-// its input. Channel counts here are tiny (2..64), so the layers are direct
-// convolutions on the vector ALUs: one thread per output (or input, for the
-// adjoint) voxel with block-uniform channel and batch indices, so weights
-// are read as scalars. Weight gradients reduce in two deterministic stages.
-// Every kernel is a template over the activation type T (float, or double
-// for finite-difference checks) and the weight storage type (bfloat16 bits,
-// float or double); accumulation is in T.
+// its input. The forward pass runs on the matrix cores as implicit GEMMs: the
+// first layer (mean-pooled labels or packed masks in, whose pooled values k/8
+// are exact in BF16) on BF16 16x16x32 products, the later convolutions with
+// Ci % 4 == 0 and the linear layers on FP32 16x16x4 / 32x32x2 products (each
+// product exact in FP32, only the summation order differs from a direct sum).
+// The backward kernels and the FP64 instantiation used by finite-difference
+// checks are direct convolutions on the vector ALUs: one thread per output (or
+// input, for the adjoint) voxel with block-uniform channel and batch indices.
+// Weight gradients reduce in two deterministic stages. Kernels are templates
+// over the activation type T (float, or double) and the weight storage type
+// (bfloat16 bits, float or double); accumulation is in T.
 #include <hip/hip_runtime.h>
 
 #include "../../include/tumornn.h"

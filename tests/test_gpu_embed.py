@@ -287,3 +287,21 @@ def test_rerank_in_two_calls_matches_rerank():
     db.sync()
     for a, w in zip(got, want):
         assert torch.equal(a, w)
+
+
+@pytest.mark.parametrize("fmt", [0, 1])
+def test_latents_quantised_on_a_side_stream(fmt):
+    """Quantisation enqueued on another stream (the float32 copy of the input is made on
+    the current stream) gives the same codes, scales and norms as on the current stream."""
+    need_gpu()
+    from paper_2205_04550_amd import binding as b
+    lat = _lat(300, 128, 13).cuda().to(torch.float16)      # converted to float32 inside
+    want = b.Latents(lat, fmt)
+    side = torch.cuda.Stream()
+    got = b.Latents(lat, fmt, stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    assert torch.equal(got.codes.view(torch.uint8), want.codes.view(torch.uint8))
+    assert torch.equal(got.sq, want.sq)
+    if fmt == b.EMB_FP8:
+        assert torch.equal(got.scale, want.scale)
