@@ -320,12 +320,13 @@ def bench_batch(args, db, gen, n, build_s) -> int:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": f"batched exact scan, {nq} box-restricted queries x {n} sims x "
-                               f"{gen.nx}^3, top-{k} each, one persistent launch from a HIP graph",
+                               f"{gen.nx}^3, top-{k} each, one kernel launch (a block per tile of "
+                               f"entries and query chunk, costliest tiles first) from a HIP graph",
                    "n_db": n, "nq": nq, "k": k, "mean_box_voxels": pairs_vox / n / nq},
         "queries_per_s": nq / (ms * 1e-3),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                      "unit": "Tops/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
-                     "kernel": "batch_lds_kernel (persistent, from a HIP graph)",
+                     "kernel": "batch_lds_kernel (from a HIP graph)",
                      "kernel_avg_ms": g_avg,
                      "algorithmic_ops_per_launch": ops,
                      "dense_box_ops_per_launch": dense_ops,

@@ -146,9 +146,9 @@ int db_query_sparse(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx
 
 /* nq queries in one launch sequence, each optionally restricted to its own
  * box: both masks are cut to the box before Dice (an extension; the paper
- * compares whole volumes). The scan is one persistent kernel: resident blocks
- * take (tile of database entries, chunk of queries) items, costliest tiles
- * first, from a counter until none is left. q_labels: device uint8 [nq][nz][ny][nx];
+ * compares whole volumes). The scan is one kernel launch of one block per
+ * (tile of database entries, chunk of queries) item, dispatched costliest tile
+ * first. q_labels: device uint8 [nq][nz][ny][nx];
  * rois: HOST array [nq] (validated before enqueue: inside the grid, non-empty)
  * or NULL for whole grids; outputs idx [nq][k], score [nq][k], counts
  * [nq][k] or NULL (device). The kernel sequence is recorded once into a HIP

@@ -270,8 +270,8 @@ static hipError_t dist_launch(int fmt, int M, int N, int dim, const void *q_code
 // Sort the entries by the centre of their row boxes (z in bands of 8 planes,
 // then y), so that the batched kernel's tiles (groups of `tile` consecutive
 // entries) hold overlapping boxes; then order the tiles by the size of the union
-// of their members' row boxes, largest first (the persistent kernel takes tiles
-// in this order, so the longest items start first). Reads the boxes back after a
+// of their members' row boxes, largest first (blocks are dispatched in this
+// order, so the longest items start first). Reads the boxes back after a
 // device synchronisation; host sort; one upload.
 static int build_tile_order(db_t *db, int tile)
 {

@@ -108,7 +108,7 @@ hipError_t launch_scan(const db_t *db, int64_t n, const uint32_t *qpack, uint32_
 // Shape of a batched launch: LDS slabs of Z planes (use_lds) or the L2 fallback.
 struct BatchPlan {
     bool use_lds;
-    int Z, nslabs, qchunk, nchunks, threads, tile, grid;
+    int Z, nslabs, qchunk, nchunks, threads, tile;
     size_t lds_bytes;
 };
 BatchPlan batch_plan(const db_t *db, int nq);

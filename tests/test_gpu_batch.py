@@ -1,4 +1,4 @@
-"""GPU parity of the batched, box-restricted scan (persistent kernel replayed from a HIP graph).
+"""GPU parity of the batched, box-restricted scan (one kernel launch replayed from a HIP graph).
 
 Each query q is cut to its box R_q on both sides: I = |A n B n R|,
 A = |A n R|, B = |B n R| (the paper compares whole volumes; the box is this
@@ -143,7 +143,7 @@ def test_batch_results_do_not_depend_on_launch_shape():
 @pytest.mark.parametrize("planes,tile", [(0, 4), (0, 8), (-1, 0)])
 def test_batch_more_queries_than_one_chunk(planes, tile):
     """300 queries (more than the 256 of one query chunk: two chunks, each an item of the
-    persistent grid per tile) with uneven boxes, against the oracle's loop over every entry;
+    block per tile) with uneven boxes, against the oracle's loop over every entry;
     also through the kernel that reads the database through L2."""
     need_gpu()
     gen = synth.GenConfig(128, 24, 20, 2.0, 10.0, 0.5, 3.0, 37)
