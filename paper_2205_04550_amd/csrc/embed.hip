@@ -181,7 +181,8 @@ __device__ __forceinline__ uint32_t row16_min_scatter(const uint32_t (&k)[16], i
 // GMIN: also write, for every row and every whole group of 16 consecutive columns
 // g < ngroups, the smallest order key (fkey) of the group's distances to
 // gmin[row * gld + g]; the bound of the top-k selection below then reads these
-// instead of the distances (mode 0 only).
+// instead of the distances (mode 0 only). With GMIN, D may be null: then only the
+// minima are written.
 template <bool FP8, bool TAIL, int DEPTH, bool GMIN>
 __global__ void __launch_bounds__(kDThreads, 4) dist_lds_kernel(int M, int N, int K, int mt,
                                                              int ntiles,
@@ -314,7 +315,8 @@ __global__ void __launch_bounds__(kDThreads, 4) dist_lds_kernel(int M, int N, in
                 const float xc = t[0][kDM + cl];
                 const float sc = FP8 ? t[1][kDM + cl] : 1.0f;
                 float *out = D + (int64_t)(m0 + rl0) * ldd + col;
-                const int rows = col < N ? M - (m0 + rl0) : 0;
+                // No D (group minima only): nothing is stored.
+                const int rows = col < N && D ? M - (m0 + rl0) : 0;
                 uint32_t key[16];
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
@@ -1330,7 +1332,7 @@ static hipError_t dist_lds_launch(int M, int N, int K, const uint8_t *Q, const f
         const int g = min(ntiles, resident[dev]);
         hipLaunchKernelGGL((dist_lds_kernel<FP8, TAIL, DEPTH, GMIN>), dim3(g), dim3(kDThreads), 0, s,
                            M, n, K, mt, ntiles, Q, qs, qn, X + c0 * Kb, FP8 ? xs + c0 : nullptr,
-                           xn + c0, D + c0, (int64_t)N, mode, GMIN ? gmin + c0 / 16 : nullptr,
+                           xn + c0, D ? D + c0 : nullptr, (int64_t)N, mode, GMIN ? gmin + c0 / 16 : nullptr,
                            (int64_t)(N / 16), n / 16);
         e = hipGetLastError();
         if (e != hipSuccess) return e;

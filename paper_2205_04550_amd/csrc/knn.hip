@@ -11,11 +11,15 @@
 //   - A candidate is packed as fkey(d) << 32 | index: the order of packed values is the
 //     order (distance ascending, index ascending), and every packed value of a row is
 //     distinct.
+//   - Before the full pass, the distance kernel runs over a sample (the first 16,384
+//     entries) writing only the smallest key of every group of 16 entries; the k-th
+//     smallest of those minima bounds each row for the whole database (k groups, hence
+//     k entries, lie at or below it). Databases too small for the sample start without a
+//     bound and take one from each block's first tile.
 //   - Block (query tile, split) walks the database tiles of its split. A row's bound B is
-//     a packed value such that at least k entries of the split seen so far are <= B (or
-//     all ones while fewer are known). Every distance with packed <= B is appended to the
-//     row's list (an LDS counter and a store to the workspace); all others have k better
-//     entries in the same split and can never be among the k nearest.
+//     a packed value such that at least k entries are <= B. Every distance with packed
+//     <= B is appended to the row's list (a per-lane LDS atomic and a store to the
+//     workspace); all others have k better entries and can never be among the k nearest.
 //   - When a list outgrows its trigger, one wave tightens B: each lane takes the four
 //     smallest keys of the entries it holds, B becomes the k-th smallest of those 256 keys
 //     (k distinct entries lie at or below it; bisection on the key with ballot counts),
@@ -165,7 +169,7 @@ __device__ __forceinline__ void knn_compact(uint64_t *__restrict__ L, uint32_t *
 // so the blocks of one split (all query tiles) share an XCD and its L2 copy of the split's
 // database tiles. Split s takes database tiles [s nt / nsplit, (s + 1) nt / nsplit).
 // Outputs per (block, row): the list lists[b][row][0 .. cnt), cnt, and the bound.
-// SEEDB: no bound is given; the block's first tile provides one (the sample pass).
+// SEEDB: no bound is given; the block's first tile provides one (small databases).
 template <bool FP8, bool TAIL, bool SEEDB>
 __global__ void __launch_bounds__(kDThreads, 4) knn_kernel(
     int M, int N, int K, int k, int mt, int nsplit, int nt, const uint8_t *__restrict__ Q,
@@ -174,55 +178,61 @@ __global__ void __launch_bounds__(kDThreads, 4) knn_kernel(
     uint64_t *__restrict__ lists, uint32_t *__restrict__ cnt_out, uint64_t *__restrict__ bound_out)
 {
     __shared__ __attribute__((aligned(16))) uint8_t lds[2][(kDM + kDN) * kDRow];
-    __shared__ float tv[2][2][kDM + kDN];
+    __shared__ __attribute__((aligned(16))) float tv[2][2][kDM + kDN];
     __shared__ uint64_t s_bound[kDM];
     __shared__ uint32_t s_cnt[kDM];
     __shared__ float s_tauf[kDM];
-    __shared__ float s_alpha[kDM], s_qn[kDM];
+    __shared__ __attribute__((aligned(16))) float s_alpha[kDM];
+    __shared__ float s_qn[kDM];
     __shared__ uint32_t s_seed[kDM];
     const int b = blockIdx.x;
     const int m = (b / kXcds) % mt, s = (b / kXcds) / mt * kXcds + b % kXcds;
     const int m0 = m * kDM;
     const int t0 = (int)((int64_t)s * nt / nsplit), t1 = (int)((int64_t)(s + 1) * nt / nsplit);
+    const int T = t1 - t0;                                 // database tiles of this block
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     uint64_t *const Lb = lists + (size_t)b * kDM * kKnnCap;
     if (tid < kDM) {
         // A bound given for the whole row (from a sample of the database) holds for every
-        // split; without one, the block's first tile provides the first bound.
+        // split; without one, the block's first tile provides the first bound. A row past
+        // M gets alpha = +inf, so no distance of it passes the test below.
         const uint64_t B = !SEEDB && m0 + tid < M ? seed[m0 + tid] : ~0ull;
         s_bound[tid] = B;
         s_cnt[tid] = 0;
         s_tauf[tid] = bound_float(B);
         s_qn[tid] = qn[min(m0 + tid, M - 1)];
-        s_alpha[tid] = knn_alpha(s_qn[tid], s_tauf[tid]);
+        s_alpha[tid] = m0 + tid < M ? knn_alpha(s_qn[tid], s_tauf[tid]) : __int_as_float(0x7f800000);
         s_seed[tid] = 0;
     }
     const int Kb = FP8 ? K : 2 * K;                        // bytes per row in Q and X
     const int nslices = (2 * K + kDSlice - 1) / kDSlice;   // 32 values per slice
-    const int U = (t1 - t0) * nslices;
     const int wm = wave >> 2, wn = wave & 3;
     const int half = lane >> 5, r32 = lane & 31;
     const int frow = tid >> 2, fpart = (tid & 3) * 16;
+    // 32-bit offsets: the host keeps N Kb (and M Kb) below 4 GiB. The query row is fixed for
+    // the block; the two database rows change with the tile being fetched.
+    const uint32_t oq = (uint32_t)min(m0 + frow, M - 1) * (uint32_t)Kb;
+    uint32_t ox[2] = {0u, 0u};
     u32x4 pre[3];
     float prv[2];
-    auto fetch = [&](int v, u32x4 (&dst)[3], float (&dv)[2]) {
-        const int i = v / nslices, sl = v - i * nslices;
+    // Slice sl of the block's tile i into registers (the fetch runs two slices ahead).
+    auto fetch = [&](int i, int sl, u32x4 (&dst)[3], float (&dv)[2]) {
         const int n0 = (t0 + i) * kDN;
+        if (sl == 0) {
+            ox[0] = (uint32_t)min(n0 + frow, N - 1) * (uint32_t)Kb;
+            ox[1] = (uint32_t)min(n0 + kDM + frow, N - 1) * (uint32_t)Kb;
+        }
         const uint32_t kb = FP8 ? (uint32_t)(sl * (kDSlice / 2) + (fpart >> 1))
                                 : (uint32_t)(sl * kDSlice + fpart);
         if (!TAIL || (int)kb < Kb) {
-            // 32-bit offsets: the host keeps N Kb (and M Kb) below 4 GiB.
-            const uint32_t o0 = (uint32_t)min(m0 + frow, M - 1) * (uint32_t)Kb + kb;
-            const uint32_t o1 = (uint32_t)min(n0 + frow, N - 1) * (uint32_t)Kb + kb;
-            const uint32_t o2 = (uint32_t)min(n0 + kDM + frow, N - 1) * (uint32_t)Kb + kb;
             if (FP8) {
-                dst[0] = e4m3x8_to_bf16(*reinterpret_cast<const u32x2 *>(Q + o0));
-                dst[1] = e4m3x8_to_bf16(*reinterpret_cast<const u32x2 *>(X + o1));
-                dst[2] = e4m3x8_to_bf16(*reinterpret_cast<const u32x2 *>(X + o2));
+                dst[0] = e4m3x8_to_bf16(*reinterpret_cast<const u32x2 *>(Q + oq + kb));
+                dst[1] = e4m3x8_to_bf16(*reinterpret_cast<const u32x2 *>(X + ox[0] + kb));
+                dst[2] = e4m3x8_to_bf16(*reinterpret_cast<const u32x2 *>(X + ox[1] + kb));
             } else {
-                dst[0] = *reinterpret_cast<const u32x4 *>(Q + o0);
-                dst[1] = *reinterpret_cast<const u32x4 *>(X + o1);
-                dst[2] = *reinterpret_cast<const u32x4 *>(X + o2);
+                dst[0] = *reinterpret_cast<const u32x4 *>(Q + oq + kb);
+                dst[1] = *reinterpret_cast<const u32x4 *>(X + ox[0] + kb);
+                dst[2] = *reinterpret_cast<const u32x4 *>(X + ox[1] + kb);
             }
         } else {
             dst[0] = dst[1] = dst[2] = (u32x4){0u, 0u, 0u, 0u};
@@ -239,13 +249,12 @@ __global__ void __launch_bounds__(kDThreads, 4) knn_kernel(
             }
         }
     };
-    auto stash = [&](int v, const u32x4 (&src)[3], const float (&sv)[2]) {
-        uint8_t *Ls = &lds[v & 1][0];
+    auto stash = [&](int i, int sl, int buf, const u32x4 (&src)[3], const float (&sv)[2]) {
+        uint8_t *Ls = &lds[buf][0];
 #pragma unroll
         for (int j = 0; j < 3; ++j)
             *reinterpret_cast<u32x4 *>(&Ls[(j * kDM + frow) * kDRow + fpart]) = src[j];
-        const int i = v / nslices;
-        if (v - i * nslices == 0 && tid < kDM + kDN) {
+        if (sl == 0 && tid < kDM + kDN) {
             tv[i & 1][0][tid] = sv[0];
             if (FP8) tv[i & 1][1][tid] = sv[1];
         }
@@ -281,7 +290,9 @@ __global__ void __launch_bounds__(kDThreads, 4) knn_kernel(
         }
     };
     // The distances of a finished tile (the arithmetic of the distance kernel's epilogue),
-    // appended to the lists of their rows where they are within the rows' bounds.
+    // appended to the lists of their rows where they are within the rows' bounds. The
+    // lanes that hold such a distance each reserve a place in the row's list with an LDS
+    // atomic; most (row, column) pairs fail a two-operation test first.
     //
     // seed (the block's first tile, when no bound was given): first a bound from the tile
     // itself. The 64 distances a wave holds for one row are split over the 32 lanes of a
@@ -293,20 +304,40 @@ __global__ void __launch_bounds__(kDThreads, 4) knn_kernel(
         const int n0 = (t0 + i_tile) * kDN;
         const float(&t)[2][kDM + kDN] = tv[i_tile & 1];
         // The lane's first row, made opaque here so that the compiler does not hoist the
-        // 32 row addresses of the lists out of the tile loop (they would be spilled).
+        // row addresses of the lists out of the tile loop (they would be spilled).
         int rbase = wm * 64 + 4 * half;
         asm volatile("" : "+v"(rbase));
-        auto dist = [&](int i, int j, int r, int rl) {
+        // Per column of the lane: its index, norm, scale and the column part of the test
+        // (+inf past N, so that no distance of it passes).
+        uint32_t colv[2];
+        float xc[2], scol[2], beta[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
             const int cl = wn * 64 + j * 32 + r32;
-            const float xc = t[0][kDM + cl];
-            const float sc = FP8 ? t[1][kDM + cl] : 1.0f;
-            const float dot = FP8 ? (t[1][rl] * sc) * acc[i][j][r] : acc[i][j][r];
-            const float dv = (t[0][rl] + xc) - 2.0f * dot;
-            // An entry outside the matrix gets NaN: it passes no test below.
-            return (m0 + rl < M && n0 + cl < N) ? dv : __int_as_float(0x7fc00000);
+            colv[j] = (uint32_t)(n0 + cl);
+            xc[j] = t[0][kDM + cl];
+            scol[j] = FP8 ? t[1][kDM + cl] : 1.0f;
+            beta[j] = n0 + cl < N ? xc[j] * 0.5f - 4e-7f * xc[j] : __int_as_float(0x7f800000);
+        }
+        auto append = [&](int rl, int j, float dv) {
+            const uint64_t p = ((uint64_t)fkey(dv) << 32) | colv[j];
+            if (p <= s_bound[rl]) {
+                const uint32_t pos = atomicAdd(&s_cnt[rl], 1u);
+                // Opaque row: the list address is formed here, on the rare path, not kept
+                // live across the epilogue.
+                int ro = rl;
+                asm volatile("" : "+v"(ro));
+                Lb[(uint32_t)ro * (uint32_t)kKnnCap + pos] = p;
+            }
         };
         if constexpr (SEEDB) {
-            // The block's first tile: distances into the accumulators, then the bound.
+            auto dist = [&](int i, int j, int r, int rl) {
+                const float dot = FP8 ? (t[1][rl] * scol[j]) * acc[i][j][r] : acc[i][j][r];
+                const float dv = (t[0][rl] + xc[j]) - 2.0f * dot;
+                // An entry outside the matrix gets NaN: it passes no test below.
+                return (m0 + rl < M && (int)colv[j] < N) ? dv : __int_as_float(0x7fc00000);
+            };
+            // Distances into the accumulators, then (first tile) the bound.
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -351,96 +382,90 @@ __global__ void __launch_bounds__(kDThreads, 4) knn_kernel(
                 }
                 __syncthreads();
             }
-        }
-        // Appends: a float test against the bound first (most distances fail it), then the
-        // exact test on the packed value; the lanes of a half-wave (one row) reserve their
-        // places in the row's list with one LDS atomic.
-        const uint64_t hmask = half ? 0xffffffff00000000ull : 0x00000000ffffffffull;
-        float beta[2], scol[2];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const float xn_c = t[0][kDM + wn * 64 + j * 32 + r32];
-            beta[j] = xn_c * 0.5f - 4e-7f * xn_c;
-            scol[j] = FP8 ? t[1][kDM + wn * 64 + j * 32 + r32] : 1.0f;
-        }
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int rl = rbase + i * 32 + 8 * (r >> 2) + (r & 3);
-                float dv[2];
-                bool pre0, pre1;
-                if constexpr (SEEDB) {
+                for (int r = 0; r < 16; ++r) {
+                    const int rl = rbase + i * 32 + 8 * (r >> 2) + (r & 3);
                     const float tau = s_tauf[rl];
-                    dv[0] = acc[i][0][r];
-                    dv[1] = acc[i][1][r];
-                    pre0 = dv[0] <= tau;
-                    pre1 = dv[1] <= tau;
-                } else {
-                    // The conservative test on the dot product (two operations per entry).
-                    const float al = s_alpha[rl];
-                    float dt[2];
 #pragma unroll
                     for (int j = 0; j < 2; ++j)
-                        dt[j] = FP8 ? (t[1][rl] * scol[j]) * acc[i][j][r] : acc[i][j][r];
-                    pre0 = dt[0] >= al + beta[0];
-                    pre1 = dt[1] >= al + beta[1];
-                    if (__ballot(pre0 || pre1) == 0) continue;      // uniform
-                    dv[0] = dist(i, 0, r, rl);
-                    dv[1] = dist(i, 1, r, rl);
+                        if (acc[i][j][r] <= tau) append(rl, j, acc[i][j][r]);
                 }
-                if (__ballot(pre0 || pre1) == 0) continue;          // uniform
-                const uint64_t B = s_bound[rl];
-                uint64_t p[2];
-                bool ok[2];
+        } else {
+            // The conservative test on the dot product, four rows (consecutive in the
+            // accumulator layout) per LDS read of their row terms.
 #pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const int col = n0 + wn * 64 + j * 32 + r32;
-                    p[j] = ((uint64_t)fkey(dv[j]) << 32) | (uint32_t)col;
-                    ok[j] = (j ? pre1 : pre0) && p[j] <= B;
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int rl0 = rbase + i * 32 + 8 * a;
+                    const f32x4 al = *reinterpret_cast<const f32x4 *>(&s_alpha[rl0]);
+                    f32x4 sr = {1.0f, 1.0f, 1.0f, 1.0f};
+                    if (FP8) sr = *reinterpret_cast<const f32x4 *>(&t[1][rl0]);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const int r = 4 * a + c;
+                        float dt[2];
+                        bool ok[2];
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) {
+                            dt[j] = FP8 ? (sr[c] * scol[j]) * acc[i][j][r] : acc[i][j][r];
+                            ok[j] = dt[j] >= al[c] + beta[j];
+                        }
+                        if (ok[0] || ok[1]) {
+                            const float qr = t[0][rl0 + c];
+#pragma unroll
+                            for (int j = 0; j < 2; ++j)
+                                if (ok[j]) append(rl0 + c, j, (qr + xc[j]) - 2.0f * dt[j]);
+                        }
+                    }
                 }
-                const uint64_t m0b = __ballot(ok[0]) & hmask, m1b = __ballot(ok[1]) & hmask;
-                const uint32_t c0 = (uint32_t)__popcll(m0b), c = c0 + (uint32_t)__popcll(m1b);
-                uint32_t base = 0;
-                if (r32 == 0 && c) base = atomicAdd(&s_cnt[rl], c);
-                base = __shfl(base, half * 32, 64);
-                // mbcnt: set bits of the mask in the lanes below this one.
-                const uint32_t b0 = __builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(m0b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m0b, 0u));
-                const uint32_t b1 = __builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(m1b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m1b, 0u));
-                uint64_t *Lr = Lb + (size_t)rl * kKnnCap + base;
-                if (ok[0]) Lr[b0] = p[0];
-                if (ok[1]) Lr[c0 + b1] = p[1];
-            }
+        }
     };
+    // Slice positions (tile, K slice) of the next slice to stash and to fetch; each step
+    // advances them by one slice.
+    auto advance = [&](int &i, int &sl) {
+        if (++sl == nslices) {
+            sl = 0;
+            ++i;
+        }
+    };
+    int si = 0, ssl = 0, fi = 0, fsl = 0;
     __syncthreads();
-    if (U > 0) {
-        fetch(0, pre, prv);
-        stash(0, pre, prv);
-        if (1 < U) fetch(1, pre, prv);
+    if (T > 0) {
+        fetch(0, 0, pre, prv);
+        stash(0, 0, 0, pre, prv);
+        advance(si, ssl);
+        fi = si;
+        fsl = ssl;
+        if (fi < T) fetch(fi, fsl, pre, prv);
+        advance(fi, fsl);
         __syncthreads();
     }
-    // Slice u of the block's stream: tile u / nslices, K slice u % nslices. The first
-    // slice of a tile is peeled off the slice loop, so the accumulators are dead between
-    // a tile's epilogue and the next tile (the list compaction uses those registers).
+    // Slice u of the block's stream is multiplied from LDS buffer u % 2 while slice u + 1 is
+    // stashed into the other buffer and slice u + 2 is fetched. The first slice of a tile is
+    // peeled off the slice loop, so the accumulators are dead between a tile's epilogue and
+    // the next tile (the list compaction uses those registers).
     int u = 0;
-    for (int tile = 0; tile < t1 - t0; ++tile) {
-        compute(u & 1, true);
-        if (u + 1 < U) {
-            stash(u + 1, pre, prv);
-            if (u + 2 < U) fetch(u + 2, pre, prv);
-        }
-        for (int sl = 1; sl < nslices; ++sl) {
-            __syncthreads();
-            ++u;
-            compute(u & 1, false);
-            if (u + 1 < U) {
-                stash(u + 1, pre, prv);
-                if (u + 2 < U) fetch(u + 2, pre, prv);
+    auto step = [&](bool first) {
+        compute(u & 1, first);
+        if (si < T) {
+            stash(si, ssl, (u + 1) & 1, pre, prv);
+            advance(si, ssl);
+            if (fi < T) {
+                fetch(fi, fsl, pre, prv);
+                advance(fi, fsl);
             }
         }
         ++u;
+    };
+    for (int tile = 0; tile < T; ++tile) {
+        step(true);
+        for (int sl = 1; sl < nslices; ++sl) {
+            __syncthreads();
+            step(false);
+        }
         epilogue(tile, tile == 0);
         __syncthreads();                           // every append of the tile is done
         // A list that outgrows the trigger is tightened.
@@ -469,7 +494,7 @@ constexpr int kMergeCap = 8192;     // gathered candidates held in LDS
 __global__ void __launch_bounds__(kMergeThreads) knn_merge_kernel(
     int k, int mt, int nsplit, const uint64_t *__restrict__ lists,
     const uint32_t *__restrict__ cnt, const uint64_t *__restrict__ bound, int32_t *__restrict__ idx,
-    float *__restrict__ dout, uint64_t *__restrict__ kth_out)
+    float *__restrict__ dout)
 {
     __shared__ uint64_t buf[kMergeCap];
     __shared__ uint64_t win[kKnnMaxK];
@@ -548,11 +573,7 @@ __global__ void __launch_bounds__(kMergeThreads) knn_merge_kernel(
     // the bin holding the k-th smallest is fixed; once that bin's count equals what is
     // still needed, every candidate whose fixed bits are <= the prefix is a winner.
     const int kk = min(k, (int)min(total, (uint32_t)INT_MAX));
-    if (kk < k) {                           // fewer candidates than k (cannot happen for k <= N)
-        if (kth_out && tid == 0) kth_out[q] = ~0ull;
-        if (kth_out) return;
-    }
-    if (kk == 0) {
+    if (kk == 0) {                          // no candidate (cannot happen for k <= N)
         if (tid < k) {
             idx[(size_t)q * k + tid] = -1;
             dout[(size_t)q * k + tid] = __int_as_float(0x7fc00000);
@@ -675,9 +696,7 @@ __global__ void __launch_bounds__(kMergeThreads) knn_merge_kernel(
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int e = 64 * u + lane;
-        if (kth_out) {
-            if (e == k - 1) kth_out[q] = w[u];     // the k-th smallest packed value
-        } else if (e < k) {
+        if (e < k) {
             idx[(size_t)q * k + e] = e < kk ? (int32_t)(uint32_t)w[u] : -1;
             dout[(size_t)q * k + e] = e < kk ? fkey_inv((uint32_t)(w[u] >> 32)) : __int_as_float(0x7fc00000);
         }
@@ -740,20 +759,61 @@ int knn_splits(int M, int N)
     return max(kXcds, min(kKnnMaxSplit, ns));
 }
 
-// Columns of the sample whose exact k-th smallest distance bounds every row before the
-// full pass (0: no sample pass). One tile per split, so its blocks are short.
+// The row bounds before the full pass. The distance kernel leaves, for the first S
+// database entries, the smallest key of every group of 16 consecutive entries; at least
+// k groups have a minimum <= the k-th smallest of those minima, so at least k entries of
+// the row have a packed value <= (that key, all ones): a bound for the whole row. One
+// wave per row; ng <= kSeedMaxGroups groups; no bound (all ones) when ng < k.
+constexpr int kSeedMaxGroups = 2048;
+
+__global__ void __launch_bounds__(256) knn_seed_kernel(int M, int ng, int k,
+                                                       const uint32_t *__restrict__ gmin,
+                                                       uint64_t *__restrict__ seed)
+{
+    constexpr int R = kSeedMaxGroups / 64;
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= M) return;                         // whole wave
+    if (ng < k) {
+        if (lane == 0) seed[row] = ~0ull;
+        return;
+    }
+    uint32_t v[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        const int g = u * 64 + lane;
+        v[u] = g < ng ? gmin[(size_t)row * ng + g] : ~0u;
+    }
+    // The smallest key with at least k minima <= it (bisection; ballot counts).
+    uint32_t lo = 0, hi = ~0u;
+    while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        int c = 0;
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+            if (u * 64 < ng) c += __popcll(__ballot(v[u] <= mid));
+        if (c >= k) hi = mid;
+        else lo = mid + 1;
+    }
+    if (lane == 0) seed[row] = lo == ~0u ? ~0ull : (((uint64_t)lo << 32) | 0xffffffffull);
+}
+
+// Database entries of the sample that bounds every row before the full pass (0: none;
+// the blocks then bound their rows from their own first tile).
 static int knn_sample_cols(int N)
 {
-    if (N < 8 * kXcds * kDN) return 0;
-    const int t = min(kKnnMaxSplit, max(kXcds, (N / 8 / kDN) / kXcds * kXcds));
-    return t * kDN;
+    constexpr int kSample = 16384;
+    static_assert(kSample / 16 <= kSeedMaxGroups && kSample / 16 >= kKnnMaxK, "sample size");
+    return N >= 2 * kSample ? kSample : 0;
 }
 
 size_t knn_ws_bytes(int M, int N)
 {
     const size_t G = (size_t)((M + kDM - 1) / kDM) * knn_splits(M, N);
+    const size_t S = (size_t)knn_sample_cols(N);
     return align_up(G * kDM * kKnnCap * 8, kAlign) + align_up(G * kDM * 4, kAlign) +
-           align_up(G * kDM * 8, kAlign) + align_up((size_t)M * 8, kAlign);
+           align_up(G * kDM * 8, kAlign) + align_up((size_t)M * 8, kAlign) +
+           align_up((size_t)M * (S / 16) * 4, kAlign);
 }
 
 template <bool FP8, bool TAIL, bool SEEDB>
@@ -781,43 +841,48 @@ hipError_t launch_knn(bool fp8, int M, int N, int K, const void *Q, const float 
     uint64_t *bound = reinterpret_cast<uint64_t *>(p);
     p += align_up(G * kDM * 8, kAlign);
     uint64_t *seed = reinterpret_cast<uint64_t *>(p);
+    p += align_up((size_t)M * 8, kAlign);
+    uint32_t *gmin = reinterpret_cast<uint32_t *>(p);
     const auto *q = static_cast<const uint8_t *>(Q);
     const auto *x = static_cast<const uint8_t *>(X);
     const bool tail = !fp8 && (2 * K) % kDSlice;
-    auto pass = [&](int n, int ns, const uint64_t *sd) {
-        if (!sd) {
-            if (fp8) return knn_pass<true, false, true>(M, n, K, k, ns, q, qs, qn, x, xs, xn, sd,
-                                                        lists, cnt, bound, s);
-            if (tail) return knn_pass<false, true, true>(M, n, K, k, ns, q, nullptr, qn, x,
-                                                         nullptr, xn, sd, lists, cnt, bound, s);
-            return knn_pass<false, false, true>(M, n, K, k, ns, q, nullptr, qn, x, nullptr, xn,
-                                                sd, lists, cnt, bound, s);
-        }
-        if (fp8) return knn_pass<true, false, false>(M, n, K, k, ns, q, qs, qn, x, xs, xn, sd,
-                                                     lists, cnt, bound, s);
-        if (tail) return knn_pass<false, true, false>(M, n, K, k, ns, q, nullptr, qn, x, nullptr,
-                                                      xn, sd, lists, cnt, bound, s);
-        return knn_pass<false, false, false>(M, n, K, k, ns, q, nullptr, qn, x, nullptr, xn, sd,
-                                             lists, cnt, bound, s);
-    };
     hipError_t e = hipSuccess;
-    const uint64_t *sd = nullptr;
-    if (const int S = knn_sample_cols(N)) {
-        // The first S entries, one tile per split: the exact k-th smallest (distance, index)
-        // of each row over them bounds the row for the whole database.
-        const int ns1 = S / kDN;
-        e = pass(S, ns1, nullptr);
+    const int S = knn_sample_cols(N);
+    if (S) {
+        // Group minima of the first S entries (no distances written), then the seeds.
+        if (fp8)
+            e = launch_dist_fp8(M, S, K, q, qs, qn, x, xs, xn, nullptr, 0, gmin, s);
+        else
+            e = launch_dist_bf16(M, S, K, static_cast<const uint16_t *>(Q), qn,
+                                 static_cast<const uint16_t *>(X), xn, nullptr, 0, gmin, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(knn_merge_kernel, dim3((unsigned)M), dim3(kMergeThreads), 0, s, k, mt,
-                           ns1, lists, cnt, bound, nullptr, nullptr, seed);
+        hipLaunchKernelGGL(knn_seed_kernel, dim3((unsigned)((M + 3) / 4)), dim3(256), 0, s, M,
+                           S / 16, k, gmin, seed);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        sd = seed;
+        if (fp8)
+            e = knn_pass<true, false, false>(M, N, K, k, nsplit, q, qs, qn, x, xs, xn, seed,
+                                             lists, cnt, bound, s);
+        else if (tail)
+            e = knn_pass<false, true, false>(M, N, K, k, nsplit, q, nullptr, qn, x, nullptr, xn,
+                                             seed, lists, cnt, bound, s);
+        else
+            e = knn_pass<false, false, false>(M, N, K, k, nsplit, q, nullptr, qn, x, nullptr, xn,
+                                              seed, lists, cnt, bound, s);
+    } else {
+        if (fp8)
+            e = knn_pass<true, false, true>(M, N, K, k, nsplit, q, qs, qn, x, xs, xn, nullptr,
+                                            lists, cnt, bound, s);
+        else if (tail)
+            e = knn_pass<false, true, true>(M, N, K, k, nsplit, q, nullptr, qn, x, nullptr, xn,
+                                            nullptr, lists, cnt, bound, s);
+        else
+            e = knn_pass<false, false, true>(M, N, K, k, nsplit, q, nullptr, qn, x, nullptr, xn,
+                                             nullptr, lists, cnt, bound, s);
     }
-    e = pass(N, nsplit, sd);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(knn_merge_kernel, dim3((unsigned)M), dim3(kMergeThreads), 0, s, k, mt,
-                       nsplit, lists, cnt, bound, idx, d, nullptr);
+                       nsplit, lists, cnt, bound, idx, d);
     e = hipGetLastError();
     if (e != hipSuccess || !direct) return e;
     const int64_t pairs = (int64_t)M * k;

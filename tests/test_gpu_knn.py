@@ -40,6 +40,9 @@ def _check_equal(Q, X, k):
     (0, 300, 50_021, 64, (1, 100)),              # many tiles per split, lists compacted
     (1, 9, 50_021, 64, (10, 256)),
     (0, 3, 150, 32, (1, 150)),                   # one partial tile: k = N
+    (0, 5, 40_000, 48, (7, 100)),                # sampled bound, K with a partial slice
+    (1, 130, 32_767, 64, (100,)),                # just below the sample size: own bounds
+    (1, 130, 32_768, 64, (100, 256)),            # smallest database with the sampled bound
 ])
 def test_knn_equals_distances_then_topk(fmt, M, N, dim, ks):
     need_gpu()
@@ -57,14 +60,14 @@ def test_knn_equals_distances_then_topk(fmt, M, N, dim, ks):
     assert np.array_equal(i1.cpu().numpy(), want)
 
 
-@pytest.mark.parametrize("fmt", [0, 1])
-def test_knn_all_distances_equal(fmt):
+@pytest.mark.parametrize("fmt,N", [(0, 20_000), (1, 20_000), (0, 40_000), (1, 40_000)])
+def test_knn_all_distances_equal(fmt, N):
     """Every database row identical: every distance of a query row ties, so each list's
-    bound must fall back to the exact k-th entry; the lowest indices win."""
+    bound must fall back to the exact k-th entry; the lowest indices win. At 40,000 the
+    sampled bound (the sample's k-th group minimum) admits every entry."""
     need_gpu()
     from paper_2205_04550_amd import binding as b
     g = torch.Generator(device="cuda").manual_seed(5)
-    N = 20_000
     Xf = torch.randn(1, 64, generator=g, device="cuda").repeat(N, 1)
     Qf = torch.randn(6, 64, generator=g, device="cuda")
     Q, X = b.Latents(Qf, fmt), b.Latents(Xf, fmt)
