@@ -436,13 +436,16 @@ def cpu_baseline_embed(model, X, labels, gen, n, n_cand, k, target_s: float):
     import oracle
     from oracle import encoder as E
     threads = oracle._threads()
-    params = {k2: p.detach().to("cpu", torch.float64) for k2, p in model.params.items()}
+    # The encoder as the GPU runs it: bfloat16 working weights, float biases, activations
+    # stored as bfloat16 between the convolutions.
+    params = {k2: (model.work[k2] if k2 in model.work else p).detach().to("cpu", torch.float64)
+              for k2, p in model.params.items()}
     xlat = E.bf16_decode(X.codes.view(torch.int16).cpu().numpy())
     t0 = time.perf_counter()
     done = 0
     while time.perf_counter() - t0 < target_s or done == 0:
         lab = labels[done % len(labels)]
-        z = E.encode(params, torch.from_numpy(E.meanpool(lab[None]))).numpy()
+        z = E.encode_bf16_activations(params, torch.from_numpy(E.meanpool(lab[None]))).numpy()
         d = E.sqdist_direct(z, xlat)[0]
         cand = E.topk_by_distance(d[None], n_cand)[0]
         _, cnt, sc = oracle.scan(gen, n, lab, synth_t()[0], synth_t()[1], indices=cand.tolist(),
@@ -500,6 +503,17 @@ def encoder_forward_flop(model, nq: int) -> float:
     return 2.0 * macs * nq
 
 
+def encode_stage_bytes(model, gen, nq: int) -> float:
+    """HBM bytes of the embedding step's encode stage for nq queries (BF16 forward): labels
+    read twice (first layer, query packing), the packed masks written, each convolution's
+    output written and read once (bfloat16; the last one float), the latents written."""
+    g, c = model.grid, model.channels
+    per = 2 * gen.nvox + 2 * gen.nvox // 8
+    per += sum(2 * 2 * (g >> (i + 1)) ** 3 * c[i + 1] for i in range(3))
+    per += 2 * 4 * (g >> 4) ** 3 * c[4] + 4 * model.latent
+    return float(per) * nq
+
+
 def embed_run(args, db, gen, n, with_variants: bool) -> dict:
     """Held-out queries through the encoder, the fused latent search (distances + top-100 in
     one pass) and the exact rerank. Returns the measurements as a dict."""
@@ -518,10 +532,10 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
     log(f"trained in {train_s:.1f} s, loss {losses[0]:.5f} -> {losses[-1]:.5f}")
     t0 = time.perf_counter()
     lat = torch.empty((n, model.latent), dtype=torch.float32, device="cuda")
-    with torch.no_grad():
-        for s in range(0, n, 500):
-            idx = torch.arange(s, min(n, s + 500), dtype=torch.int32, device="cuda")
-            lat[s:s + idx.numel()] = model.encode(nn.meanpool_db(db, idx))
+    dims = (gen.nx, gen.ny, gen.nz)
+    for s in range(0, n, 500):
+        idx = torch.arange(s, min(n, s + 500), dtype=torch.int32, device="cuda")
+        lat[s:s + idx.numel()] = model.encode_planes_bf16(db.planes, dims, idx)
     X = B.Latents(lat, B.EMB_BF16)
     torch.cuda.synchronize()
     encode_db_s = time.perf_counter() - t0
@@ -559,13 +573,13 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
     def step(timed: bool):
         if timed:
             ev[0].record()
-        h1 = model.first_layer_labels(lab_d)
+        h1 = model.first_layer_labels_bf16(lab_d)
         side.wait_stream(torch.cuda.current_stream())    # after the first layer (and the
         with torch.cuda.stream(side):                    # previous step's use of ws_rr)
             db.rerank_pack(lab_d, ws_rr)
         packed = torch.cuda.Event()
         packed.record(side)
-        ql = model.encode_after_first(h1)
+        ql = model.encode_after_first_bf16(h1)
         Q = B.Latents(ql, B.EMB_BF16)
         if timed:
             ev[1].record()
@@ -608,6 +622,7 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
         log(f"cpu oracle {cpu['value']:.3f} queries/s on {cpu['cores']} threads")
     gemm_flop = 2.0 * nq * n * model.latent
     enc_flop = encoder_forward_flop(model, nq)
+    enc_bytes = encode_stage_bytes(model, gen, nq)
     names = ["encode + pack queries (two streams)",
              "latent distances + top-100 in one pass (BF16 MFMA), direct-form candidate distances",
              "exact rerank"]
@@ -636,13 +651,15 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
                      "note": "the longest single launch of the step; bytes = database rows inside "
                              "(query row box n candidate row box), both masks"},
         "encode_stage_roofline": {
-            "bound": "mfma", "achieved": enc_flop / (stage[0] * 1e-3) / 1e12,
-            "peak": FP32_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
-            "frac": enc_flop / (stage[0] * 1e-3) / FP32_MFMA_PEAK,
-            "algorithmic_flop": enc_flop, "stage_ms": stage[0],
-            "note": "the encoder's forward FLOP over the whole stage (five kernels, with the query "
-                    "packing on a second stream beside them) against the FP32 matrix peak; the "
-                    "first layer runs on the BF16 matrix cores"},
+            "bound": "hbm", "achieved": enc_bytes / (stage[0] * 1e-3) / 1e9,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": enc_bytes / (stage[0] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "algorithmic_bytes": enc_bytes, "stage_ms": stage[0],
+            "encoder_flop": enc_flop, "encoder_tflops": enc_flop / (stage[0] * 1e-3) / 1e12,
+            "note": "the stage's HBM bytes: the labels read by the first layer and by the query "
+                    "packing (second stream), the packed masks written, each layer's bfloat16 "
+                    "activations written once and read once, the last layer's float output; the "
+                    "convolutions run on the BF16 matrix cores, the linear head on the FP32 ones"},
         "latent_search": {"bound": "mfma", "achieved_tflops": gemm_flop / (stage[1] * 1e-3) / 1e12,
                           "peak_tflops": BF16_MFMA_PEAK / 1e12,
                           "frac": gemm_flop / (stage[1] * 1e-3) / BF16_MFMA_PEAK,
@@ -665,6 +682,7 @@ def embed_variants(args, db, gen, n, model, lat, lab_d, ex, Dbuf_shape) -> dict:
 
     from paper_2205_04550_amd import binding as B, nn
     nq, n_cand, k = args.embed_nq, 100, 15
+    dims = (gen.nx, gen.ny, gen.nz)
     Dbuf = torch.empty(Dbuf_shape, dtype=torch.float32, device="cuda")
 
     def leg(name, fmt, encode_q, Xl):
@@ -691,7 +709,7 @@ def embed_variants(args, db, gen, n, model, lat, lab_d, ex, Dbuf_shape) -> dict:
 
     def enc_fp8():
         with torch.no_grad():
-            return B.Latents(model.encode_labels(lab_d), B.EMB_FP8)
+            return B.Latents(model.encode_labels_bf16(lab_d), B.EMB_FP8)
     variants["fp8_latents"] = leg("FP8 latents", B.EMB_FP8, enc_fp8, X8)
     del X8
     log(f"training the hashing encoder (Bi-half layer) for {args.train_steps} steps of 32")
@@ -703,12 +721,12 @@ def embed_variants(args, db, gen, n, model, lat, lab_d, ex, Dbuf_shape) -> dict:
     with torch.no_grad():
         for s0 in range(0, n, 500):
             idx_b = torch.arange(s0, min(n, s0 + 500), dtype=torch.int32, device="cuda")
-            lat[s0:s0 + idx_b.numel()] = model_h.encode(nn.meanpool_db(db, idx_b))
+            lat[s0:s0 + idx_b.numel()] = model_h.encode_planes_bf16(db.planes, dims, idx_b)
     Xh = B.BinaryCodes(lat)
 
     def enc_hash():
         with torch.no_grad():
-            return B.BinaryCodes(model_h.encode_labels(lab_d), Xh.thr)
+            return B.BinaryCodes(model_h.encode_labels_bf16(lab_d), Xh.thr)
     variants["bf_hash_512bit"] = leg("Bi-half codes (Hamming)", B.EMB_BIN, enc_hash, Xh)
     variants["bf_hash_512bit"].update({"train_s": hash_train_s, "gamma": HASH_GAMMA,
                                        "train_loss_first_last": [losses_h[0], losses_h[-1]]})
@@ -728,7 +746,8 @@ def embed_variants(args, db, gen, n, model, lat, lab_d, ex, Dbuf_shape) -> dict:
             with torch.no_grad():
                 for s0 in range(0, n, 500):
                     idx_b = torch.arange(s0, min(n, s0 + 500), dtype=torch.int32, device="cuda")
-                    lat[s0:s0 + idx_b.numel()] = mdl.encode(nn.meanpool_db(db, idx_b, mask=m))
+                    lat[s0:s0 + idx_b.numel()] = mdl.encode_planes_bf16(db.planes, dims, idx_b,
+                                                                        mask=m)
             Xs.append(B.Latents(lat, B.EMB_BF16))
             pair.append((mdl, m))
         torch.cuda.synchronize()
@@ -736,7 +755,7 @@ def embed_variants(args, db, gen, n, model, lat, lab_d, ex, Dbuf_shape) -> dict:
 
         def step_pair():
             with torch.no_grad():
-                qs = [B.Latents(mdl.encode_labels(lab_d, mask=m), B.EMB_BF16)
+                qs = [B.Latents(mdl.encode_labels_bf16(lab_d, mask=m), B.EMB_BF16)
                       for mdl, m in pair]
             D = B.emb_distances_l2sum(qs[0], Xs[0], qs[1], Xs[1], out=Dbuf)
             ci2, _ = B.emb_topk_min(D, n_cand)
@@ -809,7 +828,8 @@ def bench_embed500k(args, db, gen, n, build_s, n_big: int = 500_000) -> int:
         with torch.no_grad():
             for b0 in range(0, c, 512):
                 idx = torch.arange(b0, min(c, b0 + 512), dtype=torch.int32, device="cuda")
-                lat[s0 + b0:s0 + b0 + idx.numel()] = model.encode(nn.meanpool_db(part, idx))
+                lat[s0 + b0:s0 + b0 + idx.numel()] = model.encode_planes_bf16(
+                    part.planes, (gen.nx, gen.ny, gen.nz), idx)
         del part
         if (s0 // chunk) % 40 == 0:
             log(f"  {s0 + c}/{n_big}")
@@ -824,8 +844,7 @@ def bench_embed500k(args, db, gen, n, build_s, n_big: int = 500_000) -> int:
     labels, _ = synth.make_queries(gen, n, nq, synth.HELDOUT_SEED, held_out_seed=synth.HELDOUT_SEED)
     lab_d = torch.from_numpy(labels).cuda()
     del labels
-    with torch.no_grad():
-        ql = model.encode_labels(lab_d)
+    ql = model.encode_labels_bf16(lab_d)
     Q8, Q16 = B.Latents(ql, B.EMB_FP8), B.Latents(ql, B.EMB_BF16)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     kws = B.knn_workspace(nq, n_big, n_cand)

@@ -87,6 +87,43 @@ int nn_pool_conv_planes(const uint32_t *planes, int64_t sample_words, const int3
                         int nx, int ny, int nz, int mask, int Co, const void *Wt,
                         const float *bias, int relu, float *Y, void *stream);
 
+/* ---- BF16 inference forward -------------------------------------------------
+ * The encoder's forward for inference with bfloat16 activations stored
+ * channels-last. Each layer's output is the FP32 result (BF16 x BF16 products,
+ * exact in FP32, summed in FP32, plus bias, ReLU) rounded to the nearest
+ * bfloat16 (ties to even); the last convolution may write float instead, in
+ * the [B][Co][D][H][W] order the linear head flattens. This is a different
+ * numerics contract from the float path (nn_pool_conv_labels,
+ * nn_conv3d_s2_fwd): a layer's output equals the float64 result of the same
+ * bfloat16 inputs and weights, rounded to bfloat16, except where the FP32 sum
+ * and the exact value round to neighbouring bfloat16 values. */
+
+/* nn_pool_conv_labels writing Y as bfloat16 channels-last [B][nz/4][ny/4][nx/4][Co]
+ * (device, 8-byte aligned); also needs Co % 4 == 0. Same arguments otherwise. */
+int nn_pool_conv_labels_bf16(const uint8_t *labels, int B, int nx, int ny, int nz, int mask,
+                             int Co, const void *Wt, const float *bias, int relu, void *Y,
+                             void *stream);
+/* nn_pool_conv_planes with the output of nn_pool_conv_labels_bf16 (bit for bit the same
+ * for the labels that packed to these masks). */
+int nn_pool_conv_planes_bf16(const uint32_t *planes, int64_t sample_words, const int32_t *idx,
+                             int B, int nx, int ny, int nz, int mask, int Co, const void *Wt,
+                             const float *bias, int relu, void *Y, void *stream);
+/* Tap-major copy of bfloat16 convolution weights for nn_conv3d_s2_fwd_bf16:
+ * out[co][t][ci] = Wt[co][ci][t] for the 27 taps t (kd, kh, kw order) and 0 for
+ * t = 27; out holds Co * 28 * Ci bfloat16 values (device). */
+int nn_conv3d_weights_tapmajor(const void *Wt, int Co, int Ci, void *out, void *stream);
+/* Y = act(conv(X) + bias), stride 2, padding 1, kernel 3, on the BF16 matrix
+ * cores. X bfloat16 channels-last [B][D][H][W][Ci] (16-byte aligned); Wtm the
+ * tap-major weights of nn_conv3d_weights_tapmajor (16-byte aligned); bias float
+ * [Co] or NULL; Y bfloat16 channels-last [B][D/2][H/2][W/2][Co], or with
+ * out_f32 float [B][Co][D/2][H/2][W/2] (8-byte aligned). (Ci, Co) one of
+ * (8, 16), (16, 32), (32, 64), whose output boxes per block are 2 x 4 x 16,
+ * 4 x 4 x 8 and 4 x 4 x 4: D/2, H/2, W/2 must be multiples of them;
+ * B <= 65535. DB_EINVAL otherwise. */
+int nn_conv3d_s2_fwd_bf16(int B, int Ci, int Co, int D, int H, int W, const void *X,
+                          const void *Wtm, const float *bias, int relu, int out_f32, void *Y,
+                          void *stream);
+
 /* Y = act(conv(X)) with X [B][Ci][D][H][W], Y [B][Co][D/2][H/2][W/2];
  * bias [Co] or NULL; relu != 0 applies max(0, .). */
 int nn_conv3d_s2_fwd(int dtype, int B, int Ci, int Co, int D, int H, int W, const void *X,

@@ -51,6 +51,25 @@ def encode(params: dict, x: torch.Tensor) -> torch.Tensor:
     return F.linear(h.reshape(h.shape[0], -1), params["enc_fc.w"], params["enc_fc.b"])
 
 
+def round_bf16(t: torch.Tensor) -> torch.Tensor:
+    """The bfloat16 storage of a layer output: each value rounded to float32 (nearest, ties
+    to even), then to bfloat16 (nearest, ties to even), returned as float64."""
+    a = np.asarray(t.detach().cpu().numpy(), dtype=np.float64).astype(np.float32)
+    return torch.from_numpy(bf16_decode(bf16_encode(a)).reshape(a.shape))
+
+
+def encode_bf16_activations(params: dict, x: torch.Tensor) -> torch.Tensor:
+    """encode with bfloat16 activation storage between the convolutions: the output of each
+    of the first three convolutions (after bias and ReLU) is rounded by round_bf16 before the
+    next layer reads it; the last convolution and the linear layer are as in encode."""
+    h = x
+    for i in range(4):
+        h = conv(h, params[f"enc{i}.w"], params[f"enc{i}.b"], True)
+        if i < 3:
+            h = round_bf16(h)
+    return F.linear(h.reshape(h.shape[0], -1), params["enc_fc.w"], params["enc_fc.b"])
+
+
 def decode(params: dict, z: torch.Tensor, channels: int, s: int) -> torch.Tensor:
     """Linear (ReLU), reshape to [channels][s][s][s], four transposed convolutions (ReLU but the last)."""
     h = torch.relu(F.linear(z, params["dec_fc.w"], params["dec_fc.b"]))

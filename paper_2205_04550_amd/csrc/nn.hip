@@ -964,7 +964,9 @@ __global__ void __launch_bounds__(256) meanpool_labels_fast_kernel(const uint8_t
 // rows (Co <= 16). XCD-aware: the tiles one XCD receives are neighbours, so the
 // pooled halo rows they share come from its L2.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 constexpr int kPlRow = 68;
+
 
 __device__ __forceinline__ uint32_t pooled_word(uint32_t f, uint32_t h, int e)
 {
@@ -998,7 +1000,11 @@ __device__ __forceinline__ uint32_t pair_counts4(uint32_t x16)
 // FLAIR, plane 1 T1Gd, sample_words = 2 Wp per sample, sample b at
 // planes + (idx ? idx[b] : b) * sample_words) instead of as label bytes: a
 // pooled row is 4 x 16 bits per mask instead of 4 x 16 bytes.
-template <bool PLANES>
+//
+// OUTBF: Y is bfloat16 channels-last [B][nz/4][ny/4][nx/4][Co] (round to nearest even of the
+// FP32 result; Co % 4 == 0), the activation layout of the BF16 forward below; otherwise float
+// [B][Co][nz/4][ny/4][nx/4].
+template <bool PLANES, bool OUTBF>
 __global__ void __launch_bounds__(256) pool_conv_labels_kernel(const uint8_t *__restrict__ lab,
                                                                const uint32_t *__restrict__ planes,
                                                                int64_t sample_words,
@@ -1007,7 +1013,7 @@ __global__ void __launch_bounds__(256) pool_conv_labels_kernel(const uint8_t *__
                                                                int Ci, int Co, int npb,
                                                                const uint16_t *__restrict__ Wt,
                                                                const float *__restrict__ bias,
-                                                               int relu, float *__restrict__ Y)
+                                                               int relu, void *__restrict__ Yv)
 {
     __shared__ __attribute__((aligned(16))) uint32_t pl[45 * kPlRow];
     // PLANES: the raw mask words of the patch, [pooled row][label row q][mask][halo word,
@@ -1210,17 +1216,193 @@ __global__ void __launch_bounds__(256) pool_conv_labels_kernel(const uint8_t *__
             const int oz = od0 + z, oy = oh0 + y, ox = ow0 + x;
             if (oz >= OD || oy >= OH) continue;
             const int64_t o = ((int64_t)oz * OH + oy) * OW + ox;
+            float yv[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int co = 4 * g + r;
-                if (co < Co) {
-                    float yv = acc[r] + bco[r];
-                    if (relu && yv < 0.f) yv = 0.f;
-                    Y[((int64_t)b * Co + co) * osp + o] = yv;
+                yv[r] = acc[r] + bco[r];
+                if (relu && yv[r] < 0.f) yv[r] = 0.f;
+            }
+            if constexpr (OUTBF) {
+                if (4 * g < Co) {                  // four channels, one 8-byte store
+                    uint16_t *Y = static_cast<uint16_t *>(Yv);
+                    const uint32_t lo = f32_to_bf16_rne(yv[0]) | ((uint32_t)f32_to_bf16_rne(yv[1]) << 16);
+                    const uint32_t hi = f32_to_bf16_rne(yv[2]) | ((uint32_t)f32_to_bf16_rne(yv[3]) << 16);
+                    *reinterpret_cast<u32x2 *>(&Y[((int64_t)b * osp + o) * Co + 4 * g]) =
+                        (u32x2){lo, hi};
                 }
+            } else {
+                float *Y = static_cast<float *>(Yv);
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (4 * g + r < Co) Y[((int64_t)b * Co + 4 * g + r) * osp + o] = yv[r];
             }
         }
         __syncthreads();                           // the next tile overwrites pl
+    }
+}
+
+// ---- BF16 forward (inference) -----------------------------------------------------------
+//
+// The later encoder convolutions with bfloat16 activations. X is channels-last bfloat16
+// [B][D][H][W][CI]; Y is channels-last bfloat16 [B][D/2][H/2][W/2][CO] (round to nearest even
+// of the FP32 result) or, OUTF32, float [B][CO][D/2][H/2][W/2] (the flatten order of the
+// linear head). An implicit GEMM on the BF16 matrix cores,
+// Y[co][v] = sum over (tap, ci) of Wtm[co][tap][ci] X[2 v + tap - 1][ci], with the tap-major
+// weights of conv_w_tapmajor_kernel (28 taps, the last zero). One 16 x 16 x 32 product takes
+// four groups of eight channels: in step s, lane quarter q gives group kg = 4 s + q (tap
+// kg / NG, channels 8 (kg % NG) .. + 7); rows are 16 output channels, columns 16 output
+// voxels. Each product of two bfloat16 values is exact in FP32; the sums are FP32. A block
+// takes a TD x TH x TW box of output voxels of one sample (four waves; a wave owns MV voxel
+// tiles and MC channel tiles) and stages the input patch in LDS split by x parity, so the
+// taps of consecutive output x read consecutive voxels of one parity. The channel groups of
+// a patch voxel are rotated by its row (group g stored at g ^ ((py / 2) % NG)), so the rows
+// one voxel tile spans fall on different LDS banks.
+template <int CI, int CO, int TD, int TH, int TW, bool OUTF32>
+__global__ void __launch_bounds__(256, 4) conv_bf16_kernel(int D, int H, int W, int tiles_h,
+                                                           int tiles_w, int T, int npb,
+                                                           const uint16_t *__restrict__ X,
+                                                           const uint16_t *__restrict__ Wtm,
+                                                           const float *__restrict__ bias,
+                                                           int relu, void *__restrict__ Yv)
+{
+    constexpr int NG = CI / 8, S = 7 * NG;
+    constexpr int NVT = TD * TH * TW / 16, NCO = CO / 16;
+    constexpr int WCO = NCO < 4 ? NCO : 4, WVT = 4 / WCO;
+    constexpr int MV = NVT / WVT, MC = NCO / WCO;
+    constexpr int PD = 2 * TD + 1, PH = 2 * TH + 1, PW = 2 * TW + 1, HW2 = TW + 1;
+    constexpr int NCH = PD * PH * PW * NG;                 // 16-byte chunks of the patch
+    constexpr int NIT = (NCH + 255) / 256;
+    static_assert(CI % 8 == 0 && (NG & (NG - 1)) == 0 && CO % 16 == 0, "channels");
+    static_assert((TD * TH * TW) % 16 == 0 && NVT % WVT == 0 && NCO % WCO == 0, "tile");
+    __shared__ __attribute__((aligned(16))) uint16_t xs[PD * PH * 2 * HW2 * CI];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4, j = lane & 15;
+    const int OD = D / 2, OH = H / 2, OW = W / 2;
+    const int per = (OD / TD) * tiles_h * tiles_w;         // tiles per sample
+    // This block's npb consecutive tiles (numbered over all samples, T in all); the next
+    // tile's patch is loaded into registers while the current one is multiplied.
+    const int t0 = blockIdx.x * npb;
+    u32x4 v[NIT];
+    auto load = [&](int gt) {
+        const int b = gt / per, t = gt - b * per;
+        const uint16_t *Xb = X + (int64_t)b * D * H * W * CI;
+        const int tw = t % tiles_w, th = (t / tiles_w) % tiles_h, td = t / (tiles_w * tiles_h);
+        const int iz0 = 2 * td * TD - 1, iy0 = 2 * th * TH - 1, ix0 = 2 * tw * TW - 1;
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+            const int e = i * 256 + tid;
+            const int g = e % NG, r = e / NG;
+            const int px = r % PW, py = (r / PW) % PH, pz = r / (PW * PH);
+            const int iz = iz0 + pz, iy = iy0 + py, ix = ix0 + px;
+            v[i] = (u32x4){0u, 0u, 0u, 0u};
+            if (e < NCH && (unsigned)iz < (unsigned)D && (unsigned)iy < (unsigned)H &&
+                (unsigned)ix < (unsigned)W)
+                v[i] = *reinterpret_cast<const u32x4 *>(
+                    Xb + (((int64_t)iz * H + iy) * W + ix) * CI + 8 * g);
+        }
+    };
+    // The lane's voxel of each of its voxel tiles: the slot of its tap (0, 0, 0) and its
+    // output row within the tile (the patch row of tap kh is 2 oy + kh).
+    int vslot[MV], vrow[MV];
+#pragma unroll
+    for (int m = 0; m < MV; ++m) {
+        const int vv = (wave / WCO + m * WVT) * 16 + j;
+        const int oz = vv / (TH * TW), oy = (vv / TW) % TH, ox = vv % TW;
+        vslot[m] = (2 * oz * PH + 2 * oy) * 2 * HW2 + ox;
+        vrow[m] = oy;
+    }
+    const uint16_t *wl = Wtm + (int64_t)((wave % WCO) * 16 + j) * 28 * CI + 8 * q;
+    const int64_t osp = (int64_t)OD * OH * OW;
+    if (t0 < T) load(t0);
+    for (int n = 0; n < npb; ++n) {
+        const int gt = t0 + n;
+        if (gt >= T) break;                                 // uniform over the block
+        const int b = gt / per, t = gt - b * per;
+        // The patch into LDS (zeros outside the volume), split by x parity.
+#pragma unroll
+        for (int i = 0; i < NIT; ++i) {
+            const int e = i * 256 + tid;
+            if (e < NCH) {
+                const int g = e % NG, r = e / NG;
+                const int px = r % PW, py = (r / PW) % PH, pz = r / (PW * PH);
+                const int slot = ((pz * PH + py) * 2 + (px & 1)) * HW2 + (px >> 1);
+                *reinterpret_cast<u32x4 *>(&xs[slot * CI + 8 * (g ^ ((py >> 1) & (NG - 1)))]) =
+                    v[i];
+            }
+        }
+        __syncthreads();
+        if (n + 1 < npb && gt + 1 < T) load(gt + 1);
+        f32x4 acc[MV][MC];
+#pragma unroll
+        for (int m = 0; m < MV; ++m)
+#pragma unroll
+            for (int c = 0; c < MC; ++c) acc[m][c] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int st = 0; st < S; ++st) {
+            const int kg = 4 * st + q, tap = kg / NG, g = kg % NG;
+            const int tp = tap < 27 ? tap : 0;              // tap 27: zero weights
+            const int kd = tp / 9, kh = (tp / 3) % 3, kw = tp % 3;
+            const int toff = ((kd * PH + kh) * 2 + (kw & 1)) * HW2 + (kw >> 1);
+            bf16x8 a[MC];
+#pragma unroll
+            for (int c = 0; c < MC; ++c)
+                a[c] = *reinterpret_cast<const bf16x8 *>(wl + (int64_t)c * WCO * 16 * 28 * CI +
+                                                         32 * st);
+#pragma unroll
+            for (int m = 0; m < MV; ++m) {
+                const int off =
+                    (vslot[m] + toff) * CI + 8 * (g ^ ((vrow[m] + (kh >> 1)) & (NG - 1)));
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&xs[off]);
+#pragma unroll
+                for (int c = 0; c < MC; ++c)
+                    acc[m][c] =
+                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[c], bv, acc[m][c], 0, 0, 0);
+            }
+        }
+        const int tw = t % tiles_w, th = (t / tiles_w) % tiles_h, td = t / (tiles_w * tiles_h);
+#pragma unroll
+        for (int m = 0; m < MV; ++m) {
+            const int vv = (wave / WCO + m * WVT) * 16 + j;
+            const int oz = td * TD + vv / (TH * TW), oy = th * TH + (vv / TW) % TH;
+            const int ox = tw * TW + vv % TW;
+            const int64_t o = ((int64_t)oz * OH + oy) * OW + ox;
+#pragma unroll
+            for (int c = 0; c < MC; ++c) {
+                const int co0 = (wave % WCO + c * WCO) * 16 + 4 * q;
+                float y[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    y[r] = acc[m][c][r] + (bias ? bias[co0 + r] : 0.f);
+                    if (relu && y[r] < 0.f) y[r] = 0.f;
+                }
+                if constexpr (OUTF32) {
+                    float *Y = static_cast<float *>(Yv);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Y[((int64_t)b * CO + co0 + r) * osp + o] = y[r];
+                } else {
+                    uint16_t *Y = static_cast<uint16_t *>(Yv);
+                    const uint32_t lo =
+                        f32_to_bf16_rne(y[0]) | ((uint32_t)f32_to_bf16_rne(y[1]) << 16);
+                    const uint32_t hi =
+                        f32_to_bf16_rne(y[2]) | ((uint32_t)f32_to_bf16_rne(y[3]) << 16);
+                    *reinterpret_cast<u32x2 *>(&Y[((int64_t)b * osp + o) * CO + co0]) =
+                        (u32x2){lo, hi};
+                }
+            }
+        }
+        __syncthreads();                                    // the next patch overwrites xs
+    }
+}
+
+// Tap-major copy of convolution weights for conv_bf16_kernel: out[co][t][ci] = w[co][ci][t]
+// (t < 27; the model's [co][ci][kd][kh][kw] order) and 0 for t = 27.
+__global__ void conv_w_tapmajor_kernel(int Co, int Ci, const uint16_t *__restrict__ w,
+                                       uint16_t *__restrict__ out)
+{
+    const int64_t n = (int64_t)Co * 28 * Ci;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int ci = (int)(e % Ci), tp = (int)((e / Ci) % 28), co = (int)(e / ((int64_t)28 * Ci));
+        out[e] = tp < 27 ? w[((int64_t)co * Ci + ci) * 27 + tp] : (uint16_t)0;
     }
 }
 
@@ -1456,7 +1638,7 @@ int nn_pool_conv_labels(const uint8_t *labels, int B, int nx, int ny, int nz, in
         return tdb_set_error(DB_EINVAL, "nn_pool_conv_labels: bad arguments");
     const int T = (nx / 128) * ((ny / 4 + 3) / 4) * ((nz / 4 + 1) / 2);
     const int npb = T % 32 == 0 ? 4 : 1;           // tiles per block
-    hipLaunchKernelGGL(pool_conv_labels_kernel<false>, dim3((unsigned)((T + npb - 1) / npb), (unsigned)B),
+    hipLaunchKernelGGL((pool_conv_labels_kernel<false, false>), dim3((unsigned)((T + npb - 1) / npb), (unsigned)B),
                        dim3(256), 0, static_cast<hipStream_t>(stream), labels, nullptr, (int64_t)0,
                        nullptr, nx, ny, nz, mask, mask < 0 ? 2 : 1, Co, npb,
                        static_cast<const uint16_t *>(Wt), bias, relu, Y);
@@ -1474,11 +1656,98 @@ int nn_pool_conv_planes(const uint32_t *planes, int64_t sample_words, const int3
         return tdb_set_error(DB_EINVAL, "nn_pool_conv_planes: bad arguments");
     const int T = (nx / 128) * ((ny / 4 + 3) / 4) * ((nz / 4 + 1) / 2);
     const int npb = T % 32 == 0 ? 4 : 1;           // tiles per block
-    hipLaunchKernelGGL(pool_conv_labels_kernel<true>, dim3((unsigned)((T + npb - 1) / npb), (unsigned)B),
+    hipLaunchKernelGGL((pool_conv_labels_kernel<true, false>), dim3((unsigned)((T + npb - 1) / npb), (unsigned)B),
                        dim3(256), 0, static_cast<hipStream_t>(stream), nullptr, planes,
                        sample_words, idx, nx, ny, nz, mask, mask < 0 ? 2 : 1, Co, npb,
                        static_cast<const uint16_t *>(Wt), bias, relu, Y);
     return launched("nn_pool_conv_planes");
+}
+
+int nn_pool_conv_labels_bf16(const uint8_t *labels, int B, int nx, int ny, int nz, int mask,
+                             int Co, const void *Wt, const float *bias, int relu, void *Y,
+                             void *stream)
+{
+    if (!labels || !Wt || !Y || B <= 0 || B > 65535 || nx <= 0 || ny <= 0 || nz <= 0 ||
+        nx % 128 || ny % 4 || nz % 4 || Co <= 0 || Co > 16 || Co % 4 || mask < -1 || mask > 1 ||
+        (uintptr_t)labels % 16 || (uintptr_t)Y % 8 || (int64_t)nx * ny * nz >= ((int64_t)1 << 31))
+        return tdb_set_error(DB_EINVAL, "nn_pool_conv_labels_bf16: bad arguments");
+    const int T = (nx / 128) * ((ny / 4 + 3) / 4) * ((nz / 4 + 1) / 2);
+    const int npb = T % 32 == 0 ? 4 : 1;
+    hipLaunchKernelGGL((pool_conv_labels_kernel<false, true>),
+                       dim3((unsigned)((T + npb - 1) / npb), (unsigned)B), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), labels, nullptr, (int64_t)0, nullptr, nx,
+                       ny, nz, mask, mask < 0 ? 2 : 1, Co, npb, static_cast<const uint16_t *>(Wt),
+                       bias, relu, Y);
+    return launched("nn_pool_conv_labels_bf16");
+}
+
+int nn_pool_conv_planes_bf16(const uint32_t *planes, int64_t sample_words, const int32_t *idx,
+                             int B, int nx, int ny, int nz, int mask, int Co, const void *Wt,
+                             const float *bias, int relu, void *Y, void *stream)
+{
+    const int64_t words = (int64_t)nx * ny * nz / 32;
+    if (!planes || !Wt || !Y || B <= 0 || B > 65535 || nx <= 0 || ny <= 0 || nz <= 0 ||
+        nx % 128 || ny % 4 || nz % 4 || Co <= 0 || Co > 16 || Co % 4 || mask < -1 || mask > 1 ||
+        sample_words % 2 || sample_words / 2 < words || (uintptr_t)Y % 8 ||
+        (int64_t)nx * ny * nz >= ((int64_t)1 << 31))
+        return tdb_set_error(DB_EINVAL, "nn_pool_conv_planes_bf16: bad arguments");
+    const int T = (nx / 128) * ((ny / 4 + 3) / 4) * ((nz / 4 + 1) / 2);
+    const int npb = T % 32 == 0 ? 4 : 1;
+    hipLaunchKernelGGL((pool_conv_labels_kernel<true, true>),
+                       dim3((unsigned)((T + npb - 1) / npb), (unsigned)B), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), nullptr, planes, sample_words, idx, nx, ny,
+                       nz, mask, mask < 0 ? 2 : 1, Co, npb, static_cast<const uint16_t *>(Wt), bias,
+                       relu, Y);
+    return launched("nn_pool_conv_planes_bf16");
+}
+
+int nn_conv3d_weights_tapmajor(const void *Wt, int Co, int Ci, void *out, void *stream)
+{
+    if (!Wt || !out || Co <= 0 || Ci <= 0 || (int64_t)Co * Ci * 28 >= ((int64_t)1 << 31))
+        return tdb_set_error(DB_EINVAL, "nn_conv3d_weights_tapmajor: bad arguments");
+    const int64_t n = (int64_t)Co * 28 * Ci;
+    hipLaunchKernelGGL(conv_w_tapmajor_kernel, dim3(grid1(n, 4096)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), Co, Ci, static_cast<const uint16_t *>(Wt),
+                       static_cast<uint16_t *>(out));
+    return launched("nn_conv3d_weights_tapmajor");
+}
+
+int nn_conv3d_s2_fwd_bf16(int B, int Ci, int Co, int D, int H, int W, const void *X,
+                          const void *Wtm, const float *bias, int relu, int out_f32, void *Y,
+                          void *stream)
+{
+    // Output box per block for each supported (Ci, Co).
+    int TD = 0, TH = 0, TW = 0;
+    if (Ci == 8 && Co == 16) TD = 2, TH = 4, TW = 16;
+    else if (Ci == 16 && Co == 32) TD = 4, TH = 4, TW = 8;
+    else if (Ci == 32 && Co == 64) TD = 4, TH = 4, TW = 4;
+    if (!TD || !X || !Wtm || !Y || B <= 0 || B > 65535 || D <= 0 || H <= 0 || W <= 0 ||
+        D % (2 * TD) || H % (2 * TH) || W % (2 * TW) || (uintptr_t)X % 16 || (uintptr_t)Wtm % 16 ||
+        (uintptr_t)Y % 8 || (int64_t)D * H * W * Ci >= ((int64_t)1 << 31))
+        return tdb_set_error(DB_EINVAL, "nn_conv3d_s2_fwd_bf16: bad arguments");
+    const int th = H / 2 / TH, tw = W / 2 / TW;
+    const int64_t T = (int64_t)B * (D / 2 / TD) * th * tw;   // tiles over all samples
+    if (T >= ((int64_t)1 << 31)) return tdb_set_error(DB_EINVAL, "nn_conv3d_s2_fwd_bf16: too large");
+    // Tiles per block (the next one prefetched), while at least 2,048 blocks remain.
+    const int npb = (int)std::max<int64_t>(1, std::min<int64_t>(4, T / 2048));
+    const dim3 grid((unsigned)((T + npb - 1) / npb));
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const auto *x = static_cast<const uint16_t *>(X);
+    const auto *w = static_cast<const uint16_t *>(Wtm);
+#define TDB_CONV_BF16(CI_, CO_, TD_, TH_, TW_)                                                      \
+    do {                                                                                           \
+        if (out_f32)                                                                               \
+            hipLaunchKernelGGL((conv_bf16_kernel<CI_, CO_, TD_, TH_, TW_, true>), grid, dim3(256), \
+                               0, s, D, H, W, th, tw, (int)T, npb, x, w, bias, relu, Y);         \
+        else                                                                                       \
+            hipLaunchKernelGGL((conv_bf16_kernel<CI_, CO_, TD_, TH_, TW_, false>), grid,           \
+                               dim3(256), 0, s, D, H, W, th, tw, (int)T, npb, x, w, bias, relu, Y); \
+    } while (0)
+    if (Ci == 8) TDB_CONV_BF16(8, 16, 2, 4, 16);
+    else if (Ci == 16) TDB_CONV_BF16(16, 32, 4, 4, 8);
+    else TDB_CONV_BF16(32, 64, 4, 4, 4);
+#undef TDB_CONV_BF16
+    return launched("nn_conv3d_s2_fwd_bf16");
 }
 
 int nn_conv3d_s2_fwd(int dtype, int B, int Ci, int Co, int D, int H, int W, const void *X,

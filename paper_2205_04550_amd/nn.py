@@ -55,6 +55,12 @@ _SIGS = {
     "nn_vae_head_fwd": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "nn_vae_head_bwd": (_i32, [_i32, _i32, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]),
     "nn_bihalf_bwd": (_i32, [_i32, _i32, _i32, ctypes.c_double, _vp, _vp, _vp, _vp, _vp]),
+    "nn_pool_conv_labels_bf16": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _i32,
+                                        _vp, _vp]),
+    "nn_pool_conv_planes_bf16": (_i32, [_vp, _i64, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp,
+                                        _vp, _i32, _vp, _vp]),
+    "nn_conv3d_weights_tapmajor": (_i32, [_vp, _i32, _i32, _vp, _vp]),
+    "nn_conv3d_s2_fwd_bf16": (_i32, [_i32] * 6 + [_vp, _vp, _vp, _i32, _i32, _vp, _vp]),
 }
 for _n, (_r, _a) in _SIGS.items():
     _f = getattr(LIB, _n)
@@ -160,6 +166,75 @@ def pool_conv_planes(planes: torch.Tensor, dims, w_bf16: torch.Tensor, bias: tor
     _check(LIB.nn_pool_conv_planes(planes.data_ptr(), 2 * Wp, _p(idx), B, nx, ny, nz,
                                    -1 if mask is None else mask, Co, w_bf16.data_ptr(), _p(bias),
                                    int(relu), y.data_ptr(), _s()))
+    return y
+
+
+# ---- BF16 inference forward -----------------------------------------------------------------
+# Activations bfloat16 channels-last [B][D][H][W][C]; each layer rounds its FP32 result to the
+# nearest bfloat16. Forward only (no autograd).
+
+def pool_conv_labels_bf16(labels: torch.Tensor, w_bf16: torch.Tensor, bias: torch.Tensor | None,
+                          relu: bool = True, mask: int | None = None) -> torch.Tensor:
+    """pool_conv_labels with a bfloat16 channels-last output [B][nz/4][ny/4][nx/4][Co]."""
+    labels = _c(labels)
+    if labels.dim() == 3:
+        labels = labels[None]
+    B, nz, ny, nx = labels.shape
+    Co = w_bf16.shape[0]
+    assert w_bf16.dtype == torch.bfloat16 and w_bf16.shape[1] == (2 if mask is None else 1)
+    w_bf16 = _c(w_bf16)
+    bias = None if bias is None else _c(bias.detach())
+    y = torch.empty((B, nz // 4, ny // 4, nx // 4, Co), dtype=torch.bfloat16, device=labels.device)
+    _check(LIB.nn_pool_conv_labels_bf16(labels.data_ptr(), B, nx, ny, nz,
+                                        -1 if mask is None else mask, Co, w_bf16.data_ptr(),
+                                        _p(bias), int(relu), y.data_ptr(), _s()))
+    return y
+
+
+def pool_conv_planes_bf16(planes: torch.Tensor, dims, w_bf16: torch.Tensor,
+                          bias: torch.Tensor | None, relu: bool = True, mask: int | None = None,
+                          idx: torch.Tensor | None = None) -> torch.Tensor:
+    """pool_conv_planes with the output of pool_conv_labels_bf16."""
+    nx, ny, nz = dims
+    S, two, Wp = planes.shape
+    assert two == 2 and planes.is_contiguous()
+    B = S if idx is None else idx.numel()
+    Co = w_bf16.shape[0]
+    assert w_bf16.dtype == torch.bfloat16 and w_bf16.shape[1] == (2 if mask is None else 1)
+    w_bf16 = _c(w_bf16)
+    bias = None if bias is None else _c(bias.detach())
+    idx = None if idx is None else _c(idx.to(torch.int32))
+    y = torch.empty((B, nz // 4, ny // 4, nx // 4, Co), dtype=torch.bfloat16, device=planes.device)
+    _check(LIB.nn_pool_conv_planes_bf16(planes.data_ptr(), 2 * Wp, _p(idx), B, nx, ny, nz,
+                                        -1 if mask is None else mask, Co, w_bf16.data_ptr(),
+                                        _p(bias), int(relu), y.data_ptr(), _s()))
+    return y
+
+
+def conv_weights_tapmajor(w_bf16: torch.Tensor) -> torch.Tensor:
+    """[Co][Ci][3][3][3] bfloat16 -> [Co][28][Ci] (tap-major, tap 27 zero) for conv3d_bf16."""
+    assert w_bf16.dtype == torch.bfloat16
+    Co, Ci = w_bf16.shape[:2]
+    out = torch.empty((Co, 28, Ci), dtype=torch.bfloat16, device=w_bf16.device)
+    _check(LIB.nn_conv3d_weights_tapmajor(_c(w_bf16).data_ptr(), Co, Ci, out.data_ptr(), _s()))
+    return out
+
+
+def conv3d_bf16(x: torch.Tensor, w_tm: torch.Tensor, bias: torch.Tensor | None, relu: bool = True,
+                out_f32: bool = False) -> torch.Tensor:
+    """Stride-2 convolution of bfloat16 channels-last x [B][D][H][W][Ci] with tap-major weights
+    w_tm [Co][28][Ci]: bfloat16 [B][D/2][H/2][W/2][Co], or float [B][Co][D/2][H/2][W/2]."""
+    x = _c(x)
+    assert x.dtype == torch.bfloat16 and w_tm.dtype == torch.bfloat16
+    B, D, H, W, Ci = x.shape
+    Co = w_tm.shape[0]
+    bias = None if bias is None else _c(bias.detach())
+    if out_f32:
+        y = torch.empty((B, Co, D // 2, H // 2, W // 2), dtype=torch.float32, device=x.device)
+    else:
+        y = torch.empty((B, D // 2, H // 2, W // 2, Co), dtype=torch.bfloat16, device=x.device)
+    _check(LIB.nn_conv3d_s2_fwd_bf16(B, Ci, Co, D, H, W, x.data_ptr(), _c(w_tm).data_ptr(),
+                                     _p(bias), int(relu), int(out_f32), y.data_ptr(), _s()))
     return y
 
 
@@ -430,6 +505,9 @@ class AutoEncoder:
         for k in self.params:
             self.params[k] = self.params[k].to(device=device, dtype=dtype).requires_grad_(True)
         self.work = {}
+        # Version of the working weights (refresh_working_weights and every Adam step bump it),
+        # and the version the tap-major copies of the BF16 forward were made from.
+        self.work_version, self._tm_version, self.work_tm = 0, -1, {}
         self.refresh_working_weights()
 
     def refresh_working_weights(self) -> None:
@@ -445,6 +523,7 @@ class AutoEncoder:
                 _check(LIB.nn_to_bf16(p.numel(), p.data_ptr(), wb.data_ptr(), _s()))
             else:
                 self.work[k] = p.detach()
+        self.work_version += 1
 
     def _w(self, name):
         return self.params[name + ".w"], self.params[name + ".b"], self.work[name + ".w"]
@@ -497,6 +576,55 @@ class AutoEncoder:
                 w, b, wc = self._w(f"enc{i}")
                 h = Conv3dS2.apply(h, w, b, wc, True)
             return self._head(h.reshape(h.shape[0], -1))
+
+    # ---- BF16 inference forward: bfloat16 channels-last activations, each layer's FP32 result
+    # rounded to bfloat16 (a different numerics contract from encode; see conv3d_bf16).
+
+    def bf16_inference_ok(self, dims) -> bool:
+        """Whether the BF16 forward covers this model and mask grid (nx, ny, nz)."""
+        nx, ny, nz = dims
+        return (self.bf16 and tuple(self.channels[1:]) == (8, 16, 32, 64)
+                and nx % 128 == 0 and ny % 128 == 0 and nz % 128 == 0)
+
+    def first_layer_labels_bf16(self, labels: torch.Tensor, mask: int | None = None) -> torch.Tensor:
+        """The fused first layer from label bytes, bfloat16 channels-last output."""
+        with torch.no_grad():
+            w, b, wc = self._w("enc0")
+            return pool_conv_labels_bf16(labels, wc, b, True, mask)
+
+    def _tapmajor(self) -> dict:
+        """Tap-major copies of the later convolutions' working weights, remade whenever the
+        working weights changed (training updates them in place)."""
+        if self._tm_version != self.work_version:
+            self.work_tm = {f"enc{i}": conv_weights_tapmajor(self.work[f"enc{i}.w"])
+                            for i in range(1, 4)}
+            self._tm_version = self.work_version
+        return self.work_tm
+
+    def encode_after_first_bf16(self, h: torch.Tensor) -> torch.Tensor:
+        """The later convolutions on the BF16 matrix cores, then the head (float)."""
+        with torch.no_grad():
+            tm = self._tapmajor()
+            for i in range(1, 4):
+                w, b, wc = self._w(f"enc{i}")
+                h = conv3d_bf16(h, tm[f"enc{i}"], b, True, out_f32=(i == 3))
+            return self._head(h.reshape(h.shape[0], -1))
+
+    def encode_labels_bf16(self, labels: torch.Tensor, mask: int | None = None) -> torch.Tensor:
+        """Latents of query labels [B][nz][ny][nx] by the BF16 forward."""
+        nz, ny, nx = labels.shape[-3:]
+        assert self.bf16_inference_ok((nx, ny, nz))
+        return self.encode_after_first_bf16(self.first_layer_labels_bf16(labels, mask))
+
+    def encode_planes_bf16(self, planes: torch.Tensor, dims, idx: torch.Tensor | None = None,
+                           mask: int | None = None) -> torch.Tensor:
+        """encode_labels_bf16 from packed masks (the database's planes, or packed queries);
+        equal to it bit for bit for the labels that packed to these masks."""
+        assert self.bf16_inference_ok(dims)
+        with torch.no_grad():
+            w, b, wc = self._w("enc0")
+            h = pool_conv_planes_bf16(planes, dims, wc, b, True, mask, idx)
+        return self.encode_after_first_bf16(h)
 
     def _head(self, h: torch.Tensor) -> torch.Tensor:
         w, b, wc = self._w("enc_fc")
@@ -562,6 +690,7 @@ class Adam:
                                     p.grad.data_ptr(), _p(wb), self.lr, self.b1, self.b2, self.eps,
                                     self.t, _s()))
             p.grad = None
+        self.model.work_version += 1
 
 
 def train_step(model: AutoEncoder, opt: Adam, x: torch.Tensor) -> torch.Tensor:

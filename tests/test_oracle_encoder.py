@@ -110,6 +110,45 @@ def test_bf16_encode_pins():
     assert np.all(np.abs(d - x) <= np.abs(x) * 2.0 ** -8)
 
 
+def _delta_params(w0_centre: float, latent: int = 4):
+    """Encoder 2 -> 8 -> 16 -> 32 -> 64 whose convolutions copy channel co % Ci at the centre tap
+    (the first one scaled by w0_centre), zero biases, on a 16^3 input (flat = 64), and a head
+    that picks the first `latent` flattened values."""
+    chans = (2, 8, 16, 32, 64)
+    P = {}
+    for i in range(4):
+        ci, co = chans[i], chans[i + 1]
+        w = torch.zeros(co, ci, 3, 3, 3, dtype=torch.float64)
+        for c in range(co):
+            w[c, c % ci, 1, 1, 1] = w0_centre if i == 0 else 1.0
+        P[f"enc{i}.w"], P[f"enc{i}.b"] = w, torch.zeros(co, dtype=torch.float64)
+    P["enc_fc.w"] = torch.eye(latent, 64, dtype=torch.float64)
+    P["enc_fc.b"] = torch.zeros(latent, dtype=torch.float64)
+    return P
+
+
+def test_bf16_activation_rounding_and_forward_pins():
+    """round_bf16 on hand values (float32 first, then bfloat16 with ties to even), and
+    encode_bf16_activations against encode on networks whose activations are copies."""
+    v = torch.tensor([0.0, 1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -8 + 2 ** -20,
+                      -(1 + 2 ** -8 + 2 ** -20), 1 + 2 ** -8 + 2 ** -30, 3.0], dtype=torch.float64)
+    assert E.round_bf16(v).tolist() == [0.0, 1.0, 1.0, 1 + 2 ** -6, 1 + 2 ** -7,
+                                        -(1 + 2 ** -7), 1.0, 3.0]
+    # Copies of values k/8 (exact in bfloat16): the rounding changes nothing.
+    rng = np.random.default_rng(3)
+    x = torch.from_numpy(rng.integers(0, 9, (2, 2, 16, 16, 16)) / 8.0)
+    P = _delta_params(1.0)
+    z = E.encode_bf16_activations(P, x)
+    assert torch.equal(z, E.encode(P, x))
+    assert z[:, 0].tolist() == x[:, 0, 0, 0, 0].tolist() and z[:, 1].tolist() == x[:, 1, 0, 0, 0].tolist()
+    # A first layer that scales by 1 + 2^-8 + 2^-20: its output is stored rounded to
+    # 1 + 2^-7 (times the input), which the later copies carry to the latent.
+    x1 = torch.ones(1, 2, 16, 16, 16, dtype=torch.float64)
+    P = _delta_params(1 + 2 ** -8 + 2 ** -20)
+    assert E.encode_bf16_activations(P, x1)[0, 0].item() == 1 + 2 ** -7
+    assert E.encode(P, x1)[0, 0].item() == 1 + 2 ** -8 + 2 ** -20
+
+
 def test_hash_oracle_pins():
     """Thresholds, codes, Hamming distances and the Bi-half layer against hand values and
     the identities that tie them to the paper's L2 ranking of +-1 codes."""
