@@ -96,7 +96,8 @@ TRAFFIC_FILES = {
     "full": ("scan_full_traffic.json", SCAN_SOURCES),
     "embed500k": ("knn_fp8_500k_traffic.json", ("paper_2205_04550_amd/csrc/knn.hip",
                                                  "paper_2205_04550_amd/csrc/embed_core.hpp",
-                                                 "paper_2205_04550_amd/csrc/common.hpp")),
+                                                 "paper_2205_04550_amd/csrc/common.hpp",
+                                                 "paper_2205_04550_amd/csrc/embed.hip")),
 }
 
 
