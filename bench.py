@@ -427,6 +427,65 @@ def bench_train(args, db, gen, n, build_s) -> int:
     return 0
 
 
+def small_latency(db, qd, k, out, ws, reps: int = 50, flush_bytes: int = 1 << 30) -> dict:
+    """Single-query latency of the exact scan on a database that fits the caches: warm
+    (back to back), cold (after writing flush_bytes, which evicts the L2s and the 256 MB
+    Infinity Cache), and as one replay of a captured HIP graph (checked against the eager
+    result). Medians of per-query HIP event times, in microseconds."""
+    import numpy as np
+    import torch
+
+    cur = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(f):
+        e0.record()
+        f()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) * 1e3
+
+    q = lambda: db.query(qd, k, out=out, ws=ws)
+    for _ in range(5):
+        q()
+    warm = [timed(q) for _ in range(reps)]
+    flush = torch.empty(flush_bytes // 4, dtype=torch.int32, device="cuda")
+    cold = []
+    for i in range(reps // 2):
+        flush.fill_(i)
+        torch.cuda.synchronize()
+        cold.append(timed(q))
+    del flush
+    want = [t.clone() for t in out if t is not None]
+    side = torch.cuda.Stream()
+    side.wait_stream(cur)
+    with torch.cuda.stream(side):
+        q()
+    cur.wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        q()
+    for t in out:
+        if t is not None:
+            t.zero_()
+    graph = [timed(g.replay) for _ in range(reps)]
+    same = all(torch.equal(a, b) for a, b in zip([t for t in out if t is not None], want))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    back_to_back = (time.perf_counter() - t0) * 1e6 / reps
+    med = lambda v: float(np.median(v))
+    log(f"latency: warm {med(warm):.1f} us, cold {med(cold):.1f} us, graph replay {med(graph):.1f} us "
+        f"({back_to_back:.1f} us back to back); graph result equals eager: {same}")
+    return {"warm_us": med(warm), "cold_us": med(cold), "graph_replay_us": med(graph),
+            "graph_back_to_back_us": back_to_back, "graph_equals_eager": same,
+            "flush_bytes": flush_bytes, "reps": reps,
+            "note": "per query: pack + scan + top-k; cold after writing flush_bytes; medians of "
+                    "HIP event times"}
+
+
 def cpu_baseline_embed(model, X, labels, gen, n, n_cand, k, target_s: float):
     """The oracle's embedding query on host cores, one query at a time: float64 mean-pool
     and encoder, float64 direct distances to the stored latents, top-n_cand, and the
@@ -1294,6 +1353,8 @@ def main() -> int:
         cpu = cpu_baseline(gen, q, t_lo, t_hi, args.cpu_seconds)
         log(f"cpu oracle {cpu['value']:.3e} voxels/s on {cpu['cores']} threads")
 
+    latency = small_latency(db, qd, k, out, ws) if args.workload == "small" else None
+
     embed = None
     if args.workload == "full" and not args.no_embed:
         log("embedding search: held-out queries, fused latent search, exact rerank")
@@ -1325,6 +1386,8 @@ def main() -> int:
         "build_s": build_s,
         "embed": embed,
     }
+    if latency is not None:
+        line["latency"] = latency
     print(json.dumps(line), flush=True)
     return 0 if ok else 1
 
