@@ -564,11 +564,12 @@ def encoder_forward_flop(model, nq: int) -> float:
 
 
 def encode_stage_bytes(model, gen, nq: int) -> float:
-    """HBM bytes of the embedding step's encode stage for nq queries (BF16 forward): labels
-    read twice (first layer, query packing), the packed masks written, each convolution's
-    output written and read once (bfloat16; the last one float), the latents written."""
+    """HBM bytes of the embedding step's encode stage for nq queries (BF16 forward): the
+    labels read once (by the query packing), the packed masks and the pooled counts written,
+    the counts read by the first layer, each convolution's output written and read once
+    (bfloat16; the last one float), the latents written."""
     g, c = model.grid, model.channels
-    per = 2 * gen.nvox + 2 * gen.nvox // 8
+    per = gen.nvox + 2 * gen.nvox // 8 + 2 * gen.nvox // 8
     per += sum(2 * 2 * (g >> (i + 1)) ** 3 * c[i + 1] for i in range(3))
     per += 2 * 4 * (g >> 4) ** 3 * c[4] + 4 * model.latent
     return float(per) * nq
@@ -621,32 +622,26 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     stage = np.zeros(3)
 
-    # The rerank's packing of the query labels (HBM-bound) runs on a second stream
-    # (default priority) beside the encoder's later layers (latency-bound), after the
-    # first layer, which reads the same labels; the scoring waits for it with an event.
+    # One read of the query labels: the rerank's packing also writes their pooled counts,
+    # which the encoder's first layer reads instead of the labels.
     ws_rr = db.rerank_workspace(nq)
+    pooled = torch.empty((nq, gen.nz // 2, gen.ny // 2, gen.nx // 2), dtype=torch.uint8,
+                         device="cuda")
     kws = B.knn_workspace(nq, n, n_cand)
     kout = (torch.empty((nq, n_cand), dtype=torch.int32, device="cuda"),
             torch.empty((nq, n_cand), dtype=torch.float32, device="cuda"))
-    side = torch.cuda.Stream()
 
     def step(timed: bool):
         if timed:
             ev[0].record()
-        h1 = model.first_layer_labels_bf16(lab_d)
-        side.wait_stream(torch.cuda.current_stream())    # after the first layer (and the
-        with torch.cuda.stream(side):                    # previous step's use of ws_rr)
-            db.rerank_pack(lab_d, ws_rr)
-        packed = torch.cuda.Event()
-        packed.record(side)
-        ql = model.encode_after_first_bf16(h1)
+        db.rerank_pack_pool(lab_d, ws_rr, pooled)
+        ql = model.encode_counts_bf16(pooled)
         Q = B.Latents(ql, B.EMB_BF16)
         if timed:
             ev[1].record()
         ci, cd = B.emb_knn(Q, X, n_cand, direct=True, ws=kws, out=kout)
         if timed:
             ev[2].record()
-        torch.cuda.current_stream().wait_event(packed)
         out = db.rerank_packed(ws_rr, ci, k)
         if timed:
             ev[3].record()
@@ -683,7 +678,7 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
     gemm_flop = 2.0 * nq * n * model.latent
     enc_flop = encoder_forward_flop(model, nq)
     enc_bytes = encode_stage_bytes(model, gen, nq)
-    names = ["encode + pack queries (two streams)",
+    names = ["pack queries (masks + pooled counts), encode",
              "latent distances + top-100 in one pass (BF16 MFMA), direct-form candidate distances",
              "exact rerank"]
     dom = int(np.argmax(stage))
@@ -716,10 +711,11 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
             "frac": enc_bytes / (stage[0] * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "algorithmic_bytes": enc_bytes, "stage_ms": stage[0],
             "encoder_flop": enc_flop, "encoder_tflops": enc_flop / (stage[0] * 1e-3) / 1e12,
-            "note": "the stage's HBM bytes: the labels read by the first layer and by the query "
-                    "packing (second stream), the packed masks written, each layer's bfloat16 "
-                    "activations written once and read once, the last layer's float output; the "
-                    "convolutions run on the BF16 matrix cores, the linear head on the FP32 ones"},
+            "note": "the stage's HBM bytes: the labels read once (the query packing), the "
+                    "packed masks and the pooled counts written, the counts read by the first "
+                    "layer, each layer's bfloat16 activations written once and read once, the "
+                    "last layer's float output; the convolutions run on the BF16 matrix cores, "
+                    "the linear head on the FP32 ones"},
         "latent_search": {"bound": "mfma", "achieved_tflops": gemm_flop / (stage[1] * 1e-3) / 1e12,
                           "peak_tflops": BF16_MFMA_PEAK / 1e12,
                           "frac": gemm_flop / (stage[1] * 1e-3) / BF16_MFMA_PEAK,

@@ -295,6 +295,15 @@ int db_rerank(const db_t *db, int nq, const uint8_t *q_labels, const int32_t *ca
  * which nn_pool_conv_planes can encode without reading the labels again. */
 int db_rerank_pack(const db_t *db, int nq, const uint8_t *q_labels, void *ws, size_t ws_bytes,
                    void *stream);
+/* db_rerank_pack that also writes, from the same single read of the labels, the input of
+ * the encoder's first layer (Sec. 2.3, "Autoencoders": the masks mean-pooled by 2 in each
+ * direction): pooled (device uint8 [nq][nz/2][ny/2][nx/2], 8-byte aligned, written whole)
+ * holds per 2x2x2 block of voxels its FLAIR count (0..8) in bits 0..3 and its T1Gd count
+ * (0..8) in bits 4..7; the pooled masks are those counts / 8, and nn_pool_conv_counts_bf16
+ * encodes them. ws as after db_rerank_pack, bit for bit. DB_EINVAL when ny or nz is odd or
+ * pooled is NULL / misaligned; other rules as db_rerank_pack. */
+int db_rerank_pack_pool(const db_t *db, int nq, const uint8_t *q_labels, uint8_t *pooled,
+                        void *ws, size_t ws_bytes, void *stream);
 int db_rerank_packed(const db_t *db, int nq, const int32_t *cand, int nc, int k, int32_t *idx,
                      double *score, db_counts_t *counts, void *ws, size_t ws_bytes, void *stream);
 

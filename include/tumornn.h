@@ -108,6 +108,15 @@ int nn_pool_conv_labels_bf16(const uint8_t *labels, int B, int nx, int ny, int n
 int nn_pool_conv_planes_bf16(const uint32_t *planes, int64_t sample_words, const int32_t *idx,
                              int B, int nx, int ny, int nz, int mask, int Co, const void *Wt,
                              const float *bias, int relu, void *Y, void *stream);
+/* nn_pool_conv_labels_bf16 from the pooled counts that db_rerank_pack_pool writes:
+ * counts uint8 [B][nz/2][ny/2][nx/2] (device, 16-byte aligned), per 2x2x2 block of voxels
+ * the FLAIR count (0..8) in bits 0..3 and the T1Gd count in bits 4..7. The pooled means
+ * are counts / 8 (Sec. 2.3, "Autoencoders": the input halved by mean pooling), so Y equals
+ * nn_pool_conv_labels_bf16's for the labels the counts came from, bit for bit; the labels
+ * are not read again. Same arguments and rules otherwise. */
+int nn_pool_conv_counts_bf16(const uint8_t *counts, int B, int nx, int ny, int nz, int mask,
+                             int Co, const void *Wt, const float *bias, int relu, void *Y,
+                             void *stream);
 /* Tap-major copy of bfloat16 convolution weights for nn_conv3d_s2_fwd_bf16:
  * out[co][t][ci] = Wt[co][ci][t] for the 27 taps t (kd, kh, kw order) and 0 for
  * t = 27; out holds Co * 28 * Ci bfloat16 values (device). */

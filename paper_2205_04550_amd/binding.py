@@ -26,7 +26,8 @@ SYMBOLS = ("db_storage_bytes", "db_build", "db_append", "db_size", "db_query_wor
            "db_query_sparse", "db_query_com_workspace_bytes", "db_query_com",
            "emb_hash_thresholds", "emb_binarize", "emb_distances_l2sum", "db_rerank_pack",
            "db_rerank_packed", "emb_groups_workspace_bytes", "emb_distances_groups",
-           "emb_topk_groups", "db_query_noalloc", "emb_knn_workspace_bytes", "emb_knn")
+           "emb_topk_groups", "db_query_noalloc", "emb_knn_workspace_bytes", "emb_knn",
+           "db_rerank_pack_pool")
 EMB_BF16, EMB_FP8, EMB_BIN = 0, 1, 2
 
 
@@ -82,6 +83,7 @@ def _load():
         "db_rerank_workspace_bytes": (sz, [vp, i32]),
         "db_rerank": (i32, [vp, i32, vp, vp, i32, i32, vp, vp, vp, vp, sz, vp]),
         "db_rerank_pack": (i32, [vp, i32, vp, vp, sz, vp]),
+        "db_rerank_pack_pool": (i32, [vp, i32, vp, vp, vp, sz, vp]),
         "db_rerank_packed": (i32, [vp, i32, vp, i32, i32, vp, vp, vp, vp, sz, vp]),
         "db_query_embed_workspace_bytes": (sz, [vp, i32, i32]),
         "db_query_embed": (i32, [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, i32, vp, vp,
@@ -328,6 +330,20 @@ class TumorDB:
         """First half of rerank: pack the queries q_labels [nq][nz][ny][nx] into ws."""
         _check(LIB.db_rerank_pack(self._h, q_labels.shape[0], q_labels.data_ptr(), ws.data_ptr(),
                                   ws.numel(), _stream(stream)))
+
+    def rerank_pack_pool(self, q_labels: torch.Tensor, ws: torch.Tensor,
+                         pooled: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """rerank_pack that also returns the labels' pooled counts, uint8 [nq][nz/2][ny/2][nx/2]
+        (per 2x2x2 block: FLAIR count in bits 0..3, T1Gd count in bits 4..7), the input of
+        the encoder's first layer from the same read of the labels."""
+        nq, nz, ny, nx = q_labels.shape
+        shape = (nq, nz // 2, ny // 2, nx // 2)
+        if pooled is None:
+            pooled = torch.empty(shape, dtype=torch.uint8, device=q_labels.device)
+        assert pooled.dtype == torch.uint8 and tuple(pooled.shape) == shape and pooled.is_contiguous()
+        _check(LIB.db_rerank_pack_pool(self._h, nq, q_labels.data_ptr(), pooled.data_ptr(),
+                                       ws.data_ptr(), ws.numel(), _stream(stream)))
+        return pooled
 
     def packed_queries(self, ws: torch.Tensor, nq: int) -> torch.Tensor:
         """int32 view [nq][2][Wp] of the queries' packed masks that rerank_pack left at the start

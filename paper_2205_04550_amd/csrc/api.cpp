@@ -954,14 +954,17 @@ static hipError_t rerank_launches(const db_t *db, int nq, const uint32_t *qpack,
     return e;
 }
 
-// Pack the queries into the rerank workspace: bit planes, counts, row boxes, moments.
+// Pack the queries into the rerank workspace: bit planes, counts, row boxes, moments;
+// with pooled, also the labels' pooled counts for the encoder.
 static hipError_t enqueue_rerank_pack(const db_t *db, int nq, const uint8_t *q_labels, void *ws,
-                                      hipStream_t s)
+                                      hipStream_t s, uint8_t *pooled = nullptr)
 {
     size_t oq, op, oa, ob, om, osc;
     rerank_layout(db, nq, &oq, &op, &oa, &ob, &om, &osc);
-    hipError_t e = launch_pack_queries(db, q_labels, nq, nullptr, at<uint32_t>(ws, oq),
-                                       at<QueryPart>(ws, op), s);
+    hipError_t e = pooled ? launch_pack_pool_queries(db, q_labels, nq, at<uint32_t>(ws, oq),
+                                                     at<QueryPart>(ws, op), pooled, s)
+                          : launch_pack_queries(db, q_labels, nq, nullptr, at<uint32_t>(ws, oq),
+                                                at<QueryPart>(ws, op), s);
     if (e == hipSuccess)
         e = launch_sum_parts(at<QueryPart>(ws, op), nq, at<uint32_t>(ws, oa), at<int32_t>(ws, ob),
                              at<uint64_t>(ws, om), s);
@@ -999,6 +1002,27 @@ int db_rerank_pack(const db_t *db, int nq, const uint8_t *q_labels, void *ws, si
         return fail(DB_ENOSPC, "db_rerank_pack: workspace %zu bytes < %zu needed", ws_bytes, need);
     hipError_t e = enqueue_rerank_pack(db, nq, q_labels, ws, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "db_rerank_pack: launch");
+    return DB_OK;
+}
+
+int db_rerank_pack_pool(const db_t *db, int nq, const uint8_t *q_labels, uint8_t *pooled,
+                        void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_query_common("db_rerank_pack_pool", db, q_labels, ws);
+    if (rc) return rc;
+    if (nq <= 0) return fail(DB_EINVAL, "db_rerank_pack_pool: nq %d", nq);
+    if (db->g.ny % 2 || db->g.nz % 2)
+        return fail(DB_EINVAL, "db_rerank_pack_pool: grid %d x %d x %d: ny and nz must be even",
+                    db->g.nx, db->g.ny, db->g.nz);
+    if (!pooled || !aligned(pooled, 8))
+        return fail(DB_EINVAL, "db_rerank_pack_pool: pooled must be non-NULL and 8-byte aligned");
+    const size_t need = db_rerank_workspace_bytes(db, nq);
+    if (ws_bytes < need)
+        return fail(DB_ENOSPC, "db_rerank_pack_pool: workspace %zu bytes < %zu needed", ws_bytes,
+                    need);
+    hipError_t e = enqueue_rerank_pack(db, nq, q_labels, ws, static_cast<hipStream_t>(stream),
+                                       pooled);
+    if (e != hipSuccess) return hip_fail(e, "db_rerank_pack_pool: launch");
     return DB_OK;
 }
 

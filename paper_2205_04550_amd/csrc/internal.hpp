@@ -99,6 +99,11 @@ hipError_t launch_pack_db(const db_t *db, const float *conc, int64_t n, uint32_t
                           uint32_t *popcnt, hipStream_t s);
 hipError_t launch_pack_queries(const db_t *db, const uint8_t *labels, int nq, const int32_t *rois,
                                uint32_t *qpack, QueryPart *qpart, hipStream_t s);
+// launch_pack_queries without ROI that also writes the labels' 2x2x2 pooled counts,
+// uint8 [nq][nz/2][ny/2][nx/2] (FLAIR count bits 0..3, T1Gd count bits 4..7); ny, nz even.
+hipError_t launch_pack_pool_queries(const db_t *db, const uint8_t *labels, int nq,
+                                    uint32_t *qpack, QueryPart *qpart, uint8_t *pooled,
+                                    hipStream_t s);
 // Per query: counts acnt [nq][2], row box qbox [nq][4] (z0, z1, y0, y1; all zero when
 // empty) and FLAIR moments qmom [nq][4] (sum x, sum y, sum z, count).
 hipError_t launch_sum_parts(const QueryPart *qpart, int nq, uint32_t *acnt, int32_t *qbox,

@@ -801,6 +801,16 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
     return (uint16_t)((u + bias) >> 16);
 }
 
+// Two floats -> two bfloat16 values, round to nearest even, lo in bits 0..15 (one
+// v_cvt_pk_bf16_f32). FP32 denormals are kept in these kernels (denormal mode 3), so
+// every non-NaN input gives f32_to_bf16_rne's bits; a NaN stays a NaN.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16x2_rne(float lo, float hi)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t){lo, hi}, bf16x2_t));
+}
+
 __global__ void adam_kernel(int64_t n, float *__restrict__ w, float *__restrict__ m,
                             float *__restrict__ v, const float *__restrict__ g,
                             uint16_t *__restrict__ wb, float lr, float b1, float b2, float eps,
@@ -965,6 +975,7 @@ __global__ void __launch_bounds__(256) meanpool_labels_fast_kernel(const uint8_t
 // pooled halo rows they share come from its L2.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 constexpr int kPlRow = 68;
 
 
@@ -994,6 +1005,88 @@ __device__ __forceinline__ uint32_t pair_counts4(uint32_t x16)
     t = (t | (t << 8)) & 0x00ff00ffu;
     t = (t | (t << 4)) & 0x0f0f0f0fu;
     return (t | (t << 2)) & 0x33333333u;
+}
+
+// The first layer's weights as this lane's A operands (row co = j, eight k from 8 g per
+// step), its four biases (rows 4 g .. + 3) and the LDS word of each of its four taps per
+// step for the wave's first 16 voxels (tap >= 27: weight zero, any word). Wave w owns the
+// tile's voxels 64 w .. + 63: output z = w / 2, y = 2 (w % 2) + m / 2 and x = 16 (m % 2) + j
+// for its four products m, so voxels m sit at the compile-time offsets of tile_moff.
+__device__ __forceinline__ void first_layer_setup(const uint16_t *__restrict__ Wt,
+                                                  const float *__restrict__ bias, int Ci, int Co,
+                                                  int wave, int g, int j, bf16x8 (&a)[2],
+                                                  float (&bco)[4], int (&ad)[2][4])
+{
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int tap = 16 * st + 4 * g + (e >> 1), c = e & 1;
+            uint16_t bits = 0;
+            if (j < Co && tap < 27 && c < Ci) bits = Wt[((int64_t)j * Ci + c) * 27 + tap];
+            a[st][e] = __builtin_bit_cast(__bf16, bits);
+        }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bco[r] = (bias && 4 * g + r < Co) ? bias[4 * g + r] : 0.f;
+    const int base = (18 * (wave >> 1) + 4 * (wave & 1)) * kPlRow + 2 * j + 3;
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int tap = 16 * st + 4 * g + i;
+            ad[st][i] = base + (tap < 27 ? ((tap / 9) * 9 + (tap / 3) % 3) * kPlRow + tap % 3 : 0);
+        }
+}
+
+// LDS offset of product m's voxels from the wave's first ones: one output y row is two
+// pooled rows, 16 output x are 32 pooled x.
+__device__ __forceinline__ constexpr int tile_moff(int m) { return (m >> 1) * 2 * kPlRow + (m & 1) * 32; }
+
+// One tile of the first layer from its pooled patch in LDS (pl, laid out as above): the
+// 2 x 4 x 32 output voxels at (od0, oh0, ow0) of sample b, two 16 x 16 x 32 products per
+// 16 voxels, then bias, ReLU and the store.
+template <bool OUTBF>
+__device__ __forceinline__ void first_layer_tile(const uint32_t *pl, const bf16x8 (&a)[2],
+                                                 const float (&bco)[4], const int (&ad)[2][4],
+                                                 int wave, int g, int j, int od0, int oh0,
+                                                 int ow0, int OD, int OH, int OW, int b, int Co,
+                                                 int relu, void *__restrict__ Yv)
+{
+    const int64_t osp = (int64_t)OD * OH * OW;
+    const int oz = od0 + (wave >> 1), oy0 = oh0 + 2 * (wave & 1);
+    // Output index of product 0's voxel; product m adds (m % 2) 16 + (m / 2) OW.
+    const int64_t o0 = ((int64_t)oz * OH + oy0) * OW + ow0 + j;
+    const float lo = relu ? 0.f : -INFINITY;       // values below lo become 0 (ReLU)
+    uint16_t *Yb = static_cast<uint16_t *>(Yv) + ((int64_t)b * osp + o0) * Co + 4 * g;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+            const u32x4 bw = {pl[ad[st][0] + tile_moff(m)], pl[ad[st][1] + tile_moff(m)],
+                              pl[ad[st][2] + tile_moff(m)], pl[ad[st][3] + tile_moff(m)]};
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[st], __builtin_bit_cast(bf16x8, bw),
+                                                          acc, 0, 0, 0);
+        }
+        if (oz >= OD || oy0 + (m >> 1) >= OH) continue;
+        const int64_t o = o0 + (m & 1) * 16 + (m >> 1) * OW;
+        float yv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            yv[r] = acc[r] + bco[r];
+            yv[r] = yv[r] < lo ? 0.f : yv[r];
+        }
+        if constexpr (OUTBF) {
+            if (4 * g < Co)                        // four channels, one 8-byte store
+                *reinterpret_cast<u32x2 *>(Yb + ((m & 1) * 16 + (m >> 1) * OW) * Co) =
+                    (u32x2){bf16x2_rne(yv[0], yv[1]), bf16x2_rne(yv[2], yv[3])};
+        } else {
+            float *Y = static_cast<float *>(Yv);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (4 * g + r < Co) Y[((int64_t)b * Co + 4 * g + r) * osp + o] = yv[r];
+        }
+    }
 }
 
 // PLANES: the masks come packed (LSB-first uint32 words, x fastest; plane 0
@@ -1033,29 +1126,10 @@ __global__ void __launch_bounds__(256) pool_conv_labels_kernel(const uint8_t *__
     const int64_t Wp = sample_words / 2;
     const int nxw = nx / 32;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, j = lane & 15;
-    // Weights of both steps for this lane: row co = j, eight k from 8 g.
     bf16x8 a[2];
-#pragma unroll
-    for (int st = 0; st < 2; ++st)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int tap = 16 * st + 4 * g + (e >> 1), c = e & 1;
-            uint16_t bits = 0;
-            if (j < Co && tap < 27 && c < Ci) bits = Wt[((int64_t)j * Ci + c) * 27 + tap];
-            a[st][e] = __builtin_bit_cast(__bf16, bits);
-        }
     float bco[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) bco[r] = (bias && 4 * g + r < Co) ? bias[4 * g + r] : 0.f;
-    // LDS offsets of this lane's four taps per step (tap >= 27: weight zero, any word).
-    int toff[2][4];
-#pragma unroll
-    for (int st = 0; st < 2; ++st)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int tap = 16 * st + 4 * g + i;
-            toff[st][i] = tap < 27 ? ((tap / 9) * 9 + (tap / 3) % 3) * kPlRow + tap % 3 : 0;
-        }
+    int ad[2][4];
+    first_layer_setup(Wt, bias, Ci, Co, wave, g, j, a, bco, ad);
     // Pooling items: 45 pooled rows x 8 groups of 8 pooled x (16 label bytes per label
     // row), plus one halo column per row (pooled x = 2 ow0 - 1): 405, at most two per
     // thread. The labels of the next tile are loaded while the current one is computed.
@@ -1116,7 +1190,6 @@ __global__ void __launch_bounds__(256) pool_conv_labels_kernel(const uint8_t *__
         }
     };
     load(t0);
-    const int64_t osp = (int64_t)OD * OH * OW;
     for (int n = 0; n < npb; ++n) {
         const int t = t0 + n;
         if (t >= T) break;                         // uniform over the block
@@ -1199,44 +1272,108 @@ __global__ void __launch_bounds__(256) pool_conv_labels_kernel(const uint8_t *__
         __syncthreads();
         if (!PLANES && n + 1 < npb && t + 1 < T) load(t + 1);
         const int twi = t % tw_n, thi = (t / tw_n) % th_n, tdi = t / (tw_n * th_n);
-        const int od0 = 2 * tdi, oh0 = 4 * thi, ow0 = 32 * twi;
+        first_layer_tile<OUTBF>(pl, a, bco, ad, wave, g, j, 2 * tdi, 4 * thi, 32 * twi, OD, OH,
+                                OW, b, Co, relu, Yv);
+        __syncthreads();                           // the next tile overwrites pl
+    }
+}
+
+// The first layer from pooled counts instead of labels: C is uint8 [B][nz/2][ny/2][nx/2],
+// per 2x2x2 block of label voxels its FLAIR count (0..8) in bits 0..3 and its T1Gd count in
+// bits 4..7. The pooled means are the counts / 8, so the LDS words, the products and their
+// order are pool_conv_labels_kernel's and Y equals its output bit for bit. A tile's patch is
+// 45 pooled rows of 64 counts and the count before each row (the halo): 720 groups of four
+// counts and 45 halo counts, three per thread, the next tile's in flight while the current
+// one is computed.
+__device__ __forceinline__ void count_words(uint32_t cb, int Ci, int mask, uint32_t (&w)[4])
+{
+    // Counts k -> float k (one conversion per byte) -> the two channels' bfloat16 values in
+    // one word -> k / 8 by lowering both exponents by 3 (a saturating 16-bit subtract, so
+    // k = 0 stays 0). One mask: it goes to channel 0, channel 1 stays zero.
+    uint32_t f = cb & 0x0f0f0f0fu, h = (cb >> 4) & 0x0f0f0f0fu;
+    if (Ci == 1) {
+        if (mask == 1) f = h;
+        h = 0u;
+    }
+    asm volatile("" : "+v"(f), "+v"(h));   // keep the byte-wise conversions
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int vx = (wave * 4 + m) * 16 + j;
-            const int z = vx >> 7, y = (vx >> 5) & 3, x = vx & 31;
-            const int base = (2 * z * 9 + 2 * y) * kPlRow + 2 * x + 3;
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int e = 0; e < 4; ++e) {
+        const uint32_t x = bf16x2_rne((float)((f >> (8 * e)) & 0xffu), (float)((h >> (8 * e)) & 0xffu));
+        w[e] = __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(
+                                                __builtin_bit_cast(u16x2, x), (u16x2){0x180, 0x180}));
+    }
+}
+
+template <bool OUTBF>
+__global__ void __launch_bounds__(256) pool_conv_counts_kernel(const uint8_t *__restrict__ C,
+                                                               int nx, int ny, int nz, int mask,
+                                                               int Ci, int Co, int npb,
+                                                               const uint16_t *__restrict__ Wt,
+                                                               const float *__restrict__ bias,
+                                                               int relu, void *__restrict__ Yv)
+{
+    __shared__ __attribute__((aligned(16))) uint32_t pl[45 * kPlRow];
+    const int PZ = nz / 2, PY = ny / 2, PX = nx / 2;
+    const int OD = nz / 4, OH = ny / 4, OW = nx / 4;
+    const int tw_n = OW / 32, th_n = (OH + 3) / 4, td_n = (OD + 1) / 2;
+    const int T = tw_n * th_n * td_n;
+    int t0 = blockIdx.x * npb;
+    if (T % (8 * npb) == 0) t0 = (blockIdx.x % 8) * (T / 8) + (blockIdx.x / 8) * npb;
+    const int b = blockIdx.y;
+    const uint8_t *Cb = C + (int64_t)b * PZ * PY * PX;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, j = lane & 15;
+    bf16x8 a[2];
+    float bco[4];
+    int ad[2][4];
+    first_layer_setup(Wt, bias, Ci, Co, wave, g, j, a, bco, ad);
+    // Item it = tid + 256 s: it < 720 is group it % 16 (pooled x 2 ow0 + 4 (it % 16) .. + 3) of
+    // patch row it / 16; 720 <= it < 765 is the halo count (pooled x 2 ow0 - 1) of row it - 720,
+    // zero at ow0 = 0 like the rows outside the volume. Patch row r is pooled z 2 od0 - 1 + r / 9,
+    // pooled y 2 oh0 - 1 + r % 9.
+    int rz[3], ry[3], lds[3];
+    int64_t roff[3];
 #pragma unroll
-            for (int st = 0; st < 2; ++st) {
-                const u32x4 bw = {pl[base + toff[st][0]], pl[base + toff[st][1]],
-                                  pl[base + toff[st][2]], pl[base + toff[st][3]]};
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[st], __builtin_bit_cast(bf16x8, bw),
-                                                              acc, 0, 0, 0);
-            }
-            const int oz = od0 + z, oy = oh0 + y, ox = ow0 + x;
-            if (oz >= OD || oy >= OH) continue;
-            const int64_t o = ((int64_t)oz * OH + oy) * OW + ox;
-            float yv[4];
+    for (int s = 0; s < 3; ++s) {
+        const int it = tid + 256 * s;
+        const int r = it < 720 ? it >> 4 : min(it - 720, 44);
+        rz[s] = r / 9 - 1;
+        ry[s] = r % 9 - 1;
+        roff[s] = ((int64_t)rz[s] * PY + ry[s]) * PX + (it < 720 ? 4 * (it & 15) : -1);
+        lds[s] = r * kPlRow + (it < 720 ? 4 + 4 * (it & 15) : 3);
+    }
+    uint32_t v[3];
+    auto load = [&](int t) {
+        const int twi = t % tw_n, thi = (t / tw_n) % th_n, tdi = t / (tw_n * th_n);
+        const int z0 = 4 * tdi, y0 = 8 * thi, x0 = 64 * twi;   // pooled corner of the patch + 1
+        const int64_t toff = ((int64_t)z0 * PY + y0) * PX + x0;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                yv[r] = acc[r] + bco[r];
-                if (relu && yv[r] < 0.f) yv[r] = 0.f;
-            }
-            if constexpr (OUTBF) {
-                if (4 * g < Co) {                  // four channels, one 8-byte store
-                    uint16_t *Y = static_cast<uint16_t *>(Yv);
-                    const uint32_t lo = f32_to_bf16_rne(yv[0]) | ((uint32_t)f32_to_bf16_rne(yv[1]) << 16);
-                    const uint32_t hi = f32_to_bf16_rne(yv[2]) | ((uint32_t)f32_to_bf16_rne(yv[3]) << 16);
-                    *reinterpret_cast<u32x2 *>(&Y[((int64_t)b * osp + o) * Co + 4 * g]) =
-                        (u32x2){lo, hi};
-                }
-            } else {
-                float *Y = static_cast<float *>(Yv);
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (4 * g + r < Co) Y[((int64_t)b * Co + 4 * g + r) * osp + o] = yv[r];
+        for (int s = 0; s < 3; ++s) {
+            const int it = tid + 256 * s, Z = z0 + rz[s], Yp = y0 + ry[s];
+            v[s] = 0u;
+            if (it < 765 && Z >= 0 && Z < PZ && Yp >= 0 && Yp < PY) {
+                if (it < 720) v[s] = *reinterpret_cast<const uint32_t *>(Cb + toff + roff[s]);
+                else if (x0 > 0) v[s] = Cb[toff + roff[s]];
             }
         }
+    };
+    load(t0);
+    for (int n = 0; n < npb; ++n) {
+        const int t = t0 + n;
+        if (t >= T) break;                         // uniform over the block
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int it = tid + 256 * s;
+            if (it >= 765) break;
+            uint32_t w[4];
+            count_words(v[s], Ci, mask, w);
+            if (it < 720) *reinterpret_cast<u32x4 *>(&pl[lds[s]]) = (u32x4){w[0], w[1], w[2], w[3]};
+            else pl[lds[s]] = w[0];
+        }
+        __syncthreads();
+        if (n + 1 < npb && t + 1 < T) load(t + 1);
+        const int twi = t % tw_n, thi = (t / tw_n) % th_n, tdi = t / (tw_n * th_n);
+        first_layer_tile<OUTBF>(pl, a, bco, ad, wave, g, j, 2 * tdi, 4 * thi, 32 * twi, OD, OH,
+                                OW, b, Co, relu, Yv);
         __syncthreads();                           // the next tile overwrites pl
     }
 }
@@ -1699,6 +1836,24 @@ int nn_pool_conv_planes_bf16(const uint32_t *planes, int64_t sample_words, const
                        nz, mask, mask < 0 ? 2 : 1, Co, npb, static_cast<const uint16_t *>(Wt), bias,
                        relu, Y);
     return launched("nn_pool_conv_planes_bf16");
+}
+
+int nn_pool_conv_counts_bf16(const uint8_t *counts, int B, int nx, int ny, int nz, int mask,
+                             int Co, const void *Wt, const float *bias, int relu, void *Y,
+                             void *stream)
+{
+    if (!counts || !Wt || !Y || B <= 0 || B > 65535 || nx <= 0 || ny <= 0 || nz <= 0 ||
+        nx % 128 || ny % 4 || nz % 4 || Co <= 0 || Co > 16 || Co % 4 || mask < -1 || mask > 1 ||
+        (uintptr_t)counts % 16 || (uintptr_t)Y % 8 || (int64_t)nx * ny * nz >= ((int64_t)1 << 31))
+        return tdb_set_error(DB_EINVAL, "nn_pool_conv_counts_bf16: bad arguments");
+    const int T = (nx / 128) * ((ny / 4 + 3) / 4) * ((nz / 4 + 1) / 2);
+    const int npb = T % 32 == 0 ? 4 : 1;
+    hipLaunchKernelGGL((pool_conv_counts_kernel<true>),
+                       dim3((unsigned)((T + npb - 1) / npb), (unsigned)B), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), counts, nx, ny, nz, mask,
+                       mask < 0 ? 2 : 1, Co, npb, static_cast<const uint16_t *>(Wt), bias, relu,
+                       Y);
+    return launched("nn_pool_conv_counts_bf16");
 }
 
 int nn_conv3d_weights_tapmajor(const void *Wt, int Co, int Ci, void *out, void *stream)

@@ -119,6 +119,26 @@ struct PartAcc {
         }
     }
 
+    // One plane's word b of row (z, y), word wx of the row: the same sums as add() over
+    // the two planes' words of that row taken one at a time (moments from FLAIR only).
+    __device__ void add_plane(uint32_t b, int plane, int wx, int y, int z)
+    {
+        const uint32_t c = popc(b);
+        n0 += plane ? 0u : c;
+        n1 += plane ? c : 0u;
+        if (b) {
+            zlo = min(zlo, z);
+            zhi = max(zhi, z);
+            ylo = min(ylo, y);
+            yhi = max(yhi, y);
+            if (!plane) {
+                sx += (uint64_t)(32u * (uint32_t)wx) * c + bit_position_sum(b);
+                sy += (uint64_t)y * c;
+                sz += (uint64_t)z * c;
+            }
+        }
+    }
+
     // Block-wide sum (at most 4 waves); thread 0 writes the part.
     __device__ void write(QueryPart &p)
     {
@@ -238,6 +258,103 @@ hipError_t launch_pack_queries(const db_t *db, const uint8_t *labels, int nq, co
     const Geometry &g = db->g;
     hipLaunchKernelGGL(pack_query_kernel, dim3(kQueryParts, nq), dim3(256), 0, s, labels, g.V,
                        g.W, g.Wp, g.nxw, g.ny, rois, qpack, qpart);
+    return hipGetLastError();
+}
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kPoolBatch = 2;   // lane units per pass of pack_pool_query_kernel, loads first
+
+// grid (kQueryParts, nq): pack_query_kernel's outputs (no ROI) and, from the same read of
+// the labels, their pooled counts for the encoder's first layer: uint8 [nq][nz/2][ny/2][nx/2],
+// per 2x2x2 block of voxels its FLAIR count (0..8) in bits 0..3 and its T1Gd count in bits
+// 4..7. Needs ny and nz even. A lane unit is 16 voxels along x in each of the four rows
+// (2 pz + dz, 2 py + dy), 16 label bytes per row; the two units of one word form a lane pair:
+// per row the even lane assembles the FLAIR word and the odd lane the T1Gd word (one
+// exchange), and each lane adds its bytes into the 8 pooled counts of its 16 voxels.
+__global__ void __launch_bounds__(256) pack_pool_query_kernel(const uint8_t *__restrict__ labels,
+                                                              int64_t V, int Wp, int nx,
+                                                              int ny, uint32_t *__restrict__ qpack,
+                                                              QueryPart *__restrict__ qpart,
+                                                              uint8_t *__restrict__ pooled)
+{
+    const int q = blockIdx.y;
+    const u32x4 *lab = reinterpret_cast<const u32x4 *>(labels + (int64_t)q * V);
+    uint32_t *o = qpack + (int64_t)q * 2 * Wp;
+    uint8_t *P = pooled + (int64_t)q * (V >> 3);
+    const int nxw = nx >> 5, PY = ny >> 1, PX = nx >> 1, rowv = nx >> 4;   // rowv: u32x4 per row
+    const int half = threadIdx.x & 1;
+    PartAcc acc;   // with ny, nz even W = nxw ny nz is a multiple of 4: no padding words
+    const int U = (int)(V >> 6);                       // lane units; ubeg and seg even
+    const int seg = 2 * ((U / 2 + gridDim.x - 1) / gridDim.x);
+    const int ubeg = blockIdx.x * seg, uend = min(U, ubeg + seg);
+    for (int u0 = ubeg + threadIdx.x; u0 - (int)threadIdx.x < uend;
+         u0 += kPoolBatch * blockDim.x) {
+        u32x4 v[kPoolBatch][4];
+        int xw[kPoolBatch], py[kPoolBatch], pz[kPoolBatch];
+#pragma unroll
+        for (int i = 0; i < kPoolBatch; ++i) {
+            const int u = u0 + i * blockDim.x, pair = u >> 1;
+            xw[i] = pair % nxw;
+            py[i] = (pair / nxw) % PY;
+            pz[i] = pair / (nxw * PY);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = (int64_t)(2 * pz[i] + (r >> 1)) * ny + 2 * py[i] + (r & 1);
+                v[i][r] = (u32x4){0u, 0u, 0u, 0u};
+                if (u < uend) v[i][r] = load_stream(lab + row * rowv + 2 * xw[i] + half);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kPoolBatch; ++i) {
+            const bool valid = u0 + i * (int)blockDim.x < uend;
+            uint32_t f[4] = {0u, 0u, 0u, 0u}, h2[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                uint32_t m0 = 0, m1 = 0;   // this lane's 16 bits of each mask in row r
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    uint32_t f4, t4;
+                    label_nibbles(v[i][r][e], f4, t4);
+                    m0 |= f4 << (4 * e);
+                    m1 |= t4 << (4 * e);
+                    f[e] += v[i][r][e] & 0x01010101u;    // per byte: FLAIR voxels so far
+                    h2[e] += v[i][r][e] & 0x02020202u;   // per byte: twice the T1Gd voxels
+                }
+                const uint32_t got = __shfl_xor(half ? m0 : m1, 1, 64);
+                const uint32_t word = half ? (got | (m1 << 16)) : (m0 | (got << 16));
+                if (valid) {
+                    const int z = 2 * pz[i] + (r >> 1), y = 2 * py[i] + (r & 1);
+                    o[half * Wp + (z * ny + y) * nxw + xw[i]] = word;
+                    acc.add_plane(word, half, xw[i], y, z);
+                }
+            }
+            // Byte pairs (x, x + 1) -> pooled counts: FLAIR in bits 0..3, T1Gd in 4..7 of
+            // bytes 0 and 2 of c[e] (pooled x 2 e and 2 e + 1 of this lane's 8).
+            uint32_t c[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t fp = (f[e] & 0x00ff00ffu) + ((f[e] >> 8) & 0x00ff00ffu);
+                const uint32_t hp = (h2[e] & 0x00ff00ffu) + ((h2[e] >> 8) & 0x00ff00ffu);
+                c[e] = fp | (hp << 3);
+            }
+            if (valid) {
+                const u32x2 pw = {__builtin_amdgcn_perm(c[1], c[0], 0x06040200u),
+                                  __builtin_amdgcn_perm(c[3], c[2], 0x06040200u)};
+                *reinterpret_cast<u32x2 *>(P + ((int64_t)pz[i] * PY + py[i]) * PX + 16 * xw[i] +
+                                           8 * half) = pw;
+            }
+        }
+    }
+    acc.write(qpart[(int64_t)q * kQueryParts + blockIdx.x]);
+}
+
+hipError_t launch_pack_pool_queries(const db_t *db, const uint8_t *labels, int nq,
+                                    uint32_t *qpack, QueryPart *qpart, uint8_t *pooled,
+                                    hipStream_t s)
+{
+    const Geometry &g = db->g;
+    hipLaunchKernelGGL(pack_pool_query_kernel, dim3(kQueryParts, nq), dim3(256), 0, s, labels,
+                       g.V, g.Wp, g.nx, g.ny, qpack, qpart, pooled);
     return hipGetLastError();
 }
 

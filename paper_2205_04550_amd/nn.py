@@ -59,6 +59,8 @@ _SIGS = {
                                         _vp, _vp]),
     "nn_pool_conv_planes_bf16": (_i32, [_vp, _i64, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp,
                                         _vp, _i32, _vp, _vp]),
+    "nn_pool_conv_counts_bf16": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _i32,
+                                        _vp, _vp]),
     "nn_conv3d_weights_tapmajor": (_i32, [_vp, _i32, _i32, _vp, _vp]),
     "nn_conv3d_s2_fwd_bf16": (_i32, [_i32] * 6 + [_vp, _vp, _vp, _i32, _i32, _vp, _vp]),
 }
@@ -206,6 +208,25 @@ def pool_conv_planes_bf16(planes: torch.Tensor, dims, w_bf16: torch.Tensor,
     idx = None if idx is None else _c(idx.to(torch.int32))
     y = torch.empty((B, nz // 4, ny // 4, nx // 4, Co), dtype=torch.bfloat16, device=planes.device)
     _check(LIB.nn_pool_conv_planes_bf16(planes.data_ptr(), 2 * Wp, _p(idx), B, nx, ny, nz,
+                                        -1 if mask is None else mask, Co, w_bf16.data_ptr(),
+                                        _p(bias), int(relu), y.data_ptr(), _s()))
+    return y
+
+
+def pool_conv_counts_bf16(counts: torch.Tensor, w_bf16: torch.Tensor, bias: torch.Tensor | None,
+                          relu: bool = True, mask: int | None = None) -> torch.Tensor:
+    """pool_conv_labels_bf16 from the pooled counts uint8 [B][nz/2][ny/2][nx/2] that
+    TumorDB.rerank_pack_pool writes; equal to it bit for bit for the labels they came from."""
+    counts = _c(counts)
+    B, pz, py, px = counts.shape
+    nz, ny, nx = 2 * pz, 2 * py, 2 * px
+    Co = w_bf16.shape[0]
+    assert counts.dtype == torch.uint8
+    assert w_bf16.dtype == torch.bfloat16 and w_bf16.shape[1] == (2 if mask is None else 1)
+    w_bf16 = _c(w_bf16)
+    bias = None if bias is None else _c(bias.detach())
+    y = torch.empty((B, nz // 4, ny // 4, nx // 4, Co), dtype=torch.bfloat16, device=counts.device)
+    _check(LIB.nn_pool_conv_counts_bf16(counts.data_ptr(), B, nx, ny, nz,
                                         -1 if mask is None else mask, Co, w_bf16.data_ptr(),
                                         _p(bias), int(relu), y.data_ptr(), _s()))
     return y
@@ -592,6 +613,12 @@ class AutoEncoder:
             w, b, wc = self._w("enc0")
             return pool_conv_labels_bf16(labels, wc, b, True, mask)
 
+    def first_layer_counts_bf16(self, counts: torch.Tensor, mask: int | None = None) -> torch.Tensor:
+        """first_layer_labels_bf16 from pooled counts (TumorDB.rerank_pack_pool), bit for bit."""
+        with torch.no_grad():
+            w, b, wc = self._w("enc0")
+            return pool_conv_counts_bf16(counts, wc, b, True, mask)
+
     def _tapmajor(self) -> dict:
         """Tap-major copies of the later convolutions' working weights, remade whenever the
         working weights changed (training updates them in place)."""
@@ -615,6 +642,12 @@ class AutoEncoder:
         nz, ny, nx = labels.shape[-3:]
         assert self.bf16_inference_ok((nx, ny, nz))
         return self.encode_after_first_bf16(self.first_layer_labels_bf16(labels, mask))
+
+    def encode_counts_bf16(self, counts: torch.Tensor, mask: int | None = None) -> torch.Tensor:
+        """encode_labels_bf16 from pooled counts [B][nz/2][ny/2][nx/2], bit for bit."""
+        pz, py, px = counts.shape[-3:]
+        assert self.bf16_inference_ok((2 * px, 2 * py, 2 * pz))
+        return self.encode_after_first_bf16(self.first_layer_counts_bf16(counts, mask))
 
     def encode_planes_bf16(self, planes: torch.Tensor, dims, idx: torch.Tensor | None = None,
                            mask: int | None = None) -> torch.Tensor:

@@ -107,6 +107,7 @@ def test_first_layer_bf16_is_the_float_layer_rounded():
     ws = db.rerank_workspace(B)
     db.rerank_pack(lab_d, ws)
     planes = db.packed_queries(ws, B).clone()
+    counts = db.rerank_pack_pool(lab_d, db.rerank_workspace(B))
     g = torch.Generator().manual_seed(4)
     for mask in (None, 0, 1):
         ci = 2 if mask is None else 1
@@ -118,6 +119,8 @@ def test_first_layer_bf16_is_the_float_layer_rounded():
             assert torch.equal(yb, yf.permute(0, 2, 3, 4, 1).to(torch.bfloat16)), (mask, relu)
             yp = nn.pool_conv_planes_bf16(planes, (nx, ny, nz), wc, b, relu, mask)
             assert torch.equal(yp.view(torch.int16), yb.view(torch.int16)), (mask, relu)
+            yc = nn.pool_conv_counts_bf16(counts, wc, b, relu, mask)
+            assert torch.equal(yc.view(torch.int16), yb.view(torch.int16)), (mask, relu)
 
 
 def test_encode_bf16_matches_oracle():
@@ -159,3 +162,65 @@ def test_encode_bf16_matches_oracle():
     db.rerank_pack(lab_d, ws)
     zp = model.encode_planes_bf16(db.packed_queries(ws, 3), (nx, ny, nz))
     assert torch.equal(zp, zb)
+    zc = model.encode_counts_bf16(db.rerank_pack_pool(lab_d, db.rerank_workspace(3)))
+    assert torch.equal(zc, zb)
+
+
+@pytest.mark.parametrize("dims", [(96, 10, 6), (64, 64, 64), (128, 128, 128)])
+def test_pack_pool_counts_and_packed_queries(dims):
+    """db_rerank_pack_pool: the pooled counts are 8x the oracle's 2x2x2 means of both masks
+    (exactly), and the packed masks, counts, boxes and moments it leaves in the workspace are
+    db_rerank_pack's: the same bits, and the same rerank results bit for bit. Grids with a
+    word count per row of 3, lane units that fill some blocks partly and others not at all,
+    an empty query, a one-voxel query and an all-set query."""
+    need_gpu()
+    from paper_2205_04550_amd import TumorDB
+    import synth
+    nx, ny, nz = dims
+    n, nq = 40, 6
+    rng = np.random.default_rng(nx + ny + nz)
+    lab = rng.integers(0, 4, size=(nq, nz, ny, nx), dtype=np.uint8)
+    lab[1] = 0
+    lab[2] = 0
+    lab[2, nz - 1, ny - 1, nx - 1] = 3
+    lab[3] = 3
+    lab[4, : nz // 2] = 0
+    lab_d = torch.from_numpy(lab).cuda()
+    db = TumorDB(nx, ny, nz, n, synth.T_LO, synth.T_HI)
+    db.append(torch.from_numpy(rng.random((n, nz, ny, nx), dtype=np.float32)).cuda())
+    ws_a, ws_b = db.rerank_workspace(nq), db.rerank_workspace(nq)
+    ws_b.fill_(0xA5)                              # the pooled call must write all it reads
+    db.rerank_pack(lab_d, ws_a)
+    counts = db.rerank_pack_pool(lab_d, ws_b)
+    db.sync()
+    mp = E.meanpool(lab)                           # float64 [nq][2][nz/2][ny/2][nx/2]
+    c = counts.cpu().numpy()
+    assert np.array_equal((c & 15).astype(np.float64), 8 * mp[:, 0])
+    assert np.array_equal((c >> 4).astype(np.float64), 8 * mp[:, 1])
+    assert torch.equal(db.packed_queries(ws_a, nq), db.packed_queries(ws_b, nq))
+    cand = torch.from_numpy(np.stack([rng.choice(n, 12, replace=False) for _ in range(nq)])
+                            .astype(np.int32)).cuda()
+    want = db.rerank_packed(ws_a, cand, 5)
+    got = db.rerank_packed(ws_b, cand, 5)
+    db.sync()
+    for a, w in zip(got, want):
+        assert torch.equal(a, w)
+
+
+def test_pack_pool_rejects_odd_grids_and_bad_pointers():
+    need_gpu()
+    from paper_2205_04550_amd import TumorDB
+    from paper_2205_04550_amd.binding import DbError
+    import synth
+    db = TumorDB(32, 4, 3, 1, synth.T_LO, synth.T_HI)
+    db.append(torch.zeros((1, 3, 4, 32), dtype=torch.float32, device="cuda"))
+    lab = torch.zeros((2, 3, 4, 32), dtype=torch.uint8, device="cuda")
+    with pytest.raises(DbError, match="ny and nz must be even"):
+        db.rerank_pack_pool(lab, db.rerank_workspace(2),
+                            torch.empty((2, 1, 2, 16), dtype=torch.uint8, device="cuda"))
+    db2 = TumorDB(32, 4, 4, 1, synth.T_LO, synth.T_HI)
+    db2.append(torch.zeros((1, 4, 4, 32), dtype=torch.float32, device="cuda"))
+    lab2 = torch.zeros((2, 4, 4, 32), dtype=torch.uint8, device="cuda")
+    buf = torch.empty(2 * 2 * 2 * 16 + 1, dtype=torch.uint8, device="cuda")
+    with pytest.raises(DbError, match="8-byte aligned"):
+        db2.rerank_pack_pool(lab2, db2.rerank_workspace(2), buf[1:].view(2, 2, 2, 16))
