@@ -156,6 +156,17 @@ int nn_conv3d_s2_bwd_weight(int dtype, int B, int Ci, int Co, int D, int H, int 
 /* Y[b,j] = act(bias[j] + sum_i Wt[j,i] X[b,i]); X [B][In], Wt [Out][In]. */
 int nn_linear_fwd(int dtype, int B, int In, int Out, const void *X, const void *Wt, int wdtype,
                   const void *bias, int relu, void *Y, void *stream);
+/* nn_linear_fwd for float X and bfloat16 Wt on the FP32 matrix cores with K split into
+ * `splits` slices, so that a small batch still fills the GPU: slice z sums k in
+ * [z kc, (z + 1) kc) (kc = In / splits rounded up to a multiple of 64) into ws
+ * (float [splits][B][Out], device, ws_bytes >= 4 splits B Out), then a second kernel adds
+ * the slices in order z = 0, 1, ..., adds the bias and applies the ReLU. Deterministic; with
+ * splits = 1 equal to nn_linear_fwd bit for bit, otherwise within the same FP32 sum bound.
+ * Needs In % 4 == 0, X 16-byte and Wt 8-byte aligned, 1 <= splits <= 64, B <= 65535;
+ * DB_EINVAL / DB_ENOSPC otherwise. */
+int nn_linear_fwd_split(int B, int In, int Out, const float *X, const void *Wt,
+                        const float *bias, int relu, float *Y, int splits, float *ws,
+                        size_t ws_bytes, void *stream);
 /* dX[b,i] = sum_j Wt[j,i] dY[b,j]. */
 int nn_linear_bwd_data(int dtype, int B, int In, int Out, const void *dY, const void *Wt,
                        int wdtype, void *dX, void *stream);

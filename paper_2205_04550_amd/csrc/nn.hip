@@ -650,13 +650,16 @@ __device__ __forceinline__ f32x4 ld4_w(const uint16_t *p)
                    __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u)};
 }
 
-template <class WT, bool B_KN>
+// SPLIT: block z multiplies only k in [z kc, (z + 1) kc) (kc a multiple of kMK) and writes its
+// raw sums to C + z M N (no bias, no ReLU); linear_split_final_kernel adds the slices.
+template <class WT, bool B_KN, bool SPLIT = false>
 __global__ void __launch_bounds__(512) linear_mfma_kernel(int M, int N, int K,
                                                           const float *__restrict__ A,
                                                           const WT *__restrict__ Wt,
                                                           const float *__restrict__ bias, int relu,
-                                                          float *__restrict__ C)
+                                                          float *__restrict__ C, int kc = 0)
 {
+    const int kb = SPLIT ? blockIdx.z * kc : 0, ke = SPLIT ? min(K, kb + kc) : K;
     __shared__ __attribute__((aligned(16))) float As[kMM * kMPad];
     __shared__ __attribute__((aligned(16))) float Bs[kMM * kMPad];
     __shared__ float red[4 * 16 * 64];
@@ -678,22 +681,22 @@ __global__ void __launch_bounds__(512) linear_mfma_kernel(int M, int N, int K,
         for (int j = 0; j < kSt; ++j) {
             const int k = k0 + sk;
             const int m = m0 + srow + kRows * j, n = n0 + srow + kRows * j;
-            pa[j] = (m < M && k < K) ? ld4_w(A + (int64_t)m * K + k) : (f32x4){0.f, 0.f, 0.f, 0.f};
+            pa[j] = (m < M && k < ke) ? ld4_w(A + (int64_t)m * K + k) : (f32x4){0.f, 0.f, 0.f, 0.f};
             if (B_KN) {
-                const int kb = k0 + bk + 32 * j, nb = n0 + bq;
-                pb[j] = (kb < K && nb < N) ? ld4_w(Wt + (int64_t)kb * N + nb)
-                                           : (f32x4){0.f, 0.f, 0.f, 0.f};
+                const int kr = k0 + bk + 32 * j, nb = n0 + bq;
+                pb[j] = (kr < ke && nb < N) ? ld4_w(Wt + (int64_t)kr * N + nb)
+                                            : (f32x4){0.f, 0.f, 0.f, 0.f};
             } else {
-                pb[j] = (n < N && k < K) ? ld4_w(Wt + (int64_t)n * K + k)
-                                         : (f32x4){0.f, 0.f, 0.f, 0.f};
+                pb[j] = (n < N && k < ke) ? ld4_w(Wt + (int64_t)n * K + k)
+                                          : (f32x4){0.f, 0.f, 0.f, 0.f};
             }
         }
     };
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-    fetch(0);
-    for (int k0 = 0; k0 < K; k0 += kMK) {
+    fetch(kb);
+    for (int k0 = kb; k0 < ke; k0 += kMK) {
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kSt; ++j) {
@@ -706,7 +709,7 @@ __global__ void __launch_bounds__(512) linear_mfma_kernel(int M, int N, int K,
             }
         }
         __syncthreads();
-        if (k0 + kMK < K) fetch(k0 + kMK);
+        if (k0 + kMK < ke) fetch(k0 + kMK);
         // In product s of this wave's half, lane l supplies row (or column) l % 32 at
         // k = (kMK / 2) (l / 32) + (kMK / 4) kh + s.
         const float *ar = &As[(wm * 32 + r32) * kMPad + (kMK / 2) * h + (kMK / 4) * kh];
@@ -729,14 +732,33 @@ __global__ void __launch_bounds__(512) linear_mfma_kernel(int M, int N, int K,
     const int n = n0 + wn * 32 + r32;
     if (n >= N) return;
     const float bn = bias ? bias[n] : 0.f;
+    if (SPLIT) C += (int64_t)blockIdx.z * M * N;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int m = m0 + wm * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
         if (m < M) {
-            float v = (acc[r] + red[(w4 * 16 + r) * 64 + lane]) + bn;
-            if (relu && v < 0.f) v = 0.f;
+            float v = acc[r] + red[(w4 * 16 + r) * 64 + lane];
+            if (!SPLIT) {
+                v += bn;
+                if (relu && v < 0.f) v = 0.f;
+            }
             C[(int64_t)m * N + n] = v;
         }
+    }
+}
+
+// Y[m][n] = act(sum over z < S of P[z][m][n], in that order, + bias[n]): the slices of a
+// split linear_mfma_kernel. With S = 1 the result is the unsplit kernel's bit for bit.
+__global__ void linear_split_final_kernel(int64_t MN, int N, int S, const float *__restrict__ P,
+                                          const float *__restrict__ bias, int relu,
+                                          float *__restrict__ Y)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < MN;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float v = P[i];
+        for (int z = 1; z < S; ++z) v += P[z * MN + i];
+        v += bias ? bias[i % N] : 0.f;
+        Y[i] = relu && v < 0.f ? 0.f : v;
     }
 }
 
@@ -1847,7 +1869,7 @@ int nn_pool_conv_counts_bf16(const uint8_t *counts, int B, int nx, int ny, int n
         (uintptr_t)counts % 16 || (uintptr_t)Y % 8 || (int64_t)nx * ny * nz >= ((int64_t)1 << 31))
         return tdb_set_error(DB_EINVAL, "nn_pool_conv_counts_bf16: bad arguments");
     const int T = (nx / 128) * ((ny / 4 + 3) / 4) * ((nz / 4 + 1) / 2);
-    const int npb = T % 32 == 0 ? 4 : 1;
+    const int npb = T < 16 ? T : 16;               // tiles per block (the weights loaded once)
     hipLaunchKernelGGL((pool_conv_counts_kernel<true>),
                        dim3((unsigned)((T + npb - 1) / npb), (unsigned)B), dim3(256), 0,
                        static_cast<hipStream_t>(stream), counts, nx, ny, nz, mask,
@@ -2011,6 +2033,28 @@ int nn_conv3d_s2_bwd_weight(int dtype, int B, int Ci, int Co, int D, int H, int 
                            Co, (const double *)ws, (double *)dWt, (double *)dbias);
     }
     return launched("nn_conv3d_s2_bwd_weight");
+}
+
+int nn_linear_fwd_split(int B, int In, int Out, const float *X, const void *Wt,
+                        const float *bias, int relu, float *Y, int splits, float *ws,
+                        size_t ws_bytes, void *stream)
+{
+    if (B <= 0 || In <= 0 || Out <= 0 || B > 65535 || !X || !Wt || !Y || !ws || splits < 1 ||
+        splits > 64 || In % 4 || (uintptr_t)X % 16 || (uintptr_t)Wt % 8)
+        return tdb_set_error(DB_EINVAL, "nn_linear_fwd_split: bad arguments");
+    // K per slice: a multiple of the staging step; trailing slices may be empty (zero sums).
+    const int kc = (In + splits * kMK - 1) / (splits * kMK) * kMK;
+    if (ws_bytes < (size_t)splits * B * Out * sizeof(float))
+        return tdb_set_error(DB_ENOSPC, "nn_linear_fwd_split: workspace %zu bytes < %zu needed",
+                             ws_bytes, (size_t)splits * B * Out * sizeof(float));
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const dim3 mgrid((Out + kMM - 1) / kMM, (B + kMM - 1) / kMM, splits);
+    hipLaunchKernelGGL((linear_mfma_kernel<uint16_t, false, true>), mgrid, dim3(512), 0, s, B,
+                       Out, In, X, (const uint16_t *)Wt, nullptr, 0, ws, kc);
+    const int64_t MN = (int64_t)B * Out;
+    hipLaunchKernelGGL(linear_split_final_kernel, dim3((unsigned)std::min<int64_t>((MN + 255) / 256, 4096)),
+                       dim3(256), 0, s, MN, Out, splits, (const float *)ws, bias, relu, Y);
+    return launched("nn_linear_fwd_split");
 }
 
 int nn_linear_fwd(int dtype, int B, int In, int Out, const void *X, const void *Wt, int wdtype,

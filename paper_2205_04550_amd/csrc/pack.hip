@@ -119,26 +119,6 @@ struct PartAcc {
         }
     }
 
-    // One plane's word b of row (z, y), word wx of the row: the same sums as add() over
-    // the two planes' words of that row taken one at a time (moments from FLAIR only).
-    __device__ void add_plane(uint32_t b, int plane, int wx, int y, int z)
-    {
-        const uint32_t c = popc(b);
-        n0 += plane ? 0u : c;
-        n1 += plane ? c : 0u;
-        if (b) {
-            zlo = min(zlo, z);
-            zhi = max(zhi, z);
-            ylo = min(ylo, y);
-            yhi = max(yhi, y);
-            if (!plane) {
-                sx += (uint64_t)(32u * (uint32_t)wx) * c + bit_position_sum(b);
-                sy += (uint64_t)y * c;
-                sz += (uint64_t)z * c;
-            }
-        }
-    }
-
     // Block-wide sum (at most 4 waves); thread 0 writes the part.
     __device__ void write(QueryPart &p)
     {
@@ -264,13 +244,33 @@ hipError_t launch_pack_queries(const db_t *db, const uint8_t *labels, int nq, co
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 constexpr int kPoolBatch = 2;   // lane units per pass of pack_pool_query_kernel, loads first
 
+// Swap the bits of x selected by mask with the bits d places above them.
+__device__ __forceinline__ uint32_t delta_swap(uint32_t x, uint32_t mask, int d)
+{
+    const uint32_t t = ((x >> d) ^ x) & mask;
+    return x ^ t ^ (t << d);
+}
+
+// The two mask bits of 16 label bytes (x[q] byte r = voxel 4 q + r) as one word: FLAIR of
+// voxel k at bit k, T1Gd of voxel k at bit 16 + k. The masked words are merged so that
+// bit 8 r + 2 q + p holds mask p of voxel 4 q + r; four swaps of index bits (r1 with p, then
+// r0 past q1 and q0 to the bottom) put it at 16 p + 4 q + r.
+__device__ __forceinline__ uint32_t gather_masks(const uint32_t (&a)[4])
+{
+    uint32_t z = a[0] | (a[1] << 2) | (a[2] << 4) | (a[3] << 6);
+    z = delta_swap(z, 0x0000aaaau, 15);
+    z = delta_swap(z, 0x00f000f0u, 4);
+    z = delta_swap(z, 0x0c0c0c0cu, 2);
+    return delta_swap(z, 0x22222222u, 1);
+}
+
 // grid (kQueryParts, nq): pack_query_kernel's outputs (no ROI) and, from the same read of
 // the labels, their pooled counts for the encoder's first layer: uint8 [nq][nz/2][ny/2][nx/2],
 // per 2x2x2 block of voxels its FLAIR count (0..8) in bits 0..3 and its T1Gd count in bits
 // 4..7. Needs ny and nz even. A lane unit is 16 voxels along x in each of the four rows
 // (2 pz + dz, 2 py + dy), 16 label bytes per row; the two units of one word form a lane pair:
-// per row the even lane assembles the FLAIR word and the odd lane the T1Gd word (one
-// exchange), and each lane adds its bytes into the 8 pooled counts of its 16 voxels.
+// per row the even lane stores the FLAIR word and the odd lane the T1Gd word (one exchange),
+// and each lane sums its bytes into the 8 pooled counts of its 16 voxels.
 __global__ void __launch_bounds__(256) pack_pool_query_kernel(const uint8_t *__restrict__ labels,
                                                               int64_t V, int Wp, int nx,
                                                               int ny, uint32_t *__restrict__ qpack,
@@ -279,10 +279,13 @@ __global__ void __launch_bounds__(256) pack_pool_query_kernel(const uint8_t *__r
 {
     const int q = blockIdx.y;
     const u32x4 *lab = reinterpret_cast<const u32x4 *>(labels + (int64_t)q * V);
-    uint32_t *o = qpack + (int64_t)q * 2 * Wp;
+    const int half = threadIdx.x & 1;
+    uint32_t *o = qpack + (int64_t)q * 2 * Wp + half * Wp;   // this lane's plane
     uint8_t *P = pooled + (int64_t)q * (V >> 3);
     const int nxw = nx >> 5, PY = ny >> 1, PX = nx >> 1, rowv = nx >> 4;   // rowv: u32x4 per row
-    const int half = threadIdx.x & 1;
+    // Exchange selector: the even lane keeps its FLAIR half and takes its partner's; the odd
+    // lane takes its partner's T1Gd half and keeps its own.
+    const uint32_t sel = half ? 0x03020706u : 0x05040100u;
     PartAcc acc;   // with ny, nz even W = nxw ny nz is a multiple of 4: no padding words
     const int U = (int)(V >> 6);                       // lane units; ubeg and seg even
     const int seg = 2 * ((U / 2 + gridDim.x - 1) / gridDim.x);
@@ -297,45 +300,66 @@ __global__ void __launch_bounds__(256) pack_pool_query_kernel(const uint8_t *__r
             xw[i] = pair % nxw;
             py[i] = (pair / nxw) % PY;
             pz[i] = pair / (nxw * PY);
+            const int64_t row0 = (int64_t)(2 * pz[i]) * ny + 2 * py[i];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t row = (int64_t)(2 * pz[i] + (r >> 1)) * ny + 2 * py[i] + (r & 1);
                 v[i][r] = (u32x4){0u, 0u, 0u, 0u};
-                if (u < uend) v[i][r] = load_stream(lab + row * rowv + 2 * xw[i] + half);
+                if (u < uend)
+                    v[i][r] = load_stream(lab + (row0 + (r >> 1) * ny + (r & 1)) * rowv +
+                                          2 * xw[i] + half);
             }
         }
 #pragma unroll
         for (int i = 0; i < kPoolBatch; ++i) {
             const bool valid = u0 + i * (int)blockDim.x < uend;
-            uint32_t f[4] = {0u, 0u, 0u, 0u}, h2[4] = {0u, 0u, 0u, 0u};
+            // Per byte, over the four rows: S = FLAIR + 2 T1Gd voxels, T2 = 2 T1Gd voxels.
+            uint32_t S[4] = {0u, 0u, 0u, 0u}, T2[4] = {0u, 0u, 0u, 0u};
+            uint32_t cnt = 0, cdz = 0, cdy = 0, bps = 0;   // this unit's words of this lane's plane
+            uint32_t *ow = o + (int64_t)(2 * pz[i] * ny + 2 * py[i]) * nxw + xw[i];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                uint32_t m0 = 0, m1 = 0;   // this lane's 16 bits of each mask in row r
+                uint32_t a[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    uint32_t f4, t4;
-                    label_nibbles(v[i][r][e], f4, t4);
-                    m0 |= f4 << (4 * e);
-                    m1 |= t4 << (4 * e);
-                    f[e] += v[i][r][e] & 0x01010101u;    // per byte: FLAIR voxels so far
-                    h2[e] += v[i][r][e] & 0x02020202u;   // per byte: twice the T1Gd voxels
+                    a[e] = v[i][r][e] & 0x03030303u;
+                    S[e] += a[e];
+                    T2[e] += a[e] & 0x02020202u;
                 }
-                const uint32_t got = __shfl_xor(half ? m0 : m1, 1, 64);
-                const uint32_t word = half ? (got | (m1 << 16)) : (m0 | (got << 16));
+                const uint32_t z = gather_masks(a);
+                const uint32_t other = __builtin_amdgcn_mov_dpp(z, 0xb1, 0xf, 0xf, true);   // lane ^ 1
+                const uint32_t word = __builtin_amdgcn_perm(other, z, sel);
                 if (valid) {
-                    const int z = 2 * pz[i] + (r >> 1), y = 2 * py[i] + (r & 1);
-                    o[half * Wp + (z * ny + y) * nxw + xw[i]] = word;
-                    acc.add_plane(word, half, xw[i], y, z);
+                    const int dz = r >> 1, dy = r & 1;
+                    ow[(dz * ny + dy) * nxw] = word;
+                    const uint32_t c = popc(word);
+                    cnt += c;
+                    cdz += dz ? c : 0u;
+                    cdy += dy ? c : 0u;
+                    if (word) {
+                        const int zz = 2 * pz[i] + dz, yy = 2 * py[i] + dy;
+                        acc.zlo = min(acc.zlo, zz);
+                        acc.zhi = max(acc.zhi, zz);
+                        acc.ylo = min(acc.ylo, yy);
+                        acc.yhi = max(acc.yhi, yy);
+                        if (!half) bps += bit_position_sum(word);
+                    }
                 }
+            }
+            if (half) {
+                acc.n1 += cnt;
+            } else {
+                acc.n0 += cnt;
+                acc.sx += (uint64_t)(32u * (uint32_t)xw[i]) * cnt + bps;
+                acc.sy += (uint64_t)(2u * (uint32_t)py[i]) * cnt + cdy;
+                acc.sz += (uint64_t)(2u * (uint32_t)pz[i]) * cnt + cdz;
             }
             // Byte pairs (x, x + 1) -> pooled counts: FLAIR in bits 0..3, T1Gd in 4..7 of
             // bytes 0 and 2 of c[e] (pooled x 2 e and 2 e + 1 of this lane's 8).
             uint32_t c[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const uint32_t fp = (f[e] & 0x00ff00ffu) + ((f[e] >> 8) & 0x00ff00ffu);
-                const uint32_t hp = (h2[e] & 0x00ff00ffu) + ((h2[e] >> 8) & 0x00ff00ffu);
-                c[e] = fp | (hp << 3);
+                const uint32_t b = (S[e] - T2[e]) | (T2[e] << 3);
+                c[e] = (b & 0x00ff00ffu) + ((b >> 8) & 0x00ff00ffu);
             }
             if (valid) {
                 const u32x2 pw = {__builtin_amdgcn_perm(c[1], c[0], 0x06040200u),

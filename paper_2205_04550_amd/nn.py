@@ -62,6 +62,8 @@ _SIGS = {
     "nn_pool_conv_counts_bf16": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _i32,
                                         _vp, _vp]),
     "nn_conv3d_weights_tapmajor": (_i32, [_vp, _i32, _i32, _vp, _vp]),
+    "nn_linear_fwd_split": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _sz,
+                                   _vp]),
     "nn_conv3d_s2_fwd_bf16": (_i32, [_i32] * 6 + [_vp, _vp, _vp, _i32, _i32, _vp, _vp]),
 }
 for _n, (_r, _a) in _SIGS.items():
@@ -229,6 +231,24 @@ def pool_conv_counts_bf16(counts: torch.Tensor, w_bf16: torch.Tensor, bias: torc
     _check(LIB.nn_pool_conv_counts_bf16(counts.data_ptr(), B, nx, ny, nz,
                                         -1 if mask is None else mask, Co, w_bf16.data_ptr(),
                                         _p(bias), int(relu), y.data_ptr(), _s()))
+    return y
+
+
+def linear_split(x: torch.Tensor, w_bf16: torch.Tensor, bias: torch.Tensor | None,
+                 relu: bool = False, splits: int = 4) -> torch.Tensor:
+    """Forward-only linear layer (float x [B][In], bfloat16 weights [Out][In]) with K split into
+    `splits` slices summed in a fixed order: the encoder head for a batch of queries."""
+    x = _c(x)
+    B, In = x.shape
+    Out = w_bf16.shape[0]
+    assert x.dtype == torch.float32 and w_bf16.dtype == torch.bfloat16 and w_bf16.shape[1] == In
+    w_bf16 = _c(w_bf16)
+    bias = None if bias is None else _c(bias.detach())
+    y = torch.empty((B, Out), dtype=torch.float32, device=x.device)
+    ws = torch.empty(splits * B * Out, dtype=torch.float32, device=x.device)
+    _check(LIB.nn_linear_fwd_split(B, In, Out, x.data_ptr(), w_bf16.data_ptr(), _p(bias),
+                                   int(relu), y.data_ptr(), splits, ws.data_ptr(),
+                                   ws.numel() * 4, _s()))
     return y
 
 
@@ -635,7 +655,9 @@ class AutoEncoder:
             for i in range(1, 4):
                 w, b, wc = self._w(f"enc{i}")
                 h = conv3d_bf16(h, tm[f"enc{i}"], b, True, out_f32=(i == 3))
-            return self._head(h.reshape(h.shape[0], -1))
+            w, b, wc = self._w("enc_fc")
+            L = self.latent
+            return linear_split(h.reshape(h.shape[0], -1), wc[:L], b[:L])
 
     def encode_labels_bf16(self, labels: torch.Tensor, mask: int | None = None) -> torch.Tensor:
         """Latents of query labels [B][nz][ny][nx] by the BF16 forward."""

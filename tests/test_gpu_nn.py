@@ -324,6 +324,35 @@ def test_linear_forward_matrix_core(shape):
             assert ok, (shape, wdt, relu, worst)
 
 
+@pytest.mark.parametrize("shape", [(1024, 4096, 512), (70, 1000, 130), (5, 8, 3)])
+def test_linear_split_forward(shape):
+    """The head's split-K forward: with one slice the unsplit kernel's bits; with 4, 7 and 8
+    slices (some empty when K is small, the last one ragged) within the FP32 sum bound of the
+    float64 product and the same bits on a second call."""
+    need_gpu()
+    from paper_2205_04550_amd import nn
+    B, In, Out = shape
+    g = torch.Generator().manual_seed(B + In + Out + 1)
+    x64 = torch.randn(B, In, generator=g, dtype=torch.float64)
+    w64 = torch.randn(Out, In, generator=g, dtype=torch.float64) * (1.0 / math.sqrt(In))
+    b64 = torch.randn(Out, generator=g, dtype=torch.float64)
+    wc = w64.to(torch.bfloat16)
+    x = x64.to("cuda", torch.float32)
+    for relu in (False, True):
+        want = nn.Linear.apply(x, w64.cuda().float(), b64.cuda().float(), wc.cuda(), relu)
+        y1 = nn.linear_split(x, wc.cuda(), b64.cuda().float(), relu, splits=1)
+        assert torch.equal(y1, want), (shape, relu)
+        yr = x64 @ wc.to(torch.float64).T + b64
+        yr = torch.relu(yr) if relu else yr
+        S = x64.abs() @ wc.to(torch.float64).abs().T + b64.abs()
+        for splits in (4, 7, 8):
+            y = nn.linear_split(x, wc.cuda(), b64.cuda().float(), relu, splits=splits)
+            ok, worst = _within_sum_bound(y, yr, S, In)
+            assert ok, (shape, relu, splits, worst)
+            assert torch.equal(y, nn.linear_split(x, wc.cuda(), b64.cuda().float(), relu,
+                                                  splits=splits))
+
+
 @pytest.mark.parametrize("shape", [(3, 4, 20, 14, 10, 40), (2, 32, 64, 8, 8, 8), (2, 20, 16, 18, 12, 20),
                                    (1, 8, 16, 32, 32, 32), (2, 16, 33, 6, 22, 12), (2, 12, 8, 4, 6, 36)])
 def test_conv_forward_matrix_core(shape):

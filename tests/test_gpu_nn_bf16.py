@@ -166,6 +166,37 @@ def test_encode_bf16_matches_oracle():
     assert torch.equal(zc, zb)
 
 
+@pytest.mark.parametrize("dims", [(128, 20, 12), (256, 36, 28)])
+def test_first_layer_from_counts_on_ragged_grids(dims):
+    """The first layer from pooled counts equals the labels path bit for bit where tiles are
+    cut by the grid (output y and z not multiples of the 4 x 2 tile), where a sample has two
+    tile columns (the halo count taken from the neighbouring column) and where a block has
+    fewer tiles than the launch gives it."""
+    need_gpu()
+    from paper_2205_04550_amd import TumorDB, nn
+    import synth
+    nx, ny, nz = dims
+    B = 3
+    rng = np.random.default_rng(nx + ny)
+    lab = rng.integers(0, 4, size=(B, nz, ny, nx), dtype=np.uint8)
+    lab[1, :, : ny // 2] = 0
+    lab_d = torch.from_numpy(lab).cuda()
+    db = TumorDB(nx, ny, nz, 1, synth.T_LO, synth.T_HI)
+    db.append(torch.zeros((1, nz, ny, nx), dtype=torch.float32, device="cuda"))
+    counts = db.rerank_pack_pool(lab_d, db.rerank_workspace(B))
+    g = torch.Generator().manual_seed(9)
+    for mask in (None, 0, 1):
+        ci = 2 if mask is None else 1
+        wc = (torch.randn(8, ci, 3, 3, 3, generator=g) * 0.3).to(torch.bfloat16).cuda()
+        b = torch.randn(8, generator=g).cuda()
+        for relu in (True, False):
+            yb = nn.pool_conv_labels_bf16(lab_d, wc, b, relu, mask)
+            yc = nn.pool_conv_counts_bf16(counts, wc, b, relu, mask)
+            assert torch.equal(yc.view(torch.int16), yb.view(torch.int16)), (mask, relu)
+            yf = nn.pool_conv_labels(lab_d, wc, b, relu, mask)
+            assert torch.equal(yb, yf.permute(0, 2, 3, 4, 1).to(torch.bfloat16)), (mask, relu)
+
+
 @pytest.mark.parametrize("dims", [(96, 10, 6), (64, 64, 64), (128, 128, 128)])
 def test_pack_pool_counts_and_packed_queries(dims):
     """db_rerank_pack_pool: the pooled counts are 8x the oracle's 2x2x2 means of both masks
