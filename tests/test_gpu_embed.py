@@ -233,6 +233,42 @@ def test_rerank_bit_exact_and_full_candidate_set_equals_scan():
         assert torch.equal(ri[q], si) and torch.equal(rs[q], ss) and torch.equal(rc[q], sc_)
 
 
+@pytest.mark.parametrize("nq,nc", [(70, 100), (96, 128)])
+def test_rerank_batch_with_shared_candidates_bit_exact(nq, nc):
+    """A batch of many queries whose candidates are drawn from 150 entries (each entry a
+    candidate of many queries): the top-k, scores and counts equal the oracle's exhaustive
+    loop and those of the same queries reranked in batches of 10, bit for bit; an empty query
+    and a one-voxel query among them."""
+    need_gpu()
+    gen = synth.SMALL
+    n = 300
+    db, conc = build_db_from_host(gen, n, synth.T_LO, synth.T_HI)
+    labels, _ = synth.make_queries(gen, n, nq, synth.BATCH_QUERY_SEED)
+    labels[5] = 0
+    labels[9] = 0
+    labels[9, 30, 31, 32] = 3
+    rng = np.random.default_rng(nq + nc)
+    cand = np.stack([rng.choice(150, nc, replace=False) for _ in range(nq)]).astype(np.int32)
+    lab_d = torch.from_numpy(labels).cuda()
+    cand_d = torch.from_numpy(cand).cuda()
+    k = 12
+    idx, score, counts = db.rerank(lab_d, cand_d, k)
+    db.sync()
+    cnt, sc = oracle.scan_block_multi(conc[:150], labels, synth.T_LO, synth.T_HI)
+    for q in range(nq):
+        order = sorted(range(nc), key=lambda j: (-sc[q, cand[q][j]], cand[q][j]))[:k]
+        assert idx[q].cpu().tolist() == [int(cand[q][j]) for j in order], q
+        assert np.array_equal(score[q].cpu().numpy().view(np.uint64),
+                              sc[q, cand[q][order]].view(np.uint64)), q
+        assert np.array_equal(counts[q].cpu().numpy().view(np.uint32).astype(np.uint64),
+                              cnt[q, cand[q][order]]), q
+    for q0 in range(0, nq, 10):
+        pi, ps, pc = db.rerank(lab_d[q0:q0 + 10], cand_d[q0:q0 + 10], k)
+        db.sync()
+        assert torch.equal(pi, idx[q0:q0 + 10]) and torch.equal(ps, score[q0:q0 + 10])
+        assert torch.equal(pc, counts[q0:q0 + 10])
+
+
 def test_query_embed_chain_matches_its_parts():
     need_gpu()
     from paper_2205_04550_amd import binding as b, nn
