@@ -528,31 +528,37 @@ VAE_BETA = 1e-5    # KL weight against the per-voxel mean MSE (about 2.6 against
 
 
 def rerank_bytes(db, lab_d, cand, gen, lines: bool = False) -> float:
-    """Database bytes the candidate-scoring kernel reads: per (query, candidate), the rows
-    inside both the query's and the candidate's row box, 2 masks (measurement bookkeeping).
-    lines=True counts the 128-byte cache lines those rows touch instead (the rows of one
-    z-slice are contiguous, so a slice's run starts and ends inside a line)."""
+    """Database bytes the candidate-scoring kernel reads: per (query, candidate), the FLAIR
+    plane's rows inside both the query's and the candidate's row box and the T1Gd plane's
+    rows inside both T1Gd row boxes (measurement bookkeeping). lines=True counts the 128-byte
+    cache lines those rows touch instead (the rows of one z-slice are contiguous, so a
+    slice's run starts and ends inside a line)."""
     import torch
     nxw = gen.nx // 32
-    rows = ((lab_d & 3).reshape(lab_d.shape[0], gen.nz, gen.ny, gen.nx).amax(dim=3) != 0)
-    zany, yany = rows.any(dim=2), rows.any(dim=1)
+    rb = nxw * 4                                                   # bytes per row and plane
     ar_z = torch.arange(gen.nz, device=lab_d.device)
     ar_y = torch.arange(gen.ny, device=lab_d.device)
     big = 1 << 20
-    qz0 = torch.where(zany, ar_z, big).amin(1)
-    qz1 = torch.where(zany, ar_z + 1, -big).amax(1)
-    qy0 = torch.where(yany, ar_y, big).amin(1)
-    qy1 = torch.where(yany, ar_y + 1, -big).amax(1)
-    eb = db.boxes[cand.to(torch.int64)].to(torch.int64)           # [nq][nc][4]
-    dz = (torch.minimum(eb[..., 1], qz1[:, None]) - torch.maximum(eb[..., 0], qz0[:, None])).clamp(min=0)
-    y0 = torch.maximum(eb[..., 2], qy0[:, None])
-    y1 = torch.minimum(eb[..., 3], qy1[:, None])
-    if lines:
-        rb = nxw * 4
-        ln = torch.where(y1 > y0, (y1 * rb + 127) // 128 - (y0 * rb) // 128, torch.zeros_like(y0))
-        return float((dz * ln).sum()) * 2 * 128
-    dy = (y1 - y0).clamp(min=0)
-    return float((dz * dy).sum()) * 2 * nxw * 4
+    total = 0.0
+    for bits, boxes in ((3, db.boxes), (2, db.tboxes)):
+        rows = ((lab_d & bits).reshape(lab_d.shape[0], gen.nz, gen.ny, gen.nx).amax(dim=3) != 0)
+        zany, yany = rows.any(dim=2), rows.any(dim=1)
+        qz0 = torch.where(zany, ar_z, big).amin(1)
+        qz1 = torch.where(zany, ar_z + 1, -big).amax(1)
+        qy0 = torch.where(yany, ar_y, big).amin(1)
+        qy1 = torch.where(yany, ar_y + 1, -big).amax(1)
+        eb = boxes[cand.to(torch.int64)].to(torch.int64)          # [nq][nc][4]
+        dz = (torch.minimum(eb[..., 1], qz1[:, None]) -
+              torch.maximum(eb[..., 0], qz0[:, None])).clamp(min=0)
+        y0 = torch.maximum(eb[..., 2], qy0[:, None])
+        y1 = torch.minimum(eb[..., 3], qy1[:, None])
+        if lines:
+            ln = torch.where(y1 > y0, (y1 * rb + 127) // 128 - (y0 * rb) // 128,
+                             torch.zeros_like(y0))
+            total += float((dz * ln).sum()) * 128
+        else:
+            total += float((dz * (y1 - y0).clamp(min=0)).sum()) * rb
+    return total
 
 
 def encoder_forward_flop(model, nq: int) -> float:
@@ -704,7 +710,8 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
                      "kernel": "rerank_score_kernel", "kernel_avg_ms": rr_avg,
                      "algorithmic_bytes_per_launch": rr_bytes,
                      "note": "the longest single launch of the step; bytes = database rows inside "
-                             "(query row box n candidate row box), both masks"},
+                             "(query row box n candidate row box) for FLAIR, inside (query T1Gd "
+                             "row box n candidate T1Gd row box) for T1Gd"},
         "encode_stage_roofline": {
             "bound": "hbm", "achieved": enc_bytes / (stage[0] * 1e-3) / 1e9,
             "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -79,7 +79,10 @@ enum {
  *   moments:  uint64 [capacity][4] = sum of x, of y, of z over the FLAIR
  *             voxels, and their count (the centre of mass is sum / count);
  *   order:    int32 [capacity], the entries grouped by row-box centre for
- *             db_query_batch (library-internal).
+ *             db_query_batch (library-internal);
+ *   tbox:     int32 [capacity][4], the box of the x-rows holding a T1Gd bit
+ *             (as box, for that mask alone; the rerank reads an entry's T1Gd
+ *             plane only inside it).
  * Returns 0 if the dimensions are invalid. */
 size_t db_storage_bytes(int nx, int ny, int nz, int64_t capacity);
 
@@ -94,7 +97,7 @@ int db_build(db_t **out, int nx, int ny, int nz, float t_lo, float t_hi, int64_t
  * 16-byte aligned) into entries db_size() .. db_size()+n-1 (Sec. 2.3: the
  * masks are extracted from the raw simulations once, before any query).
  * DB_ENOSPC if capacity would be exceeded. The input may be released once the
- * stream has passed this call. Also fills the entries' box and moments. */
+ * stream has passed this call. Also fills the entries' boxes and moments. */
 int db_append(db_t *db, const float *conc, int64_t n, void *stream);
 
 /* Number of entries appended so far (-1 for an invalid handle). */
@@ -276,7 +279,10 @@ int emb_knn(int fmt, int M, int N, int dim, const void *q_codes, const float *q_
 /* Exact re-scoring: for query q (labels [nq][nz][ny][nx]) and its candidate
  * entries cand [nq][nc] (device int32, each in [0, db_size())), the k best by
  * Dice_T1Gd + Dice_FLAIR (score desc, index asc) among the candidates.
- * nc <= DB_KMAX, k <= nc. Candidates must be distinct within a row. */
+ * nc <= DB_KMAX, k <= nc. Candidates must be distinct within a row. Each
+ * overlap is counted over the x-rows inside both sides' boxes of that mask
+ * (the FLAIR overlap inside both row boxes, the T1Gd one inside both T1Gd
+ * boxes): every other row is zero on one side. */
 size_t db_rerank_workspace_bytes(const db_t *db, int nq);
 int db_rerank(const db_t *db, int nq, const uint8_t *q_labels, const int32_t *cand, int nc, int k,
               int32_t *idx, double *score, db_counts_t *counts, void *ws, size_t ws_bytes,

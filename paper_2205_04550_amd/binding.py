@@ -163,7 +163,8 @@ class TumorDB:
         box = pc + up(self.capacity * 8)
         mom = box + up(self.capacity * 16)
         order = mom + up(self.capacity * 32)
-        return pc, box, mom, order
+        tbox = order + up(self.capacity * 4)
+        return pc, box, mom, order, tbox
 
     @property
     def popcounts(self) -> torch.Tensor:
@@ -175,6 +176,12 @@ class TumorDB:
     def boxes(self) -> torch.Tensor:
         """int32 view [capacity][4] of the row boxes z0, z1, y0, y1 of the set bits."""
         off = self._offsets()[1]
+        return self.storage[off:off + self.capacity * 16].view(torch.int32).view(self.capacity, 4)
+
+    @property
+    def tboxes(self) -> torch.Tensor:
+        """int32 view [capacity][4] of the row boxes z0, z1, y0, y1 of the T1Gd bits alone."""
+        off = self._offsets()[4]
         return self.storage[off:off + self.capacity * 16].view(torch.int32).view(self.capacity, 4)
 
     @property

@@ -334,7 +334,8 @@ size_t db_storage_bytes(int nx, int ny, int nz, int64_t capacity)
         return 0;
     return align_up((size_t)capacity * 2 * g.Wp * 4, kAlign) +
            align_up((size_t)capacity * 2 * 4, kAlign) + align_up((size_t)capacity * 4 * 4, kAlign) +
-           align_up((size_t)capacity * 4 * 8, kAlign) + align_up((size_t)capacity * 4, kAlign);
+           align_up((size_t)capacity * 4 * 8, kAlign) + align_up((size_t)capacity * 4, kAlign) +
+           align_up((size_t)capacity * 4 * 4, kAlign);
 }
 
 int db_build(db_t **out, int nx, int ny, int nz, float t_lo, float t_hi, int64_t capacity,
@@ -382,6 +383,8 @@ int db_build(db_t **out, int nx, int ny, int nz, float t_lo, float t_hi, int64_t
     db->mom = reinterpret_cast<uint64_t *>(static_cast<char *>(storage) + o_mom);
     const size_t o_ord = o_mom + align_up((size_t)capacity * 4 * 8, kAlign);
     db->tile_order = reinterpret_cast<int32_t *>(static_cast<char *>(storage) + o_ord);
+    const size_t o_tbox = o_ord + align_up((size_t)capacity * 4, kAlign);
+    db->tbox = reinterpret_cast<int32_t *>(static_cast<char *>(storage) + o_tbox);
     db->tile_order_n = 0;
     db->storage_bytes = storage_bytes;
     db->cus = cus;
@@ -414,7 +417,8 @@ int db_append(db_t *db, const float *conc, int64_t n, void *stream)
     uint32_t *pc = db->popcnt + db->count * 2;
     hipError_t e = launch_pack_db(db, conc, n, planes, pc, s);
     if (e == hipSuccess)
-        e = launch_meta(planes, n, db->g, db->box + db->count * 4, db->mom + db->count * 4, s);
+        e = launch_meta(planes, n, db->g, db->box + db->count * 4, db->tbox + db->count * 4,
+                        db->mom + db->count * 4, s);
     if (e != hipSuccess) return hip_fail(e, "db_append: launch");
     db->count += n;
     return DB_OK;
@@ -915,7 +919,7 @@ int emb_knn(int fmt, int M, int N, int dim, const void *q_codes, const float *q_
 
 static size_t rerank_layout(const db_t *db, int nq, size_t *o_qpack, size_t *o_qpart,
                             size_t *o_acnt, size_t *o_box, size_t *o_mom = nullptr,
-                            size_t *o_scored = nullptr)
+                            size_t *o_scored = nullptr, size_t *o_tbox = nullptr)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -931,6 +935,8 @@ static size_t rerank_layout(const db_t *db, int nq, size_t *o_qpack, size_t *o_q
     if (o_mom) *o_mom = om;
     const size_t osc = take(rerank_ws_bytes(nq));
     if (o_scored) *o_scored = osc;
+    const size_t otb = take((size_t)nq * 4 * 4);
+    if (o_tbox) *o_tbox = otb;
     return off;
 }
 
@@ -943,12 +949,12 @@ size_t db_rerank_workspace_bytes(const db_t *db, int nq)
 
 // Score the candidates (the dominant kernel of a rerank: profiled), then rank them.
 static hipError_t rerank_launches(const db_t *db, int nq, const uint32_t *qpack,
-                                  const uint32_t *acnt, const int32_t *box, const int32_t *cand,
-                                  int nc, int k, int32_t *idx, double *score, db_counts_t *counts,
-                                  void *ws, hipStream_t s)
+                                  const uint32_t *acnt, const int32_t *box, const int32_t *tbox,
+                                  const int32_t *cand, int nc, int k, int32_t *idx, double *score,
+                                  db_counts_t *counts, void *ws, hipStream_t s)
 {
     hipError_t e = prof_mark(db, s);
-    if (e == hipSuccess) e = launch_rerank_score(db, nq, qpack, acnt, box, cand, nc, ws, s);
+    if (e == hipSuccess) e = launch_rerank_score(db, nq, qpack, acnt, box, tbox, cand, nc, ws, s);
     if (e == hipSuccess) e = prof_mark(db, s);
     if (e == hipSuccess) e = launch_rerank_rank(db, nq, acnt, nc, k, idx, score, counts, ws, s);
     return e;
@@ -959,15 +965,15 @@ static hipError_t rerank_launches(const db_t *db, int nq, const uint32_t *qpack,
 static hipError_t enqueue_rerank_pack(const db_t *db, int nq, const uint8_t *q_labels, void *ws,
                                       hipStream_t s, uint8_t *pooled = nullptr)
 {
-    size_t oq, op, oa, ob, om, osc;
-    rerank_layout(db, nq, &oq, &op, &oa, &ob, &om, &osc);
+    size_t oq, op, oa, ob, om, osc, otb;
+    rerank_layout(db, nq, &oq, &op, &oa, &ob, &om, &osc, &otb);
     hipError_t e = pooled ? launch_pack_pool_queries(db, q_labels, nq, at<uint32_t>(ws, oq),
                                                      at<QueryPart>(ws, op), pooled, s)
                           : launch_pack_queries(db, q_labels, nq, nullptr, at<uint32_t>(ws, oq),
                                                 at<QueryPart>(ws, op), s);
     if (e == hipSuccess)
         e = launch_sum_parts(at<QueryPart>(ws, op), nq, at<uint32_t>(ws, oa), at<int32_t>(ws, ob),
-                             at<uint64_t>(ws, om), s);
+                             at<uint64_t>(ws, om), s, at<int32_t>(ws, otb));
     return e;
 }
 
@@ -976,10 +982,11 @@ static hipError_t enqueue_rerank_score(const db_t *db, int nq, const int32_t *ca
                                        int32_t *idx, double *score, db_counts_t *counts, void *ws,
                                        hipStream_t s)
 {
-    size_t oq, op, oa, ob, om, osc;
-    rerank_layout(db, nq, &oq, &op, &oa, &ob, &om, &osc);
+    size_t oq, op, oa, ob, om, osc, otb;
+    rerank_layout(db, nq, &oq, &op, &oa, &ob, &om, &osc, &otb);
     return rerank_launches(db, nq, at<uint32_t>(ws, oq), at<uint32_t>(ws, oa), at<int32_t>(ws, ob),
-                           cand, nc, k, idx, score, counts, at<char>(ws, osc), s);
+                           at<int32_t>(ws, otb), cand, nc, k, idx, score, counts,
+                           at<char>(ws, osc), s);
 }
 
 static hipError_t enqueue_rerank(const db_t *db, int nq, const uint8_t *q_labels,
@@ -1179,23 +1186,24 @@ int db_query_com(const db_t *db, int nq, const uint8_t *q_labels, int n_cand, in
     int32_t *ci = cand_idx ? cand_idx : at<int32_t>(ws, oci);
     float *cd = cand_d ? cand_d : at<float>(ws, ocd);
     char *rr = at<char>(ws, orr);
-    size_t oq, op, oa, ob, om, osc;
-    rerank_layout(db, nq, &oq, &op, &oa, &ob, &om, &osc);
+    size_t oq, op, oa, ob, om, osc, otb;
+    rerank_layout(db, nq, &oq, &op, &oa, &ob, &om, &osc, &otb);
     uint32_t *qpack = at<uint32_t>(rr, oq);
     uint32_t *acnt = at<uint32_t>(rr, oa);
-    int32_t *box = at<int32_t>(rr, ob);
+    int32_t *box = at<int32_t>(rr, ob), *tbox = at<int32_t>(rr, otb);
     uint64_t *qmom = at<uint64_t>(rr, om);
     QueryPart *qpart = at<QueryPart>(rr, op);
     hipError_t e = launch_pack_queries(db, q_labels, nq, nullptr, qpack, qpart, s);
-    if (e == hipSuccess) e = launch_sum_parts(qpart, nq, acnt, box, qmom, s);
+    if (e == hipSuccess) e = launch_sum_parts(qpart, nq, acnt, box, qmom, s, tbox);
     if (e == hipSuccess) e = launch_com_dist(nq, qmom, db->mom, (int)n, D, s);
     size_t osel, sel_bytes;
     embed_layout(db, nq, n_cand, &oD, &oci, &ocd, &orr, &osel, &sel_bytes);
     if (e == hipSuccess)
         e = launch_topk_min(nq, (int)n, n_cand, D, ci, cd, sel_bytes ? at<char>(ws, osel) : nullptr,
                             sel_bytes, s);
-    if (e == hipSuccess) e = rerank_launches(db, nq, qpack, acnt, box, ci, n_cand, k, idx, score,
-                                             counts, at<char>(rr, osc), s);
+    if (e == hipSuccess)
+        e = rerank_launches(db, nq, qpack, acnt, box, tbox, ci, n_cand, k, idx, score, counts,
+                            at<char>(rr, osc), s);
     if (e != hipSuccess) return hip_fail(e, "db_query_com: launch");
     return DB_OK;
 }
@@ -1235,7 +1243,8 @@ int db_append_resampled(db_t *dst, const db_t *src, int64_t first, int64_t n, vo
     hipError_t e = launch_resample_db(src, first, n, dst, maps, s);
     if (e == hipSuccess)
         e = launch_meta(dst->planes + dst->count * 2 * (int64_t)dst->g.Wp, n, dst->g,
-                        dst->box + dst->count * 4, dst->mom + dst->count * 4, s);
+                        dst->box + dst->count * 4, dst->tbox + dst->count * 4,
+                        dst->mom + dst->count * 4, s);
     if (e != hipSuccess) return hip_fail(e, "db_append_resampled: launch");
     dst->count += n;
     return DB_OK;

@@ -507,16 +507,19 @@ constexpr int kRerankPerBlock = 4 * kRC;   // candidates scored per block (4 wav
 // gives every block of query q to XCD q % 8, so the query's rows are fetched into
 // one L2 only. Each wave scores
 // kRC candidates of query q at once: lanes sweep the rows where the query's row
-// box meets the candidates' stored row boxes (outside either box one side is
-// zero and adds nothing), AND + popcount against each candidate's planes; the
-// score and overlaps go to ws (score bits [nq][nc], index [nq][nc], I [nq][nc][2]).
+// boxes meet the candidates' stored row boxes (outside either box one side is
+// zero and adds nothing; the T1Gd plane has boxes of its own, smaller than those
+// of both masks), AND + popcount against each candidate's planes; the score and
+// overlaps go to ws (score bits [nq][nc], index [nq][nc], I [nq][nc][2]).
 __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__restrict__ planes,
                                                            const uint32_t *__restrict__ popcnt,
-                                                           const int32_t *__restrict__ ebox, int Wp,
+                                                           const int32_t *__restrict__ ebox,
+                                                           const int32_t *__restrict__ etbox, int Wp,
                                                            int nxw, int ny,
                                                            const uint32_t *__restrict__ qpack,
                                                            const uint32_t *__restrict__ acnt,
                                                            const int32_t *__restrict__ box,
+                                                           const int32_t *__restrict__ tbox,
                                                            const int32_t *__restrict__ cand, int nc,
                                                            uint64_t *__restrict__ ws_s,
                                                            int32_t *__restrict__ ws_i,
@@ -528,16 +531,18 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
     if (q >= nq) return;                       // whole block, before any barrier
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t *Q0 = qpack + (int64_t)q * 2 * Wp, *Q1 = Q0 + Wp;
-    const int32_t *b = box + 4 * q;
+    const int32_t *b = box + 4 * q, *tb = tbox + 4 * q;
     const int qz0 = b[0], qz1 = b[1], qy0 = b[2], qy1 = b[3];
+    const int tqz0 = tb[0], tqz1 = tb[1], tqy0 = tb[2], tqy1 = tb[3];
     const uint32_t A0 = acnt[2 * q], A1 = acnt[2 * q + 1];
-    // kRC candidates per wave: each query row is loaded once per group, and the
-    // group sweeps the union of its members' boxes (each clipped to the query's);
-    // a member reads only the rows inside its own box.
+    // kRC candidates per wave: each query row is loaded once per group, and the group sweeps
+    // the union of its members' boxes. A member reads its FLAIR rows inside (its row box n the
+    // query's) and its T1Gd rows inside (its T1Gd box n the query's): outside either pair of
+    // boxes one of the two masks is empty.
     const int c0 = qb * kRerankPerBlock + wave * kRC;
     if (c0 >= nc) return;   // a whole wave leaves; no block barrier below
     const uint32_t *D0[kRC], *D1[kRC];
-    int z0[kRC], z1[kRC], y0[kRC], y1[kRC];
+    int z0[kRC], z1[kRC], y0[kRC], y1[kRC], tz0[kRC], tz1[kRC], ty0[kRC], ty1[kRC];
     int uz0 = INT_MAX, uz1 = INT_MIN, uy0 = INT_MAX, uy1 = INT_MIN;
 #pragma unroll
     for (int j = 0; j < kRC; ++j) {
@@ -545,16 +550,26 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
         const int32_t e = cand[(int64_t)q * nc + c];
         D0[j] = planes + (int64_t)e * 2 * Wp;
         D1[j] = D0[j] + Wp;
-        const int32_t *eb = ebox + 4 * (int64_t)e;
+        const int32_t *eb = ebox + 4 * (int64_t)e, *etb = etbox + 4 * (int64_t)e;
         z0[j] = max(eb[0], qz0);
         z1[j] = min(eb[1], qz1);
         y0[j] = max(eb[2], qy0);
         y1[j] = min(eb[3], qy1);
+        tz0[j] = max(etb[0], tqz0);
+        tz1[j] = min(etb[1], tqz1);
+        ty0[j] = max(etb[2], tqy0);
+        ty1[j] = min(etb[3], tqy1);
         if (z1[j] > z0[j] && y1[j] > y0[j]) {
             uz0 = min(uz0, z0[j]);
             uz1 = max(uz1, z1[j]);
             uy0 = min(uy0, y0[j]);
             uy1 = max(uy1, y1[j]);
+        }
+        if (tz1[j] > tz0[j] && ty1[j] > ty0[j]) {
+            uz0 = min(uz0, tz0[j]);
+            uz1 = max(uz1, tz1[j]);
+            uy0 = min(uy0, ty0[j]);
+            uy1 = max(uy1, ty1[j]);
         }
     }
     const int nyr = uy1 > uy0 ? uy1 - uy0 : 0;
@@ -568,7 +583,6 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
         constexpr int U = 2;
         for (int r0 = lane; r0 < nr; r0 += 64 * U) {
             u32x4 qa[U], qb[U], da[U][kRC], db[U][kRC];
-            bool in[U][kRC];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int r = r0 + 64 * u;
@@ -576,20 +590,20 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
                 const int z = uz0 + zr, y = uy0 + r - zr * nyr;
                 const int base = (z * ny + y) * 4;
                 const bool live = r < nr;
-                qa[u] = qb[u] = (u32x4){0u, 0u, 0u, 0u};
-                if (live) {
-                    qa[u] = *reinterpret_cast<const u32x4 *>(Q0 + base);
-                    qb[u] = *reinterpret_cast<const u32x4 *>(Q1 + base);
-                }
+                bool any0 = false, any1 = false;
 #pragma unroll
                 for (int j = 0; j < kRC; ++j) {
-                    in[u][j] = live && z >= z0[j] && z < z1[j] && y >= y0[j] && y < y1[j];
+                    const bool in0 = live && z >= z0[j] && z < z1[j] && y >= y0[j] && y < y1[j];
+                    const bool in1 = live && z >= tz0[j] && z < tz1[j] && y >= ty0[j] && y < ty1[j];
+                    any0 |= in0;
+                    any1 |= in1;
                     da[u][j] = db[u][j] = (u32x4){0u, 0u, 0u, 0u};
-                    if (in[u][j]) {
-                        da[u][j] = load_stream(reinterpret_cast<const u32x4 *>(D0[j] + base));
-                        db[u][j] = load_stream(reinterpret_cast<const u32x4 *>(D1[j] + base));
-                    }
+                    if (in0) da[u][j] = load_stream(reinterpret_cast<const u32x4 *>(D0[j] + base));
+                    if (in1) db[u][j] = load_stream(reinterpret_cast<const u32x4 *>(D1[j] + base));
                 }
+                qa[u] = qb[u] = (u32x4){0u, 0u, 0u, 0u};
+                if (any0) qa[u] = *reinterpret_cast<const u32x4 *>(Q0 + base);
+                if (any1) qb[u] = *reinterpret_cast<const u32x4 *>(Q1 + base);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
@@ -604,18 +618,19 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
             const int zr = r / nyr;
             const int z = uz0 + zr, y = uy0 + r - zr * nyr;
             const int base = (z * ny + y) * nxw;
-            bool in[kRC];
+            bool in0[kRC], in1[kRC];
 #pragma unroll
-            for (int j = 0; j < kRC; ++j)
-                in[j] = z >= z0[j] && z < z1[j] && y >= y0[j] && y < y1[j];
+            for (int j = 0; j < kRC; ++j) {
+                in0[j] = z >= z0[j] && z < z1[j] && y >= y0[j] && y < y1[j];
+                in1[j] = z >= tz0[j] && z < tz1[j] && y >= ty0[j] && y < ty1[j];
+            }
             for (int w = 0; w < nxw; ++w) {
                 const uint32_t qa = Q0[base + w], qb = Q1[base + w];
 #pragma unroll
-                for (int j = 0; j < kRC; ++j)
-                    if (in[j]) {
-                        i0[j] += popc(qa & D0[j][base + w]);
-                        i1[j] += popc(qb & D1[j][base + w]);
-                    }
+                for (int j = 0; j < kRC; ++j) {
+                    if (in0[j]) i0[j] += popc(qa & D0[j][base + w]);
+                    if (in1[j]) i1[j] += popc(qb & D1[j][base + w]);
+                }
             }
         }
     }
@@ -1456,8 +1471,8 @@ hipError_t launch_topk_min(int M, int N, int k, const float *D, int32_t *idx, fl
 size_t rerank_ws_bytes(int nq) { return (size_t)nq * kRerankMaxCand * 20; }  // 8 + 4 + 2 * 4 bytes per candidate
 
 hipError_t launch_rerank_score(const db_t *db, int nq, const uint32_t *qpack, const uint32_t *acnt,
-                               const int32_t *box, const int32_t *cand, int nc, void *ws,
-                               hipStream_t s)
+                               const int32_t *box, const int32_t *tbox, const int32_t *cand,
+                               int nc, void *ws, hipStream_t s)
 {
     const Geometry &g = db->g;
     uint64_t *ws_s = static_cast<uint64_t *>(ws);
@@ -1466,8 +1481,8 @@ hipError_t launch_rerank_score(const db_t *db, int nq, const uint32_t *qpack, co
     const int nbq = (nc + kRerankPerBlock - 1) / kRerankPerBlock;
     const int64_t blocks = (int64_t)nbq * 8 * ((nq + 7) / 8);
     hipLaunchKernelGGL(rerank_score_kernel, dim3((unsigned)blocks), dim3(256), 0, s, db->planes,
-                       db->popcnt, db->box, g.Wp, g.nxw, g.ny, qpack, acnt, box, cand, nc, ws_s,
-                       ws_i, ws_I, nq, nbq);
+                       db->popcnt, db->box, db->tbox, g.Wp, g.nxw, g.ny, qpack, acnt, box, tbox,
+                       cand, nc, ws_s, ws_i, ws_I, nq, nbq);
     return hipGetLastError();
 }
 

@@ -43,6 +43,7 @@ struct db_t {
     uint32_t *planes;   // [capacity][2][Wp]
     uint32_t *popcnt;   // [capacity][2]
     int32_t *box;       // [capacity][4] row box z0, z1, y0, y1 of the set bits
+    int32_t *tbox;      // [capacity][4] row box of the T1Gd bits alone (all zero: none)
     uint64_t *mom;      // [capacity][4] FLAIR moments: sum x, sum y, sum z, count
     int32_t *tile_order;  // [capacity] entries sorted by row-box centre, in tiles by cost
     int64_t tile_order_n; // entries the tile order covers (it is rebuilt when count differs)
@@ -81,6 +82,7 @@ struct WsLayout {
 struct QueryPart {
     uint32_t cnt[2];   // set bits of the FLAIR and T1Gd masks
     int32_t box[4];    // z min, z max, y min, y max of rows with a set bit (INT_MAX/-1: none)
+    int32_t tbox[4];   // the same for the rows with a T1Gd bit
     uint64_t mom[3];   // sum of x, y, z over the FLAIR bits
 };
 
@@ -105,9 +107,10 @@ hipError_t launch_pack_pool_queries(const db_t *db, const uint8_t *labels, int n
                                     uint32_t *qpack, QueryPart *qpart, uint8_t *pooled,
                                     hipStream_t s);
 // Per query: counts acnt [nq][2], row box qbox [nq][4] (z0, z1, y0, y1; all zero when
-// empty) and FLAIR moments qmom [nq][4] (sum x, sum y, sum z, count).
+// empty), FLAIR moments qmom [nq][4] (sum x, sum y, sum z, count) and, unless qtbox is NULL,
+// the row box of the T1Gd bits alone qtbox [nq][4].
 hipError_t launch_sum_parts(const QueryPart *qpart, int nq, uint32_t *acnt, int32_t *qbox,
-                            uint64_t *qmom, hipStream_t s);
+                            uint64_t *qmom, hipStream_t s, int32_t *qtbox = nullptr);
 hipError_t launch_scan(const db_t *db, int64_t n, const uint32_t *qpack, uint32_t *inter,
                        hipStream_t s);
 // Shape of a batched launch: LDS slabs of Z planes (use_lds) or the L2 fallback.
@@ -162,16 +165,19 @@ hipError_t launch_knn(bool fp8, int M, int N, int K, const void *Q, const float 
 // Exact rerank of nc <= DB_KMAX candidates per query; ws of rerank_ws_bytes(nq) holds the
 // scored candidates between the scoring and the ranking kernel.
 size_t rerank_ws_bytes(int nq);
+// box: the queries' row boxes; tbox: those of their T1Gd bits alone (the T1Gd plane of a
+// pair is read only inside both T1Gd boxes).
 hipError_t launch_rerank_score(const db_t *db, int nq, const uint32_t *qpack, const uint32_t *acnt,
-                               const int32_t *box, const int32_t *cand, int nc, void *ws,
-                               hipStream_t s);
+                               const int32_t *box, const int32_t *tbox, const int32_t *cand,
+                               int nc, void *ws, hipStream_t s);
 hipError_t launch_rerank_rank(const db_t *db, int nq, const uint32_t *acnt, int nc, int k,
                               int32_t *idx, double *score, db_counts_t *counts, const void *ws,
                               hipStream_t s);
 
 // Row boxes, moments, box-restricted scan, centre-of-mass distances (sparse.hip).
+// Per entry of recs: box (rows with a set bit), tbox (rows with a T1Gd bit), mom.
 hipError_t launch_meta(const uint32_t *recs, int64_t n, const Geometry &g, int32_t *box,
-                       uint64_t *mom, hipStream_t s);
+                       int32_t *tbox, uint64_t *mom, hipStream_t s);
 hipError_t launch_box_scan(const db_t *db, int64_t n, const uint32_t *qpack, const int32_t *qbox,
                            uint32_t *inter, hipStream_t s);
 hipError_t launch_com_dist(int nq, const uint64_t *qmom, const uint64_t *mom, int n, float *D,

@@ -98,7 +98,16 @@ constexpr int kPackBatch = 8;
 struct PartAcc {
     uint32_t n0 = 0, n1 = 0;
     int zlo = INT_MAX, zhi = -1, ylo = INT_MAX, yhi = -1;
+    int tzlo = INT_MAX, tzhi = -1, tylo = INT_MAX, tyhi = -1;   // rows with a T1Gd bit
     uint64_t sx = 0, sy = 0, sz = 0;
+
+    __device__ void add_t1gd_row(int z, int y)
+    {
+        tzlo = min(tzlo, z);
+        tzhi = max(tzhi, z);
+        tylo = min(tylo, y);
+        tyhi = max(tyhi, y);
+    }
 
     __device__ void add(uint32_t b0, uint32_t b1, int w, int nxw, int ny)
     {
@@ -112,6 +121,7 @@ struct PartAcc {
             zhi = max(zhi, z);
             ylo = min(ylo, y);
             yhi = max(yhi, y);
+            if (b1) add_t1gd_row(z, y);
             const uint32_t c = popc(b0);
             sx += (uint64_t)(32u * (uint32_t)wx) * c + bit_position_sum(b0);
             sy += (uint64_t)y * c;
@@ -123,7 +133,7 @@ struct PartAcc {
     __device__ void write(QueryPart &p)
     {
         __shared__ uint32_t rc[4][2];
-        __shared__ int rb[4][4];
+        __shared__ int rb[4][8];
         __shared__ uint64_t rm[4][3];
         n0 = wave_sum(n0);
         n1 = wave_sum(n1);
@@ -131,6 +141,10 @@ struct PartAcc {
         ylo = wave_min(ylo);
         zhi = wave_max(zhi);
         yhi = wave_max(yhi);
+        tzlo = wave_min(tzlo);
+        tylo = wave_min(tylo);
+        tzhi = wave_max(tzhi);
+        tyhi = wave_max(tyhi);
         sx = wave_sum64(sx);
         sy = wave_sum64(sy);
         sz = wave_sum64(sz);
@@ -142,6 +156,10 @@ struct PartAcc {
             rb[wv][1] = zhi;
             rb[wv][2] = ylo;
             rb[wv][3] = yhi;
+            rb[wv][4] = tzlo;
+            rb[wv][5] = tzhi;
+            rb[wv][6] = tylo;
+            rb[wv][7] = tyhi;
             rm[wv][0] = sx;
             rm[wv][1] = sy;
             rm[wv][2] = sz;
@@ -155,6 +173,10 @@ struct PartAcc {
                 zhi = max(zhi, rb[i][1]);
                 ylo = min(ylo, rb[i][2]);
                 yhi = max(yhi, rb[i][3]);
+                tzlo = min(tzlo, rb[i][4]);
+                tzhi = max(tzhi, rb[i][5]);
+                tylo = min(tylo, rb[i][6]);
+                tyhi = max(tyhi, rb[i][7]);
                 sx += rm[i][0];
                 sy += rm[i][1];
                 sz += rm[i][2];
@@ -165,6 +187,10 @@ struct PartAcc {
             p.box[1] = zhi;
             p.box[2] = ylo;
             p.box[3] = yhi;
+            p.tbox[0] = tzlo;
+            p.tbox[1] = tzhi;
+            p.tbox[2] = tylo;
+            p.tbox[3] = tyhi;
             p.mom[0] = sx;
             p.mom[1] = sy;
             p.mom[2] = sz;
@@ -341,7 +367,8 @@ __global__ void __launch_bounds__(256) pack_pool_query_kernel(const uint8_t *__r
                         acc.zhi = max(acc.zhi, zz);
                         acc.ylo = min(acc.ylo, yy);
                         acc.yhi = max(acc.yhi, yy);
-                        if (!half) bps += bit_position_sum(word);
+                        if (half) acc.add_t1gd_row(zz, yy);
+                        else bps += bit_position_sum(word);
                     }
                 }
             }
@@ -383,14 +410,29 @@ hipError_t launch_pack_pool_queries(const db_t *db, const uint8_t *labels, int n
 }
 
 // One wave per query: combine its kQueryParts partials.
+// A row box as [z0, z1) x [y0, y1) from the extreme rows (all zero when there is none).
+__device__ __forceinline__ void write_box(int32_t *bx, int zlo, int zhi, int ylo, int yhi)
+{
+    if (zhi < 0) {
+        bx[0] = bx[1] = bx[2] = bx[3] = 0;
+    } else {
+        bx[0] = zlo;
+        bx[1] = zhi + 1;
+        bx[2] = ylo;
+        bx[3] = yhi + 1;
+    }
+}
+
 __global__ void __launch_bounds__(64) sum_parts_kernel(const QueryPart *__restrict__ qpart,
                                                       uint32_t *__restrict__ acnt,
                                                       int32_t *__restrict__ qbox,
-                                                      uint64_t *__restrict__ qmom)
+                                                      uint64_t *__restrict__ qmom,
+                                                      int32_t *__restrict__ qtbox)
 {
     const int q = blockIdx.x;
     uint32_t a = 0, b = 0;
     int zlo = INT_MAX, zhi = -1, ylo = INT_MAX, yhi = -1;
+    int tzlo = INT_MAX, tzhi = -1, tylo = INT_MAX, tyhi = -1;
     uint64_t sx = 0, sy = 0, sz = 0;
     for (int i = threadIdx.x; i < kQueryParts; i += 64) {
         const QueryPart &p = qpart[(int64_t)q * kQueryParts + i];
@@ -400,6 +442,10 @@ __global__ void __launch_bounds__(64) sum_parts_kernel(const QueryPart *__restri
         zhi = max(zhi, p.box[1]);
         ylo = min(ylo, p.box[2]);
         yhi = max(yhi, p.box[3]);
+        tzlo = min(tzlo, p.tbox[0]);
+        tzhi = max(tzhi, p.tbox[1]);
+        tylo = min(tylo, p.tbox[2]);
+        tyhi = max(tyhi, p.tbox[3]);
         sx += p.mom[0];
         sy += p.mom[1];
         sz += p.mom[2];
@@ -410,21 +456,18 @@ __global__ void __launch_bounds__(64) sum_parts_kernel(const QueryPart *__restri
     ylo = wave_min(ylo);
     zhi = wave_max(zhi);
     yhi = wave_max(yhi);
+    tzlo = wave_min(tzlo);
+    tylo = wave_min(tylo);
+    tzhi = wave_max(tzhi);
+    tyhi = wave_max(tyhi);
     sx = wave_sum64(sx);
     sy = wave_sum64(sy);
     sz = wave_sum64(sz);
     if (threadIdx.x == 0) {
         acnt[2 * q] = a;
         acnt[2 * q + 1] = b;
-        int32_t *bx = qbox + 4 * q;
-        if (zhi < 0) {
-            bx[0] = bx[1] = bx[2] = bx[3] = 0;   // no set bit: an empty box
-        } else {
-            bx[0] = zlo;
-            bx[1] = zhi + 1;
-            bx[2] = ylo;
-            bx[3] = yhi + 1;
-        }
+        write_box(qbox + 4 * q, zlo, zhi, ylo, yhi);
+        if (qtbox) write_box(qtbox + 4 * q, tzlo, tzhi, tylo, tyhi);
         uint64_t *m = qmom + 4 * q;
         m[0] = sx;
         m[1] = sy;
@@ -434,9 +477,10 @@ __global__ void __launch_bounds__(64) sum_parts_kernel(const QueryPart *__restri
 }
 
 hipError_t launch_sum_parts(const QueryPart *qpart, int nq, uint32_t *acnt, int32_t *qbox,
-                            uint64_t *qmom, hipStream_t s)
+                            uint64_t *qmom, hipStream_t s, int32_t *qtbox)
 {
-    hipLaunchKernelGGL(sum_parts_kernel, dim3(nq), dim3(64), 0, s, qpart, acnt, qbox, qmom);
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(nq), dim3(64), 0, s, qpart, acnt, qbox, qmom,
+                       qtbox);
     return hipGetLastError();
 }
 

@@ -21,18 +21,21 @@
 
 namespace tdb {
 
-// One 256-thread block per record of `rec_words` words (two planes of Wp
-// words): row box [4] and FLAIR moments [4] = (sum x, sum y, sum z, count).
+// One 256-thread block per record of `rec_words` words (two planes of Wp words): its row box
+// [4] (rows with a set bit in either mask), the row box of its T1Gd bits alone [4] and its
+// FLAIR moments [4] = (sum x, sum y, sum z, count). Boxes are [z0, z1) x [y0, y1), all zero
+// when empty.
 __global__ void __launch_bounds__(256) meta_kernel(const uint32_t *__restrict__ recs,
                                                    int64_t rec_words, int Wp, int W, int nxw,
                                                    int ny, int32_t *__restrict__ box,
+                                                   int32_t *__restrict__ tbox,
                                                    uint64_t *__restrict__ mom)
 {
-    __shared__ int rb[4][4];
+    __shared__ int rb[4][8];
     __shared__ uint64_t rm[4][4];
     const int64_t e = blockIdx.x;
     const uint32_t *P0 = recs + e * rec_words, *P1 = P0 + Wp;
-    int zlo = INT_MAX, zhi = -1, ylo = INT_MAX, yhi = -1;
+    int bx[8] = {INT_MAX, -1, INT_MAX, -1, INT_MAX, -1, INT_MAX, -1};   // z lo/hi, y lo/hi; twice
     uint64_t sx = 0, sy = 0, sz = 0, cnt = 0;
     for (int w = threadIdx.x; w < W; w += blockDim.x) {
         const uint32_t a = P0[w], b = P1[w];
@@ -40,10 +43,16 @@ __global__ void __launch_bounds__(256) meta_kernel(const uint32_t *__restrict__ 
             const int row = w / nxw;
             const int wx = w - row * nxw;
             const int z = row / ny, y = row - z * ny;
-            zlo = min(zlo, z);
-            zhi = max(zhi, z);
-            ylo = min(ylo, y);
-            yhi = max(yhi, y);
+            bx[0] = min(bx[0], z);
+            bx[1] = max(bx[1], z);
+            bx[2] = min(bx[2], y);
+            bx[3] = max(bx[3], y);
+            if (b) {
+                bx[4] = min(bx[4], z);
+                bx[5] = max(bx[5], z);
+                bx[6] = min(bx[6], y);
+                bx[7] = max(bx[7], y);
+            }
             const uint32_t c = popc(a);
             cnt += c;
             sx += (uint64_t)(32u * (uint32_t)wx) * c + bit_position_sum(a);
@@ -51,20 +60,16 @@ __global__ void __launch_bounds__(256) meta_kernel(const uint32_t *__restrict__ 
             sz += (uint64_t)z * c;
         }
     }
-    zlo = wave_min(zlo);
-    ylo = wave_min(ylo);
-    zhi = wave_max(zhi);
-    yhi = wave_max(yhi);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) bx[i] = (i & 1) ? wave_max(bx[i]) : wave_min(bx[i]);
     sx = wave_sum64(sx);
     sy = wave_sum64(sy);
     sz = wave_sum64(sz);
     cnt = wave_sum64(cnt);
     const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        rb[wv][0] = zlo;
-        rb[wv][1] = zhi;
-        rb[wv][2] = ylo;
-        rb[wv][3] = yhi;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) rb[wv][i] = bx[i];
         rm[wv][0] = sx;
         rm[wv][1] = sy;
         rm[wv][2] = sz;
@@ -74,23 +79,25 @@ __global__ void __launch_bounds__(256) meta_kernel(const uint32_t *__restrict__ 
     if (threadIdx.x == 0) {
         const int nw = blockDim.x >> 6;
         for (int i = 1; i < nw; ++i) {
-            zlo = min(zlo, rb[i][0]);
-            zhi = max(zhi, rb[i][1]);
-            ylo = min(ylo, rb[i][2]);
-            yhi = max(yhi, rb[i][3]);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) bx[t] = (t & 1) ? max(bx[t], rb[i][t]) : min(bx[t], rb[i][t]);
             sx += rm[i][0];
             sy += rm[i][1];
             sz += rm[i][2];
             cnt += rm[i][3];
         }
-        int32_t *b = box + 4 * e;
-        if (zhi < 0) {
-            b[0] = b[1] = b[2] = b[3] = 0;   // no set bit: an empty box
-        } else {
-            b[0] = zlo;
-            b[1] = zhi + 1;
-            b[2] = ylo;
-            b[3] = yhi + 1;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            int32_t *b = (h ? tbox : box) + 4 * e;
+            const int *x = bx + 4 * h;
+            if (x[1] < 0) {
+                b[0] = b[1] = b[2] = b[3] = 0;   // no set bit: an empty box
+            } else {
+                b[0] = x[0];
+                b[1] = x[1] + 1;
+                b[2] = x[2];
+                b[3] = x[3] + 1;
+            }
         }
         uint64_t *m = mom + 4 * e;
         m[0] = sx;
@@ -101,10 +108,10 @@ __global__ void __launch_bounds__(256) meta_kernel(const uint32_t *__restrict__ 
 }
 
 hipError_t launch_meta(const uint32_t *recs, int64_t n, const Geometry &g, int32_t *box,
-                       uint64_t *mom, hipStream_t s)
+                       int32_t *tbox, uint64_t *mom, hipStream_t s)
 {
     hipLaunchKernelGGL(meta_kernel, dim3((unsigned)n), dim3(256), 0, s, recs, 2 * (int64_t)g.Wp,
-                       g.Wp, g.W, g.nxw, g.ny, box, mom);
+                       g.Wp, g.W, g.nxw, g.ny, box, tbox, mom);
     return hipGetLastError();
 }
 

@@ -43,9 +43,11 @@ def test_meta_and_sparse_query_match_oracle(dims):
     labs2 = np.concatenate([labs, np.stack([oracle.threshold(c, T_LO, T_HI) for c in conc2])])
     for d, L in ((db, labs), (db2, labs2)):
         boxes = _host(d.boxes)[:len(L)]
+        tboxes = _host(d.tboxes)[:len(L)]
         moms = _host(d.moments)[:len(L)].view(np.uint64)
         for i in range(len(L)):
             assert tuple(boxes[i]) == oracle.rowbox(L[i]), i
+            assert tuple(tboxes[i]) == oracle.rowbox(L[i] & 2), i      # the T1Gd rows alone
             assert tuple(int(v) for v in moms[i]) == oracle.moments(L[i]), i
     rng = np.random.default_rng(3)
     for j, q in enumerate(_edge_queries(gen, labs2, rng)):
