@@ -83,6 +83,7 @@ WsLayout ws_layout(const db_t *db, int nq, int k, bool batched)
     L.acnt = take((size_t)nq * 2 * 4);
     L.rois = take((size_t)nq * 6 * 4);
     L.qbox = take((size_t)nq * 4 * 4);
+    L.qtbox = take((size_t)nq * 4 * 4);
     L.qmom = take((size_t)nq * 4 * 8);
     L.inter = take((size_t)nq * cap * 2 * 4);
     L.bcnt = batched ? take((size_t)nq * cap * 2 * 4) : off;
@@ -547,12 +548,13 @@ int db_query_sparse(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx
     uint32_t *qpack = at<uint32_t>(ws, L.qpack);
     uint32_t *inter = at<uint32_t>(ws, L.inter);
     uint32_t *acnt = at<uint32_t>(ws, L.acnt);
-    int32_t *qbox = at<int32_t>(ws, L.qbox);
+    int32_t *qbox = at<int32_t>(ws, L.qbox), *qtbox = at<int32_t>(ws, L.qtbox);
     QueryPart *qpart = at<QueryPart>(ws, L.qpart);
     hipError_t e = launch_pack_queries(db, q_labels, 1, nullptr, qpack, qpart, s);
-    if (e == hipSuccess) e = launch_sum_parts(qpart, 1, acnt, qbox, at<uint64_t>(ws, L.qmom), s);
+    if (e == hipSuccess)
+        e = launch_sum_parts(qpart, 1, acnt, qbox, at<uint64_t>(ws, L.qmom), s, qtbox);
     if (e == hipSuccess) e = prof_mark(db, s);
-    if (e == hipSuccess) e = launch_box_scan(db, db->count, qpack, qbox, inter, s);
+    if (e == hipSuccess) e = launch_box_scan(db, db->count, qpack, qbox, qtbox, inter, s);
     if (e == hipSuccess) e = prof_mark(db, s);
     if (e == hipSuccess) {
         TopkArgs a{};

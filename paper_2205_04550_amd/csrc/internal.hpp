@@ -69,6 +69,7 @@ struct WsLayout {
     size_t acnt;     // uint32 [nq][2] query counts |A_m (n R)|
     size_t rois;     // int32 [nq][6] ROI boxes (batched calls)
     size_t qbox;     // int32 [nq][4] row boxes of the packed queries
+    size_t qtbox;    // int32 [nq][4] row boxes of their T1Gd bits alone
     size_t qmom;     // uint64 [nq][4] FLAIR moments of the packed queries
     size_t inter;    // uint32 [nq][capacity][2] intersections
     size_t bcnt;     // uint32 [nq][capacity][2] database counts inside the ROI (batched)
@@ -178,8 +179,9 @@ hipError_t launch_rerank_rank(const db_t *db, int nq, const uint32_t *acnt, int 
 // Per entry of recs: box (rows with a set bit), tbox (rows with a T1Gd bit), mom.
 hipError_t launch_meta(const uint32_t *recs, int64_t n, const Geometry &g, int32_t *box,
                        int32_t *tbox, uint64_t *mom, hipStream_t s);
+// qtbox: the query's T1Gd row box (the T1Gd plane is read only inside both T1Gd boxes).
 hipError_t launch_box_scan(const db_t *db, int64_t n, const uint32_t *qpack, const int32_t *qbox,
-                           uint32_t *inter, hipStream_t s);
+                           const int32_t *qtbox, uint32_t *inter, hipStream_t s);
 hipError_t launch_com_dist(int nq, const uint64_t *qmom, const uint64_t *mom, int n, float *D,
                            hipStream_t s);
 

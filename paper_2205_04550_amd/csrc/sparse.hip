@@ -132,16 +132,22 @@ template <bool V4, int U>
 __global__ void __launch_bounds__(256) box_scan_kernel(const uint32_t *__restrict__ planes, int Wp,
                                                        int nxw, int ny,
                                                        const int32_t *__restrict__ box,
+                                                       const int32_t *__restrict__ tbox,
                                                        const uint32_t *__restrict__ qpack,
-                                                       const int32_t *__restrict__ qbox, int64_t n,
+                                                       const int32_t *__restrict__ qbox,
+                                                       const int32_t *__restrict__ qtbox, int64_t n,
                                                        uint32_t *__restrict__ inter)
 {
     const int lane = threadIdx.x & 63;
     const int64_t e = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (e >= n) return;   // a whole wave leaves; the kernel has no block barrier
-    const int32_t *b = box + 4 * e;
+    const int32_t *b = box + 4 * e, *tb = tbox + 4 * e;
     const int z0 = max(b[0], qbox[0]), z1 = min(b[1], qbox[1]);
     const int y0 = max(b[2], qbox[2]), y1 = min(b[3], qbox[3]);
+    // The T1Gd plane only inside both T1Gd boxes (a part of the box swept: each T1Gd box lies
+    // inside its side's box of both masks).
+    const int tz0 = max(tb[0], qtbox[0]), tz1 = min(tb[1], qtbox[1]);
+    const int ty0 = max(tb[2], qtbox[2]), ty1 = min(tb[3], qtbox[3]);
     const int nyr = y1 - y0;
     const int nr = (z1 > z0 && nyr > 0) ? (z1 - z0) * nyr : 0;
     const float inv = nyr > 0 ? 1.0f / (float)nyr : 0.0f;
@@ -154,15 +160,17 @@ __global__ void __launch_bounds__(256) box_scan_kernel(const uint32_t *__restric
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int r = r0 + u * 64 + lane;
+                d0[u] = d1[u] = q0[u] = q1[u] = (u32x4){0u, 0u, 0u, 0u};
                 if (r < nr) {
                     const int zr = row_div(r, nyr, inv);
-                    const int64_t base = ((int64_t)(z0 + zr) * ny + (y0 + r - zr * nyr)) * 4;
+                    const int z = z0 + zr, y = y0 + r - zr * nyr;
+                    const int64_t base = ((int64_t)z * ny + y) * 4;
                     d0[u] = load_stream(reinterpret_cast<const u32x4 *>(D0 + base));
-                    d1[u] = load_stream(reinterpret_cast<const u32x4 *>(D1 + base));
                     q0[u] = *reinterpret_cast<const u32x4 *>(Q0 + base);
-                    q1[u] = *reinterpret_cast<const u32x4 *>(Q1 + base);
-                } else {
-                    d0[u] = d1[u] = q0[u] = q1[u] = (u32x4){0u, 0u, 0u, 0u};
+                    if (z >= tz0 && z < tz1 && y >= ty0 && y < ty1) {
+                        d1[u] = load_stream(reinterpret_cast<const u32x4 *>(D1 + base));
+                        q1[u] = *reinterpret_cast<const u32x4 *>(Q1 + base);
+                    }
                 }
             }
 #pragma unroll
@@ -176,9 +184,10 @@ __global__ void __launch_bounds__(256) box_scan_kernel(const uint32_t *__restric
         for (int64_t t = lane; t < nt; t += 64) {
             const int r = (int)(t / nxw), w = (int)(t - (int64_t)r * nxw);
             const int zr = row_div(r, nyr, inv);
-            const int64_t base = ((int64_t)(z0 + zr) * ny + (y0 + r - zr * nyr)) * nxw + w;
+            const int z = z0 + zr, y = y0 + r - zr * nyr;
+            const int64_t base = ((int64_t)z * ny + y) * nxw + w;
             c0 += popc(Q0[base] & D0[base]);
-            c1 += popc(Q1[base] & D1[base]);
+            if (z >= tz0 && z < tz1 && y >= ty0 && y < ty1) c1 += popc(Q1[base] & D1[base]);
         }
     }
     c0 = wave_sum(c0);
@@ -190,16 +199,18 @@ __global__ void __launch_bounds__(256) box_scan_kernel(const uint32_t *__restric
 }
 
 hipError_t launch_box_scan(const db_t *db, int64_t n, const uint32_t *qpack, const int32_t *qbox,
-                           uint32_t *inter, hipStream_t s)
+                           const int32_t *qtbox, uint32_t *inter, hipStream_t s)
 {
     const Geometry &g = db->g;
     const int64_t blocks = (n + 3) / 4;
     if (g.nxw == 4)
         hipLaunchKernelGGL((box_scan_kernel<true, 4>), dim3((unsigned)blocks), dim3(256), 0, s,
-                           db->planes, g.Wp, g.nxw, g.ny, db->box, qpack, qbox, n, inter);
+                           db->planes, g.Wp, g.nxw, g.ny, db->box, db->tbox, qpack, qbox, qtbox, n,
+                           inter);
     else
         hipLaunchKernelGGL((box_scan_kernel<false, 1>), dim3((unsigned)blocks), dim3(256), 0, s,
-                           db->planes, g.Wp, g.nxw, g.ny, db->box, qpack, qbox, n, inter);
+                           db->planes, g.Wp, g.nxw, g.ny, db->box, db->tbox, qpack, qbox, qtbox, n,
+                           inter);
     return hipGetLastError();
 }
 
