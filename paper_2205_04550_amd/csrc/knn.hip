@@ -505,30 +505,38 @@ __global__ void __launch_bounds__(kMergeThreads) knn_merge_kernel(
     __shared__ unsigned long long s_lo, s_hi;
     const int q = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     const int m = q / kDM, r = q % kDM;
-    if (tid < nsplit) {
+    // The first wave: lane s reads split s's list length and bound; B* is their smallest bound
+    // and the lists are laid end to end at the exclusive prefix sums of the lengths.
+    if (tid < 64) {
         const int s = tid;
-        const uint32_t blk = (uint32_t)(kXcds * (m + mt * (s / kXcds)) + s % kXcds);
-        s_blk[s] = blk;
-        s_n[s] = cnt[(size_t)blk * kDM + r];
-    }
-    if (tid == 0) {
-        s_gather = 0;
-        s_win = 0;
-        s_lo = ~0ull;
-        s_hi = 0;
-    }
-    __syncthreads();
-    if (tid == 0) {
+        uint32_t n_s = 0;
         uint64_t B = ~0ull;
-        uint32_t off = 0;
-        for (int s = 0; s < nsplit; ++s) {
-            const uint64_t v = bound[(size_t)s_blk[s] * kDM + r];
-            B = v < B ? v : B;
-            s_off[s] = off;
-            off += s_n[s];
+        if (s < nsplit) {
+            const uint32_t blk = (uint32_t)(kXcds * (m + mt * (s / kXcds)) + s % kXcds);
+            s_blk[s] = blk;
+            n_s = cnt[(size_t)blk * kDM + r];
+            B = bound[(size_t)blk * kDM + r];
         }
-        s_off[nsplit] = off;
-        s_B = B;
+        uint32_t incl = n_s;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+            const uint64_t b2 = __shfl_xor(B, o, 64);
+            B = b2 < B ? b2 : B;
+        }
+        if (s < nsplit) {
+            s_n[s] = n_s;
+            s_off[s] = incl - n_s;
+        }
+        if (s == nsplit - 1) s_off[nsplit] = incl;
+        if (s == 0) {
+            s_B = B;
+            s_gather = 0;
+            s_win = 0;
+            s_lo = ~0ull;
+            s_hi = 0;
+        }
     }
     __syncthreads();
     const uint64_t Bs = s_B;
@@ -544,14 +552,20 @@ __global__ void __launch_bounds__(kMergeThreads) knn_merge_kernel(
         return lists[((size_t)s_blk[lo] * kDM + r) * kKnnCap + (f - s_off[lo])];
     };
     // Gather the entries <= B* into LDS while they fit; four loads in flight per thread.
-    // Their smallest and largest values fix the bits all of them share.
+    // Their smallest and largest values fix the bits all of them share. A thread's entries
+    // only move forward through the lists, so it keeps the split of its last one.
     uint64_t lo_t = ~0ull, hi_t = 0;
+    int sp = 0;
     for (uint32_t f0 = 0; f0 < n_all; f0 += 4 * kMergeThreads) {
         uint64_t e[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const uint32_t f = f0 + u * kMergeThreads + tid;
-            e[u] = f < n_all ? entry(f) : ~0ull;
+            e[u] = ~0ull;
+            if (f < n_all) {
+                while (s_off[sp + 1] <= f) ++sp;      // s_off[nsplit] = n_all > f stops it
+                e[u] = lists[((size_t)s_blk[sp] * kDM + r) * kKnnCap + (f - s_off[sp])];
+            }
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
