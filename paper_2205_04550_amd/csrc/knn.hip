@@ -488,6 +488,7 @@ __global__ void __launch_bounds__(kDThreads, 4) knn_kernel(
 }
 
 constexpr int kMergeThreads = 256;
+constexpr int kDirectPairs = 4;      // (query, candidate) pairs per wave of knn_direct_kernel
 constexpr int kMergeCap = 8192;     // gathered candidates held in LDS
 
 // One block per query row: the k smallest packed values over the row's split lists.
@@ -719,7 +720,8 @@ __global__ void __launch_bounds__(kMergeThreads) knn_merge_kernel(
 
 // Direct-form squared distances of given pairs: d = sum_i (q_i - x_i)^2 over the stored
 // (dequantised) values, summed in double and rounded once to float; exactly 0 for equal
-// codes and scales. One wave per pair, four pairs per block.
+// codes and scales. A wave takes kDirectPairs pairs (their loads all in flight together),
+// four waves per block; each pair's terms are summed in the same order as one pair alone.
 template <bool FP8>
 __global__ void __launch_bounds__(256) knn_direct_kernel(int M, int N, int k, int K,
                                                          const uint8_t *__restrict__ Q,
@@ -729,38 +731,61 @@ __global__ void __launch_bounds__(256) knn_direct_kernel(int M, int N, int k, in
                                                          const int32_t *__restrict__ idx,
                                                          float *__restrict__ d)
 {
+    constexpr int P = kDirectPairs;
     const int lane = threadIdx.x & 63;
-    const int64_t pair = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (pair >= (int64_t)M * k) return;
-    const int q = (int)(pair / k);
-    const int32_t e = idx[pair];
-    if (e < 0 || e >= N) return;
-    double acc = 0.0;
+    const int64_t pair0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * P;
+    const int64_t npairs = (int64_t)M * k;
+    if (pair0 >= npairs) return;                  // whole wave
+    // The wave's P pairs: their candidates first, then every row they need, all in flight.
+    int q[P];
+    int32_t e[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        const int64_t pair = pair0 + j;
+        q[j] = pair < npairs ? (int)(pair / k) : 0;
+        e[j] = pair < npairs ? idx[pair] : -1;
+    }
+    double acc[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) acc[j] = 0.0;
     // Eight values per lane per step (K % 8 == 0; rows 8-byte (FP8) / 16-byte (BF16) aligned).
     for (int i0 = lane * 8; i0 < K; i0 += 512) {
-        u32x4 a, c;
-        double sa = 1.0, sc = 1.0;
-        if (FP8) {
-            a = e4m3x8_to_bf16(*reinterpret_cast<const u32x2 *>(Q + (int64_t)q * K + i0));
-            c = e4m3x8_to_bf16(*reinterpret_cast<const u32x2 *>(X + (int64_t)e * K + i0));
-            sa = qs[q];
-            sc = xs[e];
-        } else {
-            a = *reinterpret_cast<const u32x4 *>(Q + ((int64_t)q * K + i0) * 2);
-            c = *reinterpret_cast<const u32x4 *>(X + ((int64_t)e * K + i0) * 2);
+        u32x4 a[P], c[P];
+        double sa[P], sc[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const bool live = e[j] >= 0 && e[j] < N;
+            const int ej = live ? e[j] : 0;
+            sa[j] = sc[j] = 1.0;
+            if (FP8) {
+                a[j] = e4m3x8_to_bf16(*reinterpret_cast<const u32x2 *>(Q + (int64_t)q[j] * K + i0));
+                c[j] = e4m3x8_to_bf16(*reinterpret_cast<const u32x2 *>(X + (int64_t)ej * K + i0));
+                sa[j] = qs[q[j]];
+                sc[j] = xs[ej];
+            } else {
+                a[j] = *reinterpret_cast<const u32x4 *>(Q + ((int64_t)q[j] * K + i0) * 2);
+                c[j] = *reinterpret_cast<const u32x4 *>(X + ((int64_t)ej * K + i0) * 2);
+            }
         }
 #pragma unroll
-        for (int w = 0; w < 4; ++w)
+        for (int j = 0; j < P; ++j)
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const double va = sa * (double)bf16_val((uint16_t)(a[w] >> (16 * h)));
-                const double vc = sc * (double)bf16_val((uint16_t)(c[w] >> (16 * h)));
-                acc += (va - vc) * (va - vc);
-            }
+            for (int w = 0; w < 4; ++w)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const double va = sa[j] * (double)bf16_val((uint16_t)(a[j][w] >> (16 * h)));
+                    const double vc = sc[j] * (double)bf16_val((uint16_t)(c[j][w] >> (16 * h)));
+                    acc[j] += (va - vc) * (va - vc);
+                }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) d[pair] = (float)acc;
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int j = 0; j < P; ++j) acc[j] += __shfl_xor(acc[j], o, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+            if (pair0 + j < npairs && e[j] >= 0 && e[j] < N) d[pair0 + j] = (float)acc[j];
 }
 
 // ---- launchers ----
@@ -900,12 +925,13 @@ hipError_t launch_knn(bool fp8, int M, int N, int K, const void *Q, const float 
     e = hipGetLastError();
     if (e != hipSuccess || !direct) return e;
     const int64_t pairs = (int64_t)M * k;
+    const unsigned dblocks = (unsigned)((pairs + 4 * kDirectPairs - 1) / (4 * kDirectPairs));
     if (fp8)
-        hipLaunchKernelGGL((knn_direct_kernel<true>), dim3((unsigned)((pairs + 3) / 4)), dim3(256),
-                           0, s, M, N, k, K, q, qs, x, xs, idx, d);
+        hipLaunchKernelGGL((knn_direct_kernel<true>), dim3(dblocks), dim3(256), 0, s, M, N, k, K,
+                           q, qs, x, xs, idx, d);
     else
-        hipLaunchKernelGGL((knn_direct_kernel<false>), dim3((unsigned)((pairs + 3) / 4)),
-                           dim3(256), 0, s, M, N, k, K, q, nullptr, x, nullptr, idx, d);
+        hipLaunchKernelGGL((knn_direct_kernel<false>), dim3(dblocks), dim3(256), 0, s, M, N, k, K,
+                           q, nullptr, x, nullptr, idx, d);
     return hipGetLastError();
 }
 
