@@ -527,38 +527,60 @@ HASH_GAMMA = 3.0   # weight of the Bi-half layer's pull of latents towards their
 VAE_BETA = 1e-5    # KL weight against the per-voxel mean MSE (about 2.6 against a voxel sum)
 
 
-def rerank_bytes(db, lab_d, cand, gen, lines: bool = False) -> float:
-    """Database bytes the candidate-scoring kernel reads: per (query, candidate), the FLAIR
-    plane's rows inside both the query's and the candidate's row box and the T1Gd plane's
-    rows inside both T1Gd row boxes (measurement bookkeeping). lines=True counts the 128-byte
-    cache lines those rows touch instead (the rows of one z-slice are contiguous, so a
-    slice's run starts and ends inside a line)."""
+def _query_boxes(lab, gen, bits):
+    """Row boxes (z0, z1, y0, y1) [nq] of the rows of labels lab [nq][nz][ny][nx] holding one
+    of `bits`."""
     import torch
-    nxw = gen.nx // 32
-    rb = nxw * 4                                                   # bytes per row and plane
-    ar_z = torch.arange(gen.nz, device=lab_d.device)
-    ar_y = torch.arange(gen.ny, device=lab_d.device)
+    rows = ((lab & bits).reshape(lab.shape[0], gen.nz, gen.ny, gen.nx).amax(dim=3) != 0)
+    zany, yany = rows.any(dim=2), rows.any(dim=1)
+    ar_z = torch.arange(gen.nz, device=lab.device)
+    ar_y = torch.arange(gen.ny, device=lab.device)
     big = 1 << 20
+    return (torch.where(zany, ar_z, big).amin(1), torch.where(zany, ar_z + 1, -big).amax(1),
+            torch.where(yany, ar_y, big).amin(1), torch.where(yany, ar_y + 1, -big).amax(1))
+
+
+def _plane_rows(eb, zr, q, gen, rb, lines):
+    """Per (query, entry): rows one plane's scan reads, or the 128-byte lines they touch:
+    slices of (entry box n query box), in each the entry's y-range of that slice cut to the
+    boxes' y-range. eb [..][4] entry boxes, zr [..][nz] the entry's packed slice ranges,
+    q = (z0, z1, y0, y1) of the query (broadcast against eb)."""
+    import torch
+    z0 = torch.maximum(eb[..., 0], q[0])
+    z1 = torch.minimum(eb[..., 1], q[1])
+    y0 = torch.maximum(eb[..., 2], q[2])
+    y1 = torch.minimum(eb[..., 3], q[3])
+    zs = torch.arange(gen.nz, device=eb.device)
+    inz = (zs >= z0[..., None]) & (zs < z1[..., None])
+    a0 = torch.maximum(zr & 0xffff, y0[..., None])
+    a1 = torch.minimum(zr >> 16, y1[..., None])
+    ok = inz & (a1 > a0)
+    if lines:
+        n = (a1 * rb + 127) // 128 - (a0 * rb) // 128
+    else:
+        n = a1 - a0
+    return (torch.where(ok, n, torch.zeros_like(n))).sum(dim=-1)
+
+
+def rerank_bytes(db, lab_d, cand, gen, lines: bool = False) -> float:
+    """Database bytes the candidate-scoring kernel reads: per (query, candidate) and plane, the
+    rows of the slices inside both row boxes of that plane (the boxes of both masks for FLAIR,
+    the T1Gd boxes for T1Gd) that lie in the candidate's y-range of that plane in the slice
+    (measurement bookkeeping). lines=True counts the 128-byte cache lines those rows touch
+    instead (a slice's run of rows starts and ends inside a line)."""
+    import torch
+    rb = gen.nx // 32 * 4                                          # bytes per row and plane
+    c = cand.to(torch.int64)
     total = 0.0
-    for bits, boxes in ((3, db.boxes), (2, db.tboxes)):
-        rows = ((lab_d & bits).reshape(lab_d.shape[0], gen.nz, gen.ny, gen.nx).amax(dim=3) != 0)
-        zany, yany = rows.any(dim=2), rows.any(dim=1)
-        qz0 = torch.where(zany, ar_z, big).amin(1)
-        qz1 = torch.where(zany, ar_z + 1, -big).amax(1)
-        qy0 = torch.where(yany, ar_y, big).amin(1)
-        qy1 = torch.where(yany, ar_y + 1, -big).amax(1)
-        eb = boxes[cand.to(torch.int64)].to(torch.int64)          # [nq][nc][4]
-        dz = (torch.minimum(eb[..., 1], qz1[:, None]) -
-              torch.maximum(eb[..., 0], qz0[:, None])).clamp(min=0)
-        y0 = torch.maximum(eb[..., 2], qy0[:, None])
-        y1 = torch.minimum(eb[..., 3], qy1[:, None])
-        if lines:
-            ln = torch.where(y1 > y0, (y1 * rb + 127) // 128 - (y0 * rb) // 128,
-                             torch.zeros_like(y0))
-            total += float((dz * ln).sum()) * 128
-        else:
-            total += float((dz * (y1 - y0).clamp(min=0)).sum()) * rb
-    return total
+    for p, (bits, boxes) in enumerate(((3, db.boxes), (2, db.tboxes))):
+        qz0, qz1, qy0, qy1 = _query_boxes(lab_d, gen, bits)
+        q = (qz0[:, None], qz1[:, None], qy0[:, None], qy1[:, None])
+        for r0 in range(0, c.shape[0], 128):                      # bounded temporaries
+            eb = boxes[c[r0:r0 + 128]].to(torch.int64)            # [128][nc][4]
+            zr = db.zranges[c[r0:r0 + 128]][..., p].to(torch.int64)   # [128][nc][nz]
+            qq = tuple(t[r0:r0 + 128] for t in q)
+            total += float(_plane_rows(eb, zr, qq, gen, rb, lines).sum())
+    return total * (128 if lines else rb)
 
 
 def encoder_forward_flop(model, nq: int) -> float:
@@ -1135,35 +1157,26 @@ def bench_sparse(args, db, gen, n, build_s) -> int:
         same &= all(bool(torch.equal(a, b)) for a, b in zip(out_d, out_s))
     torch.cuda.synchronize()
     log(f"sparse == dense on {nq} queries: {same}")
-    # Bytes the sparse kernel reads from HBM: per plane, the database rows where that plane's
-    # boxes meet (the boxes of both masks for FLAIR, the T1Gd boxes for T1Gd); measurement
-    # bookkeeping from the stored boxes and the query's set rows.
-    nxw = gen.nx // 32
-    rb = nxw * 4                                       # bytes per row and plane
+    # Bytes the sparse kernel reads from HBM: per plane, the database rows of the slices where
+    # that plane's boxes meet (the boxes of both masks for FLAIR, the T1Gd boxes for T1Gd) that
+    # lie in the entry's y-range of that plane in the slice; measurement bookkeeping from the
+    # stored boxes and ranges and the query's set rows.
+    rb = gen.nx // 32 * 4                              # bytes per row and plane
     rows_read = np.zeros(nq)                           # rows inside both boxes of both masks
     bytes_read, line_bytes = np.zeros(nq), np.zeros(nq)
-    for bits, boxes in ((3, db.boxes), (2, db.tboxes)):
+    eb_any = db.boxes[:n].to(torch.int64)
+    for p, (bits, boxes) in enumerate(((3, db.boxes), (2, db.tboxes))):
         eb = boxes[:n].to(torch.int64)
+        zr = db.zranges[:n][..., p].to(torch.int64)
+        qb = _query_boxes(lab_d, gen, bits)
         for q in range(nq):
-            rows = (lab_d[q] & bits).reshape(gen.nz, gen.ny, gen.nx).amax(dim=2) != 0
-            zi = torch.nonzero(rows.any(dim=1)).flatten()
-            yi = torch.nonzero(rows.any(dim=0)).flatten()
-            if zi.numel() == 0:
-                continue
-            qz0, qz1 = int(zi.min()), int(zi.max()) + 1
-            qy0, qy1 = int(yi.min()), int(yi.max()) + 1
-            dz = (torch.minimum(eb[:, 1], torch.tensor(qz1)) -
-                  torch.maximum(eb[:, 0], torch.tensor(qz0))).clamp(min=0)
-            y0 = torch.maximum(eb[:, 2], torch.tensor(qy0))
-            y1 = torch.minimum(eb[:, 3], torch.tensor(qy1))
-            nrow = int((dz * (y1 - y0).clamp(min=0)).sum())
-            if bits == 3:
-                rows_read[q] = nrow
-            bytes_read[q] += nrow * rb
-            # the 128-byte lines those rows touch (a z-slice's run starts and ends inside one)
-            ln = torch.where(y1 > y0, (y1 * rb + 127) // 128 - (y0 * rb) // 128,
-                             torch.zeros_like(y0))
-            line_bytes[q] += int((dz * ln).sum()) * 128
+            qq = tuple(t[q] for t in qb)
+            bytes_read[q] += float(_plane_rows(eb, zr, qq, gen, rb, False).sum()) * rb
+            line_bytes[q] += float(_plane_rows(eb, zr, qq, gen, rb, True).sum()) * 128
+            if p == 0:
+                dz = (torch.minimum(eb_any[:, 1], qq[1]) - torch.maximum(eb_any[:, 0], qq[0])).clamp(min=0)
+                dy = (torch.minimum(eb_any[:, 3], qq[3]) - torch.maximum(eb_any[:, 2], qq[2])).clamp(min=0)
+                rows_read[q] = float((dz * dy).sum())
     for _ in range(args.warmup):
         for q in range(min(nq, 8)):
             db.query_sparse(lab_d[q], k, out=out_s, ws=ws)

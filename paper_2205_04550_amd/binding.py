@@ -164,7 +164,8 @@ class TumorDB:
         mom = box + up(self.capacity * 16)
         order = mom + up(self.capacity * 32)
         tbox = order + up(self.capacity * 4)
-        return pc, box, mom, order, tbox
+        zrange = tbox + up(self.capacity * 16)
+        return pc, box, mom, order, tbox, zrange
 
     @property
     def popcounts(self) -> torch.Tensor:
@@ -183,6 +184,14 @@ class TumorDB:
         """int32 view [capacity][4] of the row boxes z0, z1, y0, y1 of the T1Gd bits alone."""
         off = self._offsets()[4]
         return self.storage[off:off + self.capacity * 16].view(torch.int32).view(self.capacity, 4)
+
+    @property
+    def zranges(self) -> torch.Tensor:
+        """int32 view [capacity][nz][2] of the per z-slice y-ranges of the FLAIR and the T1Gd
+        rows, each y0 | y1 << 16 ([y0, y1); 0 for a slice without such rows)."""
+        off = self._offsets()[5]
+        return (self.storage[off:off + self.capacity * self.dims[2] * 8].view(torch.int32)
+                .view(self.capacity, self.dims[2], 2))
 
     @property
     def tile_order(self) -> torch.Tensor:

@@ -336,7 +336,7 @@ size_t db_storage_bytes(int nx, int ny, int nz, int64_t capacity)
     return align_up((size_t)capacity * 2 * g.Wp * 4, kAlign) +
            align_up((size_t)capacity * 2 * 4, kAlign) + align_up((size_t)capacity * 4 * 4, kAlign) +
            align_up((size_t)capacity * 4 * 8, kAlign) + align_up((size_t)capacity * 4, kAlign) +
-           align_up((size_t)capacity * 4 * 4, kAlign);
+           align_up((size_t)capacity * 4 * 4, kAlign) + align_up((size_t)capacity * nz * 2 * 4, kAlign);
 }
 
 int db_build(db_t **out, int nx, int ny, int nz, float t_lo, float t_hi, int64_t capacity,
@@ -386,6 +386,8 @@ int db_build(db_t **out, int nx, int ny, int nz, float t_lo, float t_hi, int64_t
     db->tile_order = reinterpret_cast<int32_t *>(static_cast<char *>(storage) + o_ord);
     const size_t o_tbox = o_ord + align_up((size_t)capacity * 4, kAlign);
     db->tbox = reinterpret_cast<int32_t *>(static_cast<char *>(storage) + o_tbox);
+    const size_t o_zr = o_tbox + align_up((size_t)capacity * 4 * 4, kAlign);
+    db->zrange = reinterpret_cast<uint32_t *>(static_cast<char *>(storage) + o_zr);
     db->tile_order_n = 0;
     db->storage_bytes = storage_bytes;
     db->cus = cus;
@@ -419,7 +421,7 @@ int db_append(db_t *db, const float *conc, int64_t n, void *stream)
     hipError_t e = launch_pack_db(db, conc, n, planes, pc, s);
     if (e == hipSuccess)
         e = launch_meta(planes, n, db->g, db->box + db->count * 4, db->tbox + db->count * 4,
-                        db->mom + db->count * 4, s);
+                        db->mom + db->count * 4, db->zrange + db->count * db->g.nz * 2, s);
     if (e != hipSuccess) return hip_fail(e, "db_append: launch");
     db->count += n;
     return DB_OK;
@@ -1246,7 +1248,7 @@ int db_append_resampled(db_t *dst, const db_t *src, int64_t first, int64_t n, vo
     if (e == hipSuccess)
         e = launch_meta(dst->planes + dst->count * 2 * (int64_t)dst->g.Wp, n, dst->g,
                         dst->box + dst->count * 4, dst->tbox + dst->count * 4,
-                        dst->mom + dst->count * 4, s);
+                        dst->mom + dst->count * 4, dst->zrange + dst->count * dst->g.nz * 2, s);
     if (e != hipSuccess) return hip_fail(e, "db_append_resampled: launch");
     dst->count += n;
     return DB_OK;

@@ -501,6 +501,7 @@ constexpr int kRerankMaxCand = 1024;
 
 constexpr int kRC = 4;                 // candidates per wave
 constexpr int kRerankPerBlock = 4 * kRC;   // candidates scored per block (4 waves)
+constexpr int kZStage = 128;           // z-slices of per-slice row ranges a wave stages in LDS
 
 // 1-D grid of nbq * 8 * ceil(nq / 8) blocks (nbq = ceil(nc / kRerankPerBlock)),
 // 256 threads (4 waves). Blocks go to the 8 XCDs round-robin; the mapping below
@@ -514,7 +515,9 @@ constexpr int kRerankPerBlock = 4 * kRC;   // candidates scored per block (4 wav
 __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__restrict__ planes,
                                                            const uint32_t *__restrict__ popcnt,
                                                            const int32_t *__restrict__ ebox,
-                                                           const int32_t *__restrict__ etbox, int Wp,
+                                                           const int32_t *__restrict__ etbox,
+                                                           const uint32_t *__restrict__ zrange,
+                                                           int nz, int Wp,
                                                            int nxw, int ny,
                                                            const uint32_t *__restrict__ qpack,
                                                            const uint32_t *__restrict__ acnt,
@@ -574,6 +577,28 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
     }
     const int nyr = uy1 > uy0 ? uy1 - uy0 : 0;
     const int nr = uz1 > uz0 ? (uz1 - uz0) * nyr : 0;
+    // Each member's per-slice y-ranges of its FLAIR and T1Gd rows over the slices swept, in
+    // this wave's part of LDS (a sweep deeper than kZStage slices goes by the boxes alone).
+    __shared__ uint2 s_zr[4][kRC][kZStage];
+    const bool zr_ok = nr > 0 && uz1 - uz0 <= kZStage;
+    if (zr_ok) {
+        const int nzs = uz1 - uz0;
+        for (int i = lane; i < kRC * nzs; i += 64) {
+            const int j = i / nzs, zz = i - j * nzs;
+            const int32_t e = cand[(int64_t)q * nc + min(c0 + j, nc - 1)];
+            s_zr[wave][j][zz] = *reinterpret_cast<const uint2 *>(zrange + ((int64_t)e * nz + uz0 + zz) * 2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // Row (z, y) of member j holds FLAIR bits only if y is in its FLAIR range of slice z.
+    auto in_range = [&](int j, int z, int y, bool t1gd) {
+        if (!zr_ok) return true;
+        const uint2 rg = s_zr[wave][j][z - uz0];
+        const uint32_t v = t1gd ? rg.y : rg.x;
+        return y >= (int)(v & 0xffffu) && y < (int)(v >> 16);
+    };
     uint32_t i0[kRC], i1[kRC];
 #pragma unroll
     for (int j = 0; j < kRC; ++j) i0[j] = i1[j] = 0;
@@ -593,8 +618,10 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
                 bool any0 = false, any1 = false;
 #pragma unroll
                 for (int j = 0; j < kRC; ++j) {
-                    const bool in0 = live && z >= z0[j] && z < z1[j] && y >= y0[j] && y < y1[j];
-                    const bool in1 = live && z >= tz0[j] && z < tz1[j] && y >= ty0[j] && y < ty1[j];
+                    const bool in0 = live && z >= z0[j] && z < z1[j] && y >= y0[j] && y < y1[j] &&
+                                     in_range(j, z, y, false);
+                    const bool in1 = live && z >= tz0[j] && z < tz1[j] && y >= ty0[j] && y < ty1[j] &&
+                                     in_range(j, z, y, true);
                     any0 |= in0;
                     any1 |= in1;
                     da[u][j] = db[u][j] = (u32x4){0u, 0u, 0u, 0u};
@@ -621,8 +648,8 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
             bool in0[kRC], in1[kRC];
 #pragma unroll
             for (int j = 0; j < kRC; ++j) {
-                in0[j] = z >= z0[j] && z < z1[j] && y >= y0[j] && y < y1[j];
-                in1[j] = z >= tz0[j] && z < tz1[j] && y >= ty0[j] && y < ty1[j];
+                in0[j] = z >= z0[j] && z < z1[j] && y >= y0[j] && y < y1[j] && in_range(j, z, y, false);
+                in1[j] = z >= tz0[j] && z < tz1[j] && y >= ty0[j] && y < ty1[j] && in_range(j, z, y, true);
             }
             for (int w = 0; w < nxw; ++w) {
                 const uint32_t qa = Q0[base + w], qb = Q1[base + w];
@@ -1481,8 +1508,8 @@ hipError_t launch_rerank_score(const db_t *db, int nq, const uint32_t *qpack, co
     const int nbq = (nc + kRerankPerBlock - 1) / kRerankPerBlock;
     const int64_t blocks = (int64_t)nbq * 8 * ((nq + 7) / 8);
     hipLaunchKernelGGL(rerank_score_kernel, dim3((unsigned)blocks), dim3(256), 0, s, db->planes,
-                       db->popcnt, db->box, db->tbox, g.Wp, g.nxw, g.ny, qpack, acnt, box, tbox,
-                       cand, nc, ws_s, ws_i, ws_I, nq, nbq);
+                       db->popcnt, db->box, db->tbox, db->zrange, g.nz, g.Wp, g.nxw, g.ny, qpack,
+                       acnt, box, tbox, cand, nc, ws_s, ws_i, ws_I, nq, nbq);
     return hipGetLastError();
 }
 

@@ -44,6 +44,7 @@ struct db_t {
     uint32_t *popcnt;   // [capacity][2]
     int32_t *box;       // [capacity][4] row box z0, z1, y0, y1 of the set bits
     int32_t *tbox;      // [capacity][4] row box of the T1Gd bits alone (all zero: none)
+    uint32_t *zrange;   // [capacity][nz][2] per z-slice y-range of the FLAIR / T1Gd rows
     uint64_t *mom;      // [capacity][4] FLAIR moments: sum x, sum y, sum z, count
     int32_t *tile_order;  // [capacity] entries sorted by row-box centre, in tiles by cost
     int64_t tile_order_n; // entries the tile order covers (it is rebuilt when count differs)
@@ -176,9 +177,10 @@ hipError_t launch_rerank_rank(const db_t *db, int nq, const uint32_t *acnt, int 
                               hipStream_t s);
 
 // Row boxes, moments, box-restricted scan, centre-of-mass distances (sparse.hip).
-// Per entry of recs: box (rows with a set bit), tbox (rows with a T1Gd bit), mom.
+// Per entry of recs: box (rows with a set bit), tbox (rows with a T1Gd bit), mom, and the
+// per z-slice y-ranges of its FLAIR and T1Gd rows zrange [nz][2] (y0 | y1 << 16; 0: none).
 hipError_t launch_meta(const uint32_t *recs, int64_t n, const Geometry &g, int32_t *box,
-                       int32_t *tbox, uint64_t *mom, hipStream_t s);
+                       int32_t *tbox, uint64_t *mom, uint32_t *zrange, hipStream_t s);
 // qtbox: the query's T1Gd row box (the T1Gd plane is read only inside both T1Gd boxes).
 hipError_t launch_box_scan(const db_t *db, int64_t n, const uint32_t *qpack, const int32_t *qbox,
                            const int32_t *qtbox, uint32_t *inter, hipStream_t s);

@@ -22,43 +22,74 @@
 namespace tdb {
 
 // One 256-thread block per record of `rec_words` words (two planes of Wp words): its row box
-// [4] (rows with a set bit in either mask), the row box of its T1Gd bits alone [4] and its
-// FLAIR moments [4] = (sum x, sum y, sum z, count). Boxes are [z0, z1) x [y0, y1), all zero
-// when empty.
+// [4] (rows with a set bit in either mask), the row box of its T1Gd bits alone [4], its
+// FLAIR moments [4] = (sum x, sum y, sum z, count) and, per z-slice, the y-range of the rows
+// with a FLAIR bit and of those with a T1Gd bit (zrange [nz][2], y0 | y1 << 16, [y0, y1);
+// zero when the slice has none). Boxes are [z0, z1) x [y0, y1), all zero when empty. The
+// slices are taken kZChunk at a time, their ranges gathered with LDS atomics.
+constexpr int kZChunk = 512;
+
 __global__ void __launch_bounds__(256) meta_kernel(const uint32_t *__restrict__ recs,
                                                    int64_t rec_words, int Wp, int W, int nxw,
                                                    int ny, int32_t *__restrict__ box,
                                                    int32_t *__restrict__ tbox,
-                                                   uint64_t *__restrict__ mom)
+                                                   uint64_t *__restrict__ mom,
+                                                   uint32_t *__restrict__ zrange)
 {
     __shared__ int rb[4][8];
     __shared__ uint64_t rm[4][4];
+    __shared__ int zy[4][kZChunk];             // per slice of the chunk: FLAIR y lo, hi; T1Gd
     const int64_t e = blockIdx.x;
     const uint32_t *P0 = recs + e * rec_words, *P1 = P0 + Wp;
+    const int slice_w = ny * nxw, nz = W / slice_w;
     int bx[8] = {INT_MAX, -1, INT_MAX, -1, INT_MAX, -1, INT_MAX, -1};   // z lo/hi, y lo/hi; twice
     uint64_t sx = 0, sy = 0, sz = 0, cnt = 0;
-    for (int w = threadIdx.x; w < W; w += blockDim.x) {
-        const uint32_t a = P0[w], b = P1[w];
-        if (a | b) {
-            const int row = w / nxw;
-            const int wx = w - row * nxw;
-            const int z = row / ny, y = row - z * ny;
-            bx[0] = min(bx[0], z);
-            bx[1] = max(bx[1], z);
-            bx[2] = min(bx[2], y);
-            bx[3] = max(bx[3], y);
-            if (b) {
-                bx[4] = min(bx[4], z);
-                bx[5] = max(bx[5], z);
-                bx[6] = min(bx[6], y);
-                bx[7] = max(bx[7], y);
-            }
-            const uint32_t c = popc(a);
-            cnt += c;
-            sx += (uint64_t)(32u * (uint32_t)wx) * c + bit_position_sum(a);
-            sy += (uint64_t)y * c;
-            sz += (uint64_t)z * c;
+    for (int zc = 0; zc < nz; zc += kZChunk) {
+        const int nzc = min(kZChunk, nz - zc);
+        for (int i = threadIdx.x; i < nzc; i += blockDim.x) {
+            zy[0][i] = zy[2][i] = INT_MAX;
+            zy[1][i] = zy[3][i] = -1;
         }
+        __syncthreads();
+        const int wend = (zc + nzc) * slice_w;
+        for (int w = zc * slice_w + threadIdx.x; w < wend; w += blockDim.x) {
+            const uint32_t a = P0[w], b = P1[w];
+            if (a | b) {
+                const int row = w / nxw;
+                const int wx = w - row * nxw;
+                const int z = row / ny, y = row - z * ny;
+                bx[0] = min(bx[0], z);
+                bx[1] = max(bx[1], z);
+                bx[2] = min(bx[2], y);
+                bx[3] = max(bx[3], y);
+                if (a) {
+                    atomicMin(&zy[0][z - zc], y);
+                    atomicMax(&zy[1][z - zc], y);
+                }
+                if (b) {
+                    bx[4] = min(bx[4], z);
+                    bx[5] = max(bx[5], z);
+                    bx[6] = min(bx[6], y);
+                    bx[7] = max(bx[7], y);
+                    atomicMin(&zy[2][z - zc], y);
+                    atomicMax(&zy[3][z - zc], y);
+                }
+                const uint32_t c = popc(a);
+                cnt += c;
+                sx += (uint64_t)(32u * (uint32_t)wx) * c + bit_position_sum(a);
+                sy += (uint64_t)y * c;
+                sz += (uint64_t)z * c;
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < nzc; i += blockDim.x) {
+            uint32_t *o = zrange + (e * nz + zc + i) * 2;
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+                o[p] = zy[2 * p + 1][i] < 0 ? 0u
+                                            : (uint32_t)zy[2 * p][i] | ((uint32_t)(zy[2 * p + 1][i] + 1) << 16);
+        }
+        __syncthreads();                        // the next chunk reuses zy
     }
 #pragma unroll
     for (int i = 0; i < 8; ++i) bx[i] = (i & 1) ? wave_max(bx[i]) : wave_min(bx[i]);
@@ -108,10 +139,10 @@ __global__ void __launch_bounds__(256) meta_kernel(const uint32_t *__restrict__ 
 }
 
 hipError_t launch_meta(const uint32_t *recs, int64_t n, const Geometry &g, int32_t *box,
-                       int32_t *tbox, uint64_t *mom, hipStream_t s)
+                       int32_t *tbox, uint64_t *mom, uint32_t *zrange, hipStream_t s)
 {
     hipLaunchKernelGGL(meta_kernel, dim3((unsigned)n), dim3(256), 0, s, recs, 2 * (int64_t)g.Wp,
-                       g.Wp, g.W, g.nxw, g.ny, box, tbox, mom);
+                       g.Wp, g.W, g.nxw, g.ny, box, tbox, mom, zrange);
     return hipGetLastError();
 }
 
@@ -128,11 +159,14 @@ __device__ __forceinline__ int row_div(int r, int nyr, float inv)
 // One wave per entry, four entries per 256-thread block. Lanes sweep the
 // flattened rows of (entry box n query box); x-rows of 128 voxels (nxw == 4)
 // are single 16-byte loads, other widths go word by word.
+constexpr int kZStageScan = 128;   // z-slices of the entry's row ranges a wave stages in LDS
+
 template <bool V4, int U>
 __global__ void __launch_bounds__(256) box_scan_kernel(const uint32_t *__restrict__ planes, int Wp,
-                                                       int nxw, int ny,
+                                                       int nxw, int ny, int nz,
                                                        const int32_t *__restrict__ box,
                                                        const int32_t *__restrict__ tbox,
+                                                       const uint32_t *__restrict__ zrange,
                                                        const uint32_t *__restrict__ qpack,
                                                        const int32_t *__restrict__ qbox,
                                                        const int32_t *__restrict__ qtbox, int64_t n,
@@ -151,6 +185,24 @@ __global__ void __launch_bounds__(256) box_scan_kernel(const uint32_t *__restric
     const int nyr = y1 - y0;
     const int nr = (z1 > z0 && nyr > 0) ? (z1 - z0) * nyr : 0;
     const float inv = nyr > 0 ? 1.0f / (float)nyr : 0.0f;
+    // The entry's per-slice y-ranges of its FLAIR and T1Gd rows over the slices swept, in this
+    // wave's part of LDS (a box deeper than kZStageScan slices goes by the boxes alone).
+    __shared__ uint2 s_zr[4][kZStageScan];
+    const int wv = threadIdx.x >> 6;
+    const bool zr_ok = nr > 0 && z1 - z0 <= kZStageScan;
+    if (zr_ok) {
+        for (int i = lane; i < z1 - z0; i += 64)
+            s_zr[wv][i] = *reinterpret_cast<const uint2 *>(zrange + (e * nz + z0 + i) * 2);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    auto in_range = [&](int z, int y, bool t1gd) {
+        if (!zr_ok) return true;
+        const uint2 rg = s_zr[wv][z - z0];
+        const uint32_t v = t1gd ? rg.y : rg.x;
+        return y >= (int)(v & 0xffffu) && y < (int)(v >> 16);
+    };
     const uint32_t *D0 = planes + e * 2 * (int64_t)Wp, *D1 = D0 + Wp;
     const uint32_t *Q0 = qpack, *Q1 = qpack + Wp;
     uint32_t c0 = 0, c1 = 0;
@@ -165,9 +217,11 @@ __global__ void __launch_bounds__(256) box_scan_kernel(const uint32_t *__restric
                     const int zr = row_div(r, nyr, inv);
                     const int z = z0 + zr, y = y0 + r - zr * nyr;
                     const int64_t base = ((int64_t)z * ny + y) * 4;
-                    d0[u] = load_stream(reinterpret_cast<const u32x4 *>(D0 + base));
-                    q0[u] = *reinterpret_cast<const u32x4 *>(Q0 + base);
-                    if (z >= tz0 && z < tz1 && y >= ty0 && y < ty1) {
+                    if (in_range(z, y, false)) {
+                        d0[u] = load_stream(reinterpret_cast<const u32x4 *>(D0 + base));
+                        q0[u] = *reinterpret_cast<const u32x4 *>(Q0 + base);
+                    }
+                    if (z >= tz0 && z < tz1 && y >= ty0 && y < ty1 && in_range(z, y, true)) {
                         d1[u] = load_stream(reinterpret_cast<const u32x4 *>(D1 + base));
                         q1[u] = *reinterpret_cast<const u32x4 *>(Q1 + base);
                     }
@@ -186,8 +240,9 @@ __global__ void __launch_bounds__(256) box_scan_kernel(const uint32_t *__restric
             const int zr = row_div(r, nyr, inv);
             const int z = z0 + zr, y = y0 + r - zr * nyr;
             const int64_t base = ((int64_t)z * ny + y) * nxw + w;
-            c0 += popc(Q0[base] & D0[base]);
-            if (z >= tz0 && z < tz1 && y >= ty0 && y < ty1) c1 += popc(Q1[base] & D1[base]);
+            if (in_range(z, y, false)) c0 += popc(Q0[base] & D0[base]);
+            if (z >= tz0 && z < tz1 && y >= ty0 && y < ty1 && in_range(z, y, true))
+                c1 += popc(Q1[base] & D1[base]);
         }
     }
     c0 = wave_sum(c0);
@@ -205,12 +260,12 @@ hipError_t launch_box_scan(const db_t *db, int64_t n, const uint32_t *qpack, con
     const int64_t blocks = (n + 3) / 4;
     if (g.nxw == 4)
         hipLaunchKernelGGL((box_scan_kernel<true, 4>), dim3((unsigned)blocks), dim3(256), 0, s,
-                           db->planes, g.Wp, g.nxw, g.ny, db->box, db->tbox, qpack, qbox, qtbox, n,
-                           inter);
+                           db->planes, g.Wp, g.nxw, g.ny, g.nz, db->box, db->tbox, db->zrange,
+                           qpack, qbox, qtbox, n, inter);
     else
         hipLaunchKernelGGL((box_scan_kernel<false, 1>), dim3((unsigned)blocks), dim3(256), 0, s,
-                           db->planes, g.Wp, g.nxw, g.ny, db->box, db->tbox, qpack, qbox, qtbox, n,
-                           inter);
+                           db->planes, g.Wp, g.nxw, g.ny, g.nz, db->box, db->tbox, db->zrange,
+                           qpack, qbox, qtbox, n, inter);
     return hipGetLastError();
 }
 

@@ -37,15 +37,16 @@ def test_library_exports_every_declared_symbol():
 def test_storage_bytes():
     from paper_2205_04550_amd import binding
     # 128^3: 65,536 words per mask plane, 2 planes, 4 bytes; popcounts 8 bytes per entry;
-    # row boxes 16, moments 32, the tile order 4 and the T1Gd row boxes 16 bytes per entry;
-    # each piece 256-byte aligned.
+    # row boxes 16, moments 32, the tile order 4, the T1Gd row boxes 16 and the per-slice
+    # y-ranges 8 nz bytes per entry; each piece 256-byte aligned.
     up = lambda b: (b + 255) // 256 * 256
     planes = 50000 * 2 * 65536 * 4
-    meta = up(50000 * 8) + up(50000 * 16) + up(50000 * 32) + up(50000 * 4) + up(50000 * 16)
+    meta = (up(50000 * 8) + up(50000 * 16) + up(50000 * 32) + up(50000 * 4) + up(50000 * 16) +
+            up(50000 * 128 * 8))
     assert binding.storage_bytes(128, 128, 128, 50000) == planes + meta
     # Ragged plane: 32x3x1 = 3 words, padded to 4: 10*2*4*4 = 320 -> 512; then 80, 160,
-    # 320, 40 and 160 bytes -> 256, 256, 512, 256 and 256.
-    assert binding.storage_bytes(32, 3, 1, 10) == 512 + 256 + 256 + 512 + 256 + 256
+    # 320, 40, 160 and 80 bytes -> 256, 256, 512, 256, 256 and 256.
+    assert binding.storage_bytes(32, 3, 1, 10) == 512 + 256 + 256 + 512 + 256 + 256 + 256
     assert binding.storage_bytes(33, 4, 4, 10) == 0      # nx not a multiple of 32
     assert binding.storage_bytes(32, 0, 4, 10) == 0
     assert binding.storage_bytes(32, 4, 4, 0) == 0

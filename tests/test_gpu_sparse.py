@@ -44,10 +44,20 @@ def test_meta_and_sparse_query_match_oracle(dims):
     for d, L in ((db, labs), (db2, labs2)):
         boxes = _host(d.boxes)[:len(L)]
         tboxes = _host(d.tboxes)[:len(L)]
+        zr = _host(d.zranges)[:len(L)].view(np.uint32)
         moms = _host(d.moments)[:len(L)].view(np.uint64)
         for i in range(len(L)):
             assert tuple(boxes[i]) == oracle.rowbox(L[i]), i
             assert tuple(tboxes[i]) == oracle.rowbox(L[i] & 2), i      # the T1Gd rows alone
+            # Per z-slice: [y0, y1) of the rows holding a FLAIR bit, and of those holding a T1Gd
+            # bit, packed y0 | y1 << 16 (0 for a slice without any).
+            for p, bit in ((0, 1), (1, 2)):
+                rows = ((L[i] & bit) != 0).any(axis=2)                  # [nz][ny]
+                want = np.zeros(L[i].shape[0], np.uint32)
+                for z in np.nonzero(rows.any(axis=1))[0]:
+                    ys = np.nonzero(rows[z])[0]
+                    want[z] = int(ys.min()) | (int(ys.max()) + 1) << 16
+                assert np.array_equal(zr[i, :, p], want), (i, p)
             assert tuple(int(v) for v in moms[i]) == oracle.moments(L[i]), i
     rng = np.random.default_rng(3)
     for j, q in enumerate(_edge_queries(gen, labs2, rng)):
