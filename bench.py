@@ -731,9 +731,10 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
                      "frac": rr_bytes / (rr_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "rerank_score_kernel", "kernel_avg_ms": rr_avg,
                      "algorithmic_bytes_per_launch": rr_bytes,
-                     "note": "the longest single launch of the step; bytes = database rows inside "
-                             "(query row box n candidate row box) for FLAIR, inside (query T1Gd "
-                             "row box n candidate T1Gd row box) for T1Gd"},
+                     "note": "the longest single launch of the step; bytes = database rows of "
+                             "the slices inside (query row box n candidate row box) for FLAIR, "
+                             "inside (query T1Gd row box n candidate T1Gd row box) for T1Gd, "
+                             "each within the candidate's y-range of that plane in the slice"},
         "encode_stage_roofline": {
             "bound": "hbm", "achieved": enc_bytes / (stage[0] * 1e-3) / 1e9,
             "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -82,7 +82,12 @@ enum {
  *             db_query_batch (library-internal);
  *   tbox:     int32 [capacity][4], the box of the x-rows holding a T1Gd bit
  *             (as box, for that mask alone; the rerank reads an entry's T1Gd
- *             plane only inside it).
+ *             plane only inside it);
+ *   zrange:   uint32 [capacity][nz][2]: for slice z of an entry, element 0
+ *             covers the x-rows holding a FLAIR bit and element 1 those
+ *             holding a T1Gd bit, as y0 | y1 << 16 with the rows in
+ *             [y0, y1) (0 for a slice without such a row). The rerank and
+ *             the row-box scan read a plane's row (z, y) only inside it.
  * Returns 0 if the dimensions are invalid. */
 size_t db_storage_bytes(int nx, int ny, int nz, int64_t capacity);
 
