@@ -117,6 +117,20 @@ int nn_pool_conv_planes_bf16(const uint32_t *planes, int64_t sample_words, const
 int nn_pool_conv_counts_bf16(const uint8_t *counts, int B, int nx, int ny, int nz, int mask,
                              int Co, const void *Wt, const float *bias, int relu, void *Y,
                              void *stream);
+/* The encoder's first two layers in one pass (Sec. 2.3, "Autoencoders": the convolutions of
+ * the halved input): nn_pool_conv_counts_bf16 with Co = 8 and ReLU, then
+ * nn_conv3d_s2_fwd_bf16 with (Ci, Co) = (8, 16) and ReLU, bit for bit, without the first
+ * layer's activations leaving the chip. counts uint8 [B][nz/2][ny/2][nx/2] as for
+ * nn_pool_conv_counts_bf16 (16-byte aligned); Wt1 bfloat16 [8][Ci][27] (Ci = 2, or 1 with
+ * mask = 0 / 1 as there); b1 float [8] or NULL; Wtm2 the tap-major bfloat16 second-layer
+ * weights [16][28][8] of nn_conv3d_weights_tapmajor (16-byte aligned); b2 float [16] or NULL;
+ * Y bfloat16 channels-last [B][nz/8][ny/8][nx/8][16] (8-byte aligned). nx % 128 == 0,
+ * ny % 32 == 0, nz % 16 == 0 (the grids of the two kernels), nx * ny * nz < 2^31;
+ * DB_EINVAL otherwise. All device
+ * pointers, owned by the caller; enqueued on `stream`. */
+int nn_counts_conv12_bf16(const uint8_t *counts, int B, int nx, int ny, int nz, int mask,
+                          const void *Wt1, const float *b1, const void *Wtm2, const float *b2,
+                          void *Y, void *stream);
 /* Tap-major copy of bfloat16 convolution weights for nn_conv3d_s2_fwd_bf16:
  * out[co][t][ci] = Wt[co][ci][t] for the 27 taps t (kd, kh, kw order) and 0 for
  * t = 27; out holds Co * 28 * Ci bfloat16 values (device). */

@@ -1309,21 +1309,21 @@ __global__ void __launch_bounds__(256) pool_conv_labels_kernel(const uint8_t *__
 // one is computed.
 __device__ __forceinline__ void count_words(uint32_t cb, int Ci, int mask, uint32_t (&w)[4])
 {
-    // Counts k -> float k (one conversion per byte) -> the two channels' bfloat16 values in
-    // one word -> k / 8 by lowering both exponents by 3 (a saturating 16-bit subtract, so
-    // k = 0 stays 0). One mask: it goes to channel 0, channel 1 stays zero.
+    // A count k in 0..8 read as an e4m3 FP8 code is k 2^-9 exactly (codes 1..7 are
+    // subnormal, 8 is 2^-6), so the scaled FP8 -> bfloat16 pair conversion with scale 2^6
+    // gives k / 8: each count pair (FLAIR, T1Gd), interleaved into byte pairs, becomes one
+    // word in one instruction. One mask: it goes to channel 0, channel 1 stays zero.
     uint32_t f = cb & 0x0f0f0f0fu, h = (cb >> 4) & 0x0f0f0f0fu;
     if (Ci == 1) {
         if (mask == 1) f = h;
         h = 0u;
     }
-    asm volatile("" : "+v"(f), "+v"(h));   // keep the byte-wise conversions
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const uint32_t x = bf16x2_rne((float)((f >> (8 * e)) & 0xffu), (float)((h >> (8 * e)) & 0xffu));
-        w[e] = __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(
-                                                __builtin_bit_cast(u16x2, x), (u16x2){0x180, 0x180}));
-    }
+    const uint32_t lo = __builtin_amdgcn_perm(h, f, 0x05010400u);   // f0 h0 f1 h1
+    const uint32_t hi = __builtin_amdgcn_perm(h, f, 0x07030602u);   // f2 h2 f3 h3
+    w[0] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(lo, 64.f, false));
+    w[1] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(lo, 64.f, true));
+    w[2] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(hi, 64.f, false));
+    w[3] = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(hi, 64.f, true));
 }
 
 template <bool OUTBF>
@@ -1549,6 +1549,289 @@ __global__ void __launch_bounds__(256, 4) conv_bf16_kernel(int D, int H, int W, 
             }
         }
         __syncthreads();                                    // the next patch overwrites xs
+    }
+}
+
+// ---- The first two layers in one pass ---------------------------------------------------
+//
+// pool_conv_counts_kernel followed by conv_bf16_kernel<8, 16, ...> without the first layer's
+// activations leaving the chip. A block owns the 4 x 16 (y, x) second-layer outputs at
+// (Y0, X0) of one sample over zc consecutive output slices and walks them in z. Each step loads
+// the next four pooled slices into a ring of five (19 rows of 64 counts and the word before
+// each row: the 4 x 16 outputs' pooled patch), computes the next two first-layer slices of the
+// second layer's patch (9 rows x 33 x) into a ring of three, then the step's output slice.
+// Both layers take the operands, sums and roundings of those two kernels, so Y equals
+// conv_bf16(pool_conv_counts(C)) bit for bit (a first-layer sum is never -0, so ReLU as a
+// maximum gives the same bits); first-layer voxels outside the volume are the second layer's
+// zero padding. ReLU after both layers (the encoder's). CI: 2, or 1 (the mask `mask` alone).
+constexpr int kC12Rows = 19;                  // pooled rows of a slice patch: 4 x 4 + 3
+constexpr int kC12Half = 17;                  // first-layer voxels per row and x parity
+constexpr int kC12L1 = 9 * 2 * kC12Half;      // first-layer voxels per slice, 16 bytes each
+constexpr int kC12Main = 4 * kC12Rows;        // 16-count groups of a pooled slice
+
+// Pooled item `it` of a load of ns slices: it < 4 ns 19 is group p (16 counts at pooled x
+// 4 X0 + 16 p) of row r of slice s; the next 19 ns are the words before the rows (pooled x
+// 4 X0 - 4 .. - 1), halo = true.
+__device__ __forceinline__ void c12_item(int it, int ns, int &s, int &r, int &p, bool &halo)
+{
+    halo = it >= ns * kC12Main;
+    const int h = it - ns * kC12Main;
+    s = halo ? h / kC12Rows : it / kC12Main;
+    const int rem = halo ? h - s * kC12Rows : it - s * kC12Main;
+    r = halo ? rem : rem >> 2;
+    p = halo ? 4 : rem & 3;
+}
+
+template <int CI>
+__global__ void __launch_bounds__(256, 4) counts_conv12_kernel(
+    const uint8_t *__restrict__ C, int nx, int ny, int nz, int mask, int zc, int units,
+    const uint16_t *__restrict__ Wt1, const float *__restrict__ b1,
+    const uint16_t *__restrict__ Wtm2, const float *__restrict__ b2, uint16_t *__restrict__ Y)
+{
+    __shared__ __attribute__((aligned(16))) uint32_t pool[5 * kC12Rows * kPlRow];
+    __shared__ __attribute__((aligned(16))) uint16_t l1[3 * kC12L1 * 8];
+    const int PY = ny / 2, PX = nx / 2;
+    const int OD2 = nz / 8, OH2 = ny / 8, OW2 = nx / 8;
+    const int tx_n = OW2 / 16, ty_n = OH2 / 4, zc_n = OD2 / zc;
+    // Unit u: x tile fastest, then y tile, z chunk, sample. With units % 8 == 0 the units one
+    // XCD receives (blocks x, x + 8, ...) are one contiguous run, so the neighbours that share
+    // pooled halo rows read them through one L2.
+    int u = blockIdx.x;
+    if (units % 8 == 0) u = (blockIdx.x % 8) * (units / 8) + blockIdx.x / 8;
+    const int tx = u % tx_n, ty = (u / tx_n) % ty_n, zi = (u / (tx_n * ty_n)) % zc_n;
+    const int b = u / (tx_n * ty_n * zc_n);
+    const int X0 = 16 * tx, Y0 = 4 * ty, oz0 = zi * zc;
+    const int64_t slice = (int64_t)PY * PX;
+    const uint8_t *Cb = C + (int64_t)b * (nz / 2) * slice + 4 * X0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, j = lane & 15;
+
+    // First layer: this lane's weights and biases (first_layer_setup's layout), and per tap
+    // of its two products the pooled slice (kd) and the offset within the slice.
+    bf16x8 a1[2];
+    float bc1[4];
+    {
+        int unused[2][4];
+        first_layer_setup(Wt1, b1, CI, 8, 0, g, j, a1, bc1, unused);
+    }
+    int kd1[2][4], to1[2][4];
+#pragma unroll
+    for (int st = 0; st < 2; ++st)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int tap = 16 * st + 4 * g + i;   // >= 27: weight zero, any written word
+            kd1[st][i] = tap < 27 ? tap / 9 : 0;
+            to1[st][i] = tap < 27 ? ((tap / 3) % 3) * kPlRow + tap % 3 : 0;
+        }
+    // Second layer: weights (conv_bf16_kernel's tap-major layout; lane quarter g is the
+    // k group), biases, and per product step the first-layer slice (kd) and voxel of the
+    // lane's output voxel (row wave, x j).
+    bf16x8 a2[7];
+    int kd2[7], vo2[7];
+#pragma unroll
+    for (int st = 0; st < 7; ++st) {
+        a2[st] = *reinterpret_cast<const bf16x8 *>(Wtm2 + j * 28 * 8 + 8 * g + 32 * st);
+        const int tap = 4 * st + g, tp = tap < 27 ? tap : 0;
+        const int kd = tp / 9, kh = (tp / 3) % 3, kw = tp % 3;
+        kd2[st] = kd;
+        vo2[st] = ((2 * wave + kh) * 2 + (kw & 1)) * kC12Half + j + (kw >> 1);
+    }
+    float bc2[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bc2[r] = b2 ? b2[4 * g + r] : 0.f;
+
+    // The pooled items of the four-slice loads, two per thread: per item its slice, the
+    // offset of its counts from slice pzf's row 4 Y0 - 3 (pooled y checked per load) and its
+    // LDS word within the slot. At X0 = 0 the words before the rows are zero, written once.
+    const int nit = 4 * kC12Main + (X0 > 0 ? 4 * kC12Rows : 0);
+    int is[2], iy[2], ig[2], il[2];
+    bool ih[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        int s, r, p;
+        bool halo;
+        c12_item(tid + 256 * k, 4, s, r, p, halo);
+        is[k] = s;
+        iy[k] = 4 * Y0 - 3 + r;
+        ig[k] = (int)(s * slice) + iy[k] * PX + (halo ? -4 : 16 * p);
+        il[k] = r * kPlRow + (halo ? 0 : 4 + 16 * p);
+        ih[k] = halo;
+    }
+    u32x4 v[2];
+    auto load4 = [&](int pzf) {
+        const uint8_t *base = Cb + (int64_t)pzf * slice;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            v[k] = (u32x4){0u, 0u, 0u, 0u};
+            if (tid + 256 * k < nit && iy[k] >= 0 && iy[k] < PY) {
+                if (!ih[k]) v[k] = *reinterpret_cast<const u32x4 *>(base + ig[k]);
+                else v[k].x = *reinterpret_cast<const uint32_t *>(base + ig[k]);
+            }
+        }
+    };
+    auto words = [&](uint32_t cb, uint32_t *d) {
+        uint32_t w[4];
+        count_words(cb, CI, mask, w);
+        *reinterpret_cast<u32x4 *>(d) = (u32x4){w[0], w[1], w[2], w[3]};
+    };
+    auto store4 = [&](int pzf) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (tid + 256 * k < nit) {
+                uint32_t *d = pool + ((pzf + is[k] + 5) % 5) * kC12Rows * kPlRow + il[k];
+                if (!ih[k]) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) words(v[k][e], d + 4 * e);
+                } else {
+                    words(v[k].x, d);
+                }
+            }
+        }
+    };
+
+    // One first-layer slice z1: wave w takes the x half w % 2 of the rows r1 = p, p + 2, ...
+    // (p = (w / 2) ^ s, so two slices give every wave nine columns of 16 voxels); with
+    // X0 > 0 wave 2 + s also takes the column x = 2 X0 - 1 of the nine rows (lane j = row).
+    auto l1_slice = [&](int z1, int s) {
+        int sb[3];
+#pragma unroll
+        for (int kd = 0; kd < 3; ++kd) sb[kd] = ((2 * z1 - 1 + kd + 5) % 5) * kC12Rows * kPlRow;
+        const int lsb = ((z1 + 3) % 3) * kC12L1;
+        const int p = (wave >> 1) ^ s, h = wave & 1;
+        const bool zin = z1 >= 0;
+        int o[2][4];
+#pragma unroll
+        for (int st = 0; st < 2; ++st)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                o[st][i] = (kd1[st][i] == 0 ? sb[0] : kd1[st][i] == 1 ? sb[1] : sb[2]) +
+                           to1[st][i] + 2 * p * kPlRow + 32 * h + 2 * j + 3;
+        // First-layer voxel x = 2 X0 + 16 h + j is patch column c1 = 1 + 16 h + j.
+        const int sl = lsb + p * 2 * kC12Half + ((1 + j) & 1) * kC12Half + 8 * h + ((1 + j) >> 1);
+        auto product = [&](int k) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int st = 0; st < 2; ++st) {
+                const u32x4 bw = {pool[o[st][0] + 4 * k * kPlRow], pool[o[st][1] + 4 * k * kPlRow],
+                                  pool[o[st][2] + 4 * k * kPlRow], pool[o[st][3] + 4 * k * kPlRow]};
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[st], __builtin_bit_cast(bf16x8, bw),
+                                                              acc, 0, 0, 0);
+            }
+            return acc;
+        };
+        // Bias, ReLU, bfloat16 of a column's channels (lanes 0..31); zero for a row r1 = p + 2 k
+        // outside the volume (y = 2 Y0 - 1 + r1 < 0 only for r1 = 0, Y0 = 0) or a slice below it.
+        auto finish = [&](f32x4 acc, bool inside) {
+            float y[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) y[r] = fmaxf(acc[r] + bc1[r], 0.f);
+            const uint32_t m = inside ? 0xffffffffu : 0u;
+            return (u32x2){bf16x2_rne(y[0], y[1]) & m, bf16x2_rne(y[2], y[3]) & m};
+        };
+        auto in_vol = [&](int k) { return zin && (p + k > 0 || Y0 > 0); };
+        // Columns k, k + 1 in one store: lanes 0..31 (channels 0..7) of column k + 1 go to the
+        // unused lanes 32..63 of column k, which then store to column k + 1's slots.
+        const int pst = (sl + (g >= 2 ? 4 * kC12Half : 0)) * 8 + 4 * (g & 1);
+#pragma unroll
+        for (int k = 0; k < 4; k += 2) {
+            const u32x2 e0 = finish(product(k), in_vol(k)), e1 = finish(product(k + 1), in_vol(k + 1));
+            const u32x2 c = {__builtin_amdgcn_permlane32_swap(e0.x, e1.x, false, false)[0],
+                             __builtin_amdgcn_permlane32_swap(e0.y, e1.y, false, false)[0]};
+            *reinterpret_cast<u32x2 *>(&l1[pst + 4 * k * kC12Half * 8]) = c;
+        }
+        if (!p) {                                  // even rows: r1 = 8 as well
+            const u32x2 e = finish(product(4), in_vol(4));
+            if (g < 2) *reinterpret_cast<u32x2 *>(&l1[(sl + 16 * kC12Half) * 8 + 4 * g]) = e;
+        }
+        if (X0 > 0 && wave == 2 + s) {
+            const int r1 = j < 9 ? j : 8;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int st = 0; st < 2; ++st) {
+                int w4[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    w4[i] = (kd1[st][i] == 0 ? sb[0] : kd1[st][i] == 1 ? sb[1] : sb[2]) + to1[st][i] +
+                            2 * r1 * kPlRow + 1;
+                const u32x4 bw = {pool[w4[0]], pool[w4[1]], pool[w4[2]], pool[w4[3]]};
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[st], __builtin_bit_cast(bf16x8, bw),
+                                                              acc, 0, 0, 0);
+            }
+            if (j < 9 && g < 2) {
+                float y[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) y[r] = fmaxf(acc[r] + bc1[r], 0.f);
+                const uint32_t m = zin && (r1 > 0 || Y0 > 0) ? 0xffffffffu : 0u;
+                *reinterpret_cast<u32x2 *>(&l1[(lsb + r1 * 2 * kC12Half) * 8 + 4 * g]) =
+                    (u32x2){bf16x2_rne(y[0], y[1]) & m, bf16x2_rne(y[2], y[3]) & m};
+            }
+        }
+    };
+
+    // At X0 = 0 the column x = -1 of every first-layer slice is padding and the word before
+    // every pooled row is zero: both written once, never again.
+    if (X0 == 0) {
+        if (tid < 27)
+            *reinterpret_cast<u32x4 *>(&l1[((tid % 3) * kC12L1 + (tid / 3) * 2 * kC12Half) * 8]) =
+                (u32x4){0u, 0u, 0u, 0u};
+        else if (tid < 27 + 5 * kC12Rows)
+            *reinterpret_cast<u32x4 *>(&pool[(tid - 27) * kPlRow]) = (u32x4){0u, 0u, 0u, 0u};
+    }
+    // Prologue: the first-layer slice 2 oz0 - 1 from pooled slices 4 oz0 - 3 .. - 1 (zero
+    // below the volume), its items computed here.
+    {
+        const int pzf = 4 * oz0 - 3, n3 = 3 * kC12Main + (X0 > 0 ? 3 * kC12Rows : 0);
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int it = tid + 256 * k;
+            if (it < n3) {
+                int s, r, p;
+                bool halo;
+                c12_item(it, 3, s, r, p, halo);
+                const int pz = pzf + s, py = 4 * Y0 - 3 + r;
+                uint32_t *d = pool + ((pz + 5) % 5) * kC12Rows * kPlRow + r * kPlRow;
+                u32x4 x = {0u, 0u, 0u, 0u};
+                if (pz >= 0 && py >= 0 && py < PY) {
+                    const uint8_t *row = Cb + pz * slice + (int64_t)py * PX;
+                    if (!halo) x = *reinterpret_cast<const u32x4 *>(row + 16 * p);
+                    else x.x = *reinterpret_cast<const uint32_t *>(row - 4);
+                }
+                if (!halo) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) words(x[e], d + 4 + 16 * p + 4 * e);
+                } else {
+                    words(x.x, d);
+                }
+            }
+        }
+    }
+    load4(4 * oz0);
+    __syncthreads();
+    l1_slice(2 * oz0 - 1, 0);
+    __syncthreads();
+    const int64_t yrow = (int64_t)OH2 * OW2;
+    for (int oz = oz0; oz < oz0 + zc; ++oz) {
+        store4(4 * oz);
+        if (oz + 1 < oz0 + zc) load4(4 * oz + 4);   // in flight during the products
+        __syncthreads();
+        l1_slice(2 * oz, 0);
+        l1_slice(2 * oz + 1, 1);
+        __syncthreads();
+        // Second layer: output row Y0 + wave, x X0 + j, channels 4 g .. + 3.
+        int lb[3];
+#pragma unroll
+        for (int kd = 0; kd < 3; ++kd) lb[kd] = ((2 * oz - 1 + kd + 3) % 3) * kC12L1;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int st = 0; st < 7; ++st) {
+            const int vox = (kd2[st] == 0 ? lb[0] : kd2[st] == 1 ? lb[1] : lb[2]) + vo2[st];
+            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&l1[vox * 8]);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[st], bv, acc, 0, 0, 0);
+        }
+        float y[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) y[r] = fmaxf(acc[r] + bc2[r], 0.f);
+        const int64_t o = (((int64_t)b * OD2 + oz) * yrow + (int64_t)(Y0 + wave) * OW2 + X0 + j) * 16;
+        *reinterpret_cast<u32x2 *>(&Y[o + 4 * g]) = (u32x2){bf16x2_rne(y[0], y[1]), bf16x2_rne(y[2], y[3])};
     }
 }
 
@@ -1876,6 +2159,36 @@ int nn_pool_conv_counts_bf16(const uint8_t *counts, int B, int nx, int ny, int n
                        mask < 0 ? 2 : 1, Co, npb, static_cast<const uint16_t *>(Wt), bias, relu,
                        Y);
     return launched("nn_pool_conv_counts_bf16");
+}
+
+int nn_counts_conv12_bf16(const uint8_t *counts, int B, int nx, int ny, int nz, int mask,
+                          const void *Wt1, const float *b1, const void *Wtm2, const float *b2,
+                          void *Y, void *stream)
+{
+    if (!counts || !Wt1 || !Wtm2 || !Y || B <= 0 || nx <= 0 || ny <= 0 || nz <= 0 || nx % 128 ||
+        ny % 32 || nz % 16 || mask < -1 || mask > 1 || (uintptr_t)counts % 16 ||
+        (uintptr_t)Wtm2 % 16 || (uintptr_t)Y % 8 || (int64_t)nx * ny * nz >= ((int64_t)1 << 31))
+        return tdb_set_error(DB_EINVAL, "nn_counts_conv12_bf16: bad arguments");
+    const int OD2 = nz / 8;
+    const int64_t cols = (int64_t)B * (nx / 128) * (ny / 32);   // 4 x 16 output columns
+    // Output slices per block: all of them, halved (each chunk recomputes one first-layer
+    // slice) while fewer than 2,048 blocks would fill the chip.
+    int zc = OD2;
+    while (zc % 2 == 0 && zc > 4 && cols * (OD2 / zc) < 2048) zc /= 2;
+    const int64_t units = cols * (OD2 / zc);
+    if (units >= ((int64_t)1 << 31))
+        return tdb_set_error(DB_EINVAL, "nn_counts_conv12_bf16: too large");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const auto *w1 = static_cast<const uint16_t *>(Wt1);
+    const auto *w2 = static_cast<const uint16_t *>(Wtm2);
+    auto *y = static_cast<uint16_t *>(Y);
+    if (mask < 0)
+        hipLaunchKernelGGL(counts_conv12_kernel<2>, dim3((unsigned)units), dim3(256), 0, s, counts,
+                           nx, ny, nz, mask, zc, (int)units, w1, b1, w2, b2, y);
+    else
+        hipLaunchKernelGGL(counts_conv12_kernel<1>, dim3((unsigned)units), dim3(256), 0, s, counts,
+                           nx, ny, nz, mask, zc, (int)units, w1, b1, w2, b2, y);
+    return launched("nn_counts_conv12_bf16");
 }
 
 int nn_conv3d_weights_tapmajor(const void *Wt, int Co, int Ci, void *out, void *stream)

@@ -61,6 +61,8 @@ _SIGS = {
                                         _vp, _i32, _vp, _vp]),
     "nn_pool_conv_counts_bf16": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _i32,
                                         _vp, _vp]),
+    "nn_counts_conv12_bf16": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
+                                     _vp]),
     "nn_conv3d_weights_tapmajor": (_i32, [_vp, _i32, _i32, _vp, _vp]),
     "nn_linear_fwd_split": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _sz,
                                    _vp]),
@@ -231,6 +233,28 @@ def pool_conv_counts_bf16(counts: torch.Tensor, w_bf16: torch.Tensor, bias: torc
     _check(LIB.nn_pool_conv_counts_bf16(counts.data_ptr(), B, nx, ny, nz,
                                         -1 if mask is None else mask, Co, w_bf16.data_ptr(),
                                         _p(bias), int(relu), y.data_ptr(), _s()))
+    return y
+
+
+def counts_conv12_bf16(counts: torch.Tensor, w1_bf16: torch.Tensor, b1: torch.Tensor | None,
+                       w2_tm: torch.Tensor, b2: torch.Tensor | None,
+                       mask: int | None = None) -> torch.Tensor:
+    """The encoder's first two layers (8 then 16 channels, ReLU) from pooled counts uint8
+    [B][nz/2][ny/2][nx/2] in one kernel: conv3d_bf16(pool_conv_counts_bf16(...)) bit for bit,
+    bfloat16 channels-last [B][nz/8][ny/8][nx/8][16]."""
+    counts = _c(counts)
+    B, pz, py, px = counts.shape
+    nz, ny, nx = 2 * pz, 2 * py, 2 * px
+    assert counts.dtype == torch.uint8
+    assert w1_bf16.dtype == torch.bfloat16 and w1_bf16.shape[:2] == (8, 2 if mask is None else 1)
+    assert w2_tm.dtype == torch.bfloat16 and tuple(w2_tm.shape) == (16, 28, 8)
+    w1_bf16, w2_tm = _c(w1_bf16), _c(w2_tm)
+    b1 = None if b1 is None else _c(b1.detach())
+    b2 = None if b2 is None else _c(b2.detach())
+    y = torch.empty((B, nz // 8, ny // 8, nx // 8, 16), dtype=torch.bfloat16, device=counts.device)
+    _check(LIB.nn_counts_conv12_bf16(counts.data_ptr(), B, nx, ny, nz, -1 if mask is None else mask,
+                                     w1_bf16.data_ptr(), _p(b1), w2_tm.data_ptr(), _p(b2),
+                                     y.data_ptr(), _s()))
     return y
 
 
@@ -648,11 +672,11 @@ class AutoEncoder:
             self._tm_version = self.work_version
         return self.work_tm
 
-    def encode_after_first_bf16(self, h: torch.Tensor) -> torch.Tensor:
-        """The later convolutions on the BF16 matrix cores, then the head (float)."""
+    def encode_after_first_bf16(self, h: torch.Tensor, first: int = 1) -> torch.Tensor:
+        """The convolutions from layer `first` on (BF16 matrix cores), then the head (float)."""
         with torch.no_grad():
             tm = self._tapmajor()
-            for i in range(1, 4):
+            for i in range(first, 4):
                 w, b, wc = self._w(f"enc{i}")
                 h = conv3d_bf16(h, tm[f"enc{i}"], b, True, out_f32=(i == 3))
             w, b, wc = self._w("enc_fc")
@@ -666,10 +690,15 @@ class AutoEncoder:
         return self.encode_after_first_bf16(self.first_layer_labels_bf16(labels, mask))
 
     def encode_counts_bf16(self, counts: torch.Tensor, mask: int | None = None) -> torch.Tensor:
-        """encode_labels_bf16 from pooled counts [B][nz/2][ny/2][nx/2], bit for bit."""
+        """encode_labels_bf16 from pooled counts [B][nz/2][ny/2][nx/2], bit for bit (the first
+        two layers in one kernel)."""
         pz, py, px = counts.shape[-3:]
         assert self.bf16_inference_ok((2 * px, 2 * py, 2 * pz))
-        return self.encode_after_first_bf16(self.first_layer_counts_bf16(counts, mask))
+        with torch.no_grad():
+            _, b1, wc1 = self._w("enc0")
+            _, b2, _ = self._w("enc1")
+            h = counts_conv12_bf16(counts, wc1, b1, self._tapmajor()["enc1"], b2, mask)
+        return self.encode_after_first_bf16(h, first=2)
 
     def encode_planes_bf16(self, planes: torch.Tensor, dims, idx: torch.Tensor | None = None,
                            mask: int | None = None) -> torch.Tensor:

@@ -255,3 +255,51 @@ def test_pack_pool_rejects_odd_grids_and_bad_pointers():
     buf = torch.empty(2 * 2 * 2 * 16 + 1, dtype=torch.uint8, device="cuda")
     with pytest.raises(DbError, match="8-byte aligned"):
         db2.rerank_pack_pool(lab2, db2.rerank_workspace(2), buf[1:].view(2, 2, 2, 16))
+
+
+@pytest.mark.parametrize("dims,B", [
+    ((128, 128, 128), 3),     # the workload's grid; chunks of 4 output slices per block
+    ((256, 64, 32), 2),       # two x tiles: the first layer's column x = 2 X0 - 1 computed
+    ((128, 32, 48), 1),       # one y tile, three output slices in one chunk
+    ((128, 96, 16), 700),     # every slice per block, three y tiles, units % 8 != 0
+    ((128, 96, 16), 704),     # the same with the XCD-contiguous unit order
+])
+def test_first_two_layers_in_one_kernel(dims, B):
+    """nn_counts_conv12_bf16 equals the first layer from counts followed by the second BF16
+    convolution (two kernels, the activations through memory) bit for bit, for both masks and
+    each one alone, with and without biases; counts in 0..8 per mask, a zero region (ReLU of
+    the bias alone) and a full region."""
+    need_gpu()
+    from paper_2205_04550_amd import nn
+    nx, ny, nz = dims
+    rng = np.random.default_rng(nx + ny + nz + B)
+    f = rng.integers(0, 9, size=(B, nz // 2, ny // 2, nx // 2), dtype=np.uint8)
+    t = np.minimum(f, rng.integers(0, 9, size=f.shape, dtype=np.uint8))
+    f[0, :, : ny // 8] = 0
+    t[0, :, : ny // 8] = 0
+    f[-1, : nz // 4, :, : nx // 8] = 8
+    counts = torch.from_numpy(f | (t << 4)).cuda()
+    g = torch.Generator().manual_seed(B)
+    for mask, bias in ((None, True), (None, False), (0, True), (1, True)):
+        ci = 2 if mask is None else 1
+        w1 = (torch.randn(8, ci, 3, 3, 3, generator=g) * 0.3).to(torch.bfloat16).cuda()
+        w2 = (torch.randn(16, 8, 3, 3, 3, generator=g) * 0.2).to(torch.bfloat16).cuda()
+        b1 = torch.randn(8, generator=g).cuda() * 0.1 if bias else None
+        b2 = torch.randn(16, generator=g).cuda() * 0.1 if bias else None
+        w2tm = nn.conv_weights_tapmajor(w2)
+        want = nn.conv3d_bf16(nn.pool_conv_counts_bf16(counts, w1, b1, True, mask), w2tm, b2, True)
+        got = nn.counts_conv12_bf16(counts, w1, b1, w2tm, b2, mask)
+        assert got.shape == want.shape
+        assert torch.equal(got.view(torch.int16), want.view(torch.int16)), (mask, bias)
+        assert float((want != 0).double().mean()) > 0.05
+
+
+def test_first_two_layers_reject_bad_grids():
+    need_gpu()
+    from paper_2205_04550_amd import nn
+    w1 = torch.zeros(8, 2, 3, 3, 3, dtype=torch.bfloat16, device="cuda")
+    w2tm = torch.zeros(16, 28, 8, dtype=torch.bfloat16, device="cuda")
+    for pz, py, px in ((8, 16, 32), (8, 8, 64), (4, 16, 64)):   # nx, ny or nz not covered
+        c = torch.zeros(1, pz, py, px, dtype=torch.uint8, device="cuda")
+        with pytest.raises(RuntimeError):
+            nn.counts_conv12_bf16(c, w1, None, w2tm, None)
