@@ -562,12 +562,13 @@ def _plane_rows(eb, zr, q, gen, rb, lines):
     return (torch.where(ok, n, torch.zeros_like(n))).sum(dim=-1)
 
 
-def rerank_bytes(db, lab_d, cand, gen, lines: bool = False) -> float:
+def rerank_bytes(db, lab_d, cand, gen, lines: bool = False, scored=None) -> float:
     """Database bytes the candidate-scoring kernel reads: per (query, candidate) and plane, the
     rows of the slices inside both row boxes of that plane (the boxes of both masks for FLAIR,
     the T1Gd boxes for T1Gd) that lie in the candidate's y-range of that plane in the slice
-    (measurement bookkeeping). lines=True counts the 128-byte cache lines those rows touch
-    instead (a slice's run of rows starts and ends inside a line)."""
+    (measurement bookkeeping), over the pairs of `scored` (bool [nq][nc]; None: all).
+    lines=True counts the 128-byte cache lines those rows touch instead (a slice's run of rows
+    starts and ends inside a line)."""
     import torch
     rb = gen.nx // 32 * 4                                          # bytes per row and plane
     c = cand.to(torch.int64)
@@ -579,8 +580,69 @@ def rerank_bytes(db, lab_d, cand, gen, lines: bool = False) -> float:
             eb = boxes[c[r0:r0 + 128]].to(torch.int64)            # [128][nc][4]
             zr = db.zranges[c[r0:r0 + 128]][..., p].to(torch.int64)   # [128][nc][nz]
             qq = tuple(t[r0:r0 + 128] for t in q)
-            total += float(_plane_rows(eb, zr, qq, gen, rb, lines).sum())
+            rows = _plane_rows(eb, zr, qq, gen, rb, lines)
+            if scored is not None:
+                rows = rows * scored[r0:r0 + 128].to(rows.dtype)
+            total += float(rows.sum())
     return total * (128 if lines else rb)
+
+
+def bound_scored(db, lab_d, cand, k, gen):
+    """The candidates the bound-ordered rerank scores, by its rule on the host (measurement
+    bookkeeping): every candidate's bound (the score formula at the sums over 16^3 blocks of
+    the smaller of the two sides' counts), the first n1 = max(16, k) rounded to 16 in (bound
+    desc, slot asc) order, then those whose bound reaches the k-th best exact score of the
+    first n1. Returns (scored bool [nq][nc], bytes of the bound pass: the candidates' block
+    counts and the queries' rows inside their row boxes)."""
+    import torch
+    nq, nc = cand.shape
+    nbx, nby, nbz, nbp = db.block_dims()
+    n1 = (max(k, 16) + 15) // 16 * 16
+    if nbp == 0 or k <= 0 or n1 > 64 or nc <= n1:
+        return torch.ones((nq, nc), dtype=torch.bool, device=cand.device), 0.0
+    ws = db.rerank_workspace(nq)
+    db.rerank_pack(lab_d, ws)
+    db.set_rerank_bound(False)
+    fi, fs, _ = db.rerank_packed(ws, cand, nc)                     # every candidate's score
+    db.set_rerank_bound(True)
+    c = cand.to(torch.int64)
+    _, perm = torch.sort(c, dim=1)
+    fsort, fperm = torch.sort(fi.to(torch.int64), dim=1)
+    sc = torch.empty_like(fs).scatter_(1, perm, fs.gather(1, fperm))   # exact score per slot
+    nz, ny, nx = gen.nz, gen.ny, gen.nx
+    pad = (0, -nx % 16, 0, -ny % 16, 0, -nz % 16)
+    ub = torch.empty((nq, nc), dtype=torch.float64, device=cand.device)
+    pc = db.popcounts.to(torch.int64)
+
+    def dice(i, a, b):
+        den = a + b
+        return torch.where(den == 0, torch.ones_like(i, dtype=torch.float64),
+                           (2 * i).to(torch.float64) / den.clamp(min=1).to(torch.float64))
+
+    for r0 in range(0, nq, 64):
+        lab = lab_d[r0:r0 + 64]
+        qb = []
+        for bit in (1, 2):
+            m = torch.nn.functional.pad(((lab & bit) != 0).to(torch.int32), pad)
+            m = m.reshape(m.shape[0], nbz, 16, nby, 16, nbx, 16).sum(dim=(2, 4, 6))
+            qb.append(torch.nn.functional.pad(m.reshape(m.shape[0], -1), (0, nbp - nbx * nby * nbz)))
+        qb = torch.stack(qb, dim=1)                                 # [b][2][nbp]
+        a = qb.sum(-1).to(torch.int64)                              # query popcounts
+        bc = db.block_counts[c[r0:r0 + 64]].to(torch.int32) & 0xffff   # [b][nc][2][nbp]
+        u = torch.minimum(bc, qb[:, None]).sum(-1).to(torch.int64)  # [b][nc][2]
+        b = pc[c[r0:r0 + 64]]
+        ub[r0:r0 + 64] = dice(u[..., 1], a[:, None, 1], b[..., 1]) + dice(u[..., 0], a[:, None, 0],
+                                                                        b[..., 0])
+    order = torch.sort(-ub, dim=1, stable=True)[1]
+    ubs = ub.gather(1, order)
+    tau = sc.gather(1, order[:, :n1]).topk(k, dim=1)[0][:, -1:]
+    pos = torch.arange(nc, device=cand.device)[None] < n1
+    keep = pos | (ubs >= tau)
+    scored = torch.zeros_like(keep).scatter_(1, order, keep)
+    qz0, qz1, qy0, qy1 = _query_boxes(lab_d, gen, 3)
+    qrows = ((qz1 - qz0).clamp(min=0) * (qy1 - qy0).clamp(min=0)).sum()
+    bound_bytes = nq * nc * 2 * nbp * 2 + float(qrows) * 2 * (gen.nx // 8)
+    return scored, bound_bytes
 
 
 def encoder_forward_flop(model, nq: int) -> float:
@@ -648,8 +710,9 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
     exact_ms_per_query = (time.perf_counter() - t0) * 1e3 / nq
     log(f"exact scan: {exact_ms_per_query:.3f} ms per query")
 
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
     stage = np.zeros(3)
+    pack_ms = 0.0
 
     # One read of the query labels: the rerank's packing also writes their pooled counts,
     # which the encoder's first layer reads instead of the labels.
@@ -664,6 +727,8 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
         if timed:
             ev[0].record()
         db.rerank_pack_pool(lab_d, ws_rr, pooled)
+        if timed:
+            ev[4].record()
         ql = model.encode_counts_bf16(pooled)
         Q = B.Latents(ql, B.EMB_BF16)
         if timed:
@@ -686,11 +751,35 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
         (idx, score, counts), ci = step(True)
         torch.cuda.synchronize()
         stage += [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
+        pack_ms += ev[0].elapsed_time(ev[4])
     t1 = time.perf_counter()
     rr_ms, rr_launches = db.profile_read()
     db.profile(False)
     rr_avg = rr_ms / max(1, rr_launches)
-    rr_bytes = rerank_bytes(db, lab_d, ci, gen)
+    scored, bound_bytes = bound_scored(db, lab_d, ci, k, gen)
+    rr_bytes = rerank_bytes(db, lab_d, ci, gen, scored=scored) + bound_bytes
+    n_scored = float(scored.double().sum(1).mean())
+    rr_roof = {"bound": "hbm", "achieved": rr_bytes / (rr_avg * 1e-3) / 1e9,
+               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": rr_bytes / (rr_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+               "kernel": "rerank_bound_kernel + rerank_score_kernel (two rounds)",
+               "kernel_avg_ms": rr_avg, "algorithmic_bytes_per_launch": rr_bytes,
+               "candidates_scored_per_query": n_scored,
+               "note": "the rerank's scoring between HIP events; bytes = every candidate's "
+                       "16^3-block counts and the query's rows inside its row box (the bound), "
+                       "then for the candidates scored: database rows of the slices inside "
+                       "(query row box n candidate row box) for FLAIR, inside (query T1Gd row "
+                       "box n candidate T1Gd row box) for T1Gd, each within the candidate's "
+                       "y-range of that plane in the slice"}
+    pack_ms /= args.steps
+    pack_bytes = float(gen.nvox + 2 * gen.nvox // 8 + gen.nvox // 8) * nq
+    pack_roof = {"bound": "hbm", "achieved": pack_bytes / (pack_ms * 1e-3) / 1e9,
+                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": pack_bytes / (pack_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                 "kernel": "pack_pool_query_kernel + sum_parts_kernel", "kernel_avg_ms": pack_ms,
+                 "algorithmic_bytes_per_launch": pack_bytes,
+                 "note": "the query packing between HIP events; bytes = the labels read once, "
+                         "the packed masks and the pooled counts written"}
     ms = (t1 - t0) * 1e3 / args.steps
     stage /= args.steps
     got = idx.cpu().numpy()
@@ -714,7 +803,8 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
     log(f"{ms:.2f} ms per {nq} queries ({nq / (ms * 1e-3):.0f} q/s); stages "
         + ", ".join(f"{a} {b:.3f} ms" for a, b in zip(names, stage))
         + f"; recall@10 {recall10:.3f}; {top_n}; speed-up vs exact "
-          f"{exact_ms_per_query * nq / ms:.0f}x")
+          f"{exact_ms_per_query * nq / ms:.0f}x; rerank scored {n_scored:.1f} of {n_cand} "
+          f"candidates per query (query packing {pack_ms:.3f} ms)")
     out = {
         "metric": "queries/sec at recall@10", "value": nq / (ms * 1e-3), "unit": "queries/s",
         "ms_per_step": ms, "steps": args.steps, "warmup": args.warmup, "dtype": "bf16",
@@ -727,15 +817,9 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
         "exact_ms_per_query": exact_ms_per_query,
         "stages_ms": dict(zip(names, stage.tolist())),
         "dominant_stage": names[dom],
-        "roofline": {"bound": "hbm", "achieved": rr_bytes / (rr_avg * 1e-3) / 1e9,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": rr_bytes / (rr_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "rerank_score_kernel", "kernel_avg_ms": rr_avg,
-                     "algorithmic_bytes_per_launch": rr_bytes,
-                     "note": "the longest single launch of the step; bytes = database rows of "
-                             "the slices inside (query row box n candidate row box) for FLAIR, "
-                             "inside (query T1Gd row box n candidate T1Gd row box) for T1Gd, "
-                             "each within the candidate's y-range of that plane in the slice"},
+        "roofline": pack_roof if pack_ms >= rr_avg else rr_roof,
+        "rerank_roofline" if pack_ms >= rr_avg else "pack_roofline":
+            rr_roof if pack_ms >= rr_avg else pack_roof,
         "encode_stage_roofline": {
             "bound": "hbm", "achieved": enc_bytes / (stage[0] * 1e-3) / 1e9,
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -1228,12 +1312,16 @@ def bench_sparse(args, db, gen, n, build_s) -> int:
         got = o[0].cpu().numpy()
         topn = {f"top{t}": float(np.mean([best[q] in got[q, :t] for q in range(nqc)]))
                 for t in (1, 5, 15)}
-        rr_alg = rerank_bytes(db, held_d, o[3], gen)
-        rr_lines = rerank_bytes(db, held_d, o[3], gen, lines=True)
+        scored, bound_b = bound_scored(db, held_d, o[3], ks, gen)
+        rr_alg = rerank_bytes(db, held_d, o[3], gen, scored=scored) + bound_b
+        rr_lines = rerank_bytes(db, held_d, o[3], gen, lines=True, scored=scored) + bound_b
         com[f"n_cand_{n_cand}"] = {"queries_per_s": nqc / el_c, "ms_per_query": el_c * 1e3 / nqc,
                                    **topn, "rerank_score_ms": rr_ms / max(1, rr_n),
                                    "rerank_algorithmic_bytes": rr_alg,
-                                   "rerank_line_bytes": rr_lines}
+                                   "rerank_line_bytes": rr_lines,
+                                   "candidates_scored_per_query":
+                                       float(scored.double().sum(1).mean()),
+                                   "bound_pass_bytes": bound_b}
         log(f"COM prefilter {n_cand}: {nqc / el_c:.0f} q/s, Top-1/5/15 {topn['top1']:.3f} / "
             f"{topn['top5']:.3f} / {topn['top15']:.3f}")
         del wsc

@@ -87,7 +87,13 @@ enum {
  *             covers the x-rows holding a FLAIR bit and element 1 those
  *             holding a T1Gd bit, as y0 | y1 << 16 with the rows in
  *             [y0, y1) (0 for a slice without such a row). The rerank and
- *             the row-box scan read a plane's row (z, y) only inside it.
+ *             the row-box scan read a plane's row (z, y) only inside it;
+ *   bcnt:     uint16 [capacity][2][nbp], the set voxels of each mask in each
+ *             16 x 16 x 16 block of the grid: block (bz, by, bx) at
+ *             (bz nby + by) nbx + bx with nbx = nx / 16, nby = ceil(ny / 16),
+ *             nbz = ceil(nz / 16), nbp = that count rounded up to a multiple
+ *             of 8 (entries past it zero); absent (0 bytes) when the grid
+ *             has more than 2,048 blocks. The rerank bounds candidates by it.
  * Returns 0 if the dimensions are invalid. */
 size_t db_storage_bytes(int nx, int ny, int nz, int64_t capacity);
 
@@ -166,6 +172,12 @@ int db_query_sparse(const db_t *db, const uint8_t *q_labels, int k, int32_t *idx
 int db_query_batch(const db_t *db, int nq, const uint8_t *q_labels, const db_roi_t *rois, int k,
                    int32_t *idx, double *score, db_counts_t *counts, void *ws, size_t ws_bytes,
                    void *stream);
+
+/* on = 0: the rerank (db_rerank, db_rerank_packed, db_query_embed,
+ * db_query_com) scores every candidate; on != 0 (the default): in bound
+ * order, leaving out those that cannot reach the top k (db_rerank). Results
+ * are the same either way. DB_EINVAL on an invalid handle. */
+int db_set_rerank_bound(db_t *db, int on);
 
 /* Launch shape of db_query_batch: z-planes per LDS slab (0 = as many as fit;
  * -1 = no LDS slabs: the kernel that reads the database through L2), block
@@ -287,7 +299,14 @@ int emb_knn(int fmt, int M, int N, int dim, const void *q_codes, const float *q_
  * nc <= DB_KMAX, k <= nc. Candidates must be distinct within a row. Each
  * overlap is counted over the x-rows inside both sides' boxes of that mask
  * (the FLAIR overlap inside both row boxes, the T1Gd one inside both T1Gd
- * boxes): every other row is zero on one side. */
+ * boxes): every other row is zero on one side. With the block counts kept
+ * (bcnt above), k <= 64 and nc > n1 = max(16, k) rounded up to 16, the
+ * candidates are scored in decreasing order of a bound on their score (the
+ * score formula at the sums over 16^3 blocks of the smaller of the two
+ * sides' counts, which no overlap exceeds): the first n1, then only those
+ * whose bound reaches the k-th best of those n1 scores. Every candidate left
+ * out scores below that, so the top k are the same, bit for bit, as when
+ * scoring them all (db_set_rerank_bound). */
 size_t db_rerank_workspace_bytes(const db_t *db, int nq);
 int db_rerank(const db_t *db, int nq, const uint8_t *q_labels, const int32_t *cand, int nc, int k,
               int32_t *idx, double *score, db_counts_t *counts, void *ws, size_t ws_bytes,

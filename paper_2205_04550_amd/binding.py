@@ -27,7 +27,7 @@ SYMBOLS = ("db_storage_bytes", "db_build", "db_append", "db_size", "db_query_wor
            "emb_hash_thresholds", "emb_binarize", "emb_distances_l2sum", "db_rerank_pack",
            "db_rerank_packed", "emb_groups_workspace_bytes", "emb_distances_groups",
            "emb_topk_groups", "db_query_noalloc", "emb_knn_workspace_bytes", "emb_knn",
-           "db_rerank_pack_pool")
+           "db_rerank_pack_pool", "db_set_rerank_bound")
 EMB_BF16, EMB_FP8, EMB_BIN = 0, 1, 2
 
 
@@ -66,6 +66,7 @@ def _load():
         "db_last_error": (ctypes.c_char_p, []),
         "db_profile": (i32, [vp, i32]),
         "db_tune_batch": (i32, [vp, i32, i32, i32, i32]),
+        "db_set_rerank_bound": (i32, [vp, i32]),
         "db_append_resampled": (i32, [vp, vp, i64, i64, vp]),
         "labels_resample": (i32, [i32, vp, i32, i32, i32, vp, i32, i32, i32, vp]),
         "emb_quantize": (i32, [i64, i32, vp, i32, vp, vp, vp, vp]),
@@ -165,7 +166,15 @@ class TumorDB:
         order = mom + up(self.capacity * 32)
         tbox = order + up(self.capacity * 4)
         zrange = tbox + up(self.capacity * 16)
-        return pc, box, mom, order, tbox, zrange
+        bcnt = zrange + up(self.capacity * self.dims[2] * 8)
+        return pc, box, mom, order, tbox, zrange, bcnt
+
+    def block_dims(self):
+        """(nbx, nby, nbz, nbp) of the per-entry 16^3-block counts (nbp = 0: none kept)."""
+        nx, ny, nz = self.dims
+        nbx, nby, nbz = nx // 16, (ny + 15) // 16, (nz + 15) // 16
+        nb = nbx * nby * nbz
+        return nbx, nby, nbz, ((nb + 7) // 8 * 8 if nb <= 2048 else 0)
 
     @property
     def popcounts(self) -> torch.Tensor:
@@ -192,6 +201,15 @@ class TumorDB:
         off = self._offsets()[5]
         return (self.storage[off:off + self.capacity * self.dims[2] * 8].view(torch.int32)
                 .view(self.capacity, self.dims[2], 2))
+
+    @property
+    def block_counts(self) -> torch.Tensor:
+        """int16 view [capacity][2][nbp] of the set voxels per 16^3 block and mask (uint16
+        values; block (bz, by, bx) at (bz nby + by) nbx + bx)."""
+        nbp = self.block_dims()[3]
+        off = self._offsets()[6]
+        return (self.storage[off:off + self.capacity * 4 * nbp].view(torch.int16)
+                .view(self.capacity, 2, nbp))
 
     @property
     def tile_order(self) -> torch.Tensor:
@@ -412,6 +430,11 @@ class TumorDB:
         """Launch shape of query_batch (0 = defaults; slab_planes = -1 selects the kernel that
         reads the database through L2); results are the same for any shape."""
         _check(LIB.db_tune_batch(self._h, slab_planes, block_threads, tile_entries, query_chunk))
+
+    def set_rerank_bound(self, on: bool) -> None:
+        """Rerank in bound order, leaving out candidates that cannot reach the top k (the
+        default), or score every candidate; results are the same either way."""
+        _check(LIB.db_set_rerank_bound(self._h, 1 if on else 0))
 
     def profile(self, enable: bool) -> None:
         """Record HIP events around the dominant kernel of every later query call."""

@@ -326,6 +326,12 @@ static int build_tile_order(db_t *db, int tile)
     return DB_OK;
 }
 
+// Block counts of entry e (nullptr when the grid has too many blocks to keep them).
+static uint16_t *block_counts_at(const db_t *db, int64_t e)
+{
+    return db->bcnt ? db->bcnt + e * 2 * bound_blocks(db->g, nullptr, nullptr) : nullptr;
+}
+
 extern "C" {
 
 size_t db_storage_bytes(int nx, int ny, int nz, int64_t capacity)
@@ -333,10 +339,12 @@ size_t db_storage_bytes(int nx, int ny, int nz, int64_t capacity)
     Geometry g;
     if (!make_geometry(nx, ny, nz, &g) || capacity <= 0 || capacity > INT32_MAX)
         return 0;
+    const int nbp = bound_blocks(g, nullptr, nullptr);
     return align_up((size_t)capacity * 2 * g.Wp * 4, kAlign) +
            align_up((size_t)capacity * 2 * 4, kAlign) + align_up((size_t)capacity * 4 * 4, kAlign) +
            align_up((size_t)capacity * 4 * 8, kAlign) + align_up((size_t)capacity * 4, kAlign) +
-           align_up((size_t)capacity * 4 * 4, kAlign) + align_up((size_t)capacity * nz * 2 * 4, kAlign);
+           align_up((size_t)capacity * 4 * 4, kAlign) + align_up((size_t)capacity * nz * 2 * 4, kAlign) +
+           align_up((size_t)capacity * 2 * nbp * 2, kAlign);
 }
 
 int db_build(db_t **out, int nx, int ny, int nz, float t_lo, float t_hi, int64_t capacity,
@@ -388,6 +396,11 @@ int db_build(db_t **out, int nx, int ny, int nz, float t_lo, float t_hi, int64_t
     db->tbox = reinterpret_cast<int32_t *>(static_cast<char *>(storage) + o_tbox);
     const size_t o_zr = o_tbox + align_up((size_t)capacity * 4 * 4, kAlign);
     db->zrange = reinterpret_cast<uint32_t *>(static_cast<char *>(storage) + o_zr);
+    const size_t o_bc = o_zr + align_up((size_t)capacity * nz * 2 * 4, kAlign);
+    db->bcnt = bound_blocks(g, nullptr, nullptr)
+                   ? reinterpret_cast<uint16_t *>(static_cast<char *>(storage) + o_bc)
+                   : nullptr;
+    db->rerank_bound = 1;
     db->tile_order_n = 0;
     db->storage_bytes = storage_bytes;
     db->cus = cus;
@@ -422,6 +435,9 @@ int db_append(db_t *db, const float *conc, int64_t n, void *stream)
     if (e == hipSuccess)
         e = launch_meta(planes, n, db->g, db->box + db->count * 4, db->tbox + db->count * 4,
                         db->mom + db->count * 4, db->zrange + db->count * db->g.nz * 2, s);
+    if (e == hipSuccess)
+        e = launch_block_counts(db, planes, n, db->box + db->count * 4, block_counts_at(db, db->count),
+                                s);
     if (e != hipSuccess) return hip_fail(e, "db_append: launch");
     db->count += n;
     return DB_OK;
@@ -958,7 +974,7 @@ static hipError_t rerank_launches(const db_t *db, int nq, const uint32_t *qpack,
                                   db_counts_t *counts, void *ws, hipStream_t s)
 {
     hipError_t e = prof_mark(db, s);
-    if (e == hipSuccess) e = launch_rerank_score(db, nq, qpack, acnt, box, tbox, cand, nc, ws, s);
+    if (e == hipSuccess) e = launch_rerank_score(db, nq, qpack, acnt, box, tbox, cand, nc, k, ws, s);
     if (e == hipSuccess) e = prof_mark(db, s);
     if (e == hipSuccess) e = launch_rerank_rank(db, nq, acnt, nc, k, idx, score, counts, ws, s);
     return e;
@@ -1249,6 +1265,9 @@ int db_append_resampled(db_t *dst, const db_t *src, int64_t first, int64_t n, vo
         e = launch_meta(dst->planes + dst->count * 2 * (int64_t)dst->g.Wp, n, dst->g,
                         dst->box + dst->count * 4, dst->tbox + dst->count * 4,
                         dst->mom + dst->count * 4, dst->zrange + dst->count * dst->g.nz * 2, s);
+    if (e == hipSuccess)
+        e = launch_block_counts(dst, dst->planes + dst->count * 2 * (int64_t)dst->g.Wp, n,
+                                dst->box + dst->count * 4, block_counts_at(dst, dst->count), s);
     if (e != hipSuccess) return hip_fail(e, "db_append_resampled: launch");
     dst->count += n;
     return DB_OK;
@@ -1274,6 +1293,13 @@ int db_sync(const db_t *db, void *stream)
     hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "db_sync");
+    return DB_OK;
+}
+
+int db_set_rerank_bound(db_t *db, int on)
+{
+    if (!live(db)) return fail(DB_EINVAL, "db_set_rerank_bound: invalid handle");
+    db->rerank_bound = on ? 1 : 0;
     return DB_OK;
 }
 

@@ -500,6 +500,7 @@ __global__ void __launch_bounds__(kSelThreads) topk_min_kernel(const float *__re
 constexpr int kRerankMaxCand = 1024;
 
 constexpr int kRC = 4;                 // candidates per wave
+static_assert(kRC == 4, "the LDS staging of the per-slice ranges picks among four members");
 constexpr int kRerankPerBlock = 4 * kRC;   // candidates scored per block (4 waves)
 constexpr int kZStage = 128;           // z-slices of per-slice row ranges a wave stages in LDS
 
@@ -512,6 +513,10 @@ constexpr int kZStage = 128;           // z-slices of per-slice row ranges a wav
 // zero and adds nothing; the T1Gd plane has boxes of its own, smaller than those
 // of both masks), AND + popcount against each candidate's planes; the score and
 // overlaps go to ws (score bits [nq][nc], index [nq][nc], I [nq][nc][2]).
+// SPLIT = 4: a block scores kRC candidates (not 4 kRC), its four waves taking every fourth
+// pass over the rows and adding their overlaps in LDS: four times the waves per candidate, for
+// launches with few candidates per query.
+template <int SPLIT>
 __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__restrict__ planes,
                                                            const uint32_t *__restrict__ popcnt,
                                                            const int32_t *__restrict__ ebox,
@@ -527,7 +532,11 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
                                                            uint64_t *__restrict__ ws_s,
                                                            int32_t *__restrict__ ws_i,
                                                            uint32_t *__restrict__ ws_I, int nq,
-                                                           int nbq)
+                                                           int nbq,
+                                                           const int32_t *__restrict__ order,
+                                                           const int32_t *__restrict__ ents,
+                                                           const int32_t *__restrict__ qcount,
+                                                           int first, int count)
 {
     const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8;
     const int q = (slot / nbq) * 8 + xcd, qb = slot % nbq;
@@ -542,24 +551,40 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
     // the union of its members' boxes. A member reads its FLAIR rows inside (its row box n the
     // query's) and its T1Gd rows inside (its T1Gd box n the query's): outside either pair of
     // boxes one of the two masks is empty.
-    const int c0 = qb * kRerankPerBlock + wave * kRC;
-    if (c0 >= nc) return;   // a whole wave leaves; no block barrier below
+    // This wave's candidates: positions first + c0 .. + kRC - 1 of the query's list, count of
+    // them (qcount: the query's own count). With order, position i is slot order[i] and entry
+    // ents[i] (the candidates in bound order); else slot = position.
+    const int c0 = SPLIT == 1 ? qb * kRerankPerBlock + wave * kRC : qb * kRC;
+    const int64_t qo = (int64_t)q * nc;
+    const int cnt = qcount ? qcount[q] : count;
+    int cs[kRC];
+    int32_t ent[kRC];
+    bool act[kRC], any = false;
+#pragma unroll
+    for (int j = 0; j < kRC; ++j) {
+        const int i = first + c0 + j;
+        act[j] = c0 + j < cnt && i < nc;
+        const int ii = act[j] ? i : 0;
+        cs[j] = order ? order[qo + ii] : ii;
+        ent[j] = ents ? ents[qo + ii] : cand[qo + cs[j]];
+        any |= act[j];
+    }
+    if (!any) return;       // a whole wave leaves; no block barrier below
     const uint32_t *D0[kRC], *D1[kRC];
     int z0[kRC], z1[kRC], y0[kRC], y1[kRC], tz0[kRC], tz1[kRC], ty0[kRC], ty1[kRC];
     int uz0 = INT_MAX, uz1 = INT_MIN, uy0 = INT_MAX, uy1 = INT_MIN;
 #pragma unroll
     for (int j = 0; j < kRC; ++j) {
-        const int c = min(c0 + j, nc - 1);          // a repeated candidate is discarded
-        const int32_t e = cand[(int64_t)q * nc + c];
+        const int32_t e = ent[j];             // an inactive member sweeps no rows
         D0[j] = planes + (int64_t)e * 2 * Wp;
         D1[j] = D0[j] + Wp;
         const int32_t *eb = ebox + 4 * (int64_t)e, *etb = etbox + 4 * (int64_t)e;
-        z0[j] = max(eb[0], qz0);
-        z1[j] = min(eb[1], qz1);
+        z0[j] = act[j] ? max(eb[0], qz0) : 0;
+        z1[j] = act[j] ? min(eb[1], qz1) : 0;
         y0[j] = max(eb[2], qy0);
         y1[j] = min(eb[3], qy1);
-        tz0[j] = max(etb[0], tqz0);
-        tz1[j] = min(etb[1], tqz1);
+        tz0[j] = act[j] ? max(etb[0], tqz0) : 0;
+        tz1[j] = act[j] ? min(etb[1], tqz1) : 0;
         ty0[j] = max(etb[2], tqy0);
         ty1[j] = min(etb[3], tqy1);
         if (z1[j] > z0[j] && y1[j] > y0[j]) {
@@ -585,7 +610,7 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
         const int nzs = uz1 - uz0;
         for (int i = lane; i < kRC * nzs; i += 64) {
             const int j = i / nzs, zz = i - j * nzs;
-            const int32_t e = cand[(int64_t)q * nc + min(c0 + j, nc - 1)];
+            const int32_t e = j == 0 ? ent[0] : j == 1 ? ent[1] : j == 2 ? ent[2] : ent[3];
             s_zr[wave][j][zz] = *reinterpret_cast<const uint2 *>(zrange + ((int64_t)e * nz + uz0 + zz) * 2);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -606,7 +631,8 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
         // Rows of 128 voxels: one 16-byte load per plane; two rows per lane per pass, all
         // loads of the pass issued before any is used.
         constexpr int U = 2;
-        for (int r0 = lane; r0 < nr; r0 += 64 * U) {
+        const int rw = SPLIT == 1 ? 0 : wave;
+        for (int r0 = lane + 64 * U * rw; r0 < nr; r0 += 64 * U * SPLIT) {
             u32x4 qa[U], qb[U], da[U][kRC], db[U][kRC];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -641,7 +667,7 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
                 }
         }
     } else {
-        for (int r = lane; r < nr; r += 64) {
+        for (int r = lane + (SPLIT == 1 ? 0 : 64 * wave); r < nr; r += 64 * SPLIT) {
             const int zr = r / nyr;
             const int z = uz0 + zr, y = uy0 + r - zr * nyr;
             const int base = (z * ny + y) * nxw;
@@ -661,13 +687,30 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
             }
         }
     }
+    if constexpr (SPLIT > 1) {                // the four waves' overlaps, added in wave 0
+        __shared__ uint32_t s_red[4][kRC][2];
+#pragma unroll
+        for (int j = 0; j < kRC; ++j) {
+            const uint32_t a0 = wave_sum(i0[j]), a1 = wave_sum(i1[j]);
+            if (lane == 0) {
+                s_red[wave][j][0] = a0;
+                s_red[wave][j][1] = a1;
+            }
+        }
+        __syncthreads();
+        if (wave) return;
+#pragma unroll
+        for (int j = 0; j < kRC; ++j) {
+            i0[j] = lane == 0 ? s_red[0][j][0] + s_red[1][j][0] + s_red[2][j][0] + s_red[3][j][0] : 0u;
+            i1[j] = lane == 0 ? s_red[0][j][1] + s_red[1][j][1] + s_red[2][j][1] + s_red[3][j][1] : 0u;
+        }
+    }
 #pragma unroll
     for (int j = 0; j < kRC; ++j) {
         const uint32_t a0 = wave_sum(i0[j]), a1 = wave_sum(i1[j]);
-        const int c = c0 + j;
-        if (lane == 0 && c < nc) {
-            const int64_t o = (int64_t)q * nc + c;
-            const int32_t e = cand[o];
+        if (lane == 0 && act[j]) {
+            const int64_t o = qo + cs[j];
+            const int32_t e = ent[j];
             const double sc = dice(a1, A1, popcnt[2 * (int64_t)e + 1]) +
                               dice(a0, A0, popcnt[2 * (int64_t)e]);
             ws_s[o] = (uint64_t)__double_as_longlong(sc);
@@ -676,6 +719,241 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
             ws_I[2 * o + 1] = a1;
         }
     }
+}
+
+// ---- bound-ordered rerank ---------------------------------------------------------------------
+//
+// Per entry and mask, the set voxels of every 16 x 16 x 16 block of the grid (uint16
+// [2][nbp], blocks (bz, by, bx) at (bz nby + by) nbx + bx, the rest zero). For a query with
+// block counts a_b and a candidate with b_b, |A n B| <= sum over blocks of min(a_b, b_b), and
+// Dice is increasing in |A n B|: the candidate's score is at most the same formula at those
+// sums (in floating point too: the same operations on larger arguments). Scoring candidates
+// in decreasing bound and leaving out those whose bound is below the k-th best exact score
+// found gives the top k of scoring them all, bit for bit.
+
+// Set voxels per block of the rows inside [z0, z1) x [y0, y1) of the two planes at P, into
+// the LDS counts c[2][nbp] (zeroed before). With nxw % 4 == 0 an item is 16 bytes of a row
+// (eight 16-voxel blocks), four items per thread in flight.
+__device__ __forceinline__ void block_counts_rows(const uint32_t *__restrict__ P, int Wp, int nxw,
+                                                  int ny, int z0, int z1, int y0, int y1, int nbx,
+                                                  int nby, int nbp, uint32_t *c)
+{
+    const int nyr = y1 - y0;
+    if (z1 <= z0 || nyr <= 0) return;
+    const int rows = (z1 - z0) * nyr;
+    if (nxw % 4 == 0) {
+        const int nv = nxw / 4, items = rows * 2 * nv;
+        constexpr int B = 4;
+        for (int i0 = threadIdx.x; i0 < items; i0 += B * blockDim.x) {
+            u32x4 v[B];
+            int at[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u) {
+                const int it = i0 + u * blockDim.x;
+                v[u] = (u32x4){0u, 0u, 0u, 0u};
+                at[u] = 0;
+                if (it < items) {
+                    const int vi = it % nv, rem = it / nv, pl = rem & 1, r = rem >> 1;
+                    const int zr = r / nyr, z = z0 + zr, y = y0 + r - zr * nyr;
+                    v[u] = *reinterpret_cast<const u32x4 *>(
+                        P + (int64_t)pl * Wp + ((int64_t)z * ny + y) * nxw + 4 * vi);
+                    at[u] = pl * nbp + ((z >> 4) * nby + (y >> 4)) * nbx + 8 * vi;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t word = v[u][e];
+                    if (word) {
+                        const uint32_t lo = popc(word & 0xffffu), hi = popc(word >> 16);
+                        if (lo) atomicAdd(&c[at[u] + 2 * e], lo);
+                        if (hi) atomicAdd(&c[at[u] + 2 * e + 1], hi);
+                    }
+                }
+        }
+        return;
+    }
+    const int items = rows * 2 * nxw;
+    for (int it = threadIdx.x; it < items; it += blockDim.x) {
+        const int w = it % nxw, rem = it / nxw, pl = rem & 1, r = rem >> 1;
+        const int z = z0 + r / nyr, y = y0 + r % nyr;
+        const uint32_t word = P[(int64_t)pl * Wp + ((int64_t)z * ny + y) * nxw + w];
+        if (word) {
+            const int b = pl * nbp + ((z >> 4) * nby + (y >> 4)) * nbx + 2 * w;
+            const uint32_t lo = popc(word & 0xffffu), hi = popc(word >> 16);
+            if (lo) atomicAdd(&c[b], lo);
+            if (hi) atomicAdd(&c[b + 1], hi);
+        }
+    }
+}
+
+// grid n entries, 256 threads: the block counts of entries e0 + blockIdx.x from their planes,
+// inside their row boxes (zero outside).
+__global__ void __launch_bounds__(256) block_count_kernel(const uint32_t *__restrict__ planes,
+                                                          int Wp, int nxw, int ny,
+                                                          const int32_t *__restrict__ box,
+                                                          int nbx, int nby, int nbp,
+                                                          uint16_t *__restrict__ bcnt)
+{
+    __shared__ uint32_t c[2 * kBoundMaxBlocks];
+    const int64_t e = blockIdx.x;
+    for (int i = threadIdx.x; i < 2 * nbp; i += blockDim.x) c[i] = 0u;
+    __syncthreads();
+    const int32_t *b = box + 4 * e;
+    block_counts_rows(planes + e * 2 * Wp, Wp, nxw, ny, b[0], b[1], b[2], b[3], nbx, nby, nbp, c);
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * nbp; i += blockDim.x) bcnt[e * 2 * nbp + i] = (uint16_t)c[i];
+}
+
+// grid nq, 256 threads: the query's block counts (from its packed planes inside its row box)
+// into qbc [nq][2][nbp] (uint32).
+__global__ void __launch_bounds__(256) query_block_kernel(const uint32_t *__restrict__ qpack,
+                                                          int Wp, int nxw, int ny,
+                                                          const int32_t *__restrict__ box,
+                                                          int nbx, int nby, int nbp,
+                                                          uint32_t *__restrict__ qbc)
+{
+    __shared__ uint32_t c[2 * kBoundMaxBlocks];
+    const int q = blockIdx.x;
+    for (int i = threadIdx.x; i < 2 * nbp; i += blockDim.x) c[i] = 0u;
+    __syncthreads();
+    const int32_t *b = box + 4 * q;
+    block_counts_rows(qpack + (int64_t)q * 2 * Wp, Wp, nxw, ny, b[0], b[1], b[2], b[3], nbx, nby,
+                      nbp, c);
+    __syncthreads();
+    for (int i = threadIdx.x; i < 2 * nbp; i += blockDim.x) qbc[(int64_t)q * 2 * nbp + i] = c[i];
+}
+
+// One wave per (query, candidate), blocks of four: the candidate's bound into ub [nq][nc].
+// With nbx % 8 == 0 a 16-byte chunk of counts is eight blocks of one (bz, by) block row, and
+// only the block rows the query's row box meets are read (the query's counts are zero
+// elsewhere).
+__global__ void __launch_bounds__(256) rerank_ub_kernel(const uint16_t *__restrict__ bcnt,
+                                                        int nbx, int nby, int nbp,
+                                                        const uint32_t *__restrict__ popcnt,
+                                                        const uint32_t *__restrict__ qbc,
+                                                        const int32_t *__restrict__ box,
+                                                        const uint32_t *__restrict__ acnt,
+                                                        const int32_t *__restrict__ cand, int nc,
+                                                        int nq, double *__restrict__ ub)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int per = (nc + 3) / 4;
+    const int q = blockIdx.x / per, c = (blockIdx.x % per) * 4 + wave;
+    if (q >= nq || c >= nc) return;            // a whole wave leaves; no block barrier below
+    const int64_t qo = (int64_t)q * nc;
+    const int32_t e = cand[qo + c];
+    const int32_t *b = box + 4 * q;
+    const bool rows = nbx % 8 == 0;
+    const int bz0 = b[0] >> 4, bz1 = b[1] > b[0] ? (b[1] - 1) >> 4 : -1;
+    const int by0 = b[2] >> 4, by1 = b[3] > b[2] ? (b[3] - 1) >> 4 : -1;
+    const u32x4 *E = reinterpret_cast<const u32x4 *>(bcnt + (int64_t)e * 2 * nbp);
+    const uint32_t *Q = qbc + (int64_t)q * 2 * nbp;
+    const int nch = nbp / 8;                   // 16-byte chunks per plane
+    uint32_t u0 = 0u, u1 = 0u;
+    for (int ch = lane; ch < 2 * nch; ch += 64) {
+        const int pl = ch >= nch, b0 = 8 * (ch - pl * nch);
+        if (rows) {
+            const int br = b0 / nbx, bz = br / nby, by = br - bz * nby;
+            if (bz < bz0 || bz > bz1 || by < by0 || by > by1) continue;   // padding: bz >= nbz
+        }
+        const u32x4 v = E[ch];
+        const uint32_t *qq = Q + 8 * ch;
+        uint32_t m = 0u;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            m += min(v[t] & 0xffffu, qq[2 * t]) + min(v[t] >> 16, qq[2 * t + 1]);
+        if (pl) u1 += m;
+        else u0 += m;
+    }
+    u0 = wave_sum(u0);
+    u1 = wave_sum(u1);
+    if (lane == 0)
+        ub[qo + c] = dice(u1, acnt[2 * q + 1], popcnt[2 * (int64_t)e + 1]) +
+                     dice(u0, acnt[2 * q], popcnt[2 * (int64_t)e]);
+}
+
+// grid nq, 256 threads: the query's candidates sorted by (bound desc, slot asc) into order /
+// ubs [nq][nc]; every slot's score set to the smallest positive double's bits (below any
+// score a ranked candidate can have once it is left out) and its entry index.
+__global__ void __launch_bounds__(256) rerank_order_kernel(const double *__restrict__ ub,
+                                                           const int32_t *__restrict__ cand, int nc,
+                                                           int32_t *__restrict__ order,
+                                                           double *__restrict__ ubs,
+                                                           int32_t *__restrict__ ents,
+                                                           uint64_t *__restrict__ ws_s,
+                                                           int32_t *__restrict__ ws_i)
+{
+    __shared__ double sk[kRerankMaxCand];
+    __shared__ int32_t si[kRerankMaxCand];
+    const int64_t qo = (int64_t)blockIdx.x * nc;
+    int P = 1;
+    while (P < nc) P <<= 1;
+    for (int t = threadIdx.x; t < P; t += blockDim.x) {
+        sk[t] = t < nc ? ub[qo + t] : -1.0;
+        si[t] = t < nc ? t : INT_MAX;
+        if (t < nc) {
+            ws_s[qo + t] = 1ull;
+            ws_i[qo + t] = cand[qo + t];
+        }
+    }
+    for (int size = 2; size <= P; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < P / 2; t += blockDim.x) {
+                const int i = 2 * t - (t & (stride - 1));
+                const int j = i + stride;
+                const bool up = (i & size) == 0;
+                const double ki = sk[i], kj = sk[j];
+                const int32_t ii = si[i], ij = si[j];
+                const bool j_first = kj > ki || (kj == ki && ij < ii);
+                if (j_first == up) {
+                    sk[i] = kj;
+                    sk[j] = ki;
+                    si[i] = ij;
+                    si[j] = ii;
+                }
+            }
+        }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nc; t += blockDim.x) {
+        order[qo + t] = si[t];
+        ubs[qo + t] = sk[t];
+        ents[qo + t] = cand[qo + si[t]];
+    }
+}
+
+// One wave per query (grid ceil(nq / 4), 256 threads), after the first n1 positions in bound
+// order are scored: tau = the k-th best of their scores (k <= n1 <= 64), and qcount[q] = the
+// positions from n1 on whose bound reaches tau (a prefix: the bounds are sorted). Every other
+// candidate's score is at most its bound < tau, below the k best.
+__global__ void __launch_bounds__(256) rerank_gate_kernel(const uint64_t *__restrict__ ws_s,
+                                                          const int32_t *__restrict__ order,
+                                                          const double *__restrict__ ubs, int nc,
+                                                          int n1, int k, int nq,
+                                                          int32_t *__restrict__ qcount)
+{
+    const int lane = threadIdx.x & 63, q = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= nq) return;
+    const int64_t qo = (int64_t)q * nc;
+    const double v = lane < n1 ? __longlong_as_double((long long)ws_s[qo + order[qo + lane]])
+                               : -INFINITY;
+    int rank = 0;
+    for (int l = 0; l < n1; ++l) {
+        const double w = __shfl(v, l);
+        rank += (w > v || (w == v && l < lane)) ? 1 : 0;
+    }
+    const uint64_t hit = __ballot(lane < n1 && rank == k - 1);
+    const double tau = __shfl(v, (int)__builtin_ctzll(hit));
+    int n2 = 0;
+    for (int i0 = n1; i0 < nc; i0 += 64) {
+        const int i = i0 + lane;
+        const uint64_t in = __ballot(i < nc && ubs[qo + i] >= tau);
+        n2 += __builtin_popcountll(in);
+        if (in != __ballot(i < nc)) break;     // the prefix ended in this pass
+    }
+    if (lane == 0) qcount[q] = n2;
 }
 
 // grid nq, 256 threads: rank the query's nc scored candidates by (score desc,
@@ -1495,21 +1773,76 @@ hipError_t launch_topk_min(int M, int N, int k, const float *D, int32_t *idx, fl
     return hipGetLastError();
 }
 
-size_t rerank_ws_bytes(int nq) { return (size_t)nq * kRerankMaxCand * 20; }  // 8 + 4 + 2 * 4 bytes per candidate
+// Per candidate: score 8, entry 4, overlaps 2 x 4, bound order 4, sorted and unsorted bounds
+// 2 x 8, entry in bound order 4 bytes; per query a count 4 and its block counts 2 x 4 bytes
+// per block.
+size_t rerank_ws_bytes(int nq)
+{
+    return (size_t)nq * kRerankMaxCand * 44 + 512 + (size_t)nq * (4 + 2 * kBoundMaxBlocks * 4);
+}
 
 hipError_t launch_rerank_score(const db_t *db, int nq, const uint32_t *qpack, const uint32_t *acnt,
                                const int32_t *box, const int32_t *tbox, const int32_t *cand,
-                               int nc, void *ws, hipStream_t s)
+                               int nc, int k, void *ws, hipStream_t s)
 {
     const Geometry &g = db->g;
+    const size_t m = (size_t)nq * nc;
     uint64_t *ws_s = static_cast<uint64_t *>(ws);
-    int32_t *ws_i = reinterpret_cast<int32_t *>(ws_s + (size_t)nq * nc);
-    uint32_t *ws_I = reinterpret_cast<uint32_t *>(ws_i + (size_t)nq * nc);
-    const int nbq = (nc + kRerankPerBlock - 1) / kRerankPerBlock;
-    const int64_t blocks = (int64_t)nbq * 8 * ((nq + 7) / 8);
-    hipLaunchKernelGGL(rerank_score_kernel, dim3((unsigned)blocks), dim3(256), 0, s, db->planes,
-                       db->popcnt, db->box, db->tbox, db->zrange, g.nz, g.Wp, g.nxw, g.ny, qpack,
-                       acnt, box, tbox, cand, nc, ws_s, ws_i, ws_I, nq, nbq);
+    int32_t *ws_i = reinterpret_cast<int32_t *>(ws_s + m);
+    uint32_t *ws_I = reinterpret_cast<uint32_t *>(ws_i + m);
+    int32_t *order = reinterpret_cast<int32_t *>(ws_I + 2 * m);
+    double *ubs = reinterpret_cast<double *>(order + m);   // 24 m bytes in: 8-byte aligned
+    double *ub = ubs + m;
+    int32_t *ents = reinterpret_cast<int32_t *>(ub + m);
+    char *tail = static_cast<char *>(ws) + (44 * m + 255) / 256 * 256;
+    int32_t *qcount = reinterpret_cast<int32_t *>(tail);
+    uint32_t *qbc = reinterpret_cast<uint32_t *>(tail + ((size_t)nq * 4 + 255) / 256 * 256);
+    // split: kRC candidates per block with the waves splitting the rows (the bound-ordered
+    // rounds, few candidates per query), else 4 kRC per block.
+    auto score = [&](int first, int count, const int32_t *ord, const int32_t *en,
+                     const int32_t *qc, bool split) {
+        const int per = split ? kRC : kRerankPerBlock;
+        const int nbq = (count + per - 1) / per;
+        const int64_t blocks = (int64_t)nbq * 8 * ((nq + 7) / 8);
+        if (split)
+            hipLaunchKernelGGL(rerank_score_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, s,
+                               db->planes, db->popcnt, db->box, db->tbox, db->zrange, g.nz, g.Wp,
+                               g.nxw, g.ny, qpack, acnt, box, tbox, cand, nc, ws_s, ws_i, ws_I, nq,
+                               nbq, ord, en, qc, first, count);
+        else
+            hipLaunchKernelGGL(rerank_score_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, s,
+                               db->planes, db->popcnt, db->box, db->tbox, db->zrange, g.nz, g.Wp,
+                               g.nxw, g.ny, qpack, acnt, box, tbox, cand, nc, ws_s, ws_i, ws_I, nq,
+                               nbq, ord, en, qc, first, count);
+    };
+    int nbx = 0, nby = 0;
+    const int nbp = bound_blocks(g, &nbx, &nby);
+    const int n1 = (std::max(k, 16) + 15) / 16 * 16;    // scored before the gate
+    if (!db->rerank_bound || !db->bcnt || nbp == 0 || k <= 0 || n1 > 64 || nc <= n1) {
+        score(0, nc, nullptr, nullptr, nullptr, false);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(query_block_kernel, dim3((unsigned)nq), dim3(256), 0, s, qpack, g.Wp, g.nxw,
+                       g.ny, box, nbx, nby, nbp, qbc);
+    hipLaunchKernelGGL(rerank_ub_kernel, dim3((unsigned)((int64_t)nq * ((nc + 3) / 4))), dim3(256),
+                       0, s, db->bcnt, nbx, nby, nbp, db->popcnt, qbc, box, acnt, cand, nc, nq, ub);
+    hipLaunchKernelGGL(rerank_order_kernel, dim3((unsigned)nq), dim3(256), 0, s, ub, cand, nc, order,
+                       ubs, ents, ws_s, ws_i);
+    score(0, n1, order, ents, nullptr, true);
+    hipLaunchKernelGGL(rerank_gate_kernel, dim3((unsigned)((nq + 3) / 4)), dim3(256), 0, s, ws_s,
+                       order, ubs, nc, n1, k, nq, qcount);
+    score(n1, nc - n1, order, ents, qcount, true);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_counts(const db_t *db, const uint32_t *planes, int64_t n,
+                               const int32_t *box, uint16_t *bcnt, hipStream_t s)
+{
+    int nbx = 0, nby = 0;
+    const int nbp = bound_blocks(db->g, &nbx, &nby);
+    if (!bcnt || nbp == 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(block_count_kernel, dim3((unsigned)n), dim3(256), 0, s, planes, db->g.Wp,
+                       db->g.nxw, db->g.ny, box, nbx, nby, nbp, bcnt);
     return hipGetLastError();
 }
 

@@ -26,6 +26,19 @@ struct Geometry {
 
 bool make_geometry(int nx, int ny, int nz, Geometry *g);
 
+// The 16^3-voxel blocks of the per-entry counts that bound a candidate's Dice score in the
+// rerank: nbx = 2 nxw x blocks, ceil(ny / 16) y blocks, ceil(nz / 16) z blocks; returns the
+// blocks per mask padded to a multiple of 8, or 0 (no counts kept) above kBoundMaxBlocks.
+constexpr int kBoundMaxBlocks = 2048;
+inline int bound_blocks(const Geometry &g, int *nbx, int *nby)
+{
+    const int bx = 2 * g.nxw, by = (g.ny + 15) / 16, bz = (g.nz + 15) / 16;
+    if (nbx) *nbx = bx;
+    if (nby) *nby = by;
+    const int64_t nb = (int64_t)bx * by * bz;
+    return nb <= kBoundMaxBlocks ? (int)((nb + 7) / 8 * 8) : 0;
+}
+
 // Error reporting shared by every C entry point (message read by db_last_error).
 int tdb_set_error(int code, const char *fmt, ...);
 bool tdb_live(const db_t *db);
@@ -45,6 +58,8 @@ struct db_t {
     int32_t *box;       // [capacity][4] row box z0, z1, y0, y1 of the set bits
     int32_t *tbox;      // [capacity][4] row box of the T1Gd bits alone (all zero: none)
     uint32_t *zrange;   // [capacity][nz][2] per z-slice y-range of the FLAIR / T1Gd rows
+    uint16_t *bcnt;     // [capacity][2][nbp] set voxels per 16^3 block (nbp = bound_blocks)
+    int rerank_bound;   // 1: the rerank scores candidates in bound order and skips the rest
     uint64_t *mom;      // [capacity][4] FLAIR moments: sum x, sum y, sum z, count
     int32_t *tile_order;  // [capacity] entries sorted by row-box centre, in tiles by cost
     int64_t tile_order_n; // entries the tile order covers (it is rebuilt when count differs)
@@ -169,9 +184,14 @@ hipError_t launch_knn(bool fp8, int M, int N, int K, const void *Q, const float 
 size_t rerank_ws_bytes(int nq);
 // box: the queries' row boxes; tbox: those of their T1Gd bits alone (the T1Gd plane of a
 // pair is read only inside both T1Gd boxes).
+// With the block counts kept and k <= 64, the candidates go in bound order: the first
+// max(16, k) rounded to 16 are scored, then those whose bound reaches the k-th best score.
 hipError_t launch_rerank_score(const db_t *db, int nq, const uint32_t *qpack, const uint32_t *acnt,
                                const int32_t *box, const int32_t *tbox, const int32_t *cand,
-                               int nc, void *ws, hipStream_t s);
+                               int nc, int k, void *ws, hipStream_t s);
+// The 16^3-block counts of n entries (planes, row boxes) into bcnt.
+hipError_t launch_block_counts(const db_t *db, const uint32_t *planes, int64_t n,
+                               const int32_t *box, uint16_t *bcnt, hipStream_t s);
 hipError_t launch_rerank_rank(const db_t *db, int nq, const uint32_t *acnt, int nc, int k,
                               int32_t *idx, double *score, db_counts_t *counts, const void *ws,
                               hipStream_t s);

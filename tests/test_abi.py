@@ -37,16 +37,21 @@ def test_library_exports_every_declared_symbol():
 def test_storage_bytes():
     from paper_2205_04550_amd import binding
     # 128^3: 65,536 words per mask plane, 2 planes, 4 bytes; popcounts 8 bytes per entry;
-    # row boxes 16, moments 32, the tile order 4, the T1Gd row boxes 16 and the per-slice
-    # y-ranges 8 nz bytes per entry; each piece 256-byte aligned.
+    # row boxes 16, moments 32, the tile order 4, the T1Gd row boxes 16, the per-slice
+    # y-ranges 8 nz bytes and the 16^3-block counts 2 masks x 512 blocks x 2 bytes per entry;
+    # each piece 256-byte aligned.
     up = lambda b: (b + 255) // 256 * 256
     planes = 50000 * 2 * 65536 * 4
     meta = (up(50000 * 8) + up(50000 * 16) + up(50000 * 32) + up(50000 * 4) + up(50000 * 16) +
-            up(50000 * 128 * 8))
+            up(50000 * 128 * 8) + up(50000 * 2 * 512 * 2))
     assert binding.storage_bytes(128, 128, 128, 50000) == planes + meta
     # Ragged plane: 32x3x1 = 3 words, padded to 4: 10*2*4*4 = 320 -> 512; then 80, 160,
-    # 320, 40, 160 and 80 bytes -> 256, 256, 512, 256, 256 and 256.
-    assert binding.storage_bytes(32, 3, 1, 10) == 512 + 256 + 256 + 512 + 256 + 256 + 256
+    # 320, 40, 160 and 80 bytes -> 256, 256, 512, 256, 256 and 256; 2 x 1 x 1 blocks padded
+    # to 8: 10*2*8*2 = 320 -> 512.
+    assert binding.storage_bytes(32, 3, 1, 10) == 512 + 256 + 256 + 512 + 256 + 256 + 256 + 512
+    # 512^3: 32^3 blocks, more than the bound keeps: no block counts.
+    assert binding.storage_bytes(512, 512, 512, 1) == (
+        up(2 * 512 ** 3 // 8) + 256 * 5 + up(512 * 8))
     assert binding.storage_bytes(33, 4, 4, 10) == 0      # nx not a multiple of 32
     assert binding.storage_bytes(32, 0, 4, 10) == 0
     assert binding.storage_bytes(32, 4, 4, 0) == 0
