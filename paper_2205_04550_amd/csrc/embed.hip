@@ -742,35 +742,34 @@ __device__ __forceinline__ void block_counts_rows(const uint32_t *__restrict__ P
     if (z1 <= z0 || nyr <= 0) return;
     const int rows = (z1 - z0) * nyr;
     if (nxw % 4 == 0) {
-        const int nv = nxw / 4, items = rows * 2 * nv;
-        constexpr int B = 4;
-        for (int i0 = threadIdx.x; i0 < items; i0 += B * blockDim.x) {
-            u32x4 v[B];
-            int at[B];
+        // An item is 16 bytes (eight blocks) of the rows y of one 16-row block row at one
+        // (plane, z): summed in registers, then one LDS add per block.
+        const int nv = nxw / 4, yb0 = y0 >> 4, nyb = ((y1 - 1) >> 4) - yb0 + 1;
+        const int items = 2 * (z1 - z0) * nyb * nv;
+        for (int it = threadIdx.x; it < items; it += blockDim.x) {
+            const int vi = it % nv, r1 = it / nv, yb = yb0 + r1 % nyb, r2 = r1 / nyb;
+            const int pl = r2 & 1, z = z0 + (r2 >> 1);
+            const int ya = max(y0, 16 * yb), yz = min(y1, 16 * yb + 16);
+            const u32x4 *row = reinterpret_cast<const u32x4 *>(
+                P + (int64_t)pl * Wp + ((int64_t)z * ny + ya) * nxw + 4 * vi);
+            uint32_t acc[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+            for (int y = ya; y < yz; y += 4) {
+                u32x4 v[4];
 #pragma unroll
-            for (int u = 0; u < B; ++u) {
-                const int it = i0 + u * blockDim.x;
-                v[u] = (u32x4){0u, 0u, 0u, 0u};
-                at[u] = 0;
-                if (it < items) {
-                    const int vi = it % nv, rem = it / nv, pl = rem & 1, r = rem >> 1;
-                    const int zr = r / nyr, z = z0 + zr, y = y0 + r - zr * nyr;
-                    v[u] = *reinterpret_cast<const u32x4 *>(
-                        P + (int64_t)pl * Wp + ((int64_t)z * ny + y) * nxw + 4 * vi);
-                    at[u] = pl * nbp + ((z >> 4) * nby + (y >> 4)) * nbx + 8 * vi;
-                }
-            }
+                for (int u = 0; u < 4; ++u)
+                    v[u] = y + u < yz ? row[(int64_t)(y - ya + u) * nv] : (u32x4){0u, 0u, 0u, 0u};
 #pragma unroll
-            for (int u = 0; u < B; ++u)
+                for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const uint32_t word = v[u][e];
-                    if (word) {
-                        const uint32_t lo = popc(word & 0xffffu), hi = popc(word >> 16);
-                        if (lo) atomicAdd(&c[at[u] + 2 * e], lo);
-                        if (hi) atomicAdd(&c[at[u] + 2 * e + 1], hi);
+                    for (int t = 0; t < 4; ++t) {
+                        acc[2 * t] += popc(v[u][t] & 0xffffu);
+                        acc[2 * t + 1] += popc(v[u][t] >> 16);
                     }
-                }
+            }
+            const int at = pl * nbp + ((z >> 4) * nby + yb) * nbx + 8 * vi;
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                if (acc[t]) atomicAdd(&c[at + t], acc[t]);
         }
         return;
     }
@@ -825,10 +824,10 @@ __global__ void __launch_bounds__(256) query_block_kernel(const uint32_t *__rest
     for (int i = threadIdx.x; i < 2 * nbp; i += blockDim.x) qbc[(int64_t)q * 2 * nbp + i] = c[i];
 }
 
-// One wave per (query, candidate), blocks of four: the candidate's bound into ub [nq][nc].
-// With nbx % 8 == 0 a 16-byte chunk of counts is eight blocks of one (bz, by) block row, and
-// only the block rows the query's row box meets are read (the query's counts are zero
-// elsewhere).
+// One wave per four candidates of a query (blocks of four waves): each candidate's bound into
+// ub [nq][nc], the loads of the four issued together. With nbx % 8 == 0 a 16-byte chunk of
+// counts is eight blocks of one (bz, by) block row, and only the block rows the query's row
+// box meets are read (the query's counts are zero elsewhere).
 __global__ void __launch_bounds__(256) rerank_ub_kernel(const uint16_t *__restrict__ bcnt,
                                                         int nbx, int nby, int nbp,
                                                         const uint32_t *__restrict__ popcnt,
@@ -838,40 +837,66 @@ __global__ void __launch_bounds__(256) rerank_ub_kernel(const uint16_t *__restri
                                                         const int32_t *__restrict__ cand, int nc,
                                                         int nq, double *__restrict__ ub)
 {
+    constexpr int C = 4, CH = 2;               // candidates per wave; chunks per lane and pass
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int per = (nc + 3) / 4;
-    const int q = blockIdx.x / per, c = (blockIdx.x % per) * 4 + wave;
-    if (q >= nq || c >= nc) return;            // a whole wave leaves; no block barrier below
+    const int per = (nc + 4 * C - 1) / (4 * C);
+    const int q = blockIdx.x / per, c0 = ((blockIdx.x % per) * 4 + wave) * C;
+    if (q >= nq || c0 >= nc) return;           // a whole wave leaves; no block barrier below
     const int64_t qo = (int64_t)q * nc;
-    const int32_t e = cand[qo + c];
     const int32_t *b = box + 4 * q;
     const bool rows = nbx % 8 == 0;
     const int bz0 = b[0] >> 4, bz1 = b[1] > b[0] ? (b[1] - 1) >> 4 : -1;
     const int by0 = b[2] >> 4, by1 = b[3] > b[2] ? (b[3] - 1) >> 4 : -1;
-    const u32x4 *E = reinterpret_cast<const u32x4 *>(bcnt + (int64_t)e * 2 * nbp);
     const uint32_t *Q = qbc + (int64_t)q * 2 * nbp;
     const int nch = nbp / 8;                   // 16-byte chunks per plane
-    uint32_t u0 = 0u, u1 = 0u;
-    for (int ch = lane; ch < 2 * nch; ch += 64) {
-        const int pl = ch >= nch, b0 = 8 * (ch - pl * nch);
-        if (rows) {
-            const int br = b0 / nbx, bz = br / nby, by = br - bz * nby;
-            if (bz < bz0 || bz > bz1 || by < by0 || by > by1) continue;   // padding: bz >= nbz
-        }
-        const u32x4 v = E[ch];
-        const uint32_t *qq = Q + 8 * ch;
-        uint32_t m = 0u;
+    int32_t e[C];
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-            m += min(v[t] & 0xffffu, qq[2 * t]) + min(v[t] >> 16, qq[2 * t + 1]);
-        if (pl) u1 += m;
-        else u0 += m;
+    for (int j = 0; j < C; ++j) e[j] = cand[qo + min(c0 + j, nc - 1)];
+    uint32_t u0[C] = {}, u1[C] = {};
+    for (int ch0 = lane; ch0 < 2 * nch; ch0 += 64 * CH) {
+        bool use[CH];
+        u32x4 v[CH][C];
+#pragma unroll
+        for (int h = 0; h < CH; ++h) {
+            const int ch = ch0 + 64 * h;
+            const int pl = ch >= nch, b0 = 8 * (ch - pl * nch);
+            bool in = ch < 2 * nch;
+            if (rows && in) {
+                const int br = b0 / nbx, bz = br / nby, by = br - bz * nby;
+                in = bz >= bz0 && bz <= bz1 && by >= by0 && by <= by1;   // padding: bz >= nbz
+            }
+            use[h] = in;
+#pragma unroll
+            for (int j = 0; j < C; ++j)
+                v[h][j] = in ? reinterpret_cast<const u32x4 *>(bcnt + (int64_t)e[j] * 2 * nbp)[ch]
+                             : (u32x4){0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int h = 0; h < CH; ++h) {
+            if (!use[h]) continue;
+            const int ch = ch0 + 64 * h;
+            const uint32_t *qq = Q + 8 * ch;
+            uint32_t qv[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) qv[t] = qq[t];
+#pragma unroll
+            for (int j = 0; j < C; ++j) {
+                uint32_t m = 0u;
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    m += min(v[h][j][t] & 0xffffu, qv[2 * t]) + min(v[h][j][t] >> 16, qv[2 * t + 1]);
+                if (ch >= nch) u1[j] += m;
+                else u0[j] += m;
+            }
+        }
     }
-    u0 = wave_sum(u0);
-    u1 = wave_sum(u1);
-    if (lane == 0)
-        ub[qo + c] = dice(u1, acnt[2 * q + 1], popcnt[2 * (int64_t)e + 1]) +
-                     dice(u0, acnt[2 * q], popcnt[2 * (int64_t)e]);
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+        const uint32_t a0 = wave_sum(u0[j]), a1 = wave_sum(u1[j]);
+        if (lane == 0 && c0 + j < nc)
+            ub[qo + c0 + j] = dice(a1, acnt[2 * q + 1], popcnt[2 * (int64_t)e[j] + 1]) +
+                              dice(a0, acnt[2 * q], popcnt[2 * (int64_t)e[j]]);
+    }
 }
 
 // grid nq, 256 threads: the query's candidates sorted by (bound desc, slot asc) into order /
@@ -1824,7 +1849,7 @@ hipError_t launch_rerank_score(const db_t *db, int nq, const uint32_t *qpack, co
     }
     hipLaunchKernelGGL(query_block_kernel, dim3((unsigned)nq), dim3(256), 0, s, qpack, g.Wp, g.nxw,
                        g.ny, box, nbx, nby, nbp, qbc);
-    hipLaunchKernelGGL(rerank_ub_kernel, dim3((unsigned)((int64_t)nq * ((nc + 3) / 4))), dim3(256),
+    hipLaunchKernelGGL(rerank_ub_kernel, dim3((unsigned)((int64_t)nq * ((nc + 15) / 16))), dim3(256),
                        0, s, db->bcnt, nbx, nby, nbp, db->popcnt, qbc, box, acnt, cand, nc, nq, ub);
     hipLaunchKernelGGL(rerank_order_kernel, dim3((unsigned)nq), dim3(256), 0, s, ub, cand, nc, order,
                        ubs, ents, ws_s, ws_i);
