@@ -570,6 +570,32 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
         any |= act[j];
     }
     if (!any) return;       // a whole wave leaves; no block barrier below
+    // Each member's per-slice y-ranges of its FLAIR and T1Gd rows over the query's slices (every
+    // slice swept lies in them), in this wave's part of LDS, their loads issued together and
+    // before the members' boxes are known (a query deeper than kZStage slices goes by the
+    // boxes alone).
+    __shared__ uint2 s_zr[4][kRC][kZStage];
+    const int nzs = qz1 - qz0;
+    const bool zr_ok = nzs > 0 && nzs <= kZStage;
+    if (zr_ok) {
+        constexpr int kStageMax = kRC * kZStage / 64;
+        uint2 t[kStageMax];
+#pragma unroll
+        for (int u = 0; u < kStageMax; ++u) {
+            const int i = lane + 64 * u, j = i / nzs, zz = i - j * nzs;
+            const int32_t e = j == 0 ? ent[0] : j == 1 ? ent[1] : j == 2 ? ent[2] : ent[3];
+            t[u] = i < kRC * nzs ? *reinterpret_cast<const uint2 *>(zrange + ((int64_t)e * nz + qz0 + zz) * 2)
+                                 : (uint2){0u, 0u};
+        }
+#pragma unroll
+        for (int u = 0; u < kStageMax; ++u) {
+            const int i = lane + 64 * u, j = i / nzs, zz = i - j * nzs;
+            if (i < kRC * nzs) s_zr[wave][j][zz] = t[u];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     const uint32_t *D0[kRC], *D1[kRC];
     int z0[kRC], z1[kRC], y0[kRC], y1[kRC], tz0[kRC], tz1[kRC], ty0[kRC], ty1[kRC];
     int uz0 = INT_MAX, uz1 = INT_MIN, uy0 = INT_MAX, uy1 = INT_MIN;
@@ -602,25 +628,10 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
     }
     const int nyr = uy1 > uy0 ? uy1 - uy0 : 0;
     const int nr = uz1 > uz0 ? (uz1 - uz0) * nyr : 0;
-    // Each member's per-slice y-ranges of its FLAIR and T1Gd rows over the slices swept, in
-    // this wave's part of LDS (a sweep deeper than kZStage slices goes by the boxes alone).
-    __shared__ uint2 s_zr[4][kRC][kZStage];
-    const bool zr_ok = nr > 0 && uz1 - uz0 <= kZStage;
-    if (zr_ok) {
-        const int nzs = uz1 - uz0;
-        for (int i = lane; i < kRC * nzs; i += 64) {
-            const int j = i / nzs, zz = i - j * nzs;
-            const int32_t e = j == 0 ? ent[0] : j == 1 ? ent[1] : j == 2 ? ent[2] : ent[3];
-            s_zr[wave][j][zz] = *reinterpret_cast<const uint2 *>(zrange + ((int64_t)e * nz + uz0 + zz) * 2);
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
     // Row (z, y) of member j holds FLAIR bits only if y is in its FLAIR range of slice z.
     auto in_range = [&](int j, int z, int y, bool t1gd) {
         if (!zr_ok) return true;
-        const uint2 rg = s_zr[wave][j][z - uz0];
+        const uint2 rg = s_zr[wave][j][z - qz0];
         const uint32_t v = t1gd ? rg.y : rg.x;
         return y >= (int)(v & 0xffffu) && y < (int)(v >> 16);
     };
