@@ -657,11 +657,12 @@ def encode_stage_bytes(model, gen, nq: int) -> float:
     """HBM bytes of the embedding step's encode stage for nq queries (BF16 forward): the
     labels read once (by the query packing), the packed masks and the pooled counts written,
     the counts read by the first two layers (one kernel: the first layer's output stays on
-    chip), the second and third convolutions' outputs written and read once (bfloat16), the
-    last one's (float) and the latents written."""
+    chip), the second layer's output written and read once (bfloat16), the third and fourth
+    layers in one kernel (the third's output stays on chip), the fourth's output (float)
+    written and read once and the latents written."""
     g, c = model.grid, model.channels
     per = gen.nvox + 2 * gen.nvox // 8 + 2 * gen.nvox // 8
-    per += sum(2 * 2 * (g >> (i + 1)) ** 3 * c[i + 1] for i in range(1, 3))
+    per += 2 * 2 * (g >> 2) ** 3 * c[2]
     per += 2 * 4 * (g >> 4) ** 3 * c[4] + 4 * model.latent
     return float(per) * nq
 
@@ -829,9 +830,10 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
             "note": "the stage's HBM bytes: the labels read once (the query packing), the "
                     "packed masks and the pooled counts written, the counts read by the first "
                     "two layers (one kernel; the first layer's activations stay on chip), the "
-                    "second and third layers' bfloat16 activations written once and read once, "
-                    "the last layer's float output; the convolutions run on the BF16 matrix "
-                    "cores, the linear head on the FP32 ones"},
+                    "second layer's bfloat16 activations written once and read once by the third "
+                    "and fourth layers (one kernel; the third's activations stay on chip), the "
+                    "last layer's float output; the convolutions run on the BF16 matrix cores, "
+                    "the linear head on the FP32 ones"},
         "latent_search": {"bound": "mfma", "achieved_tflops": gemm_flop / (stage[1] * 1e-3) / 1e12,
                           "peak_tflops": BF16_MFMA_PEAK / 1e12,
                           "frac": gemm_flop / (stage[1] * 1e-3) / BF16_MFMA_PEAK,

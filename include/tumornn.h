@@ -131,6 +131,15 @@ int nn_pool_conv_counts_bf16(const uint8_t *counts, int B, int nx, int ny, int n
 int nn_counts_conv12_bf16(const uint8_t *counts, int B, int nx, int ny, int nz, int mask,
                           const void *Wt1, const float *b1, const void *Wtm2, const float *b2,
                           void *Y, void *stream);
+/* The encoder's third and fourth layers in one pass (Sec. 2.3, "Autoencoders"), one block per
+ * sample: nn_conv3d_s2_fwd_bf16 with (Ci, Co) = (16, 32), ReLU, bfloat16 output, then with
+ * (32, 64), ReLU, float output, bit for bit, the third layer's output kept on chip.
+ * X bfloat16 channels-last [B][16][16][16][16] (16-byte aligned); Wtm3 / Wtm4 the tap-major
+ * weights [32][28][16] / [64][28][32] of nn_conv3d_weights_tapmajor (16-byte aligned); b3 [32]
+ * and b4 [64] float or NULL; Y float [B][64][4][4][4]. Device pointers, caller-owned;
+ * enqueued on `stream`. DB_EINVAL for B <= 0, a NULL or misaligned pointer. */
+int nn_conv34_bf16(int B, const void *X, const void *Wtm3, const float *b3, const void *Wtm4,
+                   const float *b4, float *Y, void *stream);
 /* Tap-major copy of bfloat16 convolution weights for nn_conv3d_s2_fwd_bf16:
  * out[co][t][ci] = Wt[co][ci][t] for the 27 taps t (kd, kh, kw order) and 0 for
  * t = 27; out holds Co * 28 * Ci bfloat16 values (device). */

@@ -1835,6 +1835,126 @@ __global__ void __launch_bounds__(256, 4) counts_conv12_kernel(
     }
 }
 
+// ---- The third and fourth layers in one pass, per sample ------------------------------------
+//
+// conv_bf16_kernel<16, 32, ...> (bfloat16 output) followed by conv_bf16_kernel<32, 64, ...>
+// (float output) for a 16^3 x 16-channel input: a block per sample streams the input through
+// a ring of three z-slices in LDS, computes each 8 x 8 output slice of the third layer into an
+// LDS copy of its whole 8^3 x 32 output, then the fourth layer's 4^3 x 64 outputs from it. The
+// operands (k = 32 per product: lane quarter g takes tap kg / NG, channels 8 (kg % NG) .. + 7
+// with kg = 4 st + g), sums and roundings are those kernels': Y equals theirs bit for bit.
+// Zero padding by range checks on the operand reads (no halo stored).
+constexpr int kC34In = 16 * 16 * 16;              // one input slice: 16 x 16 voxels x 16 ch (bf16)
+constexpr int kC34Mid = 8 * 8 * 8 * 32;           // the third layer's output, bf16
+
+__global__ void __launch_bounds__(512, 1) conv34_kernel(const uint16_t *__restrict__ X,
+                                                        const uint16_t *__restrict__ Wtm3,
+                                                        const float *__restrict__ b3,
+                                                        const uint16_t *__restrict__ Wtm4,
+                                                        const float *__restrict__ b4,
+                                                        float *__restrict__ Y)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t ring[3 * kC34In];
+    __shared__ __attribute__((aligned(16))) uint16_t mid[kC34Mid];
+    const int b = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, j = lane & 15;
+    const uint16_t *Xb = X + (int64_t)b * 16 * kC34In;
+    const bf16x8 zero8 = __builtin_bit_cast(bf16x8, (u32x4){0u, 0u, 0u, 0u});
+
+    // Two input slices (16 KB) per step, 32 bytes per thread: z = zs, zs + 1.
+    u32x4 v[2];
+    auto load2 = [&](int zs) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int c = tid + 512 * u, z = zs + (c >> 9);           // 512 chunks per slice
+            v[u] = z < 16 ? *reinterpret_cast<const u32x4 *>(Xb + (int64_t)z * kC34In + 8 * (c & 511))
+                          : (u32x4){0u, 0u, 0u, 0u};
+        }
+    };
+    auto store2 = [&](int zs) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int c = tid + 512 * u, z = zs + (c >> 9);
+            *reinterpret_cast<u32x4 *>(&ring[((z + 3) % 3) * kC34In + 8 * (c & 511)]) = v[u];
+        }
+    };
+
+    // Third layer: wave w owns output rows oy = 2 (w / 2), + 1 (voxel tile of 16: oy = 2 (w / 2)
+    // + j / 8, ox = j % 8) and the 16-channel tile w % 2.
+    const int oy = 2 * (wave >> 1) + (j >> 3), ox = j & 7, ct = wave & 1;
+    const uint16_t *w3 = Wtm3 + (ct * 16 + j) * 28 * 16 + 8 * g;
+    float bias3[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bias3[r] = b3 ? b3[ct * 16 + 4 * g + r] : 0.f;
+
+    load2(0);                      // slices 0, 1; slice -1 is padding
+    for (int z3 = 0; z3 < 8; ++z3) {
+        store2(2 * z3);
+        if (z3 + 1 < 8) load2(2 * z3 + 2);   // in flight during the products
+        __syncthreads();
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int st = 0; st < 14; ++st) {
+            const int kg = 4 * st + g, tap = kg >> 1, cg = kg & 1;
+            const int tp = tap < 27 ? tap : 0;
+            const int kd = tp / 9, kh = (tp / 3) % 3, kw = tp % 3;
+            const int iz = 2 * z3 - 1 + kd, iy = 2 * oy - 1 + kh, ix = 2 * ox - 1 + kw;
+            const bool in = iz >= 0 && iy >= 0 && ix >= 0;            // < 16 always
+            const bf16x8 bv = in ? *reinterpret_cast<const bf16x8 *>(
+                                       &ring[((iz + 3) % 3) * kC34In + (iy * 16 + ix) * 16 + 8 * cg])
+                                 : zero8;
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                *reinterpret_cast<const bf16x8 *>(w3 + 32 * st), bv, acc, 0, 0, 0);
+        }
+        // Bias, ReLU, bfloat16 into the third layer's output [z][y][x][32].
+        {
+            float y[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                y[r] = acc[r] + bias3[r];
+                if (y[r] < 0.f) y[r] = 0.f;
+            }
+            *reinterpret_cast<u32x2 *>(&mid[((z3 * 8 + oy) * 8 + ox) * 32 + ct * 16 + 4 * g]) =
+                (u32x2){bf16x2_rne(y[0], y[1]), bf16x2_rne(y[2], y[3])};
+        }
+        __syncthreads();           // the next step's slices overwrite the ring
+    }
+
+    // Fourth layer: wave w owns output channels 16 (w / 2) .. + 15 and the voxel tiles
+    // m = 2 (w % 2), + 1 (tile m: oz = m, oy = j / 4, ox = j % 4).
+    f32x4 acc4[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+    const int c4 = wave >> 1, m0 = 2 * (wave & 1);
+    const uint16_t *wl = Wtm4 + (int64_t)(c4 * 16 + j) * 28 * 32 + 8 * g;
+    const int py = j >> 2, px = j & 3;
+#pragma unroll 4
+    for (int st = 0; st < 28; ++st) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(wl + 32 * st);
+        const int kg = 4 * st + g, tap = kg >> 2, cg = kg & 3;
+        const int tp = tap < 27 ? tap : 0;
+        const int kd = tp / 9, kh = (tp / 3) % 3, kw = tp % 3;
+        const int iy = 2 * py - 1 + kh, ix = 2 * px - 1 + kw;
+#pragma unroll
+        for (int mm = 0; mm < 2; ++mm) {
+            const int m = m0 + mm, iz = 2 * m - 1 + kd;
+            const bool in = iz >= 0 && iy >= 0 && ix >= 0;             // < 8 always
+            const bf16x8 bv = in ? *reinterpret_cast<const bf16x8 *>(
+                                       &mid[((iz * 8 + iy) * 8 + ix) * 32 + 8 * cg])
+                                 : zero8;
+            acc4[mm] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc4[mm], 0, 0, 0);
+        }
+    }
+    float *Yb = Y + (int64_t)b * 64 * 64;
+#pragma unroll
+    for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int co = c4 * 16 + 4 * g + r;
+            float y = acc4[mm][r] + (b4 ? b4[co] : 0.f);
+            if (y < 0.f) y = 0.f;
+            Yb[co * 64 + (m0 + mm) * 16 + j] = y;
+        }
+}
+
 // Tap-major copy of convolution weights for conv_bf16_kernel: out[co][t][ci] = w[co][ci][t]
 // (t < 27; the model's [co][ci][kd][kh][kw] order) and 0 for t = 27.
 __global__ void conv_w_tapmajor_kernel(int Co, int Ci, const uint16_t *__restrict__ w,
@@ -2189,6 +2309,19 @@ int nn_counts_conv12_bf16(const uint8_t *counts, int B, int nx, int ny, int nz, 
         hipLaunchKernelGGL(counts_conv12_kernel<1>, dim3((unsigned)units), dim3(256), 0, s, counts,
                            nx, ny, nz, mask, zc, (int)units, w1, b1, w2, b2, y);
     return launched("nn_counts_conv12_bf16");
+}
+
+int nn_conv34_bf16(int B, const void *X, const void *Wtm3, const float *b3, const void *Wtm4,
+                   const float *b4, float *Y, void *stream)
+{
+    if (B <= 0 || !X || !Wtm3 || !Wtm4 || !Y || (uintptr_t)X % 16 || (uintptr_t)Wtm3 % 16 ||
+        (uintptr_t)Wtm4 % 16)
+        return tdb_set_error(DB_EINVAL, "nn_conv34_bf16: bad arguments");
+    hipLaunchKernelGGL(conv34_kernel, dim3((unsigned)B), dim3(512), 0,
+                       static_cast<hipStream_t>(stream), static_cast<const uint16_t *>(X),
+                       static_cast<const uint16_t *>(Wtm3), b3, static_cast<const uint16_t *>(Wtm4),
+                       b4, Y);
+    return launched("nn_conv34_bf16");
 }
 
 int nn_conv3d_weights_tapmajor(const void *Wt, int Co, int Ci, void *out, void *stream)

@@ -63,6 +63,7 @@ _SIGS = {
                                         _vp, _vp]),
     "nn_counts_conv12_bf16": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
                                      _vp]),
+    "nn_conv34_bf16": (_i32, [_i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "nn_conv3d_weights_tapmajor": (_i32, [_vp, _i32, _i32, _vp, _vp]),
     "nn_linear_fwd_split": (_i32, [_i32, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _i32, _vp, _sz,
                                    _vp]),
@@ -255,6 +256,22 @@ def counts_conv12_bf16(counts: torch.Tensor, w1_bf16: torch.Tensor, b1: torch.Te
     _check(LIB.nn_counts_conv12_bf16(counts.data_ptr(), B, nx, ny, nz, -1 if mask is None else mask,
                                      w1_bf16.data_ptr(), _p(b1), w2_tm.data_ptr(), _p(b2),
                                      y.data_ptr(), _s()))
+    return y
+
+
+def conv34_bf16(x: torch.Tensor, w3_tm: torch.Tensor, b3: torch.Tensor | None,
+                w4_tm: torch.Tensor, b4: torch.Tensor | None) -> torch.Tensor:
+    """The third and fourth layers (ReLU; 16 -> 32 -> 64 channels) of bfloat16 channels-last
+    x [B][16][16][16][16] in one kernel: conv3d_bf16 twice (the second with float output),
+    bit for bit; float [B][64][4][4][4]."""
+    x = _c(x)
+    assert x.dtype == torch.bfloat16 and tuple(x.shape[1:]) == (16, 16, 16, 16)
+    assert tuple(w3_tm.shape) == (32, 28, 16) and tuple(w4_tm.shape) == (64, 28, 32)
+    b3 = None if b3 is None else _c(b3.detach())
+    b4 = None if b4 is None else _c(b4.detach())
+    y = torch.empty((x.shape[0], 64, 4, 4, 4), dtype=torch.float32, device=x.device)
+    _check(LIB.nn_conv34_bf16(x.shape[0], x.data_ptr(), _c(w3_tm).data_ptr(), _p(b3),
+                              _c(w4_tm).data_ptr(), _p(b4), y.data_ptr(), _s()))
     return y
 
 
@@ -676,6 +693,11 @@ class AutoEncoder:
         """The convolutions from layer `first` on (BF16 matrix cores), then the head (float)."""
         with torch.no_grad():
             tm = self._tapmajor()
+            if first == 2 and tuple(h.shape[1:]) == (16, 16, 16, 16):   # layers 3 and 4 fused
+                _, b3, _ = self._w("enc2")
+                _, b4, _ = self._w("enc3")
+                h = conv34_bf16(h, tm["enc2"], b3, tm["enc3"], b4)
+                first = 4
             for i in range(first, 4):
                 w, b, wc = self._w(f"enc{i}")
                 h = conv3d_bf16(h, tm[f"enc{i}"], b, True, out_f32=(i == 3))

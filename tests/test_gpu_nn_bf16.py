@@ -303,3 +303,25 @@ def test_first_two_layers_reject_bad_grids():
         c = torch.zeros(1, pz, py, px, dtype=torch.uint8, device="cuda")
         with pytest.raises(RuntimeError):
             nn.counts_conv12_bf16(c, w1, None, w2tm, None)
+
+
+@pytest.mark.parametrize("B", [1, 3, 300])
+def test_third_and_fourth_layers_in_one_kernel(B):
+    """nn_conv34_bf16 equals the third and fourth BF16 convolutions as two kernels bit for
+    bit, with and without biases, on inputs with zero regions (ReLU of the bias alone)."""
+    need_gpu()
+    from paper_2205_04550_amd import nn
+    x = _bf16_input((B, 16, 16, 16, 16), B)
+    x[0, :4] = 0
+    x = x.cuda()
+    g = torch.Generator().manual_seed(B + 1)
+    for bias in (True, False):
+        w3 = (torch.randn(32, 16, 3, 3, 3, generator=g) * 0.1).to(torch.bfloat16).cuda()
+        w4 = (torch.randn(64, 32, 3, 3, 3, generator=g) * 0.1).to(torch.bfloat16).cuda()
+        b3 = torch.randn(32, generator=g).cuda() * 0.1 if bias else None
+        b4 = torch.randn(64, generator=g).cuda() * 0.1 if bias else None
+        t3, t4 = nn.conv_weights_tapmajor(w3), nn.conv_weights_tapmajor(w4)
+        want = nn.conv3d_bf16(nn.conv3d_bf16(x, t3, b3, True), t4, b4, True, out_f32=True)
+        got = nn.conv34_bf16(x, t3, b3, t4, b4)
+        assert torch.equal(got.view(torch.int32), want.view(torch.int32)), bias
+        assert float((want != 0).double().mean()) > 0.05
