@@ -763,7 +763,7 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
     rr_roof = {"bound": "hbm", "achieved": rr_bytes / (rr_avg * 1e-3) / 1e9,
                "peak": HBM_PEAK_GBS, "unit": "GB/s",
                "frac": rr_bytes / (rr_avg * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-               "kernel": "rerank_bound_kernel + rerank_score_kernel (two rounds)",
+               "kernel": "query_block_kernel + rerank_ub_kernel + rerank_order_kernel + rerank_score_kernel<4> x 2 + rerank_gate_kernel",
                "kernel_avg_ms": rr_avg, "algorithmic_bytes_per_launch": rr_bytes,
                "candidates_scored_per_query": n_scored,
                "note": "the rerank's scoring between HIP events; bytes = every candidate's "
