@@ -641,7 +641,7 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
     if (nxw == 4) {
         // Rows of 128 voxels: one 16-byte load per plane; two rows per lane per pass, all
         // loads of the pass issued before any is used.
-        constexpr int U = 2;
+        constexpr int U = SPLIT == 1 ? 2 : 1;
         const int rw = SPLIT == 1 ? 0 : wave;
         for (int r0 = lane + 64 * U * rw; r0 < nr; r0 += 64 * U * SPLIT) {
             u32x4 qa[U], qb[U], da[U][kRC], db[U][kRC];
