@@ -886,10 +886,9 @@ __global__ void __launch_bounds__(256) rerank_ub_kernel(const uint16_t *__restri
         for (int h = 0; h < CH; ++h) {
             if (!use[h]) continue;
             const int ch = ch0 + 64 * h;
-            const uint32_t *qq = Q + 8 * ch;
-            uint32_t qv[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) qv[t] = qq[t];
+            const u32x4 qa = *reinterpret_cast<const u32x4 *>(Q + 8 * ch);    // 32-byte aligned
+            const u32x4 qb = *reinterpret_cast<const u32x4 *>(Q + 8 * ch + 4);
+            const uint32_t qv[8] = {qa[0], qa[1], qa[2], qa[3], qb[0], qb[1], qb[2], qb[3]};
 #pragma unroll
             for (int j = 0; j < C; ++j) {
                 uint32_t m = 0u;
