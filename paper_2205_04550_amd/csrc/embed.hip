@@ -515,8 +515,9 @@ constexpr int kZStage = 128;           // z-slices of per-slice row ranges a wav
 // overlaps go to ws (score bits [nq][nc], index [nq][nc], I [nq][nc][2]).
 // SPLIT = 4: a block scores kRC candidates (not 4 kRC), its four waves taking every fourth
 // pass over the rows and adding their overlaps in LDS: four times the waves per candidate, for
-// launches with few candidates per query.
-template <int SPLIT>
+// launches with few candidates per query. ALLZR: nz <= kZStage, so every query's slices have
+// their ranges staged.
+template <int SPLIT, bool ALLZR>
 __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__restrict__ planes,
                                                            const uint32_t *__restrict__ popcnt,
                                                            const int32_t *__restrict__ ebox,
@@ -653,12 +654,22 @@ __global__ void __launch_bounds__(256) rerank_score_kernel(const uint32_t *__res
                 const int base = (z * ny + y) * 4;
                 const bool live = r < nr;
                 bool any0 = false, any1 = false;
+                // With the slice ranges staged, a member's range of a slice lies in its own row
+                // boxes and the sweep in the query's row box: the range decides for FLAIR, the
+                // range and the query's T1Gd box for T1Gd.
+                const bool tin = z >= tqz0 && z < tqz1 && y >= tqy0 && y < tqy1;
 #pragma unroll
                 for (int j = 0; j < kRC; ++j) {
-                    const bool in0 = live && z >= z0[j] && z < z1[j] && y >= y0[j] && y < y1[j] &&
-                                     in_range(j, z, y, false);
-                    const bool in1 = live && z >= tz0[j] && z < tz1[j] && y >= ty0[j] && y < ty1[j] &&
-                                     in_range(j, z, y, true);
+                    bool in0, in1;
+                    if constexpr (ALLZR) {
+                        in0 = live && act[j] && in_range(j, z, y, false);
+                        in1 = live && act[j] && tin && in_range(j, z, y, true);
+                    } else {
+                        in0 = live && z >= z0[j] && z < z1[j] && y >= y0[j] && y < y1[j] &&
+                              in_range(j, z, y, false);
+                        in1 = live && z >= tz0[j] && z < tz1[j] && y >= ty0[j] && y < ty1[j] &&
+                              in_range(j, z, y, true);
+                    }
                     any0 |= in0;
                     any1 |= in1;
                     da[u][j] = db[u][j] = (u32x4){0u, 0u, 0u, 0u};
@@ -1839,16 +1850,17 @@ hipError_t launch_rerank_score(const db_t *db, int nq, const uint32_t *qpack, co
         const int per = split ? kRC : kRerankPerBlock;
         const int nbq = (count + per - 1) / per;
         const int64_t blocks = (int64_t)nbq * 8 * ((nq + 7) / 8);
-        if (split)
-            hipLaunchKernelGGL(rerank_score_kernel<4>, dim3((unsigned)blocks), dim3(256), 0, s,
-                               db->planes, db->popcnt, db->box, db->tbox, db->zrange, g.nz, g.Wp,
-                               g.nxw, g.ny, qpack, acnt, box, tbox, cand, nc, ws_s, ws_i, ws_I, nq,
-                               nbq, ord, en, qc, first, count);
-        else
-            hipLaunchKernelGGL(rerank_score_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, s,
-                               db->planes, db->popcnt, db->box, db->tbox, db->zrange, g.nz, g.Wp,
-                               g.nxw, g.ny, qpack, acnt, box, tbox, cand, nc, ws_s, ws_i, ws_I, nq,
-                               nbq, ord, en, qc, first, count);
+#define TDB_RERANK_SCORE(SPLIT_, ALLZR_)                                                            \
+    hipLaunchKernelGGL((rerank_score_kernel<SPLIT_, ALLZR_>), dim3((unsigned)blocks), dim3(256), 0, \
+                       s, db->planes, db->popcnt, db->box, db->tbox, db->zrange, g.nz, g.Wp,      \
+                       g.nxw, g.ny, qpack, acnt, box, tbox, cand, nc, ws_s, ws_i, ws_I, nq, nbq,  \
+                       ord, en, qc, first, count)
+        const bool allzr = g.nz <= kZStage;
+        if (split && allzr) TDB_RERANK_SCORE(4, true);
+        else if (split) TDB_RERANK_SCORE(4, false);
+        else if (allzr) TDB_RERANK_SCORE(1, true);
+        else TDB_RERANK_SCORE(1, false);
+#undef TDB_RERANK_SCORE
     };
     int nbx = 0, nby = 0;
     const int nbp = bound_blocks(g, &nbx, &nby);
