@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=300,
                     help="encoder training steps before the embed workload")
     ap.add_argument("--embed-nq", type=int, default=1024)
+    ap.add_argument("--embed-streams", type=int, default=2,
+                    help="the embedding batch in this many parts, each chain on its own stream")
     ap.add_argument("--nq", type=int, default=256, help="queries per launch (batch workload)")
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -757,6 +759,48 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
     rr_ms, rr_launches = db.profile_read()
     db.profile(False)
     rr_avg = rr_ms / max(1, rr_launches)
+    # The same batch in H parts, each chain (packing, encoder, search, rerank) on a stream of
+    # its own, so that one part's memory-bound kernels run beside another's compute-bound ones;
+    # the top k must equal the one-stream step's.
+    H = max(1, args.embed_streams)
+    halves = []
+    for h in range(H):
+        a, b = h * nq // H, (h + 1) * nq // H
+        halves.append({"lab": lab_d[a:b], "ws": db.rerank_workspace(b - a),
+                       "pooled": torch.empty((b - a, gen.nz // 2, gen.ny // 2, gen.nx // 2),
+                                             dtype=torch.uint8, device="cuda"),
+                       "kws": B.knn_workspace(b - a, n, n_cand),
+                       "kout": (torch.empty((b - a, n_cand), dtype=torch.int32, device="cuda"),
+                                torch.empty((b - a, n_cand), dtype=torch.float32, device="cuda")),
+                       "stream": torch.cuda.Stream()})
+
+    def step_halves():
+        cur = torch.cuda.current_stream()
+        outs = []
+        for hh in halves:
+            hh["stream"].wait_stream(cur)
+            with torch.cuda.stream(hh["stream"]):
+                db.rerank_pack_pool(hh["lab"], hh["ws"], hh["pooled"])
+                Qh = B.Latents(model.encode_counts_bf16(hh["pooled"]), B.EMB_BF16)
+                ch, _ = B.emb_knn(Qh, X, n_cand, direct=True, ws=hh["kws"], out=hh["kout"])
+                outs.append(db.rerank_packed(hh["ws"], ch, k))
+        for hh in halves:
+            cur.wait_stream(hh["stream"])
+        return outs
+
+    for _ in range(args.warmup):
+        step_halves()
+    torch.cuda.synchronize()
+    th0 = time.perf_counter()
+    for _ in range(args.steps):
+        outs = step_halves()
+    torch.cuda.synchronize()
+    ms_halves = (time.perf_counter() - th0) * 1e3 / args.steps
+    halves_equal = bool(torch.equal(torch.cat([o[0] for o in outs]), idx) and
+                        torch.equal(torch.cat([o[1] for o in outs]).view(torch.int64),
+                                    score.view(torch.int64)))
+    log(f"{H} parts on {H} streams: {ms_halves:.3f} ms per {nq} queries "
+        f"({nq / (ms_halves * 1e-3):.0f} q/s), top-k equal to one stream: {halves_equal}")
     scored, bound_bytes = bound_scored(db, lab_d, ci, k, gen)
     rr_bytes = rerank_bytes(db, lab_d, ci, gen, scored=scored) + bound_bytes
     n_scored = float(scored.double().sum(1).mean())
@@ -801,20 +845,26 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
              "latent distances + top-100 in one pass (BF16 MFMA), direct-form candidate distances",
              "exact rerank"]
     dom = int(np.argmax(stage))
-    log(f"{ms:.2f} ms per {nq} queries ({nq / (ms * 1e-3):.0f} q/s); stages "
+    # The job's step: the batch in parts on their own streams when that is faster and gives
+    # the same top k; the stage times below are the one-stream step's.
+    ms_job = ms_halves if H > 1 and halves_equal and ms_halves < ms else ms
+    log(f"{ms_job:.2f} ms per {nq} queries ({nq / (ms_job * 1e-3):.0f} q/s; one stream "
+        f"{ms:.2f} ms); one-stream stages "
         + ", ".join(f"{a} {b:.3f} ms" for a, b in zip(names, stage))
         + f"; recall@10 {recall10:.3f}; {top_n}; speed-up vs exact "
-          f"{exact_ms_per_query * nq / ms:.0f}x; rerank scored {n_scored:.1f} of {n_cand} "
+          f"{exact_ms_per_query * nq / ms_job:.0f}x; rerank scored {n_scored:.1f} of {n_cand} "
           f"candidates per query (query packing {pack_ms:.3f} ms)")
     out = {
-        "metric": "queries/sec at recall@10", "value": nq / (ms * 1e-3), "unit": "queries/s",
-        "ms_per_step": ms, "steps": args.steps, "warmup": args.warmup, "dtype": "bf16",
+        "metric": "queries/sec at recall@10", "value": nq / (ms_job * 1e-3), "unit": "queries/s",
+        "ms_per_step": ms_job, "steps": args.steps, "warmup": args.warmup, "dtype": "bf16",
         "config": {"workload": f"embedding search, {nq} held-out queries x {n} latents (512-d "
                                f"BF16), top-{n_cand} by MFMA distance, exact 128^3 Dice rerank, "
                                f"top-{k}", "n_db": n, "nq": nq, "n_cand": n_cand,
-                   "train_steps": args.train_steps},
+                   "train_steps": args.train_steps, "streams": H if ms_job == ms_halves else 1},
+        "one_stream_ms_per_step": ms, "parts_streams": H, "parts_ms_per_step": ms_halves,
+        "parts_topk_equal_one_stream": halves_equal,
         "recall_at_10": recall10, **top_n, "candidate_recall_at_10": cand_recall,
-        "speedup_vs_exact_scan": exact_ms_per_query * nq / ms,
+        "speedup_vs_exact_scan": exact_ms_per_query * nq / ms_job,
         "exact_ms_per_query": exact_ms_per_query,
         "stages_ms": dict(zip(names, stage.tolist())),
         "dominant_stage": names[dom],
