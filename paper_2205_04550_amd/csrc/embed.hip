@@ -504,8 +504,8 @@ static_assert(kRC == 4, "the LDS staging of the per-slice ranges picks among fou
 constexpr int kRerankPerBlock = 4 * kRC;   // candidates scored per block (4 waves)
 constexpr int kZStage = 128;           // z-slices of per-slice row ranges a wave stages in LDS
 
-// 1-D grid of nbq * 8 * ceil(nq / 8) blocks (nbq = ceil(nc / kRerankPerBlock)),
-// 256 threads (4 waves). Blocks go to the 8 XCDs round-robin; the mapping below
+// 1-D grid of nbq * 8 * ceil(nq / 8) blocks (nbq = ceil(count / candidates per block): 4 kRC,
+// or kRC with SPLIT = 4), 256 threads (4 waves). Blocks go to the 8 XCDs round-robin; the mapping below
 // gives every block of query q to XCD q % 8, so the query's rows are fetched into
 // one L2 only. Each wave scores
 // kRC candidates of query q at once: lanes sweep the rows where the query's row
