@@ -325,6 +325,40 @@ def test_rerank_in_two_calls_matches_rerank():
         assert torch.equal(a, w)
 
 
+def test_two_halves_on_two_streams_match_one_stream():
+    """A batch reranked as two halves at once, each on its own stream with its own workspace
+    (packing with pooled counts, then the bound-ordered rerank of 60 candidates), gives the
+    one-stream top-k, scores and counts, bit for bit."""
+    need_gpu()
+    gen = synth.SMALL
+    n, nq, nc, k = 300, 24, 60, 15
+    db, _ = build_db_from_host(gen, n, synth.T_LO, synth.T_HI)
+    labels, _ = synth.make_queries(gen, n, nq, synth.QUERY_SEED)
+    labels[5] = 0
+    lab_d = torch.from_numpy(labels).cuda()
+    rng = np.random.default_rng(33)
+    cand = torch.from_numpy(np.stack([rng.choice(n, nc, replace=False) for _ in range(nq)])
+                            .astype(np.int32)).cuda()
+    want = db.rerank(lab_d, cand, k)
+    cur = torch.cuda.current_stream()
+    outs = []
+    for h in range(2):
+        a, b = h * nq // 2, (h + 1) * nq // 2
+        st = torch.cuda.Stream()
+        st.wait_stream(cur)
+        with torch.cuda.stream(st):
+            ws = db.rerank_workspace(b - a)
+            pooled = torch.empty((b - a, gen.nz // 2, gen.ny // 2, gen.nx // 2), dtype=torch.uint8,
+                                 device="cuda")
+            db.rerank_pack_pool(lab_d[a:b], ws, pooled)
+            outs.append(db.rerank_packed(ws, cand[a:b], k))
+        cur.wait_stream(st)
+    db.sync()
+    bits = lambda t: t.view(torch.int64) if t.dtype == torch.float64 else t
+    for i in range(3):
+        assert torch.equal(bits(torch.cat([o[i] for o in outs])), bits(want[i])), i
+
+
 @pytest.mark.parametrize("fmt", [0, 1])
 def test_latents_quantised_on_a_side_stream(fmt):
     """Quantisation enqueued on another stream (the float32 copy of the input is made on
