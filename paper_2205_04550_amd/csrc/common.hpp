@@ -177,4 +177,11 @@ __device__ __forceinline__ bool ranks_before(uint64_t sa, int32_t ia, uint64_t s
     return sa > sb || (sa == sb && ia < ib);
 }
 
+// v of the lane that DPP control `ctrl` names within this lane's row of 16 (all lanes active).
+template <int ctrl>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, ctrl, 0xf, 0xf, false);
+}
+
 }  // namespace tdb

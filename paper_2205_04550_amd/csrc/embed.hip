@@ -151,13 +151,6 @@ __device__ __forceinline__ uint32_t fold_zero_key(uint32_t k)
     return k == 0x7fffffffu ? 0x80000000u : k;   // raw_key(-0) -> fkey(+0)
 }
 
-// v of the lane that DPP control `ctrl` names within this lane's row of 16 (all lanes active).
-template <int ctrl>
-__device__ __forceinline__ uint32_t dpp_u32(uint32_t v)
-{
-    return (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, ctrl, 0xf, 0xf, false);
-}
-
 // Reduce-scatter of minima over each row of 16 lanes: lane l returns the minimum of
 // k[l % 16] over the 16 lanes of its row. Four exchange steps (row mirror, half-row
 // mirror, xor 2, xor 1); in each a lane keeps the half of its values that the lane
