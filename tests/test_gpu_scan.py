@@ -121,6 +121,28 @@ def test_ragged_grid_ties_and_empty_query():
     assert list(_host(score)) == [2.0] * 5
 
 
+def test_selection_levels_with_ties_across_blocks():
+    """70,000 entries (69 selection blocks of 1,024): k = 32 takes three levels, k = 33
+    the LDS path; entries drawn with repetition from 700 volumes, so equal scores fall in
+    different blocks and levels and must still come out lowest index first."""
+    need_gpu()
+    gen = synth.GenConfig(32, 4, 4, 1.0, 6.0, 0.5, 2.0, 5)
+    rng = np.random.default_rng(11)
+    conc = gen.conc_cpu(0, 700)[rng.integers(0, 700, size=70_000)]
+    n = conc.shape[0]
+    say(f"selection levels n={n}")
+    db, _ = build_db_from_host(gen, n, T_LO, T_HI, conc=conc, chunk=8192)
+    for qi, q in enumerate((oracle.threshold(conc[123], T_LO, T_HI),
+                            rng.integers(0, 4, size=conc.shape[1:], dtype=np.uint8))):
+        o_cnt, o_sc = oracle.scan_block(conc, q, T_LO, T_HI)
+        qd = torch.from_numpy(np.ascontiguousarray(q)).cuda()
+        for k in (1, 10, 32, 33, 500):
+            say(f"  query {qi} k={k}")
+            idx, score, counts = db.query(qd, k)
+            db.sync()
+            _check_topk_against_oracle(idx, score, counts, o_cnt, o_sc, k)
+
+
 def test_errors_write_nothing():
     need_gpu()
     from paper_2205_04550_amd import DbError, binding
