@@ -96,6 +96,9 @@ def source_sha(*rel: str) -> str:
 # Committed counter files per workload and the sources of the kernel they measured.
 TRAFFIC_FILES = {
     "full": ("scan_full_traffic.json", SCAN_SOURCES),
+    "embed": ("pack_pool_query_traffic.json", ("paper_2205_04550_amd/csrc/pack.hip",
+                                               "paper_2205_04550_amd/csrc/common.hpp",
+                                               "paper_2205_04550_amd/csrc/internal.hpp")),
     "embed500k": ("knn_fp8_500k_traffic.json", ("paper_2205_04550_amd/csrc/knn.hip",
                                                  "paper_2205_04550_amd/csrc/embed_core.hpp",
                                                  "paper_2205_04550_amd/csrc/common.hpp",
@@ -820,7 +823,8 @@ def embed_run(args, db, gen, n, with_variants: bool) -> dict:
     pack_bytes = float(gen.nvox + 2 * gen.nvox // 8 + gen.nvox // 8) * nq
     pack_roof = {"bound": "hbm", "achieved": pack_bytes / (pack_ms * 1e-3) / 1e9,
                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": pack_bytes / (pack_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                 "frac": pack_bytes / (pack_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                 "traffic": load_traffic("embed") if nq == 1024 else None,
                  "kernel": "pack_pool_query_kernel + sum_parts_kernel", "kernel_avg_ms": pack_ms,
                  "algorithmic_bytes_per_launch": pack_bytes,
                  "note": "the query packing between HIP events; bytes = the labels read once, "
